@@ -1,0 +1,335 @@
+"""FP64 reference of the localized FBSDE-LLR time stepping.  Test infrastructure only.
+
+Problem (paper Sec. 2.1, eqs. mainprob / FBsyst): (d_t + L) u + f(t, x, u, sigma^T grad u) = 0,
+u(T, .) = g, with sigma = s I and a constant drift mu, so that X = x0 + mu t + s W.
+
+Readings of the paper this reference takes (each one is listed with its reason
+in the design notes of the repository):
+
+* Regressor: the next-point form of Lemma 3.6 / Lemma 3.7 (Sec. 3): at level k
+  the cloud is the particles at t_{k+1}, D_j = X^j_{k+1} - (x0 + mu t_{k+1}) = s W^j_{k+1}.
+* Weights: Gaussian kernel K(r) = exp(-r^2) normalised over the cloud (eq. Dj and the
+  kernel remark of Sec. 2.4), bandwidth eps_k^2 = h^2 s^2 t_{k+1} d; h = 0 means uniform
+  weights.  The minimum squared distance is subtracted inside the exponential, which
+  leaves the normalised weights unchanged (the weight-ratio identity of that remark).
+* Weighted centring D'_j = D_j - sum_i w_i D_i, so the (d+1) normal equations (eq.
+  normal-eq) split into the Schur form of Lemma 3.7.
+* Ridge (remark after the matrix-free steps): only the slope is penalised,
+  lambda_k = ridge_rel s^2 t_{k+1}.
+* Conditional expectation of Y_{k+1} given X^m_k: the fitted local linear model
+  evaluated at the drift-transported particle, C^m_k = alpha + s alpha_x . W^m_k
+  (eq. taylorexp with alpha = u + dt d_t u at the anchor).
+* Z_k = sigma^T alpha_x = s alpha_x, shared by the cloud of one evaluation point.
+* Newton (Sec. 2.5, eqs. nonlinearf / NRiter) on F(y) = y - C - dt f(t_k, X, y, Z),
+  a fixed number of iterations started at y = C.
+* Output u(0, x0) = mean_m Y^m_0 (Algorithm 1, last step); grad u(0, x0) is the
+  x-derivative of the level-0 Newton equation, (alpha_x + dt grad_x f) / F'(u).
+
+The linear solve is direct (Cholesky): primal d x d when M > d, otherwise the dual
+M x M form (push-through identity), which needs lambda > 0.
+"""
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import philox
+
+F_ZERO, F_ALLEN_CAHN, F_HJB = 0, 1, 2
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE = 0, 1, 2, 3
+
+ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
+
+
+@dataclass
+class Problem:
+    d: int
+    M: int
+    N: int
+    T: float
+    s: float = float(np.sqrt(2.0))
+    mu: Optional[np.ndarray] = None          # [d] constant drift, None = 0
+    f_kind: int = F_ZERO
+    fp: tuple = (0.0, 0.0, 0.0, 0.0)
+    g_kind: int = G_QUAD
+    gp: tuple = (1.0, 0.0, 0.0, 0.0)
+    gvec: Optional[np.ndarray] = None        # [d] slope of G_AFFINE
+    eps_h: float = 1.0
+    ridge_rel: float = 1e-3
+    newton_iters: int = 8
+    seed: int = 0
+    instance: int = 0
+    point_base: int = 0
+    shared_dw: int = 0
+
+    def copy(self, **kw):
+        return replace(self, **kw)
+
+
+# ---------------------------------------------------------------- f and g families
+def f_eval(pb, t, y, z):
+    """f(t, x, y, z) of the built-in families with d f/dy, d f/dz and d f/d(fp).
+
+    The families do not depend on t or x.  ALLEN_CAHN: c1 y - c3 y^3 (paper Sec. 4.1
+    Case 1 has c1 = c3 = 1); HJB: -lam |z|^2.  y: array [M]; z: array [d].
+    Returns (f [M], fy [M], fz [d] per unit of the factor fz_scale [M], fth [4, M]).
+    """
+    y = np.asarray(y, dtype=np.float64)
+    zero = np.zeros_like(y)
+    fth = np.zeros((4,) + y.shape)
+    if pb.f_kind == F_ZERO:
+        return zero, zero, np.zeros_like(z), zero, fth
+    if pb.f_kind == F_ALLEN_CAHN:
+        c1, c3 = pb.fp[0], pb.fp[1]
+        f = c1 * y - c3 * y ** 3
+        fy = c1 - 3.0 * c3 * y ** 2
+        fth[0] = y
+        fth[1] = -y ** 3
+        return f, fy, np.zeros_like(z), zero, fth
+    if pb.f_kind == F_HJB:
+        lam = pb.fp[0]
+        zz = float(z @ z)
+        f = np.full_like(y, -lam * zz)
+        fth[0] = -zz
+        # d f / d z = -2 lam z, the same for every particle
+        return f, zero, -2.0 * lam * z, np.ones_like(y), fth
+    raise ValueError("unknown f kind")
+
+
+def g_eval(pb, X):
+    """Terminal g(X) for X [M, d] with grad_x g [M, d] and d g / d(gp) [4, M]."""
+    gth = np.zeros((4, X.shape[0]))
+    if pb.g_kind == G_AFFINE:
+        c = np.asarray(pb.gvec, dtype=np.float64)
+        g = X @ c + pb.gp[0]
+        gth[0] = 1.0
+        return g, np.broadcast_to(c, X.shape).copy(), gth
+    n2 = np.einsum("ij,ij->i", X, X)
+    if pb.g_kind == G_QUAD:
+        a, b = pb.gp[0], pb.gp[1]
+        g = a * n2 / pb.d + b
+        gx = (2.0 * a / pb.d) * X
+        gth[0] = n2 / pb.d
+        gth[1] = 1.0
+        return g, gx, gth
+    if pb.g_kind == G_AC:
+        a = pb.gp[0]
+        den = 2.0 + a * n2
+        g = 1.0 / den
+        gx = (-2.0 * a / den ** 2)[:, None] * X
+        gth[0] = -n2 / den ** 2
+        return g, gx, gth
+    if pb.g_kind == G_HJB_LOG:
+        a = pb.gp[0]
+        den = 1.0 + a * n2
+        g = np.log(den / 2.0)
+        gx = (2.0 * a / den)[:, None] * X
+        gth[0] = n2 / den
+        return g, gx, gth
+    raise ValueError("unknown g kind")
+
+
+# ---------------------------------------------------------------- particles
+def stream_of(pb, p):
+    return philox.SHARED_STREAM if pb.shared_dw else (pb.point_base + p) & 0xFFFFFFFF
+
+
+def brownian_path(pb, p):
+    """W[k, j, :] for k = 0..N: W_0 = 0, W_{k+1} = W_k + sqrt(dt) xi_k (paper eq. Xk with sigma = s I).
+
+    X^j_k = x0 + k dt mu + s W^j_k is the Euler-Maruyama particle; it is exact in law for
+    constant coefficients.
+    """
+    dt = pb.T / pb.N
+    W = np.zeros((pb.N + 1, pb.M, pb.d))
+    q = stream_of(pb, p)
+    for k in range(pb.N):
+        xi = philox.normals(pb.seed, pb.instance, q, k, pb.M, pb.d)
+        W[k + 1] = W[k] + np.sqrt(dt) * xi
+    return W
+
+
+def positions(pb, x0, W_k, k):
+    dt = pb.T / pb.N
+    X = x0[None, :] + pb.s * W_k
+    if pb.mu is not None:
+        X = X + (k * dt) * np.asarray(pb.mu)[None, :]
+    return X
+
+
+# ---------------------------------------------------------------- one regression
+def kernel_weights(pb, D, t_next):
+    """Normalised Gaussian kernel weights of eq. Dj, bandwidth eps^2 = h^2 s^2 t_{k+1} d."""
+    n2 = np.einsum("ij,ij->i", D, D)
+    if pb.eps_h == 0.0:
+        e = np.ones(pb.M)
+    else:
+        eps2 = pb.eps_h ** 2 * pb.s ** 2 * t_next * pb.d
+        e = np.exp(-(n2 - n2.min()) / eps2)
+    return e / e.sum()
+
+
+class RidgeSystem:
+    """(sum_j w_j D'_j D'_j^T + lam I) with its Cholesky factor, primal or dual."""
+
+    def __init__(self, Dc, w, lam, mode=None):
+        self.Dc, self.w, self.lam = Dc, w, lam
+        M, d = Dc.shape
+        self.primal = (M > d) if mode is None else (mode == "primal")
+        if self.primal:
+            A = Dc.T @ (w[:, None] * Dc) + lam * np.eye(d)
+            self.fac = sla.cho_factor(A, lower=True)
+        else:
+            if lam <= 0.0:
+                raise ValueError("the dual (M <= d) form needs a positive ridge")
+            B = np.sqrt(w)[:, None] * Dc
+            self.B = B
+            self.fac = sla.cho_factor(B @ B.T + lam * np.eye(M), lower=True)
+
+    def solve(self, v):
+        """A^{-1} v for a d-vector v."""
+        if self.primal:
+            return sla.cho_solve(self.fac, v)
+        # Woodbury: (lam I + B^T B)^{-1} = (I - B^T (lam I + B B^T)^{-1} B) / lam
+        return (v - self.B.T @ sla.cho_solve(self.fac, self.B @ v)) / self.lam
+
+    def solve_rhs_weighted(self, resid):
+        """A^{-1} D'^T W resid, written in the form that needs no d x d solve in dual mode."""
+        if self.primal:
+            return sla.cho_solve(self.fac, self.Dc.T @ (self.w * resid))
+        sw = np.sqrt(self.w)
+        return self.B.T @ sla.cho_solve(self.fac, sw * resid)
+
+
+def llr(pb, W_next, Y_next, k):
+    """Weighted ridge local linear regression of level k (paper Sec. 2.4).
+
+    Fits Y^j_{k+1} ~ alpha + alpha_x^T D_j over the cloud at t_{k+1} with D_j = s W^j_{k+1}.
+    Returns a dict with w, Wbar (weighted mean of W), Ybar, alpha_x, alpha and the system.
+    """
+    dt = pb.T / pb.N
+    t_next = (k + 1) * dt
+    D = pb.s * W_next
+    w = kernel_weights(pb, D, t_next)
+    Dbar = w @ D
+    Dc = D - Dbar[None, :]
+    Ybar = w @ Y_next
+    lam = pb.ridge_rel * pb.s ** 2 * t_next
+    sysm = RidgeSystem(Dc, w, lam)
+    alpha_x = sysm.solve_rhs_weighted(Y_next - Ybar)
+    alpha = Ybar - alpha_x @ Dbar
+    return dict(w=w, Wbar=Dbar / pb.s, Ybar=Ybar, alpha_x=alpha_x, alpha=alpha, sys=sysm)
+
+
+def newton(pb, k, C, Z):
+    """Fixed-count Newton on F(y) = y - C - dt f(t_k, X, y, Z), from y = C (paper eq. NRiter)."""
+    dt = pb.T / pb.N
+    y = np.array(C, dtype=np.float64)
+    status = 0
+    for _ in range(pb.newton_iters):
+        f, fy, _, _, _ = f_eval(pb, k * dt, y, Z)
+        F = y - C - dt * f
+        Fp = 1.0 - dt * fy
+        if np.any(np.abs(Fp) < 1e-12):
+            status |= ST_NEWTON_FLAT
+        y = y - F / Fp
+    _, fy, _, _, _ = f_eval(pb, k * dt, y, Z)
+    return y, 1.0 - dt * fy, status
+
+
+# ---------------------------------------------------------------- driver
+def solve_point(pb, x0, p, tape=False):
+    """Algorithm 1 for one evaluation point x0 [d] (global point index point_base + p).
+
+    Returns dict(u, grad, status) and, with tape=True, the per-level records used by the
+    reverse mode and by step-level tests.
+    """
+    x0 = np.asarray(x0, dtype=np.float64)
+    dt = pb.T / pb.N
+    W = brownian_path(pb, p)
+    # terminal condition on the simulated cloud (Algorithm 1 sets it after the forward sweep)
+    Y, _, _ = g_eval(pb, positions(pb, x0, W[pb.N], pb.N))
+    status = 0
+    levels = [None] * pb.N
+    Ys = [None] * (pb.N + 1)
+    Ys[pb.N] = Y
+    for k in range(pb.N - 1, -1, -1):
+        fit = llr(pb, W[k + 1], Y, k)
+        C = fit["alpha"] + pb.s * (W[k] @ fit["alpha_x"])
+        Z = pb.s * fit["alpha_x"]
+        Y, Fp, st = newton(pb, k, C, Z)
+        status |= st
+        fit.update(C=C, Z=Z, Fp=Fp)
+        levels[k] = fit
+        Ys[k] = Y
+    u = float(Y.mean())
+    # grad u(0, x0): x-derivative of y = alpha + alpha_x.(x - x0) + dt f(t_0, x, y, Z_0);
+    # the built-in f families do not depend on x.
+    grad = levels[0]["alpha_x"] / levels[0]["Fp"][0]
+    if not (np.isfinite(u) and np.all(np.isfinite(grad))):
+        status |= ST_NONFINITE
+    out = dict(u=u, grad=grad, status=status)
+    if tape:
+        out.update(W=W, Y=Ys, levels=levels)
+    return out
+
+
+def solve(pb, x0s, points=None):
+    """u [P], grad [P, d], status [P] for rows of x0s (optionally a subset of point indices)."""
+    x0s = np.asarray(x0s, dtype=np.float64)
+    idx = range(x0s.shape[0]) if points is None else points
+    res = [solve_point(pb, x0s[p], p) for p in idx]
+    return (np.array([r["u"] for r in res]), np.stack([r["grad"] for r in res]),
+            np.array([r["status"] for r in res], dtype=np.uint32))
+
+
+# ---------------------------------------------------------------- reverse mode
+def adjoint_point(pb, x0, p, ubar=1.0):
+    """Reverse mode of solve_point: d(ubar u)/d x0, d/d gp, d/d fp.
+
+    Per level (walked from k = 0 upwards), given the adjoint G^m_k of Y^m_k:
+      Newton (implicit function): cbar_m = G^m_k / F'_m; through f: Zbar += sum cbar dt df/dz,
+      fpbar += sum cbar dt df/dfp.
+      C^m = alpha + s alpha_x.W^m_k:  alphabar = sum_m cbar_m, alpha_xbar = s sum_m cbar_m W^m_k.
+      Z = s alpha_x:                  alpha_xbar += s Zbar.
+      alpha = Ybar - alpha_x.Dbar:    Ybarbar = alphabar, alpha_xbar -= alphabar Dbar.
+      alpha_x = A^{-1} b, A independent of Y (and of x0 and the parameters):  bbar = A^{-1} alpha_xbar.
+      b = sum_j w_j (Y_j - Ybar) D'_j: G^j_{k+1} += w_j D'_j.bbar, Ybarbar -= sum_j w_j D'_j.bbar.
+      Ybar = sum_j w_j Y_j:           G^j_{k+1} += w_j Ybarbar.
+    Terminal: x0bar += sum_j G^j_N grad g(X^j_N), gpbar += sum_j G^j_N dg/dgp.
+    """
+    x0 = np.asarray(x0, dtype=np.float64)
+    dt = pb.T / pb.N
+    fw = solve_point(pb, x0, p, tape=True)
+    W, Ys, levels = fw["W"], fw["Y"], fw["levels"]
+    fpbar = np.zeros(4)
+    x0bar = np.zeros(pb.d)
+    G = np.full(pb.M, ubar / pb.M)          # u = mean_m Y^m_0
+    for k in range(pb.N):
+        lv = levels[k]
+        cbar = G / lv["Fp"]
+        _, _, fz, fz_scale, fth = f_eval(pb, k * dt, Ys[k], lv["Z"])
+        Zbar = dt * (cbar * fz_scale).sum() * fz
+        fpbar += dt * (fth * cbar[None, :]).sum(axis=1)
+        abar = cbar.sum()
+        axbar = pb.s * (W[k].T @ cbar) + pb.s * Zbar - abar * (pb.s * lv["Wbar"])
+        bbar = lv["sys"].solve(axbar)
+        Dc = lv["sys"].Dc
+        proj = Dc @ bbar
+        ybarbar = abar - (lv["w"] * proj).sum()
+        G = lv["w"] * proj + lv["w"] * ybarbar
+    _, gx, gth = g_eval(pb, positions(pb, x0, W[pb.N], pb.N))
+    x0bar += G @ gx
+    gpbar = gth @ G
+    return dict(x0bar=x0bar, gpbar=gpbar, fpbar=fpbar, u=fw["u"], grad=fw["grad"])
+
+
+# ---------------------------------------------------------------- one level on given state
+def level_step(pb, k, W_next, W_k, Y_next):
+    """One backward level on a given cloud: returns alpha, alpha_x, Y_k, F'(Y_k)."""
+    fit = llr(pb, W_next, Y_next, k)
+    C = fit["alpha"] + pb.s * (W_k @ fit["alpha_x"])
+    Y, Fp, st = newton(pb, k, C, pb.s * fit["alpha_x"])
+    return dict(alpha=fit["alpha"], alpha_x=fit["alpha_x"], Y=Y, Fp=Fp, status=st, w=fit["w"],
+                Wbar=fit["Wbar"], Ybar=fit["Ybar"])

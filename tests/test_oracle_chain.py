@@ -1,0 +1,113 @@
+"""Pins of the oracle's whole time-stepping chain (Algorithm 1 under the adopted readings).
+
+* Affine invariant (closed form derived from the scheme): g = a.x + b, f = c1 y, no ridge, M > d + 1:
+  every level's fit is exact, so u(0, x0) = (a.(x0 + mu T) + b) / (1 - c1 dt)^N and
+  grad u = a / (1 - c1 dt)^N, for any seed, drift and bandwidth.
+* Heat telescoping identity (f = 0, uniform weights, any ridge):
+  u = mean_j Y^j_N - s sum_k alpha_x^(k) . mean_j dW^j_k.
+* Heat closed form u = |x0|^2/d + s^2 T (statistical, z-score over points).
+* Allen-Cahn Case 1 (paper Sec. 4.1: d = 100, T = 0.3, x0 = 0, f = u - u^3,
+  g = 1/(2 + 0.4|x|^2)): the Richardson-extrapolated value is within 5e-4 of the printed
+  reference 0.0528 (three printed digits); uniform weights.
+* HJB against the Cole-Hopf quadrature (loose gate: the scheme shares Z over the cloud,
+  which biases u upward by the cloud variance of grad u).
+* Level-0 particles coincide, so all Y^m_0 are equal; shared-increment mode equals the
+  per-point mode fed the same stream.
+"""
+import numpy as np
+import pytest
+
+from oracle import colehopf as CH
+from oracle import scheme as S
+
+
+@pytest.mark.parametrize("d,M,N,h,use_mu,c1,seed", [(5, 40, 6, 1.0, True, 0.7, 3), (8, 64, 4, 0.0, False, -0.4, 1),
+                                                    (3, 12, 9, 2.5, True, 0.0, 11)])
+def test_affine_invariant(d, M, N, h, use_mu, c1, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=d)
+    mu = rng.normal(size=d) * 0.3 if use_mu else None
+    T, b = 0.5, 0.4
+    pb = S.Problem(d=d, M=M, N=N, T=T, s=1.3, mu=mu, f_kind=S.F_ALLEN_CAHN, fp=(c1, 0.0, 0, 0),
+                   g_kind=S.G_AFFINE, gp=(b, 0, 0, 0), gvec=a, eps_h=h, ridge_rel=0.0, seed=seed)
+    x0 = rng.normal(size=d)
+    r = S.solve_point(pb, x0, 0)
+    fac = (1.0 - c1 * T / N) ** N
+    xt = x0 + (mu * T if mu is not None else 0.0)
+    assert abs(r["u"] - (a @ xt + b) / fac) < 1e-12 * max(1.0, abs(r["u"]))
+    np.testing.assert_allclose(r["grad"], a / fac, rtol=1e-11, atol=1e-12)
+
+
+def test_level0_particles_coincide():
+    pb = S.Problem(d=7, M=33, N=4, T=0.3, f_kind=S.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=S.G_AC, gp=(0.4, 0, 0, 0))
+    r = S.solve_point(pb, np.full(7, 0.2), 0, tape=True)
+    Y0 = r["Y"][0]
+    assert Y0.max() - Y0.min() == 0.0
+    assert np.all(r["W"][0] == 0.0)
+
+
+@pytest.mark.parametrize("ridge", [0.0, 1e-2])
+def test_heat_telescoping_identity(ridge):
+    rng = np.random.default_rng(9)
+    d, M, N = 6, 50, 7
+    pb = S.Problem(d=d, M=M, N=N, T=0.4, s=1.2, f_kind=S.F_ZERO, g_kind=S.G_QUAD, gp=(1.0, 0.3, 0, 0),
+                   eps_h=0.0, ridge_rel=ridge, seed=4)
+    x0 = rng.normal(size=d)
+    r = S.solve_point(pb, x0, 0, tape=True)
+    W, lv = r["W"], r["levels"]
+    rhs = r["Y"][N].mean() - pb.s * sum(lv[k]["alpha_x"] @ (W[k + 1] - W[k]).mean(0) for k in range(N))
+    assert abs(r["u"] - rhs) < 1e-13
+
+
+def test_heat_closed_form_statistical():
+    rng = np.random.default_rng(0)
+    d, P = 50, 64
+    x0s = 0.5 * rng.normal(size=(P, d))
+    pb = S.Problem(d=d, M=512, N=5, T=0.3, f_kind=S.F_ZERO, g_kind=S.G_QUAD, eps_h=0.0, ridge_rel=1e-3)
+    u, grad, st = S.solve(pb, x0s)
+    ue, ge = CH.heat_quadratic(x0s, 0.3)
+    e = u - ue
+    z = e.mean() / (e.std(ddof=1) / np.sqrt(P))
+    assert abs(z) < 5.0
+    assert np.all(st == 0)
+    # the gradient estimate is unbiased up to the ridge shrinkage: pooled z-score of its error
+    eg = (grad - ge).ravel()
+    assert abs(eg.mean() / (eg.std(ddof=1) / np.sqrt(eg.size))) < 5.0
+
+
+def test_allen_cahn_case1_reference_value():
+    vals = {}
+    for N in (20, 40):
+        us = []
+        for seed in range(2):
+            pb = S.Problem(d=100, M=4096, N=N, T=0.3, f_kind=S.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0),
+                           g_kind=S.G_AC, gp=(0.4, 0, 0, 0), eps_h=0.0, seed=seed)
+            us.append(S.solve_point(pb, np.zeros(100), 0)["u"])
+        vals[N] = np.mean(us)
+    extrap = 2 * vals[40] - vals[20]
+    assert abs(extrap - 0.0528) < 5e-4
+    assert abs(vals[40] - 0.0528) < 1e-3
+
+
+def test_hjb_against_cole_hopf():
+    rng = np.random.default_rng(1)
+    d = 200
+    x = rng.uniform(-1, 1, size=d)
+    ref = CH.hjb_log_cole_hopf(x, 1.0, 1.0)
+    pb = S.Problem(d=d, M=1024, N=10, T=1.0, f_kind=S.F_HJB, fp=(1.0, 0, 0, 0), g_kind=S.G_HJB_LOG,
+                   gp=(1.0, 0, 0, 0), eps_h=0.0, ridge_rel=1e-3)
+    u = S.solve_point(pb, x, 0)["u"]
+    assert abs(u - ref) < 1e-2 * abs(ref)
+
+
+def test_shared_mode_equals_per_point_stream():
+    rng = np.random.default_rng(2)
+    d, M = 5, 20
+    x0 = rng.normal(size=(3, d))
+    pb = S.Problem(d=d, M=M, N=3, T=0.3, f_kind=S.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=S.G_AC,
+                   gp=(0.4, 0, 0, 0), shared_dw=1, seed=5)
+    for p in range(3):
+        shared = S.solve_point(pb, x0[p], p)
+        single = S.solve_point(pb.copy(shared_dw=0, point_base=0xFFFFFFFF - p), x0[p], p)
+        assert shared["u"] == single["u"]
+        assert np.array_equal(shared["grad"], single["grad"])

@@ -1,0 +1,162 @@
+/*
+ * fbsde.h -- C ABI of the MI355X (gfx950) library for the localized stochastic FBSDE /
+ * local-linear-regression scheme for semilinear parabolic PDEs
+ *
+ *     (d_t + L) u + f(t, x, u, sigma^T grad u) = 0,   u(T, .) = g,
+ *     L = 1/2 tr(sigma sigma^T Hess) + <mu, grad>            (paper Sec. 2.1, eq. mainprob)
+ *
+ * solved at evaluation points x0 through the FBSDE Y = u(t, X), Z = sigma^T grad u(t, X)
+ * (eq. FBsyst), the implicit Euler step Y_k = E_k[Y_{k+1} + dt f(t_k, X_k, Y_k, Z_k)]
+ * (eq. Ytkdiscrete), Euler-Maruyama particles (Sec. 2.3, eq. Xk), a kernel-weighted ridge
+ * local linear regression for the gradient solved matrix-free (Sec. 2.4, eqs. leastsq, Dj,
+ * normal-eq, the two-step matrix-free product and the ridge remark) and a scalar Newton
+ * iteration for Y (Sec. 2.5, eqs. nonlinearf, NRiter), in the order of Algorithm 1.
+ *
+ * Scope of this ABI: sigma = s I (s > 0), constant drift mu, and built-in families for f and
+ * g (device code cannot call host callbacks).  The scheme's readings of the paper:
+ *   - level k regresses Y_{k+1} on the cloud at t_{k+1}: D_j = s W^j_{k+1}, the next-point
+ *     form of Lemma 3.6 / 3.7, with weighted centring (Schur form of Lemma 3.7);
+ *   - Gaussian kernel weights w_j ~ exp(-|D_j|^2 / eps_k^2), eps_k^2 = eps_h^2 s^2 t_{k+1} d,
+ *     normalised over the cloud; eps_h = 0 gives uniform weights;
+ *   - ridge only on the slope, lambda_k = ridge_rel s^2 t_{k+1};
+ *   - E_k[Y_{k+1} | X^m_k] is the fitted linear model at the drift-transported particle,
+ *     C^m_k = alpha + s alpha_x . W^m_k, and Z_k = s alpha_x;
+ *   - Newton on F(y) = y - C - dt f(t_k, X, y, Z), newton_iters iterations from y = C;
+ *   - u(0, x0) = mean_m Y^m_0 and grad u(0, x0) = (alpha_x + dt grad_x f) / F'(u) at level 0.
+ * Particle increments are Philox4x32-10 (SC'11) normals regenerated on the fly:
+ *   counter = (floor(i / 4), particle j, level k, point_base + p  | 0xFFFFFFFF if shared_dw),
+ *   key     = (seed & 0xFFFFFFFF, (seed >> 32) ^ instance),
+ *   Box-Muller on word pairs (0,1) and (2,3), u = (w + 1/2) 2^-32.
+ *
+ * Conventions for every entry point
+ *   - Pointers named "device" are device memory of the current HIP device; the caller owns
+ *     every buffer, including the workspace; the library allocates nothing and keeps no
+ *     global state.
+ *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
+ *     once it is enqueued, except where stated (CG convergence polling, see fbsde_solve).
+ *   - Return value: FBSDE_OK, or a negative code decided on the host before any launch
+ *     (FBSDE_EINVAL, FBSDE_ENOSPC) or after a failed launch (FBSDE_EHIP).
+ *   - Per-point numerical failures do not stop other points: they are OR-ed into
+ *     status[p] (FBSDE_ST_* bits).
+ *   - Particle state layout: W[p][j][i] = W^j (Brownian displacement, X = x0 + t mu + s W)
+ *     with a row pitch of fbsde_state_ld(pb) elements, padding kept at zero; element type
+ *     double for FBSDE_F64, float for FBSDE_F32C.  In shared_dw mode the state is [M][ld].
+ */
+#ifndef FBSDE_H
+#define FBSDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* fbsde_stream;   /* hipStream_t */
+
+enum { FBSDE_F64 = 0, FBSDE_F32C = 1 };       /* FP64 everywhere | FP32 state + compensated FP32
+                                                 LLR sums, FP64 CG scalars, Newton and outputs */
+enum { FBSDE_F_ZERO = 0,                      /* f = 0 (heat)                                  */
+       FBSDE_F_ALLEN_CAHN = 1,                /* f = fp0 y - fp1 y^3 (Sec. 4.1 Case 1: 1, 1)  */
+       FBSDE_F_HJB = 2 };                     /* f = -fp0 |z|^2, z = sigma^T grad u            */
+enum { FBSDE_G_QUAD = 0,                      /* g = gp0 |x|^2 / d + gp1                       */
+       FBSDE_G_AC = 1,                        /* g = 1 / (2 + gp0 |x|^2)   (Sec. 4.1 Case 1)   */
+       FBSDE_G_HJB_LOG = 2,                   /* g = ln((1 + gp0 |x|^2) / 2)                   */
+       FBSDE_G_AFFINE = 3 };                  /* g = gvec . x + gp0                            */
+enum { FBSDE_OK = 0, FBSDE_EINVAL = -1, FBSDE_ENOSPC = -2, FBSDE_EHIP = -3, FBSDE_ESTATE = -4 };
+enum { FBSDE_ST_CG_MAXIT = 1, FBSDE_ST_NEWTON_FLAT = 2, FBSDE_ST_NONFINITE = 4 };
+enum { FBSDE_WS_TAPE = 1 };                   /* workspace flag: keep the tape for the adjoint */
+
+/* Problem descriptor (host memory).  Paper Algorithm 1 takes T, d, M, N, dt = T/N and the
+ * target point; sigma, mu, f, g are the coefficients of Sec. 2.1. */
+typedef struct fbsde_problem {
+    int64_t d;               /* space dimension, >= 1                                        */
+    int64_t M;               /* particles per evaluation point, >= 2                          */
+    int64_t N;               /* time steps, >= 1; dt = T / N                                  */
+    double T;                /* horizon, > 0                                                  */
+    double s;                /* sigma = s I, > 0                                              */
+    const double* mu;        /* device [d] constant drift, or NULL for 0                      */
+    int32_t f_kind;          /* FBSDE_F_*                                                     */
+    int32_t g_kind;          /* FBSDE_G_*                                                     */
+    double fp[4];            /* parameters of f                                               */
+    double gp[4];            /* parameters of g                                               */
+    const double* gvec;      /* device [d] slope of FBSDE_G_AFFINE, else NULL                 */
+    double eps_h;            /* kernel bandwidth factor h >= 0 (0: uniform weights)           */
+    double ridge_rel;        /* ridge factor >= 0; 0 needs M > d + 1                          */
+    int32_t newton_iters;    /* Newton iterations per particle and level, >= 1                */
+    int32_t cg_maxit;        /* CG iteration cap per level, >= 1                              */
+    double cg_rtol;          /* CG stop: |r| <= cg_rtol |b|                                   */
+    int32_t cg_fixed_iters;  /* > 0: run exactly this many CG launches per level, no polling  */
+    int32_t shared_dw;       /* 1: the same increments for every evaluation point             */
+    uint64_t seed;           /* Philox key                                                     */
+    uint32_t instance;       /* PDE instance id, folded into the key                          */
+    uint32_t point_base;     /* global index of this call's point 0 (Philox counter word 3)   */
+    int32_t prec;            /* FBSDE_F64 or FBSDE_F32C                                       */
+    int32_t reserved;        /* must be 0                                                     */
+} fbsde_problem;
+
+/* Row pitch (elements) of the particle state for this problem (d rounded up so that rows
+ * start on 128-byte boundaries).  Returns 0 for an invalid descriptor. */
+int64_t fbsde_state_ld(const fbsde_problem* pb);
+
+/* Workspace bytes needed by fbsde_solve / fbsde_solve_step / fbsde_solve_backward for P
+ * points.  flags: FBSDE_WS_TAPE to keep what fbsde_solve_backward needs. */
+int fbsde_workspace_size(const fbsde_problem* pb, int64_t P, int32_t flags, size_t* bytes);
+
+/* Forward half of Algorithm 1 for P points (its first two loops): simulate the Brownian
+ * displacements W^j_N = sum_k sqrt(dt) xi^j_k (eq. Xk) and set Y^j_N = g(x0 + mu T + s W^j_N).
+ *   x0     device [P][d] evaluation points (row stride d)
+ *   W      device [P][M][ldw] (shared_dw: [M][ldw]) output state at t_N, ldw >= fbsde_state_ld
+ *   Y      device [P][M] output terminal values
+ *   status device [P] cleared, then OR-ed with FBSDE_ST_NONFINITE on overflow */
+int fbsde_terminal(const fbsde_problem* pb, int64_t P, const double* x0, void* W, int64_t ldw,
+                   double* Y, uint32_t* status, fbsde_stream stream);
+
+/* One backward level k (0 <= k < N) of Algorithm 1 on caller-owned state: the weighted ridge
+ * regression of Y_{k+1} on the cloud W_{k+1} (matrix-free CG, eq. normal-eq and the ridge
+ * remark), the particle reversal W_k = W_{k+1} - sqrt(dt) xi_k, and the Newton solve for Y_k.
+ *   W       device state, in: W_{k+1}, out: W_k (layout as fbsde_terminal; not shared_dw)
+ *   Y_next  device [P][M] in: Y_{k+1};   Y device [P][M] out: Y_k (may not alias Y_next)
+ *   alpha   device [P] out: intercept;   alpha_x device [P][d] out: slope (row stride d)
+ *   status  device [P] OR-ed with FBSDE_ST_* bits
+ *   ws      device workspace of at least fbsde_workspace_size(pb, P, 0) bytes */
+int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double* x0, void* W,
+                     int64_t ldw, const double* Y_next, double* Y, double* alpha, double* alpha_x,
+                     uint32_t* status, void* ws, size_t ws_bytes, fbsde_stream stream);
+
+/* Algorithm 1 for P evaluation points: u(0, x0_p) and grad u(0, x0_p).
+ *   x0     device [P][d];  u device [P];  grad device [P][d] or NULL;  status device [P]
+ *   ws     device workspace, fbsde_workspace_size(pb, P, flags) bytes; with FBSDE_WS_TAPE it
+ *          keeps the tape that fbsde_solve_backward reads (then do not reuse ws in between)
+ *   cg_iters_out  host [N] or NULL: CG iterations run at each level k
+ * Unless cg_fixed_iters > 0, the host waits on the stream every few CG iterations to read the
+ * number of points still iterating (so the call returns after the work is done). */
+int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, int32_t* cg_iters_out,
+                fbsde_stream stream);
+
+/* Reverse mode of fbsde_solve for the loss L = sum_p u_bar[p] u(0, x0_p): hand-written adjoint of
+ * the whole backward chain (Newton by the implicit-function rule, the regression through one extra
+ * CG solve per level with the same symmetric matrix, the terminal condition), regenerating the
+ * particles from their Philox counters forward in time.
+ *   Requires the immediately preceding fbsde_solve on the same pb, P, x0 and ws with
+ *   flags = FBSDE_WS_TAPE (FBSDE_ESTATE otherwise).
+ *   u_bar  device [P];  x0_bar device [P][d] out;  gp_bar, fp_bar device [4] out (summed
+ *   over points);  status device [P] OR-ed. */
+int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar,
+                         double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status,
+                         void* ws, size_t ws_bytes, fbsde_stream stream);
+
+/* Diagnostic: the normals xi^j_k of point p (or the shared stream) for rows j0..j0+rows-1 of
+ * level k, exactly as the kernels generate them.  out device [rows][d]; words device
+ * [rows][ceil(d/4)][4] raw Philox output or NULL. */
+int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows,
+                  double* out, uint32_t* words, fbsde_stream stream);
+
+/* Human-readable text of a return code. */
+const char* fbsde_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FBSDE_H */

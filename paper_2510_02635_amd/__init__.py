@@ -1,0 +1,11 @@
+"""MI355X (gfx950) implementation of the localized stochastic FBSDE / local-linear-regression scheme
+for very high-dimensional semilinear parabolic PDEs: HIP kernels behind a C ABI (include/fbsde.h),
+with a thin Python front end over PyTorch device memory and streams."""
+from . import _native
+from .api import (Problem, normals, solve, solve_backward, solve_step, state_ld, terminal, workspace,
+                  workspace_size)
+from ._native import (F32C, F64, F_ALLEN_CAHN, F_HJB, F_ZERO, G_AC, G_AFFINE, G_HJB_LOG, G_QUAD, FbsdeError)
+
+__all__ = ["Problem", "solve", "solve_step", "solve_backward", "terminal", "normals", "state_ld", "workspace",
+           "workspace_size", "F64", "F32C", "F_ZERO", "F_ALLEN_CAHN", "F_HJB", "G_QUAD", "G_AC", "G_HJB_LOG",
+           "G_AFFINE", "FbsdeError"]

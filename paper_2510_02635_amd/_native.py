@@ -1,0 +1,78 @@
+"""ctypes binding of libfbsde.so (the C ABI of include/fbsde.h).  Argument marshalling only."""
+import ctypes
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfbsde.so")
+
+F64, F32C = 0, 1
+F_ZERO, F_ALLEN_CAHN, F_HJB = 0, 1, 2
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE = 0, 1, 2, 3
+OK, EINVAL, ENOSPC, EHIP, ESTATE = 0, -1, -2, -3, -4
+ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
+WS_TAPE = 1
+
+EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
+            "fbsde_solve_backward", "fbsde_normals", "fbsde_strerror")
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64),
+        ("T", ctypes.c_double), ("s", ctypes.c_double),
+        ("mu", ctypes.c_void_p),
+        ("f_kind", ctypes.c_int32), ("g_kind", ctypes.c_int32),
+        ("fp", ctypes.c_double * 4), ("gp", ctypes.c_double * 4),
+        ("gvec", ctypes.c_void_p),
+        ("eps_h", ctypes.c_double), ("ridge_rel", ctypes.c_double),
+        ("newton_iters", ctypes.c_int32), ("cg_maxit", ctypes.c_int32),
+        ("cg_rtol", ctypes.c_double),
+        ("cg_fixed_iters", ctypes.c_int32), ("shared_dw", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("instance", ctypes.c_uint32), ("point_base", ctypes.c_uint32),
+        ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class FbsdeError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def load():
+    """Load libfbsde.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise FbsdeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2510_02635_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    pb = P(CProblem)
+    lib.fbsde_state_ld.argtypes = [pb]
+    lib.fbsde_state_ld.restype = i64
+    lib.fbsde_workspace_size.argtypes = [pb, i64, i32, P(sz)]
+    lib.fbsde_terminal.argtypes = [pb, i64, vp, vp, i64, vp, vp, vp]
+    lib.fbsde_solve_step.argtypes = [pb, i64, i32, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fbsde_solve.argtypes = [pb, i64, vp, vp, vp, vp, vp, sz, i32, vp, vp]
+    lib.fbsde_solve_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fbsde_normals.argtypes = [pb, i64, i32, i64, i64, vp, vp, vp]
+    lib.fbsde_strerror.argtypes = [ctypes.c_int]
+    lib.fbsde_strerror.restype = ctypes.c_char_p
+    for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
+                 "fbsde_solve_backward", "fbsde_normals"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc != OK:
+        raise FbsdeError(f"libfbsde: {load().fbsde_strerror(rc).decode()} (code {rc})")
+    return rc

@@ -1,0 +1,172 @@
+"""Python front end of libfbsde.so: torch tensors in, torch tensors out.
+
+PyTorch supplies device memory and the current HIP stream; every step of the scheme runs in the
+library's HIP kernels.  There is no CPU or PyTorch fallback: a missing library raises.
+"""
+import ctypes
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+from . import _native as N
+
+
+@dataclass
+class Problem:
+    """Problem descriptor (mirrors fbsde_problem).  mu and gvec, when given, are device tensors."""
+    d: int
+    M: int
+    N: int
+    T: float
+    s: float = math.sqrt(2.0)
+    mu: Optional[torch.Tensor] = None
+    f_kind: int = N.F_ZERO
+    fp: tuple = (0.0, 0.0, 0.0, 0.0)
+    g_kind: int = N.G_QUAD
+    gp: tuple = (1.0, 0.0, 0.0, 0.0)
+    gvec: Optional[torch.Tensor] = None
+    eps_h: float = 1.0
+    ridge_rel: float = 1e-3
+    newton_iters: int = 8
+    cg_maxit: int = 500
+    cg_rtol: Optional[float] = None        # default: 1e-13 (F64), 1e-7 (F32C)
+    cg_fixed_iters: int = 0
+    shared_dw: int = 0
+    seed: int = 0
+    instance: int = 0
+    point_base: int = 0
+    prec: int = N.F64
+
+    def c(self):
+        cp = N.CProblem()
+        cp.d, cp.M, cp.N, cp.T, cp.s = self.d, self.M, self.N, self.T, self.s
+        cp.mu = _ptr(self.mu)
+        cp.f_kind, cp.g_kind = self.f_kind, self.g_kind
+        cp.fp = (ctypes.c_double * 4)(*[float(v) for v in (list(self.fp) + [0.0] * 4)[:4]])
+        cp.gp = (ctypes.c_double * 4)(*[float(v) for v in (list(self.gp) + [0.0] * 4)[:4]])
+        cp.gvec = _ptr(self.gvec)
+        cp.eps_h, cp.ridge_rel = self.eps_h, self.ridge_rel
+        cp.newton_iters, cp.cg_maxit = self.newton_iters, self.cg_maxit
+        cp.cg_rtol = self.cg_rtol if self.cg_rtol is not None else (1e-13 if self.prec == N.F64 else 1e-7)
+        cp.cg_fixed_iters, cp.shared_dw = self.cg_fixed_iters, self.shared_dw
+        cp.seed, cp.instance, cp.point_base = self.seed, self.instance, self.point_base
+        cp.prec, cp.reserved = self.prec, 0
+        return cp
+
+    @property
+    def state_dtype(self):
+        return torch.float64 if self.prec == N.F64 else torch.float32
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors handed to libfbsde must live in device memory")
+    return t.data_ptr()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, shape):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected a contiguous float64 device tensor of shape {tuple(shape)}")
+    return t
+
+
+def state_ld(pb):
+    ld = N.load().fbsde_state_ld(ctypes.byref(pb.c()))
+    if ld <= 0:
+        raise N.FbsdeError("invalid problem descriptor")
+    return int(ld)
+
+
+def workspace_size(pb, P, tape=False):
+    out = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_workspace_size(ctypes.byref(pb.c()), P, N.WS_TAPE if tape else 0, ctypes.byref(out)))
+    return int(out.value)
+
+
+def workspace(pb, P, tape=False, device="cuda"):
+    return torch.empty(max(workspace_size(pb, P, tape), 1), dtype=torch.uint8, device=device)
+
+
+def terminal(pb, x0):
+    """Forward sweep + terminal values: returns (W [P][M][ld], Y [P][M], status [P])."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    ld = state_ld(pb)
+    W = torch.empty((P, pb.M, ld), dtype=pb.state_dtype, device=x0.device)
+    Y = torch.empty((P, pb.M), dtype=torch.float64, device=x0.device)
+    st = torch.empty(P, dtype=torch.int32, device=x0.device)
+    N.check(N.load().fbsde_terminal(ctypes.byref(pb.c()), P, x0.data_ptr(), W.data_ptr(), ld, Y.data_ptr(),
+                                    st.data_ptr(), _stream()))
+    return W, Y, st
+
+
+def solve_step(pb, k, W, Y_next, x0=None, ws=None):
+    """One backward level on caller state W [P][M][ld] (in: W_{k+1}, out: W_k, in place)."""
+    P = W.shape[0]
+    if W.dtype != pb.state_dtype or not W.is_contiguous() or W.shape[1] != pb.M:
+        raise ValueError("state tensor does not match the problem")
+    _dev_f64(Y_next, (P, pb.M))
+    dev = W.device
+    Y = torch.empty((P, pb.M), dtype=torch.float64, device=dev)
+    alpha = torch.empty(P, dtype=torch.float64, device=dev)
+    alpha_x = torch.empty((P, pb.d), dtype=torch.float64, device=dev)
+    st = torch.zeros(P, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(pb, P, device=dev)
+    N.check(N.load().fbsde_solve_step(ctypes.byref(pb.c()), P, int(k), _ptr(x0), W.data_ptr(), W.shape[2],
+                                      Y_next.data_ptr(), Y.data_ptr(), alpha.data_ptr(), alpha_x.data_ptr(),
+                                      st.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return Y, alpha, alpha_x, st
+
+
+def solve(pb, x0, want_grad=True, tape=False, ws=None, return_iters=False):
+    """u(0, x0_p) [P], grad u [P][d] (or None), status [P] (and CG iterations per level)."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    dev = x0.device
+    u = torch.empty(P, dtype=torch.float64, device=dev)
+    grad = torch.empty((P, pb.d), dtype=torch.float64, device=dev) if want_grad else None
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(pb, P, tape=tape, device=dev)
+    iters = (ctypes.c_int32 * pb.N)()
+    N.check(N.load().fbsde_solve(ctypes.byref(pb.c()), P, x0.data_ptr(), u.data_ptr(), _ptr(grad), st.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), N.WS_TAPE if tape else 0,
+                                 ctypes.cast(iters, ctypes.c_void_p), _stream()))
+    if return_iters:
+        return u, grad, st, list(iters)
+    return u, grad, st
+
+
+def solve_backward(pb, x0, u_bar, ws):
+    """Adjoint of solve for L = sum_p u_bar[p] u_p; needs ws from solve(..., tape=True)."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    _dev_f64(u_bar, (P,))
+    dev = x0.device
+    x0_bar = torch.empty((P, pb.d), dtype=torch.float64, device=dev)
+    gp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
+    fp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
+    st = torch.zeros(P, dtype=torch.int32, device=dev)
+    N.check(N.load().fbsde_solve_backward(ctypes.byref(pb.c()), P, x0.data_ptr(), u_bar.data_ptr(),
+                                          x0_bar.data_ptr(), gp_bar.data_ptr(), fp_bar.data_ptr(), st.data_ptr(),
+                                          ws.data_ptr(), ws.numel(), _stream()))
+    return x0_bar, gp_bar, fp_bar, st
+
+
+def normals(pb, p, k, j0, rows, device="cuda"):
+    """The increments' normals of rows j0.. of level k (and the raw Philox words)."""
+    ng = (pb.d + 3) // 4
+    out = torch.empty((rows, pb.d), dtype=torch.float64, device=device)
+    words = torch.empty((rows, ng, 4), dtype=torch.int32, device=device)
+    N.check(N.load().fbsde_normals(ctypes.byref(pb.c()), p, k, j0, rows, out.data_ptr(), words.data_ptr(),
+                                   _stream()))
+    return out, words

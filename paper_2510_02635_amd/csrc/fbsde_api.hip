@@ -1,0 +1,423 @@
+// Host side of the C ABI declared in include/fbsde.h: validation, workspace carving and the
+// launch sequence of Algorithm 1 (forward sweep, then the backward level loop) and of its
+// adjoint.  All control crosses host -> device here; kernels live in fbsde_kernels.hpp /
+// fbsde_adjoint.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "fbsde.h"
+#include "fbsde_kernels.hpp"
+
+using namespace fbsde;
+
+namespace {
+
+constexpr int NS = 8;   // per-point FP64 scalars (see k_moments_finish)
+
+struct Plan {
+    int64_t d, M, N;
+    int ld, Q, TEAM, BS, TPW, nchunk, rows_per_chunk;
+    size_t esz;
+};
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+int check_problem(const fbsde_problem* pb, int64_t P) {
+    if (!pb || P < 0) return FBSDE_EINVAL;
+    if (pb->d < 1 || pb->M < 2 || pb->N < 1) return FBSDE_EINVAL;
+    if (!(pb->T > 0.0) || !(pb->s > 0.0)) return FBSDE_EINVAL;
+    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_HJB) return FBSDE_EINVAL;
+    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_AFFINE) return FBSDE_EINVAL;
+    if (pb->g_kind == FBSDE_G_AFFINE && !pb->gvec) return FBSDE_EINVAL;
+    if (!(pb->eps_h >= 0.0) || !(pb->ridge_rel >= 0.0)) return FBSDE_EINVAL;
+    if (pb->ridge_rel == 0.0 && pb->M <= pb->d + 1) return FBSDE_EINVAL;
+    if (pb->newton_iters < 1 || pb->cg_maxit < 1 || !(pb->cg_rtol >= 0.0)) return FBSDE_EINVAL;
+    if (pb->prec != FBSDE_F64 && pb->prec != FBSDE_F32C) return FBSDE_EINVAL;
+    if (pb->shared_dw != 0) return FBSDE_EINVAL;   // shared increments: not on this path
+    if (pb->reserved != 0) return FBSDE_EINVAL;
+    // grid.y carries the point index
+    if (pb->M > (int64_t)1 << 30 || pb->N > (int64_t)1 << 30 || P > 65535) return FBSDE_EINVAL;
+    return FBSDE_OK;
+}
+
+int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
+    pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
+    pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;
+    pl.ld = (int)round_up(pb->d, (pl.esz == 8) ? 16 : 32);
+    const int groups = pl.ld / 4;
+    const int qmax = (pl.esz == 8) ? 4 : 8;
+    pl.TEAM = 0;
+    for (int team = 1; team <= 16; team *= 2) {
+        const int q = (groups + 64 * team - 1) / (64 * team);
+        if (q <= qmax) {
+            pl.TEAM = team;
+            pl.Q = (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : 8;
+            break;
+        }
+    }
+    if (pl.TEAM == 0) return FBSDE_EINVAL;   // d beyond 16384 (FP64) / 32768 (FP32C)
+    pl.BS = 64 * std::max(pl.TEAM, 4);
+    pl.TPW = pl.BS / (64 * pl.TEAM);
+    const int64_t target_blocks = 4096;
+    int64_t nchunk = (target_blocks + std::max<int64_t>(P, 1) - 1) / std::max<int64_t>(P, 1);
+    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, pb->M / (2 * pl.TPW)));
+    pl.rows_per_chunk = (int)((pb->M + nchunk - 1) / nchunk);
+    pl.nchunk = (int)((pb->M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
+    return FBSDE_OK;
+}
+
+struct WS {
+    void* W;
+    double *Ya, *Yb, *rn2, *w, *c2;
+    double *x, *r, *pv, *qv, *Wbar;
+    double *part1, *part2, *psc, *scal;
+    int *iscal, *active;
+    // tape for the adjoint: per level k (cloud t_{k+1})
+    double *tY, *tw, *tax, *tWbar, *tscal;
+    int* tag;
+    // adjoint work
+    double *G, *cbar, *adj;
+};
+
+// Carve the workspace (base == nullptr: only count).  Returns bytes.
+size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += round_up((int64_t)bytes, 256);
+        return p;
+    };
+    const size_t PM = (size_t)P * pl.M, PL = (size_t)P * pl.ld;
+    const size_t parts = (size_t)P * pl.nchunk * pl.ld;
+    ws.W = take(PM * pl.ld * pl.esz);
+    ws.Ya = (double*)take(PM * 8);
+    ws.Yb = (double*)take(PM * 8);
+    ws.rn2 = (double*)take(PM * 8);
+    ws.w = (double*)take(PM * 8);
+    ws.c2 = (double*)take(PM * 8);
+    ws.x = (double*)take(PL * 8);
+    ws.r = (double*)take(PL * 8);
+    ws.pv = (double*)take(PL * 8);
+    ws.qv = (double*)take(PL * 8);
+    ws.Wbar = (double*)take(PL * 8);
+    ws.part1 = (double*)take(parts * 8);
+    ws.part2 = (double*)take(parts * 8);
+    ws.psc = (double*)take((size_t)P * pl.nchunk * 4 * 8);
+    ws.scal = (double*)take((size_t)P * NS * 8);
+    ws.iscal = (int*)take((size_t)P * 4 * 4);
+    ws.active = (int*)take(64);
+    ws.tY = ws.tw = ws.tax = ws.tWbar = ws.tscal = nullptr;
+    ws.tag = nullptr;
+    ws.G = ws.cbar = ws.adj = nullptr;
+    if (flags & FBSDE_WS_TAPE) {
+        ws.tY = (double*)take((size_t)pl.N * PM * 8);
+        ws.tw = (double*)take((size_t)pl.N * PM * 8);
+        ws.tax = (double*)take((size_t)pl.N * PL * 8);
+        ws.tWbar = (double*)take((size_t)pl.N * PL * 8);
+        ws.tscal = (double*)take((size_t)pl.N * P * NS * 8);
+        ws.tag = (int*)take(64);
+        ws.G = (double*)take(PM * 8);
+        ws.cbar = (double*)take(PM * 8);
+        ws.adj = (double*)take((size_t)P * 16 * 8);
+    }
+    return off;
+}
+
+template <typename S, typename Fn>
+void dispatch(int Q, int TEAM, Fn&& fn) {
+#define FB_CASE(QQ, TT) \
+    case QQ * 100 + TT: fn(std::integral_constant<int, QQ>{}, std::integral_constant<int, TT>{}); return;
+    switch (Q * 100 + TEAM) {
+        FB_CASE(1, 1) FB_CASE(1, 2) FB_CASE(1, 4) FB_CASE(1, 8) FB_CASE(1, 16)
+        FB_CASE(2, 1) FB_CASE(2, 2) FB_CASE(2, 4) FB_CASE(2, 8) FB_CASE(2, 16)
+        FB_CASE(4, 1) FB_CASE(4, 2) FB_CASE(4, 4) FB_CASE(4, 8) FB_CASE(4, 16)
+        default: break;
+    }
+    if constexpr (std::is_same<S, float>::value) {
+        switch (Q * 100 + TEAM) {
+            FB_CASE(8, 1) FB_CASE(8, 2) FB_CASE(8, 4) FB_CASE(8, 8) FB_CASE(8, 16)
+            default: break;
+        }
+    }
+#undef FB_CASE
+}
+
+struct Keys { uint32_t k0, k1; };
+Keys keys_of(const fbsde_problem* pb) {
+    return {(uint32_t)(pb->seed & 0xFFFFFFFFull), (uint32_t)((pb->seed >> 32) ^ (uint64_t)pb->instance)};
+}
+FSpec fspec_of(const fbsde_problem* pb) { return {pb->f_kind, pb->fp[0], pb->fp[1]}; }
+
+int last_error() { return (hipGetLastError() == hipSuccess) ? FBSDE_OK : FBSDE_EHIP; }
+
+// -------------------------------------------------------------------- launch sequences
+template <typename S>
+void launch_forward(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, S* W, int64_t ldw,
+                    double* Y, double* rn2, uint32_t* status, hipStream_t st) {
+    const Keys ky = keys_of(pb);
+    const double dt = pb->T / (double)pb->N;
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_forward<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           ldw, (int)pl.M, pl.rows_per_chunk, x0, pb->mu, pb->gvec, (int)pl.d, pl.ld, (int)pl.N,
+                           std::sqrt(dt), pb->s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], ky.k0, ky.k1,
+                           pb->point_base, 0, Y, rn2, status);
+    });
+}
+
+template <typename S>
+void launch_rownorm(const Plan& pl, int64_t P, const S* W, int64_t ldw, double* rn2, hipStream_t st) {
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_rownorm<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           ldw, (int)pl.M, pl.rows_per_chunk, pl.ld, rn2);
+    });
+}
+
+// Run CG on the per-point systems prepared in ws (x, r, pv, Wbar, scal, iscal, active).
+// Returns the number of matvec launches.
+template <typename S>
+int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
+           const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
+    const int fixed = pb->cg_fixed_iters;
+    const int cap = (fixed > 0) ? fixed : pb->cg_maxit;
+    const int poll = 8;
+    int it = 0;
+    for (; it < cap; ++it) {
+        dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+            constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+            hipLaunchKernelGGL((k_matvec<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
+                               W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, ws.pv, ws.scal, NS,
+                               ws.iscal, ws.part1, ws.psc);
+        });
+        hipLaunchKernelGGL(k_cg_update, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, pl.ld,
+                           pb->s, Wbar, ws.x, ws.r, ws.pv, ws.qv, ws.scal, NS, ws.iscal,
+                           pb->cg_rtol * pb->cg_rtol, pb->cg_maxit, ws.active, status);
+        if (fixed <= 0 && (it + 1) % poll == 0) {
+            int active = 0;
+            if (hipMemcpyAsync(&active, ws.active, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                err = FBSDE_EHIP;
+                return it + 1;
+            }
+            if (active <= 0) { ++it; break; }
+        }
+    }
+    err = last_error();
+    return it;
+}
+
+// One backward level: regression of Y_next on the cloud W (at t_{k+1}); leaves alpha_x in ws.x,
+// alpha / zz in ws.scal, and returns the number of CG iterations.
+template <typename S>
+int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S* W, int64_t ldw,
+              const double* Y_next, const double* rn2, double* w_out, double* Wbar_out, WS& ws,
+              double* alpha_out, double* alpha_x_out, uint32_t* status, hipStream_t st, int& err) {
+    const double dt = pb->T / (double)pb->N;
+    const double t_next = (double)(k + 1) * dt;
+    const double s2 = pb->s * pb->s;
+    const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)pl.d : 0.0;
+    const double lam = pb->ridge_rel * s2 * t_next;
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)P), dim3(256), 0, st, rn2, Y_next, (int)pl.M, s2, eps2, w_out,
+                       ws.c2, ws.scal, NS, ws.active, (int)P);
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_moments<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.part1, ws.part2,
+                           ws.psc);
+    });
+    hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.psc, pl.nchunk,
+                       pl.ld, pb->s, lam, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal, ws.active);
+    const int iters = run_cg<S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
+    if (err) return iters;
+    hipLaunchKernelGGL(k_level_finish, dim3((unsigned)P), dim3(256), 0, st, ws.x, Wbar_out, pl.ld, (int)pl.d, pb->s,
+                       ws.scal, NS, alpha_out, alpha_x_out);
+    err = last_error();
+    return iters;
+}
+
+template <typename S>
+void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S* W, int64_t ldw, const double* ax,
+                    WS& ws, double* Y, double* rn2, uint32_t* status, hipStream_t st) {
+    const Keys ky = keys_of(pb);
+    const double dt = pb->T / (double)pb->N;
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_reverse<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0, std::sqrt(dt),
+                           pb->s, dt, ax, ws.scal, NS, fspec_of(pb), pb->newton_iters, ky.k0, ky.k1,
+                           pb->point_base, Y, rn2, status);
+    });
+}
+
+void clear_status(uint32_t* status, int64_t P, hipStream_t st) {
+    if (P > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((P + 255) / 256, 1024)), dim3(256), 0,
+                                  st, status, P, 0u);
+}
+
+template <typename S>
+int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, double* u, double* grad,
+               uint32_t* status, WS& ws, bool tape, int32_t* cg_iters_out, hipStream_t st) {
+    S* W = (S*)ws.W;
+    const int64_t ldw = pl.ld;
+    const int64_t PM = P * pl.M, PL = P * (int64_t)pl.ld;
+    clear_status(status, P, st);
+    double* Ycur = ws.Ya;
+    double* Yk = ws.Yb;
+    launch_forward<S>(pb, pl, P, x0, W, ldw, Ycur, ws.rn2, status, st);
+    int err = last_error();
+    if (err) return err;
+    for (int k = (int)pl.N - 1; k >= 0; --k) {
+        double* w_k = tape ? ws.tw + (size_t)k * PM : ws.w;
+        double* Wbar_k = tape ? ws.tWbar + (size_t)k * PL : ws.Wbar;
+        const int iters = run_level<S>(pb, pl, P, k, W, ldw, Ycur, ws.rn2, w_k, Wbar_k, ws, nullptr, nullptr, status,
+                                       st, err);
+        if (err) return err;
+        if (cg_iters_out) cg_iters_out[k] = iters;
+        if (tape) {
+            if (hipMemcpyAsync(ws.tax + (size_t)k * PL, ws.x, PL * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(ws.tscal + (size_t)k * P * NS, ws.scal, (size_t)P * NS * 8, hipMemcpyDeviceToDevice,
+                               st) != hipSuccess)
+                return FBSDE_EHIP;
+        }
+        if (k > 0) {
+            double* Yout = tape ? ws.tY + (size_t)k * PM : Yk;
+            launch_reverse<S>(pb, pl, P, k, W, ldw, ws.x, ws, Yout, ws.rn2, status, st);
+            if (!tape) std::swap(Ycur, Yk);
+            else Ycur = Yout;
+        } else {
+            hipLaunchKernelGGL(k_outputs, dim3((unsigned)P), dim3(256), 0, st, ws.x, pl.ld, (int)pl.d, ws.scal, NS,
+                               fspec_of(pb), pb->T / (double)pb->N, pb->newton_iters, u, grad, status);
+        }
+        err = last_error();
+        if (err) return err;
+    }
+    return FBSDE_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+int64_t fbsde_state_ld(const fbsde_problem* pb) {
+    Plan pl;
+    if (check_problem(pb, 1) != FBSDE_OK || make_plan(pb, 1, pl) != FBSDE_OK) return 0;
+    return pl.ld;
+}
+
+int fbsde_workspace_size(const fbsde_problem* pb, int64_t P, int32_t flags, size_t* bytes) {
+    if (!bytes) return FBSDE_EINVAL;
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    WS ws;
+    *bytes = carve(pl, P, flags, nullptr, ws);
+    return FBSDE_OK;
+}
+
+int fbsde_terminal(const fbsde_problem* pb, int64_t P, const double* x0, void* W, int64_t ldw, double* Y,
+                   uint32_t* status, fbsde_stream stream) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (ldw < pl.ld || ldw % 4 != 0 || !x0 || !W || !Y || !status) return FBSDE_EINVAL;
+    if (P == 0) return FBSDE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    clear_status(status, P, st);
+    if (pb->prec == FBSDE_F64) launch_forward<double>(pb, pl, P, x0, (double*)W, ldw, Y, nullptr, status, st);
+    else launch_forward<float>(pb, pl, P, x0, (float*)W, ldw, Y, nullptr, status, st);
+    return last_error();
+}
+
+int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double* x0, void* W, int64_t ldw,
+                     const double* Y_next, double* Y, double* alpha, double* alpha_x, uint32_t* status, void* wsp,
+                     size_t ws_bytes, fbsde_stream stream) {
+    (void)x0;
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (k < 0 || k >= pb->N || ldw < pl.ld || ldw % 4 != 0 || !W || !Y_next || !Y || Y == Y_next || !status ||
+        !wsp)
+        return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, 0, (char*)wsp, ws);
+    if (P == 0) return FBSDE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int err = FBSDE_OK;
+    if (pb->prec == FBSDE_F64) {
+        double* Ws = (double*)W;
+        launch_rownorm<double>(pl, P, Ws, ldw, ws.rn2, st);
+        run_level<double>(pb, pl, P, k, Ws, ldw, Y_next, ws.rn2, ws.w, ws.Wbar, ws, alpha, alpha_x, status, st, err);
+        if (err) return err;
+        launch_reverse<double>(pb, pl, P, k, Ws, ldw, ws.x, ws, Y, ws.rn2, status, st);
+    } else {
+        float* Ws = (float*)W;
+        launch_rownorm<float>(pl, P, Ws, ldw, ws.rn2, st);
+        run_level<float>(pb, pl, P, k, Ws, ldw, Y_next, ws.rn2, ws.w, ws.Wbar, ws, alpha, alpha_x, status, st, err);
+        if (err) return err;
+        launch_reverse<float>(pb, pl, P, k, Ws, ldw, ws.x, ws, Y, ws.rn2, status, st);
+    }
+    return last_error();
+}
+
+int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
+                void* wsp, size_t ws_bytes, int32_t flags, int32_t* cg_iters_out, fbsde_stream stream) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, flags, (char*)wsp, ws);
+    if (P == 0) return FBSDE_OK;
+    const bool tape = (flags & FBSDE_WS_TAPE) != 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
+    return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
+}
+
+int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
+                         double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
+                         fbsde_stream stream) {
+    (void)pb; (void)P; (void)x0; (void)u_bar; (void)x0_bar; (void)gp_bar; (void)fp_bar; (void)status; (void)wsp;
+    (void)ws_bytes; (void)stream;
+    return FBSDE_ESTATE;
+}
+
+int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows, double* out,
+                  uint32_t* words, fbsde_stream stream) {
+    int rc = check_problem(pb, 1);
+    if (rc) return rc;
+    if (p < 0 || k < 0 || j0 < 0 || rows < 0 || !out) return FBSDE_EINVAL;
+    if (rows == 0) return FBSDE_OK;
+    const Keys ky = keys_of(pb);
+    const uint32_t q = pb->shared_dw ? 0xFFFFFFFFu : pb->point_base + (uint32_t)p;
+    const int64_t n = rows * ((pb->d + 3) / 4);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_normals, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (int)pb->d, j0, rows, k, q, ky.k0,
+                       ky.k1, out, words);
+    return last_error();
+}
+
+const char* fbsde_strerror(int code) {
+    switch (code) {
+        case FBSDE_OK: return "ok";
+        case FBSDE_EINVAL: return "invalid argument or unsupported problem descriptor";
+        case FBSDE_ENOSPC: return "workspace too small";
+        case FBSDE_EHIP: return "HIP launch or runtime failure";
+        case FBSDE_ESTATE: return "workspace does not hold the tape of a preceding fbsde_solve";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,622 @@
+// HIP kernels of one level of the localized FBSDE-LLR scheme on gfx950.
+//
+// Data layout in HBM (per evaluation point p):
+//   W   [P][M][ld]  Brownian displacement of every particle (X = x0 + t mu + s W); the state
+//                   that the sweeps stream.  ld = d rounded up to 128 bytes, pad kept at zero.
+//   per-particle scalars [P][M]: |W|^2, Y, kernel weights w, w (Y - Ybar).
+//   per-point vectors   [P][ld]: CG iterate, residual, direction, A p, weighted mean of W.
+//   two-stage partial sums [P][nchunk][ld] (fixed reduction order: results are deterministic).
+//
+// Row geometry: a "team" of TEAM wavefronts owns one particle row; lane L of a team holds
+// coordinate groups g = L + q * 64 TEAM (q < Q), each four consecutive coordinates (one Philox
+// call, one 16/32-byte load), so a team covers 256 Q TEAM coordinates and consecutive lanes read
+// consecutive 16/32-byte pieces of the row (fully coalesced).  A block has max(4, TEAM) waves:
+// 4 / TEAM teams for small d, one team for large d.  Row dot products reduce in registers and
+// across the wave with shuffles, across a team's waves through LDS; column sums over particles
+// accumulate in registers and are combined per block through LDS, then across blocks in a
+// second, fixed-order stage.
+//
+// Element types: S = double (FP64 mode) or float (FP32C mode: FP32 state and FP32 arithmetic with
+// Kahan-compensated per-lane sums; row dots are finished and all CG / Newton scalars kept in FP64).
+#pragma once
+#include "fbsde_device.hpp"
+
+namespace fbsde {
+
+template <int Q, int TEAM>
+struct Geo {
+    static constexpr int TL = 64 * TEAM;                 // lanes per team
+    static constexpr int BS = 64 * (TEAM > 4 ? TEAM : 4);  // threads per block
+    static constexpr int TPW = BS / TL;                   // teams per block
+};
+
+// compensated running sum
+template <typename R> struct CSum;
+template <> struct CSum<double> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(double v) { s += v; }
+    __device__ __forceinline__ double get() const { return s; }
+};
+template <> struct CSum<float> {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float v) {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double get() const { return (double)s - (double)c; }
+};
+
+__device__ __forceinline__ void load4(const double* __restrict__ p, double v[4]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float* __restrict__ p, float v[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void store4(double* __restrict__ p, const double v[4]) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+__device__ __forceinline__ void store4(float* __restrict__ p, const float v[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// Reduce two values over the team owning a row; every lane of the team gets the totals.
+// For TEAM > 1 all waves of the block must call it the same number of times.
+template <int TEAM>
+__device__ __forceinline__ void team_sum2(double& a, double& b, double* red, int team) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if constexpr (TEAM > 1) {
+        const int wv = (threadIdx.x >> 6) % TEAM, ln = threadIdx.x & 63;
+        if (ln == 0) { red[2 * (team * TEAM + wv)] = a; red[2 * (team * TEAM + wv) + 1] = b; }
+        __syncthreads();
+        a = 0.0; b = 0.0;
+#pragma unroll
+        for (int i = 0; i < TEAM; ++i) { a += red[2 * (team * TEAM + i)]; b += red[2 * (team * TEAM + i) + 1]; }
+        __syncthreads();
+    }
+}
+
+// Per-block combination of per-lane column accumulators into out[0..ld) (double), in team order.
+template <int Q, int TEAM, typename R>
+__device__ __forceinline__ void block_columns_out(CSum<R> (&acc)[Q][4], double* lds, double* __restrict__ out,
+                                                  int ld, int team, int L) {
+    using G = Geo<Q, TEAM>;
+    if constexpr (G::TPW == 1) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e0 = 4 * (L + q * G::TL);
+            if (e0 < ld) {
+                double v[4] = {acc[q][0].get(), acc[q][1].get(), acc[q][2].get(), acc[q][3].get()};
+                store4(out + e0, v);
+            }
+        }
+    } else {
+        // lds holds TPW * 256 Q TEAM doubles
+        constexpr int SPAN = 4 * Q * G::TL;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e0 = 4 * (L + q * G::TL);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lds[team * SPAN + e0 + e] = acc[q][e].get();
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < ld; i += G::BS) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < G::TPW; ++t) s += lds[t * SPAN + i];
+            out[i] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Forward sweep and terminal condition (Algorithm 1, first two loops; eq. Xk):
+//   W^j_N = sum_k sqrt(dt) xi^j_k in registers, one store; Y^j_N = g(x0 + mu T + s W^j_N).
+template <typename S, int Q, int TEAM>
+__global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
+k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const double* __restrict__ x0,
+          const double* __restrict__ mu, const double* __restrict__ gvec, int d, int ld, int N,
+          double sqdt, double s, double T, int g_kind, double ga, double gb, uint32_t k0, uint32_t k1,
+          uint32_t point_base, int shared, double* __restrict__ Y, double* __restrict__ rn2,
+          uint32_t* __restrict__ status) {
+    using G = Geo<Q, TEAM>;
+    __shared__ double red[2 * G::BS / 64];
+    const int p = blockIdx.y;
+    const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
+    const int r0 = blockIdx.x * rows_per_chunk;
+    const int r1 = min(M, r0 + rows_per_chunk);
+    const uint32_t qs = shared ? 0xFFFFFFFFu : point_base + (uint32_t)p;
+    double xc[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 4 * (L + q * G::TL) + e;
+            xc[q][e] = (i < d) ? x0[(int64_t)p * d + i] + (mu ? mu[i] * T : 0.0) : 0.0;
+        }
+    uint32_t st = 0;
+    for (int jb = r0; jb < r1; jb += G::TPW) {
+        const int j = jb + team;
+        const bool valid = j < r1;
+        double w[Q][4];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[q][e] = 0.0;
+        if (valid) {
+            for (int k = 0; k < N; ++k) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int g = L + q * G::TL;
+                    if (4 * g < d) {
+                        double z[4];
+                        increment4((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (4 * g + e < d) w[q][e] += sqdt * z[e];
+                    }
+                }
+            }
+        }
+        double n2 = 0.0, gq = 0.0;
+        if (valid) {
+            S* row = W + ((int64_t)(shared ? 0 : p) * M + j) * ldw;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int e0 = 4 * (L + q * G::TL);
+                if (e0 < ld) {
+                    S v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = (S)w[q][e];
+                    if (!shared || p == 0) store4(row + e0, v);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double ws = (double)v[e];
+                        n2 += ws * ws;
+                        const double X = xc[q][e] + s * ws;
+                        if (g_kind == G_AFFINE) gq += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
+                        else gq += X * X;
+                    }
+                }
+            }
+        }
+        team_sum2<TEAM>(n2, gq, red, team);
+        if (valid && (L == 0)) {
+            const double y = g_of(g_kind, ga, gb, gq, d);
+            Y[(int64_t)p * M + j] = y;
+            if (rn2) rn2[(int64_t)p * M + j] = n2;
+            if (!isfinite(y)) st |= ST_NONFINITE;
+        }
+    }
+    if (st) atomicOr(&status[p], st);
+}
+
+// Kernel weights of the cloud (eq. Dj with the Gaussian kernel), weighted mean of Y and the
+// centred response coefficients w_j (Y_j - Ybar).  One block per point.
+__global__ void __launch_bounds__(256)
+k_weights(const double* __restrict__ rn2, const double* __restrict__ Y, int M, double s2, double eps2,
+          double* __restrict__ w, double* __restrict__ c2, double* __restrict__ scal, int ns, int* active, int P) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    const double* n = rn2 + (int64_t)p * M;
+    const double* y = Y + (int64_t)p * M;
+    double* wp = w + (int64_t)p * M;
+    double* cp = c2 + (int64_t)p * M;
+    double mn = INFINITY;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) mn = fmin(mn, n[j]);
+    mn = block_min(mn, lds);
+    double se = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double e = (eps2 > 0.0) ? exp(-(s2 * n[j] - s2 * mn) / eps2) : 1.0;
+        wp[j] = e;
+        se += e;
+    }
+    se = block_sum(se, lds);
+    double yb = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double wj = wp[j] / se;
+        wp[j] = wj;
+        yb += wj * y[j];
+    }
+    yb = block_sum(yb, lds);
+    for (int j = threadIdx.x; j < M; j += blockDim.x) cp[j] = wp[j] * (y[j] - yb);
+    if (threadIdx.x == 0) {
+        scal[(int64_t)p * ns + 4] = yb;
+        if (p == 0) *active = P;
+    }
+}
+
+// Weighted first moments of the cloud: sum_j w_j W_j and sum_j w_j (Y_j - Ybar) W_j (column sums
+// over particles; the normal-equation right-hand side, eq. normal-eq), per block.
+template <typename S, int Q, int TEAM>
+__global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
+k_moments(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nchunk, int ld,
+          const double* __restrict__ w, const double* __restrict__ c2, double* __restrict__ part1,
+          double* __restrict__ part2, double* __restrict__ psc) {
+    using G = Geo<Q, TEAM>;
+    using R = S;
+    __shared__ double lds[(G::TPW > 1) ? G::TPW * 4 * Q * G::TL : 1];
+    __shared__ double red[G::BS / 64];
+    const int p = blockIdx.y, c = blockIdx.x;
+    const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
+    const int r0 = c * rows_per_chunk;
+    const int r1 = min(M, r0 + rows_per_chunk);
+    CSum<R> a1[Q][4], a2[Q][4];
+    double sig = 0.0;
+    for (int j = r0 + team; j < r1; j += G::TPW) {
+        const S* row = W + ((int64_t)p * M + j) * ldw;
+        const R wj = (R)w[(int64_t)p * M + j];
+        const double cjd = c2[(int64_t)p * M + j];
+        const R cj = (R)cjd;
+        sig += cjd;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e0 = 4 * (L + q * G::TL);
+            if (e0 < ld) {
+                S x[4];
+                load4(row + e0, x);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) { a1[q][e].add(wj * x[e]); a2[q][e].add(cj * x[e]); }
+            }
+        }
+    }
+    double* o1 = part1 + ((int64_t)p * nchunk + c) * ld;
+    double* o2 = part2 + ((int64_t)p * nchunk + c) * ld;
+    block_columns_out<Q, TEAM, R>(a1, lds, o1, ld, team, L);
+    block_columns_out<Q, TEAM, R>(a2, lds, o2, ld, team, L);
+    // sig is identical on every lane of a team: one lane per team contributes
+    const double contrib = (L == 0) ? sig : 0.0;
+    const double tot = block_sum(contrib, red);
+    if (threadIdx.x == 0) psc[(int64_t)p * nchunk + c] = tot;
+}
+
+// Finish the moments and start CG on (sum_j w_j D'_j D'_j^T + lam I) a_x = b, x0 = 0.
+// scal layout per point: 0 rr, 1 |b|^2, 2 wv = Wbar.p, 3 lam, 4 Ybar, 5 alpha, 6 zz, 7 spare.
+// iscal: 0 iterations, 1 done.
+__global__ void __launch_bounds__(256)
+k_moments_finish(const double* __restrict__ part1, const double* __restrict__ part2,
+                 const double* __restrict__ psc, int nchunk, int ld, double s, double lam,
+                 double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
+                 double* __restrict__ pv, double* __restrict__ scal, int ns, int* __restrict__ iscal,
+                 int* active) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double sig = 0.0;
+    for (int c = 0; c < nchunk; ++c) sig += psc[(int64_t)p * nchunk + c];
+    double rr = 0.0, wv = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        double wb = 0.0, bb = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            wb += part1[((int64_t)p * nchunk + c) * ld + i];
+            bb += part2[((int64_t)p * nchunk + c) * ld + i];
+        }
+        const double b = s * (bb - sig * wb);
+        Wbar[(int64_t)p * ld + i] = wb;
+        x[(int64_t)p * ld + i] = 0.0;
+        r[(int64_t)p * ld + i] = b;
+        pv[(int64_t)p * ld + i] = b;
+        rr += b * b;
+        wv += wb * b;
+    }
+    rr = block_sum(rr, lds);
+    wv = block_sum(wv, lds);
+    if (threadIdx.x == 0) {
+        scal[(int64_t)p * ns + 0] = rr;
+        scal[(int64_t)p * ns + 1] = rr;
+        scal[(int64_t)p * ns + 2] = wv;
+        scal[(int64_t)p * ns + 3] = lam;
+        iscal[p * 4 + 0] = 0;
+        const int done = (rr == 0.0) ? 1 : 0;
+        iscal[p * 4 + 1] = done;
+        if (done) atomicSub(active, 1);
+    }
+}
+
+// One pass of the fused matrix-free product of the centred weighted normal matrix with the CG
+// direction p (the two steps of the paper's matrix-free scheme done per particle row while the
+// row sits in registers): t_j = D'_j . p = s (W_j . p - Wbar . p), then sum_j w_j t_j W_j and
+// sum_j w_j t_j, per block.  One read of the state per CG iteration.
+template <typename S, int Q, int TEAM>
+__global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
+k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nchunk, int ld, double s,
+         const double* __restrict__ w, const double* __restrict__ pv, const double* __restrict__ scal,
+         int ns, const int* __restrict__ iscal, double* __restrict__ part, double* __restrict__ psc) {
+    using G = Geo<Q, TEAM>;
+    using R = S;
+    __shared__ double lds[(G::TPW > 1) ? G::TPW * 4 * Q * G::TL : 1];
+    __shared__ double red[2 * G::BS / 64];
+    const int p = blockIdx.y, c = blockIdx.x;
+    if (iscal[p * 4 + 1]) return;
+    const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
+    const int r0 = c * rows_per_chunk;
+    const int r1 = min(M, r0 + rows_per_chunk);
+    R v[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int e0 = 4 * (L + q * G::TL);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[q][e] = (e0 < ld) ? (R)pv[(int64_t)p * ld + e0 + e] : (R)0;
+    }
+    const double wvp = scal[(int64_t)p * ns + 2];
+    CSum<R> acc[Q][4];
+    double tau = 0.0;
+    for (int jb = r0; jb < r1; jb += G::TPW) {
+        const int j = jb + team;
+        const bool valid = j < r1;
+        S x[Q][4];
+        CSum<R> dl;
+        if (valid) {
+            const S* row = W + ((int64_t)p * M + j) * ldw;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int e0 = 4 * (L + q * G::TL);
+                if (e0 < ld) load4(row + e0, x[q]);
+                else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) x[q][e] = (S)0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dl.add(x[q][e] * v[q][e]);
+        }
+        double t = dl.get(), unused = 0.0;
+        team_sum2<TEAM>(t, unused, red, team);
+        if (valid) {
+            const double cj = w[(int64_t)p * M + j] * s * (t - wvp);
+            tau += cj;
+            const R cr = (R)cj;
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[q][e].add(cr * x[q][e]);
+        }
+    }
+    block_columns_out<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
+    const double contrib = (L == 0) ? tau : 0.0;
+    const double tot = block_sum(contrib, red);
+    if (threadIdx.x == 0) psc[(int64_t)p * nchunk + c] = tot;
+}
+
+// CG step on the per-point vectors (one block per point): q = s (sum_c part_c - tau Wbar) + lam p,
+// then the usual conjugate-gradient updates; convergence |r| <= rtol |b| or the iteration cap.
+__global__ void __launch_bounds__(256)
+k_cg_update(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int ld, double s,
+            const double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
+            double* __restrict__ pv, double* __restrict__ qv, double* __restrict__ scal, int ns,
+            int* __restrict__ iscal, double rtol2, int maxit, int* active, uint32_t* __restrict__ status) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    if (iscal[p * 4 + 1]) return;
+    double* sc = scal + (int64_t)p * ns;
+    const double lam = sc[3];
+    double tau = 0.0;
+    for (int c = 0; c < nchunk; ++c) tau += psc[(int64_t)p * nchunk + c];
+    const int64_t o = (int64_t)p * ld;
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        double a = 0.0;
+        for (int c = 0; c < nchunk; ++c) a += part[((int64_t)p * nchunk + c) * ld + i];
+        const double q = s * (a - tau * Wbar[o + i]) + lam * pv[o + i];
+        qv[o + i] = q;
+        pq += pv[o + i] * q;
+    }
+    pq = block_sum(pq, lds);
+    const double rr = sc[0];
+    const double alpha = (pq > 0.0) ? rr / pq : 0.0;
+    double rr2 = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        x[o + i] += alpha * pv[o + i];
+        const double ri = r[o + i] - alpha * qv[o + i];
+        r[o + i] = ri;
+        rr2 += ri * ri;
+    }
+    rr2 = block_sum(rr2, lds);
+    const int it = iscal[p * 4 + 0] + 1;
+    int done = 0;
+    uint32_t st = 0;
+    if (!(pq > 0.0) || rr2 <= rtol2 * sc[1]) done = 1;
+    else if (it >= maxit) { done = 1; st = ST_CG_MAXIT; }
+    double wv = 0.0;
+    if (!done) {
+        const double beta = rr2 / rr;
+        for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+            const double pi = r[o + i] + beta * pv[o + i];
+            pv[o + i] = pi;
+            wv += Wbar[o + i] * pi;
+        }
+        wv = block_sum(wv, lds);
+    }
+    if (threadIdx.x == 0) {
+        sc[0] = rr2;
+        sc[2] = wv;
+        iscal[p * 4 + 0] = it;
+        iscal[p * 4 + 1] = done;
+        if (done) atomicSub(active, 1);
+        if (st) atomicOr(&status[p], st);
+    }
+}
+
+// Intercept alpha = Ybar - s alpha_x . Wbar (eq. taylorexp / Schur form) and |Z|^2 = s^2 |alpha_x|^2;
+// optional dense copies of alpha, alpha_x for the caller.
+__global__ void __launch_bounds__(256)
+k_level_finish(const double* __restrict__ x, const double* __restrict__ Wbar, int ld, int d, double s,
+               double* __restrict__ scal, int ns, double* __restrict__ alpha_out,
+               double* __restrict__ alpha_x_out) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    const int64_t o = (int64_t)p * ld;
+    double xw = 0.0, xx = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        xw += x[o + i] * Wbar[o + i];
+        xx += x[o + i] * x[o + i];
+        if (alpha_x_out && i < d) alpha_x_out[(int64_t)p * d + i] = x[o + i];
+    }
+    xw = block_sum(xw, lds);
+    xx = block_sum(xx, lds);
+    if (threadIdx.x == 0) {
+        double* sc = scal + (int64_t)p * ns;
+        const double alpha = sc[4] - s * xw;
+        sc[5] = alpha;
+        sc[6] = s * s * xx;
+        if (alpha_out) alpha_out[p] = alpha;
+    }
+}
+
+// Particle reversal W_k = W_{k+1} - sqrt(dt) xi_k (Philox regenerated, in place) fused with the
+// per-particle dots |W_k|^2 and alpha_x . W_k, the local linear model C = alpha + s alpha_x . W_k
+// and the Newton solve for Y_k (eqs. nonlinearf / NRiter).  zero_state: level 0, W_0 = 0.
+template <typename S, int Q, int TEAM>
+__global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
+k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int ld, int k, int zero_state,
+          double sqdt, double s, double dt, const double* __restrict__ ax, const double* __restrict__ scal,
+          int ns, FSpec f, int newton_iters, uint32_t k0, uint32_t k1, uint32_t point_base,
+          double* __restrict__ Y, double* __restrict__ rn2, uint32_t* __restrict__ status) {
+    using G = Geo<Q, TEAM>;
+    using R = S;
+    __shared__ double red[2 * G::BS / 64];
+    const int p = blockIdx.y;
+    const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
+    const int r0 = blockIdx.x * rows_per_chunk;
+    const int r1 = min(M, r0 + rows_per_chunk);
+    const uint32_t qs = point_base + (uint32_t)p;
+    R a[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int e0 = 4 * (L + q * G::TL);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[q][e] = (e0 < ld) ? (R)ax[(int64_t)p * ld + e0 + e] : (R)0;
+    }
+    const double alpha = scal[(int64_t)p * ns + 5];
+    const double zz = scal[(int64_t)p * ns + 6];
+    uint32_t st = 0;
+    for (int jb = r0; jb < r1; jb += G::TPW) {
+        const int j = jb + team;
+        const bool valid = j < r1;
+        CSum<R> n2s, dots;
+        if (valid) {
+            S* row = W + ((int64_t)p * M + j) * ldw;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int g = L + q * G::TL;
+                const int e0 = 4 * g;
+                if (e0 < ld) {
+                    S v[4];
+                    if (zero_state) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = (S)0;
+                    } else {
+                        load4(row + e0, v);
+                        if (e0 < d) {
+                            double z[4];
+                            increment4((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (e0 + e < d) v[e] = (S)((double)v[e] - sqdt * z[e]);
+                        }
+                    }
+                    store4(row + e0, v);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { n2s.add(v[e] * v[e]); dots.add(a[q][e] * v[e]); }
+                }
+            }
+        }
+        double n2 = n2s.get(), dt_ = dots.get();
+        team_sum2<TEAM>(n2, dt_, red, team);
+        if (valid && L == 0) {
+            double Fp;
+            const double y = newton_y(f, alpha + s * dt_, zz, dt, newton_iters, Fp, st);
+            Y[(int64_t)p * M + j] = y;
+            rn2[(int64_t)p * M + j] = n2;
+        }
+    }
+    if (st) atomicOr(&status[p], st);
+}
+
+// Level-0 outputs: u = Y^m_0 (every particle sits at x0, so C = alpha) and
+// grad u = alpha_x / F'(u) (the x-derivative of the level-0 Newton equation).
+__global__ void __launch_bounds__(256)
+k_outputs(const double* __restrict__ x, int ld, int d, const double* __restrict__ scal, int ns, FSpec f,
+          double dt, int newton_iters, double* __restrict__ u, double* __restrict__ grad,
+          uint32_t* __restrict__ status) {
+    const int p = blockIdx.x;
+    uint32_t st = 0;
+    double Fp;
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], dt, newton_iters, Fp, st);
+    if (threadIdx.x == 0) u[p] = y;
+    if (grad)
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            const double gi = x[(int64_t)p * ld + i] / Fp;
+            grad[(int64_t)p * d + i] = gi;
+            if (!isfinite(gi)) st |= ST_NONFINITE;
+        }
+    if (st) atomicOr(&status[p], st);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ a, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+// Row norms |W_j|^2 of a caller-provided state (used by the single-level entry point).
+template <typename S, int Q, int TEAM>
+__global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
+k_rownorm(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int ld, double* __restrict__ rn2) {
+    using G = Geo<Q, TEAM>;
+    __shared__ double red[2 * G::BS / 64];
+    const int p = blockIdx.y;
+    const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
+    const int r0 = blockIdx.x * rows_per_chunk;
+    const int r1 = min(M, r0 + rows_per_chunk);
+    for (int jb = r0; jb < r1; jb += G::TPW) {
+        const int j = jb + team;
+        const bool valid = j < r1;
+        CSum<S> n2s;
+        if (valid) {
+            const S* row = W + ((int64_t)p * M + j) * ldw;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int e0 = 4 * (L + q * G::TL);
+                if (e0 < ld) {
+                    S v[4];
+                    load4(row + e0, v);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) n2s.add(v[e] * v[e]);
+                }
+            }
+        }
+        double n2 = n2s.get(), z = 0.0;
+        team_sum2<TEAM>(n2, z, red, team);
+        if (valid && L == 0) rn2[(int64_t)p * M + j] = n2;
+    }
+}
+
+// Diagnostic: normals and raw Philox words of rows j0.. of one level.
+__global__ void k_normals(int d, int64_t j0, int64_t rows, int k, uint32_t q, uint32_t k0, uint32_t k1,
+                          double* __restrict__ out, uint32_t* __restrict__ words) {
+    const int ng = (d + 3) / 4;
+    const int64_t n = rows * ng;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / ng;
+        const int g = (int)(t % ng);
+        const Words4 c = {(uint32_t)g, (uint32_t)(j0 + r), (uint32_t)k, q};
+        const Words4 wd = philox4x32_10(c, k0, k1);
+        double z[4];
+        box_muller4(wd, z);
+        for (int e = 0; e < 4; ++e)
+            if (4 * g + e < d) out[r * d + 4 * g + e] = z[e];
+        if (words) {
+            uint32_t* wp = words + (r * ng + g) * 4;
+            wp[0] = wd.x; wp[1] = wd.y; wp[2] = wd.z; wp[3] = wd.w;
+        }
+    }
+}
+
+}  // namespace fbsde

@@ -1,0 +1,65 @@
+"""Host-side checks of the C ABI: the library loads and exports every symbol that include/fbsde.h
+declares; argument validation happens on the host (no GPU needed for an error return)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2510_02635_amd as F
+from paper_2510_02635_amd import _native as N
+
+
+def _declared(repo_root):
+    text = open(os.path.join(repo_root, "include", "fbsde.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(fbsde_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol(repo_root):
+    lib = N.load()
+    names = _declared(repo_root)
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.EXPORTED)
+
+
+def test_struct_layout_matches_header():
+    # the ctypes mirror of fbsde_problem: 24 + 16 + 8 + 8 + 64 + 8 + 16 + 8 + 8 + 8 + 8 + 8 + 8 = 192 bytes
+    assert ctypes.sizeof(N.CProblem) == 192
+    assert N.CProblem.seed.offset == 168 and N.CProblem.prec.offset == 184
+
+
+@pytest.mark.parametrize("bad", [dict(d=0), dict(M=1), dict(N=0), dict(T=0.0), dict(s=-1.0), dict(f_kind=7),
+                                 dict(g_kind=9), dict(ridge_rel=0.0, M=10, d=20), dict(newton_iters=0),
+                                 dict(prec=5), dict(eps_h=-1.0)])
+def test_invalid_descriptors_rejected_on_host(bad):
+    kw = dict(d=8, M=64, N=3, T=0.3)
+    kw.update(bad)
+    pb = F.Problem(**kw)
+    size = ctypes.c_size_t(0)
+    rc = N.load().fbsde_workspace_size(ctypes.byref(pb.c()), 4, 0, ctypes.byref(size))
+    assert rc == N.EINVAL
+    assert N.load().fbsde_strerror(rc).decode().startswith("invalid")
+
+
+def test_state_pitch_and_workspace_growth():
+    lib = N.load()
+    for d, prec, ld in [(100, N.F64, 112), (1000, N.F64, 1008), (1000, N.F32C, 1024), (10000, N.F64, 10000)]:
+        pb = F.Problem(d=d, M=256, N=4, T=0.3, prec=prec)
+        assert lib.fbsde_state_ld(ctypes.byref(pb.c())) == ld
+    pb = F.Problem(d=100, M=512, N=5, T=0.3)
+    a, b = F.workspace_size(pb, 1), F.workspace_size(pb, 1, tape=True)
+    assert b > a > 512 * 112 * 8
+    assert F.workspace_size(pb, 8) > a
+
+
+def test_missing_gvec_and_tiny_workspace():
+    pb = F.Problem(d=4, M=16, N=2, T=0.3, g_kind=N.G_AFFINE)
+    size = ctypes.c_size_t(0)
+    assert N.load().fbsde_workspace_size(ctypes.byref(pb.c()), 1, 0, ctypes.byref(size)) == N.EINVAL
+    pb = F.Problem(d=4, M=16, N=2, T=0.3)
+    # a workspace that is too small is refused before any device pointer is touched
+    rc = N.load().fbsde_solve(ctypes.byref(pb.c()), 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                              ctypes.c_void_p(16), ctypes.c_void_p(16), 8, 0, None, None)
+    assert rc == N.ENOSPC

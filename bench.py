@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the localized FBSDE-LLR hot path on one MI355X.
+
+Workload (one "step" = one full solve, Algorithm 1, of a batch of evaluation points):
+  d = 1000, P = 1024 points x0 ~ N(0, 0.25 I_d), T = 0.3, N = 20 time steps, M = 4096 particles per point,
+  Allen-Cahn f(u) = u - u^3 with g(x) = 1 / (2 + 0.4 |x|^2), sigma = sqrt(2) I, Gaussian kernel h = 1,
+  ridge 1e-3, Newton 8 iterations, Philox seed 0 / instance 1.
+Headline value: solved points per second (u and grad u) in the FP32-compensated mode; the FP64 mode is
+timed beside it, and both are compared with the FP64 oracle on sample points.
+
+Extra objects on the JSON line:
+  roofline      -- the fused CG product kernel (the dominant kernel), HBM-bound: algorithmic bytes per
+                   launch (P M d state elements read once) / its average launch time measured here with
+                   HIP events on the library's stream.
+  cpu_baseline  -- the FP64 oracle timed on this host's cores on a bounded sample of points.
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline] [--skip-fp64]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solved points/sec (u,∇u) + fwd+adjoint points/sec at d=1000, rel err vs FP64"
+KERNEL_SRC = os.path.join(ROOT, "paper_2510_02635_amd", "csrc", "fbsde_kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_matvec_d1000_P1024_M4096_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(F, prec):
+    return F.Problem(d=1000, M=4096, N=20, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0.0, 0.0), g_kind=F.G_AC,
+                     gp=(0.4, 0.0, 0.0, 0.0), eps_h=1.0, ridge_rel=1e-3, newton_iters=8, seed=0, instance=1,
+                     prec=prec)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def timed_solves(F, torch, pb, x0, ws, warmup, steps):
+    for _ in range(warmup):
+        F.solve(pb, x0, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = None
+    for _ in range(steps):
+        u, g, st, iters = F.solve(pb, x0, ws=ws, return_iters=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt / steps, u, g, st, iters
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--points", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="oracle points timed for the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the points of this workload are independent, so a multi-GPU run "
+              f"would shard them with no exchange; --gpus {args.gpus} is not supported.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_02635_amd as F
+    from paper_2510_02635_amd import workloads
+
+    F._native.load()
+    dev = "cuda"
+    P = args.points
+    x0_np = workloads.points("normal:0.5", P, 1000, seed=1)
+    x0 = torch.tensor(x0_np, dtype=torch.float64, device=dev)
+    out = {}
+
+    # ---------------- FP32C (headline)
+    pb32 = workload(F, F.F32C)
+    ws32 = F.workspace(pb32, P, device=dev)
+    log(f"[bench] fp32c: workspace {ws32.numel() / 2**30:.1f} GiB")
+    sec32, u32, g32, st32, it32 = timed_solves(F, torch, pb32, x0, ws32, args.warmup, args.steps)
+    log(f"[bench] fp32c: {sec32 * 1e3:.1f} ms/solve, cg iterations per level {it32}")
+    mv32_ms = F.time_kernel(pb32, P, "cg_matvec", ws32, reps=6)
+    rev32_ms = F.time_kernel(pb32, P, "reverse_newton", ws32, reps=3)
+    u32, g32, st32 = u32.cpu().numpy(), g32.cpu().numpy(), st32.cpu().numpy()
+    del ws32
+    torch.cuda.empty_cache()
+
+    # ---------------- FP64
+    sec64 = None
+    u64 = g64 = None
+    mv64_ms = None
+    it64 = None
+    if not args.skip_fp64:
+        pb64 = workload(F, F.F64)
+        ws64 = F.workspace(pb64, P, device=dev)
+        log(f"[bench] fp64: workspace {ws64.numel() / 2**30:.1f} GiB")
+        sec64, u64, g64, st64, it64 = timed_solves(F, torch, pb64, x0, ws64, min(args.warmup, 1), args.steps)
+        log(f"[bench] fp64: {sec64 * 1e3:.1f} ms/solve, cg iterations per level {it64}")
+        mv64_ms = F.time_kernel(pb64, P, "cg_matvec", ws64, reps=6)
+        u64, g64 = u64.cpu().numpy(), g64.cpu().numpy()
+        del ws64
+        torch.cuda.empty_cache()
+
+    # ---------------- roofline of the dominant kernel (FP32C fused CG product)
+    d, M = 1000, 4096
+    alg_bytes32 = P * M * d * 4
+    achieved32 = alg_bytes32 / (mv32_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_source_sha256_16") == kernel_source_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved32 / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_matvec<float> (fused CG product, one state read)",
+                "algorithmic_bytes_per_launch": alg_bytes32, "avg_launch_ms": round(mv32_ms, 4)}
+    if mv64_ms:
+        roofline["fp64_kernel"] = {"achieved": round(P * M * d * 8 / (mv64_ms * 1e-3) / 1e9, 1),
+                                   "avg_launch_ms": round(mv64_ms, 4), "algorithmic_bytes_per_launch": P * M * d * 8}
+
+    # ---------------- oracle: CPU baseline and errors on sample points
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        from oracle import scheme as OS
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        except Exception:   # threadpoolctl missing: the BLAS default is every core
+            threads = os.cpu_count()
+        op = OS.Problem(d=1000, M=4096, N=20, T=0.3, f_kind=OS.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=OS.G_AC,
+                        gp=(0.4, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3, newton_iters=8, seed=0, instance=1)
+        n = max(1, args.cpu_sample)
+        t0 = time.perf_counter()
+        refs = [OS.solve_point(op, x0_np[p], p) for p in range(n)]
+        tcpu = time.perf_counter() - t0
+        cpu = {"value": round(n / tcpu, 5), "unit": "points/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"points 0..{n - 1} of the {P}-point workload, full solve each ({tcpu:.1f} s)"}
+        for name, uu, gg in (("fp32c", u32, g32), ("fp64", u64, g64)):
+            if uu is None:
+                continue
+            eu = max(abs(uu[p] - refs[p]["u"]) / abs(refs[p]["u"]) for p in range(n))
+            eg = max(float(np.linalg.norm(gg[p] - refs[p]["grad"]) / np.linalg.norm(refs[p]["grad"]))
+                     for p in range(n))
+            errs[name] = {"u": float(f"{eu:.3e}"), "grad": float(f"{eg:.3e}")}
+
+    value = P / sec32
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec32 * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32c", "data": "synthetic",
+        "config": {"workload": "allen_cahn_d1000_P1024_M4096_N20", "d": 1000, "points": P, "M": 4096, "N": 20,
+                   "T": 0.3, "f": "u-u^3", "g": "1/(2+0.4|x|^2)", "x0": "N(0,0.25 I)", "kernel_h": 1.0,
+                   "ridge_rel": 1e-3, "cg_rtol": 1e-7},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": None if sec64 is None else {"value": round(P / sec64, 3), "unit": "points/s",
+                                             "ms_per_step": round(sec64 * 1e3, 3), "cg_rtol": 1e-13,
+                                             "cg_iters_per_level": it64},
+        "speedup_fp32c_over_fp64": None if sec64 is None else round(sec64 / sec32, 3),
+        "rel_err_vs_fp64_oracle": errs or None,
+        "cg_iters_per_level_fp32c": it32,
+        "reverse_sweep_avg_ms_fp32c": round(rev32_ms, 4),
+        "status_nonzero_points": int(np.count_nonzero(st32)),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

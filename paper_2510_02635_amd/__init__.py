@@ -2,7 +2,7 @@
 for very high-dimensional semilinear parabolic PDEs: HIP kernels behind a C ABI (include/fbsde.h),
 with a thin Python front end over PyTorch device memory and streams."""
 from . import _native
-from .api import (Problem, normals, solve, solve_backward, solve_step, state_ld, terminal, workspace,
+from .api import (Problem, normals, solve, solve_backward, solve_step, state_ld, terminal, time_kernel, workspace,
                   workspace_size)
 from ._native import (F32C, F64, F_ALLEN_CAHN, F_HJB, F_ZERO, G_AC, G_AFFINE, G_HJB_LOG, G_QUAD, FbsdeError)
 

@@ -170,3 +170,14 @@ def normals(pb, p, k, j0, rows, device="cuda"):
     N.check(N.load().fbsde_normals(ctypes.byref(pb.c()), p, k, j0, rows, out.data_ptr(), words.data_ptr(),
                                    _stream()))
     return out, words
+
+
+KERNELS = {"cg_matvec": 0, "reverse_newton": 1, "moments": 2, "forward_terminal": 3}
+
+
+def time_kernel(pb, P, which, ws, reps=5):
+    """Average milliseconds of one launch of a hot-path kernel (HIP events on the library's stream)."""
+    out = ctypes.c_float(0.0)
+    N.check(N.load().fbsde_time_kernel(ctypes.byref(pb.c()), P, KERNELS[which], reps, ws.data_ptr(), ws.numel(),
+                                       ctypes.byref(out), _stream()))
+    return float(out.value)

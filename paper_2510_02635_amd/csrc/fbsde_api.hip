@@ -409,6 +409,63 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
     return last_error();
 }
 
+int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t reps, void* wsp, size_t ws_bytes,
+                      float* avg_ms, fbsde_stream stream) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (!wsp || !avg_ms || reps < 1 || which < 0 || which > 3 || P == 0) return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, 0, (char*)wsp, ws);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return FBSDE_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FBSDE_EHIP; }
+    // iscal[p][1] = 0: every point iterates
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((P * 4 + 255) / 256, 1024)), dim3(256), 0, st,
+                       (uint32_t*)ws.iscal, P * 4, 0u);
+    auto body = [&](auto tag) {
+        using S = decltype(tag);
+        S* W = (S*)ws.W;
+        const int64_t ldw = pl.ld;
+        for (int r = 0; r < reps; ++r) {
+            if (which == 0) {
+                dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+                    constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+                    hipLaunchKernelGGL((k_matvec<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
+                                       0, st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, ws.w,
+                                       ws.pv, ws.scal, NS, ws.iscal, ws.part1, ws.psc);
+                });
+            } else if (which == 1) {
+                launch_reverse<S>(pb, pl, P, 1, W, ldw, ws.x, ws, ws.Yb, ws.rn2, (uint32_t*)ws.iscal, st);
+            } else if (which == 2) {
+                dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+                    constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+                    hipLaunchKernelGGL((k_moments<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
+                                       0, st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, ws.w, ws.c2,
+                                       ws.part1, ws.part2, ws.psc);
+                });
+            } else {
+                // the evaluation points of this timing run: the [P][ld] >= [P][d] scratch vector
+                launch_forward<S>(pb, pl, P, ws.Wbar, W, ldw, ws.Yb, ws.rn2, (uint32_t*)ws.iscal, st);
+            }
+            if (r == 0) (void)hipEventRecord(e0, st);   // the first launch warms up, the rest are timed
+        }
+    };
+    if (reps < 2) reps = 2;
+    if (pb->prec == FBSDE_F64) body(double{}); else body(float{});
+    (void)hipEventRecord(e1, st);
+    rc = (hipEventSynchronize(e1) == hipSuccess) ? last_error() : FBSDE_EHIP;
+    float ms = 0.0f;
+    if (rc == FBSDE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = FBSDE_EHIP;
+    *avg_ms = ms / (float)(reps - 1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 const char* fbsde_strerror(int code) {
     switch (code) {
         case FBSDE_OK: return "ok";

@@ -181,3 +181,44 @@ def time_kernel(pb, P, which, ws, reps=5):
     N.check(N.load().fbsde_time_kernel(ctypes.byref(pb.c()), P, KERNELS[which], reps, ws.data_ptr(), ws.numel(),
                                        ctypes.byref(out), _stream()))
     return float(out.value)
+
+
+class FBSDEFunction(torch.autograd.Function):
+    """u(0, x0) as a differentiable function of the points x0 [P][d] and the parameters gp [4], fp [4].
+
+    forward: fbsde_solve with the adjoint tape; backward: fbsde_solve_backward (hand-written reverse mode
+    of the whole backward level chain, particles regenerated from their Philox counters).  The gradient
+    output grad u is returned as a non-differentiable tensor (second derivatives are not provided).
+    """
+
+    @staticmethod
+    def forward(ctx, x0, gp, fp, pb):
+        from dataclasses import replace
+        pbv = replace(pb, gp=tuple(float(v) for v in gp.detach().cpu().tolist()),
+                      fp=tuple(float(v) for v in fp.detach().cpu().tolist()))
+        P = x0.shape[0]
+        ws = workspace(pbv, P, tape=True, device=x0.device)
+        u, grad, st = solve(pbv, x0.detach().contiguous(), tape=True, ws=ws)
+        ctx.pb, ctx.ws = pbv, ws
+        ctx.save_for_backward(x0.detach())
+        ctx.gp_meta = (gp.dtype, gp.device)
+        ctx.fp_meta = (fp.dtype, fp.device)
+        ctx.mark_non_differentiable(grad, st)
+        return u, grad, st
+
+    @staticmethod
+    def backward(ctx, u_bar, grad_bar, st_bar):
+        (x0,) = ctx.saved_tensors
+        if u_bar is None:
+            u_bar = torch.zeros(x0.shape[0], dtype=torch.float64, device=x0.device)
+        x0_bar, gp_bar, fp_bar, _ = solve_backward(ctx.pb, x0, u_bar.to(torch.float64).contiguous(), ctx.ws)
+        ctx.ws = None
+        return (x0_bar, gp_bar.to(dtype=ctx.gp_meta[0], device=ctx.gp_meta[1]),
+                fp_bar.to(dtype=ctx.fp_meta[0], device=ctx.fp_meta[1]), None)
+
+
+def solve_autograd(pb, x0, gp=None, fp=None):
+    """Differentiable solve: returns (u, grad, status); u carries gradients to x0, gp and fp."""
+    gp = torch.tensor(pb.gp, dtype=torch.float64) if gp is None else gp
+    fp = torch.tensor(pb.fp, dtype=torch.float64) if fp is None else fp
+    return FBSDEFunction.apply(x0, gp, fp, pb)

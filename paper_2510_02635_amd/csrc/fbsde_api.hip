@@ -11,6 +11,7 @@
 
 #include "fbsde.h"
 #include "fbsde_kernels.hpp"
+#include "fbsde_adjoint.hpp"
 
 using namespace fbsde;
 
@@ -254,6 +255,14 @@ void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S
     });
 }
 
+int tape_tag(const fbsde_problem* pb, int64_t P) {
+    uint64_t h = 1469598103934665603ull;
+    const uint64_t v[6] = {(uint64_t)pb->d, (uint64_t)pb->M, (uint64_t)pb->N, (uint64_t)P, (uint64_t)pb->prec,
+                           pb->seed ^ ((uint64_t)pb->instance << 32) ^ pb->point_base};
+    for (uint64_t x : v) { h ^= x; h *= 1099511628211ull; }
+    return (int)(h & 0x7FFFFFFF) | 1;
+}
+
 void clear_status(uint32_t* status, int64_t P, hipStream_t st) {
     if (P > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((P + 255) / 256, 1024)), dim3(256), 0,
                                   st, status, P, 0u);
@@ -296,7 +305,64 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
         err = last_error();
         if (err) return err;
     }
-    return FBSDE_OK;
+    if (tape) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, tape_tag(pb, P));
+    return last_error();
+}
+
+template <typename S>
+int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, const double* u_bar,
+                  double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, WS& ws, hipStream_t st) {
+    S* W = (S*)ws.W;
+    const int64_t ldw = pl.ld;
+    const int64_t PM = P * pl.M, PL = P * (int64_t)pl.ld;
+    const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt), s2 = pb->s * pb->s;
+    const Keys ky = keys_of(pb);
+    const FSpec fs = fspec_of(pb);
+    int err = FBSDE_OK;
+    for (int k = 0; k < (int)pl.N; ++k) {
+        const double lam = pb->ridge_rel * s2 * (double)(k + 1) * dt;
+        hipLaunchKernelGGL(k_adj_newton, dim3((unsigned)P), dim3(256), 0, st, ws.G,
+                           k > 0 ? ws.tw + (size_t)(k - 1) * PM : nullptr, ws.psc, pl.nchunk,
+                           k > 0 ? ws.tY + (size_t)k * PM : nullptr, ws.tscal + (size_t)k * P * NS, NS, fs, dt,
+                           pb->newton_iters, (int)pl.M, u_bar, ws.cbar, ws.adj, k == 0 ? 1 : 0, 0, status);
+        dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+            constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+            hipLaunchKernelGGL((k_adj_advance<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, (int)pl.d, pl.ld, k,
+                               k == 0 ? 1 : 0, sqdt, ws.cbar, ky.k0, ky.k1, pb->point_base, ws.part1);
+        });
+        const double* w_k = ws.tw + (size_t)k * PM;
+        const double* Wbar_k = ws.tWbar + (size_t)k * PL;
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.active, (int)P);
+        hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, pl.ld, pb->s,
+                           lam, Wbar_k, ws.tax + (size_t)k * PL, ws.adj, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
+                           ws.active);
+        run_cg<S>(pb, pl, P, W, ldw, w_k, Wbar_k, ws, status, st, err);
+        if (err) return err;
+        hipLaunchKernelGGL(k_adj_bbar, dim3((unsigned)P), dim3(256), 0, st, ws.x, Wbar_k, pl.ld, ws.adj);
+        dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+            constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+            hipLaunchKernelGGL((k_adj_rowdot<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w_k, ws.x, ws.adj,
+                               ws.G, ws.psc);
+        });
+        if ((err = last_error())) return err;
+    }
+    hipLaunchKernelGGL(k_adj_newton, dim3((unsigned)P), dim3(256), 0, st, ws.G, ws.tw + (size_t)(pl.N - 1) * PM,
+                       ws.psc, pl.nchunk, nullptr, ws.tscal, NS, fs, dt, pb->newton_iters, (int)pl.M, u_bar, ws.cbar,
+                       ws.adj, 0, 1, status);
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_adj_terminal<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, (int)pl.d, pl.ld, x0, pb->mu, pb->gvec, pb->s,
+                           pb->T, pb->g_kind, pb->gp[0], ws.G, ws.part1, ws.psc);
+    });
+    hipLaunchKernelGGL(k_adj_x0bar, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, (int)pl.d,
+                       pl.ld, x0, pb->mu, pb->gvec, pb->s, pb->T, pb->g_kind, ws.adj, x0_bar);
+    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(64), 0, st, ws.adj, P, gp_bar, fp_bar);
+    // the tape is consumed: the state no longer holds W_1 of the primal pass
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, 0);
+    return last_error();
 }
 
 }  // namespace
@@ -389,9 +455,24 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
 int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
                          double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
                          fbsde_stream stream) {
-    (void)pb; (void)P; (void)x0; (void)u_bar; (void)x0_bar; (void)gp_bar; (void)fp_bar; (void)status; (void)wsp;
-    (void)ws_bytes; (void)stream;
-    return FBSDE_ESTATE;
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (!x0 || !u_bar || !x0_bar || !gp_bar || !fp_bar || !status || !wsp) return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, FBSDE_WS_TAPE, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, FBSDE_WS_TAPE, (char*)wsp, ws);
+    if (P == 0) return FBSDE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int tag = 0;
+    if (hipMemcpyAsync(&tag, ws.tag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return FBSDE_EHIP;
+    if (tag != tape_tag(pb, P)) return FBSDE_ESTATE;
+    if (pb->prec == FBSDE_F64)
+        return backward_impl<double>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, st);
+    return backward_impl<float>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, st);
 }
 
 int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows, double* out,

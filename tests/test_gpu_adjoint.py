@@ -1,0 +1,130 @@
+"""GPU parity of the hand-written adjoint (fbsde_solve_backward) against the oracle's reverse mode,
+and against central finite differences of the GPU forward solve itself.
+
+FP64: x0bar per point and the parameter gradients (summed over points) within 1e-10 of the FP64 oracle;
+FP32C within 1e-5.  Finite differences: step 1e-4, common random numbers, 1e-6 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2510_02635_amd as F  # noqa: E402
+from oracle import scheme as OS  # noqa: E402
+from paper_2510_02635_amd import workloads  # noqa: E402
+
+from _convert import problems, rel_err  # noqa: E402
+
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F._native.load()
+
+
+ADJ_CASES = [
+    ("ac_d100", dict(d=100, M=256, N=4, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,
+                     gp=(0.4, 0, 0, 0)), "normal_over_sqrt_d", 3),
+    ("hjb_d37_mu", dict(d=37, M=100, N=3, T=0.5, f_kind=F.F_HJB, fp=(0.8, 0, 0, 0), g_kind=F.G_HJB_LOG,
+                        gp=(1.0, 0, 0, 0), seed=7), "uniform", 2),
+    ("heat_d1000", dict(d=1000, M=300, N=2, T=0.3, f_kind=F.F_ZERO, g_kind=F.G_QUAD, gp=(1.3, 0.2, 0, 0)),
+     "normal:0.5", 2),
+    ("ac_d3000_team4", dict(d=3000, M=64, N=2, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(0.5, 2.0, 0, 0),
+                            g_kind=F.G_HJB_LOG, gp=(0.6, 0, 0, 0)), "normal_over_sqrt_d", 2),
+    ("ac_d10000_team16", dict(d=10000, M=40, N=2, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
+                              gp=(0.4, 0, 0, 0)), "normal_over_sqrt_d", 1),
+]
+
+
+def _adjoint_case(kw, xkind, P, prec, tol):
+    mu = 0.2 * np.sin(np.arange(kw["d"])) if "seed" in kw else None
+    hp, op = problems(mu=mu, prec=prec, **kw)
+    x0 = workloads.points(xkind, P, kw["d"], 9)
+    ubar = np.linspace(1.0, 2.0, P)
+    _say(f"[adjoint] d={kw['d']} M={kw['M']} N={kw['N']} P={P} prec={prec}")
+    xt = torch.tensor(x0, device=DEV)
+    ws = F.workspace(hp, P, tape=True)
+    u, g, st = F.solve(hp, xt, tape=True, ws=ws)
+    x0b, gpb, fpb, st2 = F.solve_backward(hp, xt, torch.tensor(ubar, device=DEV), ws)
+    torch.cuda.synchronize()
+    x0b = x0b.cpu().numpy()
+    gp_ref = np.zeros(4)
+    fp_ref = np.zeros(4)
+    for p in range(P):
+        ref = OS.adjoint_point(op, x0[p], p, ubar=ubar[p])
+        e = rel_err(x0b[p], ref["x0bar"])
+        _say(f"  p={p} rel_x0bar={e:.2e}")
+        assert e <= tol
+        gp_ref += ref["gpbar"]
+        fp_ref += ref["fpbar"]
+    for got, ref, name in ((gpb.cpu().numpy(), gp_ref, "gp"), (fpb.cpu().numpy(), fp_ref, "fp")):
+        for i in range(4):
+            if ref[i] != 0.0 or got[i] != 0.0:
+                err = abs(got[i] - ref[i]) / max(abs(ref[i]), 1e-300)
+                _say(f"  {name}[{i}] got={got[i]:.12g} ref={ref[i]:.12g} rel={err:.2e}")
+                assert err <= tol, (name, i)
+    assert np.all(st.cpu().numpy() == 0) and np.all(st2.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("name,kw,xkind,P", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+def test_adjoint_fp64_matches_oracle(name, kw, xkind, P):
+    _adjoint_case(kw, xkind, P, F.F64, 1e-10)
+
+
+@pytest.mark.parametrize("name,kw,xkind,P", ADJ_CASES[:3], ids=[c[0] for c in ADJ_CASES[:3]])
+def test_adjoint_fp32c_matches_fp64_oracle(name, kw, xkind, P):
+    _adjoint_case(kw, xkind, P, F.F32C, 1e-5)
+
+
+def test_adjoint_against_gpu_central_differences_and_autograd():
+    kw = dict(d=200, M=256, N=5, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0))
+    hp, _ = problems(**kw)
+    P = 3
+    x0 = torch.tensor(workloads.points("normal_over_sqrt_d", P, 200, 4), device=DEV, requires_grad=True)
+    gp = torch.tensor([0.4, 0.0, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    fp = torch.tensor([1.0, 1.0, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    _say("[adjoint] autograd vs central differences")
+    u, g, st = F.solve_autograd(hp, x0, gp, fp)
+    u.sum().backward()
+    torch.cuda.synchronize()
+    h = 1e-4
+
+    def L(xx, gpv=(0.4, 0, 0, 0), fpv=(1.0, 1.0, 0, 0)):
+        from dataclasses import replace
+        return F.solve(replace(hp, gp=gpv, fp=fpv), xx)[0].sum().item()
+
+    rng = np.random.default_rng(0)
+    with torch.no_grad():
+        for _ in range(4):
+            v = torch.tensor(rng.standard_normal((P, 200)), device=DEV)
+            v /= v.norm()
+            fd = (L(x0 + h * v) - L(x0 - h * v)) / (2 * h)
+            an = float((x0.grad * v).sum())
+            _say(f"  dir fd={fd:.10g} adj={an:.10g}")
+            assert abs(fd - an) <= 1e-6 * abs(fd)
+        fd_a = (L(x0, gpv=(0.4 + h, 0, 0, 0)) - L(x0, gpv=(0.4 - h, 0, 0, 0))) / (2 * h)
+        fd_c1 = (L(x0, fpv=(1.0 + h, 1.0, 0, 0)) - L(x0, fpv=(1.0 - h, 1.0, 0, 0))) / (2 * h)
+        _say(f"  a: fd={fd_a:.10g} adj={gp.grad[0].item():.10g}   c1: fd={fd_c1:.10g} adj={fp.grad[0].item():.10g}")
+        assert abs(fd_a - gp.grad[0].item()) <= 1e-6 * abs(fd_a)
+        assert abs(fd_c1 - fp.grad[0].item()) <= 1e-6 * abs(fd_c1)
+
+
+def test_backward_without_tape_is_refused():
+    hp, _ = problems(d=16, M=64, N=2, T=0.3)
+    xt = torch.zeros((2, 16), dtype=torch.float64, device=DEV)
+    ws = F.workspace(hp, 2, tape=True)
+    ws.zero_()
+    with pytest.raises(F.FbsdeError):
+        F.solve_backward(hp, xt, torch.ones(2, dtype=torch.float64, device=DEV), ws)

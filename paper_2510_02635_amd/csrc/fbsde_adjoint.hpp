@@ -109,11 +109,11 @@ k_adj_advance(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nch
                     for (int e = 0; e < 4; ++e) acc[q][e].add(cb * v[e]);
                 }
                 if (e0 < d) {
-                    double z[4];
-                    increment4((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
+                    S z[4];
+                    increment4<S>((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (e0 + e < d) v[e] = (S)((double)v[e] + sqdt * z[e]);
+                        if (e0 + e < d) v[e] = (S)((double)v[e] + sqdt * (double)z[e]);
                 }
                 store4(row + e0, v);
             }

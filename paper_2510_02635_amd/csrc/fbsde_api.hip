@@ -75,7 +75,7 @@ struct WS {
     void* W;
     double *Ya, *Yb, *rn2, *w, *c2;
     double *x, *r, *pv, *qv, *Wbar;
-    double *part1, *part2, *psc, *scal;
+    double *part1, *part2, *part3, *psc, *scal;
     int *iscal, *active;
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
@@ -107,6 +107,7 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     ws.Wbar = (double*)take(PL * 8);
     ws.part1 = (double*)take(parts * 8);
     ws.part2 = (double*)take(parts * 8);
+    ws.part3 = (double*)take(parts * 8);
     ws.psc = (double*)take((size_t)P * pl.nchunk * 4 * 8);
     ws.scal = (double*)take((size_t)P * NS * 8);
     ws.iscal = (int*)take((size_t)P * 4 * 4);
@@ -217,22 +218,23 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
 template <typename S>
 int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S* W, int64_t ldw,
               const double* Y_next, const double* rn2, double* w_out, double* Wbar_out, WS& ws,
-              double* alpha_out, double* alpha_x_out, uint32_t* status, hipStream_t st, int& err) {
+              double* alpha_out, double* alpha_x_out, uint32_t* status, hipStream_t st, int& err, int warm = 0) {
     const double dt = pb->T / (double)pb->N;
     const double t_next = (double)(k + 1) * dt;
     const double s2 = pb->s * pb->s;
     const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)pl.d : 0.0;
     const double lam = pb->ridge_rel * s2 * t_next;
     hipLaunchKernelGGL(k_weights, dim3((unsigned)P), dim3(256), 0, st, rn2, Y_next, (int)pl.M, s2, eps2, w_out,
-                       ws.c2, ws.scal, NS, ws.active, (int)P);
+                       ws.c2, ws.scal, NS, ws.active, (int)P, warm);
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
         hipLaunchKernelGGL((k_moments<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
-                           ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.part1, ws.part2,
-                           ws.psc);
+                           ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.x, ws.scal, NS, warm,
+                           ws.part1, ws.part2, ws.part3, ws.psc);
     });
-    hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.psc, pl.nchunk,
-                       pl.ld, pb->s, lam, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal, ws.active);
+    hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.part3, ws.psc,
+                       pl.nchunk, pl.ld, pb->s, lam, warm, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
+                       ws.active);
     const int iters = run_cg<S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
     if (err) return iters;
     hipLaunchKernelGGL(k_level_finish, dim3((unsigned)P), dim3(256), 0, st, ws.x, Wbar_out, pl.ld, (int)pl.d, pb->s,
@@ -243,7 +245,7 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
 
 template <typename S>
 void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S* W, int64_t ldw, const double* ax,
-                    WS& ws, double* Y, double* rn2, uint32_t* status, hipStream_t st) {
+                    WS& ws, double* Y, double* rn2, uint32_t* status, hipStream_t st, double* dydc = nullptr) {
     const Keys ky = keys_of(pb);
     const double dt = pb->T / (double)pb->N;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
@@ -251,7 +253,7 @@ void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S
         hipLaunchKernelGGL((k_reverse<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
                            ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0, std::sqrt(dt),
                            pb->s, dt, ax, ws.scal, NS, fspec_of(pb), pb->newton_iters, ky.k0, ky.k1,
-                           pb->point_base, Y, rn2, status);
+                           pb->point_base, Y, rn2, dydc, status);
     });
 }
 
@@ -283,8 +285,13 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
     for (int k = (int)pl.N - 1; k >= 0; --k) {
         double* w_k = tape ? ws.tw + (size_t)k * PM : ws.w;
         double* Wbar_k = tape ? ws.tWbar + (size_t)k * PL : ws.Wbar;
+        // Warm start from the previous level's slope (Y_{k+1} is the Newton image of a linear model),
+        // only when the centred design has full rank (M > d + 1): otherwise A has a (d - M + 1)-fold
+        // eigenvalue lam whose eigenspace a cold start never enters, while the previous slope does,
+        // and the residual test would then bound the error there only up to a factor 1 / lam.
+        const int warm = (k < (int)pl.N - 1 && pl.M > pl.d + 1) ? 1 : 0;
         const int iters = run_level<S>(pb, pl, P, k, W, ldw, Ycur, ws.rn2, w_k, Wbar_k, ws, nullptr, nullptr, status,
-                                       st, err);
+                                       st, err, warm);
         if (err) return err;
         if (cg_iters_out) cg_iters_out[k] = iters;
         if (tape) {
@@ -295,7 +302,7 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
         }
         if (k > 0) {
             double* Yout = tape ? ws.tY + (size_t)k * PM : Yk;
-            launch_reverse<S>(pb, pl, P, k, W, ldw, ws.x, ws, Yout, ws.rn2, status, st);
+            launch_reverse<S>(pb, pl, P, k, W, ldw, ws.x, ws, Yout, ws.rn2, status, st, ws.c2);
             if (!tape) std::swap(Ycur, Yk);
             else Ycur = Yout;
         } else {
@@ -526,7 +533,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
                     constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
                     hipLaunchKernelGGL((k_moments<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
                                        0, st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, ws.w, ws.c2,
-                                       ws.part1, ws.part2, ws.psc);
+                                       ws.x, ws.scal, NS, 1, ws.part1, ws.part2, ws.part3, ws.psc);
                 });
             } else {
                 // the evaluation points of this timing run: the [P][ld] >= [P][d] scratch vector

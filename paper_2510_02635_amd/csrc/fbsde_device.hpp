@@ -28,28 +28,94 @@ __device__ __forceinline__ Words4 philox4x32_10(Words4 c, uint32_t k0, uint32_t 
     return c;
 }
 
+// sin and cos of the angle 2 pi (w + 1/2) 2^-32 of one Philox word w.  The octant comes exactly from
+// the top three bits; the angle left over, |psi| <= pi/4, is taken from the low 29 bits in integer
+// arithmetic (for odd octants as the distance to the next octant boundary, also exact), so no
+// floating-point range reduction is needed; sin and cos of psi are their Taylor series, truncated where
+// the next term is below half an ulp of the type (psi^19/19! for double, psi^11/11! for float).
+template <typename R>
+__device__ __forceinline__ void sincos_turn(uint32_t w, R& sn, R& cs);
+
+template <>
+__device__ __forceinline__ void sincos_turn<double>(uint32_t w, double& sn, double& cs) {
+    const uint32_t o = w >> 29;                       // octant 0..7
+    const uint32_t f = w & 0x1FFFFFFFu;
+    const double two_pi_2m32 = 1.4629180792671596e-09;  // 2 pi 2^-32
+    // even octant: psi = theta in [0, pi/4); odd: psi = theta - pi/4 in [-pi/4, 0)
+    const double t = (o & 1u) ? -((double)(0x1FFFFFFFu - f) + 0.5) : ((double)f + 0.5);
+    const double psi = t * two_pi_2m32;
+    const double z = psi * psi;
+    double ps = 1.0 / 121645100408832000.0;            // 1/19!
+    ps = ps * z - 1.0 / 355687428096000.0;             // 1/17!
+    ps = ps * z + 1.0 / 1307674368000.0;               // 1/15!
+    ps = ps * z - 1.0 / 6227020800.0;                  // 1/13!
+    ps = ps * z + 1.0 / 39916800.0;                    // 1/11!
+    ps = ps * z - 1.0 / 362880.0;                      // 1/9!
+    ps = ps * z + 1.0 / 5040.0;                        // 1/7!
+    ps = ps * z - 1.0 / 120.0;                         // 1/5!
+    ps = ps * z + 1.0 / 6.0;                           // 1/3!
+    const double s_ = psi - psi * z * ps;
+    double pc = 1.0 / 6402373705728000.0;              // 1/18!
+    pc = pc * z - 1.0 / 20922789888000.0;              // 1/16!
+    pc = pc * z + 1.0 / 87178291200.0;                 // 1/14!
+    pc = pc * z - 1.0 / 479001600.0;                   // 1/12!
+    pc = pc * z + 1.0 / 3628800.0;                     // 1/10!
+    pc = pc * z - 1.0 / 40320.0;                       // 1/8!
+    pc = pc * z + 1.0 / 720.0;                         // 1/6!
+    pc = pc * z - 1.0 / 24.0;                          // 1/4!
+    pc = pc * z + 0.5;                                 // 1/2!
+    const double c_ = 1.0 - z * pc;
+    const uint32_t q = ((o + 1u) >> 1) & 3u;          // angle = psi + q pi/2
+    sn = (q == 0) ? s_ : (q == 1) ? c_ : (q == 2) ? -s_ : -c_;
+    cs = (q == 0) ? c_ : (q == 1) ? -s_ : (q == 2) ? -c_ : s_;
+}
+
+template <>
+__device__ __forceinline__ void sincos_turn<float>(uint32_t w, float& sn, float& cs) {
+    const uint32_t o = w >> 29;
+    const uint32_t f = w & 0x1FFFFFFFu;
+    const float two_pi_2m32 = 1.46291808e-09f;
+    const float t = (o & 1u) ? -((float)(0x1FFFFFFFu - f) + 0.5f) : ((float)f + 0.5f);
+    const float psi = t * two_pi_2m32;
+    const float z = psi * psi;
+    float ps = 1.0f / 362880.0f;                       // 1/9!
+    ps = ps * z - 1.0f / 5040.0f;
+    ps = ps * z + 1.0f / 120.0f;
+    ps = ps * z - 1.0f / 6.0f;
+    const float s_ = psi + psi * z * ps;
+    float pc = 1.0f / 3628800.0f;                      // 1/10!
+    pc = pc * z - 1.0f / 40320.0f;
+    pc = pc * z + 1.0f / 720.0f;
+    pc = pc * z - 1.0f / 24.0f;
+    pc = pc * z + 0.5f;
+    const float c_ = 1.0f - z * pc;
+    const uint32_t q = ((o + 1u) >> 1) & 3u;
+    sn = (q == 0) ? s_ : (q == 1) ? c_ : (q == 2) ? -s_ : -c_;
+    cs = (q == 0) ? c_ : (q == 1) ? -s_ : (q == 2) ? -c_ : s_;
+}
+
 // Four normals from one Philox call: Box-Muller on the word pairs (x, y) and (z, w) with
-// u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even), angle 2 pi u_odd.
-__device__ __forceinline__ void box_muller4(const Words4& w, double z[4]) {
+// u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even) (FP64 log for both element types),
+// angle 2 pi u_odd.
+template <typename R>
+__device__ __forceinline__ void box_muller4(const Words4& w, R z[4]) {
     const double two_m32 = 2.3283064365386963e-10;   // 2^-32
-    const double two_pi = 6.283185307179586;
     const double u0 = ((double)w.x + 0.5) * two_m32;
-    const double u1 = ((double)w.y + 0.5) * two_m32;
     const double u2 = ((double)w.z + 0.5) * two_m32;
-    const double u3 = ((double)w.w + 0.5) * two_m32;
-    const double r0 = sqrt(-2.0 * log(u0));
-    const double r2 = sqrt(-2.0 * log(u2));
-    double s1, c1, s3, c3;
-    sincos(two_pi * u1, &s1, &c1);
-    sincos(two_pi * u3, &s3, &c3);
+    const R r0 = (R)sqrt(-2.0 * log(u0));
+    const R r2 = (R)sqrt(-2.0 * log(u2));
+    R s1, c1, s3, c3;
+    sincos_turn<R>(w.y, s1, c1);
+    sincos_turn<R>(w.w, s3, c3);
     z[0] = r0 * c1; z[1] = r0 * s1; z[2] = r2 * c3; z[3] = r2 * s3;
 }
 
 // Normals of coordinates 4g..4g+3 of particle j, level k, stream q (point or shared).
+template <typename R>
 __device__ __forceinline__ void increment4(uint32_t g, uint32_t j, uint32_t k, uint32_t q,
-                                           uint32_t k0, uint32_t k1, double z[4]) {
+                                           uint32_t k0, uint32_t k1, R z[4]) {
     const Words4 c = {g, j, k, q};
-    box_muller4(philox4x32_10(c, k0, k1), z);
+    box_muller4<R>(philox4x32_10(c, k0, k1), z);
 }
 
 // ------------------------------------------------------------------ reductions

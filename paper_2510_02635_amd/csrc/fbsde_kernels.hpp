@@ -156,11 +156,11 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
                 for (int q = 0; q < Q; ++q) {
                     const int g = L + q * G::TL;
                     if (4 * g < d) {
-                        double z[4];
-                        increment4((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
+                        S z[4];
+                        increment4<S>((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (4 * g + e < d) w[q][e] += sqdt * z[e];
+                            if (4 * g + e < d) w[q][e] += sqdt * (double)z[e];
                     }
                 }
             }
@@ -199,10 +199,13 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
 }
 
 // Kernel weights of the cloud (eq. Dj with the Gaussian kernel), weighted mean of Y and the
-// centred response coefficients w_j (Y_j - Ybar).  One block per point.
+// centred response coefficients w_j (Y_j - Ybar).  One block per point.  warm: c2 holds
+// dY_j/dC_j = 1/F'(Y_j) from the previous level's Newton solve, and rho = sum_j w_j dY_j/dC_j is
+// stored in scal[7] (the scale of the CG warm start).
 __global__ void __launch_bounds__(256)
 k_weights(const double* __restrict__ rn2, const double* __restrict__ Y, int M, double s2, double eps2,
-          double* __restrict__ w, double* __restrict__ c2, double* __restrict__ scal, int ns, int* active, int P) {
+          double* __restrict__ w, double* __restrict__ c2, double* __restrict__ scal, int ns, int* active, int P,
+          int warm) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
     const double* n = rn2 + (int64_t)p * M;
@@ -219,97 +222,153 @@ k_weights(const double* __restrict__ rn2, const double* __restrict__ Y, int M, d
         se += e;
     }
     se = block_sum(se, lds);
-    double yb = 0.0;
+    double yb = 0.0, rho = 0.0;
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
         const double wj = wp[j] / se;
         wp[j] = wj;
         yb += wj * y[j];
+        if (warm) rho += wj * cp[j];
     }
     yb = block_sum(yb, lds);
+    rho = block_sum(rho, lds);
     for (int j = threadIdx.x; j < M; j += blockDim.x) cp[j] = wp[j] * (y[j] - yb);
     if (threadIdx.x == 0) {
         scal[(int64_t)p * ns + 4] = yb;
+        scal[(int64_t)p * ns + 7] = warm ? rho : 0.0;
         if (p == 0) *active = P;
     }
 }
 
 // Weighted first moments of the cloud: sum_j w_j W_j and sum_j w_j (Y_j - Ybar) W_j (column sums
-// over particles; the normal-equation right-hand side, eq. normal-eq), per block.
+// over particles; the normal-equation right-hand side, eq. normal-eq), per block.  warm: also the
+// pieces of A x0 for the CG warm start x0 = rho * xw (xw = previous level's slope):
+// t_j = W_j . x0, sum_j w_j t_j W_j and sum_j w_j t_j, with the row still in registers.
 template <typename S, int Q, int TEAM>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_moments(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nchunk, int ld,
-          const double* __restrict__ w, const double* __restrict__ c2, double* __restrict__ part1,
-          double* __restrict__ part2, double* __restrict__ psc) {
+          const double* __restrict__ w, const double* __restrict__ c2, const double* __restrict__ xw,
+          const double* __restrict__ scal, int ns, int warm, double* __restrict__ part1, double* __restrict__ part2,
+          double* __restrict__ part3, double* __restrict__ psc) {
     using G = Geo<Q, TEAM>;
     using R = S;
     __shared__ double lds[(G::TPW > 1) ? G::TPW * 4 * Q * G::TL : 1];
-    __shared__ double red[G::BS / 64];
+    __shared__ double red[2 * G::BS / 64];
     const int p = blockIdx.y, c = blockIdx.x;
     const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
     const int r0 = c * rows_per_chunk;
     const int r1 = min(M, r0 + rows_per_chunk);
-    CSum<R> a1[Q][4], a2[Q][4];
-    double sig = 0.0;
-    for (int j = r0 + team; j < r1; j += G::TPW) {
-        const S* row = W + ((int64_t)p * M + j) * ldw;
-        const R wj = (R)w[(int64_t)p * M + j];
-        const double cjd = c2[(int64_t)p * M + j];
-        const R cj = (R)cjd;
-        sig += cjd;
+    R v[Q][4];
+    const double rho = warm ? scal[(int64_t)p * ns + 7] : 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int e0 = 4 * (L + q * G::TL);
-            if (e0 < ld) {
-                S x[4];
-                load4(row + e0, x);
+    for (int q = 0; q < Q; ++q) {
+        const int e0 = 4 * (L + q * G::TL);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) { a1[q][e].add(wj * x[e]); a2[q][e].add(cj * x[e]); }
+        for (int e = 0; e < 4; ++e) v[q][e] = (warm && e0 < ld) ? (R)(rho * xw[(int64_t)p * ld + e0 + e]) : (R)0;
+    }
+    CSum<R> a1[Q][4], a2[Q][4], a3[Q][4];
+    double sig = 0.0, tau = 0.0;
+    for (int jb = r0; jb < r1; jb += G::TPW) {
+        const int j = jb + team;
+        const bool valid = j < r1;
+        S x[Q][4];
+        CSum<R> dl;
+        double wjd = 0.0;
+        if (valid) {
+            const S* row = W + ((int64_t)p * M + j) * ldw;
+            wjd = w[(int64_t)p * M + j];
+            const R wj = (R)wjd;
+            const double cjd = c2[(int64_t)p * M + j];
+            const R cj = (R)cjd;
+            sig += cjd;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int e0 = 4 * (L + q * G::TL);
+                if (e0 < ld) load4(row + e0, x[q]);
+                else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) x[q][e] = (S)0;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    a1[q][e].add(wj * x[q][e]);
+                    a2[q][e].add(cj * x[q][e]);
+                    if (warm) dl.add(x[q][e] * v[q][e]);
+                }
+            }
+        }
+        if (warm) {
+            double t = dl.get(), unused = 0.0;
+            team_sum2<TEAM>(t, unused, red, team);
+            if (valid) {
+                const double ct = wjd * t;
+                tau += ct;
+                const R cr = (R)ct;
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) a3[q][e].add(cr * x[q][e]);
             }
         }
     }
-    double* o1 = part1 + ((int64_t)p * nchunk + c) * ld;
-    double* o2 = part2 + ((int64_t)p * nchunk + c) * ld;
-    block_columns_out<Q, TEAM, R>(a1, lds, o1, ld, team, L);
-    block_columns_out<Q, TEAM, R>(a2, lds, o2, ld, team, L);
-    // sig is identical on every lane of a team: one lane per team contributes
-    const double contrib = (L == 0) ? sig : 0.0;
-    const double tot = block_sum(contrib, red);
-    if (threadIdx.x == 0) psc[(int64_t)p * nchunk + c] = tot;
+    const int64_t off = ((int64_t)p * nchunk + c) * ld;
+    block_columns_out<Q, TEAM, R>(a1, lds, part1 + off, ld, team, L);
+    block_columns_out<Q, TEAM, R>(a2, lds, part2 + off, ld, team, L);
+    if (warm) block_columns_out<Q, TEAM, R>(a3, lds, part3 + off, ld, team, L);
+    // sig and tau are identical on every lane of a team: one lane per team contributes
+    const double ts = block_sum((L == 0) ? sig : 0.0, red);
+    const double tt = block_sum((L == 0) ? tau : 0.0, red);
+    if (threadIdx.x == 0) {
+        psc[((int64_t)p * nchunk + c) * 2] = ts;
+        psc[((int64_t)p * nchunk + c) * 2 + 1] = tt;
+    }
 }
 
-// Finish the moments and start CG on (sum_j w_j D'_j D'_j^T + lam I) a_x = b, x0 = 0.
-// scal layout per point: 0 rr, 1 |b|^2, 2 wv = Wbar.p, 3 lam, 4 Ybar, 5 alpha, 6 zz, 7 spare.
+// Finish the moments and start CG on (sum_j w_j D'_j D'_j^T + lam I) a_x = b.
+// Cold start x0 = 0; warm start x0 = rho * (previous level's slope, in x) with
+// A x0 = s^2 (sum_j w_j t_j W_j - (sum_j w_j t_j) Wbar) + lam x0, t_j = W_j . x0.
+// scal layout per point: 0 rr, 1 |b|^2, 2 wv = Wbar.p, 3 lam, 4 Ybar, 5 alpha, 6 zz, 7 rho.
 // iscal: 0 iterations, 1 done.
 __global__ void __launch_bounds__(256)
 k_moments_finish(const double* __restrict__ part1, const double* __restrict__ part2,
-                 const double* __restrict__ psc, int nchunk, int ld, double s, double lam,
-                 double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
-                 double* __restrict__ pv, double* __restrict__ scal, int ns, int* __restrict__ iscal,
-                 int* active) {
+                 const double* __restrict__ part3, const double* __restrict__ psc, int nchunk, int ld, double s,
+                 double lam, int warm, double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
+                 double* __restrict__ pv, double* __restrict__ scal, int ns, int* __restrict__ iscal, int* active) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
-    double sig = 0.0;
-    for (int c = 0; c < nchunk; ++c) sig += psc[(int64_t)p * nchunk + c];
-    double rr = 0.0, wv = 0.0;
+    double sig = 0.0, tau = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        sig += psc[((int64_t)p * nchunk + c) * 2];
+        tau += psc[((int64_t)p * nchunk + c) * 2 + 1];
+    }
+    const double rho = warm ? scal[(int64_t)p * ns + 7] : 0.0;
+    double rr = 0.0, bb2 = 0.0, wv = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-        double wb = 0.0, bb = 0.0;
+        double wb = 0.0, bb = 0.0, ab = 0.0;
         for (int c = 0; c < nchunk; ++c) {
             wb += part1[((int64_t)p * nchunk + c) * ld + i];
             bb += part2[((int64_t)p * nchunk + c) * ld + i];
+            if (warm) ab += part3[((int64_t)p * nchunk + c) * ld + i];
         }
         const double b = s * (bb - sig * wb);
+        double x0 = 0.0, res = b;
+        if (warm) {
+            x0 = rho * x[(int64_t)p * ld + i];
+            res = b - (s * s * (ab - tau * wb) + lam * x0);
+        }
         Wbar[(int64_t)p * ld + i] = wb;
-        x[(int64_t)p * ld + i] = 0.0;
-        r[(int64_t)p * ld + i] = b;
-        pv[(int64_t)p * ld + i] = b;
-        rr += b * b;
-        wv += wb * b;
+        x[(int64_t)p * ld + i] = x0;
+        r[(int64_t)p * ld + i] = res;
+        pv[(int64_t)p * ld + i] = res;
+        rr += res * res;
+        bb2 += b * b;
+        wv += wb * res;
     }
     rr = block_sum(rr, lds);
+    bb2 = block_sum(bb2, lds);
     wv = block_sum(wv, lds);
     if (threadIdx.x == 0) {
         scal[(int64_t)p * ns + 0] = rr;
-        scal[(int64_t)p * ns + 1] = rr;
+        scal[(int64_t)p * ns + 1] = bb2;
         scal[(int64_t)p * ns + 2] = wv;
         scal[(int64_t)p * ns + 3] = lam;
         iscal[p * 4 + 0] = 0;
@@ -479,7 +538,7 @@ __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int ld, int k, int zero_state,
           double sqdt, double s, double dt, const double* __restrict__ ax, const double* __restrict__ scal,
           int ns, FSpec f, int newton_iters, uint32_t k0, uint32_t k1, uint32_t point_base,
-          double* __restrict__ Y, double* __restrict__ rn2, uint32_t* __restrict__ status) {
+          double* __restrict__ Y, double* __restrict__ rn2, double* __restrict__ dydc, uint32_t* __restrict__ status) {
     using G = Geo<Q, TEAM>;
     using R = S;
     __shared__ double red[2 * G::BS / 64];
@@ -516,11 +575,11 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
                     } else {
                         load4(row + e0, v);
                         if (e0 < d) {
-                            double z[4];
-                            increment4((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
+                            S z[4];
+                            increment4<S>((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
-                                if (e0 + e < d) v[e] = (S)((double)v[e] - sqdt * z[e]);
+                                if (e0 + e < d) v[e] = (S)((double)v[e] - sqdt * (double)z[e]);
                         }
                     }
                     store4(row + e0, v);
@@ -536,6 +595,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
             const double y = newton_y(f, alpha + s * dt_, zz, dt, newton_iters, Fp, st);
             Y[(int64_t)p * M + j] = y;
             rn2[(int64_t)p * M + j] = n2;
+            if (dydc) dydc[(int64_t)p * M + j] = 1.0 / Fp;
         }
     }
     if (st) atomicOr(&status[p], st);
@@ -609,7 +669,7 @@ __global__ void k_normals(int d, int64_t j0, int64_t rows, int k, uint32_t q, ui
         const Words4 c = {(uint32_t)g, (uint32_t)(j0 + r), (uint32_t)k, q};
         const Words4 wd = philox4x32_10(c, k0, k1);
         double z[4];
-        box_muller4(wd, z);
+        box_muller4<double>(wd, z);
         for (int e = 0; e < 4; ++e)
             if (4 * g + e < d) out[r * d + 4 * g + e] = z[e];
         if (words) {

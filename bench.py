@@ -101,6 +101,27 @@ def main():
     del ws32
     torch.cuda.empty_cache()
 
+    # ---------------- FP32C forward (with tape) + adjoint of L = sum_p u_p
+    wsa = F.workspace(pb32, P, tape=True, device=dev)
+    ubar = torch.ones(P, dtype=torch.float64, device=dev)
+
+    def fwd_adj():
+        F.solve(pb32, x0, tape=True, ws=wsa)
+        return F.solve_backward(pb32, x0, ubar, wsa)
+
+    for _ in range(args.warmup):
+        fwd_adj()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x0bar, gpbar, fpbar, sta = fwd_adj()
+    torch.cuda.synchronize()
+    sec_fa = (time.perf_counter() - t0) / args.steps
+    log(f"[bench] fp32c fwd+adj: {sec_fa * 1e3:.1f} ms per solve + backward")
+    x0bar = x0bar.cpu().numpy()
+    del wsa
+    torch.cuda.empty_cache()
+
     # ---------------- FP64
     sec64 = None
     u64 = g64 = None
@@ -152,6 +173,8 @@ def main():
         tcpu = time.perf_counter() - t0
         cpu = {"value": round(n / tcpu, 5), "unit": "points/s", "cores": int(threads), "kind": "oracle",
                "sample": f"points 0..{n - 1} of the {P}-point workload, full solve each ({tcpu:.1f} s)"}
+        adj_ref = OS.adjoint_point(op, x0_np[0], 0, ubar=1.0)
+        errs["fp32c_x0bar_point0"] = float(f"{np.linalg.norm(x0bar[0] - adj_ref['x0bar']) / np.linalg.norm(adj_ref['x0bar']):.3e}")
         for name, uu, gg in (("fp32c", u32, g32), ("fp64", u64, g64)):
             if uu is None:
                 continue
@@ -173,6 +196,8 @@ def main():
         "fp64": None if sec64 is None else {"value": round(P / sec64, 3), "unit": "points/s",
                                              "ms_per_step": round(sec64 * 1e3, 3), "cg_rtol": 1e-13,
                                              "cg_iters_per_level": it64},
+        "fwd_adj": {"value": round(P / sec_fa, 3), "unit": "points/s", "ms_per_step": round(sec_fa * 1e3, 3),
+                    "dtype": "fp32c", "loss": "sum_p u(0, x0_p)", "outputs": "d/dx0 [P][d], d/dgp, d/dfp"},
         "speedup_fp32c_over_fp64": None if sec64 is None else round(sec64 / sec32, 3),
         "rel_err_vs_fp64_oracle": errs or None,
         "cg_iters_per_level_fp32c": it32,

@@ -134,6 +134,12 @@ int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double
 int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
                 uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, int32_t* cg_iters_out,
                 fbsde_stream stream);
+/* shared_dw = 1 (increments common to all points, the common-randomness remark after Lemma 3.7):
+ * one cloud, one ridge system per level; the regressions of all points become dense MFMA
+ * contractions and a blocked Cholesky of the M x M dual matrix lam I + s^2 Dt Dt^T,
+ * Dt_j = sqrt(w_j)(W_j - Wbar) (push-through form of the ridge solve); no CG (cg_iters_out gets 0),
+ * no tape (flags must be 0).  fbsde_terminal, fbsde_solve_step, fbsde_solve_backward and
+ * fbsde_time_kernel return FBSDE_EINVAL for shared_dw = 1. */
 
 /* Reverse mode of fbsde_solve for the loss L = sum_p u_bar[p] u(0, x0_p): hand-written adjoint of
  * the whole backward chain (Newton by the implicit-function rule, the regression through one extra
@@ -161,6 +167,21 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
  * overwrites them: solve again before using ws for anything else. */
 int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t reps, void* ws,
                       size_t ws_bytes, float* avg_ms, fbsde_stream stream);
+
+/* Dense helpers of the shared-increment form, exported for verification and reuse.
+ * fbsde_gemm: C = alpha * A op(B) + beta * C on the matrix cores (v_mfma 16x16x4, FP64 or FP32
+ *   operands by prec), A [m][lda] row-major (k contiguous); nt = 1: B [n][ldb] (op(B) = B^T),
+ *   nt = 0: B [k][ldb] (op(B) = B); C [m][ldc]; all device memory.
+ * fbsde_cholesky_solve: blocked Cholesky K = L L^T in place (lower triangle of the n x n SPD matrix
+ *   K [n][ldk]) and, for P > 0, the solve X (L L^T) = R of the P right-hand sides stored as rows of
+ *   R [P][ldr], in place; ws device scratch of fbsde_cholesky_workspace(prec, n, P) bytes; *info
+ *   (host) is nonzero if a non-positive pivot was met; synchronises the stream. */
+int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+               const void* B, int64_t ldb, void* C, int64_t ldc, double alpha, double beta,
+               fbsde_stream stream);
+size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P);
+int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr,
+                         void* ws, size_t ws_bytes, int32_t* info, fbsde_stream stream);
 
 /* Human-readable text of a return code. */
 const char* fbsde_strerror(int code);

@@ -2,7 +2,8 @@
 for very high-dimensional semilinear parabolic PDEs: HIP kernels behind a C ABI (include/fbsde.h),
 with a thin Python front end over PyTorch device memory and streams."""
 from . import _native
-from .api import (FBSDEFunction, Problem, normals, solve, solve_autograd, solve_backward, solve_step, state_ld,
+from .api import (FBSDEFunction, Problem, cholesky_solve, gemm, normals, solve, solve_autograd, solve_backward,
+                  solve_step, state_ld,
                   terminal, time_kernel, workspace,
                   workspace_size)
 from ._native import (F32C, F64, F_ALLEN_CAHN, F_HJB, F_ZERO, G_AC, G_AFFINE, G_HJB_LOG, G_QUAD, FbsdeError)

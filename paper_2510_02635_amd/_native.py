@@ -12,7 +12,8 @@ ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
 WS_TAPE = 1
 
 EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
-            "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_strerror")
+            "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
+            "fbsde_cholesky_solve", "fbsde_strerror")
 
 
 class CProblem(ctypes.Structure):
@@ -64,10 +65,16 @@ def load():
     lib.fbsde_solve_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_normals.argtypes = [pb, i64, i32, i64, i64, vp, vp, vp]
     lib.fbsde_time_kernel.argtypes = [pb, i64, i32, i32, vp, sz, P(ctypes.c_float), vp]
+    lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
+                               ctypes.c_double, vp]
+    lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]
+    lib.fbsde_cholesky_workspace.restype = sz
+    lib.fbsde_cholesky_solve.argtypes = [i32, i64, vp, i64, i64, vp, i64, vp, sz, P(i32), vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
-                 "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel"):
+                 "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm",
+                 "fbsde_cholesky_solve"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -222,3 +222,28 @@ def solve_autograd(pb, x0, gp=None, fp=None):
     gp = torch.tensor(pb.gp, dtype=torch.float64) if gp is None else gp
     fp = torch.tensor(pb.fp, dtype=torch.float64) if fp is None else fp
     return FBSDEFunction.apply(x0, gp, fp, pb)
+
+
+def gemm(A, B, nt=True, C=None, alpha=1.0, beta=0.0):
+    """C = alpha * A op(B) + beta * C on the matrix cores; op(B) = B^T (nt) or B.  float32 / float64."""
+    prec = N.F64 if A.dtype == torch.float64 else N.F32C
+    m, k = A.shape
+    n = B.shape[0] if nt else B.shape[1]
+    if C is None:
+        C = torch.zeros((m, n), dtype=A.dtype, device=A.device)
+    N.check(N.load().fbsde_gemm(prec, 1 if nt else 0, m, n, k, A.data_ptr(), A.stride(0), B.data_ptr(), B.stride(0),
+                                C.data_ptr(), C.stride(0), alpha, beta, _stream()))
+    return C
+
+
+def cholesky_solve(K, R=None):
+    """In-place blocked Cholesky of K (lower) and in-place solve X K = R of the rows of R; returns info."""
+    prec = N.F64 if K.dtype == torch.float64 else N.F32C
+    n = K.shape[0]
+    P = 0 if R is None else R.shape[0]
+    ws = torch.empty(int(N.load().fbsde_cholesky_workspace(prec, n, P)), dtype=torch.uint8, device=K.device)
+    info = ctypes.c_int32(0)
+    N.check(N.load().fbsde_cholesky_solve(prec, n, K.data_ptr(), K.stride(0), P, None if R is None else R.data_ptr(),
+                                          n if R is None else R.stride(0), ws.data_ptr(), ws.numel(),
+                                          ctypes.byref(info), _stream()))
+    return int(info.value)

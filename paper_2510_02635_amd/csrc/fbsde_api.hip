@@ -12,6 +12,7 @@
 #include "fbsde.h"
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
+#include "fbsde_shared.hpp"
 
 using namespace fbsde;
 
@@ -38,7 +39,7 @@ int check_problem(const fbsde_problem* pb, int64_t P) {
     if (pb->ridge_rel == 0.0 && pb->M <= pb->d + 1) return FBSDE_EINVAL;
     if (pb->newton_iters < 1 || pb->cg_maxit < 1 || !(pb->cg_rtol >= 0.0)) return FBSDE_EINVAL;
     if (pb->prec != FBSDE_F64 && pb->prec != FBSDE_F32C) return FBSDE_EINVAL;
-    if (pb->shared_dw != 0) return FBSDE_EINVAL;   // shared increments: not on this path
+    if (pb->shared_dw != 0 && pb->shared_dw != 1) return FBSDE_EINVAL;
     if (pb->reserved != 0) return FBSDE_EINVAL;
     // grid.y carries the point index
     if (pb->M > (int64_t)1 << 30 || pb->N > (int64_t)1 << 30 || P > 65535) return FBSDE_EINVAL;
@@ -126,6 +127,50 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
         ws.cbar = (double*)take(PM * 8);
         ws.adj = (double*)take((size_t)P * 16 * 8);
     }
+    return off;
+}
+
+// ------------------------------------------------------------------ shared-increment workspace
+struct SWS {
+    void *W, *Dt, *K, *Linv, *scr, *R, *ax, *xc, *DtT;
+    double *Wbar, *wpart, *w, *sqw, *rn2, *Ya, *Yb, *scal, *xc2, *ysc;
+    int* info;
+};
+constexpr int SH_RCH = 64;   // row chunks of the two-stage weighted mean
+
+size_t carve_shared(const Plan& pl, int64_t P, char* base, SWS& ws) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += round_up((int64_t)bytes, 256);
+        return p;
+    };
+    const size_t M = pl.M, ld = pl.ld, e = pl.esz;
+    const size_t nb = (M + CB - 1) / CB;
+    ws.W = take(M * ld * e);
+    ws.Dt = take(M * ld * e);
+    // dual form (M <= d): K is M x M; primal form (M > d): K is ld x ld, Dt^T [ld][M] is needed
+    const bool primal = pl.M > pl.d;
+    const size_t kn = primal ? ld : M;
+    const size_t nbk = (kn + CB - 1) / CB;
+    ws.K = take(kn * kn * e);
+    ws.Linv = take(std::max(nb, nbk) * CB * CB * e);
+    ws.scr = take(std::max<size_t>(std::max<size_t>(M, ld), (size_t)P) * CB * e);
+    ws.DtT = primal ? take(ld * M * e) : nullptr;
+    ws.R = take((size_t)P * M * e);
+    ws.ax = take((size_t)P * ld * e);
+    ws.xc = take((size_t)P * ld * e);
+    ws.Wbar = (double*)take(ld * 8);
+    ws.wpart = (double*)take((size_t)SH_RCH * ld * 8);
+    ws.w = (double*)take(M * 8);
+    ws.sqw = (double*)take(M * 8);
+    ws.rn2 = (double*)take(M * 8);
+    ws.Ya = (double*)take((size_t)P * M * 8);
+    ws.Yb = (double*)take((size_t)P * M * 8);
+    ws.scal = (double*)take((size_t)P * NS * 8);
+    ws.xc2 = (double*)take((size_t)P * 8);
+    ws.ysc = (double*)take(M * 8);
+    ws.info = (int*)take(64);
     return off;
 }
 
@@ -245,15 +290,16 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
 
 template <typename S>
 void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S* W, int64_t ldw, const double* ax,
-                    WS& ws, double* Y, double* rn2, uint32_t* status, hipStream_t st, double* dydc = nullptr) {
+                    WS& ws, double* Y, double* rn2, uint32_t* status, hipStream_t st, double* dydc = nullptr,
+                    const double* scal = nullptr, int shared = 0) {
     const Keys ky = keys_of(pb);
     const double dt = pb->T / (double)pb->N;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
         hipLaunchKernelGGL((k_reverse<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
                            ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0, std::sqrt(dt),
-                           pb->s, dt, ax, ws.scal, NS, fspec_of(pb), pb->newton_iters, ky.k0, ky.k1,
-                           pb->point_base, Y, rn2, dydc, status);
+                           pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters, ky.k0, ky.k1,
+                           pb->point_base, Y, rn2, dydc, status, shared);
     });
 }
 
@@ -372,6 +418,99 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     return last_error();
 }
 
+__global__ void k_info_to_status(const int* info, uint32_t* status, int64_t P) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < P && *info) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
+}
+
+// Algorithm 1 with increments shared by all points: one cloud, one ridge system per level, the
+// regressions of all points as dense MFMA contractions (fbsde_shared.hpp).
+template <typename T>
+int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, int64_t P, const double* x0,
+                      double* u, double* grad, uint32_t* status, SWS& ws, hipStream_t st) {
+    T* W = (T*)ws.W;
+    T* Dt = (T*)ws.Dt;
+    T* K = (T*)ws.K;
+    T* R = (T*)ws.R;
+    T* ax = (T*)ws.ax;
+    T* xc = (T*)ws.xc;
+    const int M = (int)pl.M, ld = pl.ld, d = (int)pl.d, Pi = (int)P;
+    const double dt = pb->T / (double)pb->N, s = pb->s, s2 = s * s;
+    const Keys ky = keys_of(pb);
+    const FSpec fs = fspec_of(pb);
+    clear_status(status, P, st);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.info, 0);
+    // the shared cloud at t_N (one row set, stream 0xFFFFFFFF) and its squared norms
+    dispatch<T>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_forward<T, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W, (int64_t)ld,
+                           M, pl1.rows_per_chunk, nullptr, nullptr, nullptr, d, ld, (int)pl.N, std::sqrt(dt), s, pb->T,
+                           G_QUAD, 1.0, 0.0, ky.k0, ky.k1, 0u, 1, ws.ysc, ws.rn2, status);
+    });
+    double* Ycur = ws.Ya;
+    double* Yk = ws.Yb;
+    if (pb->g_kind == FBSDE_G_AFFINE) {
+        hipLaunchKernelGGL((k_sh_affine_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, W, ld, M, d, pb->gvec, x0,
+                           pb->mu, pb->T, s, pb->gp[0], Pi, Ycur);
+    } else {
+        hipLaunchKernelGGL((k_sh_xc<T>), dim3((unsigned)P), dim3(256), 0, st, x0, pb->mu, d, ld, pb->T, xc, ws.xc2);
+        gemm<T, true>(Pi, M, ld, xc, ld, W, ld,
+                      EpiTerminal{Ycur, ws.xc2, ws.rn2, s, pb->gp[0], pb->gp[1], pb->g_kind, M, d, status}, st);
+    }
+    int err = last_error();
+    if (err) return err;
+    const unsigned cblocks = (unsigned)((ld + 255) / 256);
+    const int rch = std::min(SH_RCH, M);
+    const int rpc = (M + rch - 1) / rch;
+    for (int k = (int)pl.N - 1; k >= 0; --k) {
+        const double t_next = (double)(k + 1) * dt;
+        const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)d : 0.0;
+        const double lam = pb->ridge_rel * s2 * t_next;
+        hipLaunchKernelGGL(k_sh_weights, dim3(1), dim3(256), 0, st, ws.rn2, M, s2, eps2, ws.w, ws.sqw);
+        hipLaunchKernelGGL((k_sh_rhs<T>), dim3((unsigned)P), dim3(256), 0, st, Ycur, ws.w, ws.sqw, M, R, ws.scal, NS);
+        hipLaunchKernelGGL((k_sh_colsum<T>), dim3(cblocks, (unsigned)((M + rpc - 1) / rpc)), dim3(256), 0, st, W, ld,
+                           M, rpc, ws.w, ws.wpart);
+        hipLaunchKernelGGL((k_sh_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, ws.wpart,
+                           (M + rpc - 1) / rpc, ws.sqw, ws.Wbar, Dt);
+        if (pl.M <= pl.d) {
+            // dual: alpha_x[p] = s F[p] Dt with F = R (lam I + s^2 Dt Dt^T)^{-1}
+            gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiStore<T>{K, (int64_t)M, s2, 0.0, lam}, st, 1);
+            cholesky<T>(K, M, M, (T*)ws.Linv, (T*)ws.scr, ws.info, st);
+            cholesky_solve_rows<T>(K, M, M, (const T*)ws.Linv, R, M, Pi, (T*)ws.scr, st);
+            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
+        } else {
+            // primal: alpha_x[p] = b_p (lam I + s^2 Dt^T Dt)^{-1}, b_p = s R[p] Dt (the pad rows/columns
+            // of the ld x ld matrix are lam I and decouple)
+            T* DtT = (T*)ws.DtT;
+            hipLaunchKernelGGL((k_transpose<T>), dim3(cblocks * 8, (unsigned)((M + 31) / 32)), dim3(256), 0, st, Dt,
+                               (int64_t)ld, M, ld, DtT, (int64_t)M);
+            gemm<T, true>(ld, ld, M, DtT, M, DtT, M, EpiStore<T>{K, (int64_t)ld, s2, 0.0, lam, d, 1.0}, st, 1);
+            cholesky<T>(K, ld, ld, (T*)ws.Linv, (T*)ws.scr, ws.info, st);
+            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
+            cholesky_solve_rows<T>(K, ld, ld, (const T*)ws.Linv, ax, ld, Pi, (T*)ws.scr, st);
+        }
+        hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, ws.Wbar, s, ws.scal, NS);
+        if (k > 0) {
+            // reverse the shared cloud to t_k (its Newton output goes to scratch) and |W_k|^2
+            dispatch<T>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
+                constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+                hipLaunchKernelGGL((k_reverse<T, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                                   (int64_t)ld, M, pl1.rows_per_chunk, d, ld, k, 0, std::sqrt(dt), s, dt, ws.Wbar,
+                                   ws.scal, NS, fs, 1, ky.k0, ky.k1, 0u, ws.ysc, ws.rn2, nullptr, status, 1);
+            });
+            gemm<T, true>(Pi, M, ld, ax, ld, W, ld, EpiNewton{Yk, ws.scal, NS, M, pb->newton_iters, fs, s, dt, status},
+                          st);
+            std::swap(Ycur, Yk);
+        } else {
+            hipLaunchKernelGGL((k_sh_outputs<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, d, ws.scal, NS, fs, dt,
+                               pb->newton_iters, u, grad, status);
+        }
+        if ((err = last_error())) return err;
+    }
+    hipLaunchKernelGGL(k_info_to_status, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, ws.info, status, P);
+    return last_error();
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -389,6 +528,12 @@ int fbsde_workspace_size(const fbsde_problem* pb, int64_t P, int32_t flags, size
     if (rc) return rc;
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
+    if (pb->shared_dw) {
+        if (flags & FBSDE_WS_TAPE) return FBSDE_EINVAL;   // the shared form has no adjoint tape yet
+        SWS sws;
+        *bytes = carve_shared(pl, P, nullptr, sws);
+        return FBSDE_OK;
+    }
     WS ws;
     *bytes = carve(pl, P, flags, nullptr, ws);
     return FBSDE_OK;
@@ -398,6 +543,7 @@ int fbsde_terminal(const fbsde_problem* pb, int64_t P, const double* x0, void* W
                    uint32_t* status, fbsde_stream stream) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
+    if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (ldw < pl.ld || ldw % 4 != 0 || !x0 || !W || !Y || !status) return FBSDE_EINVAL;
@@ -415,6 +561,7 @@ int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double
     (void)x0;
     int rc = check_problem(pb, P);
     if (rc) return rc;
+    if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (k < 0 || k >= pb->N || ldw < pl.ld || ldw % 4 != 0 || !W || !Y_next || !Y || Y == Y_next || !status ||
@@ -449,6 +596,20 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    if (pb->shared_dw) {
+        if (flags & FBSDE_WS_TAPE) return FBSDE_EINVAL;
+        Plan pl1;
+        if ((rc = make_plan(pb, 1, pl1))) return rc;
+        SWS sws;
+        if (carve_shared(pl, P, nullptr, sws) > ws_bytes) return FBSDE_ENOSPC;
+        carve_shared(pl, P, (char*)wsp, sws);
+        if (P == 0) return FBSDE_OK;
+        if (cg_iters_out)
+            for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solve
+        hipStream_t st = (hipStream_t)stream;
+        if (pb->prec == FBSDE_F64) return solve_shared_impl<double>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
+        return solve_shared_impl<float>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
+    }
     WS ws;
     if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, flags, (char*)wsp, ws);
@@ -464,6 +625,7 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
                          fbsde_stream stream) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
+    if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!x0 || !u_bar || !x0_bar || !gp_bar || !fp_bar || !status || !wsp) return FBSDE_EINVAL;
@@ -501,6 +663,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
                       float* avg_ms, fbsde_stream stream) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
+    if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!wsp || !avg_ms || reps < 1 || which < 0 || which > 3 || P == 0) return FBSDE_EINVAL;
@@ -552,6 +715,61 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+               int64_t ldb, void* C, int64_t ldc, double alpha, double beta, fbsde_stream stream) {
+    if ((prec != FBSDE_F64 && prec != FBSDE_F32C) || m < 0 || n < 0 || k < 0 || !A || !B || !C) return FBSDE_EINVAL;
+    if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX || lda < k * (nt ? 1 : 0) || ldc < n) return FBSDE_EINVAL;
+    if (nt ? ldb < k : ldb < n) return FBSDE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == FBSDE_F64) {
+        if (nt) gemm<double, true>((int)m, (int)n, (int)k, (const double*)A, lda, (const double*)B, ldb,
+                                   EpiStore<double>{(double*)C, ldc, alpha, beta, 0.0}, st);
+        else gemm<double, false>((int)m, (int)n, (int)k, (const double*)A, lda, (const double*)B, ldb,
+                                 EpiStore<double>{(double*)C, ldc, alpha, beta, 0.0}, st);
+    } else {
+        if (nt) gemm<float, true>((int)m, (int)n, (int)k, (const float*)A, lda, (const float*)B, ldb,
+                                  EpiStore<float>{(float*)C, ldc, alpha, beta, 0.0}, st);
+        else gemm<float, false>((int)m, (int)n, (int)k, (const float*)A, lda, (const float*)B, ldb,
+                                EpiStore<float>{(float*)C, ldc, alpha, beta, 0.0}, st);
+    }
+    return last_error();
+}
+
+size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P) {
+    const size_t e = (prec == FBSDE_F64) ? 8 : 4;
+    const size_t nb = (size_t)((n + CB - 1) / CB);
+    return nb * CB * CB * e + (size_t)std::max<int64_t>(n, P) * CB * e + 256;
+}
+
+int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr, void* ws,
+                         size_t ws_bytes, int32_t* info, fbsde_stream stream) {
+    if ((prec != FBSDE_F64 && prec != FBSDE_F32C) || n < 1 || n > INT32_MAX || P < 0 || P > INT32_MAX || !K || !ws ||
+        !info || ldk < n || (P > 0 && (!R || ldr < n)))
+        return FBSDE_EINVAL;
+    if (fbsde_cholesky_workspace(prec, n, P) > ws_bytes) return FBSDE_ENOSPC;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t e = (prec == FBSDE_F64) ? 8 : 4;
+    const size_t nb = (size_t)((n + CB - 1) / CB);
+    char* base = (char*)ws;
+    void* Linv = base;
+    void* scr = base + nb * CB * CB * e;
+    int* dinfo = (int*)(base + nb * CB * CB * e + (size_t)std::max<int64_t>(n, P) * CB * e);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, dinfo, 0);
+    if (prec == FBSDE_F64) {
+        cholesky<double>((double*)K, ldk, (int)n, (double*)Linv, (double*)scr, dinfo, st);
+        if (P > 0) cholesky_solve_rows<double>((const double*)K, ldk, (int)n, (const double*)Linv, (double*)R, ldr,
+                                               (int)P, (double*)scr, st);
+    } else {
+        cholesky<float>((float*)K, ldk, (int)n, (float*)Linv, (float*)scr, dinfo, st);
+        if (P > 0) cholesky_solve_rows<float>((const float*)K, ldk, (int)n, (const float*)Linv, (float*)R, ldr, (int)P,
+                                              (float*)scr, st);
+    }
+    if (hipMemcpyAsync(info, dinfo, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return FBSDE_EHIP;
+    return last_error();
 }
 
 const char* fbsde_strerror(int code) {

@@ -139,7 +139,7 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int i = 4 * (L + q * G::TL) + e;
-            xc[q][e] = (i < d) ? x0[(int64_t)p * d + i] + (mu ? mu[i] * T : 0.0) : 0.0;
+            xc[q][e] = (i < d) ? (x0 ? x0[(int64_t)p * d + i] : 0.0) + (mu ? mu[i] * T : 0.0) : 0.0;
         }
     uint32_t st = 0;
     for (int jb = r0; jb < r1; jb += G::TPW) {
@@ -538,7 +538,8 @@ __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int ld, int k, int zero_state,
           double sqdt, double s, double dt, const double* __restrict__ ax, const double* __restrict__ scal,
           int ns, FSpec f, int newton_iters, uint32_t k0, uint32_t k1, uint32_t point_base,
-          double* __restrict__ Y, double* __restrict__ rn2, double* __restrict__ dydc, uint32_t* __restrict__ status) {
+          double* __restrict__ Y, double* __restrict__ rn2, double* __restrict__ dydc, uint32_t* __restrict__ status,
+          int shared) {
     using G = Geo<Q, TEAM>;
     using R = S;
     __shared__ double red[2 * G::BS / 64];
@@ -546,7 +547,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     const int team = threadIdx.x / G::TL, L = threadIdx.x % G::TL;
     const int r0 = blockIdx.x * rows_per_chunk;
     const int r1 = min(M, r0 + rows_per_chunk);
-    const uint32_t qs = point_base + (uint32_t)p;
+    const uint32_t qs = shared ? 0xFFFFFFFFu : point_base + (uint32_t)p;
     R a[Q][4];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {

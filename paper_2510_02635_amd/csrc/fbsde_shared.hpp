@@ -1,0 +1,208 @@
+// Shared-increment form of one backward level (the common-randomness remark after Lemma 3.7):
+// all P evaluation points use the same particle cloud W [M][ld], so the kernel weights, the weighted
+// mean and the ridge system are shared and only the responses Y [P][M] differ.  Per level
+//   w_j            from |W_j|^2 (eq. Dj, Gaussian kernel)
+//   Dt_j           = sqrt(w_j) (W_j - Wbar)                       [M][ld]
+//   K              = lam I + s^2 Dt Dt^T                          [M][M] (Gram, MFMA)   -> Cholesky
+//   R[p][j]        = sqrt(w_j) (Y_pj - Ybar_p)                    [P][M]
+//   F              = R K^{-1}                                     (triangular solves)
+//   alpha_x[p]     = s F[p] Dt   (the dual form of the ridge normal equations: A^{-1} D'^T W (Y - Ybar))
+//   alpha_p        = Ybar_p - s alpha_x[p] . Wbar
+//   C[p][m]        = alpha_p + s alpha_x[p] . W^m_k  -> Newton in the GEMM epilogue
+// The two [P x M] x [M x d] / [P x d] x [d x M] contractions and the Gram are the MFMA GEMMs of
+// fbsde_mfma.hpp.
+#pragma once
+#include "fbsde_mfma.hpp"
+
+namespace fbsde {
+
+// Terminal values from the contraction v = xc_p . W_j (radial g): |X|^2 = |xc_p|^2 + 2 s v + s^2 |W_j|^2.
+struct EpiTerminal {
+    double* Y;
+    const double* xc2;
+    const double* rn2;
+    double s, ga, gb;
+    int g_kind, M, d;
+    uint32_t* status;
+    __device__ __forceinline__ void operator()(int p, int j, double v) const {
+        const double q = xc2[p] + 2.0 * s * v + s * s * rn2[j];
+        const double y = g_of(g_kind, ga, gb, q, d);
+        Y[(int64_t)p * M + j] = y;
+        if (!isfinite(y)) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
+    }
+};
+
+// Newton for Y^m_k of point p from the contraction v = alpha_x[p] . W^m_k.
+struct EpiNewton {
+    double* Y;
+    const double* scal;
+    int ns, M, newton_iters;
+    FSpec f;
+    double s, dt;
+    uint32_t* status;
+    __device__ __forceinline__ void operator()(int p, int j, double v) const {
+        uint32_t st = 0;
+        double Fp;
+        const double y = newton_y(f, scal[(int64_t)p * ns + 5] + s * v, scal[(int64_t)p * ns + 6], dt, newton_iters, Fp,
+                                  st);
+        Y[(int64_t)p * M + j] = y;
+        if (st) atomicOr(&status[p], st);
+    }
+};
+
+// x0 + mu T (element type T, pad zero) and its squared norm.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_xc(const double* __restrict__ x0, const double* __restrict__ mu, int d, int ld, double Tend, T* __restrict__ xc,
+        double* __restrict__ xc2) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        const double v = (i < d) ? x0[(int64_t)p * d + i] + (mu ? mu[i] * Tend : 0.0) : 0.0;
+        xc[(int64_t)p * ld + i] = (T)v;
+        s += v * v;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) xc2[p] = s;
+}
+
+// Affine terminal g = gvec . (xc_p + s W_j) + b: per-particle gvec . W_j then per (p, j).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_affine_terminal(const T* __restrict__ W, int ld, int M, int d, const double* __restrict__ gvec,
+                     const double* __restrict__ x0, const double* __restrict__ mu, double Tend, double s, double b,
+                     int P, double* __restrict__ Y) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double gx = 0.0;
+    for (int i = threadIdx.x; i < d; i += blockDim.x) gx += gvec[i] * (x0[(int64_t)p * d + i] + (mu ? mu[i] * Tend : 0.0));
+    gx = block_sum(gx, lds);
+    for (int j = 0; j < M; ++j) {
+        double gw = 0.0;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) gw += gvec[i] * (double)W[(int64_t)j * ld + i];
+        gw = block_sum(gw, lds);
+        if (threadIdx.x == 0) Y[(int64_t)p * M + j] = gx + s * gw + b;
+    }
+}
+
+// Shared kernel weights (one block): w_j, sqrt(w_j).
+__global__ void __launch_bounds__(256)
+k_sh_weights(const double* __restrict__ rn2, int M, double s2, double eps2, double* __restrict__ w,
+             double* __restrict__ sqw) {
+    __shared__ double lds[16];
+    double mn = INFINITY;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) mn = fmin(mn, rn2[j]);
+    mn = block_min(mn, lds);
+    double se = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double e = (eps2 > 0.0) ? exp(-(s2 * rn2[j] - s2 * mn) / eps2) : 1.0;
+        w[j] = e;
+        se += e;
+    }
+    se = block_sum(se, lds);
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double wj = w[j] / se;
+        w[j] = wj;
+        sqw[j] = sqrt(wj);
+    }
+}
+
+// Per point: Ybar_p = sum_j w_j Y_pj and R[p][j] = sqrt(w_j) (Y_pj - Ybar_p).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_rhs(const double* __restrict__ Y, const double* __restrict__ w, const double* __restrict__ sqw, int M,
+         T* __restrict__ R, double* __restrict__ scal, int ns) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    const double* y = Y + (int64_t)p * M;
+    double yb = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) yb += w[j] * y[j];
+    yb = block_sum(yb, lds);
+    for (int j = threadIdx.x; j < M; j += blockDim.x) R[(int64_t)p * M + j] = (T)(sqw[j] * (y[j] - yb));
+    if (threadIdx.x == 0) scal[(int64_t)p * ns + 4] = yb;
+}
+
+// Weighted mean of the cloud, two stages: part[c][i] = sum over the rows of chunk c of w_j W_j[i].
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_colsum(const T* __restrict__ W, int ld, int M, int rows_per_chunk, const double* __restrict__ w,
+            double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= ld) return;
+    const int r0 = c * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
+    double s = 0.0;
+    for (int j = r0; j < r1; ++j) s += w[j] * (double)W[(int64_t)j * ld + i];
+    part[(int64_t)c * ld + i] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_dtilde(const T* __restrict__ W, int ld, int M, const double* __restrict__ part, int nchunk,
+            const double* __restrict__ sqw, double* __restrict__ Wbar, T* __restrict__ Dt) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= ld) return;
+    double wb = 0.0;
+    for (int c = 0; c < nchunk; ++c) wb += part[(int64_t)c * ld + i];
+    if (blockIdx.y == 0) Wbar[i] = wb;
+    const int rows = (M + gridDim.y - 1) / gridDim.y;
+    const int r0 = blockIdx.y * rows, r1 = min(M, r0 + rows);
+    for (int j = r0; j < r1; ++j) Dt[(int64_t)j * ld + i] = (T)(sqw[j] * ((double)W[(int64_t)j * ld + i] - wb));
+}
+
+// out[c][r] = in[r][c] for r < rows, c < cols (32 x 32 tiles through LDS).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_transpose(const T* __restrict__ in, int64_t ldi, int rows, int cols, T* __restrict__ out, int64_t ldo) {
+    __shared__ T tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        tile[i][tx] = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : (T)0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int c = c0 + i, r = r0 + tx;
+        if (c < cols && r < rows) out[(int64_t)c * ldo + r] = tile[tx][i];
+    }
+}
+
+// Per point: alpha_p = Ybar_p - s alpha_x[p] . Wbar,  zz_p = s^2 |alpha_x[p]|^2.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_point_finish(const T* __restrict__ ax, int ld, const double* __restrict__ Wbar, double s,
+                  double* __restrict__ scal, int ns) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double xw = 0.0, xx = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        const double a = (double)ax[(int64_t)p * ld + i];
+        xw += a * Wbar[i];
+        xx += a * a;
+    }
+    xw = block_sum(xw, lds);
+    xx = block_sum(xx, lds);
+    if (threadIdx.x == 0) {
+        scal[(int64_t)p * ns + 5] = scal[(int64_t)p * ns + 4] - s * xw;
+        scal[(int64_t)p * ns + 6] = s * s * xx;
+    }
+}
+
+// Level-0 outputs in the shared form: u_p = Newton(alpha_p), grad = alpha_x[p] / F'(u).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sh_outputs(const T* __restrict__ ax, int ld, int d, const double* __restrict__ scal, int ns, FSpec f, double dt,
+             int newton_iters, double* __restrict__ u, double* __restrict__ grad, uint32_t* __restrict__ status) {
+    const int p = blockIdx.x;
+    uint32_t st = 0;
+    double Fp;
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], dt, newton_iters, Fp, st);
+    if (threadIdx.x == 0) u[p] = y;
+    if (grad)
+        for (int i = threadIdx.x; i < d; i += blockDim.x) grad[(int64_t)p * d + i] = (double)ax[(int64_t)p * ld + i] / Fp;
+    if (st && threadIdx.x == 0) atomicOr(&status[p], st);
+}
+
+}  // namespace fbsde

@@ -12,7 +12,7 @@ from paper_2510_02635_amd import _native as N
 
 def _declared(repo_root):
     text = open(os.path.join(repo_root, "include", "fbsde.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(fbsde_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|size_t|const char\*)\s+(fbsde_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol(repo_root):

@@ -132,7 +132,7 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
 
 // ------------------------------------------------------------------ shared-increment workspace
 struct SWS {
-    void *W, *Dt, *K, *Linv, *scr, *R, *ax, *xc, *DtT;
+    void *W, *Dt, *K, *R, *ax, *xc, *DtT;
     double *Wbar, *wpart, *w, *sqw, *rn2, *Ya, *Yb, *scal, *xc2, *ysc;
     int* info;
 };
@@ -146,16 +146,12 @@ size_t carve_shared(const Plan& pl, int64_t P, char* base, SWS& ws) {
         return p;
     };
     const size_t M = pl.M, ld = pl.ld, e = pl.esz;
-    const size_t nb = (M + CB - 1) / CB;
     ws.W = take(M * ld * e);
     ws.Dt = take(M * ld * e);
     // dual form (M <= d): K is M x M; primal form (M > d): K is ld x ld, Dt^T [ld][M] is needed
     const bool primal = pl.M > pl.d;
     const size_t kn = primal ? ld : M;
-    const size_t nbk = (kn + CB - 1) / CB;
     ws.K = take(kn * kn * e);
-    ws.Linv = take(std::max(nb, nbk) * CB * CB * e);
-    ws.scr = take(std::max<size_t>(std::max<size_t>(M, ld), (size_t)P) * CB * e);
     ws.DtT = primal ? take(ld * M * e) : nullptr;
     ws.R = take((size_t)P * M * e);
     ws.ax = take((size_t)P * ld * e);
@@ -475,8 +471,8 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
         if (pl.M <= pl.d) {
             // dual: alpha_x[p] = s F[p] Dt with F = R (lam I + s^2 Dt Dt^T)^{-1}
             gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiStore<T>{K, (int64_t)M, s2, 0.0, lam}, st, 1);
-            cholesky<T>(K, M, M, (T*)ws.Linv, (T*)ws.scr, ws.info, st);
-            cholesky_solve_rows<T>(K, M, M, (const T*)ws.Linv, R, M, Pi, (T*)ws.scr, st);
+            cholesky<T>(K, M, M, ws.info, st);
+            cholesky_solve_rows<T>(K, M, M, R, M, Pi, st);
             gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
         } else {
             // primal: alpha_x[p] = b_p (lam I + s^2 Dt^T Dt)^{-1}, b_p = s R[p] Dt (the pad rows/columns
@@ -485,9 +481,9 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
             hipLaunchKernelGGL((k_transpose<T>), dim3(cblocks * 8, (unsigned)((M + 31) / 32)), dim3(256), 0, st, Dt,
                                (int64_t)ld, M, ld, DtT, (int64_t)M);
             gemm<T, true>(ld, ld, M, DtT, M, DtT, M, EpiStore<T>{K, (int64_t)ld, s2, 0.0, lam, d, 1.0}, st, 1);
-            cholesky<T>(K, ld, ld, (T*)ws.Linv, (T*)ws.scr, ws.info, st);
+            cholesky<T>(K, ld, ld, ws.info, st);
             gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
-            cholesky_solve_rows<T>(K, ld, ld, (const T*)ws.Linv, ax, ld, Pi, (T*)ws.scr, st);
+            cholesky_solve_rows<T>(K, ld, ld, ax, ld, Pi, st);
         }
         hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, ws.Wbar, s, ws.scal, NS);
         if (k > 0) {
@@ -738,9 +734,8 @@ int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const 
 }
 
 size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P) {
-    const size_t e = (prec == FBSDE_F64) ? 8 : 4;
-    const size_t nb = (size_t)((n + CB - 1) / CB);
-    return nb * CB * CB * e + (size_t)std::max<int64_t>(n, P) * CB * e + 256;
+    (void)prec; (void)n; (void)P;
+    return 256;   // the status word of the factorisation
 }
 
 int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr, void* ws,
@@ -750,21 +745,14 @@ int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t 
         return FBSDE_EINVAL;
     if (fbsde_cholesky_workspace(prec, n, P) > ws_bytes) return FBSDE_ENOSPC;
     hipStream_t st = (hipStream_t)stream;
-    const size_t e = (prec == FBSDE_F64) ? 8 : 4;
-    const size_t nb = (size_t)((n + CB - 1) / CB);
-    char* base = (char*)ws;
-    void* Linv = base;
-    void* scr = base + nb * CB * CB * e;
-    int* dinfo = (int*)(base + nb * CB * CB * e + (size_t)std::max<int64_t>(n, P) * CB * e);
+    int* dinfo = (int*)ws;
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, dinfo, 0);
     if (prec == FBSDE_F64) {
-        cholesky<double>((double*)K, ldk, (int)n, (double*)Linv, (double*)scr, dinfo, st);
-        if (P > 0) cholesky_solve_rows<double>((const double*)K, ldk, (int)n, (const double*)Linv, (double*)R, ldr,
-                                               (int)P, (double*)scr, st);
+        cholesky<double>((double*)K, ldk, (int)n, dinfo, st);
+        if (P > 0) cholesky_solve_rows<double>((const double*)K, ldk, (int)n, (double*)R, ldr, (int)P, st);
     } else {
-        cholesky<float>((float*)K, ldk, (int)n, (float*)Linv, (float*)scr, dinfo, st);
-        if (P > 0) cholesky_solve_rows<float>((const float*)K, ldk, (int)n, (const float*)Linv, (float*)R, ldr, (int)P,
-                                              (float*)scr, st);
+        cholesky<float>((float*)K, ldk, (int)n, dinfo, st);
+        if (P > 0) cholesky_solve_rows<float>((const float*)K, ldk, (int)n, (float*)R, ldr, (int)P, st);
     }
     if (hipMemcpyAsync(info, dinfo, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)

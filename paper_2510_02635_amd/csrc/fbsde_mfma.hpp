@@ -5,7 +5,8 @@
 // responses differ per point, so the local linear regression of all P points is a set of dense
 // products: [P x M] x [M x d] and [P x d] x [d x M] contractions and one M x M Gram / Cholesky per
 // level.  This header holds the MFMA GEMM used for all of them (with fused epilogues), and the
-// blocked Cholesky factorisation and triangular solves built on it.
+// blocked Cholesky factorisation and triangular solves built on it (row-parallel substitutions for
+// the diagonal blocks, matrix-core GEMMs for every update).
 //
 // GEMM: C[m][n] (+)= sum_k A[m][k] * B(k, n), A row-major with k contiguous; B either [n][k]
 // (NT, k contiguous) or [k][n] (NN, n contiguous).  256 threads = 4 waves in a 2 x 2 layout; block
@@ -183,124 +184,130 @@ inline void gemm(int Md, int Nd, int Kd, const T* A, int64_t lda, const T* B, in
 }
 
 // ------------------------------------------------------------------ blocked Cholesky
-// K = L L^T in place (lower triangle), block size CB.  Per diagonal block: k_potrf_diag factors it
-// and writes the inverse of its triangle; the panel below becomes A_panel L_kk^{-T} (a GEMM with the
-// inverse), and the trailing lower triangle takes the rank-CB update (GEMM, lower tiles only).
+// K = L L^T in place (lower triangle), block size CB, right-looking: per diagonal block, factor it
+// (one wavefront, LDS), solve the panel below it row by row (k_trsm_rows: every row is independent),
+// and give the trailing lower triangle the rank-CB update on the matrix cores (GEMM, lower tiles only).
 constexpr int CB = 64;
 
-// Factor the CB x CB diagonal block at (kb, kb) of K (row-major, ldk) and write L_kk^{-1} into Linv
-// (CB x CB row-major, upper part zero).  One block of 256 threads; the block sits in LDS (in FP64).
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_potrf_diag(T* __restrict__ K, int64_t ldk, int n, int kb, T* __restrict__ Linv, int* __restrict__ info) {
-    __shared__ double a[CB][CB + 1];
-    __shared__ double li[CB][CB + 1];
-    const int o = kb * CB;
-    const int nb = min(CB, n - o);
-    const int tid = threadIdx.x;
-    for (int t = tid; t < CB * CB; t += 256) {
-        const int i = t / CB, j = t % CB;
-        a[i][j] = (i < nb && j < nb && j <= i) ? (double)K[(int64_t)(o + i) * ldk + o + j] : (i == j ? 1.0 : 0.0);
-        li[i][j] = 0.0;
-    }
-    __syncthreads();
-    // right-looking unblocked Cholesky of the block
-    for (int j = 0; j < CB; ++j) {
-        if (tid == 0) {
-            const double djj = a[j][j];
-            if (!(djj > 0.0)) { if (j < nb) atomicOr(info, 1); a[j][j] = 1.0; }
-            else a[j][j] = sqrt(djj);
-        }
-        __syncthreads();
-        const double djj = a[j][j];
-        for (int i = j + 1 + tid; i < CB; i += 256) a[i][j] /= djj;
-        __syncthreads();
-        const int rem = CB - j - 1;
-        for (int t = tid; t < rem * rem; t += 256) {
-            const int i = j + 1 + t / rem, c = j + 1 + t % rem;
-            if (c <= i) a[i][c] -= a[i][j] * a[c][j];
-        }
-        __syncthreads();
-    }
-    // inverse of the lower triangle, column by column: L X = I
-    for (int c = tid; c < CB; c += 256) {
-        for (int i = 0; i < CB; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) s -= a[i][k] * li[k][c];
-            li[i][c] = (i >= c) ? s / a[i][i] : 0.0;
-        }
-    }
-    __syncthreads();
-    for (int t = tid; t < CB * CB; t += 256) {
-        const int i = t / CB, j = t % CB;
-        if (i < nb && j < nb) K[(int64_t)(o + i) * ldk + o + j] = (T)((j <= i) ? a[i][j] : 0.0);
-        Linv[t] = (T)li[i][j];
-    }
+// Broadcast lane src's value to the whole wavefront (src uniform).
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Copy rows r0.. (rows of them) x columns c0..c0+cols-1 of K into scratch [rows][CB], zero beyond cols
-// (the panel GEMMs may not read and write the same memory across blocks).
+// Factor the CB x CB diagonal block at (kb, kb) in place (lower; upper part of the block zeroed).
+// One wavefront: lane i owns row i in registers; the column being eliminated is read from its owner
+// lanes with readlane (no LDS, no barriers).
 template <typename T>
-__global__ void k_copy_panel(const T* __restrict__ K, int64_t ldk, int r0, int rows, int c0, int cols,
-                             T* __restrict__ out) {
-    const int64_t n = (int64_t)rows * CB;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t / CB), j = (int)(t % CB);
-        out[t] = (j < cols) ? K[(int64_t)(r0 + i) * ldk + c0 + j] : (T)0;
+__global__ void __launch_bounds__(64)
+k_potrf_diag(T* __restrict__ K, int64_t ldk, int n, int kb, int* __restrict__ info) {
+    const int o = kb * CB;
+    const int nb = min(CB, n - o);
+    const int i = threadIdx.x;
+    double a[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+        a[j] = (i < nb && j < nb && j <= i) ? (double)K[(int64_t)(o + i) * ldk + o + j] : ((i == j) ? 1.0 : 0.0);
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        double d = lane_bcast(a[j], j);
+        if (!(d > 0.0)) { bad |= (j < nb); d = 1.0; }
+        const double piv = sqrt(d);
+        if (i == j) a[j] = piv;
+        else if (i > j) a[j] /= piv;
+#pragma unroll
+        for (int c = j + 1; c < CB; ++c) {
+            const double lcj = lane_bcast(a[j], c);   // L[c][j]
+            if (i >= c) a[c] -= a[j] * lcj;
+        }
+    }
+    if (bad && i == 0) atomicOr(info, 1);
+    if (i < nb)
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+            if (j < nb) K[(int64_t)(o + i) * ldk + o + j] = (T)((j <= i) ? a[j] : 0.0);
+}
+
+// Row-wise triangular solves with the CB x CB lower factor Lkk (row-major, ldl) for rows r of X
+// (row stride ldx, columns c0 .. c0 + w - 1, in place), one wavefront per row, lane c owning column c
+// (column-oriented substitution):
+//   upper = 0: x Lkk^T = a   (x_c = (a_c - sum_{k<c} x_k L[c][k]) / L[c][c], c ascending)
+//   upper = 1: x Lkk   = a   (x_c = (a_c - sum_{k>c} x_k L[k][c]) / L[c][c], c descending)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_trsm_rows(const T* __restrict__ Lkk, int64_t ldl, int w, T* __restrict__ X, int64_t ldx, int rows, int c0, int upper) {
+    __shared__ double L[CB][CB + 1];
+    for (int t = threadIdx.x; t < CB * CB; t += 256) {
+        const int i = t / CB, j = t % CB;
+        L[i][j] = (i < w && j < w) ? (double)Lkk[(int64_t)i * ldl + j] : ((i == j) ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = blockIdx.x * 4 + wave; r < rows; r += gridDim.x * 4) {
+        T* row = X + (int64_t)r * ldx + c0;
+        double a = (lane < w) ? (double)row[lane] : 0.0;
+        if (!upper) {
+            for (int c = 0; c < CB; ++c) {
+                const double xc = lane_bcast(a, c) / L[c][c];
+                if (lane == c) a = xc;
+                else if (lane > c) a -= xc * L[lane][c];
+            }
+        } else {
+            for (int c = CB - 1; c >= 0; --c) {
+                const double xc = lane_bcast(a, c) / L[c][c];
+                if (lane == c) a = xc;
+                else if (lane < c) a -= xc * L[c][lane];
+            }
+        }
+        if (lane < w) row[lane] = (T)a;
     }
 }
 
 // Blocked Cholesky of the n x n SPD matrix K (lower triangle used and overwritten with L).
-// Linv: nblocks x CB x CB inverses of the diagonal blocks; scratch: n x CB.
 template <typename T>
-inline void cholesky(T* K, int64_t ldk, int n, T* Linv, T* scratch, int* info, hipStream_t st) {
+inline void cholesky(T* K, int64_t ldk, int n, int* info, hipStream_t st) {
     const int nb = (n + CB - 1) / CB;
     for (int kb = 0; kb < nb; ++kb) {
         const int o = kb * CB;
-        hipLaunchKernelGGL((k_potrf_diag<T>), dim3(1), dim3(256), 0, st, K, ldk, n, kb, Linv + (size_t)kb * CB * CB,
-                           info);
+        hipLaunchKernelGGL((k_potrf_diag<T>), dim3(1), dim3(64), 0, st, K, ldk, n, kb, info);
         const int rows = n - o - CB;
         if (rows <= 0) break;
-        // panel: L[i][kb] = A[i][kb] L_kk^{-T}, i.e. C[i][c] = sum_k P[i][k] Linv[c][k]
-        hipLaunchKernelGGL((k_copy_panel<T>), dim3((unsigned)std::min<int64_t>(((int64_t)rows * CB + 255) / 256, 4096)),
-                           dim3(256), 0, st, K, ldk, o + CB, rows, o, CB, scratch);
-        gemm<T, true>(rows, CB, CB, scratch, CB, Linv + (size_t)kb * CB * CB, CB,
-                      EpiStore<T>{K + (int64_t)(o + CB) * ldk + o, ldk, 1.0, 0.0, 0.0}, st);
+        // panel: L[i][kb] solves L[i][kb] L_kk^T = A[i][kb]
+        hipLaunchKernelGGL((k_trsm_rows<T>), dim3((unsigned)std::min((rows + 3) / 4, 4096)), dim3(256), 0, st,
+                           K + (int64_t)o * ldk + o, ldk, CB, K + (int64_t)(o + CB) * ldk, ldk, rows, o, 0);
         // trailing update of the lower triangle: K[i][j] -= sum_c L[i][c] L[j][c]
         gemm<T, true>(rows, rows, CB, K + (int64_t)(o + CB) * ldk + o, ldk, K + (int64_t)(o + CB) * ldk + o, ldk,
                       EpiStore<T>{K + (int64_t)(o + CB) * ldk + o + CB, ldk, -1.0, 1.0, 0.0}, st, 1);
     }
 }
 
-// Solve (L L^T) X^T = R^T for the P right-hand sides stored as rows of R [P][n] (in place), with the
-// factor from cholesky().  Blocked forward then backward substitution on row blocks of CB columns;
-// diagonal blocks apply the stored inverses, off-diagonal parts are GEMM updates.  scratch: P x CB.
+// Solve X (L L^T) = R for the P right-hand sides stored as rows of R [P][n] (in place), with the factor
+// from cholesky().  Right-looking blocked substitutions: per column block, the row-wise triangular solve,
+// then one wide GEMM update of all remaining columns.
 template <typename T>
-inline void cholesky_solve_rows(const T* L, int64_t ldl, int n, const T* Linv, T* R, int64_t ldr, int P, T* scratch,
-                                hipStream_t st) {
+inline void cholesky_solve_rows(const T* L, int64_t ldl, int n, T* R, int64_t ldr, int P, hipStream_t st) {
     const int nb = (n + CB - 1) / CB;
-    // forward: L Y^T = R^T  <=>  Y[p][blk kb] = (R[p][kb] - sum_{j<kb} Y[p][j] L[kb][j]) L_kk^{-T}
+    const unsigned rblocks = (unsigned)std::min((P + 3) / 4, 4096);
+    // forward: Y L^T = R
     for (int kb = 0; kb < nb; ++kb) {
         const int o = kb * CB, w = std::min(CB, n - o);
-        if (kb > 0)   // R[p][o..o+w) -= sum_{j < o} Y[p][j] L[o + c][j]
-            gemm<T, true>(P, w, o, R, ldr, L + (int64_t)o * ldl, ldl, EpiStore<T>{R + o, ldr, -1.0, 1.0, 0.0}, st);
-        // Y[p][o + c] = sum_k R[p][o + k] Linv[c][k]
-        hipLaunchKernelGGL((k_copy_panel<T>), dim3((unsigned)std::min<int64_t>(((int64_t)P * CB + 255) / 256, 4096)),
-                           dim3(256), 0, st, R, ldr, 0, P, o, w, scratch);
-        gemm<T, true>(P, w, w, scratch, CB, Linv + (size_t)kb * CB * CB, CB, EpiStore<T>{R + o, ldr, 1.0, 0.0, 0.0}, st);
+        hipLaunchKernelGGL((k_trsm_rows<T>), dim3(rblocks), dim3(256), 0, st, L + (int64_t)o * ldl + o, ldl, w, R, ldr,
+                           P, o, 0);
+        const int rest = n - o - w;
+        if (rest > 0)   // R[p][o + w + c] -= sum_k Y[p][o + k] L[o + w + c][o + k]
+            gemm<T, true>(P, rest, w, R + o, ldr, L + (int64_t)(o + w) * ldl + o, ldl,
+                          EpiStore<T>{R + o + w, ldr, -1.0, 1.0, 0.0}, st);
     }
-    // backward: L^T X^T = Y^T  <=>  X[p][kb] = (Y[p][kb] - sum_{j>kb} X[p][j] L[j][kb]) L_kk^{-1}
+    // backward: X L = Y
     for (int kb = nb - 1; kb >= 0; --kb) {
         const int o = kb * CB, w = std::min(CB, n - o);
-        const int after = n - (o + w);
-        if (after > 0)   // Y[p][o + c] -= sum_{j >= o + w} X[p][j] L[j][o + c]   (NN: B[k = j][n = c])
-            gemm<T, false>(P, w, after, R + o + w, ldr, L + (int64_t)(o + w) * ldl + o, ldl,
-                           EpiStore<T>{R + o, ldr, -1.0, 1.0, 0.0}, st);
-        // X[p][o + r] = sum_c Y[p][o + c] Linv[c][r]   (L_kk^T x = y  =>  x = L_kk^{-T} y)
-        hipLaunchKernelGGL((k_copy_panel<T>), dim3((unsigned)std::min<int64_t>(((int64_t)P * CB + 255) / 256, 4096)),
-                           dim3(256), 0, st, R, ldr, 0, P, o, w, scratch);
-        gemm<T, false>(P, w, w, scratch, CB, Linv + (size_t)kb * CB * CB, CB, EpiStore<T>{R + o, ldr, 1.0, 0.0, 0.0},
-                       st);
+        hipLaunchKernelGGL((k_trsm_rows<T>), dim3(rblocks), dim3(256), 0, st, L + (int64_t)o * ldl + o, ldl, w, R, ldr,
+                           P, o, 1);
+        if (o > 0)   // Y[p][c] -= sum_r X[p][o + r] L[o + r][c]   for c < o   (NN: B[k = r][n = c])
+            gemm<T, false>(P, o, w, R + o, ldr, L + (int64_t)o * ldl, ldl, EpiStore<T>{R, ldr, -1.0, 1.0, 0.0}, st);
     }
 }
 

@@ -168,6 +168,26 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
 int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t reps, void* ws,
                       size_t ws_bytes, float* avg_ms, fbsde_stream stream);
 
+/* Many evaluation points of many PDE instances (uneven d, M, f, g, precision) in one persistent
+ * launch per geometry class (element type and row-team shape, decided by d): every workgroup owns a
+ * workspace slot, pulls (instance, point) items from an atomic queue (largest M first) and runs the
+ * whole of Algorithm 1 for that point inside the workgroup -- forward sweep, and per level the
+ * weights, moments, CG solve with workgroup reductions, reversal and Newton -- so the batch needs no
+ * host round trip and no per-level launch.  Results are the same as fbsde_solve of each instance
+ * (same Philox streams; CG stops per point at the same test).
+ *   pbs     host [n_inst] descriptors (shared_dw must be 0);  P host [n_inst] point counts
+ *   x0, u, grad, status   host arrays of n_inst device pointers ([P_i][d_i], [P_i], [P_i][d_i] or
+ *                         NULL, [P_i]); grad itself may be NULL
+ *   max_slots             workgroups (points in flight) per class; each holds one point's state
+ *   ws      device workspace of fbsde_batched_workspace_size(pbs, n_inst, P, max_slots) bytes
+ * Synchronises the stream once (after uploading the work tables), then runs asynchronously. */
+int fbsde_batched_workspace_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                                 int32_t max_slots, size_t* bytes);
+int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                        const double* const* x0, double* const* u, double* const* grad,
+                        uint32_t* const* status, int32_t max_slots, void* ws, size_t ws_bytes,
+                        fbsde_stream stream);
+
 /* Dense helpers of the shared-increment form, exported for verification and reuse.
  * fbsde_gemm: C = alpha * A op(B) + beta * C on the matrix cores (v_mfma 16x16x4, FP64 or FP32
  *   operands by prec), A [m][lda] row-major (k contiguous); nt = 1: B [n][ldb] (op(B) = B^T),

@@ -3,6 +3,7 @@ for very high-dimensional semilinear parabolic PDEs: HIP kernels behind a C ABI 
 with a thin Python front end over PyTorch device memory and streams."""
 from . import _native
 from .api import (FBSDEFunction, Problem, cholesky_solve, gemm, normals, solve, solve_autograd, solve_backward,
+                  solve_batched,
                   solve_step, state_ld,
                   terminal, time_kernel, workspace,
                   workspace_size)

@@ -13,7 +13,7 @@ WS_TAPE = 1
 
 EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
             "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
-            "fbsde_cholesky_solve", "fbsde_strerror")
+            "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched", "fbsde_strerror")
 
 
 class CProblem(ctypes.Structure):
@@ -70,11 +70,13 @@ def load():
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]
     lib.fbsde_cholesky_workspace.restype = sz
     lib.fbsde_cholesky_solve.argtypes = [i32, i64, vp, i64, i64, vp, i64, vp, sz, P(i32), vp]
+    lib.fbsde_batched_workspace_size.argtypes = [pb, i64, vp, i32, P(sz)]
+    lib.fbsde_solve_batched.argtypes = [pb, i64, vp, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
                  "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm",
-                 "fbsde_cholesky_solve"):
+                 "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

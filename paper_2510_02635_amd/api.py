@@ -247,3 +247,32 @@ def cholesky_solve(K, R=None):
                                           n if R is None else R.stride(0), ws.data_ptr(), ws.numel(),
                                           ctypes.byref(info), _stream()))
     return int(info.value)
+
+
+def solve_batched(problems, x0s, want_grad=True, max_slots=512, ws=None):
+    """Persistent batched solve of several instances: lists of Problem and of device x0 [P_i][d_i] tensors.
+
+    Returns lists (u_i, grad_i or None, status_i).
+    """
+    n = len(problems)
+    if n != len(x0s) or n == 0:
+        raise ValueError("one x0 tensor per problem")
+    cps = (N.CProblem * n)(*[pb.c() for pb in problems])
+    Ps = (ctypes.c_int64 * n)(*[int(x.shape[0]) for x in x0s])
+    us, grads, sts = [], [], []
+    for pb, x in zip(problems, x0s):
+        _dev_f64(x, (x.shape[0], pb.d))
+        us.append(torch.empty(x.shape[0], dtype=torch.float64, device=x.device))
+        grads.append(torch.empty((x.shape[0], pb.d), dtype=torch.float64, device=x.device) if want_grad else None)
+        sts.append(torch.empty(x.shape[0], dtype=torch.int32, device=x.device))
+    ptrs = lambda ts: (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
+    size = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_batched_workspace_size(cps, n, ctypes.cast(Ps, ctypes.c_void_p), max_slots,
+                                                  ctypes.byref(size)))
+    if ws is None or ws.numel() < size.value:
+        ws = torch.empty(int(size.value), dtype=torch.uint8, device=x0s[0].device)
+    gp = ptrs(grads) if want_grad else None
+    N.check(N.load().fbsde_solve_batched(cps, n, ctypes.cast(Ps, ctypes.c_void_p), ptrs(x0s), ptrs(us),
+                                         None if gp is None else ctypes.cast(gp, ctypes.c_void_p), ptrs(sts), max_slots,
+                                         ws.data_ptr(), ws.numel(), _stream()))
+    return us, grads, sts

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libfbsde.so")
-SOURCES = ["fbsde_api.hip"]
+SOURCES = ["fbsde_api.hip", "fbsde_shared_api.hip", "fbsde_batched_api.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for every HIP translation unit: the kernels are
@@ -30,15 +30,27 @@ def hipcc():
 
 
 def build(verbose=True):
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(LIBDIR, src.replace(".hip", ".o"))
         cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    with ThreadPoolExecutor(max_workers=len(jobs)) as pool:
+        results = list(pool.map(lambda j: subprocess.run(j[0], capture_output=True, text=True), jobs))
+    for (cmd, _), res in zip(jobs, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise subprocess.CalledProcessError(res.returncode, cmd)
+        if verbose and res.stderr:
+            # hipcc's host pass does not know the packed-FP32 target feature: drop that note
+            lines = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln]
+            if lines:
+                sys.stderr.write("\n".join(lines) + "\n")
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

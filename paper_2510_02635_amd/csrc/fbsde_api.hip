@@ -1,81 +1,14 @@
-// Host side of the C ABI declared in include/fbsde.h: validation, workspace carving and the
-// launch sequence of Algorithm 1 (forward sweep, then the backward level loop) and of its
-// adjoint.  All control crosses host -> device here; kernels live in fbsde_kernels.hpp /
-// fbsde_adjoint.hpp.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <type_traits>
-
-#include "fbsde.h"
+// Host side of the C ABI declared in include/fbsde.h, per-point path: validation, workspace carving and
+// the launch sequence of Algorithm 1 (forward sweep, then the backward level loop) and of its adjoint.
+// The shared-increment form and the persistent batched launch live in their own translation units.
+#include "fbsde_host.hpp"
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
-#include "fbsde_shared.hpp"
-#include "fbsde_batched.hpp"
-
-#include <map>
-#include <tuple>
-#include <vector>
 
 using namespace fbsde;
+using namespace fbsde::host;
 
 namespace {
-
-constexpr int NS = 8;   // per-point FP64 scalars (see k_moments_finish)
-
-struct Plan {
-    int64_t d, M, N;
-    int ld, Q, TEAM, BS, TPW, nchunk, rows_per_chunk;
-    size_t esz;
-};
-
-int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
-
-int check_problem(const fbsde_problem* pb, int64_t P) {
-    if (!pb || P < 0) return FBSDE_EINVAL;
-    if (pb->d < 1 || pb->M < 2 || pb->N < 1) return FBSDE_EINVAL;
-    if (!(pb->T > 0.0) || !(pb->s > 0.0)) return FBSDE_EINVAL;
-    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_HJB) return FBSDE_EINVAL;
-    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_AFFINE) return FBSDE_EINVAL;
-    if (pb->g_kind == FBSDE_G_AFFINE && !pb->gvec) return FBSDE_EINVAL;
-    if (!(pb->eps_h >= 0.0) || !(pb->ridge_rel >= 0.0)) return FBSDE_EINVAL;
-    if (pb->ridge_rel == 0.0 && pb->M <= pb->d + 1) return FBSDE_EINVAL;
-    if (pb->newton_iters < 1 || pb->cg_maxit < 1 || !(pb->cg_rtol >= 0.0)) return FBSDE_EINVAL;
-    if (pb->prec != FBSDE_F64 && pb->prec != FBSDE_F32C) return FBSDE_EINVAL;
-    if (pb->shared_dw != 0 && pb->shared_dw != 1) return FBSDE_EINVAL;
-    if (pb->reserved != 0) return FBSDE_EINVAL;
-    // grid.y carries the point index
-    if (pb->M > (int64_t)1 << 30 || pb->N > (int64_t)1 << 30 || P > 65535) return FBSDE_EINVAL;
-    return FBSDE_OK;
-}
-
-int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
-    pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
-    pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;
-    pl.ld = (int)round_up(pb->d, (pl.esz == 8) ? 16 : 32);
-    const int groups = pl.ld / 4;
-    const int qmax = (pl.esz == 8) ? 4 : 8;
-    pl.TEAM = 0;
-    for (int team = 1; team <= 16; team *= 2) {
-        const int q = (groups + 64 * team - 1) / (64 * team);
-        if (q <= qmax) {
-            pl.TEAM = team;
-            pl.Q = (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : 8;
-            break;
-        }
-    }
-    if (pl.TEAM == 0) return FBSDE_EINVAL;   // d beyond 16384 (FP64) / 32768 (FP32C)
-    pl.BS = 64 * std::max(pl.TEAM, 4);
-    pl.TPW = pl.BS / (64 * pl.TEAM);
-    const int64_t target_blocks = 4096;
-    int64_t nchunk = (target_blocks + std::max<int64_t>(P, 1) - 1) / std::max<int64_t>(P, 1);
-    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, pb->M / (2 * pl.TPW)));
-    pl.rows_per_chunk = (int)((pb->M + nchunk - 1) / nchunk);
-    pl.nchunk = (int)((pb->M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
-    return FBSDE_OK;
-}
 
 struct WS {
     void* W;
@@ -134,73 +67,6 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     }
     return off;
 }
-
-// ------------------------------------------------------------------ shared-increment workspace
-struct SWS {
-    void *W, *Dt, *K, *R, *ax, *xc, *DtT;
-    double *Wbar, *wpart, *w, *sqw, *rn2, *Ya, *Yb, *scal, *xc2, *ysc;
-    int* info;
-};
-constexpr int SH_RCH = 64;   // row chunks of the two-stage weighted mean
-
-size_t carve_shared(const Plan& pl, int64_t P, char* base, SWS& ws) {
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> char* {
-        char* p = base ? base + off : nullptr;
-        off += round_up((int64_t)bytes, 256);
-        return p;
-    };
-    const size_t M = pl.M, ld = pl.ld, e = pl.esz;
-    ws.W = take(M * ld * e);
-    ws.Dt = take(M * ld * e);
-    // dual form (M <= d): K is M x M; primal form (M > d): K is ld x ld, Dt^T [ld][M] is needed
-    const bool primal = pl.M > pl.d;
-    const size_t kn = primal ? ld : M;
-    ws.K = take(kn * kn * e);
-    ws.DtT = primal ? take(ld * M * e) : nullptr;
-    ws.R = take((size_t)P * M * e);
-    ws.ax = take((size_t)P * ld * e);
-    ws.xc = take((size_t)P * ld * e);
-    ws.Wbar = (double*)take(ld * 8);
-    ws.wpart = (double*)take((size_t)SH_RCH * ld * 8);
-    ws.w = (double*)take(M * 8);
-    ws.sqw = (double*)take(M * 8);
-    ws.rn2 = (double*)take(M * 8);
-    ws.Ya = (double*)take((size_t)P * M * 8);
-    ws.Yb = (double*)take((size_t)P * M * 8);
-    ws.scal = (double*)take((size_t)P * NS * 8);
-    ws.xc2 = (double*)take((size_t)P * 8);
-    ws.ysc = (double*)take(M * 8);
-    ws.info = (int*)take(64);
-    return off;
-}
-
-template <typename S, typename Fn>
-void dispatch(int Q, int TEAM, Fn&& fn) {
-#define FB_CASE(QQ, TT) \
-    case QQ * 100 + TT: fn(std::integral_constant<int, QQ>{}, std::integral_constant<int, TT>{}); return;
-    switch (Q * 100 + TEAM) {
-        FB_CASE(1, 1) FB_CASE(1, 2) FB_CASE(1, 4) FB_CASE(1, 8) FB_CASE(1, 16)
-        FB_CASE(2, 1) FB_CASE(2, 2) FB_CASE(2, 4) FB_CASE(2, 8) FB_CASE(2, 16)
-        FB_CASE(4, 1) FB_CASE(4, 2) FB_CASE(4, 4) FB_CASE(4, 8) FB_CASE(4, 16)
-        default: break;
-    }
-    if constexpr (std::is_same<S, float>::value) {
-        switch (Q * 100 + TEAM) {
-            FB_CASE(8, 1) FB_CASE(8, 2) FB_CASE(8, 4) FB_CASE(8, 8) FB_CASE(8, 16)
-            default: break;
-        }
-    }
-#undef FB_CASE
-}
-
-struct Keys { uint32_t k0, k1; };
-Keys keys_of(const fbsde_problem* pb) {
-    return {(uint32_t)(pb->seed & 0xFFFFFFFFull), (uint32_t)((pb->seed >> 32) ^ (uint64_t)pb->instance)};
-}
-FSpec fspec_of(const fbsde_problem* pb) { return {pb->f_kind, pb->fp[0], pb->fp[1]}; }
-
-int last_error() { return (hipGetLastError() == hipSuccess) ? FBSDE_OK : FBSDE_EHIP; }
 
 // -------------------------------------------------------------------- launch sequences
 template <typename S>
@@ -312,7 +178,7 @@ int tape_tag(const fbsde_problem* pb, int64_t P) {
     return (int)(h & 0x7FFFFFFF) | 1;
 }
 
-void clear_status(uint32_t* status, int64_t P, hipStream_t st) {
+void clear_status_impl(uint32_t* status, int64_t P, hipStream_t st) {
     if (P > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((P + 255) / 256, 1024)), dim3(256), 0,
                                   st, status, P, 0u);
 }
@@ -419,160 +285,53 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     return last_error();
 }
 
-__global__ void k_info_to_status(const int* info, uint32_t* status, int64_t P) {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < P && *info) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
-}
+}  // namespace
 
-// Algorithm 1 with increments shared by all points: one cloud, one ridge system per level, the
-// regressions of all points as dense MFMA contractions (fbsde_shared.hpp).
-template <typename T>
-int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, int64_t P, const double* x0,
-                      double* u, double* grad, uint32_t* status, SWS& ws, hipStream_t st) {
-    T* W = (T*)ws.W;
-    T* Dt = (T*)ws.Dt;
-    T* K = (T*)ws.K;
-    T* R = (T*)ws.R;
-    T* ax = (T*)ws.ax;
-    T* xc = (T*)ws.xc;
-    const int M = (int)pl.M, ld = pl.ld, d = (int)pl.d, Pi = (int)P;
-    const double dt = pb->T / (double)pb->N, s = pb->s, s2 = s * s;
+namespace fbsde {
+namespace host {
+
+void clear_status(uint32_t* status, int64_t P, hipStream_t st) { clear_status_impl(status, P, st); }
+void set_int(int* a, int v, hipStream_t st) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, a, v); }
+
+template <typename S>
+void shared_forward(const fbsde_problem* pb, const Plan& pl1, S* W, double* Yscratch, double* rn2, uint32_t* status,
+                    hipStream_t st) {
     const Keys ky = keys_of(pb);
-    const FSpec fs = fspec_of(pb);
-    clear_status(status, P, st);
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.info, 0);
-    // the shared cloud at t_N (one row set, stream 0xFFFFFFFF) and its squared norms
-    dispatch<T>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
+    const double dt = pb->T / (double)pb->N;
+    dispatch<S>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        hipLaunchKernelGGL((k_forward<T, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W, (int64_t)ld,
-                           M, pl1.rows_per_chunk, nullptr, nullptr, nullptr, d, ld, (int)pl.N, std::sqrt(dt), s, pb->T,
-                           G_QUAD, 1.0, 0.0, ky.k0, ky.k1, 0u, 1, ws.ysc, ws.rn2, status);
+        hipLaunchKernelGGL((k_forward<S, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           (int64_t)pl1.ld, (int)pl1.M, pl1.rows_per_chunk, nullptr, nullptr, nullptr, (int)pl1.d,
+                           pl1.ld, (int)pl1.N, std::sqrt(dt), pb->s, pb->T, G_QUAD, 1.0, 0.0, ky.k0, ky.k1, 0u, 1,
+                           Yscratch, rn2, status);
     });
-    double* Ycur = ws.Ya;
-    double* Yk = ws.Yb;
-    if (pb->g_kind == FBSDE_G_AFFINE) {
-        hipLaunchKernelGGL((k_sh_affine_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, W, ld, M, d, pb->gvec, x0,
-                           pb->mu, pb->T, s, pb->gp[0], Pi, Ycur);
-    } else {
-        hipLaunchKernelGGL((k_sh_xc<T>), dim3((unsigned)P), dim3(256), 0, st, x0, pb->mu, d, ld, pb->T, xc, ws.xc2);
-        gemm<T, true>(Pi, M, ld, xc, ld, W, ld,
-                      EpiTerminal{Ycur, ws.xc2, ws.rn2, s, pb->gp[0], pb->gp[1], pb->g_kind, M, d, status}, st);
-    }
-    int err = last_error();
-    if (err) return err;
-    const unsigned cblocks = (unsigned)((ld + 255) / 256);
-    const int rch = std::min(SH_RCH, M);
-    const int rpc = (M + rch - 1) / rch;
-    for (int k = (int)pl.N - 1; k >= 0; --k) {
-        const double t_next = (double)(k + 1) * dt;
-        const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)d : 0.0;
-        const double lam = pb->ridge_rel * s2 * t_next;
-        hipLaunchKernelGGL(k_sh_weights, dim3(1), dim3(256), 0, st, ws.rn2, M, s2, eps2, ws.w, ws.sqw);
-        hipLaunchKernelGGL((k_sh_rhs<T>), dim3((unsigned)P), dim3(256), 0, st, Ycur, ws.w, ws.sqw, M, R, ws.scal, NS);
-        hipLaunchKernelGGL((k_sh_colsum<T>), dim3(cblocks, (unsigned)((M + rpc - 1) / rpc)), dim3(256), 0, st, W, ld,
-                           M, rpc, ws.w, ws.wpart);
-        hipLaunchKernelGGL((k_sh_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, ws.wpart,
-                           (M + rpc - 1) / rpc, ws.sqw, ws.Wbar, Dt);
-        if (pl.M <= pl.d) {
-            // dual: alpha_x[p] = s F[p] Dt with F = R (lam I + s^2 Dt Dt^T)^{-1}
-            gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiStore<T>{K, (int64_t)M, s2, 0.0, lam}, st, 1);
-            cholesky<T>(K, M, M, ws.info, st);
-            cholesky_solve_rows<T>(K, M, M, R, M, Pi, st);
-            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
-        } else {
-            // primal: alpha_x[p] = b_p (lam I + s^2 Dt^T Dt)^{-1}, b_p = s R[p] Dt (the pad rows/columns
-            // of the ld x ld matrix are lam I and decouple)
-            T* DtT = (T*)ws.DtT;
-            hipLaunchKernelGGL((k_transpose<T>), dim3(cblocks * 8, (unsigned)((M + 31) / 32)), dim3(256), 0, st, Dt,
-                               (int64_t)ld, M, ld, DtT, (int64_t)M);
-            gemm<T, true>(ld, ld, M, DtT, M, DtT, M, EpiStore<T>{K, (int64_t)ld, s2, 0.0, lam, d, 1.0}, st, 1);
-            cholesky<T>(K, ld, ld, ws.info, st);
-            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
-            cholesky_solve_rows<T>(K, ld, ld, ax, ld, Pi, st);
-        }
-        hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, ws.Wbar, s, ws.scal, NS);
-        if (k > 0) {
-            // reverse the shared cloud to t_k (its Newton output goes to scratch) and |W_k|^2
-            dispatch<T>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
-                constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-                hipLaunchKernelGGL((k_reverse<T, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W,
-                                   (int64_t)ld, M, pl1.rows_per_chunk, d, ld, k, 0, std::sqrt(dt), s, dt, ws.Wbar,
-                                   ws.scal, NS, fs, 1, ky.k0, ky.k1, 0u, ws.ysc, ws.rn2, nullptr, status, 1);
-            });
-            gemm<T, true>(Pi, M, ld, ax, ld, W, ld, EpiNewton{Yk, ws.scal, NS, M, pb->newton_iters, fs, s, dt, status},
-                          st);
-            std::swap(Ycur, Yk);
-        } else {
-            hipLaunchKernelGGL((k_sh_outputs<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, d, ws.scal, NS, fs, dt,
-                               pb->newton_iters, u, grad, status);
-        }
-        if ((err = last_error())) return err;
-    }
-    hipLaunchKernelGGL(k_info_to_status, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, ws.info, status, P);
-    return last_error();
-}
-
-// ------------------------------------------------------------------ persistent batched launch
-SlotLayout slot_layout(int64_t M, int ld, size_t esz) {
-    SlotLayout lay;
-    size_t off = (size_t)round_up((int64_t)(M * ld * esz), 256);
-    lay.off_rn2 = off; off += (size_t)round_up(M * 8, 256);
-    lay.off_Y = off; off += (size_t)round_up(M * 8, 256);
-    lay.off_w = off; off += (size_t)round_up(M * 8, 256);
-    lay.off_c2 = off; off += (size_t)round_up(M * 8, 256);
-    lay.off_vec = off; off += (size_t)round_up(6 * (int64_t)ld * 8, 256);
-    lay.bytes = off;
-    return lay;
-}
-
-struct BatchClass {
-    int prec, Q, TEAM;
-    std::vector<int> insts;   // instance indices, by decreasing per-point cost
-    int64_t items = 0;
-    int64_t maxM = 0;
-    int ld = 0;
-};
-
-int batch_classes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, std::vector<BatchClass>& out) {
-    std::map<std::tuple<int, int, int, int>, BatchClass> cls;
-    for (int64_t i = 0; i < n_inst; ++i) {
-        int rc = check_problem(&pbs[i], P[i]);
-        if (rc) return rc;
-        if (pbs[i].shared_dw) return FBSDE_EINVAL;
-        Plan pl;
-        if ((rc = make_plan(&pbs[i], 1, pl))) return rc;
-        const auto key = std::make_tuple(pbs[i].prec, pl.Q, pl.TEAM, pl.ld);
-        BatchClass& c = cls[key];
-        c.prec = pbs[i].prec; c.Q = pl.Q; c.TEAM = pl.TEAM; c.ld = pl.ld;
-        c.insts.push_back((int)i);
-        c.items += P[i];
-        c.maxM = std::max<int64_t>(c.maxM, pbs[i].M);
-    }
-    for (auto& kv : cls) {
-        BatchClass& c = kv.second;
-        std::stable_sort(c.insts.begin(), c.insts.end(), [&](int a, int b) { return pbs[a].M > pbs[b].M; });
-        out.push_back(c);
-    }
-    return FBSDE_OK;
-}
-
-size_t batch_header_bytes(int64_t n_inst, int64_t total_items) {
-    return (size_t)round_up(n_inst * (int64_t)sizeof(BatchInst), 256) +
-           (size_t)round_up(total_items * (int64_t)sizeof(BatchItem), 256) + 256;
 }
 
 template <typename S>
-void launch_batched_class(const BatchClass& c, const BatchInst* d_insts, const BatchItem* d_items, int n_items,
-                          int* queue, char* slots, const SlotLayout& lay, int nslots, hipStream_t st) {
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, queue, 0);
-    dispatch<S>(c.Q, c.TEAM, [&](auto qc, auto tc) {
+void shared_reverse(const fbsde_problem* pb, const Plan& pl1, int k, S* W, const double* ax_dummy, const double* scal,
+                    double* Yscratch, double* rn2, uint32_t* status, hipStream_t st) {
+    const Keys ky = keys_of(pb);
+    const double dt = pb->T / (double)pb->N;
+    dispatch<S>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        hipLaunchKernelGGL((k_batched<S, QQ, TT>), dim3(nslots), dim3(Geo<QQ, TT>::BS), 0, st, d_insts, d_items,
-                           n_items, queue, slots, lay);
+        hipLaunchKernelGGL((k_reverse<S, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           (int64_t)pl1.ld, (int)pl1.M, pl1.rows_per_chunk, (int)pl1.d, pl1.ld, k, 0, std::sqrt(dt),
+                           pb->s, dt, ax_dummy, scal, NS, fspec_of(pb), 1, ky.k0, ky.k1, 0u, Yscratch, rn2, nullptr,
+                           status, 1);
     });
 }
 
-}  // namespace
+template void shared_forward<double>(const fbsde_problem*, const Plan&, double*, double*, double*, uint32_t*,
+                                     hipStream_t);
+template void shared_forward<float>(const fbsde_problem*, const Plan&, float*, double*, double*, uint32_t*,
+                                    hipStream_t);
+template void shared_reverse<double>(const fbsde_problem*, const Plan&, int, double*, const double*, const double*,
+                                     double*, double*, uint32_t*, hipStream_t);
+template void shared_reverse<float>(const fbsde_problem*, const Plan&, int, float*, const double*, const double*,
+                                    double*, double*, uint32_t*, hipStream_t);
+
+}  // namespace host
+}  // namespace fbsde
 
 // ============================================================================ C ABI
 extern "C" {
@@ -591,8 +350,7 @@ int fbsde_workspace_size(const fbsde_problem* pb, int64_t P, int32_t flags, size
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (pb->shared_dw) {
         if (flags & FBSDE_WS_TAPE) return FBSDE_EINVAL;   // the shared form has no adjoint tape yet
-        SWS sws;
-        *bytes = carve_shared(pl, P, nullptr, sws);
+        *bytes = shared_workspace_bytes(pb, P);
         return FBSDE_OK;
     }
     WS ws;
@@ -659,17 +417,9 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
         if (flags & FBSDE_WS_TAPE) return FBSDE_EINVAL;
-        Plan pl1;
-        if ((rc = make_plan(pb, 1, pl1))) return rc;
-        SWS sws;
-        if (carve_shared(pl, P, nullptr, sws) > ws_bytes) return FBSDE_ENOSPC;
-        carve_shared(pl, P, (char*)wsp, sws);
-        if (P == 0) return FBSDE_OK;
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solve
-        hipStream_t st = (hipStream_t)stream;
-        if (pb->prec == FBSDE_F64) return solve_shared_impl<double>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
-        return solve_shared_impl<float>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
+        return solve_shared(pb, P, x0, u, grad, status, wsp, ws_bytes, (hipStream_t)stream);
     }
     WS ws;
     if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
@@ -776,141 +526,6 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
-}
-
-int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
-               int64_t ldb, void* C, int64_t ldc, double alpha, double beta, fbsde_stream stream) {
-    if ((prec != FBSDE_F64 && prec != FBSDE_F32C) || m < 0 || n < 0 || k < 0 || !A || !B || !C) return FBSDE_EINVAL;
-    if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX || lda < k * (nt ? 1 : 0) || ldc < n) return FBSDE_EINVAL;
-    if (nt ? ldb < k : ldb < n) return FBSDE_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    if (prec == FBSDE_F64) {
-        if (nt) gemm<double, true>((int)m, (int)n, (int)k, (const double*)A, lda, (const double*)B, ldb,
-                                   EpiStore<double>{(double*)C, ldc, alpha, beta, 0.0}, st);
-        else gemm<double, false>((int)m, (int)n, (int)k, (const double*)A, lda, (const double*)B, ldb,
-                                 EpiStore<double>{(double*)C, ldc, alpha, beta, 0.0}, st);
-    } else {
-        if (nt) gemm<float, true>((int)m, (int)n, (int)k, (const float*)A, lda, (const float*)B, ldb,
-                                  EpiStore<float>{(float*)C, ldc, alpha, beta, 0.0}, st);
-        else gemm<float, false>((int)m, (int)n, (int)k, (const float*)A, lda, (const float*)B, ldb,
-                                EpiStore<float>{(float*)C, ldc, alpha, beta, 0.0}, st);
-    }
-    return last_error();
-}
-
-size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P) {
-    (void)prec; (void)n; (void)P;
-    return 256;   // the status word of the factorisation
-}
-
-int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr, void* ws,
-                         size_t ws_bytes, int32_t* info, fbsde_stream stream) {
-    if ((prec != FBSDE_F64 && prec != FBSDE_F32C) || n < 1 || n > INT32_MAX || P < 0 || P > INT32_MAX || !K || !ws ||
-        !info || ldk < n || (P > 0 && (!R || ldr < n)))
-        return FBSDE_EINVAL;
-    if (fbsde_cholesky_workspace(prec, n, P) > ws_bytes) return FBSDE_ENOSPC;
-    hipStream_t st = (hipStream_t)stream;
-    int* dinfo = (int*)ws;
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, dinfo, 0);
-    if (prec == FBSDE_F64) {
-        cholesky<double>((double*)K, ldk, (int)n, dinfo, st);
-        if (P > 0) cholesky_solve_rows<double>((const double*)K, ldk, (int)n, (double*)R, ldr, (int)P, st);
-    } else {
-        cholesky<float>((float*)K, ldk, (int)n, dinfo, st);
-        if (P > 0) cholesky_solve_rows<float>((const float*)K, ldk, (int)n, (float*)R, ldr, (int)P, st);
-    }
-    if (hipMemcpyAsync(info, dinfo, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return FBSDE_EHIP;
-    return last_error();
-}
-
-int fbsde_batched_workspace_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, int32_t max_slots,
-                                 size_t* bytes) {
-    if (!pbs || !P || !bytes || n_inst < 1 || max_slots < 1) return FBSDE_EINVAL;
-    std::vector<BatchClass> cls;
-    int rc = batch_classes(pbs, n_inst, P, cls);
-    if (rc) return rc;
-    int64_t total = 0;
-    size_t slot_max = 0;
-    for (const auto& c : cls) {
-        total += c.items;
-        const SlotLayout lay = slot_layout(c.maxM, c.ld, c.prec == FBSDE_F64 ? 8 : 4);
-        slot_max = std::max(slot_max, lay.bytes * (size_t)std::min<int64_t>(c.items, max_slots));
-    }
-    *bytes = batch_header_bytes(n_inst, total) + slot_max;
-    return FBSDE_OK;
-}
-
-int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const double* const* x0,
-                        double* const* u, double* const* grad, uint32_t* const* status, int32_t max_slots, void* wsp,
-                        size_t ws_bytes, fbsde_stream stream) {
-    if (!pbs || !P || !x0 || !u || !status || !wsp || n_inst < 1 || max_slots < 1) return FBSDE_EINVAL;
-    std::vector<BatchClass> cls;
-    int rc = batch_classes(pbs, n_inst, P, cls);
-    if (rc) return rc;
-    size_t need = 0;
-    if ((rc = fbsde_batched_workspace_size(pbs, n_inst, P, max_slots, &need))) return rc;
-    if (need > ws_bytes) return FBSDE_ENOSPC;
-    for (int64_t i = 0; i < n_inst; ++i)
-        if (P[i] > 0 && (!x0[i] || !u[i] || !status[i])) return FBSDE_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    // descriptor table and the work items of every class (device copies in the workspace header)
-    std::vector<BatchInst> hi((size_t)n_inst);
-    for (int64_t i = 0; i < n_inst; ++i) {
-        const fbsde_problem* pb = &pbs[i];
-        Plan pl;
-        make_plan(pb, 1, pl);
-        const Keys ky = keys_of(pb);
-        BatchInst& b = hi[(size_t)i];
-        b.d = (int)pb->d; b.ld = pl.ld; b.M = (int)pb->M; b.N = (int)pb->N; b.P = (int)P[i];
-        b.T = pb->T; b.s = pb->s; b.eps_h = pb->eps_h; b.ridge_rel = pb->ridge_rel;
-        b.rtol2 = pb->cg_rtol * pb->cg_rtol;
-        b.newton_iters = pb->newton_iters;
-        b.cg_maxit = pb->cg_fixed_iters > 0 ? pb->cg_fixed_iters : pb->cg_maxit;
-        b.g_kind = pb->g_kind;
-        b.warm = (pb->M > pb->d + 1) ? 1 : 0;
-        b.f = fspec_of(pb);
-        b.ga = pb->gp[0]; b.gb = pb->gp[1];
-        b.mu = pb->mu; b.gvec = pb->gvec;
-        b.k0 = ky.k0; b.k1 = ky.k1; b.point_base = pb->point_base;
-        b.x0 = x0[i]; b.u = u[i]; b.grad = grad ? grad[i] : nullptr; b.status = status[i];
-        clear_status(status[i], P[i], st);
-    }
-    std::vector<BatchItem> items;
-    std::vector<std::pair<int64_t, int64_t>> ranges;   // per class: [first item, count)
-    for (const auto& c : cls) {
-        const int64_t first = (int64_t)items.size();
-        for (int i : c.insts)
-            for (int64_t p = 0; p < P[i]; ++p) items.push_back(BatchItem{i, (int)p});
-        ranges.emplace_back(first, (int64_t)items.size() - first);
-    }
-    char* base = (char*)wsp;
-    BatchInst* d_insts = (BatchInst*)base;
-    BatchItem* d_items = (BatchItem*)(base + round_up(n_inst * (int64_t)sizeof(BatchInst), 256));
-    int* queue = (int*)(base + batch_header_bytes(n_inst, (int64_t)items.size()) - 256);
-    char* slots = base + batch_header_bytes(n_inst, (int64_t)items.size());
-    if (hipMemcpyAsync(d_insts, hi.data(), hi.size() * sizeof(BatchInst), hipMemcpyHostToDevice, st) != hipSuccess)
-        return FBSDE_EHIP;
-    if (!items.empty() &&
-        hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, st) != hipSuccess)
-        return FBSDE_EHIP;
-    // the host tables must outlive the copies
-    if (hipStreamSynchronize(st) != hipSuccess) return FBSDE_EHIP;
-    for (size_t ci = 0; ci < cls.size(); ++ci) {
-        const BatchClass& c = cls[ci];
-        if (ranges[ci].second == 0) continue;
-        const SlotLayout lay = slot_layout(c.maxM, c.ld, c.prec == FBSDE_F64 ? 8 : 4);
-        const int nslots = (int)std::min<int64_t>(ranges[ci].second, max_slots);
-        if (c.prec == FBSDE_F64)
-            launch_batched_class<double>(c, d_insts, d_items + ranges[ci].first, (int)ranges[ci].second, queue, slots,
-                                         lay, nslots, st);
-        else
-            launch_batched_class<float>(c, d_insts, d_items + ranges[ci].first, (int)ranges[ci].second, queue, slots,
-                                        lay, nslots, st);
-        if ((rc = last_error())) return rc;
-    }
-    return FBSDE_OK;
 }
 
 const char* fbsde_strerror(int code) {

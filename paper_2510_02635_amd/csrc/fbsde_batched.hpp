@@ -6,7 +6,7 @@
 // workspace.  Work items are ordered by decreasing cost, so the queue balances uneven instances; the
 // kernel ends when the queue is empty (every workgroup reaches that exit).
 #pragma once
-#include "fbsde_kernels.hpp"
+#include "fbsde_rowteam.hpp"
 
 namespace fbsde {
 
@@ -64,14 +64,6 @@ struct PointSolver {
     __device__ void forward() {
         const double sqdt = sqrt(I.T / I.N);
         const uint32_t qs = I.point_base + (uint32_t)p;
-        double xc[Q][4];
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int i = 4 * (L + q * G::TL) + e;
-                xc[q][e] = (i < I.d) ? I.x0[(int64_t)p * I.d + i] + (I.mu ? I.mu[i] * I.T : 0.0) : 0.0;
-            }
         uint32_t st = 0;
         for (int jb = 0; jb < I.M; jb += G::TPW) {
             const int j = jb + team;
@@ -83,7 +75,7 @@ struct PointSolver {
                 for (int e = 0; e < 4; ++e) wv[q][e] = 0.0;
             if (valid)
                 for (int k = 0; k < I.N; ++k)
-#pragma unroll
+#pragma unroll 1
                     for (int q = 0; q < Q; ++q) {
                         const int g = L + q * G::TL;
                         if (4 * g < I.d) {
@@ -109,7 +101,9 @@ struct PointSolver {
                         for (int e = 0; e < 4; ++e) {
                             const double ws = (double)v[e];
                             n2 += ws * ws;
-                            const double X = xc[q][e] + I.s * ws;
+                            const int i = e0 + e;
+                            const double xc = (i < I.d) ? I.x0[(int64_t)p * I.d + i] + (I.mu ? I.mu[i] * I.T : 0.0) : 0.0;
+                            const double X = xc + I.s * ws;
                             if (I.g_kind == G_AFFINE) gq += ((e0 + e < I.d) ? I.gvec[e0 + e] : 0.0) * X;
                             else gq += X * X;
                         }
@@ -156,50 +150,65 @@ struct PointSolver {
         __syncthreads();
     }
 
-    // moments pass + CG initialisation; returns |b|^2 and sets rr, wv.
+    // moments and CG initialisation; returns |b|^2 and sets rr, wv.  Two passes over the state when warm:
+    // (1) sum_j w_j W_j and sum_j w_j (Y_j - Ybar) W_j; (2) the pieces of A x0 -- two accumulators per pass
+    // keep the register footprint of the persistent kernel low.
     __device__ void moments(int warm, double rho, double lam, double& rr, double& bb2, double& wvp) {
-        R v[Q][4];
+        double sig = 0.0, tau = 0.0;
+        {
+            CSum<R> a1[Q][4], a2[Q][4];
+            for (int j = team; j < I.M; j += G::TPW) {
+                const S* row = W + (int64_t)j * I.ld;
+                const double wjd = w[j], cjd = c2[j];
+                sig += cjd;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int e0 = 4 * (L + q * G::TL);
+                    if (e0 < I.ld) {
+                        S xr[4];
+                        load4(row + e0, xr);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            a1[q][e].add((R)wjd * xr[e]);
+                            a2[q][e].add((R)cjd * xr[e]);
+                        }
+                    }
+                }
+            }
+            combine(a1, Wbar);
+            combine(a2, tmp);
+        }
         if (warm) {
+            R v[Q][4];
             load_vec(x, v);
 #pragma unroll
             for (int q = 0; q < Q; ++q)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[q][e] = (R)(rho * (double)v[q][e]);
-        }
-        CSum<R> a1[Q][4], a2[Q][4], a3[Q][4];
-        double sig = 0.0, tau = 0.0;
-        for (int jb = 0; jb < I.M; jb += G::TPW) {
-            const int j = jb + team;
-            const bool valid = j < I.M;
-            S xr[Q][4];
-            CSum<R> dl;
-            double wjd = 0.0;
-            if (valid) {
-                const S* row = W + (int64_t)j * I.ld;
-                wjd = w[j];
-                const double cjd = c2[j];
-                sig += cjd;
+            CSum<R> a3[Q][4];
+            for (int jb = 0; jb < I.M; jb += G::TPW) {
+                const int j = jb + team;
+                const bool valid = j < I.M;
+                S xr[Q][4];
+                CSum<R> dl;
+                if (valid) {
+                    const S* row = W + (int64_t)j * I.ld;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const int e0 = 4 * (L + q * G::TL);
-                    if (e0 < I.ld) load4(row + e0, xr[q]);
-                    else {
+                    for (int q = 0; q < Q; ++q) {
+                        const int e0 = 4 * (L + q * G::TL);
+                        if (e0 < I.ld) load4(row + e0, xr[q]);
+                        else {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) xr[q][e] = (S)0;
-                    }
+                            for (int e = 0; e < 4; ++e) xr[q][e] = (S)0;
+                        }
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        a1[q][e].add((R)wjd * xr[q][e]);
-                        a2[q][e].add((R)cjd * xr[q][e]);
-                        if (warm) dl.add(xr[q][e] * v[q][e]);
+                        for (int e = 0; e < 4; ++e) dl.add(xr[q][e] * v[q][e]);
                     }
                 }
-            }
-            if (warm) {
                 double t = dl.get(), unused = 0.0;
                 team_sum2<TEAM>(t, unused, red, team);
                 if (valid) {
-                    const double ct = wjd * t;
+                    const double ct = w[j] * t;
                     tau += ct;
 #pragma unroll
                     for (int q = 0; q < Q; ++q)
@@ -207,10 +216,8 @@ struct PointSolver {
                         for (int e = 0; e < 4; ++e) a3[q][e].add((R)ct * xr[q][e]);
                 }
             }
+            combine(a3, qv);
         }
-        combine(a1, Wbar);
-        combine(a2, tmp);
-        if (warm) combine(a3, qv);
         sig = block_sum((L == 0) ? sig : 0.0, red);
         tau = block_sum((L == 0) ? tau : 0.0, red);
         double rr_ = 0.0, bb_ = 0.0, wv_ = 0.0;
@@ -291,7 +298,7 @@ struct PointSolver {
             CSum<R> n2s, dots;
             if (valid) {
                 S* row = W + (int64_t)j * I.ld;
-#pragma unroll
+#pragma unroll 1
                 for (int q = 0; q < Q; ++q) {
                     const int g = L + q * G::TL;
                     const int e0 = 4 * g;

@@ -1,0 +1,114 @@
+// Host-side helpers shared by the translation units of libfbsde (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "fbsde.h"
+#include "fbsde_device.hpp"
+
+namespace fbsde {
+namespace host {
+
+
+constexpr int NS = 8;   // per-point FP64 scalars (see k_moments_finish)
+
+struct Plan {
+    int64_t d, M, N;
+    int ld, Q, TEAM, BS, TPW, nchunk, rows_per_chunk;
+    size_t esz;
+};
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+inline int check_problem(const fbsde_problem* pb, int64_t P) {
+    if (!pb || P < 0) return FBSDE_EINVAL;
+    if (pb->d < 1 || pb->M < 2 || pb->N < 1) return FBSDE_EINVAL;
+    if (!(pb->T > 0.0) || !(pb->s > 0.0)) return FBSDE_EINVAL;
+    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_HJB) return FBSDE_EINVAL;
+    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_AFFINE) return FBSDE_EINVAL;
+    if (pb->g_kind == FBSDE_G_AFFINE && !pb->gvec) return FBSDE_EINVAL;
+    if (!(pb->eps_h >= 0.0) || !(pb->ridge_rel >= 0.0)) return FBSDE_EINVAL;
+    if (pb->ridge_rel == 0.0 && pb->M <= pb->d + 1) return FBSDE_EINVAL;
+    if (pb->newton_iters < 1 || pb->cg_maxit < 1 || !(pb->cg_rtol >= 0.0)) return FBSDE_EINVAL;
+    if (pb->prec != FBSDE_F64 && pb->prec != FBSDE_F32C) return FBSDE_EINVAL;
+    if (pb->shared_dw != 0 && pb->shared_dw != 1) return FBSDE_EINVAL;
+    if (pb->reserved != 0) return FBSDE_EINVAL;
+    // grid.y carries the point index
+    if (pb->M > (int64_t)1 << 30 || pb->N > (int64_t)1 << 30 || P > 65535) return FBSDE_EINVAL;
+    return FBSDE_OK;
+}
+
+inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
+    pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
+    pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;
+    pl.ld = (int)round_up(pb->d, (pl.esz == 8) ? 16 : 32);
+    const int groups = pl.ld / 4;
+    const int qmax = (pl.esz == 8) ? 4 : 8;
+    pl.TEAM = 0;
+    for (int team = 1; team <= 16; team *= 2) {
+        const int q = (groups + 64 * team - 1) / (64 * team);
+        if (q <= qmax) {
+            pl.TEAM = team;
+            pl.Q = (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : 8;
+            break;
+        }
+    }
+    if (pl.TEAM == 0) return FBSDE_EINVAL;   // d beyond 16384 (FP64) / 32768 (FP32C)
+    pl.BS = 64 * std::max(pl.TEAM, 4);
+    pl.TPW = pl.BS / (64 * pl.TEAM);
+    const int64_t target_blocks = 4096;
+    int64_t nchunk = (target_blocks + std::max<int64_t>(P, 1) - 1) / std::max<int64_t>(P, 1);
+    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, pb->M / (2 * pl.TPW)));
+    pl.rows_per_chunk = (int)((pb->M + nchunk - 1) / nchunk);
+    pl.nchunk = (int)((pb->M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
+    return FBSDE_OK;
+}
+
+template <typename S, typename Fn>
+void dispatch(int Q, int TEAM, Fn&& fn) {
+#define FB_CASE(QQ, TT) \
+    case QQ * 100 + TT: fn(std::integral_constant<int, QQ>{}, std::integral_constant<int, TT>{}); return;
+    switch (Q * 100 + TEAM) {
+        FB_CASE(1, 1) FB_CASE(1, 2) FB_CASE(1, 4) FB_CASE(1, 8) FB_CASE(1, 16)
+        FB_CASE(2, 1) FB_CASE(2, 2) FB_CASE(2, 4) FB_CASE(2, 8) FB_CASE(2, 16)
+        FB_CASE(4, 1) FB_CASE(4, 2) FB_CASE(4, 4) FB_CASE(4, 8) FB_CASE(4, 16)
+        default: break;
+    }
+    if constexpr (std::is_same<S, float>::value) {
+        switch (Q * 100 + TEAM) {
+            FB_CASE(8, 1) FB_CASE(8, 2) FB_CASE(8, 4) FB_CASE(8, 8) FB_CASE(8, 16)
+            default: break;
+        }
+    }
+#undef FB_CASE
+}
+
+struct Keys { uint32_t k0, k1; };
+inline Keys keys_of(const fbsde_problem* pb) {
+    return {(uint32_t)(pb->seed & 0xFFFFFFFFull), (uint32_t)((pb->seed >> 32) ^ (uint64_t)pb->instance)};
+}
+inline FSpec fspec_of(const fbsde_problem* pb) { return {pb->f_kind, pb->fp[0], pb->fp[1]}; }
+
+inline int last_error() { return (hipGetLastError() == hipSuccess) ? FBSDE_OK : FBSDE_EHIP; }
+
+
+// Entry points of the other translation units.
+size_t shared_workspace_bytes(const fbsde_problem* pb, int64_t P);
+int solve_shared(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
+                 void* ws, size_t ws_bytes, hipStream_t st);
+// Forward sweep / reversal of a single shared cloud (core translation unit owns these kernels).
+template <typename S>
+void shared_forward(const fbsde_problem* pb, const Plan& pl1, S* W, double* Yscratch, double* rn2, uint32_t* status,
+                    hipStream_t st);
+template <typename S>
+void shared_reverse(const fbsde_problem* pb, const Plan& pl1, int k, S* W, const double* ax_dummy, const double* scal,
+                    double* Yscratch, double* rn2, uint32_t* status, hipStream_t st);
+void clear_status(uint32_t* status, int64_t P, hipStream_t st);
+void set_int(int* a, int v, hipStream_t st);
+
+}  // namespace host
+}  // namespace fbsde

@@ -1,0 +1,211 @@
+// Host side of the shared-increment form (every point uses the same increments): workspace, the dense
+// level chain on the matrix cores, and the exported dense helpers (MFMA GEMM, blocked Cholesky solve).
+#include "fbsde_host.hpp"
+#include "fbsde_shared.hpp"
+
+using namespace fbsde;
+using namespace fbsde::host;
+
+namespace {
+
+// ------------------------------------------------------------------ shared-increment workspace
+struct SWS {
+    void *W, *Dt, *K, *R, *ax, *xc, *DtT;
+    double *Wbar, *wpart, *w, *sqw, *rn2, *Ya, *Yb, *scal, *xc2, *ysc;
+    int* info;
+};
+constexpr int SH_RCH = 64;   // row chunks of the two-stage weighted mean
+
+size_t carve_shared(const Plan& pl, int64_t P, char* base, SWS& ws) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += round_up((int64_t)bytes, 256);
+        return p;
+    };
+    const size_t M = pl.M, ld = pl.ld, e = pl.esz;
+    ws.W = take(M * ld * e);
+    ws.Dt = take(M * ld * e);
+    // dual form (M <= d): K is M x M; primal form (M > d): K is ld x ld, Dt^T [ld][M] is needed
+    const bool primal = pl.M > pl.d;
+    const size_t kn = primal ? ld : M;
+    ws.K = take(kn * kn * e);
+    ws.DtT = primal ? take(ld * M * e) : nullptr;
+    ws.R = take((size_t)P * M * e);
+    ws.ax = take((size_t)P * ld * e);
+    ws.xc = take((size_t)P * ld * e);
+    ws.Wbar = (double*)take(ld * 8);
+    ws.wpart = (double*)take((size_t)SH_RCH * ld * 8);
+    ws.w = (double*)take(M * 8);
+    ws.sqw = (double*)take(M * 8);
+    ws.rn2 = (double*)take(M * 8);
+    ws.Ya = (double*)take((size_t)P * M * 8);
+    ws.Yb = (double*)take((size_t)P * M * 8);
+    ws.scal = (double*)take((size_t)P * NS * 8);
+    ws.xc2 = (double*)take((size_t)P * 8);
+    ws.ysc = (double*)take(M * 8);
+    ws.info = (int*)take(64);
+    return off;
+}
+
+__global__ void k_info_to_status(const int* info, uint32_t* status, int64_t P) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < P && *info) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
+}
+
+// Algorithm 1 with increments shared by all points: one cloud, one ridge system per level, the
+// regressions of all points as dense MFMA contractions (fbsde_shared.hpp).
+template <typename T>
+int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, int64_t P, const double* x0,
+                      double* u, double* grad, uint32_t* status, SWS& ws, hipStream_t st) {
+    T* W = (T*)ws.W;
+    T* Dt = (T*)ws.Dt;
+    T* K = (T*)ws.K;
+    T* R = (T*)ws.R;
+    T* ax = (T*)ws.ax;
+    T* xc = (T*)ws.xc;
+    const int M = (int)pl.M, ld = pl.ld, d = (int)pl.d, Pi = (int)P;
+    const double dt = pb->T / (double)pb->N, s = pb->s, s2 = s * s;
+    const Keys ky = keys_of(pb);
+    const FSpec fs = fspec_of(pb);
+    clear_status(status, P, st);
+    set_int(ws.info, 0, st);
+    // the shared cloud at t_N (one row set, stream 0xFFFFFFFF) and its squared norms
+    shared_forward<T>(pb, pl1, W, ws.ysc, ws.rn2, status, st);
+    double* Ycur = ws.Ya;
+    double* Yk = ws.Yb;
+    if (pb->g_kind == FBSDE_G_AFFINE) {
+        hipLaunchKernelGGL((k_sh_affine_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, W, ld, M, d, pb->gvec, x0,
+                           pb->mu, pb->T, s, pb->gp[0], Pi, Ycur);
+    } else {
+        hipLaunchKernelGGL((k_sh_xc<T>), dim3((unsigned)P), dim3(256), 0, st, x0, pb->mu, d, ld, pb->T, xc, ws.xc2);
+        gemm<T, true>(Pi, M, ld, xc, ld, W, ld,
+                      EpiTerminal{Ycur, ws.xc2, ws.rn2, s, pb->gp[0], pb->gp[1], pb->g_kind, M, d, status}, st);
+    }
+    int err = last_error();
+    if (err) return err;
+    const unsigned cblocks = (unsigned)((ld + 255) / 256);
+    const int rch = std::min(SH_RCH, M);
+    const int rpc = (M + rch - 1) / rch;
+    for (int k = (int)pl.N - 1; k >= 0; --k) {
+        const double t_next = (double)(k + 1) * dt;
+        const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)d : 0.0;
+        const double lam = pb->ridge_rel * s2 * t_next;
+        hipLaunchKernelGGL(k_sh_weights, dim3(1), dim3(256), 0, st, ws.rn2, M, s2, eps2, ws.w, ws.sqw);
+        hipLaunchKernelGGL((k_sh_rhs<T>), dim3((unsigned)P), dim3(256), 0, st, Ycur, ws.w, ws.sqw, M, R, ws.scal, NS);
+        hipLaunchKernelGGL((k_sh_colsum<T>), dim3(cblocks, (unsigned)((M + rpc - 1) / rpc)), dim3(256), 0, st, W, ld,
+                           M, rpc, ws.w, ws.wpart);
+        hipLaunchKernelGGL((k_sh_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, ws.wpart,
+                           (M + rpc - 1) / rpc, ws.sqw, ws.Wbar, Dt);
+        if (pl.M <= pl.d) {
+            // dual: alpha_x[p] = s F[p] Dt with F = R (lam I + s^2 Dt Dt^T)^{-1}
+            gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiStore<T>{K, (int64_t)M, s2, 0.0, lam}, st, 1);
+            cholesky<T>(K, M, M, ws.info, st);
+            cholesky_solve_rows<T>(K, M, M, R, M, Pi, st);
+            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
+        } else {
+            // primal: alpha_x[p] = b_p (lam I + s^2 Dt^T Dt)^{-1}, b_p = s R[p] Dt (the pad rows/columns
+            // of the ld x ld matrix are lam I and decouple)
+            T* DtT = (T*)ws.DtT;
+            hipLaunchKernelGGL((k_transpose<T>), dim3(cblocks * 8, (unsigned)((M + 31) / 32)), dim3(256), 0, st, Dt,
+                               (int64_t)ld, M, ld, DtT, (int64_t)M);
+            gemm<T, true>(ld, ld, M, DtT, M, DtT, M, EpiStore<T>{K, (int64_t)ld, s2, 0.0, lam, d, 1.0}, st, 1);
+            cholesky<T>(K, ld, ld, ws.info, st);
+            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
+            cholesky_solve_rows<T>(K, ld, ld, ax, ld, Pi, st);
+        }
+        hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, ws.Wbar, s, ws.scal, NS);
+        if (k > 0) {
+            // reverse the shared cloud to t_k (its Newton output goes to scratch) and |W_k|^2
+            shared_reverse<T>(pb, pl1, k, W, ws.Wbar, ws.scal, ws.ysc, ws.rn2, status, st);
+            gemm<T, true>(Pi, M, ld, ax, ld, W, ld, EpiNewton{Yk, ws.scal, NS, M, pb->newton_iters, fs, s, dt, status},
+                          st);
+            std::swap(Ycur, Yk);
+        } else {
+            hipLaunchKernelGGL((k_sh_outputs<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, d, ws.scal, NS, fs, dt,
+                               pb->newton_iters, u, grad, status);
+        }
+        if ((err = last_error())) return err;
+    }
+    hipLaunchKernelGGL(k_info_to_status, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, ws.info, status, P);
+    return last_error();
+}
+
+}  // namespace
+
+namespace fbsde {
+namespace host {
+
+size_t shared_workspace_bytes(const fbsde_problem* pb, int64_t P) {
+    Plan pl;
+    if (make_plan(pb, P, pl)) return 0;
+    SWS sws;
+    return carve_shared(pl, P, nullptr, sws);
+}
+
+int solve_shared(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
+                 void* wsp, size_t ws_bytes, hipStream_t st) {
+    Plan pl, pl1;
+    int rc;
+    if ((rc = make_plan(pb, P, pl)) || (rc = make_plan(pb, 1, pl1))) return rc;
+    SWS sws;
+    if (carve_shared(pl, P, nullptr, sws) > ws_bytes) return FBSDE_ENOSPC;
+    carve_shared(pl, P, (char*)wsp, sws);
+    if (P == 0) return FBSDE_OK;
+    if (pb->prec == FBSDE_F64) return solve_shared_impl<double>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
+    return solve_shared_impl<float>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
+}
+
+}  // namespace host
+}  // namespace fbsde
+
+extern "C" {
+
+int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+               int64_t ldb, void* C, int64_t ldc, double alpha, double beta, fbsde_stream stream) {
+    if ((prec != FBSDE_F64 && prec != FBSDE_F32C) || m < 0 || n < 0 || k < 0 || !A || !B || !C) return FBSDE_EINVAL;
+    if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX || lda < k * (nt ? 1 : 0) || ldc < n) return FBSDE_EINVAL;
+    if (nt ? ldb < k : ldb < n) return FBSDE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == FBSDE_F64) {
+        if (nt) gemm<double, true>((int)m, (int)n, (int)k, (const double*)A, lda, (const double*)B, ldb,
+                                   EpiStore<double>{(double*)C, ldc, alpha, beta, 0.0}, st);
+        else gemm<double, false>((int)m, (int)n, (int)k, (const double*)A, lda, (const double*)B, ldb,
+                                 EpiStore<double>{(double*)C, ldc, alpha, beta, 0.0}, st);
+    } else {
+        if (nt) gemm<float, true>((int)m, (int)n, (int)k, (const float*)A, lda, (const float*)B, ldb,
+                                  EpiStore<float>{(float*)C, ldc, alpha, beta, 0.0}, st);
+        else gemm<float, false>((int)m, (int)n, (int)k, (const float*)A, lda, (const float*)B, ldb,
+                                EpiStore<float>{(float*)C, ldc, alpha, beta, 0.0}, st);
+    }
+    return last_error();
+}
+
+size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P) {
+    (void)prec; (void)n; (void)P;
+    return 256;   // the status word of the factorisation
+}
+
+int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr, void* ws,
+                         size_t ws_bytes, int32_t* info, fbsde_stream stream) {
+    if ((prec != FBSDE_F64 && prec != FBSDE_F32C) || n < 1 || n > INT32_MAX || P < 0 || P > INT32_MAX || !K || !ws ||
+        !info || ldk < n || (P > 0 && (!R || ldr < n)))
+        return FBSDE_EINVAL;
+    if (fbsde_cholesky_workspace(prec, n, P) > ws_bytes) return FBSDE_ENOSPC;
+    hipStream_t st = (hipStream_t)stream;
+    int* dinfo = (int*)ws;
+    set_int(dinfo, 0, st);
+    if (prec == FBSDE_F64) {
+        cholesky<double>((double*)K, ldk, (int)n, dinfo, st);
+        if (P > 0) cholesky_solve_rows<double>((const double*)K, ldk, (int)n, (double*)R, ldr, (int)P, st);
+    } else {
+        cholesky<float>((float*)K, ldk, (int)n, dinfo, st);
+        if (P > 0) cholesky_solve_rows<float>((const float*)K, ldk, (int)n, (float*)R, ldr, (int)P, st);
+    }
+    if (hipMemcpyAsync(info, dinfo, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return FBSDE_EHIP;
+    return last_error();
+}
+
+}  // extern "C"

@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "solved points/sec (u,∇u) + fwd+adjoint points/sec at d=1000, rel err vs FP64"
-KERNEL_SRC = os.path.join(ROOT, "paper_2510_02635_amd", "csrc", "fbsde_kernels.hpp")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2510_02635_amd", "csrc", f)
+               for f in ("fbsde_kernels.hpp", "fbsde_rowteam.hpp", "fbsde_device.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_matvec_d1000_P1024_M4096_traffic.json")
 
 
@@ -44,8 +45,12 @@ def workload(F, prec):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources of the fused CG product; the stored counter traffic is used only if it matches."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def timed_solves(F, torch, pb, x0, ws, warmup, steps):

@@ -1,0 +1,55 @@
+"""Run one solve of a named workload (and optionally a plain device copy of known size), for profilers.
+
+The copy gives the calibration factor of the HBM byte counters: its kernel moves exactly `--copy-mib`
+MiB in and out, so counter / expected scales the counters of the solve's kernels.
+
+  python -m paper_2510_02635_amd.profile_workload --workload allen_cahn_d1000_P1024_M4096_N20 --prec fp32c \
+      --copy-mib 1024
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (problem kwargs, x0 kind, points)
+    "allen_cahn_d1000_P1024_M4096_N20": (dict(d=1000, M=4096, N=20, T=0.3, f_kind=1, fp=(1.0, 1.0, 0, 0), g_kind=1,
+                                              gp=(0.4, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3, seed=0, instance=1),
+                                         "normal:0.5", 1024),
+    "shared_allen_cahn_d10000_P4096_M2048_N20": (dict(d=10000, M=2048, N=20, T=0.3, f_kind=1, fp=(1.0, 1.0, 0, 0),
+                                                      g_kind=1, gp=(0.4, 0, 0, 0), shared_dw=1, seed=0, instance=4),
+                                                 "normal_over_sqrt_d", 4096),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="allen_cahn_d1000_P1024_M4096_N20", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--copy-mib", type=int, default=0, help="also run a device copy of this many MiB")
+    args = ap.parse_args()
+    import torch
+
+    import paper_2510_02635_amd as F
+    from paper_2510_02635_amd import workloads
+
+    kw, xkind, P = WORKLOADS[args.workload]
+    pb = F.Problem(prec=F.F32C if args.prec == "fp32c" else F.F64, **kw)
+    x0 = torch.tensor(workloads.points(xkind, P, kw["d"], 1), dtype=torch.float64, device="cuda")
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    u, g, st = F.solve(pb, x0)
+    torch.cuda.synchronize()
+    print(f"{args.workload} {args.prec}: u[0]={u[0].item():.12g} nonzero status={int((st != 0).sum())}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

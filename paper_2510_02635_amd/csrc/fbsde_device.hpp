@@ -94,16 +94,41 @@ __device__ __forceinline__ void sincos_turn<float>(uint32_t w, float& sn, float&
     cs = (q == 0) ? c_ : (q == 1) ? -s_ : (q == 2) ? -c_ : s_;
 }
 
+// ln u for u = (w + 1/2) 2^-32 in FP64.  x = w + 1/2 is exact; frexp gives x = m 2^e exactly with
+// m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(z) = 2 (z + z^3/3 + z^5/5 + ...) with z = (m - 1)/(m + 1),
+// |z| <= 0.1716, so twelve odd terms reach the double rounding level (m - 1 is exact, so the result
+// keeps full relative accuracy as u -> 1); (e - 32) ln 2 uses ln 2 split into a 32-bit head and a tail.
+__device__ __forceinline__ double log_unit(uint32_t w) {
+    const double x = (double)w + 0.5;
+    int e;
+    double m = frexp(x, &e);                 // x = m 2^e, m in [1/2, 1)
+    if (m < 0.7071067811865476) { m += m; --e; }
+    const double z = (m - 1.0) / (m + 1.0);
+    const double z2 = z * z;
+    double sr = 1.0 / 23.0;
+    sr = sr * z2 + 1.0 / 21.0;
+    sr = sr * z2 + 1.0 / 19.0;
+    sr = sr * z2 + 1.0 / 17.0;
+    sr = sr * z2 + 1.0 / 15.0;
+    sr = sr * z2 + 1.0 / 13.0;
+    sr = sr * z2 + 1.0 / 11.0;
+    sr = sr * z2 + 1.0 / 9.0;
+    sr = sr * z2 + 1.0 / 7.0;
+    sr = sr * z2 + 1.0 / 5.0;
+    sr = sr * z2 + 1.0 / 3.0;
+    const double lnm = 2.0 * z + 2.0 * z * z2 * sr;
+    const double k = (double)(e - 32);
+    const double ln2_hi = 0.6931471803691238, ln2_lo = 1.9082149292705877e-10;
+    return k * ln2_hi + (k * ln2_lo + lnm);
+}
+
 // Four normals from one Philox call: Box-Muller on the word pairs (x, y) and (z, w) with
-// u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even) (FP64 log for both element types),
-// angle 2 pi u_odd.
+// u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even) (FP64 logarithm; the square root in the
+// element type), angle 2 pi u_odd.
 template <typename R>
 __device__ __forceinline__ void box_muller4(const Words4& w, R z[4]) {
-    const double two_m32 = 2.3283064365386963e-10;   // 2^-32
-    const double u0 = ((double)w.x + 0.5) * two_m32;
-    const double u2 = ((double)w.z + 0.5) * two_m32;
-    const R r0 = (R)sqrt(-2.0 * log(u0));
-    const R r2 = (R)sqrt(-2.0 * log(u2));
+    const R r0 = (R)sqrt((R)(-2.0 * log_unit(w.x)));
+    const R r2 = (R)sqrt((R)(-2.0 * log_unit(w.z)));
     R s1, c1, s3, c3;
     sincos_turn<R>(w.y, s1, c1);
     sincos_turn<R>(w.w, s3, c3);

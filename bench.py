@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle points timed for the CPU baseline")
+    ap.add_argument("--no-shared", action="store_true", help="skip the shared-increment (MFMA) leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance leg")
+    ap.add_argument("--batched-points", type=int, default=8, help="points per instance in the batched leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the points of this workload are independent, so a multi-GPU run "
@@ -188,6 +191,76 @@ def main():
                      for p in range(n))
             errs[name] = {"u": float(f"{eu:.3e}"), "grad": float(f"{eg:.3e}")}
 
+    # ---------------- shared increments: d = 10^4, 4096 points, M = 2048, N = 20 on the matrix cores
+    shared = None
+    if not args.no_shared:
+        Ps, ds, Ms = 4096, 10000, 2048
+        pbs = F.Problem(d=ds, M=Ms, N=20, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0.0, 0.0), g_kind=F.G_AC,
+                        gp=(0.4, 0.0, 0.0, 0.0), shared_dw=1, prec=F.F32C, seed=0, instance=4)
+        xs_np = workloads.points("normal_over_sqrt_d", Ps, ds, seed=7)
+        xs = torch.tensor(xs_np, dtype=torch.float64, device=dev)
+        wss = F.workspace(pbs, Ps, device=dev)
+        sec_s, us_, gs_, sts_, _ = timed_solves(F, torch, pbs, xs, wss, 1, max(1, args.steps))
+        log(f"[bench] shared fp32c d=1e4 P=4096 M=2048: {sec_s * 1e3:.1f} ms/solve")
+        del wss
+        torch.cuda.empty_cache()
+        # the dominant GEMM of that leg, timed live on torch's stream (the library launches there)
+        ldp = F.state_ld(pbs)
+        A = torch.randn((Ps, ldp), dtype=torch.float32, device=dev)
+        B = torch.randn((Ms, ldp), dtype=torch.float32, device=dev)
+        C = torch.empty((Ps, Ms), dtype=torch.float32, device=dev)
+        F.gemm(A, B, nt=True, C=C)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            F.gemm(A, B, nt=True, C=C)
+        e1.record()
+        torch.cuda.synchronize()
+        gemm_ms = e0.elapsed_time(e1) / 5
+        tflops = 2.0 * Ps * Ms * ldp / (gemm_ms * 1e-3) / 1e12
+        del A, B, C
+        torch.cuda.empty_cache()
+        shared = {"value": round(Ps / sec_s, 2), "unit": "points/s", "ms_per_step": round(sec_s * 1e3, 3),
+                  "dtype": "fp32c (FP32 MFMA, FP64 Newton)",
+                  "config": {"workload": "shared_allen_cahn_d10000_P4096_M2048_N20", "shared_increments": True},
+                  "roofline": {"bound": "mfma", "kernel": "k_gemm<float, NT> [P x ld] x [M x ld]^T",
+                               "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
+                               "frac": round(tflops / 157.3, 4), "avg_launch_ms": round(gemm_ms, 4),
+                               "flops_per_launch": 2 * Ps * Ms * ldp},
+                  "status_nonzero_points": int((sts_ != 0).sum().item())}
+        del xs
+        torch.cuda.empty_cache()
+
+    # ---------------- batched: 64 uneven HJB instances in one persistent launch per geometry class
+    batched = None
+    if not args.no_batched:
+        insts = workloads.batched_instances(64)
+        Pb = args.batched_points
+        probs, xb = [], []
+        for it in insts:
+            probs.append(F.Problem(d=it["d"], M=it["M"], N=20, T=1.0, f_kind=F.F_HJB, fp=(it["lam"], 0, 0, 0),
+                                   g_kind=F.G_HJB_LOG, gp=(1.0, 0, 0, 0), prec=F.F32C, seed=0, instance=it["instance"]))
+            xb.append(torch.tensor(workloads.points("uniform", Pb, it["d"], seed=100 + it["instance"]),
+                                   dtype=torch.float64, device=dev))
+        ub, gb, stb = F.solve_batched(probs, xb, max_slots=512)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ub, gb, stb = F.solve_batched(probs, xb, max_slots=512)
+        torch.cuda.synchronize()
+        sec_b = time.perf_counter() - t0
+        n_pts = Pb * len(insts)
+        elems = sum(Pb * it["M"] * it["d"] for it in insts)
+        log(f"[bench] batched 64 instances x {Pb} points: {sec_b * 1e3:.1f} ms")
+        batched = {"value": round(n_pts / sec_b, 2), "unit": "points/s", "ms_per_step": round(sec_b * 1e3, 3),
+                   "dtype": "fp32c",
+                   "config": {"workload": "batched_hjb_64_instances", "points_per_instance": Pb,
+                              "d": "uniform over {100, 500, 1000, 5000, 10000}", "M": "multiples of 64 in [512, 8192]",
+                              "T": 1.0, "N": 20, "f": "-lam |z|^2, lam ~ U[0.5, 2]", "g": "ln((1+|x|^2)/2)",
+                              "x0": "U[-1,1]^d", "state_elements": elems},
+                   "status_nonzero_points": int(sum(int((s != 0).sum().item()) for s in stb))}
+        del xb, ub, gb, stb
+        torch.cuda.empty_cache()
+
     value = P / sec32
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
@@ -206,6 +279,8 @@ def main():
         "speedup_fp32c_over_fp64": None if sec64 is None else round(sec64 / sec32, 3),
         "rel_err_vs_fp64_oracle": errs or None,
         "cg_iters_per_level_fp32c": it32,
+        "shared_increments_mfma": shared,
+        "batched": batched,
         "reverse_sweep_avg_ms_fp32c": round(rev32_ms, 4),
         "status_nonzero_points": int(np.count_nonzero(st32)),
     }

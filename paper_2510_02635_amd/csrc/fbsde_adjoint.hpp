@@ -124,7 +124,7 @@ k_adj_advance(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nch
 
 // alpha_xbar = s sum_m cbar_m W^m_k + s Zbar - alphabar s Wbar, then CG on A bbar = alpha_xbar from 0.
 __global__ void __launch_bounds__(256)
-k_adj_rhs_finish(const double* __restrict__ part, int nchunk, int ld, double s, double lam,
+k_adj_rhs_finish(const double* __restrict__ part, int nchunk, int vchunks, int ld, double s, double lam,
                  const double* __restrict__ Wbar, const double* __restrict__ ax, const double* __restrict__ adj,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ pv, double* __restrict__ scal,
                  int ns, int* __restrict__ iscal, int* active) {
@@ -136,7 +136,7 @@ k_adj_rhs_finish(const double* __restrict__ part, int nchunk, int ld, double s, 
     double rr = 0.0, wv = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         double cs = 0.0;
-        for (int c = 0; c < nchunk; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];
+        for (int c = 0; c < vchunks; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];
         const double b = s * cs + s * s * zc * ax[o + i] - abar * s * Wbar[o + i];
         x[o + i] = 0.0;
         r[o + i] = b;
@@ -307,7 +307,7 @@ k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, 
 
 // x0bar = (sum_j G_j 2h'_j) xc + s sum_j G_j 2h'_j W_j   (affine: (sum_j G_j) gvec); per-point gp sums.
 __global__ void __launch_bounds__(256)
-k_adj_x0bar(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int d, int ld,
+k_adj_x0bar(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int vchunks, int d, int ld,
             const double* __restrict__ x0, const double* __restrict__ mu, const double* __restrict__ gvec,
             double s, double T, int g_kind, double* __restrict__ adj, double* __restrict__ x0_bar) {
     const int p = blockIdx.x;
@@ -321,7 +321,7 @@ k_adj_x0bar(const double* __restrict__ part, const double* __restrict__ psc, int
         if (g_kind == G_AFFINE) v = SG * gvec[i];
         else {
             double cs = 0.0;
-            for (int c = 0; c < nchunk; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];
+            for (int c = 0; c < vchunks; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];
             const double xc = x0[(int64_t)p * d + i] + (mu ? mu[i] * T : 0.0);
             v = S1 * xc + s * cs;
         }

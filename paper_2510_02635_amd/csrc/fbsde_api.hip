@@ -94,6 +94,15 @@ void launch_rownorm(const Plan& pl, int64_t P, const S* W, int64_t ldw, double* 
 
 // Run CG on the per-point systems prepared in ws (x, r, pv, Wbar, scal, iscal, active).
 // Returns the number of matvec launches.
+// Folds the per-chunk partial vectors of each point into chunk 0 when a point is split over more
+// than four chunks; returns how many chunk vectors the per-point finish kernel then sums.
+int fold_parts(const Plan& pl, int64_t P, double* a, double* b, double* c, hipStream_t st) {
+    if (pl.nchunk <= 4) return pl.nchunk;
+    hipLaunchKernelGGL(k_fold_chunks, dim3((unsigned)((pl.ld + 63) / 64), (unsigned)P), dim3(256), 0, st, a, b, c,
+                       pl.nchunk, pl.ld);
+    return 1;
+}
+
 template <typename S>
 int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
            const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
@@ -108,7 +117,8 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
                                W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, ws.pv, ws.scal, NS,
                                ws.iscal, ws.part1, ws.psc);
         });
-        hipLaunchKernelGGL(k_cg_update, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, pl.ld,
+        const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+        hipLaunchKernelGGL(k_cg_update, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, pl.ld,
                            pb->s, Wbar, ws.x, ws.r, ws.pv, ws.qv, ws.scal, NS, ws.iscal,
                            pb->cg_rtol * pb->cg_rtol, pb->cg_maxit, ws.active, status);
         if (fixed <= 0 && (it + 1) % poll == 0) {
@@ -144,8 +154,9 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
                            ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.x, ws.scal, NS, warm,
                            ws.part1, ws.part2, ws.part3, ws.psc);
     });
+    const int vc = fold_parts(pl, P, ws.part1, ws.part2, warm ? ws.part3 : nullptr, st);
     hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.part3, ws.psc,
-                       pl.nchunk, pl.ld, pb->s, lam, warm, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
+                       pl.nchunk, vc, pl.ld, pb->s, lam, warm, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
                        ws.active);
     const int iters = run_cg<S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
     if (err) return iters;
@@ -254,7 +265,8 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
         const double* w_k = ws.tw + (size_t)k * PM;
         const double* Wbar_k = ws.tWbar + (size_t)k * PL;
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.active, (int)P);
-        hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, pl.ld, pb->s,
+        const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+        hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, vc, pl.ld, pb->s,
                            lam, Wbar_k, ws.tax + (size_t)k * PL, ws.adj, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
                            ws.active);
         run_cg<S>(pb, pl, P, W, ldw, w_k, Wbar_k, ws, status, st, err);
@@ -277,7 +289,8 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
                            ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, (int)pl.d, pl.ld, x0, pb->mu, pb->gvec, pb->s,
                            pb->T, pb->g_kind, pb->gp[0], ws.G, ws.part1, ws.psc);
     });
-    hipLaunchKernelGGL(k_adj_x0bar, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, (int)pl.d,
+    const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+    hipLaunchKernelGGL(k_adj_x0bar, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, (int)pl.d,
                        pl.ld, x0, pb->mu, pb->gvec, pb->s, pb->T, pb->g_kind, ws.adj, x0_bar);
     hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(64), 0, st, ws.adj, P, gp_bar, fp_bar);
     // the tape is consumed: the state no longer holds W_1 of the primal pass

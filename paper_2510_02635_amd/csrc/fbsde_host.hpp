@@ -62,7 +62,9 @@ inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     pl.TPW = pl.BS / (64 * pl.TEAM);
     const int64_t target_blocks = 4096;
     int64_t nchunk = (target_blocks + std::max<int64_t>(P, 1) - 1) / std::max<int64_t>(P, 1);
-    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, pb->M / (2 * pl.TPW)));
+    // at least 64 rows per chunk: each chunk writes one [ld] FP64 partial per pass, so the partials stay
+    // within a few per cent of the state bytes the pass reads
+    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, std::min<int64_t>(pb->M / (2 * pl.TPW), pb->M / 64)));
     pl.rows_per_chunk = (int)((pb->M + nchunk - 1) / nchunk);
     pl.nchunk = (int)((pb->M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
     return FBSDE_OK;

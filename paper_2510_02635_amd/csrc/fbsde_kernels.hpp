@@ -233,12 +233,41 @@ k_moments(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
 // Finish the moments and start CG on (sum_j w_j D'_j D'_j^T + lam I) a_x = b.
 // Cold start x0 = 0; warm start x0 = rho * (previous level's slope, in x) with
 // A x0 = s^2 (sum_j w_j t_j W_j - (sum_j w_j t_j) Wbar) + lam x0, t_j = W_j . x0.
+// Per-point sum of the per-chunk partial vectors into chunk 0 of each buffer, spread over the
+// chip: block (x, p) owns 64 elements of point p; its four waves sum four contiguous chunk ranges
+// and wave 0 adds the four range sums in order.  Deterministic for a fixed chunk count.  Used when
+// a point is split over many chunks, where a one-block-per-point finish would read them serially.
+__global__ void __launch_bounds__(256)
+k_fold_chunks(double* __restrict__ a, double* __restrict__ b, double* __restrict__ c3, int nchunk, int ld) {
+    __shared__ double red[3][4][64];
+    const int p = blockIdx.y;
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int per = (nchunk + 3) / 4;
+    const int c0 = min(nchunk, g * per), c1 = min(nchunk, c0 + per);
+    double* bufs[3] = {a, b, c3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        if (bufs[k] && i < ld)
+            for (int c = c0; c < c1; ++c) acc += bufs[k][((int64_t)p * nchunk + c) * ld + i];
+        red[k][g][lane] = acc;
+    }
+    __syncthreads();
+    if (g == 0 && i < ld) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (bufs[k])
+                bufs[k][(int64_t)p * nchunk * ld + i] = ((red[k][0][lane] + red[k][1][lane]) + red[k][2][lane]) + red[k][3][lane];
+    }
+}
+
 // scal layout per point: 0 rr, 1 |b|^2, 2 wv = Wbar.p, 3 lam, 4 Ybar, 5 alpha, 6 zz, 7 rho.
 // iscal: 0 iterations, 1 done.
 __global__ void __launch_bounds__(256)
 k_moments_finish(const double* __restrict__ part1, const double* __restrict__ part2,
-                 const double* __restrict__ part3, const double* __restrict__ psc, int nchunk, int ld, double s,
-                 double lam, int warm, double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
+                 const double* __restrict__ part3, const double* __restrict__ psc, int nchunk, int vchunks, int ld,
+                 double s, double lam, int warm, double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
                  double* __restrict__ pv, double* __restrict__ scal, int ns, int* __restrict__ iscal, int* active) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
@@ -251,7 +280,7 @@ k_moments_finish(const double* __restrict__ part1, const double* __restrict__ pa
     double rr = 0.0, bb2 = 0.0, wv = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         double wb = 0.0, bb = 0.0, ab = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
+        for (int c = 0; c < vchunks; ++c) {
             wb += part1[((int64_t)p * nchunk + c) * ld + i];
             bb += part2[((int64_t)p * nchunk + c) * ld + i];
             if (warm) ab += part3[((int64_t)p * nchunk + c) * ld + i];
@@ -313,22 +342,24 @@ k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nc
     const double wvp = scal[(int64_t)p * ns + 2];
     CSum<R> acc[Q][4];
     double tau = 0.0;
+    // rows are double-buffered: the loads of the team's next row are issued before the reduction of
+    // the current one, so a wave keeps two rows in flight across the team barrier (not in 1024-lane
+    // blocks, whose 128-register cap the second buffer would overflow)
+    constexpr bool PF = G::BS < 1024;
+    const S* base = W + (int64_t)p * M * ldw;
+    S x[Q][4];
+    if (PF && r0 + team < r1) load_row<S, Q, G::TL>(base + (int64_t)(r0 + team) * ldw, ld, L, x);
     for (int jb = r0; jb < r1; jb += G::TPW) {
         const int j = jb + team;
         const bool valid = j < r1;
-        S x[Q][4];
+        S xn[Q][4];
+        if (PF) {
+            if (j + G::TPW < r1) load_row<S, Q, G::TL>(base + (int64_t)(j + G::TPW) * ldw, ld, L, xn);
+        } else if (valid) {
+            load_row<S, Q, G::TL>(base + (int64_t)j * ldw, ld, L, x);
+        }
         CSum<R> dl;
         if (valid) {
-            const S* row = W + ((int64_t)p * M + j) * ldw;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int e0 = 4 * (L + q * G::TL);
-                if (e0 < ld) load4(row + e0, x[q]);
-                else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) x[q][e] = (S)0;
-                }
-            }
 #pragma unroll
             for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -345,6 +376,12 @@ k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nc
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[q][e].add(cr * x[q][e]);
         }
+        if (PF) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x[q][e] = xn[q][e];
+        }
     }
     block_columns_out<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
     const double contrib = (L == 0) ? tau : 0.0;
@@ -355,7 +392,8 @@ k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nc
 // CG step on the per-point vectors (one block per point): q = s (sum_c part_c - tau Wbar) + lam p,
 // then the usual conjugate-gradient updates; convergence |r| <= rtol |b| or the iteration cap.
 __global__ void __launch_bounds__(256)
-k_cg_update(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int ld, double s,
+k_cg_update(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int vchunks, int ld,
+            double s,
             const double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
             double* __restrict__ pv, double* __restrict__ qv, double* __restrict__ scal, int ns,
             int* __restrict__ iscal, double rtol2, int maxit, int* active, uint32_t* __restrict__ status) {
@@ -370,7 +408,7 @@ k_cg_update(const double* __restrict__ part, const double* __restrict__ psc, int
     double pq = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         double a = 0.0;
-        for (int c = 0; c < nchunk; ++c) a += part[((int64_t)p * nchunk + c) * ld + i];
+        for (int c = 0; c < vchunks; ++c) a += part[((int64_t)p * nchunk + c) * ld + i];
         const double q = s * (a - tau * Wbar[o + i]) + lam * pv[o + i];
         qv[o + i] = q;
         pq += pv[o + i] * q;

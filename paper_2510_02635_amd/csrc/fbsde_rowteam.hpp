@@ -40,6 +40,20 @@ __device__ __forceinline__ void load4(const float* __restrict__ p, float v[4]) {
     const float4 a = *reinterpret_cast<const float4*>(p);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
+// One row of the state into a lane's registers: groups of four at 4 (L + q TL), zero beyond ld.
+template <typename S, int Q, int TL>
+__device__ __forceinline__ void load_row(const S* __restrict__ row, int ld, int L, S x[Q][4]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int e0 = 4 * (L + q * TL);
+        if (e0 < ld) load4(row + e0, x[q]);
+        else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[q][e] = (S)0;
+        }
+    }
+}
+
 __device__ __forceinline__ void store4(double* __restrict__ p, const double v[4]) {
     *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);

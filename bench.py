@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--points", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="oracle points timed for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="oracle points timed for the CPU baseline")
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-increment (MFMA) leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance leg")
     ap.add_argument("--batched-points", type=int, default=8, help="points per instance in the batched leg")
@@ -114,15 +114,15 @@ def main():
     ubar = torch.ones(P, dtype=torch.float64, device=dev)
 
     def fwd_adj():
-        F.solve(pb32, x0, tape=True, ws=wsa)
-        return F.solve_backward(pb32, x0, ubar, wsa)
+        it_f = F.solve(pb32, x0, tape=True, ws=wsa, return_iters=True)[3]
+        return F.solve_backward(pb32, x0, ubar, wsa, return_iters=True) + (it_f,)
 
     for _ in range(args.warmup):
         fwd_adj()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        x0bar, gpbar, fpbar, sta = fwd_adj()
+        x0bar, gpbar, fpbar, sta, it_adj, it_fwd_tape = fwd_adj()
     torch.cuda.synchronize()
     sec_fa = (time.perf_counter() - t0) / args.steps
     log(f"[bench] fp32c fwd+adj: {sec_fa * 1e3:.1f} ms per solve + backward")
@@ -162,6 +162,29 @@ def main():
     if mv64_ms:
         roofline["fp64_kernel"] = {"achieved": round(P * M * d * 8 / (mv64_ms * 1e-3) / 1e9, 1),
                                    "avg_launch_ms": round(mv64_ms, 4), "algorithmic_bytes_per_launch": P * M * d * 8}
+
+    # ---------------- whole-job state traffic: passes over the [P][M][ld] state per solve
+    # forward: 1 write (terminal sweep), per level 1 moments read + K_k CG reads + reversal read and
+    # write (read only at k = 0); adjoint: per level advance read and write + K'_k CG reads + 1 row-dot
+    # read, then 1 terminal read.  [P][M] FP64 side arrays (weights, Y) are below 0.3 % and not counted.
+    def fwd_passes(iters):
+        return 1 + sum(1 + k + 2 for k in iters) - 1
+
+    def adj_passes(iters):
+        return sum(3 + k for k in iters) + 1
+
+    state32 = P * M * 1024 * 4
+    state64 = P * M * 1008 * 8
+
+    def whole(passes, state, sec):
+        gbs = passes * state / sec / 1e9
+        return {"state_passes": passes, "bytes": passes * state, "achieved_GBs": round(gbs, 1),
+                "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+    whole_job = {"fp32c_forward": whole(fwd_passes(it32), state32, sec32),
+                 "fp32c_fwd_adj": whole(fwd_passes(it_fwd_tape) + adj_passes(it_adj), state32, sec_fa)}
+    if sec64:
+        whole_job["fp64_forward"] = whole(fwd_passes(it64), state64, sec64)
 
     # ---------------- oracle: CPU baseline and errors on sample points
     cpu = None
@@ -231,7 +254,8 @@ def main():
         del xs
         torch.cuda.empty_cache()
 
-    # ---------------- batched: 64 uneven HJB instances in one persistent launch per geometry class
+    # ---------------- batched: 64 uneven HJB instances (the 256-point workload cut to --batched-points per
+    # instance so the leg stays within a minute), tiled schedule
     batched = None
     if not args.no_batched:
         insts = workloads.batched_instances(64)
@@ -242,22 +266,33 @@ def main():
                                    g_kind=F.G_HJB_LOG, gp=(1.0, 0, 0, 0), prec=F.F32C, seed=0, instance=it["instance"]))
             xb.append(torch.tensor(workloads.points("uniform", Pb, it["d"], seed=100 + it["instance"]),
                                    dtype=torch.float64, device=dev))
-        ub, gb, stb = F.solve_batched(probs, xb, max_slots=512)
+        # one small warm-up batch (thread pool, streams, first launches), then the timed batch
+        F.solve_batched(probs[:2], [x[:1] for x in xb[:2]])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ub, gb, stb = F.solve_batched(probs, xb, max_slots=512)
+        ub, gb, stb = F.solve_batched(probs, xb)
         torch.cuda.synchronize()
         sec_b = time.perf_counter() - t0
+        log(f"[bench] batched 64 instances x {Pb} points (tiled): {sec_b * 1e3:.1f} ms")
+        ubs = [torch.ones(x.shape[0], dtype=torch.float64, device=dev) for x in xb]
+        t0 = time.perf_counter()
+        rb = F.solve_batched_backward(probs, xb, ubs)
+        torch.cuda.synchronize()
+        sec_ba = time.perf_counter() - t0
+        log(f"[bench] batched 64 instances x {Pb} points fwd+adj (tiled): {sec_ba * 1e3:.1f} ms")
         n_pts = Pb * len(insts)
         elems = sum(Pb * it["M"] * it["d"] for it in insts)
-        log(f"[bench] batched 64 instances x {Pb} points: {sec_b * 1e3:.1f} ms")
         batched = {"value": round(n_pts / sec_b, 2), "unit": "points/s", "ms_per_step": round(sec_b * 1e3, 3),
-                   "dtype": "fp32c",
+                   "dtype": "fp32c", "schedule": "tiled: (instance, point-tile) items over 4 streams",
+                   "fwd_adj": {"value": round(n_pts / sec_ba, 2), "unit": "points/s",
+                               "ms_per_step": round(sec_ba * 1e3, 3),
+                               "status_nonzero_points": int(sum(int((s_ != 0).sum().item()) for s_ in rb[4]))},
                    "config": {"workload": "batched_hjb_64_instances", "points_per_instance": Pb,
                               "d": "uniform over {100, 500, 1000, 5000, 10000}", "M": "multiples of 64 in [512, 8192]",
                               "T": 1.0, "N": 20, "f": "-lam |z|^2, lam ~ U[0.5, 2]", "g": "ln((1+|x|^2)/2)",
                               "x0": "U[-1,1]^d", "state_elements": elems},
-                   "status_nonzero_points": int(sum(int((s != 0).sum().item()) for s in stb))}
+                   "status_nonzero_points": int(sum(int((s_ != 0).sum().item()) for s_ in stb))}
+        del rb, ubs
         del xb, ub, gb, stb
         torch.cuda.empty_cache()
 
@@ -279,6 +314,8 @@ def main():
         "speedup_fp32c_over_fp64": None if sec64 is None else round(sec64 / sec32, 3),
         "rel_err_vs_fp64_oracle": errs or None,
         "cg_iters_per_level_fp32c": it32,
+        "adjoint_cg_iters_per_level_fp32c": it_adj,
+        "whole_job_state_traffic": whole_job,
         "shared_increments_mfma": shared,
         "batched": batched,
         "reverse_sweep_avg_ms_fp32c": round(rev32_ms, 4),

@@ -85,7 +85,8 @@ typedef struct fbsde_problem {
     double ridge_rel;        /* ridge factor >= 0; 0 needs M > d + 1                          */
     int32_t newton_iters;    /* Newton iterations per particle and level, >= 1                */
     int32_t cg_maxit;        /* CG iteration cap per level, >= 1                              */
-    double cg_rtol;          /* CG stop: |r| <= cg_rtol |b|                                   */
+    double cg_rtol;          /* CG stop: |r| <= cg_rtol |b|; FP32C with M <= d + 1 uses at     */
+                             /* least 1e-7 (FP32 rounding in the ridge-only null space)        */
     int32_t cg_fixed_iters;  /* > 0: run exactly this many CG launches per level, no polling  */
     int32_t shared_dw;       /* 1: the same increments for every evaluation point             */
     uint64_t seed;           /* Philox key                                                     */
@@ -128,7 +129,8 @@ int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double
  *   x0     device [P][d];  u device [P];  grad device [P][d] or NULL;  status device [P]
  *   ws     device workspace, fbsde_workspace_size(pb, P, flags) bytes; with FBSDE_WS_TAPE it
  *          keeps the tape that fbsde_solve_backward reads (then do not reuse ws in between)
- *   cg_iters_out  host [N] or NULL: CG iterations run at each level k
+ *   cg_iters_out  host [N] or NULL: at each level k the largest CG iteration count over the points
+ *                 (read back from the device after the level: one extra stream wait per level)
  * Unless cg_fixed_iters > 0, the host waits on the stream every few CG iterations to read the
  * number of points still iterating (so the call returns after the work is done). */
 int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
@@ -148,10 +150,14 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
  *   Requires the immediately preceding fbsde_solve on the same pb, P, x0 and ws with
  *   flags = FBSDE_WS_TAPE (FBSDE_ESTATE otherwise).
  *   u_bar  device [P];  x0_bar device [P][d] out;  gp_bar, fp_bar device [4] out (summed
- *   over points);  status device [P] OR-ed. */
+ *   over points);  status device [P] OR-ed;  cg_iters_out host [N] or NULL: the largest adjoint CG
+ *   iteration count over the points at each level k.
+ * With a rank-deficient centred design (M <= d + 1) the adjoint right-hand side reaches the
+ * ridge-only null space, so in FP32C the CG product and the row dots of this pass use FP64
+ * arithmetic on the FP32 state. */
 int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar,
                          double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status,
-                         void* ws, size_t ws_bytes, fbsde_stream stream);
+                         void* ws, size_t ws_bytes, int32_t* cg_iters_out, fbsde_stream stream);
 
 /* Diagnostic: the normals xi^j_k of point p (or the shared stream) for rows j0..j0+rows-1 of
  * level k, exactly as the kernels generate them.  out device [rows][d]; words device
@@ -168,25 +174,55 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
 int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t reps, void* ws,
                       size_t ws_bytes, float* avg_ms, fbsde_stream stream);
 
-/* Many evaluation points of many PDE instances (uneven d, M, f, g, precision) in one persistent
- * launch per geometry class (element type and row-team shape, decided by d): every workgroup owns a
- * workspace slot, pulls (instance, point) items from an atomic queue (largest M first) and runs the
- * whole of Algorithm 1 for that point inside the workgroup -- forward sweep, and per level the
- * weights, moments, CG solve with workgroup reductions, reversal and Newton -- so the batch needs no
- * host round trip and no per-level launch.  Results are the same as fbsde_solve of each instance
- * (same Philox streams; CG stops per point at the same test).
- *   pbs     host [n_inst] descriptors (shared_dw must be 0);  P host [n_inst] point counts
+/* Many evaluation points of many PDE instances (uneven d, M, f, g, N, precision) in one call
+ * (spec extension: batching over points and instances; the per-point chain is Algorithm 1).
+ * Two schedules, chosen by opts->mode:
+ *  FBSDE_BATCH_TILED (default): the work items are (instance, point-tile) pairs, largest first.  Each
+ *    tile runs the whole chain through the multi-block path of fbsde_solve (each point split over
+ *    many workgroups along its particle rows) on one of `streams` HIP streams, each owned by a host
+ *    worker thread with its own workspace arena, so tiles of different instances overlap on the chip.
+ *    A tile holds as many points as fit `tile_bytes` of workspace (at least one, at most 65535), so
+ *    memory is bounded by the tiles in flight, not by the batch.  Tile i of an instance covers its
+ *    points [p0, p0 + np) with point_base + p0: results equal fbsde_solve of the whole instance up to
+ *    the rounding order of the partial sums (same Philox streams, same CG test).
+ *  FBSDE_BATCH_PERSISTENT: one persistent launch per geometry class (element type and row-team
+ *    shape, decided by d); every workgroup owns a slot, pulls (instance, point) items from an atomic
+ *    queue (largest M first) and runs the whole chain of its point alone, with workgroup reductions.
+ *    Forward only.  Bounded by one compute unit's share of HBM per point: for points whose chain is
+ *    long (large d and M) the tiled schedule is much faster.
+ *   pbs     host [n_inst] descriptors (tiled: shared_dw allowed for the forward solve)
+ *   P       host [n_inst] point counts (>= 0)
  *   x0, u, grad, status   host arrays of n_inst device pointers ([P_i][d_i], [P_i], [P_i][d_i] or
  *                         NULL, [P_i]); grad itself may be NULL
- *   max_slots             workgroups (points in flight) per class; each holds one point's state
- *   ws      device workspace of fbsde_batched_workspace_size(pbs, n_inst, P, max_slots) bytes
- * Synchronises the stream once (after uploading the work tables), then runs asynchronously. */
+ *   opts    NULL for the defaults (tiled, 4 streams, 8 GiB tiles, 512 persistent slots)
+ *   ws      device workspace of fbsde_batched_workspace_size(pbs, n_inst, P, opts, adjoint) bytes
+ * The tiled schedule waits for the caller's stream, returns after all tiles have completed, and
+ * needs the calling thread's current device to be the one holding the buffers; the persistent one
+ * synchronises the stream once (after uploading its work tables), then runs asynchronously. */
+enum { FBSDE_BATCH_TILED = 0, FBSDE_BATCH_PERSISTENT = 1 };
+typedef struct fbsde_batch_opts {
+    int32_t mode;         /* FBSDE_BATCH_TILED or FBSDE_BATCH_PERSISTENT                 */
+    int32_t streams;      /* tiled: concurrent streams / worker threads, 1..8 (0: 4)     */
+    int64_t tile_bytes;   /* tiled: workspace cap of one tile in bytes (0: 8 GiB)        */
+    int32_t max_slots;    /* persistent: workgroups (points in flight) per class (0: 512) */
+    int32_t reserved;     /* must be 0                                                   */
+} fbsde_batch_opts;
 int fbsde_batched_workspace_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
-                                 int32_t max_slots, size_t* bytes);
+                                 const fbsde_batch_opts* opts, int32_t adjoint, size_t* bytes);
 int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
                         const double* const* x0, double* const* u, double* const* grad,
-                        uint32_t* const* status, int32_t max_slots, void* ws, size_t ws_bytes,
-                        fbsde_stream stream);
+                        uint32_t* const* status, const fbsde_batch_opts* opts, void* ws,
+                        size_t ws_bytes, fbsde_stream stream);
+/* Batched forward + reverse mode (tiled schedule only): per instance, u [P_i] and the adjoints of
+ * L_i = sum_p u_bar_i[p] u_i(0, x0_p): x0_bar [P_i][d_i], gp_bar [4], fp_bar [4] (device).  Each
+ * tile runs fbsde_solve with the tape and fbsde_solve_backward in its arena; the parameter adjoints
+ * of an instance are the sum of its tiles' sums in point order.  status ORs both passes.  Workspace:
+ * fbsde_batched_workspace_size(..., adjoint = 1). */
+int fbsde_solve_batched_backward(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                                 const double* const* x0, const double* const* u_bar, double* const* u,
+                                 double* const* x0_bar, double* const* gp_bar, double* const* fp_bar,
+                                 uint32_t* const* status, const fbsde_batch_opts* opts, void* ws,
+                                 size_t ws_bytes, fbsde_stream stream);
 
 /* Dense helpers of the shared-increment form, exported for verification and reuse.
  * fbsde_gemm: C = alpha * A op(B) + beta * C on the matrix cores (v_mfma 16x16x4, FP64 or FP32

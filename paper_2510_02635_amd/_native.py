@@ -13,7 +13,16 @@ WS_TAPE = 1
 
 EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
             "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
-            "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched", "fbsde_strerror")
+            "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
+            "fbsde_solve_batched_backward", "fbsde_strerror")
+
+
+BATCH_TILED, BATCH_PERSISTENT = 0, 1
+
+
+class CBatchOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("streams", ctypes.c_int32), ("tile_bytes", ctypes.c_int64),
+                ("max_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CProblem(ctypes.Structure):
@@ -62,7 +71,7 @@ def load():
     lib.fbsde_terminal.argtypes = [pb, i64, vp, vp, i64, vp, vp, vp]
     lib.fbsde_solve_step.argtypes = [pb, i64, i32, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_solve.argtypes = [pb, i64, vp, vp, vp, vp, vp, sz, i32, vp, vp]
-    lib.fbsde_solve_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fbsde_solve_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
     lib.fbsde_normals.argtypes = [pb, i64, i32, i64, i64, vp, vp, vp]
     lib.fbsde_time_kernel.argtypes = [pb, i64, i32, i32, vp, sz, P(ctypes.c_float), vp]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
@@ -70,13 +79,15 @@ def load():
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]
     lib.fbsde_cholesky_workspace.restype = sz
     lib.fbsde_cholesky_solve.argtypes = [i32, i64, vp, i64, i64, vp, i64, vp, sz, P(i32), vp]
-    lib.fbsde_batched_workspace_size.argtypes = [pb, i64, vp, i32, P(sz)]
-    lib.fbsde_solve_batched.argtypes = [pb, i64, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.fbsde_batched_workspace_size.argtypes = [pb, i64, vp, vp, i32, P(sz)]
+    lib.fbsde_solve_batched.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fbsde_solve_batched_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
                  "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm",
-                 "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched"):
+                 "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
+                 "fbsde_solve_batched_backward"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -146,8 +146,10 @@ def solve(pb, x0, want_grad=True, tape=False, ws=None, return_iters=False):
     return u, grad, st
 
 
-def solve_backward(pb, x0, u_bar, ws):
-    """Adjoint of solve for L = sum_p u_bar[p] u_p; needs ws from solve(..., tape=True)."""
+def solve_backward(pb, x0, u_bar, ws, return_iters=False):
+    """Adjoint of solve for L = sum_p u_bar[p] u_p; needs ws from solve(..., tape=True).
+
+    Returns x0_bar [P][d], gp_bar [4], fp_bar [4], status [P] (and the adjoint CG iterations per level)."""
     P = x0.shape[0]
     _dev_f64(x0, (P, pb.d))
     _dev_f64(u_bar, (P,))
@@ -156,9 +158,12 @@ def solve_backward(pb, x0, u_bar, ws):
     gp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
     fp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
     st = torch.zeros(P, dtype=torch.int32, device=dev)
+    iters = (ctypes.c_int32 * pb.N)()
     N.check(N.load().fbsde_solve_backward(ctypes.byref(pb.c()), P, x0.data_ptr(), u_bar.data_ptr(),
                                           x0_bar.data_ptr(), gp_bar.data_ptr(), fp_bar.data_ptr(), st.data_ptr(),
-                                          ws.data_ptr(), ws.numel(), _stream()))
+                                          ws.data_ptr(), ws.numel(), ctypes.cast(iters, ctypes.c_void_p), _stream()))
+    if return_iters:
+        return x0_bar, gp_bar, fp_bar, st, list(iters)
     return x0_bar, gp_bar, fp_bar, st
 
 
@@ -249,30 +254,80 @@ def cholesky_solve(K, R=None):
     return int(info.value)
 
 
-def solve_batched(problems, x0s, want_grad=True, max_slots=512, ws=None):
-    """Persistent batched solve of several instances: lists of Problem and of device x0 [P_i][d_i] tensors.
+def _batch_opts(mode, streams, tile_bytes, max_slots):
+    m = {"tiled": N.BATCH_TILED, "persistent": N.BATCH_PERSISTENT}[mode]
+    return N.CBatchOpts(m, int(streams), int(tile_bytes), int(max_slots), 0)
 
-    Returns lists (u_i, grad_i or None, status_i).
-    """
+
+def _batch_common(problems, x0s):
     n = len(problems)
     if n != len(x0s) or n == 0:
         raise ValueError("one x0 tensor per problem")
     cps = (N.CProblem * n)(*[pb.c() for pb in problems])
     Ps = (ctypes.c_int64 * n)(*[int(x.shape[0]) for x in x0s])
-    us, grads, sts = [], [], []
     for pb, x in zip(problems, x0s):
         _dev_f64(x, (x.shape[0], pb.d))
+    return n, cps, Ps
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[None if t is None else t.data_ptr() for t in ts])
+
+
+def batched_workspace(problems, x0s, adjoint=False, mode="tiled", streams=4, tile_bytes=0, max_slots=512):
+    n, cps, Ps = _batch_common(problems, x0s)
+    opts = _batch_opts(mode, streams, tile_bytes, max_slots)
+    size = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_batched_workspace_size(cps, n, ctypes.cast(Ps, ctypes.c_void_p), ctypes.byref(opts),
+                                                  1 if adjoint else 0, ctypes.byref(size)))
+    return torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=x0s[0].device)
+
+
+def solve_batched(problems, x0s, want_grad=True, mode="tiled", streams=4, tile_bytes=0, max_slots=512, ws=None):
+    """Batched solve of several instances: lists of Problem and of device x0 [P_i][d_i] tensors.
+
+    mode "tiled" (point tiles over `streams` concurrent streams, each tile at most `tile_bytes` of
+    workspace, 0 = 8 GiB) or "persistent" (one persistent launch per geometry class, `max_slots`
+    workgroups).  Returns lists (u_i, grad_i or None, status_i).
+    """
+    n, cps, Ps = _batch_common(problems, x0s)
+    opts = _batch_opts(mode, streams, tile_bytes, max_slots)
+    us, grads, sts = [], [], []
+    for pb, x in zip(problems, x0s):
         us.append(torch.empty(x.shape[0], dtype=torch.float64, device=x.device))
         grads.append(torch.empty((x.shape[0], pb.d), dtype=torch.float64, device=x.device) if want_grad else None)
         sts.append(torch.empty(x.shape[0], dtype=torch.int32, device=x.device))
-    ptrs = lambda ts: (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
     size = ctypes.c_size_t(0)
-    N.check(N.load().fbsde_batched_workspace_size(cps, n, ctypes.cast(Ps, ctypes.c_void_p), max_slots,
+    N.check(N.load().fbsde_batched_workspace_size(cps, n, ctypes.cast(Ps, ctypes.c_void_p), ctypes.byref(opts), 0,
                                                   ctypes.byref(size)))
     if ws is None or ws.numel() < size.value:
-        ws = torch.empty(int(size.value), dtype=torch.uint8, device=x0s[0].device)
-    gp = ptrs(grads) if want_grad else None
-    N.check(N.load().fbsde_solve_batched(cps, n, ctypes.cast(Ps, ctypes.c_void_p), ptrs(x0s), ptrs(us),
-                                         None if gp is None else ctypes.cast(gp, ctypes.c_void_p), ptrs(sts), max_slots,
-                                         ws.data_ptr(), ws.numel(), _stream()))
+        ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=x0s[0].device)
+    gp = _ptrs(grads) if want_grad else None
+    N.check(N.load().fbsde_solve_batched(cps, n, ctypes.cast(Ps, ctypes.c_void_p), _ptrs(x0s), _ptrs(us),
+                                         None if gp is None else ctypes.cast(gp, ctypes.c_void_p), _ptrs(sts),
+                                         ctypes.byref(opts), ws.data_ptr(), ws.numel(), _stream()))
     return us, grads, sts
+
+
+def solve_batched_backward(problems, x0s, u_bars, streams=4, tile_bytes=0, ws=None):
+    """Batched forward + reverse mode: per instance u [P_i], x0_bar [P_i][d_i], gp_bar [4], fp_bar [4], status."""
+    n, cps, Ps = _batch_common(problems, x0s)
+    opts = _batch_opts("tiled", streams, tile_bytes, 512)
+    for ub, x in zip(u_bars, x0s):
+        _dev_f64(ub, (x.shape[0],))
+    us, xbs, gps, fps, sts = [], [], [], [], []
+    for pb, x in zip(problems, x0s):
+        us.append(torch.empty(x.shape[0], dtype=torch.float64, device=x.device))
+        xbs.append(torch.empty((x.shape[0], pb.d), dtype=torch.float64, device=x.device))
+        gps.append(torch.empty(4, dtype=torch.float64, device=x.device))
+        fps.append(torch.empty(4, dtype=torch.float64, device=x.device))
+        sts.append(torch.empty(x.shape[0], dtype=torch.int32, device=x.device))
+    size = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_batched_workspace_size(cps, n, ctypes.cast(Ps, ctypes.c_void_p), ctypes.byref(opts), 1,
+                                                  ctypes.byref(size)))
+    if ws is None or ws.numel() < size.value:
+        ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=x0s[0].device)
+    N.check(N.load().fbsde_solve_batched_backward(cps, n, ctypes.cast(Ps, ctypes.c_void_p), _ptrs(x0s), _ptrs(u_bars),
+                                                  _ptrs(us), _ptrs(xbs), _ptrs(gps), _ptrs(fps), _ptrs(sts),
+                                                  ctypes.byref(opts), ws.data_ptr(), ws.numel(), _stream()))
+    return us, xbs, gps, fps, sts

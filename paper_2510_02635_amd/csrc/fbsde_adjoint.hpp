@@ -179,7 +179,10 @@ k_adj_rowdot(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, in
              const double* __restrict__ w, const double* __restrict__ x, const double* __restrict__ adj,
              double* __restrict__ G, double* __restrict__ psc) {
     using Gm = Geo<Q, TEAM>;
-    using R = S;
+    // FP64 arithmetic on the state: bbar carries the ridge-only null-space component of its
+    // right-hand side scaled by 1/lam, which the centred product W_j.bbar - Wbar.bbar cancels; in
+    // FP32 the cancellation would leave eps32 |W| |bbar| of noise in t_j
+    using R = double;
     __shared__ double red[2 * Gm::BS / 64];
     const int p = blockIdx.y, c = blockIdx.x;
     const int team = threadIdx.x / Gm::TL, L = threadIdx.x % Gm::TL;
@@ -207,7 +210,7 @@ k_adj_rowdot(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, in
                     S xv[4];
                     load4(row + e0, xv);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) dl.add(xv[e] * v[q][e]);
+                    for (int e = 0; e < 4; ++e) dl.add((R)xv[e] * v[q][e]);
                 }
             }
         }

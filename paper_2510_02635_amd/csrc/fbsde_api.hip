@@ -5,6 +5,8 @@
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
 
+#include <vector>
+
 using namespace fbsde;
 using namespace fbsde::host;
 
@@ -103,7 +105,7 @@ int fold_parts(const Plan& pl, int64_t P, double* a, double* b, double* c, hipSt
     return 1;
 }
 
-template <typename S>
+template <typename S, typename R = S>
 int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
            const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
     const int fixed = pb->cg_fixed_iters;
@@ -113,14 +115,14 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
     for (; it < cap; ++it) {
         dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
             constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-            hipLaunchKernelGGL((k_matvec<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
+            hipLaunchKernelGGL((k_matvec<S, R, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
                                W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, ws.pv, ws.scal, NS,
                                ws.iscal, ws.part1, ws.psc);
         });
         const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
         hipLaunchKernelGGL(k_cg_update, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, pl.ld,
                            pb->s, Wbar, ws.x, ws.r, ws.pv, ws.qv, ws.scal, NS, ws.iscal,
-                           pb->cg_rtol * pb->cg_rtol, pb->cg_maxit, ws.active, status);
+                           cg_rtol_of(pb) * cg_rtol_of(pb), pb->cg_maxit, ws.active, status);
         if (fixed <= 0 && (it + 1) % poll == 0) {
             int active = 0;
             if (hipMemcpyAsync(&active, ws.active, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -133,6 +135,20 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
     }
     err = last_error();
     return it;
+}
+
+// The largest CG iteration count over the points of the level just solved (iscal[p][0]); the
+// launches after the last point converged exit at once and are not counted.  Synchronises.
+int point_iters_max(const WS& ws, int64_t P, hipStream_t st, int& err) {
+    std::vector<int> h((size_t)P * 4);
+    if (hipMemcpyAsync(h.data(), ws.iscal, h.size() * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        err = FBSDE_EHIP;
+        return 0;
+    }
+    int m = 0;
+    for (int64_t p = 0; p < P; ++p) m = std::max(m, h[(size_t)p * 4]);
+    return m;
 }
 
 // One backward level: regression of Y_next on the cloud W (at t_{k+1}); leaves alpha_x in ws.x,
@@ -217,7 +233,11 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
         const int iters = run_level<S>(pb, pl, P, k, W, ldw, Ycur, ws.rn2, w_k, Wbar_k, ws, nullptr, nullptr, status,
                                        st, err, warm);
         if (err) return err;
-        if (cg_iters_out) cg_iters_out[k] = iters;
+        if (cg_iters_out) {
+            cg_iters_out[k] = point_iters_max(ws, P, st, err);
+            if (err) return err;
+        }
+        (void)iters;
         if (tape) {
             if (hipMemcpyAsync(ws.tax + (size_t)k * PL, ws.x, PL * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
                 hipMemcpyAsync(ws.tscal + (size_t)k * P * NS, ws.scal, (size_t)P * NS * 8, hipMemcpyDeviceToDevice,
@@ -242,7 +262,8 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
 
 template <typename S>
 int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, const double* u_bar,
-                  double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, WS& ws, hipStream_t st) {
+                  double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, WS& ws, int32_t* cg_iters_out,
+                  hipStream_t st) {
     S* W = (S*)ws.W;
     const int64_t ldw = pl.ld;
     const int64_t PM = P * pl.M, PL = P * (int64_t)pl.ld;
@@ -269,7 +290,15 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
         hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, vc, pl.ld, pb->s,
                            lam, Wbar_k, ws.tax + (size_t)k * PL, ws.adj, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
                            ws.active);
-        run_cg<S>(pb, pl, P, W, ldw, w_k, Wbar_k, ws, status, st, err);
+        // rank-deficient design: FP64 arithmetic in the CG product (the right-hand side has a
+        // large component in the ridge-only null space, carried by the iterate with weight 1/lam)
+        const int iters = (pl.M > pl.d + 1) ? run_cg<S, S>(pb, pl, P, W, ldw, w_k, Wbar_k, ws, status, st, err)
+                                            : run_cg<S, double>(pb, pl, P, W, ldw, w_k, Wbar_k, ws, status, st, err);
+        (void)iters;
+        if (cg_iters_out) {
+            cg_iters_out[k] = point_iters_max(ws, P, st, err);
+            if (err) return err;
+        }
         if (err) return err;
         hipLaunchKernelGGL(k_adj_bbar, dim3((unsigned)P), dim3(256), 0, st, ws.x, Wbar_k, pl.ld, ws.adj);
         dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
@@ -446,7 +475,7 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
 
 int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
                          double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
-                         fbsde_stream stream) {
+                         int32_t* cg_iters_out, fbsde_stream stream) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
     if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
@@ -464,8 +493,8 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
         return FBSDE_EHIP;
     if (tag != tape_tag(pb, P)) return FBSDE_ESTATE;
     if (pb->prec == FBSDE_F64)
-        return backward_impl<double>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, st);
-    return backward_impl<float>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, st);
+        return backward_impl<double>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, cg_iters_out, st);
+    return backward_impl<float>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, cg_iters_out, st);
 }
 
 int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows, double* out,
@@ -509,7 +538,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
             if (which == 0) {
                 dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
                     constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-                    hipLaunchKernelGGL((k_matvec<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
+                    hipLaunchKernelGGL((k_matvec<S, S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
                                        0, st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, ws.w,
                                        ws.pv, ws.scal, NS, ws.iscal, ws.part1, ws.psc);
                 });

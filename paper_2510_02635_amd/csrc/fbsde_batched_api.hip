@@ -1,8 +1,16 @@
-// Host side of the persistent batched launch: geometry classes, work tables, one persistent kernel per class.
+// Host side of the batched solve of many instances.
+//  Tiled (default): the work items are (instance, point-tile) pairs, each run through the whole level
+//    chain by the multi-block path of fbsde_solve (every point split over many workgroups along its
+//    particle rows), on a pool of host worker threads that each own a HIP stream and a workspace arena.
+//    Tiles are sized to the arena, taken largest first, and overlap on the chip across the streams.
+//  Persistent: one launch per geometry class; every workgroup pulls (instance, point) items from an
+//    atomic queue and runs the whole chain of its point alone.
 #include "fbsde_host.hpp"
 #include "fbsde_batched.hpp"
 
+#include <atomic>
 #include <map>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -85,13 +93,191 @@ void launch_batched_class(const BatchClass& c, const BatchInst* d_insts, const B
     });
 }
 
-}  // namespace
 
-extern "C" {
+// ------------------------------------------------------------------ tiled scheduler
+struct TileUnit {
+    int inst;
+    int64_t p0, np;
+    double cost;
+};
 
-int fbsde_batched_workspace_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, int32_t max_slots,
-                                 size_t* bytes) {
-    if (!pbs || !P || !bytes || n_inst < 1 || max_slots < 1) return FBSDE_EINVAL;
+struct Opts {
+    int mode, streams, max_slots;
+    size_t tile_bytes;
+};
+
+int read_opts(const fbsde_batch_opts* o, Opts& r) {
+    r.mode = o ? o->mode : FBSDE_BATCH_TILED;
+    r.streams = (o && o->streams) ? o->streams : 4;
+    r.max_slots = (o && o->max_slots) ? o->max_slots : 512;
+    r.tile_bytes = (o && o->tile_bytes) ? (size_t)o->tile_bytes : ((size_t)8 << 30);
+    if (r.mode != FBSDE_BATCH_TILED && r.mode != FBSDE_BATCH_PERSISTENT) return FBSDE_EINVAL;
+    if (r.streams < 1 || r.streams > 8 || r.max_slots < 1 || (o && o->tile_bytes < 0)) return FBSDE_EINVAL;
+    if (o && o->reserved != 0) return FBSDE_EINVAL;
+    return FBSDE_OK;
+}
+
+// Point tiles of every instance: the largest tile whose workspace fits the arena cap (at least one
+// point, at most 65535), then equal tiles; largest cost (points x particle rows x row bytes) first.
+int plan_tiles(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const Opts& o, int32_t flags,
+               std::vector<TileUnit>& units, size_t& arena) {
+    units.clear();
+    arena = 0;
+    for (int64_t i = 0; i < n_inst; ++i) {
+        int rc = check_problem(&pbs[i], 0);
+        if (rc) return rc;
+        if (P[i] < 0) return FBSDE_EINVAL;
+        if (P[i] == 0) continue;
+        if ((flags & FBSDE_WS_TAPE) && pbs[i].shared_dw) return FBSDE_EINVAL;
+        auto ws_of = [&](int64_t np, size_t& b) { return fbsde_workspace_size(&pbs[i], np, flags, &b); };
+        int64_t lo = 1, hi = std::min<int64_t>(P[i], 65535);
+        size_t b = 0;
+        if ((rc = ws_of(hi, b))) return rc;
+        if (b > o.tile_bytes) {
+            while (lo < hi) {   // largest np in [1, hi) that fits
+                const int64_t mid = (lo + hi + 1) / 2;
+                if ((rc = ws_of(mid, b))) return rc;
+                if (b <= o.tile_bytes) lo = mid; else hi = mid - 1;
+            }
+            hi = lo;
+        }
+        const int64_t ntiles = (P[i] + hi - 1) / hi;
+        const int64_t np = (P[i] + ntiles - 1) / ntiles;
+        Plan pl;
+        if ((rc = make_plan(&pbs[i], 1, pl))) return rc;
+        for (int64_t p0 = 0; p0 < P[i]; p0 += np) {
+            const int64_t m = std::min<int64_t>(np, P[i] - p0);
+            if ((rc = ws_of(m, b))) return rc;
+            arena = std::max(arena, (size_t)round_up((int64_t)b, 256));
+            units.push_back(TileUnit{(int)i, p0, m, (double)m * (double)pbs[i].M * (double)pl.ld * (double)pl.esz});
+        }
+    }
+    std::stable_sort(units.begin(), units.end(), [](const TileUnit& a, const TileUnit& b) { return a.cost > b.cost; });
+    return FBSDE_OK;
+}
+
+size_t tiled_header_bytes(size_t n_units) { return (size_t)round_up((int64_t)(n_units * 8 * sizeof(double)), 256); }
+
+int tiled_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const Opts& o, int32_t flags,
+               size_t* bytes, std::vector<TileUnit>* keep = nullptr, size_t* arena_out = nullptr, int* nw_out = nullptr) {
+    std::vector<TileUnit> units;
+    size_t arena = 0;
+    int rc = plan_tiles(pbs, n_inst, P, o, flags, units, arena);
+    if (rc) return rc;
+    const int nw = (int)std::min<int64_t>(o.streams, std::max<int64_t>(1, (int64_t)units.size()));
+    *bytes = tiled_header_bytes(units.size()) + (size_t)nw * arena;
+    if (keep) *keep = std::move(units);
+    if (arena_out) *arena_out = arena;
+    if (nw_out) *nw_out = nw;
+    return FBSDE_OK;
+}
+
+// Parameter adjoints of an instance: the sum of its tiles' sums, in tile order.
+__global__ void k_sum_tiles(const double* __restrict__ part, const int* __restrict__ idx, int n, double* gp_bar,
+                            double* fp_bar) {
+    const int t = threadIdx.x;
+    if (t >= 8) return;
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v += part[(int64_t)idx[k] * 8 + t];
+    if (t < 4) gp_bar[t] = v;
+    else fp_bar[t - 4] = v;
+}
+
+struct TiledArgs {
+    const fbsde_problem* pbs;
+    const double* const* x0;
+    double* const* u;
+    double* const* grad;
+    uint32_t* const* status;
+    const double* const* u_bar;      // adjoint only
+    double* const* x0_bar;
+    double* const* gp_bar;
+    double* const* fp_bar;
+};
+
+int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& o, bool adjoint, void* wsp,
+              size_t ws_bytes, hipStream_t caller) {
+    const int32_t flags = adjoint ? FBSDE_WS_TAPE : 0;
+    std::vector<TileUnit> units;
+    size_t need = 0, arena = 0;
+    int nw = 1;
+    int rc = tiled_size(a.pbs, n_inst, P, o, flags, &need, &units, &arena, &nw);
+    if (rc) return rc;
+    if (need > ws_bytes) return FBSDE_ENOSPC;
+    if (units.empty()) return FBSDE_OK;
+    char* base = (char*)wsp;
+    double* tpart = (double*)base;   // [units][8]: gp_bar, fp_bar of each tile
+    char* arenas = base + tiled_header_bytes(units.size());
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FBSDE_EHIP;
+    hipEvent_t ev0;
+    if (hipEventCreateWithFlags(&ev0, hipEventDisableTiming) != hipSuccess) return FBSDE_EHIP;
+    if (hipEventRecord(ev0, caller) != hipSuccess) { hipEventDestroy(ev0); return FBSDE_EHIP; }
+    std::atomic<int> next{0}, first_err{0};
+    auto fail = [&](int e) { int z = 0; first_err.compare_exchange_strong(z, e); };
+    auto worker = [&](int w) {
+        if (hipSetDevice(dev) != hipSuccess) { fail(FBSDE_EHIP); return; }
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { fail(FBSDE_EHIP); return; }
+        if (hipStreamWaitEvent(s, ev0, 0) != hipSuccess) fail(FBSDE_EHIP);
+        char* ar = arenas + (size_t)w * arena;
+        for (;;) {
+            if (first_err.load()) break;
+            const int k = next.fetch_add(1);
+            if (k >= (int)units.size()) break;
+            const TileUnit& t = units[(size_t)k];
+            const int i = t.inst;
+            fbsde_problem pb = a.pbs[i];
+            pb.point_base = (uint32_t)(pb.point_base + (uint32_t)t.p0);
+            const int64_t d = pb.d;
+            const double* x0 = a.x0[i] + t.p0 * d;
+            double* u = a.u[i] + t.p0;
+            double* g = a.grad && a.grad[i] ? a.grad[i] + t.p0 * d : nullptr;
+            uint32_t* st = a.status[i] + t.p0;
+            int e = fbsde_solve(&pb, t.np, x0, u, g, st, ar, arena, flags, nullptr, (fbsde_stream)s);
+            if (!e && adjoint)
+                e = fbsde_solve_backward(&pb, t.np, x0, a.u_bar[i] + t.p0, a.x0_bar[i] + t.p0 * d,
+                                         tpart + (size_t)k * 8, tpart + (size_t)k * 8 + 4, st, ar, arena, nullptr,
+                                         (fbsde_stream)s);
+            if (e) fail(e);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) fail(FBSDE_EHIP);
+        hipStreamDestroy(s);
+    };
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nw; ++w) pool.emplace_back(worker, w);
+    for (auto& th : pool) th.join();
+    hipEventDestroy(ev0);
+    if ((rc = first_err.load())) return rc;
+    if (adjoint) {
+        // per instance, the indices of its tiles in point order, then one summing launch each
+        std::vector<std::vector<int>> by_inst((size_t)n_inst);
+        std::vector<std::pair<int64_t, int>> order;
+        for (size_t k = 0; k < units.size(); ++k) order.emplace_back(units[k].p0, (int)k);
+        std::sort(order.begin(), order.end());
+        for (const auto& pk : order) by_inst[(size_t)units[(size_t)pk.second].inst].push_back(pk.second);
+        std::vector<int> flat;
+        std::vector<std::pair<size_t, int>> span((size_t)n_inst);
+        for (int64_t i = 0; i < n_inst; ++i) {
+            span[(size_t)i] = {flat.size(), (int)by_inst[(size_t)i].size()};
+            flat.insert(flat.end(), by_inst[(size_t)i].begin(), by_inst[(size_t)i].end());
+        }
+        // the index table goes to arena 0, free once every worker has synchronised its stream
+        int* d_idx = (int*)arenas;
+        if (!flat.empty() &&
+            hipMemcpyAsync(d_idx, flat.data(), flat.size() * sizeof(int), hipMemcpyHostToDevice, caller) != hipSuccess)
+            return FBSDE_EHIP;
+        for (int64_t i = 0; i < n_inst; ++i)
+            hipLaunchKernelGGL(k_sum_tiles, dim3(1), dim3(64), 0, caller, tpart, d_idx + span[(size_t)i].first,
+                               span[(size_t)i].second, a.gp_bar[i], a.fp_bar[i]);
+        if ((rc = last_error())) return rc;
+        // the host index table must outlive its copy
+        if (hipStreamSynchronize(caller) != hipSuccess) return FBSDE_EHIP;
+    }
+    return FBSDE_OK;
+}
+
+int persistent_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, int32_t max_slots, size_t* bytes) {
     std::vector<BatchClass> cls;
     int rc = batch_classes(pbs, n_inst, P, cls);
     if (rc) return rc;
@@ -106,19 +292,17 @@ int fbsde_batched_workspace_size(const fbsde_problem* pbs, int64_t n_inst, const
     return FBSDE_OK;
 }
 
-int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const double* const* x0,
-                        double* const* u, double* const* grad, uint32_t* const* status, int32_t max_slots, void* wsp,
-                        size_t ws_bytes, fbsde_stream stream) {
-    if (!pbs || !P || !x0 || !u || !status || !wsp || n_inst < 1 || max_slots < 1) return FBSDE_EINVAL;
+int run_persistent(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const double* const* x0,
+                   double* const* u, double* const* grad, uint32_t* const* status, int32_t max_slots, void* wsp,
+                   size_t ws_bytes, hipStream_t st) {
     std::vector<BatchClass> cls;
     int rc = batch_classes(pbs, n_inst, P, cls);
     if (rc) return rc;
     size_t need = 0;
-    if ((rc = fbsde_batched_workspace_size(pbs, n_inst, P, max_slots, &need))) return rc;
+    if ((rc = persistent_size(pbs, n_inst, P, max_slots, &need))) return rc;
     if (need > ws_bytes) return FBSDE_ENOSPC;
     for (int64_t i = 0; i < n_inst; ++i)
         if (P[i] > 0 && (!x0[i] || !u[i] || !status[i])) return FBSDE_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
     // descriptor table and the work items of every class (device copies in the workspace header)
     std::vector<BatchInst> hi((size_t)n_inst);
     for (int64_t i = 0; i < n_inst; ++i) {
@@ -130,7 +314,7 @@ int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t*
         BatchInst& b = hi[(size_t)i];
         b.d = (int)pb->d; b.ld = pl.ld; b.M = (int)pb->M; b.N = (int)pb->N; b.P = (int)P[i];
         b.T = pb->T; b.s = pb->s; b.eps_h = pb->eps_h; b.ridge_rel = pb->ridge_rel;
-        b.rtol2 = pb->cg_rtol * pb->cg_rtol;
+        b.rtol2 = cg_rtol_of(pb) * cg_rtol_of(pb);
         b.newton_iters = pb->newton_iters;
         b.cg_maxit = pb->cg_fixed_iters > 0 ? pb->cg_fixed_iters : pb->cg_maxit;
         b.g_kind = pb->g_kind;
@@ -176,6 +360,56 @@ int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t*
         if ((rc = last_error())) return rc;
     }
     return FBSDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fbsde_batched_workspace_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                                 const fbsde_batch_opts* opts, int32_t adjoint, size_t* bytes) {
+    if (!pbs || !P || !bytes || n_inst < 1 || (adjoint != 0 && adjoint != 1)) return FBSDE_EINVAL;
+    Opts o;
+    int rc = read_opts(opts, o);
+    if (rc) return rc;
+    if (o.mode == FBSDE_BATCH_PERSISTENT) {
+        if (adjoint) return FBSDE_EINVAL;
+        return persistent_size(pbs, n_inst, P, o.max_slots, bytes);
+    }
+    return tiled_size(pbs, n_inst, P, o, adjoint ? FBSDE_WS_TAPE : 0, bytes);
+}
+
+int fbsde_solve_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const double* const* x0,
+                        double* const* u, double* const* grad, uint32_t* const* status, const fbsde_batch_opts* opts,
+                        void* wsp, size_t ws_bytes, fbsde_stream stream) {
+    if (!pbs || !P || !x0 || !u || !status || !wsp || n_inst < 1) return FBSDE_EINVAL;
+    Opts o;
+    int rc = read_opts(opts, o);
+    if (rc) return rc;
+    for (int64_t i = 0; i < n_inst; ++i)
+        if (P[i] > 0 && (!x0[i] || !u[i] || !status[i])) return FBSDE_EINVAL;
+    if (o.mode == FBSDE_BATCH_PERSISTENT)
+        return run_persistent(pbs, n_inst, P, x0, u, grad, status, o.max_slots, wsp, ws_bytes, (hipStream_t)stream);
+    TiledArgs a{pbs, x0, u, grad, status, nullptr, nullptr, nullptr, nullptr};
+    return run_tiled(a, n_inst, P, o, false, wsp, ws_bytes, (hipStream_t)stream);
+}
+
+int fbsde_solve_batched_backward(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                                 const double* const* x0, const double* const* u_bar, double* const* u,
+                                 double* const* x0_bar, double* const* gp_bar, double* const* fp_bar,
+                                 uint32_t* const* status, const fbsde_batch_opts* opts, void* wsp, size_t ws_bytes,
+                                 fbsde_stream stream) {
+    if (!pbs || !P || !x0 || !u_bar || !u || !x0_bar || !gp_bar || !fp_bar || !status || !wsp || n_inst < 1)
+        return FBSDE_EINVAL;
+    Opts o;
+    int rc = read_opts(opts, o);
+    if (rc) return rc;
+    if (o.mode != FBSDE_BATCH_TILED) return FBSDE_EINVAL;
+    for (int64_t i = 0; i < n_inst; ++i)
+        if ((P[i] > 0 && (!x0[i] || !u_bar[i] || !u[i] || !x0_bar[i] || !status[i])) || !gp_bar[i] || !fp_bar[i])
+            return FBSDE_EINVAL;
+    TiledArgs a{pbs, x0, u, nullptr, status, u_bar, x0_bar, gp_bar, fp_bar};
+    return run_tiled(a, n_inst, P, o, true, wsp, ws_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -42,6 +42,14 @@ inline int check_problem(const fbsde_problem* pb, int64_t P) {
     return FBSDE_OK;
 }
 
+// CG stopping tolerance actually used.  In FP32C with a rank-deficient centred design (M <= d + 1) the
+// right-hand side carries FP32 rounding in the ridge-only null space; a test tighter than that rounding
+// makes CG resolve it, scaled by 1/lam, into the slope: the tolerance is held at 1e-7 or above there.
+inline double cg_rtol_of(const fbsde_problem* pb) {
+    if (pb->prec == FBSDE_F32C && pb->M <= pb->d + 1) return std::max(pb->cg_rtol, 1e-7);
+    return pb->cg_rtol;
+}
+
 inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
     pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;

@@ -317,14 +317,16 @@ k_moments_finish(const double* __restrict__ part1, const double* __restrict__ pa
 // One pass of the fused matrix-free product of the centred weighted normal matrix with the CG
 // direction p (the two steps of the paper's matrix-free scheme done per particle row while the
 // row sits in registers): t_j = D'_j . p = s (W_j . p - Wbar . p), then sum_j w_j t_j W_j and
-// sum_j w_j t_j, per block.  One read of the state per CG iteration.
-template <typename S, int Q, int TEAM>
+// sum_j w_j t_j, per block.  One read of the state per CG iteration.  R is the arithmetic type: the
+// element type with compensated FP32 sums for the forward solve, or FP64 on the FP32 state for the
+// adjoint solve, whose right-hand side reaches the ridge-only null space of the centred design (there
+// the iterate grows like 1/lam and FP32 row dots would leak eps32 |W| |x| back into the range).
+template <typename S, typename R, int Q, int TEAM>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nchunk, int ld, double s,
          const double* __restrict__ w, const double* __restrict__ pv, const double* __restrict__ scal,
          int ns, const int* __restrict__ iscal, double* __restrict__ part, double* __restrict__ psc) {
     using G = Geo<Q, TEAM>;
-    using R = S;
     __shared__ double lds[(G::TPW > 1) ? G::TPW * 4 * Q * G::TL : 1];
     __shared__ double red[2 * G::BS / 64];
     const int p = blockIdx.y, c = blockIdx.x;
@@ -344,8 +346,9 @@ k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nc
     double tau = 0.0;
     // rows are double-buffered: the loads of the team's next row are issued before the reduction of
     // the current one, so a wave keeps two rows in flight across the team barrier (not in 1024-lane
-    // blocks, whose 128-register cap the second buffer would overflow)
-    constexpr bool PF = G::BS < 1024;
+    // blocks, whose 128-register cap the second buffer would overflow, nor with FP64 arithmetic on
+    // eight groups per lane, which already fills the register file)
+    constexpr bool PF = G::BS < 1024 && !(sizeof(R) > sizeof(S) && Q == 8);
     const S* base = W + (int64_t)p * M * ldw;
     S x[Q][4];
     if (PF && r0 + team < r1) load_row<S, Q, G::TL>(base + (int64_t)(r0 + team) * ldw, ld, L, x);
@@ -363,7 +366,7 @@ k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nc
 #pragma unroll
             for (int q = 0; q < Q; ++q)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) dl.add(x[q][e] * v[q][e]);
+                for (int e = 0; e < 4; ++e) dl.add((R)x[q][e] * v[q][e]);
         }
         double t = dl.get(), unused = 0.0;
         team_sum2<TEAM>(t, unused, red, team);
@@ -374,7 +377,7 @@ k_matvec(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nc
 #pragma unroll
             for (int q = 0; q < Q; ++q)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[q][e].add(cr * x[q][e]);
+                for (int e = 0; e < 4; ++e) acc[q][e].add(cr * (R)x[q][e]);
         }
         if (PF) {
 #pragma unroll

@@ -83,7 +83,7 @@ def test_adjoint_fp64_matches_oracle(name, kw, xkind, P):
     _adjoint_case(kw, xkind, P, F.F64, 1e-10)
 
 
-@pytest.mark.parametrize("name,kw,xkind,P", ADJ_CASES[:3], ids=[c[0] for c in ADJ_CASES[:3]])
+@pytest.mark.parametrize("name,kw,xkind,P", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
 def test_adjoint_fp32c_matches_fp64_oracle(name, kw, xkind, P):
     _adjoint_case(kw, xkind, P, F.F32C, 1e-5)
 
@@ -128,3 +128,20 @@ def test_backward_without_tape_is_refused():
     ws.zero_()
     with pytest.raises(F.FbsdeError):
         F.solve_backward(hp, xt, torch.ones(2, dtype=torch.float64, device=DEV), ws)
+
+
+def test_fp32c_tight_tolerance_is_held_in_the_rank_deficient_regime():
+    """M <= d + 1 in FP32C: a CG test below the FP32 rounding of the right-hand side would resolve that
+    rounding's null-space part scaled by 1/lam into the slope (errors near 1e-3 were seen at 1e-9);
+    the library holds the tolerance at 1e-7 there, so the forward stays at the FP32C bar."""
+    kw = dict(d=700, M=96, N=2, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0))
+    hp, op = problems(prec=F.F32C, cg_rtol=1e-9, **kw)
+    x0 = workloads.points("normal_over_sqrt_d", 2, kw["d"], 9)
+    _say("[fp32c] rank-deficient design with cg_rtol=1e-9")
+    u, g, st = F.solve(hp, torch.tensor(x0, device=DEV))
+    torch.cuda.synchronize()
+    for p in range(2):
+        ref = OS.solve_point(op, x0[p], p)
+        e = rel_err(g[p].cpu().numpy(), ref["grad"])
+        _say(f"  p={p} rel_grad={e:.2e}")
+        assert e <= 1e-5

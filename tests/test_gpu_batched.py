@@ -1,8 +1,10 @@
-"""GPU parity of the persistent batched launch (fbsde_solve_batched) against the FP64 oracle.
+"""GPU parity of the batched solve (fbsde_solve_batched, fbsde_solve_batched_backward) against the FP64
+oracle and the single-instance path.
 
 Instances of uneven d (several geometry classes, team widths 1..16 waves), M, f, g and precision run in
-one call with fewer workgroup slots than points, so slots are reused through the work queue.  Each
-instance must equal the oracle at the precision bar (FP64 1e-10, FP32C 1e-5).
+one call.  Persistent schedule: fewer workgroup slots than points, so slots are reused through the work
+queue.  Tiled schedule: a small tile cap splits instances into several point tiles spread over three
+streams.  Each instance must equal the oracle at the precision bar (FP64 1e-10, FP32C 1e-5).
 """
 import sys
 
@@ -49,16 +51,20 @@ INSTANCES = [
 ]
 
 
-@pytest.mark.parametrize("max_slots", [3, 64])
-def test_batched_matches_oracle(max_slots):
+SCHEDULES = [dict(mode="persistent", max_slots=3), dict(mode="persistent", max_slots=64),
+             dict(mode="tiled", streams=3, tile_bytes=1 << 20), dict(mode="tiled")]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=["persistent3", "persistent64", "tiled_small", "tiled"])
+def test_batched_matches_oracle(sched):
     hps, ops, xs = [], [], []
     for kw, xkind, P in INSTANCES:
         hp, op = problems(**kw)
         hps.append(hp)
         ops.append(op)
         xs.append(workloads.points(xkind, P, kw["d"], 21 + kw["instance"]))
-    _say(f"[batched] {len(hps)} instances, max_slots={max_slots}")
-    us, gs, sts = F.solve_batched(hps, [torch.tensor(x, device=DEV) for x in xs], max_slots=max_slots)
+    _say(f"[batched] {len(hps)} instances, {sched}")
+    us, gs, sts = F.solve_batched(hps, [torch.tensor(x, device=DEV) for x in xs], **sched)
     torch.cuda.synchronize()
     for i, (hp, op, x) in enumerate(zip(hps, ops, xs)):
         tol = 1e-10 if hp.prec == F.F64 else 1e-5
@@ -76,8 +82,66 @@ def test_batched_equals_single_solve():
     kw, xkind, P = INSTANCES[5]
     hp, _ = problems(**kw)
     x = torch.tensor(workloads.points(xkind, P, kw["d"], 99), device=DEV)
-    us, gs, _ = F.solve_batched([hp], [x], max_slots=2)
+    _say("[batched] persistent vs single")
+    us, gs, _ = F.solve_batched([hp], [x], mode="persistent", max_slots=2)
     u1, g1, _ = F.solve(hp, x)
     torch.cuda.synchronize()
     assert torch.allclose(us[0], u1, rtol=1e-12, atol=0)
     assert torch.allclose(gs[0], g1, rtol=1e-10, atol=1e-14)
+    # one tile holding the whole instance runs the very same launches: identical bits
+    _say("[batched] tiled (one tile) vs single")
+    ut, gt, _ = F.solve_batched([hp], [x], mode="tiled", streams=2)
+    torch.cuda.synchronize()
+    assert torch.equal(ut[0], u1) and torch.equal(gt[0], g1)
+    # one point per tile: other chunk splits, same streams and test
+    _say("[batched] tiled (one point per tile) vs single")
+    w1 = F.workspace_size(hp, 1)
+    ut, gt, _ = F.solve_batched([hp], [x], mode="tiled", streams=2, tile_bytes=w1)
+    torch.cuda.synchronize()
+    assert torch.allclose(ut[0], u1, rtol=1e-12, atol=0)
+    assert torch.allclose(gt[0], g1, rtol=1e-10, atol=1e-14)
+
+
+ADJ = [
+    (dict(d=37, M=100, N=3, T=0.5, f_kind=F.F_HJB, fp=(0.8, 0, 0, 0), g_kind=F.G_HJB_LOG, gp=(1.0, 0, 0, 0), seed=7,
+          instance=0), "uniform", 5),
+    (dict(d=200, M=400, N=4, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0),
+          instance=5), "normal_over_sqrt_d", 3),
+    (dict(d=700, M=96, N=2, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0),
+          prec=F.F32C, instance=6), "normal:0.2", 2),
+]
+
+
+@pytest.mark.parametrize("tile_small", [False, True], ids=["one_tile", "point_tiles"])
+def test_batched_backward_matches_single_and_oracle(tile_small):
+    hps, ops, xs, ubs = [], [], [], []
+    for kw, xkind, P in ADJ:
+        hp, op = problems(**kw)
+        hps.append(hp)
+        ops.append(op)
+        xs.append(torch.tensor(workloads.points(xkind, P, kw["d"], 5 + kw["instance"]), device=DEV))
+        ubs.append(torch.linspace(0.5, 1.5, P, dtype=torch.float64, device=DEV))
+    tb = max(F.workspace_size(hp, 1, tape=True) for hp in hps) if tile_small else 0
+    _say(f"[batched-adjoint] {len(hps)} instances, tile_bytes={tb}")
+    us, xbs, gps, fps, sts = F.solve_batched_backward(hps, xs, ubs, streams=3, tile_bytes=tb)
+    torch.cuda.synchronize()
+    for i, (hp, op) in enumerate(zip(hps, ops)):
+        tol = 1e-10 if hp.prec == F.F64 else 1e-5
+        assert int(sts[i].abs().sum().item()) == 0
+        ws = F.workspace(hp, xs[i].shape[0], tape=True, device=DEV)
+        u1, _, _ = F.solve(hp, xs[i], tape=True, ws=ws)
+        xb1, gp1, fp1, _ = F.solve_backward(hp, xs[i], ubs[i], ws)
+        torch.cuda.synchronize()
+        _say(f"  inst {i}: |du|={float((us[i] - u1).abs().max()):.2e} |dx0bar|={float((xbs[i] - xb1).abs().max()):.2e}")
+        if not tile_small:
+            assert torch.equal(us[i], u1) and torch.equal(xbs[i], xb1)
+        assert torch.allclose(us[i], u1, rtol=1e-12, atol=0)
+        assert torch.allclose(xbs[i], xb1, rtol=1e-9, atol=1e-13)
+        assert torch.allclose(gps[i], gp1, rtol=1e-9, atol=1e-13)
+        assert torch.allclose(fps[i], fp1, rtol=1e-9, atol=1e-13)
+        # oracle on the first point: x0_bar of ubar_0 u_0
+        x = xs[i].cpu().numpy()
+        ref = OS.adjoint_point(op, x[0], 0, ubar=float(ubs[i][0]))
+        e = rel_err(xbs[i][0].cpu().numpy(), ref["x0bar"])
+        _say(f"  inst {i}: oracle rel_err x0bar[0] = {e:.2e}")
+        assert e <= tol

@@ -15,14 +15,14 @@
 
 namespace fbsde {
 
-enum { A_ABAR = 0, A_TAU = 1, A_ZC = 2, A_WB = 3, A_FP = 4, A_GP = 8, A_S1 = 12, A_NS = 16 };
 
 // Level k of the adjoint, per point: finish G_k from the previous level's row pass
 // (G_j += w^(k-1)_j (alphabar_{k-1} - tau_{k-1})), then the Newton adjoint cbar_j = G_j / F'(Y^j_k),
 // alphabar_k = sum cbar, the coefficient of Zbar (Zbar = zc Z) and the f-parameter sums.
 // init (k = 0): G = ubar / M (u is the particle mean).  terminal: only finish G_N.
 __global__ void __launch_bounds__(256)
-k_adj_newton(double* __restrict__ G, const double* __restrict__ w_prev, const double* __restrict__ psc, int nchunk,
+k_adj_newton(double* __restrict__ G, const double* __restrict__ w_prev, int64_t w_stride, const double* __restrict__ psc,
+             int nchunk,
              const double* __restrict__ Yk, const double* __restrict__ tscal_k, int ns, FSpec f, double dt,
              int newton_iters, int M, const double* __restrict__ u_bar, double* __restrict__ cbar,
              double* __restrict__ adj, int init, int terminal, uint32_t* __restrict__ status) {
@@ -40,7 +40,7 @@ k_adj_newton(double* __restrict__ G, const double* __restrict__ w_prev, const do
         double tau = 0.0;
         for (int c = 0; c < nchunk; ++c) tau += psc[((int64_t)p * nchunk + c) * 4];
         const double corr = a[A_ABAR] - tau;
-        const double* wp = w_prev + (int64_t)p * M;
+        const double* wp = w_prev + (int64_t)p * w_stride;   // stride 0: weights shared by the points
         for (int j = threadIdx.x; j < M; j += blockDim.x) Gp[j] += wp[j] * corr;
     }
     __syncthreads();
@@ -93,7 +93,7 @@ k_adj_advance(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nch
     CSum<R> acc[Q][4];
     for (int j = r0 + team; j < r1; j += G::TPW) {
         S* row = W + ((int64_t)p * M + j) * ldw;
-        const R cb = (R)cbar[(int64_t)p * M + j];
+        const R cb = cbar ? (R)cbar[(int64_t)p * M + j] : (R)0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int g = L + q * G::TL;
@@ -119,7 +119,7 @@ k_adj_advance(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nch
             }
         }
     }
-    block_columns_out<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
+    if (part) block_columns_out<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
 }
 
 // alpha_xbar = s sum_m cbar_m W^m_k + s Zbar - alphabar s Wbar, then CG on A bbar = alpha_xbar from 0.

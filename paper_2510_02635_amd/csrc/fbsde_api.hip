@@ -274,7 +274,7 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     for (int k = 0; k < (int)pl.N; ++k) {
         const double lam = pb->ridge_rel * s2 * (double)(k + 1) * dt;
         hipLaunchKernelGGL(k_adj_newton, dim3((unsigned)P), dim3(256), 0, st, ws.G,
-                           k > 0 ? ws.tw + (size_t)(k - 1) * PM : nullptr, ws.psc, pl.nchunk,
+                           k > 0 ? ws.tw + (size_t)(k - 1) * PM : nullptr, (int64_t)pl.M, ws.psc, pl.nchunk,
                            k > 0 ? ws.tY + (size_t)k * PM : nullptr, ws.tscal + (size_t)k * P * NS, NS, fs, dt,
                            pb->newton_iters, (int)pl.M, u_bar, ws.cbar, ws.adj, k == 0 ? 1 : 0, 0, status);
         dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
@@ -310,7 +310,7 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
         if ((err = last_error())) return err;
     }
     hipLaunchKernelGGL(k_adj_newton, dim3((unsigned)P), dim3(256), 0, st, ws.G, ws.tw + (size_t)(pl.N - 1) * PM,
-                       ws.psc, pl.nchunk, nullptr, ws.tscal, NS, fs, dt, pb->newton_iters, (int)pl.M, u_bar, ws.cbar,
+                       (int64_t)pl.M, ws.psc, pl.nchunk, nullptr, ws.tscal, NS, fs, dt, pb->newton_iters, (int)pl.M, u_bar, ws.cbar,
                        ws.adj, 0, 1, status);
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
@@ -363,6 +363,34 @@ void shared_reverse(const fbsde_problem* pb, const Plan& pl1, int k, S* W, const
     });
 }
 
+template <typename S>
+void shared_advance(const fbsde_problem* pb, const Plan& pl1, int k, S* W, hipStream_t st) {
+    const Keys ky = keys_of(pb);
+    const double dt = pb->T / (double)pb->N;
+    dispatch<S>(pl1.Q, pl1.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_adj_advance<S, QQ, TT>), dim3(pl1.nchunk, 1), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                           (int64_t)pl1.ld, (int)pl1.M, pl1.rows_per_chunk, pl1.nchunk, (int)pl1.d, pl1.ld, k,
+                           k == 0 ? 1 : 0, std::sqrt(dt), nullptr, ky.k0, ky.k1, 0xFFFFFFFFu, nullptr);
+    });
+}
+
+void adj_newton(const fbsde_problem* pb, int64_t P, double* G, const double* w_prev, int64_t w_stride,
+                const double* psc, int nchunk, const double* Yk, const double* tscal_k, const double* u_bar,
+                double* cbar, double* adj, int init, int terminal, uint32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_newton, dim3((unsigned)P), dim3(256), 0, st, G, w_prev, w_stride, psc, nchunk, Yk,
+                       tscal_k, NS, fspec_of(pb), pb->T / (double)pb->N, pb->newton_iters, (int)pb->M, u_bar, cbar,
+                       adj, init, terminal, status);
+}
+
+void adj_params(const double* adj, int64_t P, double* gp_bar, double* fp_bar, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(64), 0, st, adj, P, gp_bar, fp_bar);
+}
+
+int tape_tag_of(const fbsde_problem* pb, int64_t P) { return tape_tag(pb, P); }
+
+template void shared_advance<double>(const fbsde_problem*, const Plan&, int, double*, hipStream_t);
+template void shared_advance<float>(const fbsde_problem*, const Plan&, int, float*, hipStream_t);
 template void shared_forward<double>(const fbsde_problem*, const Plan&, double*, double*, double*, uint32_t*,
                                      hipStream_t);
 template void shared_forward<float>(const fbsde_problem*, const Plan&, float*, double*, double*, uint32_t*,
@@ -391,8 +419,7 @@ int fbsde_workspace_size(const fbsde_problem* pb, int64_t P, int32_t flags, size
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (pb->shared_dw) {
-        if (flags & FBSDE_WS_TAPE) return FBSDE_EINVAL;   // the shared form has no adjoint tape yet
-        *bytes = shared_workspace_bytes(pb, P);
+        *bytes = shared_workspace_bytes(pb, P, flags);
         return FBSDE_OK;
     }
     WS ws;
@@ -458,10 +485,9 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
-        if (flags & FBSDE_WS_TAPE) return FBSDE_EINVAL;
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solve
-        return solve_shared(pb, P, x0, u, grad, status, wsp, ws_bytes, (hipStream_t)stream);
+        return solve_shared(pb, P, x0, u, grad, status, wsp, ws_bytes, flags, (hipStream_t)stream);
     }
     WS ws;
     if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
@@ -478,10 +504,14 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
                          int32_t* cg_iters_out, fbsde_stream stream) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
-    if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!x0 || !u_bar || !x0_bar || !gp_bar || !fp_bar || !status || !wsp) return FBSDE_EINVAL;
+    if (pb->shared_dw) {
+        if (cg_iters_out)
+            for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solves
+        return backward_shared(pb, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, wsp, ws_bytes, (hipStream_t)stream);
+    }
     WS ws;
     if (carve(pl, P, FBSDE_WS_TAPE, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, FBSDE_WS_TAPE, (char*)wsp, ws);

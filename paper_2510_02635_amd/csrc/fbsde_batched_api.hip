@@ -128,7 +128,6 @@ int plan_tiles(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const
         if (rc) return rc;
         if (P[i] < 0) return FBSDE_EINVAL;
         if (P[i] == 0) continue;
-        if ((flags & FBSDE_WS_TAPE) && pbs[i].shared_dw) return FBSDE_EINVAL;
         auto ws_of = [&](int64_t np, size_t& b) { return fbsde_workspace_size(&pbs[i], np, flags, &b); };
         int64_t lo = 1, hi = std::min<int64_t>(P[i], 65535);
         size_t b = 0;

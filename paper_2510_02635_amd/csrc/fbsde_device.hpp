@@ -182,6 +182,10 @@ __device__ __forceinline__ double block_min(double v, double* lds) {
 // ------------------------------------------------------------------ f, g, Newton
 enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2 };
 enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3 };
+
+// Per-point FP64 slots of the reverse mode: alphabar, row-pass sum, Zbar coefficient, Wbar.bbar,
+// f-parameter sums [4], g-parameter sums [4], terminal sum of 2h'G, terminal sum of G.
+enum { A_ABAR = 0, A_TAU = 1, A_ZC = 2, A_WB = 3, A_FP = 4, A_GP = 8, A_S1 = 12, A_SG = 13, A_NS = 16 };
 enum { ST_CG_MAXIT = 1, ST_NEWTON_FLAT = 2, ST_NONFINITE = 4 };
 
 struct FSpec { int kind; double p0, p1; };

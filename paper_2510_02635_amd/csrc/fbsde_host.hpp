@@ -107,9 +107,20 @@ inline int last_error() { return (hipGetLastError() == hipSuccess) ? FBSDE_OK : 
 
 
 // Entry points of the other translation units.
-size_t shared_workspace_bytes(const fbsde_problem* pb, int64_t P);
+size_t shared_workspace_bytes(const fbsde_problem* pb, int64_t P, int32_t flags);
 int solve_shared(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
-                 void* ws, size_t ws_bytes, hipStream_t st);
+                 void* ws, size_t ws_bytes, int32_t flags, hipStream_t st);
+int backward_shared(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
+                    double* gp_bar, double* fp_bar, uint32_t* status, void* ws, size_t ws_bytes, hipStream_t st);
+// Newton adjoint of a level and the parameter sums (core translation unit owns these kernels).
+void adj_newton(const fbsde_problem* pb, int64_t P, double* G, const double* w_prev, int64_t w_stride,
+                const double* psc, int nchunk, const double* Yk, const double* tscal_k, const double* u_bar,
+                double* cbar, double* adj, int init, int terminal, uint32_t* status, hipStream_t st);
+void adj_params(const double* adj, int64_t P, double* gp_bar, double* fp_bar, hipStream_t st);
+int tape_tag_of(const fbsde_problem* pb, int64_t P);
+// W_{k+1} = W_k + sqrt(dt) xi_k on a single shared cloud (k = 0: from W_0 = 0).
+template <typename S>
+void shared_advance(const fbsde_problem* pb, const Plan& pl1, int k, S* W, hipStream_t st);
 // Forward sweep / reversal of a single shared cloud (core translation unit owns these kernels).
 template <typename S>
 void shared_forward(const fbsde_problem* pb, const Plan& pl1, S* W, double* Yscratch, double* rn2, uint32_t* status,

@@ -24,10 +24,12 @@ struct EpiTerminal {
     double s, ga, gb;
     int g_kind, M, d;
     uint32_t* status;
+    double* q_tape;   // [P][M] |X|^2 for the adjoint, or null
     __device__ __forceinline__ void operator()(int p, int j, double v) const {
         const double q = xc2[p] + 2.0 * s * v + s * s * rn2[j];
         const double y = g_of(g_kind, ga, gb, q, d);
         Y[(int64_t)p * M + j] = y;
+        if (q_tape) q_tape[(int64_t)p * M + j] = q;
         if (!isfinite(y)) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
     }
 };
@@ -203,6 +205,146 @@ k_sh_outputs(const T* __restrict__ ax, int ld, int d, const double* __restrict__
     if (grad)
         for (int i = threadIdx.x; i < d; i += blockDim.x) grad[(int64_t)p * d + i] = (double)ax[(int64_t)p * ld + i] / Fp;
     if (st && threadIdx.x == 0) atomicOr(&status[p], st);
+}
+
+// ------------------------------------------------------------------ reverse mode of the shared form
+// Per level k (walked from k = 0 upwards, the shared cloud regenerated forward in time), with G the
+// adjoint of Y_k and cbar = G / F' from the Newton adjoint:
+//   alpha_xbar[p] = s sum_m cbar[p][m] W^m_k + s^2 zc_p alpha_x[p] - alphabar_p s Wbar      (GEMM, epilogue)
+//   the ridge solve alpha_x = A^{-1} b, A = lam I + s^2 Dt^T Dt symmetric and independent of Y, enters
+//   only through sqrt(w_j) D'_j . bbar = s [A^{-1}-free form]:
+//     dual   (M <= d): V = (alpha_xbar Dt^T) K^{-1},  K = lam I + s^2 Dt Dt^T   (push-through identity)
+//     primal (M >  d): V = (alpha_xbar A^{-1}) Dt^T
+//   G_{k+1}[p][j] = s sqrt(w_j) V[p][j] + w_j (alphabar_p - s sum_i sqrt(w_i) V[p][i])
+// The dual form never forms bbar itself, whose component in the ridge-only null space of the design
+// is scaled by 1/lam.
+
+// alpha_xbar from the GEMM value v = sum_m cbar[p][m] W^m_k (element type T).
+template <typename T>
+struct EpiAxbar {
+    T* out;
+    const T* ax;
+    const double* Wbar;
+    const double* adj;
+    int ld;
+    double s;
+    __device__ __forceinline__ void operator()(int p, int i, double v) const {
+        const double* a = adj + (int64_t)p * A_NS;
+        const double r = s * v + s * s * a[A_ZC] * (double)ax[(int64_t)p * ld + i] - a[A_ABAR] * s * Wbar[i];
+        out[(int64_t)p * ld + i] = (T)r;
+    }
+};
+
+// The same at k = 0, where the cloud is W_0 = 0 and the GEMM term vanishes.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sha_axbar0(T* __restrict__ out, const T* __restrict__ ax, const double* __restrict__ Wbar,
+             const double* __restrict__ adj, int ld, double s) {
+    const int p = blockIdx.x;
+    const double* a = adj + (int64_t)p * A_NS;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x)
+        out[(int64_t)p * ld + i] =
+            (T)(s * s * a[A_ZC] * (double)ax[(int64_t)p * ld + i] - a[A_ABAR] * s * Wbar[i]);
+}
+
+// FP64 [P][M] -> element type.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sha_to_elem(const double* __restrict__ a, int64_t n, T* __restrict__ b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (T)a[i];
+}
+
+// Dt_j = sqrt(w_j) (W_j - Wbar) from the taped weights and mean (all ld columns; the pad stays 0).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sha_dtilde(const T* __restrict__ W, int ld, int M, const double* __restrict__ Wbar,
+             const double* __restrict__ sqw, T* __restrict__ Dt) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= ld) return;
+    const double wb = Wbar[i];
+    const int rows = (M + gridDim.y - 1) / gridDim.y;
+    const int r0 = blockIdx.y * rows, r1 = min(M, r0 + rows);
+    for (int j = r0; j < r1; ++j) Dt[(int64_t)j * ld + i] = (T)(sqw[j] * ((double)W[(int64_t)j * ld + i] - wb));
+}
+
+// G[p][j] = s sqrt(w_j) V[p][j] (the part before the mean-response term) and tau_p = sum_j of it,
+// stored as the per-point row-pass sum that the next Newton adjoint completes G with.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sha_G(const T* __restrict__ V, int M, const double* __restrict__ sqw, double s, double* __restrict__ G,
+        double* __restrict__ psc) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double tau = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double g = s * sqw[j] * (double)V[(int64_t)p * M + j];
+        G[(int64_t)p * M + j] = g;
+        tau += g;
+    }
+    tau = block_sum(tau, lds);
+    if (threadIdx.x == 0) psc[(int64_t)p * 4] = tau;
+}
+
+// Terminal adjoint, per point: phi_j = 2 h'(|X_j|^2) G_j (element type, for the x0bar GEMM) and the
+// sums sum_j phi_j, sum_j G_j dg/dgp0, sum_j G_j dg/dgp1, sum_j G_j (affine g: only the last two).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sha_terminal(const double* __restrict__ G, const double* __restrict__ qt, int M, int d, int g_kind, double ga,
+               T* __restrict__ phi, double* __restrict__ adj) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double s1 = 0.0, g0 = 0.0, g1 = 0.0, sg = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double gj = G[(int64_t)p * M + j];
+        double hp = 0.0, d0 = 0.0, d1 = 0.0;
+        if (g_kind == G_AFFINE) {
+            d0 = 1.0;
+        } else {
+            const double q = qt[(int64_t)p * M + j];
+            if (g_kind == G_QUAD) { hp = ga / (double)d; d0 = q / (double)d; d1 = 1.0; }
+            else if (g_kind == G_AC) { const double den = 2.0 + ga * q; hp = -ga / (den * den); d0 = -q / (den * den); }
+            else { const double den = 1.0 + ga * q; hp = ga / den; d0 = q / den; }
+        }
+        const double ph = 2.0 * hp * gj;
+        if (phi) phi[(int64_t)p * M + j] = (T)ph;
+        s1 += ph; g0 += gj * d0; g1 += gj * d1; sg += gj;
+    }
+    s1 = block_sum(s1, lds);
+    g0 = block_sum(g0, lds);
+    g1 = block_sum(g1, lds);
+    sg = block_sum(sg, lds);
+    if (threadIdx.x == 0) {
+        double* a = adj + (int64_t)p * A_NS;
+        a[A_S1] = s1;
+        a[A_GP + 0] = g0;
+        a[A_GP + 1] = g1;
+        a[A_SG] = sg;
+    }
+}
+
+// x0bar[p][i] = S1_p xc_p[i] + s v  (v = sum_j phi_pj W^j_N), xc = x0 + mu T; columns i < d.
+struct EpiX0bar {
+    double* x0bar;
+    const double* x0;
+    const double* mu;
+    const double* adj;
+    int d;
+    double s, T;
+    __device__ __forceinline__ void operator()(int p, int i, double v) const {
+        if (i >= d) return;
+        const double xc = x0[(int64_t)p * d + i] + (mu ? mu[i] * T : 0.0);
+        x0bar[(int64_t)p * d + i] = adj[(int64_t)p * A_NS + A_S1] * xc + s * v;
+    }
+};
+
+// Affine g: x0bar[p] = (sum_j G_j) gvec.
+__global__ void __launch_bounds__(256)
+k_sha_x0bar_affine(const double* __restrict__ gvec, int d, const double* __restrict__ adj,
+                   double* __restrict__ x0bar) {
+    const int p = blockIdx.x;
+    const double sg = adj[(int64_t)p * A_NS + A_SG];
+    for (int i = threadIdx.x; i < d; i += blockDim.x) x0bar[(int64_t)p * d + i] = sg * gvec[i];
 }
 
 }  // namespace fbsde

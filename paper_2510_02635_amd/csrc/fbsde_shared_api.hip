@@ -13,22 +13,32 @@ struct SWS {
     void *W, *Dt, *K, *R, *ax, *xc, *DtT;
     double *Wbar, *wpart, *w, *sqw, *rn2, *Ya, *Yb, *scal, *xc2, *ysc;
     int* info;
+    // tape for the reverse mode, per level k (cloud t_{k+1}): Y_k [P][M], alpha_x [P][ld], the
+    // Cholesky factor, w and sqrt(w) [M], Wbar [ld], the point scalars; |X_N|^2 [P][M]
+    bool tape = false;
+    double *tY, *tw, *tsqw, *tWbar, *tscal, *tq;
+    void *tax, *tK;
+    int* tag;
+    // reverse-mode work
+    double *G, *cbar, *adj, *psc;
+    size_t kn;
 };
 constexpr int SH_RCH = 64;   // row chunks of the two-stage weighted mean
 
-size_t carve_shared(const Plan& pl, int64_t P, char* base, SWS& ws) {
+size_t carve_shared(const Plan& pl, int64_t P, int32_t flags, char* base, SWS& ws) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
         char* p = base ? base + off : nullptr;
         off += round_up((int64_t)bytes, 256);
         return p;
     };
-    const size_t M = pl.M, ld = pl.ld, e = pl.esz;
+    const size_t M = pl.M, ld = pl.ld, e = pl.esz, N = pl.N;
     ws.W = take(M * ld * e);
     ws.Dt = take(M * ld * e);
     // dual form (M <= d): K is M x M; primal form (M > d): K is ld x ld, Dt^T [ld][M] is needed
     const bool primal = pl.M > pl.d;
     const size_t kn = primal ? ld : M;
+    ws.kn = kn;
     ws.K = take(kn * kn * e);
     ws.DtT = primal ? take(ld * M * e) : nullptr;
     ws.R = take((size_t)P * M * e);
@@ -45,6 +55,22 @@ size_t carve_shared(const Plan& pl, int64_t P, char* base, SWS& ws) {
     ws.xc2 = (double*)take((size_t)P * 8);
     ws.ysc = (double*)take(M * 8);
     ws.info = (int*)take(64);
+    ws.tape = (flags & FBSDE_WS_TAPE) != 0;
+    if (ws.tape) {
+        ws.tY = (double*)take(N * P * M * 8);
+        ws.tax = take(N * P * ld * e);
+        ws.tK = take(N * kn * kn * e);
+        ws.tw = (double*)take(N * M * 8);
+        ws.tsqw = (double*)take(N * M * 8);
+        ws.tWbar = (double*)take(N * ld * 8);
+        ws.tscal = (double*)take(N * P * NS * 8);
+        ws.tq = (double*)take((size_t)P * M * 8);
+        ws.tag = (int*)take(64);
+        ws.G = (double*)take((size_t)P * M * 8);
+        ws.cbar = (double*)take((size_t)P * M * 8);
+        ws.adj = (double*)take((size_t)P * A_NS * 8);
+        ws.psc = (double*)take((size_t)P * 4 * 8);
+    }
     return off;
 }
 
@@ -60,9 +86,7 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
                       double* u, double* grad, uint32_t* status, SWS& ws, hipStream_t st) {
     T* W = (T*)ws.W;
     T* Dt = (T*)ws.Dt;
-    T* K = (T*)ws.K;
     T* R = (T*)ws.R;
-    T* ax = (T*)ws.ax;
     T* xc = (T*)ws.xc;
     const int M = (int)pl.M, ld = pl.ld, d = (int)pl.d, Pi = (int)P;
     const double dt = pb->T / (double)pb->N, s = pb->s, s2 = s * s;
@@ -80,7 +104,8 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
     } else {
         hipLaunchKernelGGL((k_sh_xc<T>), dim3((unsigned)P), dim3(256), 0, st, x0, pb->mu, d, ld, pb->T, xc, ws.xc2);
         gemm<T, true>(Pi, M, ld, xc, ld, W, ld,
-                      EpiTerminal{Ycur, ws.xc2, ws.rn2, s, pb->gp[0], pb->gp[1], pb->g_kind, M, d, status}, st);
+                      EpiTerminal{Ycur, ws.xc2, ws.rn2, s, pb->gp[0], pb->gp[1], pb->g_kind, M, d, status,
+                                  ws.tape ? ws.tq : nullptr}, st);
     }
     int err = last_error();
     if (err) return err;
@@ -91,12 +116,19 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
         const double t_next = (double)(k + 1) * dt;
         const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)d : 0.0;
         const double lam = pb->ridge_rel * s2 * t_next;
-        hipLaunchKernelGGL(k_sh_weights, dim3(1), dim3(256), 0, st, ws.rn2, M, s2, eps2, ws.w, ws.sqw);
-        hipLaunchKernelGGL((k_sh_rhs<T>), dim3((unsigned)P), dim3(256), 0, st, Ycur, ws.w, ws.sqw, M, R, ws.scal, NS);
+        // with the tape, the level's weights, mean, factor, slope and scalars are written in place
+        double* w = ws.tape ? ws.tw + (size_t)k * M : ws.w;
+        double* sqw = ws.tape ? ws.tsqw + (size_t)k * M : ws.sqw;
+        double* Wbar = ws.tape ? ws.tWbar + (size_t)k * ld : ws.Wbar;
+        double* scal = ws.tape ? ws.tscal + (size_t)k * P * NS : ws.scal;
+        T* K = ws.tape ? (T*)ws.tK + (size_t)k * ws.kn * ws.kn : (T*)ws.K;
+        T* ax = ws.tape ? (T*)ws.tax + (size_t)k * P * ld : (T*)ws.ax;
+        hipLaunchKernelGGL(k_sh_weights, dim3(1), dim3(256), 0, st, ws.rn2, M, s2, eps2, w, sqw);
+        hipLaunchKernelGGL((k_sh_rhs<T>), dim3((unsigned)P), dim3(256), 0, st, Ycur, w, sqw, M, R, scal, NS);
         hipLaunchKernelGGL((k_sh_colsum<T>), dim3(cblocks, (unsigned)((M + rpc - 1) / rpc)), dim3(256), 0, st, W, ld,
-                           M, rpc, ws.w, ws.wpart);
+                           M, rpc, w, ws.wpart);
         hipLaunchKernelGGL((k_sh_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, ws.wpart,
-                           (M + rpc - 1) / rpc, ws.sqw, ws.Wbar, Dt);
+                           (M + rpc - 1) / rpc, sqw, Wbar, Dt);
         if (pl.M <= pl.d) {
             // dual: alpha_x[p] = s F[p] Dt with F = R (lam I + s^2 Dt Dt^T)^{-1}
             gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiStore<T>{K, (int64_t)M, s2, 0.0, lam}, st, 1);
@@ -114,20 +146,87 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
             gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
             cholesky_solve_rows<T>(K, ld, ld, ax, ld, Pi, st);
         }
-        hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, ws.Wbar, s, ws.scal, NS);
+        hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, Wbar, s, scal, NS);
         if (k > 0) {
             // reverse the shared cloud to t_k (its Newton output goes to scratch) and |W_k|^2
-            shared_reverse<T>(pb, pl1, k, W, ws.Wbar, ws.scal, ws.ysc, ws.rn2, status, st);
-            gemm<T, true>(Pi, M, ld, ax, ld, W, ld, EpiNewton{Yk, ws.scal, NS, M, pb->newton_iters, fs, s, dt, status},
+            shared_reverse<T>(pb, pl1, k, W, Wbar, scal, ws.ysc, ws.rn2, status, st);
+            double* Yout = ws.tape ? ws.tY + (size_t)k * P * M : Yk;
+            gemm<T, true>(Pi, M, ld, ax, ld, W, ld, EpiNewton{Yout, scal, NS, M, pb->newton_iters, fs, s, dt, status},
                           st);
-            std::swap(Ycur, Yk);
+            if (ws.tape) Ycur = Yout;
+            else std::swap(Ycur, Yk);
         } else {
-            hipLaunchKernelGGL((k_sh_outputs<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, d, ws.scal, NS, fs, dt,
+            hipLaunchKernelGGL((k_sh_outputs<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, d, scal, NS, fs, dt,
                                pb->newton_iters, u, grad, status);
         }
         if ((err = last_error())) return err;
     }
+    if (ws.tape) set_int(ws.tag, tape_tag_of(pb, P), st);
     hipLaunchKernelGGL(k_info_to_status, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, ws.info, status, P);
+    return last_error();
+}
+
+// Reverse mode of solve_shared_impl for L = sum_p ubar_p u_p (see fbsde_shared.hpp): the cloud is
+// regenerated forward in time from W_0 = 0, every level reads its taped weights, mean, factor, slope
+// and Y_k, and the contractions with the cloud are MFMA GEMMs.
+template <typename T>
+int backward_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, int64_t P, const double* x0,
+                         const double* u_bar, double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status,
+                         SWS& ws, hipStream_t st) {
+    T* W = (T*)ws.W;
+    T* Dt = (T*)ws.Dt;
+    T* V = (T*)ws.R;       // [P][M]: cbar, then the ridge adjoint, then 2h'G at the terminal
+    T* axbar = (T*)ws.xc;  // [P][ld]
+    const int M = (int)pl.M, ld = pl.ld, d = (int)pl.d, Pi = (int)P;
+    const double s = pb->s;
+    const unsigned cblocks = (unsigned)((ld + 255) / 256);
+    const bool dual = pl.M <= pl.d;
+    int err;
+    for (int k = 0; k < (int)pl.N; ++k) {
+        const double* tw_prev = k > 0 ? ws.tw + (size_t)(k - 1) * M : nullptr;
+        const double* tscal_k = ws.tscal + (size_t)k * P * NS;
+        const T* tax_k = (const T*)ws.tax + (size_t)k * P * ld;
+        const double* tWbar_k = ws.tWbar + (size_t)k * ld;
+        const T* tK_k = (const T*)ws.tK + (size_t)k * ws.kn * ws.kn;
+        adj_newton(pb, P, ws.G, tw_prev, 0, ws.psc, 1, k > 0 ? ws.tY + (size_t)k * P * M : nullptr, tscal_k, u_bar,
+                   ws.cbar, ws.adj, k == 0 ? 1 : 0, 0, status, st);
+        // alpha_xbar: the cloud term needs W_k before it is advanced
+        if (k == 0) {
+            hipLaunchKernelGGL((k_sha_axbar0<T>), dim3((unsigned)P), dim3(256), 0, st, axbar, tax_k, tWbar_k, ws.adj,
+                               ld, s);
+        } else {
+            const int64_t n = P * (int64_t)M;
+            hipLaunchKernelGGL((k_sha_to_elem<T>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
+                               0, st, ws.cbar, n, V);
+            gemm<T, false>(Pi, ld, M, V, M, W, ld, EpiAxbar<T>{axbar, tax_k, tWbar_k, ws.adj, ld, s}, st);
+        }
+        shared_advance<T>(pb, pl1, k, W, st);
+        hipLaunchKernelGGL((k_sha_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, tWbar_k,
+                           ws.tsqw + (size_t)k * M, Dt);
+        if (dual) {
+            gemm<T, true>(Pi, M, ld, axbar, ld, Dt, ld, EpiStore<T>{V, (int64_t)M, 1.0, 0.0, 0.0}, st);
+            cholesky_solve_rows<T>(tK_k, M, M, V, M, Pi, st);
+        } else {
+            cholesky_solve_rows<T>(tK_k, ld, ld, axbar, ld, Pi, st);
+            gemm<T, true>(Pi, M, ld, axbar, ld, Dt, ld, EpiStore<T>{V, (int64_t)M, 1.0, 0.0, 0.0}, st);
+        }
+        hipLaunchKernelGGL((k_sha_G<T>), dim3((unsigned)P), dim3(256), 0, st, V, M, ws.tsqw + (size_t)k * M, s, ws.G,
+                           ws.psc);
+        if ((err = last_error())) return err;
+    }
+    // G_N, then the terminal condition on the cloud at t_N (W now holds W_N)
+    adj_newton(pb, P, ws.G, ws.tw + (size_t)(pl.N - 1) * M, 0, ws.psc, 1, nullptr, ws.tscal, u_bar, ws.cbar, ws.adj,
+               0, 1, status, st);
+    if (pb->g_kind == FBSDE_G_AFFINE) {
+        hipLaunchKernelGGL((k_sha_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, ws.G, nullptr, M, d, pb->g_kind,
+                           pb->gp[0], nullptr, ws.adj);
+        hipLaunchKernelGGL(k_sha_x0bar_affine, dim3((unsigned)P), dim3(256), 0, st, pb->gvec, d, ws.adj, x0_bar);
+    } else {
+        hipLaunchKernelGGL((k_sha_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, ws.G, ws.tq, M, d, pb->g_kind,
+                           pb->gp[0], V, ws.adj);
+        gemm<T, false>(Pi, ld, M, V, M, W, ld, EpiX0bar{x0_bar, x0, pb->mu, ws.adj, d, s, pb->T}, st);
+    }
+    adj_params(ws.adj, P, gp_bar, fp_bar, st);
     return last_error();
 }
 
@@ -136,24 +235,43 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
 namespace fbsde {
 namespace host {
 
-size_t shared_workspace_bytes(const fbsde_problem* pb, int64_t P) {
+size_t shared_workspace_bytes(const fbsde_problem* pb, int64_t P, int32_t flags) {
     Plan pl;
     if (make_plan(pb, P, pl)) return 0;
     SWS sws;
-    return carve_shared(pl, P, nullptr, sws);
+    return carve_shared(pl, P, flags, nullptr, sws);
 }
 
 int solve_shared(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
-                 void* wsp, size_t ws_bytes, hipStream_t st) {
+                 void* wsp, size_t ws_bytes, int32_t flags, hipStream_t st) {
     Plan pl, pl1;
     int rc;
     if ((rc = make_plan(pb, P, pl)) || (rc = make_plan(pb, 1, pl1))) return rc;
     SWS sws;
-    if (carve_shared(pl, P, nullptr, sws) > ws_bytes) return FBSDE_ENOSPC;
-    carve_shared(pl, P, (char*)wsp, sws);
+    if (carve_shared(pl, P, flags, nullptr, sws) > ws_bytes) return FBSDE_ENOSPC;
+    carve_shared(pl, P, flags, (char*)wsp, sws);
     if (P == 0) return FBSDE_OK;
     if (pb->prec == FBSDE_F64) return solve_shared_impl<double>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
     return solve_shared_impl<float>(pb, pl, pl1, P, x0, u, grad, status, sws, st);
+}
+
+int backward_shared(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
+                    double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes, hipStream_t st) {
+    Plan pl, pl1;
+    int rc;
+    if ((rc = make_plan(pb, P, pl)) || (rc = make_plan(pb, 1, pl1))) return rc;
+    SWS sws;
+    if (carve_shared(pl, P, FBSDE_WS_TAPE, nullptr, sws) > ws_bytes) return FBSDE_ENOSPC;
+    carve_shared(pl, P, FBSDE_WS_TAPE, (char*)wsp, sws);
+    if (P == 0) return FBSDE_OK;
+    int tag = 0;
+    if (hipMemcpyAsync(&tag, sws.tag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return FBSDE_EHIP;
+    if (tag != tape_tag_of(pb, P)) return FBSDE_ESTATE;
+    if (pb->prec == FBSDE_F64)
+        return backward_shared_impl<double>(pb, pl, pl1, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, sws, st);
+    return backward_shared_impl<float>(pb, pl, pl1, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, sws, st);
 }
 
 }  // namespace host

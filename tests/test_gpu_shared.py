@@ -125,3 +125,87 @@ def test_shared_affine_closed_form():
     for p in range(7):
         assert abs(u[p].item() - (a @ x0[p] + b) / fac) <= 1e-11 * max(1, abs((a @ x0[p] + b) / fac))
         assert rel_err(g[p].cpu().numpy(), a / fac) <= 1e-10
+
+
+def _shared_adjoint_case(kw, xkind, P, prec, tol, sample):
+    hp, op = problems(shared_dw=1, prec=prec, **kw)
+    x0 = workloads.points(xkind, P, kw["d"], 17)
+    ubar = np.linspace(0.5, 1.5, P)
+    _say(f"[shared-adjoint] d={kw['d']} M={kw['M']} N={kw['N']} P={P} prec={prec}")
+    xt = torch.tensor(x0, device=DEV)
+    ws = F.workspace(hp, P, tape=True)
+    u, g, st = F.solve(hp, xt, tape=True, ws=ws)
+    x0b, gpb, fpb, st2 = F.solve_backward(hp, xt, torch.tensor(ubar, device=DEV), ws)
+    torch.cuda.synchronize()
+    x0b = x0b.cpu().numpy()
+    gp_ref, fp_ref = np.zeros(4), np.zeros(4)
+    for p in range(P):
+        ref = OS.adjoint_point(op, x0[p], p, ubar=ubar[p])
+        gp_ref += ref["gpbar"]
+        fp_ref += ref["fpbar"]
+        if p in sample:
+            e = rel_err(x0b[p], ref["x0bar"])
+            _say(f"  p={p} rel_x0bar={e:.2e}")
+            assert e <= tol
+    for got, ref, name in ((gpb.cpu().numpy(), gp_ref, "gp"), (fpb.cpu().numpy(), fp_ref, "fp")):
+        for i in range(4):
+            if ref[i] != 0.0 or got[i] != 0.0:
+                err = abs(got[i] - ref[i]) / max(abs(ref[i]), 1e-300)
+                _say(f"  {name}[{i}] got={got[i]:.12g} ref={ref[i]:.12g} rel={err:.2e}")
+                assert err <= tol, (name, i)
+    assert np.all(st.cpu().numpy() == 0) and np.all(st2.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("name,kw,xkind,P", SHARED_CASES, ids=[c[0] for c in SHARED_CASES])
+def test_shared_adjoint_fp64_matches_oracle(name, kw, xkind, P):
+    _shared_adjoint_case(kw, xkind, P, F.F64, 1e-10, sample=[0, 1, P - 1])
+
+
+@pytest.mark.parametrize("name,kw,xkind,P", SHARED_CASES, ids=[c[0] for c in SHARED_CASES])
+def test_shared_adjoint_fp32c_matches_fp64_oracle(name, kw, xkind, P):
+    _shared_adjoint_case(kw, xkind, P, F.F32C, 1e-5, sample=[0, P - 1])
+
+
+def test_shared_adjoint_affine_closed_form():
+    """Affine g with f = c1 y: u(0, x) = (a.x + b) / (1 - c1 dt)^N exactly, so the adjoint of
+    sum_p ubar_p u_p is x0bar_p = ubar_p a / (1 - c1 dt)^N and gpbar_0 = sum_p ubar_p / (1 - c1 dt)^N."""
+    d, M, N, T, c1, b = 12, 60, 4, 0.5, 0.6, 0.3
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(d)
+    hp, _ = problems(gvec=a, shared_dw=1, d=d, M=M, N=N, T=T, s=1.2, f_kind=F.F_ALLEN_CAHN, fp=(c1, 0, 0, 0),
+                     g_kind=F.G_AFFINE, gp=(b, 0, 0, 0), ridge_rel=0.0)
+    P = 7
+    x0 = torch.tensor(rng.standard_normal((P, d)), device=DEV)
+    ubar = torch.linspace(1.0, 2.0, P, dtype=torch.float64, device=DEV)
+    _say("[shared affine adjoint]")
+    ws = F.workspace(hp, P, tape=True)
+    F.solve(hp, x0, tape=True, ws=ws)
+    x0b, gpb, fpb, st = F.solve_backward(hp, x0, ubar, ws)
+    torch.cuda.synchronize()
+    fac = (1 - c1 * T / N) ** N
+    for p in range(P):
+        assert rel_err(x0b[p].cpu().numpy(), ubar[p].item() * a / fac) <= 1e-10
+    assert abs(gpb[0].item() - ubar.sum().item() / fac) <= 1e-10 * abs(ubar.sum().item() / fac)
+
+
+def test_shared_adjoint_against_central_differences():
+    kw = dict(d=150, M=120, N=3, T=0.3, f_kind=F.F_HJB, fp=(0.7, 0, 0, 0), g_kind=F.G_HJB_LOG, gp=(1.0, 0, 0, 0))
+    hp, _ = problems(shared_dw=1, **kw)
+    P = 3
+    x0 = torch.tensor(workloads.points("uniform", P, 150, 3), device=DEV)
+    ubar = torch.ones(P, dtype=torch.float64, device=DEV)
+    _say("[shared adjoint] central differences")
+    ws = F.workspace(hp, P, tape=True)
+    F.solve(hp, x0, tape=True, ws=ws)
+    x0b, _, _, _ = F.solve_backward(hp, x0, ubar, ws)
+    torch.cuda.synchronize()
+    h = 1e-4
+    for p, i in [(0, 0), (1, 77), (2, 149)]:
+        xp, xm = x0.clone(), x0.clone()
+        xp[p, i] += h
+        xm[p, i] -= h
+        up, _, _ = F.solve(hp, xp)
+        um, _, _ = F.solve(hp, xm)
+        fd = (up.sum().item() - um.sum().item()) / (2 * h)
+        _say(f"  p={p} i={i} adjoint={x0b[p, i].item():.10g} fd={fd:.10g}")
+        assert abs(x0b[p, i].item() - fd) <= 1e-6 * max(1.0, abs(fd))

@@ -243,7 +243,27 @@ def main():
         tflops = 2.0 * Ps * Ms * ldp / (gemm_ms * 1e-3) / 1e12
         del A, B, C
         torch.cuda.empty_cache()
+        # forward with the tape + reverse mode of L = sum_p u_p (the C4 training-style step)
+        wsst = F.workspace(pbs, Ps, tape=True, device=dev)
+        ubs = torch.ones(Ps, dtype=torch.float64, device=dev)
+        F.solve(pbs, xs, tape=True, ws=wsst)
+        F.solve_backward(pbs, xs, ubs, wsst)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nfa = max(1, args.steps)
+        for _ in range(nfa):
+            F.solve(pbs, xs, tape=True, ws=wsst)
+            _, _, _, st_sa = F.solve_backward(pbs, xs, ubs, wsst)
+        torch.cuda.synchronize()
+        sec_sfa = (time.perf_counter() - t0) / nfa
+        log(f"[bench] shared fp32c fwd+adj: {sec_sfa * 1e3:.1f} ms")
+        tape_gib = wsst.numel() / 2**30
+        del wsst
+        torch.cuda.empty_cache()
         shared = {"value": round(Ps / sec_s, 2), "unit": "points/s", "ms_per_step": round(sec_s * 1e3, 3),
+                  "fwd_adj": {"value": round(Ps / sec_sfa, 2), "unit": "points/s", "ms_per_step": round(sec_sfa * 1e3, 3),
+                              "workspace_with_tape_GiB": round(tape_gib, 2),
+                              "status_nonzero_points": int((st_sa != 0).sum().item())},
                   "dtype": "fp32c (FP32 MFMA, FP64 Newton)",
                   "config": {"workload": "shared_allen_cahn_d10000_P4096_M2048_N20", "shared_increments": True},
                   "roofline": {"bound": "mfma", "kernel": "k_gemm<float, NT> [P x ld] x [M x ld]^T",

@@ -87,7 +87,9 @@ typedef struct fbsde_problem {
     int32_t cg_maxit;        /* CG iteration cap per level, >= 1                              */
     double cg_rtol;          /* CG stop: |r| <= cg_rtol |b|; FP32C with M <= d + 1 uses at     */
                              /* least 1e-7 (FP32 rounding in the ridge-only null space)        */
-    int32_t cg_fixed_iters;  /* > 0: run exactly this many CG launches per level, no polling  */
+    int32_t cg_fixed_iters;  /* > 0: this many CG launches per level, no host polling (a     */
+                             /* converged point's launches exit at once; a point still not   */
+                             /* converged after them is flagged FBSDE_ST_CG_MAXIT)             */
     int32_t shared_dw;       /* 1: the same increments for every evaluation point             */
     uint64_t seed;           /* Philox key                                                     */
     uint32_t instance;       /* PDE instance id, folded into the key                          */
@@ -238,6 +240,22 @@ int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const 
 size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P);
 int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr,
                          void* ws, size_t ws_bytes, int32_t* info, fbsde_stream stream);
+
+/* Captured solve, for callers that repeat one solve with the same problem, sizes and buffers
+ * (serving loops, parameter sweeps that rewrite x0 in place): the launch sequence of fbsde_solve
+ * (flags as there) is captured once into a HIP graph on a private stream that waits for `stream`,
+ * and fbsde_graph_launch replays it with a single launch.  The graph binds every pointer given here
+ * and in pb (mu, gvec): a replay reads x0 and writes u, grad, status and ws at these addresses, so
+ * they must stay allocated until fbsde_graph_destroy.  The per-point form needs cg_fixed_iters > 0
+ * (FBSDE_EINVAL otherwise: no host polling can run inside a graph); the shared form has no CG.
+ * Status words and flags are cleared by kernels, so no memset node enters the graph.  Nothing is
+ * launched by the capture itself. */
+typedef struct fbsde_graph_s* fbsde_graph;
+int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                        uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, fbsde_graph* out,
+                        fbsde_stream stream);
+int fbsde_graph_launch(fbsde_graph graph, fbsde_stream stream);
+int fbsde_graph_destroy(fbsde_graph graph);
 
 /* Human-readable text of a return code. */
 const char* fbsde_strerror(int code);

@@ -14,7 +14,8 @@ WS_TAPE = 1
 EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
             "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
-            "fbsde_solve_batched_backward", "fbsde_strerror")
+            "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
+            "fbsde_strerror")
 
 
 BATCH_TILED, BATCH_PERSISTENT = 0, 1
@@ -82,12 +83,16 @@ def load():
     lib.fbsde_batched_workspace_size.argtypes = [pb, i64, vp, vp, i32, P(sz)]
     lib.fbsde_solve_batched.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_solve_batched_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fbsde_graph_capture.argtypes = [pb, i64, vp, vp, vp, vp, vp, sz, i32, P(vp), vp]
+    lib.fbsde_graph_launch.argtypes = [vp, vp]
+    lib.fbsde_graph_destroy.argtypes = [vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
                  "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm",
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
-                 "fbsde_solve_batched_backward"):
+                 "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
+                 "fbsde_graph_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

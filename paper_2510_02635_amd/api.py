@@ -331,3 +331,45 @@ def solve_batched_backward(problems, x0s, u_bars, streams=4, tile_bytes=0, ws=No
                                                   _ptrs(us), _ptrs(xbs), _ptrs(gps), _ptrs(fps), _ptrs(sts),
                                                   ctypes.byref(opts), ws.data_ptr(), ws.numel(), _stream()))
     return us, xbs, gps, fps, sts
+
+
+class CapturedSolve:
+    """A solve captured once into a HIP graph (fbsde_graph_capture) and replayed with one launch.
+
+    The graph is bound to this object's tensors: write new points into `x0` in place, call `launch()`,
+    read `u`, `grad`, `status`.  The per-point form needs `pb.cg_fixed_iters > 0`.
+    """
+
+    def __init__(self, pb, x0, want_grad=True, tape=False):
+        P = x0.shape[0]
+        _dev_f64(x0, (P, pb.d))
+        dev = x0.device
+        self.pb = pb
+        self.x0 = x0
+        self.u = torch.empty(P, dtype=torch.float64, device=dev)
+        self.grad = torch.empty((P, pb.d), dtype=torch.float64, device=dev) if want_grad else None
+        self.status = torch.empty(P, dtype=torch.int32, device=dev)
+        self.ws = workspace(pb, P, tape=tape, device=dev)
+        self._c = pb.c()   # keeps mu / gvec referenced through pb
+        h = ctypes.c_void_p()
+        N.check(N.load().fbsde_graph_capture(ctypes.byref(self._c), P, x0.data_ptr(), self.u.data_ptr(),
+                                             _ptr(self.grad), self.status.data_ptr(), self.ws.data_ptr(),
+                                             self.ws.numel(), N.WS_TAPE if tape else 0, ctypes.byref(h), _stream()))
+        self._h = h
+
+    def launch(self):
+        if self._h is None:
+            raise RuntimeError("graph destroyed")
+        N.check(N.load().fbsde_graph_launch(self._h, _stream()))
+        return self.u, self.grad, self.status
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            N.check(N.load().fbsde_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -5,6 +5,7 @@
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
 
+#include <new>
 #include <vector>
 
 using namespace fbsde;
@@ -122,7 +123,7 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
         const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
         hipLaunchKernelGGL(k_cg_update, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, pl.ld,
                            pb->s, Wbar, ws.x, ws.r, ws.pv, ws.qv, ws.scal, NS, ws.iscal,
-                           cg_rtol_of(pb) * cg_rtol_of(pb), pb->cg_maxit, ws.active, status);
+                           cg_rtol_of(pb) * cg_rtol_of(pb), std::min(cap, pb->cg_maxit), ws.active, status);
         if (fixed <= 0 && (it + 1) % poll == 0) {
             int active = 0;
             if (hipMemcpyAsync(&active, ws.active, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -598,6 +599,68 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+struct fbsde_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                        uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, fbsde_graph* out,
+                        fbsde_stream stream) {
+    if (!out) return FBSDE_EINVAL;
+    *out = nullptr;
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    if (!pb->shared_dw && pb->cg_fixed_iters <= 0) return FBSDE_EINVAL;   // no host polling inside a graph
+    if (!x0 || !u || !status || !ws || P < 1) return FBSDE_EINVAL;
+    size_t need = 0;
+    if ((rc = fbsde_workspace_size(pb, P, flags, &need))) return rc;
+    if (need > ws_bytes) return FBSDE_ENOSPC;
+    // capture on a private stream that first waits for the caller's stream
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return FBSDE_EHIP;
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { hipStreamDestroy(cap); return FBSDE_EHIP; }
+    int err = FBSDE_OK;
+    if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess || hipStreamWaitEvent(cap, ev, 0) != hipSuccess)
+        err = FBSDE_EHIP;
+    hipGraph_t g = nullptr;
+    if (!err && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) err = FBSDE_EHIP;
+    if (!err) {
+        const int rs = fbsde_solve(pb, P, x0, u, grad, status, ws, ws_bytes, flags, nullptr, (fbsde_stream)cap);
+        const hipError_t he = hipStreamEndCapture(cap, &g);
+        err = rs ? rs : (he != hipSuccess ? FBSDE_EHIP : FBSDE_OK);
+    }
+    hipGraphExec_t exec = nullptr;
+    if (!err && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) err = FBSDE_EHIP;
+    hipEventDestroy(ev);
+    hipStreamDestroy(cap);
+    if (err) {
+        if (g) hipGraphDestroy(g);
+        return err;
+    }
+    fbsde_graph h = new (std::nothrow) fbsde_graph_s{g, exec};
+    if (!h) {
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(g);
+        return FBSDE_EINVAL;
+    }
+    *out = h;
+    return FBSDE_OK;
+}
+
+int fbsde_graph_launch(fbsde_graph g, fbsde_stream stream) {
+    if (!g) return FBSDE_EINVAL;
+    return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? FBSDE_OK : FBSDE_EHIP;
+}
+
+int fbsde_graph_destroy(fbsde_graph g) {
+    if (!g) return FBSDE_OK;
+    const bool ok = hipGraphExecDestroy(g->exec) == hipSuccess && hipGraphDestroy(g->graph) == hipSuccess;
+    delete g;
+    return ok ? FBSDE_OK : FBSDE_EHIP;
 }
 
 const char* fbsde_strerror(int code) {

@@ -30,6 +30,7 @@ def main():
     ap.add_argument("--workload", default="allen_cahn_d1000_P1024_M4096_N20", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a device copy of this many MiB")
+    ap.add_argument("--adjoint", action="store_true", help="solve with the tape, then the reverse mode of sum_p u_p")
     args = ap.parse_args()
     import torch
 
@@ -46,7 +47,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    u, g, st = F.solve(pb, x0)
+    if args.adjoint:
+        ws = F.workspace(pb, P, tape=True)
+        u, g, st = F.solve(pb, x0, tape=True, ws=ws)
+        F.solve_backward(pb, x0, torch.ones(P, dtype=torch.float64, device="cuda"), ws)
+    else:
+        u, g, st = F.solve(pb, x0)
     torch.cuda.synchronize()
     print(f"{args.workload} {args.prec}: u[0]={u[0].item():.12g} nonzero status={int((st != 0).sum())}", flush=True)
 

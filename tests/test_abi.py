@@ -63,3 +63,14 @@ def test_missing_gvec_and_tiny_workspace():
     rc = N.load().fbsde_solve(ctypes.byref(pb.c()), 1, ctypes.c_void_p(16), ctypes.c_void_p(16), None,
                               ctypes.c_void_p(16), ctypes.c_void_p(16), 8, 0, None, None)
     assert rc == N.ENOSPC
+
+
+def test_graph_capture_needs_fixed_cg_launches():
+    # the per-point form polls the host between CG launches unless cg_fixed_iters > 0: refused before any
+    # HIP call, so this runs without a GPU
+    pb = F.Problem(d=8, M=64, N=2, T=0.3)
+    h = ctypes.c_void_p()
+    rc = N.load().fbsde_graph_capture(ctypes.byref(pb.c()), 2, 1, 1, None, 1, 1, 1 << 30, 0, ctypes.byref(h), None)
+    assert rc == N.EINVAL and not h.value
+    assert N.load().fbsde_graph_launch(None, None) == N.EINVAL
+    assert N.load().fbsde_graph_destroy(None) == 0

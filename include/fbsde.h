@@ -162,8 +162,8 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
                          void* ws, size_t ws_bytes, int32_t* cg_iters_out, fbsde_stream stream);
 
 /* Diagnostic: the normals xi^j_k of point p (or the shared stream) for rows j0..j0+rows-1 of
- * level k, exactly as the kernels generate them.  out device [rows][d]; words device
- * [rows][ceil(d/4)][4] raw Philox output or NULL. */
+ * level k, exactly as the kernels generate them in pb->prec (FP32C: the FP32 values, written as
+ * doubles).  out device [rows][d]; words device [rows][ceil(d/4)][4] raw Philox output or NULL. */
 int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows,
                   double* out, uint32_t* words, fbsde_stream stream);
 
@@ -240,6 +240,28 @@ int fbsde_gemm(int32_t prec, int32_t nt, int64_t m, int64_t n, int64_t k, const 
 size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P);
 int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr,
                          void* ws, size_t ws_bytes, int32_t* info, fbsde_stream stream);
+
+/* Autotuner of the launch shape (spec extension: the tile and split choices are picked by
+ * measurement).  For this problem's precision, d, M and this P it times the fused CG product -- the
+ * kernel that dominates a solve -- over the candidate shapes: the split of a particle row over 1, 2
+ * or 4 times the default team width of wavefronts (fewer coordinates per lane) and the split of a
+ * point's particle rows over the default, half or a quarter of the default workgroups.  The timing
+ * runs on the forward sweep of the given points x0 (device [P][d]) in ws (fbsde_workspace_size(pb, P,
+ * 0) bytes, overwritten).  The fastest shape (a new one must win by 2 %) is recorded in a process-wide
+ * table that every later plan with the same (precision, d, M, P) uses -- fbsde_solve, _step, _backward,
+ * fbsde_time_kernel and the workspace sizes (never larger than before tuning).  This table is the
+ * library's only global state; fbsde_autotune_reset clears it.  Thread-safe; synchronises the stream. */
+typedef struct fbsde_tune_result {
+    int32_t team;            /* wavefronts per particle row                        */
+    int32_t q;               /* groups of four coordinates per lane                */
+    int32_t nchunk;          /* workgroups per point                               */
+    int32_t n_candidates;    /* shapes timed                                       */
+    float best_ms;           /* one launch of the CG product at the chosen shape   */
+    float default_ms;        /* the same at the default shape                      */
+} fbsde_tune_result;
+int fbsde_autotune(const fbsde_problem* pb, int64_t P, const double* x0, void* ws, size_t ws_bytes,
+                   fbsde_tune_result* out, fbsde_stream stream);
+int fbsde_autotune_reset(void);
 
 /* Captured solve, for callers that repeat one solve with the same problem, sizes and buffers
  * (serving loops, parameter sweeps that rewrite x0 in place): the launch sequence of fbsde_solve

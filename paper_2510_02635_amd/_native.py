@@ -15,7 +15,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
-            "fbsde_strerror")
+            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_strerror")
 
 
 BATCH_TILED, BATCH_PERSISTENT = 0, 1
@@ -24,6 +24,11 @@ BATCH_TILED, BATCH_PERSISTENT = 0, 1
 class CBatchOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("streams", ctypes.c_int32), ("tile_bytes", ctypes.c_int64),
                 ("max_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CTuneResult(ctypes.Structure):
+    _fields_ = [("team", ctypes.c_int32), ("q", ctypes.c_int32), ("nchunk", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
 
 
 class CProblem(ctypes.Structure):
@@ -86,13 +91,15 @@ def load():
     lib.fbsde_graph_capture.argtypes = [pb, i64, vp, vp, vp, vp, vp, sz, i32, P(vp), vp]
     lib.fbsde_graph_launch.argtypes = [vp, vp]
     lib.fbsde_graph_destroy.argtypes = [vp]
+    lib.fbsde_autotune.argtypes = [pb, i64, vp, vp, sz, P(CTuneResult), vp]
+    lib.fbsde_autotune_reset.argtypes = []
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
                  "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm",
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
-                 "fbsde_graph_destroy"):
+                 "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -373,3 +373,21 @@ class CapturedSolve:
             self.close()
         except Exception:
             pass
+
+
+def autotune(pb, x0, ws=None):
+    """Time the candidate launch shapes of the CG product for (precision, d, M, P = len(x0)) and record
+    the fastest for every later call with the same key (fbsde_autotune).  Returns the choice as a dict."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    if ws is None:
+        ws = workspace(pb, P, device=x0.device)
+    r = N.CTuneResult()
+    N.check(N.load().fbsde_autotune(ctypes.byref(pb.c()), P, x0.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    ctypes.byref(r), _stream()))
+    return dict(team=r.team, q=r.q, nchunk=r.nchunk, n_candidates=r.n_candidates, best_ms=r.best_ms,
+                default_ms=r.default_ms)
+
+
+def autotune_reset():
+    N.check(N.load().fbsde_autotune_reset())

@@ -5,11 +5,37 @@
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
 
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 using namespace fbsde;
 using namespace fbsde::host;
+
+namespace {
+
+// ------------------------------------------------------------------ autotuned launch shapes
+using TuneKey = std::tuple<int, int64_t, int64_t, int64_t>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+TuneKey tune_key(const fbsde_problem* pb, int64_t P) { return TuneKey{pb->prec, pb->d, pb->M, P}; }
+
+}  // namespace
+
+namespace fbsde {
+namespace host {
+bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(tune_key(pb, P));
+    if (it == g_tune.end()) return false;
+    team = it->second.first;
+    nchunk = it->second.second;
+    return true;
+}
+}  // namespace host
+}  // namespace fbsde
 
 namespace {
 
@@ -538,7 +564,11 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
     const uint32_t q = pb->shared_dw ? 0xFFFFFFFFu : pb->point_base + (uint32_t)p;
     const int64_t n = rows * ((pb->d + 3) / 4);
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_normals, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (int)pb->d, j0, rows, k, q, ky.k0,
+    if (pb->prec == FBSDE_F64)
+        hipLaunchKernelGGL(k_normals<double>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (int)pb->d, j0, rows, k, q, ky.k0,
+                       ky.k1, out, words);
+    else
+        hipLaunchKernelGGL(k_normals<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (int)pb->d, j0, rows, k, q, ky.k0,
                        ky.k1, out, words);
     return last_error();
 }
@@ -599,6 +629,103 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int fbsde_autotune(const fbsde_problem* pb, int64_t P, const double* x0, void* wsp, size_t ws_bytes,
+                   fbsde_tune_result* out, fbsde_stream stream) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    if (pb->shared_dw || P < 1 || !x0 || !wsp || !out) return FBSDE_EINVAL;   // the shared form has no CG
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.erase(tune_key(pb, P));
+    }
+    Plan p0;
+    if ((rc = make_plan(pb, P, p0))) return rc;
+    WS ws;
+    if (carve(p0, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(p0, P, 0, (char*)wsp, ws);
+    hipStream_t st = (hipStream_t)stream;
+    // a state to time on: the forward sweep of these points; zero weights, direction and scalars
+    // (the product's cost does not depend on the values), every point iterating
+    auto fill0 = [&](void* a, size_t bytes) {
+        const int64_t n = (int64_t)(bytes / 4);
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, st,
+                           (uint32_t*)a, n, 0u);
+    };
+    const int64_t PM = P * p0.M, PL = P * (int64_t)p0.ld;
+    auto sweep = [&](auto tag) {
+        using S = decltype(tag);
+        launch_forward<S>(pb, p0, P, x0, (S*)ws.W, p0.ld, ws.Ya, ws.rn2, (uint32_t*)ws.iscal, st);
+    };
+    if (pb->prec == FBSDE_F64) sweep(double{}); else sweep(float{});
+    fill0(ws.w, (size_t)PM * 8);
+    fill0(ws.pv, (size_t)PL * 8);
+    fill0(ws.scal, (size_t)P * NS * 8);
+    fill0(ws.iscal, (size_t)P * 16);
+    if ((rc = last_error())) return rc;
+    // candidates: the row split over 1, 2 or 4 times the default team width, times the default,
+    // half or a quarter of the default chunks per point
+    std::vector<std::pair<int, int>> cand;
+    for (int tm = p0.TEAM; tm <= std::min(16, 4 * p0.TEAM); tm *= 2)
+        for (int nc : {p0.nchunk, p0.nchunk / 2, p0.nchunk / 4}) {
+            Plan t = p0;
+            if (nc >= 1 && shape_plan(t, tm, nc) &&
+                std::find(cand.begin(), cand.end(), std::make_pair(tm, t.nchunk)) == cand.end())
+                cand.emplace_back(tm, t.nchunk);
+        }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return FBSDE_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FBSDE_EHIP; }
+    const int reps = 4;
+    float best = 0.0f, dflt = 0.0f;
+    int bi = 0;
+    for (size_t ci = 0; ci < cand.size() && !rc; ++ci) {
+        Plan t = p0;
+        shape_plan(t, cand[ci].first, cand[ci].second);
+        auto body = [&](auto tag) {
+            using S = decltype(tag);
+            for (int r = 0; r <= reps; ++r) {
+                dispatch<S>(t.Q, t.TEAM, [&](auto qc, auto tc) {
+                    constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+                    hipLaunchKernelGGL((k_matvec<S, S, QQ, TT>), dim3(t.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                                       st, (const S*)ws.W, (int64_t)t.ld, (int)t.M, t.rows_per_chunk, t.nchunk, t.ld,
+                                       pb->s, ws.w, ws.pv, ws.scal, NS, ws.iscal, ws.part1, ws.psc);
+                });
+                if (r == 0) (void)hipEventRecord(e0, st);
+            }
+        };
+        if (pb->prec == FBSDE_F64) body(double{}); else body(float{});
+        (void)hipEventRecord(e1, st);
+        float ms = 0.0f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = FBSDE_EHIP;
+        else rc = last_error();
+        ms /= (float)reps;
+        if (ci == 0) { best = ms; dflt = ms; }
+        else if (ms < 0.98f * best) { best = ms; bi = (int)ci; }   // a new shape must win by 2 %
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(pb, P)] = cand[(size_t)bi];
+    }
+    Plan t = p0;
+    shape_plan(t, cand[(size_t)bi].first, cand[(size_t)bi].second);
+    out->team = t.TEAM;
+    out->q = t.Q;
+    out->nchunk = t.nchunk;
+    out->n_candidates = (int32_t)cand.size();
+    out->best_ms = best;
+    out->default_ms = dflt;
+    return FBSDE_OK;
+}
+
+int fbsde_autotune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return FBSDE_OK;
 }
 
 struct fbsde_graph_s {

@@ -122,13 +122,51 @@ __device__ __forceinline__ double log_unit(uint32_t w) {
     return k * ln2_hi + (k * ln2_lo + lnm);
 }
 
+// ln u for u = (w + 1/2) 2^-32 in FP32 (the FP32C mode, whose state is FP32).  The reduction is done in
+// integers so that m - 1 keeps full relative accuracy as u -> 1: with x = w + 1/2 = 2^e (1 + f),
+// e = floor(log2 w), the numerator of m - 1 over 2^(e+1) is the exact integer 2 (w - 2^e) + 1; for
+// m >= sqrt(2) the mantissa is halved, m/2 - 1 = -(2^(e+2) - 2w - 1) / 2^(e+2).  Then
+// ln m = 2 atanh(z), z = (m - 1)/(m + 1), |z| <= 0.1716: five odd terms leave a truncation below
+// 2e-9 relative.  (e - 32) ln 2 with ln 2 split into a 16-bit head (exact products) and a tail.
+__device__ __forceinline__ float log_unit_f32(uint32_t w) {
+    if (w == 0u) return -33.0f * 0.693145751953125f - 33.0f * 1.4286068e-06f;   // u = 2^-33
+    const int e = 31 - __clz((int)w);                                         // 2^e <= w < 2^(e+1)
+    // halve m when it reaches sqrt(2): m = (2w + 1) / 2^(e+1); the exact switching point does not
+    // matter (either branch is exact in its reduction, |z| stays at the 0.1716 bound to FP32 rounding)
+    const bool upper = (float)(2u * (uint64_t)w + 1u) >= 1.41421356f * ldexpf(1.0f, e + 1);
+    float mm1;   // m - 1 (or m/2 - 1), exact integer numerator, one rounding
+    int k;
+    if (!upper) {
+        const uint32_t t = 2u * (w - (1u << e)) + 1u;
+        mm1 = ldexpf((float)t, -(e + 1));
+        k = e - 32;
+    } else {
+        const uint64_t t = ((uint64_t)1 << (e + 2)) - 2u * (uint64_t)w - 1u;
+        mm1 = -ldexpf((float)t, -(e + 2));
+        k = e + 1 - 32;
+    }
+    const float z = mm1 / (2.0f + mm1);
+    const float z2 = z * z;
+    float sr = 1.0f / 9.0f;
+    sr = sr * z2 + 1.0f / 7.0f;
+    sr = sr * z2 + 1.0f / 5.0f;
+    sr = sr * z2 + 1.0f / 3.0f;
+    const float lnm = 2.0f * z + 2.0f * z * z2 * sr;
+    const float kf = (float)k;
+    return kf * 0.693145751953125f + (kf * 1.4286068e-06f + lnm);
+}
+
+template <typename R> __device__ __forceinline__ R log_unit_r(uint32_t w);
+template <> __device__ __forceinline__ double log_unit_r<double>(uint32_t w) { return log_unit(w); }
+template <> __device__ __forceinline__ float log_unit_r<float>(uint32_t w) { return log_unit_f32(w); }
+
 // Four normals from one Philox call: Box-Muller on the word pairs (x, y) and (z, w) with
-// u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even) (FP64 logarithm; the square root in the
-// element type), angle 2 pi u_odd.
+// u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even) and angle 2 pi u_odd, both in the element
+// type (FP64 logarithm for the FP64 mode, the FP32 one above for FP32C).
 template <typename R>
 __device__ __forceinline__ void box_muller4(const Words4& w, R z[4]) {
-    const R r0 = (R)sqrt((R)(-2.0 * log_unit(w.x)));
-    const R r2 = (R)sqrt((R)(-2.0 * log_unit(w.z)));
+    const R r0 = sqrt((R)-2 * log_unit_r<R>(w.x));
+    const R r2 = sqrt((R)-2 * log_unit_r<R>(w.z));
     R s1, c1, s3, c3;
     sincos_turn<R>(w.y, s1, c1);
     sincos_turn<R>(w.w, s3, c3);

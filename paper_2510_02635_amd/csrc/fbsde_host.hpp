@@ -50,6 +50,26 @@ inline double cg_rtol_of(const fbsde_problem* pb) {
     return pb->cg_rtol;
 }
 
+// Launch shapes recorded by fbsde_autotune (process-wide table keyed by precision, d, M and P).
+bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk);
+
+// Re-shape a plan: team width `team` (groups per lane recomputed) and `nchunk` chunks per point.
+// Returns false if the team cannot hold the row within the per-lane register budget.
+inline bool shape_plan(Plan& pl, int team, int nchunk) {
+    const int groups = pl.ld / 4;
+    const int qmax = (pl.esz == 8) ? 4 : 8;
+    if (team < 1 || team > 16 || (team & (team - 1)) || nchunk < 1) return false;
+    const int q = (groups + 64 * team - 1) / (64 * team);
+    if (q > qmax) return false;
+    pl.TEAM = team;
+    pl.Q = (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : 8;
+    pl.BS = 64 * std::max(pl.TEAM, 4);
+    pl.TPW = pl.BS / (64 * pl.TEAM);
+    pl.rows_per_chunk = (int)((pl.M + nchunk - 1) / nchunk);
+    pl.nchunk = (int)((pl.M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
+    return true;
+}
+
 inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
     pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;
@@ -75,6 +95,13 @@ inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, std::min<int64_t>(pb->M / (2 * pl.TPW), pb->M / 64)));
     pl.rows_per_chunk = (int)((pb->M + nchunk - 1) / nchunk);
     pl.nchunk = (int)((pb->M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
+    // a shape chosen by the autotuner: never more chunks than the default, so workspaces sized
+    // before the tuning still fit
+    int tt, tn;
+    if (P > 0 && tuned_shape(pb, P, tt, tn)) {
+        Plan t = pl;
+        if (tn <= pl.nchunk && shape_plan(t, tt, tn)) pl = t;
+    }
     return FBSDE_OK;
 }
 

@@ -506,6 +506,21 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     const double alpha = scal[(int64_t)p * ns + 5];
     const double zz = scal[(int64_t)p * ns + 6];
     uint32_t st = 0;
+    // Newton runs 64 rows at a time: lane (row count mod 64) of the team's first wave keeps the row's
+    // C and |W|^2, and every 64 rows those lanes solve together instead of one lane per row
+    int j_keep = -1;
+    double c_keep = 0.0, n2_keep = 0.0;
+    auto flush = [&]() {
+        if (j_keep >= 0) {
+            double Fp;
+            const double y = newton_y(f, c_keep, zz, dt, newton_iters, Fp, st);
+            Y[(int64_t)p * M + j_keep] = y;
+            rn2[(int64_t)p * M + j_keep] = n2_keep;
+            if (dydc) dydc[(int64_t)p * M + j_keep] = 1.0 / Fp;
+        }
+        j_keep = -1;
+    };
+    int cnt = 0;
     for (int jb = r0; jb < r1; jb += G::TPW) {
         const int j = jb + team;
         const bool valid = j < r1;
@@ -539,14 +554,14 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
         }
         double n2 = n2s.get(), dt_ = dots.get();
         team_sum2<TEAM>(n2, dt_, red, team);
-        if (valid && L == 0) {
-            double Fp;
-            const double y = newton_y(f, alpha + s * dt_, zz, dt, newton_iters, Fp, st);
-            Y[(int64_t)p * M + j] = y;
-            rn2[(int64_t)p * M + j] = n2;
-            if (dydc) dydc[(int64_t)p * M + j] = 1.0 / Fp;
+        if (valid && L == (cnt & 63)) {
+            j_keep = j;
+            c_keep = alpha + s * dt_;
+            n2_keep = n2;
         }
+        if ((++cnt & 63) == 0) flush();
     }
+    flush();
     if (st) atomicOr(&status[p], st);
 }
 
@@ -607,7 +622,9 @@ k_rownorm(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int l
     }
 }
 
-// Diagnostic: normals and raw Philox words of rows j0.. of one level.
+// Diagnostic: normals (in the element type R of the precision mode, written as FP64) and raw Philox
+// words of rows j0.. of one level.
+template <typename R>
 __global__ void k_normals(int d, int64_t j0, int64_t rows, int k, uint32_t q, uint32_t k0, uint32_t k1,
                           double* __restrict__ out, uint32_t* __restrict__ words) {
     const int ng = (d + 3) / 4;
@@ -617,10 +634,10 @@ __global__ void k_normals(int d, int64_t j0, int64_t rows, int k, uint32_t q, ui
         const int g = (int)(t % ng);
         const Words4 c = {(uint32_t)g, (uint32_t)(j0 + r), (uint32_t)k, q};
         const Words4 wd = philox4x32_10(c, k0, k1);
-        double z[4];
-        box_muller4<double>(wd, z);
+        R z[4];
+        box_muller4<R>(wd, z);
         for (int e = 0; e < 4; ++e)
-            if (4 * g + e < d) out[r * d + 4 * g + e] = z[e];
+            if (4 * g + e < d) out[r * d + 4 * g + e] = (double)z[e];
         if (words) {
             uint32_t* wp = words + (r * ng + g) * 4;
             wp[0] = wd.x; wp[1] = wd.y; wp[2] = wd.z; wp[3] = wd.w;

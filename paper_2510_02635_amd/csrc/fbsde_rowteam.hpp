@@ -31,13 +31,18 @@ template <> struct CSum<float> {
     __device__ __forceinline__ double get() const { return (double)s - (double)c; }
 };
 
+// Loads of state rows: each pass streams the [P][M][ld] state once and never re-reads a row, so the
+// loads carry the non-temporal hint (measured: the FP32 CG product 2.87 -> 2.53 ms at d = 1000,
+// P = 1024, M = 4096; no change in FP64).
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void load4(const double* __restrict__ p, double v[4]) {
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p + 2));
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 __device__ __forceinline__ void load4(const float* __restrict__ p, float v[4]) {
-    const float4 a = *reinterpret_cast<const float4*>(p);
+    const nt_f4 a = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 // One row of the state into a lane's registers: groups of four at 4 (L + q TL), zero beyond ld.

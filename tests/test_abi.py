@@ -74,3 +74,12 @@ def test_graph_capture_needs_fixed_cg_launches():
     assert rc == N.EINVAL and not h.value
     assert N.load().fbsde_graph_launch(None, None) == N.EINVAL
     assert N.load().fbsde_graph_destroy(None) == 0
+
+
+def test_autotune_validation_and_reset_on_host():
+    shared = F.Problem(d=8, M=64, N=2, T=0.3, shared_dw=1)
+    r = N.CTuneResult()
+    assert N.load().fbsde_autotune(ctypes.byref(shared.c()), 2, 1, 1, 1 << 30, ctypes.byref(r), None) == N.EINVAL
+    pb = F.Problem(d=8, M=64, N=2, T=0.3)
+    assert N.load().fbsde_autotune(ctypes.byref(pb.c()), 0, 1, 1, 1 << 30, ctypes.byref(r), None) == N.EINVAL
+    assert N.load().fbsde_autotune_reset() == 0

@@ -1,0 +1,64 @@
+"""GPU: the autotuner's recorded launch shape is used by later solves, which stay at the parity bar.
+
+fbsde_autotune times the fused CG product over the row split (team width) and the per-point chunk
+split; the solve with the recorded shape must match the FP64 oracle like the default one (only the
+summation order of the partial sums changes), and the workspace never grows."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2510_02635_amd as F  # noqa: E402
+from oracle import scheme as OS  # noqa: E402
+from paper_2510_02635_amd import workloads  # noqa: E402
+
+from _convert import problems, rel_err  # noqa: E402
+
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F._native.load()
+    yield
+    F.autotune_reset()
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, 1e-10), (F.F32C, 1e-5)], ids=["fp64", "fp32c"])
+def test_tuned_shape_keeps_parity(prec, tol):
+    kw = dict(d=1200, M=700, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0))
+    hp, op = problems(prec=prec, **kw)
+    P = 6
+    x0 = workloads.points("normal_over_sqrt_d", P, kw["d"], 4)
+    xt = torch.tensor(x0, device=DEV)
+    F.autotune_reset()
+    w0 = F.workspace_size(hp, P)
+    u0, g0, _ = F.solve(hp, xt)
+    res = F.autotune(hp, xt)
+    _say(f"[autotune] {prec}: {res}")
+    assert res["n_candidates"] >= 2 and res["best_ms"] <= res["default_ms"] * 1.0001
+    assert F.workspace_size(hp, P) <= w0
+    u, g, st = F.solve(hp, xt)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum().item()) == 0
+    for p in range(P):
+        ref = OS.solve_point(op, x0[p], p)
+        eu = abs(u[p].item() - ref["u"]) / abs(ref["u"])
+        eg = rel_err(g[p].cpu().numpy(), ref["grad"])
+        _say(f"  p={p} rel_u={eu:.2e} rel_grad={eg:.2e}")
+        assert eu <= tol and eg <= tol
+    F.autotune_reset()
+    u1, g1, _ = F.solve(hp, xt)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u0) and torch.equal(g1, g0)   # the default shape again, bit for bit

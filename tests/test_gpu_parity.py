@@ -75,6 +75,23 @@ def test_philox_words_and_normals_match_oracle():
     assert np.median(ulp) <= 2.0
 
 
+def test_fp32c_normals_match_oracle_to_fp32_rounding():
+    """FP32C draws its normals in FP32 (integer-reduced logarithm for the radius, Taylor sin/cos on the
+    exactly reduced angle): 2^17 normals within 8 FP32 ulps of the FP64 oracle, with nothing lost as
+    u -> 1 (small radii) or u -> 0 (the tail)."""
+    hp, op = problems(d=1024, M=16, N=3, T=0.3, seed=0x5EED, instance=3, prec=F.F32C)
+    out, words = F.normals(hp, 0, 2, 0, 128)
+    torch.cuda.synchronize()
+    ref = OP.normals(op.seed, op.instance, op.point_base, 2, 128, 1024)
+    got = out.cpu().numpy()
+    ulp32 = np.spacing(np.maximum(np.abs(ref), 1e-30).astype(np.float32)).astype(np.float64)
+    err = np.abs(got - ref)
+    _say(f"[normals fp32c] max abs {err.max():.2e}, max ulps {np.max(err / ulp32):.2f}, median ulps "
+         f"{np.median(err / ulp32):.2f}")
+    assert np.max(err) < 4e-6
+    assert np.max(err / np.maximum(ulp32, 1e-7)) <= 8.0
+
+
 @pytest.mark.parametrize("d,M,prec", [(37, 100, F.F64), (1000, 96, F.F64), (3000, 20, F.F32C), (10000, 8, F.F64)])
 def test_terminal_matches_oracle(d, M, prec):
     hp, op = problems(d=d, M=M, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,

@@ -30,10 +30,12 @@
  *
  * Conventions for every entry point
  *   - Pointers named "device" are device memory of the current HIP device; the caller owns
- *     every buffer, including the workspace; the library allocates nothing and keeps no
- *     global state.
+ *     every buffer, including the workspace; the library allocates no device memory.  Its
+ *     only process-wide state is the table of launch shapes chosen by fbsde_autotune; the
+ *     tiled batched schedule creates host threads, streams and events for the length of a call.
  *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
- *     once it is enqueued, except where stated (CG convergence polling, see fbsde_solve).
+ *     once it is enqueued, except where stated (CG convergence polling, see fbsde_solve; the
+ *     tiled batched schedule and the autotuner return after their work has completed).
  *   - Return value: FBSDE_OK, or a negative code decided on the host before any launch
  *     (FBSDE_EINVAL, FBSDE_ENOSPC) or after a failed launch (FBSDE_EHIP).
  *   - Per-point numerical failures do not stop other points: they are OR-ed into
@@ -140,10 +142,12 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
                 fbsde_stream stream);
 /* shared_dw = 1 (increments common to all points, the common-randomness remark after Lemma 3.7):
  * one cloud, one ridge system per level; the regressions of all points become dense MFMA
- * contractions and a blocked Cholesky of the M x M dual matrix lam I + s^2 Dt Dt^T,
- * Dt_j = sqrt(w_j)(W_j - Wbar) (push-through form of the ridge solve); no CG (cg_iters_out gets 0),
- * no tape (flags must be 0).  fbsde_terminal, fbsde_solve_step, fbsde_solve_backward and
- * fbsde_time_kernel return FBSDE_EINVAL for shared_dw = 1. */
+ * contractions with the inverse of the M x M dual matrix lam I + s^2 Dt Dt^T, Dt_j =
+ * sqrt(w_j)(W_j - Wbar) (push-through form of the ridge solve; M > d: the d x d primal matrix),
+ * formed once per level by a recursive Cholesky that carries the inverse of its factor; no CG
+ * (cg_iters_out gets 0).  flags = FBSDE_WS_TAPE keeps that inverse, the slopes and Y per level for
+ * fbsde_solve_backward.  fbsde_terminal, fbsde_solve_step and fbsde_time_kernel return
+ * FBSDE_EINVAL for shared_dw = 1. */
 
 /* Reverse mode of fbsde_solve for the loss L = sum_p u_bar[p] u(0, x0_p): hand-written adjoint of
  * the whole backward chain (Newton by the implicit-function rule, the regression through one extra

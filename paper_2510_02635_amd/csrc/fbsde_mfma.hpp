@@ -311,4 +311,120 @@ inline void cholesky_solve_rows(const T* L, int64_t ldl, int n, T* R, int64_t ld
     }
 }
 
+// out[c][r] = in[r][c] for an n x n block (32 x 32 tiles through LDS).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_transpose_sq(const T* __restrict__ in, int64_t ldi, int n, T* __restrict__ out, int64_t ldo) {
+    __shared__ T tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        tile[i][tx] = (r < n && c < n) ? in[(int64_t)r * ldi + c] : (T)0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int c = c0 + i, r = r0 + tx;
+        if (c < n && r < n) out[(int64_t)c * ldo + r] = tile[tx][i];
+    }
+}
+
+// Zero an n x n block (row pitch ld).
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_square(T* __restrict__ A, int64_t ld, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+        A[(t / n) * ld + (t % n)] = (T)0;
+}
+
+// ------------------------------------------------------------------ recursive Cholesky with the inverse
+// For the shared form only K^{-1} is needed.  With K = [[A, B^T], [B, C]] and L its factor:
+//   L11 = chol(A);  L21 = B L11^{-T};  L22 = chol(C - L21 L21^T);
+//   L^{-1} = [[L11^{-1}, 0], [-L22^{-1} L21 L11^{-1}, L22^{-1}]]
+// so the factor's inverse follows by recursion on halves, every off-diagonal step a GEMM on the matrix
+// cores; only the CB x CB leaves (factor and inverse together in LDS) run one after another.
+
+// Leaf: the w x w SPD block at K (lower triangle read), w <= CB: its factor's inverse into Li (lower,
+// zeros above).  256 threads, FP64 in LDS: right-looking factorisation (column scale, then the trailing
+// update split over the threads), then lane c of the first wave forms column c of the inverse.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_chol_inv_leaf(const T* __restrict__ K, int64_t ldk, int w, T* __restrict__ Li, int64_t ldi, int* __restrict__ info) {
+    __shared__ double Ls[CB][CB + 1];
+    __shared__ double xs[CB][CB + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < CB * CB; e += 256) {
+        const int i = e / CB, j = e % CB;
+        Ls[i][j] = (i < w && j <= i) ? (double)K[(int64_t)i * ldk + j] : ((i == j) ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    int bad = 0;
+    const int r = t >> 2, cq = t & 3;   // thread t updates row r, columns c = cq (mod 4)
+    for (int j = 0; j < w; ++j) {
+        double dj = Ls[j][j];
+        if (!(dj > 0.0)) { bad = 1; dj = 1.0; }
+        const double piv = sqrt(dj);
+        __syncthreads();   // every thread has read the pivot before it changes
+        if (cq == 0 && r < w) {
+            if (r == j) Ls[j][j] = piv;
+            else if (r > j) Ls[r][j] /= piv;
+        }
+        __syncthreads();
+        if (r > j && r < w) {
+            const double lrj = Ls[r][j];
+            for (int c = j + 1 + ((cq - (j + 1)) & 3); c <= r; c += 4) Ls[r][c] -= lrj * Ls[c][j];
+        }
+        __syncthreads();
+    }
+    if (t < CB) {
+        const int c = t;
+        for (int rr = 0; rr < CB; ++rr) {
+            double acc = (rr == c) ? 1.0 : 0.0;
+            for (int k = c; k < rr; ++k) acc -= Ls[rr][k] * xs[k][c];
+            xs[rr][c] = (rr >= c) ? acc / Ls[rr][rr] : 0.0;
+        }
+        if (c < w)
+            for (int rr = 0; rr < w; ++rr) Li[(int64_t)rr * ldi + c] = (T)xs[rr][c];
+    }
+    if (bad && t == 0) atomicOr(info, 1);
+}
+
+// Li = (chol K)^{-1} for the n x n SPD K (lower triangle read; its strictly lower blocks are left as
+// they are, the lower triangle of each diagonal block is read only).  Li needs zeros above the
+// diagonal: the caller clears it once.  S: scratch of at least (n/2 + CB)^2 elements.
+template <typename T>
+inline void chol_inverse_rec(T* K, int64_t ldk, int n, T* Li, int64_t ldi, T* S, int* info, hipStream_t st) {
+    if (n <= CB) {
+        hipLaunchKernelGGL((k_chol_inv_leaf<T>), dim3(1), dim3(256), 0, st, K, ldk, n, Li, ldi, info);
+        return;
+    }
+    const int n1 = ((n / CB + 1) / 2) * CB, n2 = n - n1;
+    T* C = K + (int64_t)n1 * ldk + n1;
+    const T* B = K + (int64_t)n1 * ldk;
+    T* Li11 = Li;
+    T* Li21 = Li + (int64_t)n1 * ldi;
+    T* Li22 = Li + (int64_t)n1 * ldi + n1;
+    chol_inverse_rec<T>(K, ldk, n1, Li11, ldi, S, info, st);
+    // L21 = B L11^{-T}, kept for now in the lower-left block of Li
+    gemm<T, true>(n2, n1, n1, B, ldk, Li11, ldi, EpiStore<T>{Li21, ldi, 1.0, 0.0, 0.0}, st);
+    // C <- C - L21 L21^T (lower tiles)
+    gemm<T, true>(n2, n2, n1, Li21, ldi, Li21, ldi, EpiStore<T>{C, ldk, -1.0, 1.0, 0.0}, st, 1);
+    chol_inverse_rec<T>(C, ldk, n2, Li22, ldi, S, info, st);
+    // Li21 = -L22^{-1} (L21 L11^{-1})
+    gemm<T, false>(n2, n1, n1, Li21, ldi, Li11, ldi, EpiStore<T>{S, (int64_t)n1, 1.0, 0.0, 0.0}, st);
+    gemm<T, false>(n2, n1, n2, Li22, ldi, S, n1, EpiStore<T>{Li21, ldi, -1.0, 0.0, 0.0}, st);
+}
+
+// K^{-1} of the SPD K (lower triangle read and overwritten) into Kinv (may be K): Li [n][n] and S [n][n]
+// scratch; *info (device) gets 1 for a non-positive pivot.
+template <typename T>
+inline void spd_inverse(T* K, int64_t ldk, int n, T* Kinv, int64_t ldkinv, T* Li, T* S, int* info, hipStream_t st) {
+    hipLaunchKernelGGL((k_zero_square<T>), dim3((unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096)),
+                       dim3(256), 0, st, Li, (int64_t)n, n);
+    chol_inverse_rec<T>(K, ldk, n, Li, n, S, info, st);
+    const unsigned tb = (unsigned)((n + 31) / 32);
+    hipLaunchKernelGGL((k_transpose_sq<T>), dim3(tb, tb), dim3(256), 0, st, Li, (int64_t)n, n, S, (int64_t)n);
+    gemm<T, false>(n, n, n, S, n, Li, n, EpiStore<T>{Kinv, ldkinv, 1.0, 0.0, 0.0}, st);
+}
+
 }  // namespace fbsde

@@ -5,7 +5,7 @@
 //   Dt_j           = sqrt(w_j) (W_j - Wbar)                       [M][ld]
 //   K              = lam I + s^2 Dt Dt^T                          [M][M] (Gram, MFMA)   -> Cholesky
 //   R[p][j]        = sqrt(w_j) (Y_pj - Ybar_p)                    [P][M]
-//   F              = R K^{-1}                                     (triangular solves)
+//   F              = R K^{-1}                                     (K^{-1} from the factor, one GEMM)
 //   alpha_x[p]     = s F[p] Dt   (the dual form of the ridge normal equations: A^{-1} D'^T W (Y - Ybar))
 //   alpha_p        = Ybar_p - s alpha_x[p] . Wbar
 //   C[p][m]        = alpha_p + s alpha_x[p] . W^m_k  -> Newton in the GEMM epilogue
@@ -15,6 +15,24 @@
 #include "fbsde_mfma.hpp"
 
 namespace fbsde {
+
+// Dual Gram matrix with the known small eigenvalue lifted: K' = lam I + s^2 Dt Dt^T + c sqrt(w) sqrt(w)^T.
+// The weighted centring makes sqrt(w) an exact null vector of Dt^T, so K itself has the eigenvalue lam
+// there (condition near 10^3 d / M); every right-hand side K^{-1} is applied to -- sqrt(w_j)(Y_j - Ybar)
+// and alpha_xbar Dt^T -- is orthogonal to sqrt(w), so K'^{-1} gives the same products while its
+// explicit inverse keeps the condition of the rest of the spectrum (c of the order of its mean).
+template <typename T>
+struct EpiGram {
+    T* K;
+    int64_t ldk;
+    double s2, lam, c;
+    const double* sqw;
+    __device__ __forceinline__ void operator()(int m, int n, double v) const {
+        double r = s2 * v + c * sqw[m] * sqw[n];
+        if (m == n) r += lam;
+        K[(int64_t)m * ldk + n] = (T)r;
+    }
+};
 
 // Terminal values from the contraction v = xc_p . W_j (radial g): |X|^2 = |xc_p|^2 + 2 s v + s^2 |W_j|^2.
 struct EpiTerminal {

@@ -10,7 +10,7 @@ namespace {
 
 // ------------------------------------------------------------------ shared-increment workspace
 struct SWS {
-    void *W, *Dt, *K, *R, *ax, *xc, *DtT;
+    void *W, *Dt, *K, *R, *ax, *xc, *DtT, *Li, *Sq, *R2;
     double *Wbar, *wpart, *w, *sqw, *rn2, *Ya, *Yb, *scal, *xc2, *ysc;
     int* info;
     // tape for the reverse mode, per level k (cloud t_{k+1}): Y_k [P][M], alpha_x [P][ld], the
@@ -40,8 +40,11 @@ size_t carve_shared(const Plan& pl, int64_t P, int32_t flags, char* base, SWS& w
     const size_t kn = primal ? ld : M;
     ws.kn = kn;
     ws.K = take(kn * kn * e);
+    ws.Li = take(kn * kn * e);
+    ws.Sq = take(kn * kn * e);
     ws.DtT = primal ? take(ld * M * e) : nullptr;
     ws.R = take((size_t)P * M * e);
+    ws.R2 = take((size_t)P * M * e);
     ws.ax = take((size_t)P * ld * e);
     ws.xc = take((size_t)P * ld * e);
     ws.Wbar = (double*)take(ld * 8);
@@ -131,10 +134,13 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
                            (M + rpc - 1) / rpc, sqw, Wbar, Dt);
         if (pl.M <= pl.d) {
             // dual: alpha_x[p] = s F[p] Dt with F = R (lam I + s^2 Dt Dt^T)^{-1}
-            gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiStore<T>{K, (int64_t)M, s2, 0.0, lam}, st, 1);
-            cholesky<T>(K, M, M, ws.info, st);
-            cholesky_solve_rows<T>(K, M, M, R, M, Pi, st);
-            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
+            // (K^{-1} formed once per level from the factor: every solve is then one GEMM; the Gram
+            // matrix carries the lift c sqrt(w) sqrt(w)^T of its null direction, c ~ s^2 t_{k+1} d / M)
+            const double lift = s2 * t_next * (double)d / (double)M;
+            gemm<T, true>(M, M, ld, Dt, ld, Dt, ld, EpiGram<T>{K, (int64_t)M, s2, lam, lift, sqw}, st, 1);
+            spd_inverse<T>(K, M, M, K, M, (T*)ws.Li, (T*)ws.Sq, ws.info, st);
+            gemm<T, false>(Pi, M, M, R, M, K, M, EpiStore<T>{(T*)ws.R2, (int64_t)M, 1.0, 0.0, 0.0}, st);
+            gemm<T, false>(Pi, ld, M, (T*)ws.R2, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
         } else {
             // primal: alpha_x[p] = b_p (lam I + s^2 Dt^T Dt)^{-1}, b_p = s R[p] Dt (the pad rows/columns
             // of the ld x ld matrix are lam I and decouple)
@@ -142,9 +148,9 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
             hipLaunchKernelGGL((k_transpose<T>), dim3(cblocks * 8, (unsigned)((M + 31) / 32)), dim3(256), 0, st, Dt,
                                (int64_t)ld, M, ld, DtT, (int64_t)M);
             gemm<T, true>(ld, ld, M, DtT, M, DtT, M, EpiStore<T>{K, (int64_t)ld, s2, 0.0, lam, d, 1.0}, st, 1);
-            cholesky<T>(K, ld, ld, ws.info, st);
-            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{ax, (int64_t)ld, s, 0.0, 0.0}, st);
-            cholesky_solve_rows<T>(K, ld, ld, ax, ld, Pi, st);
+            spd_inverse<T>(K, ld, ld, K, ld, (T*)ws.Li, (T*)ws.Sq, ws.info, st);
+            gemm<T, false>(Pi, ld, M, R, M, Dt, ld, EpiStore<T>{xc, (int64_t)ld, s, 0.0, 0.0}, st);
+            gemm<T, false>(Pi, ld, ld, xc, ld, K, ld, EpiStore<T>{ax, (int64_t)ld, 1.0, 0.0, 0.0}, st);
         }
         hipLaunchKernelGGL((k_sh_point_finish<T>), dim3((unsigned)P), dim3(256), 0, st, ax, ld, Wbar, s, scal, NS);
         if (k > 0) {
@@ -203,12 +209,13 @@ int backward_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl
         shared_advance<T>(pb, pl1, k, W, st);
         hipLaunchKernelGGL((k_sha_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, tWbar_k,
                            ws.tsqw + (size_t)k * M, Dt);
+        // the tape holds K^{-1} (dual M x M, primal ld x ld): each ridge adjoint is two GEMMs
         if (dual) {
-            gemm<T, true>(Pi, M, ld, axbar, ld, Dt, ld, EpiStore<T>{V, (int64_t)M, 1.0, 0.0, 0.0}, st);
-            cholesky_solve_rows<T>(tK_k, M, M, V, M, Pi, st);
+            gemm<T, true>(Pi, M, ld, axbar, ld, Dt, ld, EpiStore<T>{(T*)ws.R2, (int64_t)M, 1.0, 0.0, 0.0}, st);
+            gemm<T, false>(Pi, M, M, (T*)ws.R2, M, tK_k, M, EpiStore<T>{V, (int64_t)M, 1.0, 0.0, 0.0}, st);
         } else {
-            cholesky_solve_rows<T>(tK_k, ld, ld, axbar, ld, Pi, st);
-            gemm<T, true>(Pi, M, ld, axbar, ld, Dt, ld, EpiStore<T>{V, (int64_t)M, 1.0, 0.0, 0.0}, st);
+            gemm<T, false>(Pi, ld, ld, axbar, ld, tK_k, ld, EpiStore<T>{(T*)ws.ax, (int64_t)ld, 1.0, 0.0, 0.0}, st);
+            gemm<T, true>(Pi, M, ld, (T*)ws.ax, ld, Dt, ld, EpiStore<T>{V, (int64_t)M, 1.0, 0.0, 0.0}, st);
         }
         hipLaunchKernelGGL((k_sha_G<T>), dim3((unsigned)P), dim3(256), 0, st, V, M, ws.tsqw + (size_t)k * M, s, ws.G,
                            ws.psc);

@@ -144,7 +144,7 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
  * one cloud, one ridge system per level; the regressions of all points become dense MFMA
  * contractions with the inverse of the M x M dual matrix lam I + s^2 Dt Dt^T, Dt_j =
  * sqrt(w_j)(W_j - Wbar) (push-through form of the ridge solve; M > d: the d x d primal matrix),
- * formed once per level by a recursive Cholesky that carries the inverse of its factor; no CG
+ * formed once per level from its blocked Cholesky factor (blockwise inverse of the factor); no CG
  * (cg_iters_out gets 0).  flags = FBSDE_WS_TAPE keeps that inverse, the slopes and Y per level for
  * fbsde_solve_backward.  fbsde_terminal, fbsde_solve_step and fbsde_time_kernel return
  * FBSDE_EINVAL for shared_dw = 1. */

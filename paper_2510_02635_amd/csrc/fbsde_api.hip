@@ -191,17 +191,27 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
     const double lam = pb->ridge_rel * s2 * t_next;
     hipLaunchKernelGGL(k_weights, dim3((unsigned)P), dim3(256), 0, st, rn2, Y_next, (int)pl.M, s2, eps2, w_out,
                        ws.c2, ws.scal, NS, ws.active, (int)P, warm);
+    // a rank-deficient design (M <= d + 1) in FP32C: FP64 arithmetic on the FP32 state in the moments and
+    // the CG product, whose FP32 rounding would otherwise reach the ridge-only null space of the design
+    // (where the solution carries it with weight 1/lam)
+    const bool r64 = !std::is_same<S, double>::value && pl.M <= pl.d + 1;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        hipLaunchKernelGGL((k_moments<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
-                           ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.x, ws.scal, NS, warm,
-                           ws.part1, ws.part2, ws.part3, ws.psc);
+        if (r64)
+            hipLaunchKernelGGL((k_moments<S, double, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.x, ws.scal,
+                               NS, warm, ws.part1, ws.part2, ws.part3, ws.psc);
+        else
+            hipLaunchKernelGGL((k_moments<S, S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
+                               W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, w_out, ws.c2, ws.x, ws.scal, NS,
+                               warm, ws.part1, ws.part2, ws.part3, ws.psc);
     });
     const int vc = fold_parts(pl, P, ws.part1, ws.part2, warm ? ws.part3 : nullptr, st);
     hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.part3, ws.psc,
                        pl.nchunk, vc, pl.ld, pb->s, lam, warm, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
                        ws.active);
-    const int iters = run_cg<S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
+    const int iters = r64 ? run_cg<S, double>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err)
+                          : run_cg<S, S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
     if (err) return iters;
     hipLaunchKernelGGL(k_level_finish, dim3((unsigned)P), dim3(256), 0, st, ws.x, Wbar_out, pl.ld, (int)pl.d, pb->s,
                        ws.scal, NS, alpha_out, alpha_x_out);
@@ -608,7 +618,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
             } else if (which == 2) {
                 dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
                     constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-                    hipLaunchKernelGGL((k_moments<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
+                    hipLaunchKernelGGL((k_moments<S, S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS),
                                        0, st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, ws.w, ws.c2,
                                        ws.x, ws.scal, NS, 1, ws.part1, ws.part2, ws.part3, ws.psc);
                 });

@@ -149,15 +149,15 @@ k_weights(const double* __restrict__ rn2, const double* __restrict__ Y, int M, d
 // Weighted first moments of the cloud: sum_j w_j W_j and sum_j w_j (Y_j - Ybar) W_j (column sums
 // over particles; the normal-equation right-hand side, eq. normal-eq), per block.  warm: also the
 // pieces of A x0 for the CG warm start x0 = rho * xw (xw = previous level's slope):
-// t_j = W_j . x0, sum_j w_j t_j W_j and sum_j w_j t_j, with the row still in registers.
-template <typename S, int Q, int TEAM>
+// t_j = W_j . x0, sum_j w_j t_j W_j and sum_j w_j t_j, with the row still in registers.  R is the
+// arithmetic type (FP64 on the FP32 state for a rank-deficient design, as in the CG product).
+template <typename S, typename R, int Q, int TEAM>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_moments(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nchunk, int ld,
           const double* __restrict__ w, const double* __restrict__ c2, const double* __restrict__ xw,
           const double* __restrict__ scal, int ns, int warm, double* __restrict__ part1, double* __restrict__ part2,
           double* __restrict__ part3, double* __restrict__ psc) {
     using G = Geo<Q, TEAM>;
-    using R = S;
     __shared__ double lds[(G::TPW > 1) ? G::TPW * 4 * Q * G::TL : 1];
     __shared__ double red[2 * G::BS / 64];
     const int p = blockIdx.y, c = blockIdx.x;
@@ -197,9 +197,10 @@ k_moments(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    a1[q][e].add(wj * x[q][e]);
-                    a2[q][e].add(cj * x[q][e]);
-                    if (warm) dl.add(x[q][e] * v[q][e]);
+                    const R xr = (R)x[q][e];
+                    a1[q][e].add(wj * xr);
+                    a2[q][e].add(cj * xr);
+                    if (warm) dl.add(xr * v[q][e]);
                 }
             }
         }
@@ -213,7 +214,7 @@ k_moments(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
 #pragma unroll
                 for (int q = 0; q < Q; ++q)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) a3[q][e].add(cr * x[q][e]);
+                    for (int e = 0; e < 4; ++e) a3[q][e].add(cr * (R)x[q][e]);
             }
         }
     }

@@ -20,6 +20,8 @@
 #pragma once
 #include "fbsde_device.hpp"
 
+#include <type_traits>
+
 namespace fbsde {
 
 template <typename T> struct GemmCfg;
@@ -59,6 +61,17 @@ struct EpiStore {
     }
 };
 
+// Four consecutive elements from a 16-byte aligned address.
+__device__ __forceinline__ void gload4(const float* __restrict__ p, float v[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void gload4(const double* __restrict__ p, double v[4]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
 template <typename T, bool NT, typename Epi>
 __global__ void __launch_bounds__(256)
 k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
@@ -78,15 +91,23 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
     const int m0 = bm * BM, n0 = bn * BN;
 
     T ra[AV][4], rb[BV][4];
+    // groups of four consecutive elements: one 16-byte (FP32) or two (FP64) loads when the group is in
+    // bounds and the operand's rows are 16-byte aligned, element loads at the edges
+    const bool avec = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    const bool bvec = (ldb % 4 == 0) && (((uintptr_t)B & 15) == 0);
     auto load_tile = [&](int k0) {
 #pragma unroll
         for (int v = 0; v < AV; ++v) {
             const int idx = tid + 256 * v;
             const int row = idx / (BK / 4), kq = idx % (BK / 4);
             const int gm = m0 + row, gk = k0 + 4 * kq;
+            if (avec && gm < Md && gk + 3 < Kd) {
+                gload4(A + (int64_t)gm * lda + gk, ra[v]);
+            } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                ra[v][e] = (gm < Md && gk + e < Kd) ? A[(int64_t)gm * lda + gk + e] : (T)0;
+                for (int e = 0; e < 4; ++e)
+                    ra[v][e] = (gm < Md && gk + e < Kd) ? A[(int64_t)gm * lda + gk + e] : (T)0;
+            }
         }
 #pragma unroll
         for (int v = 0; v < BV; ++v) {
@@ -94,15 +115,23 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
             if constexpr (NT) {
                 const int row = idx / (BK / 4), kq = idx % (BK / 4);
                 const int gn = n0 + row, gk = k0 + 4 * kq;
+                if (bvec && gn < Nd && gk + 3 < Kd) {
+                    gload4(B + (int64_t)gn * ldb + gk, rb[v]);
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    rb[v][e] = (gn < Nd && gk + e < Kd) ? B[(int64_t)gn * ldb + gk + e] : (T)0;
+                    for (int e = 0; e < 4; ++e)
+                        rb[v][e] = (gn < Nd && gk + e < Kd) ? B[(int64_t)gn * ldb + gk + e] : (T)0;
+                }
             } else {
                 const int krow = idx / (BN / 4), nq = idx % (BN / 4);
                 const int gk = k0 + krow, gn = n0 + 4 * nq;
+                if (bvec && gk < Kd && gn + 3 < Nd) {
+                    gload4(B + (int64_t)gk * ldb + gn, rb[v]);
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    rb[v][e] = (gk < Kd && gn + e < Nd) ? B[(int64_t)gk * ldb + gn + e] : (T)0;
+                    for (int e = 0; e < 4; ++e)
+                        rb[v][e] = (gk < Kd && gn + e < Nd) ? B[(int64_t)gk * ldb + gn + e] : (T)0;
+                }
             }
         }
     };
@@ -136,6 +165,20 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
+    // FP32: the matrix cores accumulate four K tiles (128 terms) in FP32, then those sums are added into
+    // FP64 running sums, so the rounding of long contractions (K up to 10^4 here) grows with 128 terms,
+    // not with K (measured at d = 10^4, P = 4096, M = 2048: gradient error 1.8e-5 -> 1.3e-6 folding
+    // every tile)
+    constexpr bool FOLD = std::is_same<T, float>::value;
+    double fsum[FOLD ? TM : 1][FOLD ? TN : 1][4];
+    if constexpr (FOLD) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) fsum[i][j][r] = 0.0;
+    }
 
     const int nk = (Kd + BK - 1) / BK;
     load_tile(0);
@@ -156,6 +199,19 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
 #pragma unroll
                 for (int j = 0; j < TN; ++j) acc[i][j] = Cfg::mfma(af[i], bf[j], acc[i][j]);
         }
+        if constexpr (FOLD) {
+            if ((kt & 3) == 3 || kt + 1 == nk) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            fsum[i][j][r] += (double)acc[i][j][r];
+                            acc[i][j][r] = (T)0;
+                        }
+            }
+        }
         __syncthreads();
         if (kt + 1 < nk) {
             store_tile();
@@ -170,7 +226,10 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm * WM + 16 * i + Cfg::row_of(lk, r);
                 const int n = n0 + wn * WN + 16 * j + li;
-                if (m < Md && n < Nd) epi(m, n, (double)acc[i][j][r]);
+                double val;
+                if constexpr (FOLD) val = fsum[i][j][r];
+                else val = (double)acc[i][j][r];
+                if (m < Md && n < Nd) epi(m, n, val);
             }
 }
 
@@ -337,91 +396,58 @@ __global__ void __launch_bounds__(256) k_zero_square(T* __restrict__ A, int64_t 
         A[(t / n) * ld + (t % n)] = (T)0;
 }
 
-// ------------------------------------------------------------------ recursive Cholesky with the inverse
-// For the shared form only K^{-1} is needed.  With K = [[A, B^T], [B, C]] and L its factor:
-//   L11 = chol(A);  L21 = B L11^{-T};  L22 = chol(C - L21 L21^T);
-//   L^{-1} = [[L11^{-1}, 0], [-L22^{-1} L21 L11^{-1}, L22^{-1}]]
-// so the factor's inverse follows by recursion on halves, every off-diagonal step a GEMM on the matrix
-// cores; only the CB x CB leaves (factor and inverse together in LDS) run one after another.
+// ------------------------------------------------------------------ inverse from the factor
+// For the shared form only K^{-1} is needed: K = L L^T by the blocked Cholesky above, then L^{-1}
+// blockwise -- every CB x CB diagonal block inverted in one launch (one wavefront each, forward
+// substitution of the unit columns, FP64 sums), then recursive doubling joins neighbouring
+// lower-triangular blocks [[A, 0], [B, C]] into one, whose lower-left block of the inverse is
+// -C^{-1} B A^{-1} (two GEMMs on the matrix cores) -- and K^{-1} = (L^{-1})^T L^{-1} (one GEMM).
 
-// Leaf: the w x w SPD block at K (lower triangle read), w <= CB: its factor's inverse into Li (lower,
-// zeros above).  256 threads, FP64 in LDS: right-looking factorisation (column scale, then the trailing
-// update split over the threads), then lane c of the first wave forms column c of the inverse.
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_chol_inv_leaf(const T* __restrict__ K, int64_t ldk, int w, T* __restrict__ Li, int64_t ldi, int* __restrict__ info) {
-    __shared__ double Ls[CB][CB + 1];
-    __shared__ double xs[CB][CB + 1];
-    const int t = threadIdx.x;
-    for (int e = t; e < CB * CB; e += 256) {
-        const int i = e / CB, j = e % CB;
-        Ls[i][j] = (i < w && j <= i) ? (double)K[(int64_t)i * ldk + j] : ((i == j) ? 1.0 : 0.0);
-    }
+__global__ void __launch_bounds__(64)
+k_trtri_diag(const T* __restrict__ L, int64_t ldl, int n, T* __restrict__ Li, int64_t ldi) {
+    __shared__ double Ls[CB][CB];
+    __shared__ double xs[CB][CB];
+    const int o = blockIdx.x * CB, w = min(CB, n - o);
+    const int c = threadIdx.x;
+    for (int r = 0; r < w; ++r) Ls[r][c] = (c <= r) ? (double)L[(int64_t)(o + r) * ldl + o + c] : 0.0;
     __syncthreads();
-    int bad = 0;
-    const int r = t >> 2, cq = t & 3;   // thread t updates row r, columns c = cq (mod 4)
-    for (int j = 0; j < w; ++j) {
-        double dj = Ls[j][j];
-        if (!(dj > 0.0)) { bad = 1; dj = 1.0; }
-        const double piv = sqrt(dj);
-        __syncthreads();   // every thread has read the pivot before it changes
-        if (cq == 0 && r < w) {
-            if (r == j) Ls[j][j] = piv;
-            else if (r > j) Ls[r][j] /= piv;
+    if (c < w) {
+        for (int r = 0; r < w; ++r) {
+            double acc = (r == c) ? 1.0 : 0.0;
+            for (int k = c; k < r; ++k) acc -= Ls[r][k] * xs[k][c];
+            xs[r][c] = (r >= c) ? acc / Ls[r][r] : 0.0;
         }
-        __syncthreads();
-        if (r > j && r < w) {
-            const double lrj = Ls[r][j];
-            for (int c = j + 1 + ((cq - (j + 1)) & 3); c <= r; c += 4) Ls[r][c] -= lrj * Ls[c][j];
-        }
-        __syncthreads();
+        for (int r = 0; r < w; ++r) Li[(int64_t)(o + r) * ldi + o + c] = (T)xs[r][c];
     }
-    if (t < CB) {
-        const int c = t;
-        for (int rr = 0; rr < CB; ++rr) {
-            double acc = (rr == c) ? 1.0 : 0.0;
-            for (int k = c; k < rr; ++k) acc -= Ls[rr][k] * xs[k][c];
-            xs[rr][c] = (rr >= c) ? acc / Ls[rr][rr] : 0.0;
-        }
-        if (c < w)
-            for (int rr = 0; rr < w; ++rr) Li[(int64_t)rr * ldi + c] = (T)xs[rr][c];
-    }
-    if (bad && t == 0) atomicOr(info, 1);
 }
 
-// Li = (chol K)^{-1} for the n x n SPD K (lower triangle read; its strictly lower blocks are left as
-// they are, the lower triangle of each diagonal block is read only).  Li needs zeros above the
-// diagonal: the caller clears it once.  S: scratch of at least (n/2 + CB)^2 elements.
+// Li = L^{-1} (lower triangle, zeros above) of the factor in L; S: scratch of at least n^2 / 4 elements.
 template <typename T>
-inline void chol_inverse_rec(T* K, int64_t ldk, int n, T* Li, int64_t ldi, T* S, int* info, hipStream_t st) {
-    if (n <= CB) {
-        hipLaunchKernelGGL((k_chol_inv_leaf<T>), dim3(1), dim3(256), 0, st, K, ldk, n, Li, ldi, info);
-        return;
-    }
-    const int n1 = ((n / CB + 1) / 2) * CB, n2 = n - n1;
-    T* C = K + (int64_t)n1 * ldk + n1;
-    const T* B = K + (int64_t)n1 * ldk;
-    T* Li11 = Li;
-    T* Li21 = Li + (int64_t)n1 * ldi;
-    T* Li22 = Li + (int64_t)n1 * ldi + n1;
-    chol_inverse_rec<T>(K, ldk, n1, Li11, ldi, S, info, st);
-    // L21 = B L11^{-T}, kept for now in the lower-left block of Li
-    gemm<T, true>(n2, n1, n1, B, ldk, Li11, ldi, EpiStore<T>{Li21, ldi, 1.0, 0.0, 0.0}, st);
-    // C <- C - L21 L21^T (lower tiles)
-    gemm<T, true>(n2, n2, n1, Li21, ldi, Li21, ldi, EpiStore<T>{C, ldk, -1.0, 1.0, 0.0}, st, 1);
-    chol_inverse_rec<T>(C, ldk, n2, Li22, ldi, S, info, st);
-    // Li21 = -L22^{-1} (L21 L11^{-1})
-    gemm<T, false>(n2, n1, n1, Li21, ldi, Li11, ldi, EpiStore<T>{S, (int64_t)n1, 1.0, 0.0, 0.0}, st);
-    gemm<T, false>(n2, n1, n2, Li22, ldi, S, n1, EpiStore<T>{Li21, ldi, -1.0, 0.0, 0.0}, st);
+inline void triangular_inverse(const T* L, int64_t ldl, int n, T* Li, int64_t ldi, T* S, hipStream_t st) {
+    const int nb = (n + CB - 1) / CB;
+    hipLaunchKernelGGL((k_zero_square<T>), dim3((unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096)),
+                       dim3(256), 0, st, Li, ldi, n);
+    hipLaunchKernelGGL((k_trtri_diag<T>), dim3((unsigned)nb), dim3(64), 0, st, L, ldl, n, Li, ldi);
+    for (int sb = 1; sb < nb; sb *= 2)
+        for (int a0 = 0; a0 + sb < nb; a0 += 2 * sb) {
+            const int oa = a0 * CB, sa = sb * CB;              // A: rows / cols [oa, oa + sa)
+            const int oc = oa + sa, sc = std::min(sa, n - oc);  // C: rows / cols [oc, oc + sc)
+            // S = B A^{-1}  (B = L[oc.., oa..], sc x sa)
+            gemm<T, false>(sc, sa, sa, L + (int64_t)oc * ldl + oa, ldl, Li + (int64_t)oa * ldi + oa, ldi,
+                           EpiStore<T>{S, (int64_t)sa, 1.0, 0.0, 0.0}, st);
+            // Li[oc.., oa..] = -C^{-1} S
+            gemm<T, false>(sc, sa, sc, Li + (int64_t)oc * ldi + oc, ldi, S, sa,
+                           EpiStore<T>{Li + (int64_t)oc * ldi + oa, ldi, -1.0, 0.0, 0.0}, st);
+        }
 }
 
-// K^{-1} of the SPD K (lower triangle read and overwritten) into Kinv (may be K): Li [n][n] and S [n][n]
-// scratch; *info (device) gets 1 for a non-positive pivot.
+// K^{-1} of the SPD K (lower triangle read and overwritten by the factor) into Kinv (may be K): Li [n][n]
+// and S [n][n] scratch; *info (device) gets 1 for a non-positive pivot.
 template <typename T>
 inline void spd_inverse(T* K, int64_t ldk, int n, T* Kinv, int64_t ldkinv, T* Li, T* S, int* info, hipStream_t st) {
-    hipLaunchKernelGGL((k_zero_square<T>), dim3((unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096)),
-                       dim3(256), 0, st, Li, (int64_t)n, n);
-    chol_inverse_rec<T>(K, ldk, n, Li, n, S, info, st);
+    cholesky<T>(K, ldk, n, info, st);
+    triangular_inverse<T>(K, ldk, n, Li, n, S, st);
     const unsigned tb = (unsigned)((n + 31) / 32);
     hipLaunchKernelGGL((k_transpose_sq<T>), dim3(tb, tb), dim3(256), 0, st, Li, (int64_t)n, n, S, (int64_t)n);
     gemm<T, false>(n, n, n, S, n, Li, n, EpiStore<T>{Kinv, ldkinv, 1.0, 0.0, 0.0}, st);

@@ -72,7 +72,7 @@ __device__ __forceinline__ void gload4(const double* __restrict__ p, double v[4]
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
-template <typename T, bool NT, typename Epi>
+template <typename T, bool NT, typename Epi, bool FOLD_LONG = false>
 __global__ void __launch_bounds__(256)
 k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
        Epi epi, int lower_only) {
@@ -165,11 +165,13 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
-    // FP32: the matrix cores accumulate four K tiles (128 terms) in FP32, then those sums are added into
-    // FP64 running sums, so the rounding of long contractions (K up to 10^4 here) grows with 128 terms,
-    // not with K (measured at d = 10^4, P = 4096, M = 2048: gradient error 1.8e-5 -> 1.3e-6 folding
-    // every tile)
-    constexpr bool FOLD = std::is_same<T, float>::value;
+    // Long FP32 contractions (FOLD_LONG, chosen by the launcher for K > 1024): the matrix cores
+    // accumulate eight K tiles (256 terms) in FP32, then those sums are added into FP64 running sums, so
+    // the rounding grows with 256 terms, not with K (measured at d = 10^4, P = 4096, M = 2048: gradient
+    // error 1.8e-5 with plain FP32 accumulation, 3.3e-6 folded, 8.4e-6 folding only K > 4096).  The
+    // folding costs about a sixth of the kernel's speed, so short contractions (the K = 64 updates of the
+    // factorisation and of the inverse) keep plain FP32 accumulation.
+    constexpr bool FOLD = FOLD_LONG && std::is_same<T, float>::value;
     double fsum[FOLD ? TM : 1][FOLD ? TN : 1][4];
     if constexpr (FOLD) {
 #pragma unroll
@@ -200,7 +202,7 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
                 for (int j = 0; j < TN; ++j) acc[i][j] = Cfg::mfma(af[i], bf[j], acc[i][j]);
         }
         if constexpr (FOLD) {
-            if ((kt & 3) == 3 || kt + 1 == nk) {
+            if ((kt & 7) == 7 || kt + 1 == nk) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -239,7 +241,12 @@ inline void gemm(int Md, int Nd, int Kd, const T* A, int64_t lda, const T* B, in
     using Cfg = GemmCfg<T>;
     if (Md <= 0 || Nd <= 0) return;
     const dim3 grid((Nd + Cfg::BN - 1) / Cfg::BN, (Md + Cfg::BM - 1) / Cfg::BM);
-    hipLaunchKernelGGL((k_gemm<T, NT, Epi>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi, lower_only);
+    if (std::is_same<T, float>::value && Kd > 1024)
+        hipLaunchKernelGGL((k_gemm<T, NT, Epi, true>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
+                           lower_only);
+    else
+        hipLaunchKernelGGL((k_gemm<T, NT, Epi, false>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
+                           lower_only);
 }
 
 // ------------------------------------------------------------------ blocked Cholesky

@@ -166,12 +166,13 @@ def main():
     # ---------------- whole-job state traffic: passes over the [P][M][ld] state per solve
     # forward: 1 write (terminal sweep), per level 1 moments read + K_k CG reads + reversal read and
     # write (read only at k = 0); adjoint: per level advance read and write + K'_k CG reads + 1 row-dot
-    # read, then 1 terminal read.  [P][M] FP64 side arrays (weights, Y) are below 0.3 % and not counted.
+    # read (+ 1 warm-start product from the second level on), then 1 terminal read.  [P][M] FP64 side arrays (weights, Y) are below 0.3 % and not counted.
     def fwd_passes(iters):
         return 1 + sum(1 + k + 2 for k in iters) - 1
 
     def adj_passes(iters):
-        return sum(3 + k for k in iters) + 1
+        # + one CG product per warm-started level (k > 0; the design has full rank here, M > d + 1)
+        return sum(3 + k for k in iters) + 1 + (len(iters) - 1)
 
     state32 = P * M * 1024 * 4
     state64 = P * M * 1008 * 8

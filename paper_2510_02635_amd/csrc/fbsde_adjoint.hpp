@@ -122,35 +122,92 @@ k_adj_advance(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nch
     if (part) block_columns_out<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
 }
 
-// alpha_xbar = s sum_m cbar_m W^m_k + s Zbar - alphabar s Wbar, then CG on A bbar = alpha_xbar from 0.
+// alpha_xbar = s sum_m cbar_m W^m_k + s Zbar - alphabar s Wbar, then CG on A bbar = alpha_xbar.
+// Cold (warm = 0): from bbar = 0.  Warm: the right-hand side goes to r, the previous level's bbar (in x)
+// becomes the direction v of one CG product (pv, Wbar . v in scal[2]) that k_adj_warm_start turns into
+// the start gamma v.
 __global__ void __launch_bounds__(256)
 k_adj_rhs_finish(const double* __restrict__ part, int nchunk, int vchunks, int ld, double s, double lam,
                  const double* __restrict__ Wbar, const double* __restrict__ ax, const double* __restrict__ adj,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ pv, double* __restrict__ scal,
-                 int ns, int* __restrict__ iscal, int* active) {
+                 int ns, int* __restrict__ iscal, int* active, int warm) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
     const double* a = adj + (int64_t)p * A_NS;
     const double abar = a[A_ABAR], zc = a[A_ZC];
     const int64_t o = (int64_t)p * ld;
-    double rr = 0.0, wv = 0.0;
+    double bb = 0.0, wv = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         double cs = 0.0;
         for (int c = 0; c < vchunks; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];
         const double b = s * cs + s * s * zc * ax[o + i] - abar * s * Wbar[o + i];
-        x[o + i] = 0.0;
         r[o + i] = b;
-        pv[o + i] = b;
-        rr += b * b;
-        wv += Wbar[o + i] * b;
+        bb += b * b;
+        if (warm) {
+            const double v = x[o + i];
+            pv[o + i] = v;
+            wv += Wbar[o + i] * v;
+        } else {
+            x[o + i] = 0.0;
+            pv[o + i] = b;
+            wv += Wbar[o + i] * b;
+        }
+    }
+    bb = block_sum(bb, lds);
+    wv = block_sum(wv, lds);
+    if (threadIdx.x == 0) {
+        scal[(int64_t)p * ns + 0] = bb;
+        scal[(int64_t)p * ns + 1] = bb;
+        scal[(int64_t)p * ns + 2] = wv;
+        scal[(int64_t)p * ns + 3] = lam;
+        iscal[p * 4 + 0] = 0;
+        const int done = (!warm && bb == 0.0) ? 1 : 0;
+        iscal[p * 4 + 1] = done;
+        if (done) atomicSub(active, 1);
+    }
+}
+
+// Warm start of the adjoint CG from the previous level's solution v: with q = A v from one CG product
+// (per-chunk partials, summed like k_cg_update), the start gamma v with gamma = (b . v) / (v . A v)
+// minimises the A-norm error along v (never worse than starting from 0); then r = b - gamma q, p = r.
+__global__ void __launch_bounds__(256)
+k_adj_warm_start(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int vchunks, int ld,
+                 double s, const double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
+                 double* __restrict__ pv, double* __restrict__ qv, double* __restrict__ scal, int ns,
+                 int* __restrict__ iscal, int* active) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double* sc = scal + (int64_t)p * ns;
+    const double lam = sc[3];
+    double tau = 0.0;
+    for (int c = 0; c < nchunk; ++c) tau += psc[(int64_t)p * nchunk + c];
+    const int64_t o = (int64_t)p * ld;
+    double vq = 0.0, bv = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        double a = 0.0;
+        for (int c = 0; c < vchunks; ++c) a += part[((int64_t)p * nchunk + c) * ld + i];
+        const double q = s * (a - tau * Wbar[o + i]) + lam * pv[o + i];
+        qv[o + i] = q;
+        vq += pv[o + i] * q;
+        bv += r[o + i] * pv[o + i];
+    }
+    vq = block_sum(vq, lds);
+    bv = block_sum(bv, lds);
+    const double gamma = (vq > 0.0) ? bv / vq : 0.0;
+    double rr = 0.0, wv = 0.0;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        x[o + i] = gamma * pv[o + i];
+        const double ri = r[o + i] - gamma * qv[o + i];
+        r[o + i] = ri;
+        pv[o + i] = ri;
+        rr += ri * ri;
+        wv += Wbar[o + i] * ri;
     }
     rr = block_sum(rr, lds);
     wv = block_sum(wv, lds);
     if (threadIdx.x == 0) {
-        scal[(int64_t)p * ns + 0] = rr;
-        scal[(int64_t)p * ns + 1] = rr;
-        scal[(int64_t)p * ns + 2] = wv;
-        scal[(int64_t)p * ns + 3] = lam;
+        sc[0] = rr;
+        sc[2] = wv;
         iscal[p * 4 + 0] = 0;
         const int done = (rr == 0.0) ? 1 : 0;
         iscal[p * 4 + 1] = done;

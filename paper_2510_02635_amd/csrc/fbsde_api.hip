@@ -324,9 +324,22 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
         const double* Wbar_k = ws.tWbar + (size_t)k * PL;
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.active, (int)P);
         const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+        // warm start from the previous level's bbar (full-rank designs, as in the forward)
+        const int warm = (k > 0 && pl.M > pl.d + 1) ? 1 : 0;
         hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, vc, pl.ld, pb->s,
                            lam, Wbar_k, ws.tax + (size_t)k * PL, ws.adj, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
-                           ws.active);
+                           ws.active, warm);
+        if (warm) {
+            dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+                constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+                hipLaunchKernelGGL((k_matvec<S, S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                                   st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w_k, ws.pv,
+                                   ws.scal, NS, ws.iscal, ws.part1, ws.psc);
+            });
+            const int vw = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+            hipLaunchKernelGGL(k_adj_warm_start, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vw,
+                               pl.ld, pb->s, Wbar_k, ws.x, ws.r, ws.pv, ws.qv, ws.scal, NS, ws.iscal, ws.active);
+        }
         // rank-deficient design: FP64 arithmetic in the CG product (the right-hand side has a
         // large component in the ridge-only null space, carried by the iterate with weight 1/lam)
         const int iters = (pl.M > pl.d + 1) ? run_cg<S, S>(pb, pl, P, W, ldw, w_k, Wbar_k, ws, status, st, err)

@@ -40,6 +40,10 @@
  *     (FBSDE_EINVAL, FBSDE_ENOSPC) or after a failed launch (FBSDE_EHIP).
  *   - Per-point numerical failures do not stop other points: they are OR-ed into
  *     status[p] (FBSDE_ST_* bits).
+ *   - P = 0 (no evaluation points) is a valid call once the descriptor is valid: nothing is read
+ *     or launched and the per-point pointers and the workspace may be NULL; cg_iters_out, when
+ *     given, gets zeros, and the reverse modes write zeros into gp_bar and fp_bar (the gradient
+ *     of an empty sum).  At most 65535 points per call (the batched call tiles larger instances).
  *   - Particle state layout: W[p][j][i] = W^j (Brownian displacement, X = x0 + t mu + s W)
  *     with a row pitch of fbsde_state_ld(pb) elements, padding kept at zero; element type
  *     double for FBSDE_F64, float for FBSDE_F32C.  In shared_dw mode the state is [M][ld].
@@ -72,7 +76,8 @@ enum { FBSDE_WS_TAPE = 1 };                   /* workspace flag: keep the tape f
 /* Problem descriptor (host memory).  Paper Algorithm 1 takes T, d, M, N, dt = T/N and the
  * target point; sigma, mu, f, g are the coefficients of Sec. 2.1. */
 typedef struct fbsde_problem {
-    int64_t d;               /* space dimension, >= 1                                        */
+    int64_t d;               /* space dimension, 1 .. 16384 (FP64) or 32768 (FP32C): a point's */
+                             /* row is held in the registers of one team of <= 16 wavefronts  */
     int64_t M;               /* particles per evaluation point, >= 2                          */
     int64_t N;               /* time steps, >= 1; dt = T / N                                  */
     double T;                /* horizon, > 0                                                  */

@@ -484,8 +484,9 @@ int fbsde_terminal(const fbsde_problem* pb, int64_t P, const double* x0, void* W
     if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
-    if (ldw < pl.ld || ldw % 4 != 0 || !x0 || !W || !Y || !status) return FBSDE_EINVAL;
-    if (P == 0) return FBSDE_OK;
+    if (ldw < pl.ld || ldw % 4 != 0) return FBSDE_EINVAL;
+    if (P == 0) return FBSDE_OK;   // nothing is read or written; the pointers may be null
+    if (!x0 || !W || !Y || !status) return FBSDE_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     clear_status(status, P, st);
     if (pb->prec == FBSDE_F64) launch_forward<double>(pb, pl, P, x0, (double*)W, ldw, Y, nullptr, status, st);
@@ -502,13 +503,12 @@ int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double
     if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
-    if (k < 0 || k >= pb->N || ldw < pl.ld || ldw % 4 != 0 || !W || !Y_next || !Y || Y == Y_next || !status ||
-        !wsp)
-        return FBSDE_EINVAL;
+    if (k < 0 || k >= pb->N || ldw < pl.ld || ldw % 4 != 0) return FBSDE_EINVAL;
+    if (P == 0) return FBSDE_OK;   // nothing is read or written; the pointers may be null
+    if (!W || !Y_next || !Y || Y == Y_next || !status || !wsp) return FBSDE_EINVAL;
     WS ws;
     if (carve(pl, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, 0, (char*)wsp, ws);
-    if (P == 0) return FBSDE_OK;
     hipStream_t st = (hipStream_t)stream;
     int err = FBSDE_OK;
     if (pb->prec == FBSDE_F64) {
@@ -533,6 +533,11 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     if (rc) return rc;
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
+    if (P == 0) {   // nothing is read or written but the per-level counts; the pointers may be null
+        if (cg_iters_out)
+            for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;
+        return FBSDE_OK;
+    }
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
         if (cg_iters_out)
@@ -542,7 +547,6 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     WS ws;
     if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, flags, (char*)wsp, ws);
-    if (P == 0) return FBSDE_OK;
     const bool tape = (flags & FBSDE_WS_TAPE) != 0;
     hipStream_t st = (hipStream_t)stream;
     if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
@@ -556,7 +560,14 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
     if (rc) return rc;
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
-    if (!x0 || !u_bar || !x0_bar || !gp_bar || !fp_bar || !status || !wsp) return FBSDE_EINVAL;
+    if (!gp_bar || !fp_bar) return FBSDE_EINVAL;
+    if (P == 0) {   // the loss is an empty sum: zero parameter adjoints; the other pointers may be null
+        if (cg_iters_out)
+            for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;
+        adj_params(nullptr, 0, gp_bar, fp_bar, (hipStream_t)stream);
+        return last_error();
+    }
+    if (!x0 || !u_bar || !x0_bar || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solves
@@ -565,7 +576,6 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
     WS ws;
     if (carve(pl, P, FBSDE_WS_TAPE, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, FBSDE_WS_TAPE, (char*)wsp, ws);
-    if (P == 0) return FBSDE_OK;
     hipStream_t st = (hipStream_t)stream;
     int tag = 0;
     if (hipMemcpyAsync(&tag, ws.tag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||

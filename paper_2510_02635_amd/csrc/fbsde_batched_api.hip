@@ -203,7 +203,13 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
     int rc = tiled_size(a.pbs, n_inst, P, o, flags, &need, &units, &arena, &nw);
     if (rc) return rc;
     if (need > ws_bytes) return FBSDE_ENOSPC;
-    if (units.empty()) return FBSDE_OK;
+    if (units.empty()) {   // every instance is empty: its parameter adjoints are zero sums
+        if (adjoint)
+            for (int64_t i = 0; i < n_inst; ++i)
+                hipLaunchKernelGGL(k_sum_tiles, dim3(1), dim3(64), 0, caller, nullptr, nullptr, 0, a.gp_bar[i],
+                                   a.fp_bar[i]);
+        return last_error();
+    }
     char* base = (char*)wsp;
     double* tpart = (double*)base;   // [units][8]: gp_bar, fp_bar of each tile
     char* arenas = base + tiled_header_bytes(units.size());

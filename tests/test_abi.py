@@ -83,3 +83,25 @@ def test_autotune_validation_and_reset_on_host():
     pb = F.Problem(d=8, M=64, N=2, T=0.3)
     assert N.load().fbsde_autotune(ctypes.byref(pb.c()), 0, 1, 1, 1 << 30, ctypes.byref(r), None) == N.EINVAL
     assert N.load().fbsde_autotune_reset() == 0
+
+
+def test_size_limits_on_host():
+    # the widest rows each precision supports and the most points one call takes are accepted; one more is not
+    lib = N.load()
+    size = ctypes.c_size_t(0)
+    for prec, dmax in [(N.F64, 16384), (N.F32C, 32768)]:
+        for d, ok in [(dmax, True), (dmax + 1, False)]:
+            pb = F.Problem(d=d, M=64, N=2, T=0.3, prec=prec)
+            rc = lib.fbsde_workspace_size(ctypes.byref(pb.c()), 2, 0, ctypes.byref(size))
+            assert (rc == 0) == ok, (prec, d, rc)
+    pb = F.Problem(d=4, M=16, N=2, T=0.3)
+    assert lib.fbsde_workspace_size(ctypes.byref(pb.c()), 65535, 0, ctypes.byref(size)) == 0
+    assert lib.fbsde_workspace_size(ctypes.byref(pb.c()), 65536, 0, ctypes.byref(size)) == N.EINVAL
+    assert lib.fbsde_workspace_size(ctypes.byref(pb.c()), -1, 0, ctypes.byref(size)) == N.EINVAL
+    # the batched call tiles an instance larger than one call
+    cps = (N.CProblem * 1)(pb.c())
+    Ps = (ctypes.c_int64 * 1)(70000)
+    opts = N.CBatchOpts(N.BATCH_TILED, 2, 0, 512, 0)
+    assert lib.fbsde_batched_workspace_size(cps, 1, ctypes.cast(Ps, ctypes.c_void_p), ctypes.byref(opts), 0,
+                                            ctypes.byref(size)) == 0
+    assert size.value > 0

@@ -104,6 +104,9 @@ def main():
     sec32, u32, g32, st32, it32 = timed_solves(F, torch, pb32, x0, ws32, args.warmup, args.steps)
     log(f"[bench] fp32c: {sec32 * 1e3:.1f} ms/solve, cg iterations per level {it32}")
     mv32_ms = F.time_kernel(pb32, P, "cg_matvec", ws32, reps=6)
+    # the read ceiling on the same buffer: a plain stream over the whole [P][M][ld] state
+    rd32_ms = F.time_kernel(pb32, P, "stream_read", ws32, reps=6)
+    ld32 = F.state_ld(pb32)
     rev32_ms = F.time_kernel(pb32, P, "reverse_newton", ws32, reps=3)
     u32, g32, st32 = u32.cpu().numpy(), g32.cpu().numpy(), st32.cpu().numpy()
     del ws32
@@ -159,6 +162,11 @@ def main():
                 "frac": round(achieved32 / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_matvec<float> (fused CG product, one state read)",
                 "algorithmic_bytes_per_launch": alg_bytes32, "avg_launch_ms": round(mv32_ms, 4)}
+    ceiling = P * M * ld32 * 4 / (rd32_ms * 1e-3) / 1e9
+    roofline["read_ceiling"] = {"kernel": "k_stream_read (16-byte non-temporal loads over the same state, nothing else)",
+                                "bytes_per_launch": P * M * ld32 * 4, "avg_launch_ms": round(rd32_ms, 4),
+                                "achieved": round(ceiling, 1), "frac_of_peak": round(ceiling / HBM_PEAK_GBS, 4),
+                                "cg_product_frac_of_ceiling": round(achieved32 / ceiling, 4)}
     if mv64_ms:
         roofline["fp64_kernel"] = {"achieved": round(P * M * d * 8 / (mv64_ms * 1e-3) / 1e9, 1),
                                    "avg_launch_ms": round(mv64_ms, 4), "algorithmic_bytes_per_launch": P * M * d * 8}

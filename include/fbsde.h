@@ -179,7 +179,9 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
 /* Diagnostic: average duration (host float, milliseconds) of one launch of a hot-path kernel at
  * this problem's launch geometry, timed with HIP events on `stream` over reps - 1 launches after
  * one warm-up launch; synchronises the stream.  which: 0 fused CG product (the dominant kernel),
- * 1 particle reversal + Newton, 2 weighted moments, 3 forward sweep + terminal.  It runs on the
+ * 1 particle reversal + Newton, 2 weighted moments, 3 forward sweep + terminal, 4 a plain stream
+ * over the same state bytes (16-byte non-temporal loads, nothing else): the read bandwidth the
+ * hardware delivers on that buffer, the attainable ceiling for the CG product.  It runs on the
  * state and vectors left in ws by a preceding fbsde_solve with the same pb and P (flags 0) and
  * overwrites them: solve again before using ws for anything else. */
 int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t reps, void* ws,

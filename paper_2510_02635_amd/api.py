@@ -177,7 +177,7 @@ def normals(pb, p, k, j0, rows, device="cuda"):
     return out, words
 
 
-KERNELS = {"cg_matvec": 0, "reverse_newton": 1, "moments": 2, "forward_terminal": 3}
+KERNELS = {"cg_matvec": 0, "reverse_newton": 1, "moments": 2, "forward_terminal": 3, "stream_read": 4}
 
 
 def time_kernel(pb, P, which, ws, reps=5):

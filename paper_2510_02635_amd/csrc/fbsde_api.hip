@@ -377,6 +377,33 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     return last_error();
 }
 
+// Read ceiling of a buffer: a plain grid-stride stream over n16 16-byte words with four non-temporal
+// loads in flight per lane, XOR-reduced to one word per block (nothing but the loads costs time).  It
+// measures the read bandwidth the hardware delivers on the same bytes the CG product reads.
+__global__ void __launch_bounds__(256) k_stream_read(const uint4* __restrict__ a, int64_t n16, uint32_t* __restrict__ out) {
+    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+    const u4v* v = reinterpret_cast<const u4v*>(a);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint32_t x = 0;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u4v a0 = __builtin_nontemporal_load(v + i), a1 = __builtin_nontemporal_load(v + i + stride);
+        const u4v a2 = __builtin_nontemporal_load(v + i + 2 * stride), a3 = __builtin_nontemporal_load(v + i + 3 * stride);
+        const u4v t = a0 ^ a1 ^ a2 ^ a3;
+        x ^= t.x ^ t.y ^ t.z ^ t.w;
+    }
+    for (; i < n16; i += stride) {
+        const u4v t = __builtin_nontemporal_load(v + i);
+        x ^= t.x ^ t.y ^ t.z ^ t.w;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x ^= (uint32_t)__shfl_xor((int)x, off, 64);
+    __shared__ uint32_t red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
+}
+
 }  // namespace
 
 namespace fbsde {
@@ -613,7 +640,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
     if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
-    if (!wsp || !avg_ms || reps < 1 || which < 0 || which > 3 || P == 0) return FBSDE_EINVAL;
+    if (!wsp || !avg_ms || reps < 1 || which < 0 || which > 4 || P == 0) return FBSDE_EINVAL;
     WS ws;
     if (carve(pl, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, 0, (char*)wsp, ws);
@@ -638,6 +665,14 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
                 });
             } else if (which == 1) {
                 launch_reverse<S>(pb, pl, P, 1, W, ldw, ws.x, ws, ws.Yb, ws.rn2, (uint32_t*)ws.iscal, st);
+            } else if (which == 4) {
+                // the state's bytes, one XOR word per block into the chunk partials (>= P ld doubles)
+                const int64_t n16 = (int64_t)P * pl.M * pl.ld * (int64_t)sizeof(S) / 16;
+                const int64_t cap = 2 * (int64_t)P * pl.nchunk * pl.ld;
+                const unsigned blocks = (unsigned)std::max<int64_t>(
+                    1, std::min<int64_t>({32768, cap, (n16 + 1023) / 1024}));
+                hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(256), 0, st, (const uint4*)W, n16,
+                                   (uint32_t*)ws.part1);
             } else if (which == 2) {
                 dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
                     constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
@@ -782,7 +817,7 @@ int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, do
     hipStream_t cap;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return FBSDE_EHIP;
     hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { hipStreamDestroy(cap); return FBSDE_EHIP; }
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { (void)hipStreamDestroy(cap); return FBSDE_EHIP; }
     int err = FBSDE_OK;
     if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess || hipStreamWaitEvent(cap, ev, 0) != hipSuccess)
         err = FBSDE_EHIP;
@@ -795,16 +830,16 @@ int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, do
     }
     hipGraphExec_t exec = nullptr;
     if (!err && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) err = FBSDE_EHIP;
-    hipEventDestroy(ev);
-    hipStreamDestroy(cap);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cap);
     if (err) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return err;
     }
     fbsde_graph h = new (std::nothrow) fbsde_graph_s{g, exec};
     if (!h) {
-        hipGraphExecDestroy(exec);
-        hipGraphDestroy(g);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(g);
         return FBSDE_EINVAL;
     }
     *out = h;

@@ -217,7 +217,7 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
     if (hipGetDevice(&dev) != hipSuccess) return FBSDE_EHIP;
     hipEvent_t ev0;
     if (hipEventCreateWithFlags(&ev0, hipEventDisableTiming) != hipSuccess) return FBSDE_EHIP;
-    if (hipEventRecord(ev0, caller) != hipSuccess) { hipEventDestroy(ev0); return FBSDE_EHIP; }
+    if (hipEventRecord(ev0, caller) != hipSuccess) { (void)hipEventDestroy(ev0); return FBSDE_EHIP; }
     std::atomic<int> next{0}, first_err{0};
     auto fail = [&](int e) { int z = 0; first_err.compare_exchange_strong(z, e); };
     auto worker = [&](int w) {
@@ -247,12 +247,12 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
             if (e) fail(e);
         }
         if (hipStreamSynchronize(s) != hipSuccess) fail(FBSDE_EHIP);
-        hipStreamDestroy(s);
+        (void)hipStreamDestroy(s);
     };
     std::vector<std::thread> pool;
     for (int w = 0; w < nw; ++w) pool.emplace_back(worker, w);
     for (auto& th : pool) th.join();
-    hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev0);
     if ((rc = first_err.load())) return rc;
     if (adjoint) {
         // per instance, the indices of its tiles in point order, then one summing launch each

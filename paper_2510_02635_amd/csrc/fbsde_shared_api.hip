@@ -93,7 +93,6 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
     T* xc = (T*)ws.xc;
     const int M = (int)pl.M, ld = pl.ld, d = (int)pl.d, Pi = (int)P;
     const double dt = pb->T / (double)pb->N, s = pb->s, s2 = s * s;
-    const Keys ky = keys_of(pb);
     const FSpec fs = fspec_of(pb);
     clear_status(status, P, st);
     set_int(ws.info, 0, st);

@@ -62,3 +62,24 @@ def test_tuned_shape_keeps_parity(prec, tol):
     u1, g1, _ = F.solve(hp, xt)
     torch.cuda.synchronize()
     assert torch.equal(u1, u0) and torch.equal(g1, g0)   # the default shape again, bit for bit
+
+
+@pytest.mark.parametrize("prec", [F.F64, F.F32C], ids=["fp64", "fp32c"])
+def test_kernel_timer_and_read_ceiling(prec):
+    # every timed kernel returns a positive duration; the read-ceiling stream leaves the state bytes as they were
+    hp, _ = problems(d=300, M=256, N=2, T=0.3, prec=prec, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
+                     gp=(0.4, 0, 0, 0))
+    P = 5
+    xt = torch.tensor(workloads.points("normal:0.3", P, 300, 2), device=DEV)
+    ws = F.workspace(hp, P)
+    F.solve(hp, xt, ws=ws)
+    torch.cuda.synchronize()
+    state_bytes = P * hp.M * F.state_ld(hp) * (8 if prec == F.F64 else 4)
+    before = ws[:state_bytes].clone()
+    ms = F.time_kernel(hp, P, "stream_read", ws, reps=3)
+    _say(f"[timer] {prec}: stream_read {ms:.4f} ms")
+    assert ms > 0 and torch.equal(ws[:state_bytes], before)
+    for which in ("cg_matvec", "reverse_newton", "moments", "forward_terminal"):
+        t = F.time_kernel(hp, P, which, ws, reps=2)
+        _say(f"  {which} {t:.4f} ms")
+        assert t > 0

@@ -176,6 +176,13 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
 int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows,
                   double* out, uint32_t* words, fbsde_stream stream);
 
+/* Diagnostic: the Box-Muller step alone on caller-given Philox words, exactly as the kernels apply
+ * it in `prec` (FBSDE_F64, or FBSDE_F32C with its FP32 logarithm, hardware square root and sin/cos
+ * on the exactly reduced angle; FP32 values written as doubles).  Lets a test reach the words that
+ * counters rarely produce: 0, 2^32 - 1, the mantissa switch at sqrt(2), the octant boundaries.
+ *   words device [n][4] (pairs (0,1) and (2,3) as in the normals above);  out device [n][4]. */
+int fbsde_box_muller(int32_t prec, int64_t n, const uint32_t* words, double* out, fbsde_stream stream);
+
 /* Diagnostic: average duration (host float, milliseconds) of one launch of a hot-path kernel at
  * this problem's launch geometry, timed with HIP events on `stream` over reps - 1 launches after
  * one warm-up launch; synchronises the stream.  which: 0 fused CG product (the dominant kernel),

@@ -12,7 +12,7 @@ ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
 WS_TAPE = 1
 
 EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
-            "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
+            "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
             "fbsde_autotune", "fbsde_autotune_reset", "fbsde_strerror")
@@ -80,6 +80,7 @@ def load():
     lib.fbsde_solve_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
     lib.fbsde_normals.argtypes = [pb, i64, i32, i64, i64, vp, vp, vp]
     lib.fbsde_time_kernel.argtypes = [pb, i64, i32, i32, vp, sz, P(ctypes.c_float), vp]
+    lib.fbsde_box_muller.argtypes = [i32, i64, vp, vp, vp]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
                                ctypes.c_double, vp]
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]
@@ -96,7 +97,7 @@ def load():
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
-                 "fbsde_solve_backward", "fbsde_normals", "fbsde_time_kernel", "fbsde_gemm",
+                 "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm",
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset"):

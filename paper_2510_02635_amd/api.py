@@ -177,6 +177,17 @@ def normals(pb, p, k, j0, rows, device="cuda"):
     return out, words
 
 
+def box_muller(words, prec):
+    """Box-Muller normals [n][4] of Philox words [n][4] (int32 device tensor holding the uint32 bits), as the
+    kernels compute them in `prec`."""
+    if words.dtype != torch.int32 or not words.is_cuda or not words.is_contiguous() or words.dim() != 2 \
+            or words.shape[1] != 4:
+        raise ValueError("expected a contiguous int32 device tensor of shape [n][4]")
+    out = torch.empty(words.shape, dtype=torch.float64, device=words.device)
+    N.check(N.load().fbsde_box_muller(int(prec), words.shape[0], words.data_ptr(), out.data_ptr(), _stream()))
+    return out
+
+
 KERNELS = {"cg_matvec": 0, "reverse_newton": 1, "moments": 2, "forward_terminal": 3, "stream_read": 4}
 
 

@@ -377,6 +377,18 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     return last_error();
 }
 
+// Box-Muller normals of caller-given Philox words, exactly as the hot-path kernels form them.
+template <typename R>
+__global__ void k_box_muller(int64_t n, const uint32_t* __restrict__ words, double* __restrict__ out) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const Words4 w = {words[4 * t], words[4 * t + 1], words[4 * t + 2], words[4 * t + 3]};
+        R z[4];
+        box_muller4<R>(w, z);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[4 * t + e] = (double)z[e];
+    }
+}
+
 // Read ceiling of a buffer: a plain grid-stride stream over n16 16-byte words with four non-temporal
 // loads in flight per lane, XOR-reduced to one word per block (nothing but the loads costs time).  It
 // measures the read bandwidth the hardware delivers on the same bytes the CG product reads.
@@ -630,6 +642,18 @@ int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int
     else
         hipLaunchKernelGGL(k_normals<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (int)pb->d, j0, rows, k, q, ky.k0,
                        ky.k1, out, words);
+    return last_error();
+}
+
+int fbsde_box_muller(int32_t prec, int64_t n, const uint32_t* words, double* out, fbsde_stream stream) {
+    if (n < 0 || (prec != FBSDE_F64 && prec != FBSDE_F32C)) return FBSDE_EINVAL;
+    if (n == 0) return FBSDE_OK;
+    if (!words || !out) return FBSDE_EINVAL;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (prec == FBSDE_F64)
+        hipLaunchKernelGGL(k_box_muller<double>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, n, words, out);
+    else
+        hipLaunchKernelGGL(k_box_muller<float>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, n, words, out);
     return last_error();
 }
 

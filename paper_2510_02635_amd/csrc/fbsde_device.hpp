@@ -89,9 +89,13 @@ __device__ __forceinline__ void sincos_turn<float>(uint32_t w, float& sn, float&
     pc = pc * z - 1.0f / 24.0f;
     pc = pc * z + 0.5f;
     const float c_ = 1.0f - z * pc;
+    // angle = psi + q pi/2: odd q swaps sin and cos, and the signs are flipped in the sign bit
+    // (sin: q = 2, 3; cos: q = 1, 2)
     const uint32_t q = ((o + 1u) >> 1) & 3u;
-    sn = (q == 0) ? s_ : (q == 1) ? c_ : (q == 2) ? -s_ : -c_;
-    cs = (q == 0) ? c_ : (q == 1) ? -s_ : (q == 2) ? -c_ : s_;
+    const bool sw = (q & 1u) != 0u;
+    const float a = sw ? c_ : s_, b = sw ? s_ : c_;
+    sn = __uint_as_float(__float_as_uint(a) ^ ((q >> 1) << 31));
+    cs = __uint_as_float(__float_as_uint(b) ^ (((q ^ (q >> 1)) & 1u) << 31));
 }
 
 // ln u for u = (w + 1/2) 2^-32 in FP64.  x = w + 1/2 is exact; frexp gives x = m 2^e exactly with
@@ -124,28 +128,23 @@ __device__ __forceinline__ double log_unit(uint32_t w) {
 
 // ln u for u = (w + 1/2) 2^-32 in FP32 (the FP32C mode, whose state is FP32).  The reduction is done in
 // integers so that m - 1 keeps full relative accuracy as u -> 1: with x = w + 1/2 = 2^e (1 + f),
-// e = floor(log2 w), the numerator of m - 1 over 2^(e+1) is the exact integer 2 (w - 2^e) + 1; for
-// m >= sqrt(2) the mantissa is halved, m/2 - 1 = -(2^(e+2) - 2w - 1) / 2^(e+2).  Then
-// ln m = 2 atanh(z), z = (m - 1)/(m + 1), |z| <= 0.1716: five odd terms leave a truncation below
-// 2e-9 relative.  (e - 32) ln 2 with ln 2 split into a 16-bit head (exact products) and a tail.
+// e = floor(log2 w), the numerator of m - 1 over 2^(e+1) is the exact integer 2 (w - 2^e) + 1; once
+// w / 2^e reaches sqrt(2) the mantissa is halved, m/2 - 1 = -(2^(e+2) - 2w - 1) / 2^(e+2) (both
+// numerators fit 32 bits; 2^(e+2) wraps to 0 for e >= 30, which leaves the difference exact).  Both
+// candidates are formed and one is selected, with no branch.  Then ln m = 2 atanh(z),
+// z = (m - 1)/(m + 1), |z| <= 0.1716, with the hardware reciprocal (about 1 ulp) for the division and
+// five odd terms (truncation below 2e-9 relative); (e - 32) ln 2 with ln 2 split into a 16-bit head
+// (exact products) and a tail.  Over all 2^32 words, sqrt(-2 ln u) from this logarithm and the hardware
+// square root stays within 2.5 FP32 ulps of the FP64 form.
 __device__ __forceinline__ float log_unit_f32(uint32_t w) {
-    if (w == 0u) return -33.0f * 0.693145751953125f - 33.0f * 1.4286068e-06f;   // u = 2^-33
-    const int e = 31 - __clz((int)w);                                         // 2^e <= w < 2^(e+1)
-    // halve m when it reaches sqrt(2): m = (2w + 1) / 2^(e+1); the exact switching point does not
-    // matter (either branch is exact in its reduction, |z| stays at the 0.1716 bound to FP32 rounding)
-    const bool upper = (float)(2u * (uint64_t)w + 1u) >= 1.41421356f * ldexpf(1.0f, e + 1);
-    float mm1;   // m - 1 (or m/2 - 1), exact integer numerator, one rounding
-    int k;
-    if (!upper) {
-        const uint32_t t = 2u * (w - (1u << e)) + 1u;
-        mm1 = ldexpf((float)t, -(e + 1));
-        k = e - 32;
-    } else {
-        const uint64_t t = ((uint64_t)1 << (e + 2)) - 2u * (uint64_t)w - 1u;
-        mm1 = -ldexpf((float)t, -(e + 2));
-        k = e + 1 - 32;
-    }
-    const float z = mm1 / (2.0f + mm1);
+    const int e = 31 - __clz((int)(w | 1u));                 // 2^e <= w < 2^(e+1); w = 0 selected below
+    const bool upper = (w << (31 - e)) >= 0xB504F334u;       // w / 2^e >= sqrt(2)
+    const uint32_t t_lo = 2u * (w - (1u << e)) + 1u;
+    const uint32_t t_hi = ((e >= 30) ? 0u : (1u << (e + 2))) - 2u * w - 1u;
+    const float mag = ldexpf((float)(upper ? t_hi : t_lo), upper ? -(e + 2) : -(e + 1));   // one rounding
+    const float mm1 = upper ? -mag : mag;                    // m - 1 (or m/2 - 1)
+    const int k = upper ? (e - 31) : (e - 32);
+    const float z = mm1 * __builtin_amdgcn_rcpf(2.0f + mm1);
     const float z2 = z * z;
     float sr = 1.0f / 9.0f;
     sr = sr * z2 + 1.0f / 7.0f;
@@ -153,20 +152,26 @@ __device__ __forceinline__ float log_unit_f32(uint32_t w) {
     sr = sr * z2 + 1.0f / 3.0f;
     const float lnm = 2.0f * z + 2.0f * z * z2 * sr;
     const float kf = (float)k;
-    return kf * 0.693145751953125f + (kf * 1.4286068e-06f + lnm);
+    const float r = kf * 0.693145751953125f + (kf * 1.4286068e-06f + lnm);
+    return (w == 0u) ? (-33.0f * 0.693145751953125f - 33.0f * 1.4286068e-06f) : r;   // u = 2^-33
 }
 
-template <typename R> __device__ __forceinline__ R log_unit_r(uint32_t w);
-template <> __device__ __forceinline__ double log_unit_r<double>(uint32_t w) { return log_unit(w); }
-template <> __device__ __forceinline__ float log_unit_r<float>(uint32_t w) { return log_unit_f32(w); }
 
 // Four normals from one Philox call: Box-Muller on the word pairs (x, y) and (z, w) with
 // u = (w + 1/2) 2^-32 in (0, 1); radius sqrt(-2 ln u_even) and angle 2 pi u_odd, both in the element
 // type (FP64 logarithm for the FP64 mode, the FP32 one above for FP32C).
+template <typename R> __device__ __forceinline__ R radius_of(uint32_t w);
+template <> __device__ __forceinline__ double radius_of<double>(uint32_t w) { return sqrt(-2.0 * log_unit(w)); }
+// -2 ln u lies in [2.3e-10, 46]: no zero, denormal or overflow, so the hardware square root (not the
+// correctly rounded sequence) is enough
+template <> __device__ __forceinline__ float radius_of<float>(uint32_t w) {
+    return __builtin_amdgcn_sqrtf(-2.0f * log_unit_f32(w));
+}
+
 template <typename R>
 __device__ __forceinline__ void box_muller4(const Words4& w, R z[4]) {
-    const R r0 = sqrt((R)-2 * log_unit_r<R>(w.x));
-    const R r2 = sqrt((R)-2 * log_unit_r<R>(w.z));
+    const R r0 = radius_of<R>(w.x);
+    const R r2 = radius_of<R>(w.z);
     R s1, c1, s3, c3;
     sincos_turn<R>(w.y, s1, c1);
     sincos_turn<R>(w.w, s3, c3);

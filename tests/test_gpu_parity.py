@@ -200,3 +200,56 @@ def test_affine_closed_form_on_gpu():
         ue = (a @ (x0[p] + mu * T) + b) / fac
         assert abs(u[p].item() - ue) <= 1e-11 * max(1, abs(ue))
         assert rel_err(g[p].cpu().numpy(), a / fac) <= 1e-11
+
+
+def _extreme_words():
+    """Philox words that counters rarely produce, in quadruples (radius word, angle word, radius, angle)."""
+    rad = {0, 1, 2, 3, 4, 5, 0xFFFFFFFF, 0xFFFFFFFE, 0xFFFFFFFD, 0x7FFFFFFF, 0x80000000, 0x80000001, 0x55555555}
+    for e in range(32):
+        rad.update({(1 << e) - 1, 1 << e, (1 << e) + 1})
+        s = int(math.floor(math.sqrt(2.0) * (1 << e)))          # the mantissa switch at sqrt(2)
+        rad.update(range(max(s - 2, 0), s + 3))
+    rad = sorted(v for v in rad if 0 <= v <= 0xFFFFFFFF)
+    ang = {0, 1, 2, 0xFFFFFFFF, 0xFFFFFFFE}
+    for k in range(8):                                         # octant boundaries
+        ang.update(((k << 29) + dv) % (1 << 32) for dv in (-2, -1, 0, 1, 2))
+    ang = sorted(ang)
+    rng = np.random.default_rng(17)
+    rad += [int(v) for v in rng.integers(0, 1 << 32, 64, dtype=np.uint64)]
+    ang += [int(v) for v in rng.integers(0, 1 << 32, 32, dtype=np.uint64)]
+    quads = [(r, ang[i % len(ang)], rad[(i + 1) % len(rad)], ang[(7 * i + 3) % len(ang)]) for i, r in enumerate(rad)]
+    quads += [(0x55555555, a, 0xFFFFFFFF, a) for a in ang]
+    return np.array(quads, dtype=np.uint64)
+
+
+def _box_muller_mp(quads):
+    """Reference normals at 40 significant digits (independent of both the oracle's FP64 and the kernels)."""
+    import mpmath
+    mpmath.mp.dps = 40
+    out = np.zeros(quads.shape, dtype=np.float64)
+    two32 = mpmath.mpf(2) ** 32
+    for n, (a, b, c, d) in enumerate(quads.tolist()):
+        for slot, (wr, wa) in enumerate(((a, b), (c, d))):
+            r = mpmath.sqrt(-2 * mpmath.log((wr + mpmath.mpf("0.5")) / two32))
+            t = 2 * mpmath.pi * (wa + mpmath.mpf("0.5")) / two32
+            out[n, 2 * slot] = float(r * mpmath.cos(t))
+            out[n, 2 * slot + 1] = float(r * mpmath.sin(t))
+    return out
+
+
+@pytest.mark.parametrize("prec,bits,max_ulps", [(F.F64, 52, 16.0), (F.F32C, 23, 8.0)], ids=["fp64", "fp32c"])
+def test_box_muller_at_extreme_words(prec, bits, max_ulps):
+    """The transform at u -> 0 (w = 0: the largest radius), u -> 1 (w = 2^32 - 1: radius ~1.5e-5), every power of
+    two and the sqrt(2) switch of the logarithm's reduction, and angles at the eight octant boundaries, against a
+    40-digit reference: every component within `max_ulps` units in the last place of its own magnitude."""
+    quads = _extreme_words()
+    ref = _box_muller_mp(quads)
+    words = torch.tensor(quads.astype(np.uint32).view(np.int32), device=DEV)
+    got = F.box_muller(words, prec).cpu().numpy()
+    ulp = np.exp2(np.floor(np.log2(np.abs(ref))) - bits)
+    err = np.abs(got - ref) / ulp
+    i = np.unravel_index(np.argmax(err), err.shape)
+    _say(f"[box-muller extremes] prec={prec} {quads.shape[0]} quadruples, max {err.max():.2f} ulps at words "
+         f"{quads[i[0]].tolist()} slot {i[1]}, median {np.median(err):.2f}")
+    assert np.all(np.isfinite(got))
+    assert err.max() <= max_ulps

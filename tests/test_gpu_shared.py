@@ -35,7 +35,8 @@ def _gpu():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("m,n,k", [(16, 16, 4), (129, 70, 33), (300, 257, 1000), (64, 2048, 17)])
+@pytest.mark.parametrize("m,n,k", [(16, 16, 4), (129, 70, 33), (300, 257, 1000), (64, 2048, 17), (200, 130, 1500),
+                                   (70, 300, 3001)])
 @pytest.mark.parametrize("nt", [True, False])
 def test_gemm_matches_reference(dtype, m, n, k, nt):
     _say(f"[gemm] {dtype} m={m} n={n} k={k} nt={nt}")

@@ -173,6 +173,7 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
     // factorisation and of the inverse) keep plain FP32 accumulation.
     constexpr bool FOLD = FOLD_LONG && std::is_same<T, float>::value;
     double fsum[FOLD ? TM : 1][FOLD ? TN : 1][4];
+    constexpr int FOLD_TILES = (256 / BK > 0) ? 256 / BK : 1;   // K tiles per 256-term FP32 partial sum
     if constexpr (FOLD) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -187,22 +188,33 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
     store_tile();
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
+    // operand fragments of one 4-deep K step, double-buffered in registers; the scheduling groups
+    // below order the LDS reads of step kk + 4 ahead of the MFMAs of step kk, so their latency hides
+    // behind the matrix cores instead of stalling them once per step
+    T af[2][TM], bf[2][TN];
+    auto frag = [&](int kk, int b) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[b][i] = As[kk + lk][wm * WM + 16 * i + li];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bf[b][j] = Bs[kk + lk][wn * WN + 16 * j + li];
+    };
     for (int kt = 0; kt < nk; ++kt) {
         if (kt + 1 < nk) load_tile((kt + 1) * BK);
+        frag(0, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, (TM + TN) / 2, 0);   // the first step's reads
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            T af[TM], bf[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = As[kk + lk][wm * WM + 16 * i + li];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) bf[j] = Bs[kk + lk][wn * WN + 16 * j + li];
+            const int b = (kk / 4) & 1;
+            if (kk + 4 < BK) frag(kk + 4, b ^ 1);
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = Cfg::mfma(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < TN; ++j) acc[i][j] = Cfg::mfma(af[b][i], bf[b][j], acc[i][j]);
+            if (kk + 4 < BK) __builtin_amdgcn_sched_group_barrier(0x100, (TM + TN) / 2, 0);   // LDS reads
+            __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);                           // MFMAs
         }
         if constexpr (FOLD) {
-            if ((kt & 7) == 7 || kt + 1 == nk) {
+            if (kt % FOLD_TILES == FOLD_TILES - 1 || kt + 1 == nk) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll

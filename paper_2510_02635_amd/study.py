@@ -1,0 +1,182 @@
+"""Convergence-order and cost-scaling study of the scheme on the GPU path.
+
+Order in the time step (the global error bound of Theorem 3.1: first order in dt, with the Monte Carlo
+part decaying in M; the paper observes error proportional to dt in Sec. 4).  Allen-Cahn Case 1 of
+Sec. 4.1 (d = 100, T = 0.3, x0 = 0, f = u - u^3, g = 1/(2 + 0.4|x|^2), uniform weights): P evaluation points
+all at x0 = 0 run in one call; each point draws its own Philox stream, so the P values of u(0, 0) are
+independent replicas, and the level counters are shared between time grids, so u_p(N) - u_p(2N) are
+common-random-number differences.  The slope of log |mean_p (u_p(N) - u_p(2N))| against log dt
+estimates the order; 2 u(2N) - u(N) at the finest pair is the Richardson value compared with the
+printed reference.  The affine case (g = a.x + b, f = c1 y) has the closed form
+u = (a.(x0 + mu T) + b) / (1 - c1 dt)^N against the exact e^{c1 T} (a.(x0 + mu T) + b): its error is
+first order with no Monte Carlo part at all.
+
+Cost scaling (the cost claim of Sec. 2.4: work linear in N M per evaluation point): solve time over a
+grid of N and M at d = 1000, with the number of passes over the particle state counted from the CG
+iterations, so the time per pass (bandwidth) is compared across the grid.
+
+Run:  python -m paper_2510_02635_amd.study [--replicas P] [--prec f64|f32c]
+"""
+import argparse
+import math
+import sys
+import time
+
+import numpy as np
+
+AC_REFERENCE = 0.0528   # Sec. 4.1 Case 1, d = 100, u(0, 0), three printed digits
+
+
+def _problem(F, d, M, N, prec, T=0.3, **kw):
+    base = dict(f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0), eps_h=0.0)
+    base.update(kw)
+    return F.Problem(d=d, M=M, N=N, T=T, prec=prec, **base)
+
+
+def allen_cahn_order(F, torch, Ns=(5, 10, 20, 40, 80), M=4096, replicas=4096, prec=None, d=100):
+    """u_p(0, 0) for every N on the same replicas; returns the per-N means, the common-random-number
+    differences with their standard errors, the fitted order and the Richardson value."""
+    prec = F.F64 if prec is None else prec
+    x0 = torch.zeros((replicas, d), dtype=torch.float64, device="cuda")
+    us, times = {}, {}
+    for N in Ns:
+        pb = _problem(F, d, M, N, prec)
+        ws = F.workspace(pb, replicas)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, _, st = F.solve(pb, x0, want_grad=False, ws=ws)
+        torch.cuda.synchronize()
+        times[N] = time.perf_counter() - t0
+        if int((st != 0).sum().item()):
+            raise RuntimeError(f"status flags set at N = {N}")
+        us[N] = u.cpu().numpy()
+        del ws
+    rows = []
+    for a, b in zip(Ns[:-1], Ns[1:]):
+        diff = us[a] - us[b]
+        rows.append(dict(N=a, N2=b, dt=0.3 / a, diff=float(diff.mean()),
+                         se=float(diff.std(ddof=1) / math.sqrt(diff.size))))
+    dts = np.array([r["dt"] for r in rows])
+    ds = np.array([abs(r["diff"]) for r in rows])
+    slope = float(np.polyfit(np.log(dts), np.log(ds), 1)[0])
+    nf, nc = Ns[-1], Ns[-2]
+    richardson = float(2 * us[nf].mean() - us[nc].mean())
+    return dict(means={N: float(us[N].mean()) for N in Ns},
+                se={N: float(us[N].std(ddof=1) / math.sqrt(us[N].size)) for N in Ns},
+                diffs=rows, slope=slope, richardson=richardson, times=times, M=M, replicas=replicas, prec=prec)
+
+
+def affine_order(F, torch, Ns=(4, 8, 16, 32, 64), c1=0.7, T=0.5, d=24, M=96, prec=None):
+    """Error of the closed-form affine case against the exact PDE value, and its fitted order."""
+    prec = F.F64 if prec is None else prec
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(d)
+    x0 = rng.standard_normal((2, d))
+    b = 0.4
+    gvec = torch.tensor(a, dtype=torch.float64, device="cuda")
+    xt = torch.tensor(x0, device="cuda")
+    exact = math.exp(c1 * T) * (x0 @ a + b)
+    errs = {}
+    for N in Ns:
+        pb = F.Problem(d=d, M=M, N=N, T=T, f_kind=F.F_ALLEN_CAHN, fp=(c1, 0, 0, 0), g_kind=F.G_AFFINE,
+                       gp=(b, 0, 0, 0), gvec=gvec, ridge_rel=0.0, prec=prec)
+        u, _, st = F.solve(pb, xt, want_grad=False)
+        torch.cuda.synchronize()
+        errs[N] = float(np.max(np.abs(u.cpu().numpy() - exact) / np.abs(exact)))
+    dts = np.array([T / N for N in Ns])
+    slope = float(np.polyfit(np.log(dts), np.log([errs[N] for N in Ns]), 1)[0])
+    return dict(errors=errs, slope=slope)
+
+
+def cost_scaling(F, torch, Ns=(5, 10, 20, 40), Ms=(1024, 2048, 4096, 8192), d=1000, points=256, prec=None):
+    """Solve time over a grid of N and M; passes over the state counted from the CG iterations."""
+    prec = F.F32C if prec is None else prec
+    x0 = 0.5 * torch.randn((points, d), dtype=torch.float64, device="cuda",
+                           generator=torch.Generator(device="cuda").manual_seed(1))
+    rows = []
+    for M in Ms:
+        for N in Ns:
+            pb = _problem(F, d, M, N, prec, eps_h=1.0)
+            ws = F.workspace(pb, points)
+            F.solve(pb, x0, ws=ws)                 # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st, iters = F.solve(pb, x0, ws=ws, return_iters=True)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            # passes: 1 forward write, per level 1 moments + K CG products + reversal read/write (read only
+            # at level 0), warm-start products counted inside K
+            passes = 1 + sum(1 + k + 2 for k in iters) - 1
+            state = points * M * F.state_ld(pb) * (8 if prec == F.F64 else 4)
+            rows.append(dict(N=N, M=M, ms=sec * 1e3, cg=sum(iters), passes=passes,
+                             ms_per_NM=sec * 1e3 / (N * M) * 1e3, gbs=passes * state / sec / 1e9,
+                             status=int((st != 0).sum().item())))
+            del ws
+    return rows
+
+
+def report(order, affine, cost):
+    out = []
+    p = "FP64" if order["prec"] == 0 else "FP32C"
+    out.append(f"## Order in dt: Allen-Cahn Case 1 (d = 100, x0 = 0, T = 0.3, uniform weights), {p}, "
+               f"M = {order['M']}, {order['replicas']} replicas")
+    out.append("")
+    out.append("| N | dt | mean u(0,0) | standard error | solve s |")
+    out.append("|---|---|---|---|---|")
+    for N, m in order["means"].items():
+        out.append(f"| {N} | {0.3 / N:.5f} | {m:.6f} | {order['se'][N]:.1e} | {order['times'][N]:.2f} |")
+    out.append("")
+    out.append("| N -> 2N | mean of u_p(N) - u_p(2N) | standard error | ratio to the next |")
+    out.append("|---|---|---|---|")
+    for i, r in enumerate(order["diffs"]):
+        ratio = (f"{r['diff'] / order['diffs'][i + 1]['diff']:.2f}" if i + 1 < len(order["diffs"]) else "-")
+        out.append(f"| {r['N']} -> {r['N2']} | {r['diff']:.3e} | {r['se']:.1e} | {ratio} |")
+    out.append("")
+    out.append(f"Fitted order (slope of log |difference| against log dt): {order['slope']:.3f}. "
+               f"Richardson value 2 u(N_max) - u(N_max / 2) = {order['richardson']:.5f} "
+               f"(printed reference {AC_REFERENCE}, three digits).")
+    out.append("")
+    out.append("## Order in dt: affine closed form (g = a.x + b, f = c1 u, c1 = 0.7, T = 0.5, d = 24, M = 96)")
+    out.append("")
+    out.append("| N | relative error against e^{c1 T} g |")
+    out.append("|---|---|")
+    for N, e in affine["errors"].items():
+        out.append(f"| {N} | {e:.4e} |")
+    out.append("")
+    out.append(f"Fitted order: {affine['slope']:.4f} (no Monte Carlo error: every level's fit is exact).")
+    out.append("")
+    out.append("## Cost in N and M (d = 1000, 256 points, Allen-Cahn, Gaussian weights h = 1, FP32C)")
+    out.append("")
+    out.append("| M | N | solve ms | CG iterations (sum over levels) | state passes | ms per (N M) x 1e3 | GB/s over the passes |")
+    out.append("|---|---|---|---|---|---|---|")
+    for r in cost:
+        out.append(f"| {r['M']} | {r['N']} | {r['ms']:.1f} | {r['cg']} | {r['passes']} | {r['ms_per_NM']:.4f} | "
+                   f"{r['gbs']:.0f} |")
+    return "\n".join(out)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--replicas", type=int, default=4096)
+    ap.add_argument("--M", type=int, default=4096)
+    ap.add_argument("--prec", choices=("f64", "f32c"), default="f64")
+    ap.add_argument("--no-cost", action="store_true")
+    args = ap.parse_args(argv)
+    import torch
+    import paper_2510_02635_amd as F
+    if not torch.cuda.is_available():
+        raise SystemExit("the study runs on the GPU path only")
+    prec = F.F64 if args.prec == "f64" else F.F32C
+    print("[study] order in dt, Allen-Cahn", file=sys.stderr, flush=True)
+    order = allen_cahn_order(F, torch, M=args.M, replicas=args.replicas, prec=prec)
+    print("[study] order in dt, affine closed form", file=sys.stderr, flush=True)
+    affine = affine_order(F, torch, prec=prec)
+    cost = []
+    if not args.no_cost:
+        print("[study] cost grid", file=sys.stderr, flush=True)
+        cost = cost_scaling(F, torch)
+    print(report(order, affine, cost))
+
+
+if __name__ == "__main__":
+    main()

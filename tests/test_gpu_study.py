@@ -1,0 +1,64 @@
+"""Convergence-order study on the GPU path (the scheme's global error is first order in dt, Theorem 3.1;
+the paper reports error proportional to dt in Sec. 4): Allen-Cahn Case 1 of Sec. 4.1 with independent
+replicas of u(0, 0), and the affine closed form whose only error is the time discretisation."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2510_02635_amd as F  # noqa: E402
+from paper_2510_02635_amd import study  # noqa: E402
+from oracle import scheme as OS  # noqa: E402
+
+from _convert import problems  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F._native.load()
+
+
+def test_study_configuration_matches_oracle():
+    # the study's problem (uniform weights, x0 = 0) on the GPU against the oracle, two replicas
+    kw = dict(d=100, M=512, N=5, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,
+              gp=(0.4, 0, 0, 0), eps_h=0.0)
+    hp, op = problems(**kw)
+    u, g, st = F.solve(hp, torch.zeros((2, 100), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    for p in range(2):
+        ref = OS.solve_point(op, np.zeros(100), p)
+        e = abs(u[p].item() - ref["u"]) / abs(ref["u"])
+        _say(f"[study parity] p={p} u={u[p].item():.12g} oracle={ref['u']:.12g} rel={e:.1e}")
+        assert e <= 1e-10 and int(st[p].item()) == 0
+
+
+@pytest.mark.parametrize("M", [1024, 4096])
+def test_allen_cahn_first_order_in_dt(M):
+    res = study.allen_cahn_order(F, torch, Ns=(5, 10, 20, 40, 80), M=M, replicas=4096)
+    for r in res["diffs"]:
+        _say(f"[order M={M}] N={r['N']}->{r['N2']} diff={r['diff']:.3e} se={r['se']:.1e}")
+    _say(f"[order M={M}] slope {res['slope']:.3f}, Richardson {res['richardson']:.5f}")
+    # every difference is resolved above the replicas' noise, the order is one, and the extrapolated
+    # value agrees with the three printed digits
+    assert all(abs(r["diff"]) > 3 * r["se"] for r in res["diffs"])
+    assert 0.7 <= res["slope"] <= 1.3
+    assert abs(res["richardson"] - study.AC_REFERENCE) < 5e-4
+
+
+def test_affine_closed_form_is_first_order():
+    res = study.affine_order(F, torch)
+    errs = [res["errors"][N] for N in sorted(res["errors"])]
+    _say(f"[affine order] errors {['%.3e' % e for e in errs]} slope {res['slope']:.4f}")
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert abs(res["slope"] - 1.0) < 0.05

@@ -9,6 +9,12 @@
   with Z_1 ~ N(0, 1) and C ~ chi^2_{d-1} independent, sigma = s sqrt(T).  Z_1 is integrated by
   Gauss-Hermite; C by generalized Gauss-Laguerre for small d - 1 and by Gauss-Legendre on
   +-60 standard deviations of the Gamma(k/2, 2) law (log-density via lgamma) for large d - 1.
+* Burgers-type case (derived here; the printed Burgers PDE of the paper's Sec. 4 loses a coefficient):
+  u(t, x) = phi(t + sum_i x_i / d) with the logistic phi(a) = 1 / (1 + e^-a) solves
+  d_t u + (s^2/2) Lap u + c (u - kappa) sum_i z_i = 0, z = s grad u, for c = s / d and
+  kappa = d / s^2 + 1/2: with phi' = phi (1 - phi) and phi'' = phi' (1 - 2 phi) the left side is
+  phi' [1 + s^2 (1 - 2 phi) / (2d) + c s (phi - kappa)], zero for all phi exactly at those c, kappa.
+  The terminal condition is the logistic g with gvec = 1/d and offset T.
 """
 import numpy as np
 from numpy.polynomial.hermite_e import hermegauss
@@ -60,3 +66,18 @@ def hjb_log_cole_hopf(x0, T, lam, s=np.sqrt(2.0), a=1.0, **kw):
     sigma = s * np.sqrt(T)
     h = lambda q: np.exp(-2.0 * lam * np.log((1.0 + a * q) / 2.0))
     return -np.log(radial_expectation(h, r, x0.shape[0], sigma, **kw)) / (2.0 * lam)
+
+
+def burgers_coefficients(d, s=np.sqrt(2.0)):
+    """(c, kappa) of the Burgers-type nonlinearity c (y - kappa) sum_i z_i whose solution is logistic."""
+    return s / d, d / (s * s) + 0.5
+
+
+def burgers_logistic(x0, t):
+    """u(t, x) = phi(t + sum_i x_i / d) and its gradient phi'(.) / d (every coordinate)."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    d = x0.shape[-1]
+    a = t + np.sum(x0, axis=-1) / d
+    u = 1.0 / (1.0 + np.exp(-a))
+    g = (u * (1.0 - u) / d)[..., None] * np.ones_like(x0)
+    return u, g

@@ -36,8 +36,8 @@ import scipy.linalg as sla
 
 from . import philox
 
-F_ZERO, F_ALLEN_CAHN, F_HJB = 0, 1, 2
-G_QUAD, G_AC, G_HJB_LOG, G_AFFINE = 0, 1, 2, 3
+F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS = 0, 1, 2, 3
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC = 0, 1, 2, 3, 4
 
 ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
 
@@ -72,7 +72,9 @@ def f_eval(pb, t, y, z):
     """f(t, x, y, z) of the built-in families with d f/dy, d f/dz and d f/d(fp).
 
     The families do not depend on t or x.  ALLEN_CAHN: c1 y - c3 y^3 (paper Sec. 4.1
-    Case 1 has c1 = c3 = 1); HJB: -lam |z|^2.  y: array [M]; z: array [d].
+    Case 1 has c1 = c3 = 1); HJB: -lam |z|^2; BURGERS: c (y - kappa) sum_i z_i, the Burgers-type
+    nonlinearity of the paper's Sec. 4 experiments in a form whose logistic solution is exact (see
+    colehopf.burgers_coefficients).  y: array [M]; z: array [d].
     Returns (f [M], fy [M], fz [d] per unit of the factor fz_scale [M], fth [4, M]).
     """
     y = np.asarray(y, dtype=np.float64)
@@ -94,6 +96,15 @@ def f_eval(pb, t, y, z):
         fth[0] = -zz
         # d f / d z = -2 lam z, the same for every particle
         return f, zero, -2.0 * lam * z, np.ones_like(y), fth
+    if pb.f_kind == F_BURGERS:
+        c, kap = pb.fp[0], pb.fp[1]
+        zs = float(np.sum(z))
+        f = c * (y - kap) * zs
+        fy = np.full_like(y, c * zs)
+        fth[0] = (y - kap) * zs
+        fth[1] = np.full_like(y, -c * zs)
+        # d f / d z_i = c (y - kappa) for every i: the vector c 1 scaled per particle by y - kappa
+        return f, fy, np.full_like(z, c), y - kap, fth
     raise ValueError("unknown f kind")
 
 
@@ -105,6 +116,14 @@ def g_eval(pb, X):
         g = X @ c + pb.gp[0]
         gth[0] = 1.0
         return g, np.broadcast_to(c, X.shape).copy(), gth
+    if pb.g_kind == G_LOGISTIC:
+        # g = 1 / (1 + exp(-(gvec . x + gp0)))
+        c = np.asarray(pb.gvec, dtype=np.float64)
+        a = X @ c + pb.gp[0]
+        g = 1.0 / (1.0 + np.exp(-a))
+        dg = g * (1.0 - g)
+        gth[0] = dg
+        return g, dg[:, None] * c[None, :], gth
     n2 = np.einsum("ij,ij->i", X, X)
     if pb.g_kind == G_QUAD:
         a, b = pb.gp[0], pb.gp[1]

@@ -15,7 +15,13 @@ CASES = [
     dict(f_kind=S.F_HJB, fp=(0.7, 0, 0, 0), g_kind=S.G_HJB_LOG, gp=(1.0, 0, 0, 0)),
     dict(f_kind=S.F_ZERO, fp=(0, 0, 0, 0), g_kind=S.G_QUAD, gp=(1.3, 0.2, 0, 0)),
     dict(f_kind=S.F_ALLEN_CAHN, fp=(0.5, 2.0, 0, 0), g_kind=S.G_HJB_LOG, gp=(0.6, 0, 0, 0)),
+    dict(f_kind=S.F_BURGERS, fp=(0.3, 1.2, 0, 0), g_kind=S.G_LOGISTIC, gp=(0.4, 0, 0, 0)),
 ]
+
+
+def _gvec(case, d):
+    # the logistic g takes a slope vector; the other families ignore it
+    return np.linspace(-0.5, 1.0, d) if CASES[case]["g_kind"] == S.G_LOGISTIC else None
 
 
 def _u(pb, x0):
@@ -26,7 +32,7 @@ def _u(pb, x0):
 @pytest.mark.parametrize("M,d", [(48, 6), (10, 16)])
 def test_adjoint_vs_central_fd(case, M, d):
     rng = np.random.default_rng(10 + case)
-    pb = S.Problem(d=d, M=M, N=4, T=0.3, eps_h=1.0, ridge_rel=1e-2, seed=case, **CASES[case])
+    pb = S.Problem(d=d, M=M, N=4, T=0.3, eps_h=1.0, ridge_rel=1e-2, seed=case, gvec=_gvec(case, d), **CASES[case])
     x0 = 0.3 * rng.normal(size=d)
     adj = S.adjoint_point(pb, x0, 0, ubar=1.0)
     h = 1e-4

@@ -64,11 +64,15 @@ enum { FBSDE_F64 = 0, FBSDE_F32C = 1 };       /* FP64 everywhere | FP32 state + 
                                                  LLR sums, FP64 CG scalars, Newton and outputs */
 enum { FBSDE_F_ZERO = 0,                      /* f = 0 (heat)                                  */
        FBSDE_F_ALLEN_CAHN = 1,                /* f = fp0 y - fp1 y^3 (Sec. 4.1 Case 1: 1, 1)  */
-       FBSDE_F_HJB = 2 };                     /* f = -fp0 |z|^2, z = sigma^T grad u            */
+       FBSDE_F_HJB = 2,                       /* f = -fp0 |z|^2, z = sigma^T grad u            */
+       FBSDE_F_BURGERS = 3 };                 /* f = fp0 (y - fp1) sum_i z_i (Burgers type, Sec.
+                                                 4; with fp0 = s/d, fp1 = d/s^2 + 1/2 and the
+                                                 logistic g below, u = logistic(t + sum x / d)) */
 enum { FBSDE_G_QUAD = 0,                      /* g = gp0 |x|^2 / d + gp1                       */
        FBSDE_G_AC = 1,                        /* g = 1 / (2 + gp0 |x|^2)   (Sec. 4.1 Case 1)   */
        FBSDE_G_HJB_LOG = 2,                   /* g = ln((1 + gp0 |x|^2) / 2)                   */
-       FBSDE_G_AFFINE = 3 };                  /* g = gvec . x + gp0                            */
+       FBSDE_G_AFFINE = 3,                    /* g = gvec . x + gp0                            */
+       FBSDE_G_LOGISTIC = 4 };                /* g = 1 / (1 + exp(-(gvec . x + gp0)))          */
 enum { FBSDE_OK = 0, FBSDE_EINVAL = -1, FBSDE_ENOSPC = -2, FBSDE_EHIP = -3, FBSDE_ESTATE = -4 };
 enum { FBSDE_ST_CG_MAXIT = 1, FBSDE_ST_NEWTON_FLAT = 2, FBSDE_ST_NONFINITE = 4 };
 enum { FBSDE_WS_TAPE = 1 };                   /* workspace flag: keep the tape for the adjoint */
@@ -87,7 +91,7 @@ typedef struct fbsde_problem {
     int32_t g_kind;          /* FBSDE_G_*                                                     */
     double fp[4];            /* parameters of f                                               */
     double gp[4];            /* parameters of g                                               */
-    const double* gvec;      /* device [d] slope of FBSDE_G_AFFINE, else NULL                 */
+    const double* gvec;      /* device [d] slope of FBSDE_G_AFFINE / _LOGISTIC, else NULL     */
     double eps_h;            /* kernel bandwidth factor h >= 0 (0: uniform weights)           */
     double ridge_rel;        /* ridge factor >= 0; 0 needs M > d + 1                          */
     int32_t newton_iters;    /* Newton iterations per particle and level, >= 1                */

@@ -5,8 +5,8 @@ import os
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfbsde.so")
 
 F64, F32C = 0, 1
-F_ZERO, F_ALLEN_CAHN, F_HJB = 0, 1, 2
-G_QUAD, G_AC, G_HJB_LOG, G_AFFINE = 0, 1, 2, 3
+F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS = 0, 1, 2, 3
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC = 0, 1, 2, 3, 4
 OK, EINVAL, ENOSPC, EHIP, ESTATE = 0, -1, -2, -3, -4
 ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
 WS_TAPE = 1

@@ -46,15 +46,15 @@ k_adj_newton(double* __restrict__ G, const double* __restrict__ w_prev, int64_t 
     __syncthreads();
     if (terminal) return;
     const double alpha = tscal_k[(int64_t)p * ns + 5];
-    const double zz = tscal_k[(int64_t)p * ns + 6];
+    const double zz = tscal_k[(int64_t)p * ns + 6], zs = tscal_k[(int64_t)p * ns + 8];
     uint32_t st = 0;
     double y0 = 0.0, Fp0;
-    if (!Yk) y0 = newton_y(f, alpha, zz, dt, newton_iters, Fp0, st);
-    double sc = 0.0, s0 = 0.0, s1 = 0.0;
+    if (!Yk) y0 = newton_y(f, alpha, zz, zs, dt, newton_iters, Fp0, st);
+    double sc = 0.0, s0 = 0.0, s1 = 0.0, z1 = 0.0;
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
         const double y = Yk ? Yk[(int64_t)p * M + j] : y0;
         double fv, fy;
-        f_and_fy(f, y, zz, fv, fy);
+        f_and_fy(f, y, zz, zs, fv, fy);
         const double Fp = 1.0 - dt * fy;
         if (fabs(Fp) < 1e-12) st |= ST_NEWTON_FLAT;
         const double cb = Gp[j] / Fp;
@@ -62,13 +62,16 @@ k_adj_newton(double* __restrict__ G, const double* __restrict__ w_prev, int64_t 
         sc += cb;
         if (f.kind == F_ALLEN_CAHN) { s0 += cb * y; s1 -= cb * y * y * y; }
         else if (f.kind == F_HJB) { s0 -= cb * zz; }
+        else if (f.kind == F_BURGERS) { s0 += cb * (y - f.p1) * zs; s1 -= cb * f.p0 * zs; z1 += cb * (y - f.p1); }
     }
     sc = block_sum(sc, lds);
     s0 = block_sum(s0, lds);
     s1 = block_sum(s1, lds);
+    z1 = block_sum(z1, lds);
     if (threadIdx.x == 0) {
         a[A_ABAR] = sc;
         a[A_ZC] = (f.kind == F_HJB) ? -2.0 * f.p0 * dt * sc : 0.0;
+        a[A_Z1] = (f.kind == F_BURGERS) ? f.p0 * dt * z1 : 0.0;
         a[A_FP + 0] += dt * s0;
         a[A_FP + 1] += dt * s1;
         if (st) atomicOr(&status[p], st);
@@ -122,25 +125,26 @@ k_adj_advance(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nch
     if (part) block_columns_out<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
 }
 
-// alpha_xbar = s sum_m cbar_m W^m_k + s Zbar - alphabar s Wbar, then CG on A bbar = alpha_xbar.
+// alpha_xbar = s sum_m cbar_m W^m_k + s Zbar - alphabar s Wbar, then CG on A bbar = alpha_xbar; Zbar =
+// zc Z + z1 (1, ..., 1) over the d coordinates (the pad stays 0).
 // Cold (warm = 0): from bbar = 0.  Warm: the right-hand side goes to r, the previous level's bbar (in x)
 // becomes the direction v of one CG product (pv, Wbar . v in scal[2]) that k_adj_warm_start turns into
 // the start gamma v.
 __global__ void __launch_bounds__(256)
-k_adj_rhs_finish(const double* __restrict__ part, int nchunk, int vchunks, int ld, double s, double lam,
+k_adj_rhs_finish(const double* __restrict__ part, int nchunk, int vchunks, int ld, int d, double s, double lam,
                  const double* __restrict__ Wbar, const double* __restrict__ ax, const double* __restrict__ adj,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ pv, double* __restrict__ scal,
                  int ns, int* __restrict__ iscal, int* active, int warm) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
     const double* a = adj + (int64_t)p * A_NS;
-    const double abar = a[A_ABAR], zc = a[A_ZC];
+    const double abar = a[A_ABAR], zc = a[A_ZC], z1 = a[A_Z1];
     const int64_t o = (int64_t)p * ld;
     double bb = 0.0, wv = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         double cs = 0.0;
         for (int c = 0; c < vchunks; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];
-        const double b = s * cs + s * s * zc * ax[o + i] - abar * s * Wbar[o + i];
+        const double b = s * cs + s * s * zc * ax[o + i] + ((i < d) ? s * z1 : 0.0) - abar * s * Wbar[o + i];
         r[o + i] = b;
         bb += b * b;
         if (warm) {
@@ -330,7 +334,7 @@ k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, 
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const double X = xc[q][e] + s * (double)xv[q][e];
-                    if (g_kind == G_AFFINE) qsum += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
+                    if (g_dot_arg(g_kind)) qsum += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
                     else qsum += X * X;
                 }
             }
@@ -343,6 +347,7 @@ k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, 
             if (g_kind == G_QUAD) { hp = ga / (double)d; d0 = qsum / (double)d; d1 = 1.0; }
             else if (g_kind == G_AC) { const double den = 2.0 + ga * qsum; hp = -ga / (den * den); d0 = -qsum / (den * den); }
             else if (g_kind == G_HJB_LOG) { const double den = 1.0 + ga * qsum; hp = ga / den; d0 = qsum / den; }
+            else if (g_kind == G_LOGISTIC) { const double gv = 1.0 / (1.0 + exp(-(qsum + ga))); d0 = gv * (1.0 - gv); }
             else { d0 = 1.0; }
             const double phi = 2.0 * hp * gj;
             s1 += phi; g0 += gj * d0; g1 += gj * d1; sg += gj;
@@ -365,7 +370,8 @@ k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, 
     }
 }
 
-// x0bar = (sum_j G_j 2h'_j) xc + s sum_j G_j 2h'_j W_j   (affine: (sum_j G_j) gvec); per-point gp sums.
+// x0bar = (sum_j G_j 2h'_j) xc + s sum_j G_j 2h'_j W_j   (affine: (sum_j G_j) gvec; logistic:
+// (sum_j G_j g'_j) gvec, which is the gp0 sum); per-point gp sums.
 __global__ void __launch_bounds__(256)
 k_adj_x0bar(const double* __restrict__ part, const double* __restrict__ psc, int nchunk, int vchunks, int d, int ld,
             const double* __restrict__ x0, const double* __restrict__ mu, const double* __restrict__ gvec,
@@ -379,6 +385,7 @@ k_adj_x0bar(const double* __restrict__ part, const double* __restrict__ psc, int
     for (int i = threadIdx.x; i < d; i += blockDim.x) {
         double v;
         if (g_kind == G_AFFINE) v = SG * gvec[i];
+        else if (g_kind == G_LOGISTIC) v = G0 * gvec[i];
         else {
             double cs = 0.0;
             for (int c = 0; c < vchunks; ++c) cs += part[((int64_t)p * nchunk + c) * ld + i];

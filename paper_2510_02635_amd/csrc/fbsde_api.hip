@@ -326,8 +326,8 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
         const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
         // warm start from the previous level's bbar (full-rank designs, as in the forward)
         const int warm = (k > 0 && pl.M > pl.d + 1) ? 1 : 0;
-        hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, vc, pl.ld, pb->s,
-                           lam, Wbar_k, ws.tax + (size_t)k * PL, ws.adj, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
+        hipLaunchKernelGGL(k_adj_rhs_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, pl.nchunk, vc, pl.ld,
+                           (int)pl.d, pb->s, lam, Wbar_k, ws.tax + (size_t)k * PL, ws.adj, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
                            ws.active, warm);
         if (warm) {
             dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {

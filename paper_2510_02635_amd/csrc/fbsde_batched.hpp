@@ -104,7 +104,7 @@ struct PointSolver {
                             const int i = e0 + e;
                             const double xc = (i < I.d) ? I.x0[(int64_t)p * I.d + i] + (I.mu ? I.mu[i] * I.T : 0.0) : 0.0;
                             const double X = xc + I.s * ws;
-                            if (I.g_kind == G_AFFINE) gq += ((e0 + e < I.d) ? I.gvec[e0 + e] : 0.0) * X;
+                            if (g_dot_arg(I.g_kind)) gq += ((e0 + e < I.d) ? I.gvec[e0 + e] : 0.0) * X;
                             else gq += X * X;
                         }
                     }
@@ -285,7 +285,7 @@ struct PointSolver {
     }
 
     // reversal to level k (or W_0 = 0), Newton for Y_k, |W_k|^2, dY/dC
-    __device__ void reverse(int k, double alpha, double zz) {
+    __device__ void reverse(int k, double alpha, double zz, double zs) {
         const double dt = I.T / I.N, sqdt = sqrt(dt);
         const uint32_t qs = I.point_base + (uint32_t)p;
         R a[Q][4];
@@ -322,7 +322,7 @@ struct PointSolver {
             team_sum2<TEAM>(n2, dd, red, team);
             if (valid && L == 0) {
                 double Fp;
-                Y[j] = newton_y(f, alpha + I.s * dd, zz, dt, I.newton_iters, Fp, st);
+                Y[j] = newton_y(f, alpha + I.s * dd, zz, zs, dt, I.newton_iters, Fp, st);
                 rn2[j] = n2;
                 c2[j] = 1.0 / Fp;
             }
@@ -369,18 +369,19 @@ struct PointSolver {
                 wvp = block_sum(wv_, red);
                 rr = rr2;
             }
-            double xw = 0.0, xx = 0.0;
-            for (int i = threadIdx.x; i < I.ld; i += G::BS) { xw += x[i] * Wbar[i]; xx += x[i] * x[i]; }
+            double xw = 0.0, xx = 0.0, xs = 0.0;
+            for (int i = threadIdx.x; i < I.ld; i += G::BS) { xw += x[i] * Wbar[i]; xx += x[i] * x[i]; xs += x[i]; }
             xw = block_sum(xw, red);
             xx = block_sum(xx, red);
+            xs = block_sum(xs, red);
             const double alpha = ybar - I.s * xw;
-            const double zz = I.s * I.s * xx;
+            const double zz = I.s * I.s * xx, zs = I.s * xs;
             if (k > 0) {
-                reverse(k, alpha, zz);
+                reverse(k, alpha, zz, zs);
             } else {
                 double Fp;
                 uint32_t s0 = 0;
-                const double y = newton_y(I.f, alpha, zz, dt, I.newton_iters, Fp, s0);
+                const double y = newton_y(I.f, alpha, zz, zs, dt, I.newton_iters, Fp, s0);
                 st |= s0;
                 if (threadIdx.x == 0) I.u[p] = y;
                 if (I.grad)

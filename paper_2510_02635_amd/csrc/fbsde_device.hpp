@@ -223,45 +223,53 @@ __device__ __forceinline__ double block_min(double v, double* lds) {
 }
 
 // ------------------------------------------------------------------ f, g, Newton
-enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2 };
-enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3 };
+enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2, F_BURGERS = 3 };
+enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3, G_LOGISTIC = 4 };
 
-// Per-point FP64 slots of the reverse mode: alphabar, row-pass sum, Zbar coefficient, Wbar.bbar,
-// f-parameter sums [4], g-parameter sums [4], terminal sum of 2h'G, terminal sum of G.
-enum { A_ABAR = 0, A_TAU = 1, A_ZC = 2, A_WB = 3, A_FP = 4, A_GP = 8, A_S1 = 12, A_SG = 13, A_NS = 16 };
+// g families whose argument is q = gvec . X (the others take q = |X|^2)
+__device__ __forceinline__ bool g_dot_arg(int kind) { return kind == G_AFFINE || kind == G_LOGISTIC; }
+
+// Per-point FP64 slots of the reverse mode: alphabar, row-pass sum, Zbar coefficient along z, Wbar.bbar,
+// f-parameter sums [4], g-parameter sums [4], terminal sum of 2h'G, terminal sum of G, Zbar coefficient
+// along the all-ones vector (the Burgers family, whose d f / d z_i is the same for every i).
+enum { A_ABAR = 0, A_TAU = 1, A_ZC = 2, A_WB = 3, A_FP = 4, A_GP = 8, A_S1 = 12, A_SG = 13, A_Z1 = 14, A_NS = 16 };
 enum { ST_CG_MAXIT = 1, ST_NEWTON_FLAT = 2, ST_NONFINITE = 4 };
 
 struct FSpec { int kind; double p0, p1; };
 
-// f(t, x, y, z) and d f / d y of the built-in families; zz = |z|^2 (z shared by the cloud).
-__device__ __forceinline__ void f_and_fy(const FSpec& f, double y, double zz, double& fv, double& fy) {
+// f(t, x, y, z) and d f / d y of the built-in families; zz = |z|^2 and zs = sum_i z_i (z shared by the
+// cloud).  BURGERS: fp0 (y - fp1) sum_i z_i, the Burgers-type nonlinearity of the Sec. 4 experiments in
+// a form whose logistic solution is exact (fp0 = s/d, fp1 = d/s^2 + 1/2).
+__device__ __forceinline__ void f_and_fy(const FSpec& f, double y, double zz, double zs, double& fv, double& fy) {
     if (f.kind == F_ALLEN_CAHN) { fv = f.p0 * y - f.p1 * y * y * y; fy = f.p0 - 3.0 * f.p1 * y * y; }
     else if (f.kind == F_HJB) { fv = -f.p0 * zz; fy = 0.0; }
+    else if (f.kind == F_BURGERS) { fv = f.p0 * (y - f.p1) * zs; fy = f.p0 * zs; }
     else { fv = 0.0; fy = 0.0; }
 }
 
 // Fixed-count Newton for F(y) = y - C - dt f(y) from y = C; returns y and F'(y).
-__device__ __forceinline__ double newton_y(const FSpec& f, double C, double zz, double dt, int iters,
+__device__ __forceinline__ double newton_y(const FSpec& f, double C, double zz, double zs, double dt, int iters,
                                            double& Fp, uint32_t& st) {
     double y = C, fv, fy;
     for (int n = 0; n < iters; ++n) {
-        f_and_fy(f, y, zz, fv, fy);
+        f_and_fy(f, y, zz, zs, fv, fy);
         const double F = y - C - dt * fv;
         const double dF = 1.0 - dt * fy;
         if (fabs(dF) < 1e-12) st |= ST_NEWTON_FLAT;
         y = y - F / dF;
     }
-    f_and_fy(f, y, zz, fv, fy);
+    f_and_fy(f, y, zz, zs, fv, fy);
     Fp = 1.0 - dt * fy;
     if (!isfinite(y)) st |= ST_NONFINITE;
     return y;
 }
 
-// Terminal g from q = |X|^2 (radial families) or q = gvec . X (affine).
+// Terminal g from q = |X|^2 (radial families) or q = gvec . X (affine, logistic).
 __device__ __forceinline__ double g_of(int kind, double a, double b, double q, int64_t d) {
     if (kind == G_QUAD) return a * q / (double)d + b;
     if (kind == G_AC) return 1.0 / (2.0 + a * q);
     if (kind == G_HJB_LOG) return log((1.0 + a * q) * 0.5);
+    if (kind == G_LOGISTIC) return 1.0 / (1.0 + exp(-(q + a)));   // a = offset
     return q + a;   // G_AFFINE: q = gvec . X, a = offset
 }
 

@@ -14,7 +14,7 @@ namespace fbsde {
 namespace host {
 
 
-constexpr int NS = 8;   // per-point FP64 scalars (see k_moments_finish)
+constexpr int NS = 10;   // per-point FP64 scalars (see k_moments_finish and k_level_finish)
 
 struct Plan {
     int64_t d, M, N;
@@ -28,9 +28,9 @@ inline int check_problem(const fbsde_problem* pb, int64_t P) {
     if (!pb || P < 0) return FBSDE_EINVAL;
     if (pb->d < 1 || pb->M < 2 || pb->N < 1) return FBSDE_EINVAL;
     if (!(pb->T > 0.0) || !(pb->s > 0.0)) return FBSDE_EINVAL;
-    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_HJB) return FBSDE_EINVAL;
-    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_AFFINE) return FBSDE_EINVAL;
-    if (pb->g_kind == FBSDE_G_AFFINE && !pb->gvec) return FBSDE_EINVAL;
+    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_BURGERS) return FBSDE_EINVAL;
+    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_LOGISTIC) return FBSDE_EINVAL;
+    if ((pb->g_kind == FBSDE_G_AFFINE || pb->g_kind == FBSDE_G_LOGISTIC) && !pb->gvec) return FBSDE_EINVAL;
     if (!(pb->eps_h >= 0.0) || !(pb->ridge_rel >= 0.0)) return FBSDE_EINVAL;
     if (pb->ridge_rel == 0.0 && pb->M <= pb->d + 1) return FBSDE_EINVAL;
     if (pb->newton_iters < 1 || pb->cg_maxit < 1 || !(pb->cg_rtol >= 0.0)) return FBSDE_EINVAL;

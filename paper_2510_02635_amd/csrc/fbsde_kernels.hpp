@@ -88,7 +88,7 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
                         const double ws = (double)v[e];
                         n2 += ws * ws;
                         const double X = xc[q][e] + s * ws;
-                        if (g_kind == G_AFFINE) gq += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
+                        if (g_dot_arg(g_kind)) gq += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
                         else gq += X * X;
                     }
                 }
@@ -263,7 +263,8 @@ k_fold_chunks(double* __restrict__ a, double* __restrict__ b, double* __restrict
     }
 }
 
-// scal layout per point: 0 rr, 1 |b|^2, 2 wv = Wbar.p, 3 lam, 4 Ybar, 5 alpha, 6 zz, 7 rho.
+// scal layout per point: 0 rr, 1 |b|^2, 2 wv = Wbar.p, 3 lam, 4 Ybar, 5 alpha, 6 zz = |Z|^2, 7 rho,
+// 8 zs = sum_i Z_i.
 // iscal: 0 iterations, 1 done.
 __global__ void __launch_bounds__(256)
 k_moments_finish(const double* __restrict__ part1, const double* __restrict__ part2,
@@ -453,8 +454,8 @@ k_cg_update(const double* __restrict__ part, const double* __restrict__ psc, int
     }
 }
 
-// Intercept alpha = Ybar - s alpha_x . Wbar (eq. taylorexp / Schur form) and |Z|^2 = s^2 |alpha_x|^2;
-// optional dense copies of alpha, alpha_x for the caller.
+// Intercept alpha = Ybar - s alpha_x . Wbar (eq. taylorexp / Schur form), |Z|^2 = s^2 |alpha_x|^2 and
+// sum_i Z_i = s sum_i alpha_x,i; optional dense copies of alpha, alpha_x for the caller.
 __global__ void __launch_bounds__(256)
 k_level_finish(const double* __restrict__ x, const double* __restrict__ Wbar, int ld, int d, double s,
                double* __restrict__ scal, int ns, double* __restrict__ alpha_out,
@@ -462,19 +463,22 @@ k_level_finish(const double* __restrict__ x, const double* __restrict__ Wbar, in
     __shared__ double lds[16];
     const int p = blockIdx.x;
     const int64_t o = (int64_t)p * ld;
-    double xw = 0.0, xx = 0.0;
+    double xw = 0.0, xx = 0.0, xs = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         xw += x[o + i] * Wbar[o + i];
         xx += x[o + i] * x[o + i];
+        xs += x[o + i];
         if (alpha_x_out && i < d) alpha_x_out[(int64_t)p * d + i] = x[o + i];
     }
     xw = block_sum(xw, lds);
     xx = block_sum(xx, lds);
+    xs = block_sum(xs, lds);
     if (threadIdx.x == 0) {
         double* sc = scal + (int64_t)p * ns;
         const double alpha = sc[4] - s * xw;
         sc[5] = alpha;
         sc[6] = s * s * xx;
+        sc[8] = s * xs;
         if (alpha_out) alpha_out[p] = alpha;
     }
 }
@@ -505,7 +509,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
         for (int e = 0; e < 4; ++e) a[q][e] = (e0 < ld) ? (R)ax[(int64_t)p * ld + e0 + e] : (R)0;
     }
     const double alpha = scal[(int64_t)p * ns + 5];
-    const double zz = scal[(int64_t)p * ns + 6];
+    const double zz = scal[(int64_t)p * ns + 6], zs = scal[(int64_t)p * ns + 8];
     uint32_t st = 0;
     // Newton runs 64 rows at a time: lane (row count mod 64) of the team's first wave keeps the row's
     // C and |W|^2, and every 64 rows those lanes solve together instead of one lane per row
@@ -514,7 +518,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     auto flush = [&]() {
         if (j_keep >= 0) {
             double Fp;
-            const double y = newton_y(f, c_keep, zz, dt, newton_iters, Fp, st);
+            const double y = newton_y(f, c_keep, zz, zs, dt, newton_iters, Fp, st);
             Y[(int64_t)p * M + j_keep] = y;
             rn2[(int64_t)p * M + j_keep] = n2_keep;
             if (dydc) dydc[(int64_t)p * M + j_keep] = 1.0 / Fp;
@@ -575,7 +579,8 @@ k_outputs(const double* __restrict__ x, int ld, int d, const double* __restrict_
     const int p = blockIdx.x;
     uint32_t st = 0;
     double Fp;
-    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], dt, newton_iters, Fp, st);
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], scal[(int64_t)p * ns + 8], dt,
+                              newton_iters, Fp, st);
     if (threadIdx.x == 0) u[p] = y;
     if (grad)
         for (int i = threadIdx.x; i < d; i += blockDim.x) {

@@ -63,8 +63,8 @@ struct EpiNewton {
     __device__ __forceinline__ void operator()(int p, int j, double v) const {
         uint32_t st = 0;
         double Fp;
-        const double y = newton_y(f, scal[(int64_t)p * ns + 5] + s * v, scal[(int64_t)p * ns + 6], dt, newton_iters, Fp,
-                                  st);
+        const double y = newton_y(f, scal[(int64_t)p * ns + 5] + s * v, scal[(int64_t)p * ns + 6],
+                                  scal[(int64_t)p * ns + 8], dt, newton_iters, Fp, st);
         Y[(int64_t)p * M + j] = y;
         if (st) atomicOr(&status[p], st);
     }
@@ -87,12 +87,13 @@ k_sh_xc(const double* __restrict__ x0, const double* __restrict__ mu, int d, int
     if (threadIdx.x == 0) xc2[p] = s;
 }
 
-// Affine terminal g = gvec . (xc_p + s W_j) + b: per-particle gvec . W_j then per (p, j).
+// Terminal g of q = gvec . (xc_p + s W_j) (affine: q + b; logistic: 1 / (1 + e^-(q + b))): per-particle
+// gvec . W_j then per (p, j); q_tape (or null) keeps q for the adjoint.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sh_affine_terminal(const T* __restrict__ W, int ld, int M, int d, const double* __restrict__ gvec,
                      const double* __restrict__ x0, const double* __restrict__ mu, double Tend, double s, double b,
-                     int P, double* __restrict__ Y) {
+                     int P, int g_kind, double* __restrict__ Y, double* __restrict__ q_tape, uint32_t* __restrict__ status) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
     double gx = 0.0;
@@ -102,7 +103,13 @@ k_sh_affine_terminal(const T* __restrict__ W, int ld, int M, int d, const double
         double gw = 0.0;
         for (int i = threadIdx.x; i < d; i += blockDim.x) gw += gvec[i] * (double)W[(int64_t)j * ld + i];
         gw = block_sum(gw, lds);
-        if (threadIdx.x == 0) Y[(int64_t)p * M + j] = gx + s * gw + b;
+        if (threadIdx.x == 0) {
+            const double q = gx + s * gw;
+            const double y = g_of(g_kind, b, 0.0, q, d);
+            Y[(int64_t)p * M + j] = y;
+            if (q_tape) q_tape[(int64_t)p * M + j] = q;
+            if (!isfinite(y)) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
+        }
     }
 }
 
@@ -189,24 +196,27 @@ k_transpose(const T* __restrict__ in, int64_t ldi, int rows, int cols, T* __rest
     }
 }
 
-// Per point: alpha_p = Ybar_p - s alpha_x[p] . Wbar,  zz_p = s^2 |alpha_x[p]|^2.
+// Per point: alpha_p = Ybar_p - s alpha_x[p] . Wbar,  zz_p = s^2 |alpha_x[p]|^2,  zs_p = s sum_i alpha_x[p]_i.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sh_point_finish(const T* __restrict__ ax, int ld, const double* __restrict__ Wbar, double s,
                   double* __restrict__ scal, int ns) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
-    double xw = 0.0, xx = 0.0;
+    double xw = 0.0, xx = 0.0, xs = 0.0;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         const double a = (double)ax[(int64_t)p * ld + i];
         xw += a * Wbar[i];
         xx += a * a;
+        xs += a;
     }
     xw = block_sum(xw, lds);
     xx = block_sum(xx, lds);
+    xs = block_sum(xs, lds);
     if (threadIdx.x == 0) {
         scal[(int64_t)p * ns + 5] = scal[(int64_t)p * ns + 4] - s * xw;
         scal[(int64_t)p * ns + 6] = s * s * xx;
+        scal[(int64_t)p * ns + 8] = s * xs;
     }
 }
 
@@ -218,7 +228,8 @@ k_sh_outputs(const T* __restrict__ ax, int ld, int d, const double* __restrict__
     const int p = blockIdx.x;
     uint32_t st = 0;
     double Fp;
-    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], dt, newton_iters, Fp, st);
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], scal[(int64_t)p * ns + 8], dt,
+                              newton_iters, Fp, st);
     if (threadIdx.x == 0) u[p] = y;
     if (grad)
         for (int i = threadIdx.x; i < d; i += blockDim.x) grad[(int64_t)p * d + i] = (double)ax[(int64_t)p * ld + i] / Fp;
@@ -237,18 +248,20 @@ k_sh_outputs(const T* __restrict__ ax, int ld, int d, const double* __restrict__
 // The dual form never forms bbar itself, whose component in the ridge-only null space of the design
 // is scaled by 1/lam.
 
-// alpha_xbar from the GEMM value v = sum_m cbar[p][m] W^m_k (element type T).
+// alpha_xbar from the GEMM value v = sum_m cbar[p][m] W^m_k (element type T); Zbar = zc Z + z1 (1, ..., 1)
+// over the d coordinates.
 template <typename T>
 struct EpiAxbar {
     T* out;
     const T* ax;
     const double* Wbar;
     const double* adj;
-    int ld;
+    int ld, d;
     double s;
     __device__ __forceinline__ void operator()(int p, int i, double v) const {
         const double* a = adj + (int64_t)p * A_NS;
-        const double r = s * v + s * s * a[A_ZC] * (double)ax[(int64_t)p * ld + i] - a[A_ABAR] * s * Wbar[i];
+        const double r = s * v + s * s * a[A_ZC] * (double)ax[(int64_t)p * ld + i] + ((i < d) ? s * a[A_Z1] : 0.0) -
+                         a[A_ABAR] * s * Wbar[i];
         out[(int64_t)p * ld + i] = (T)r;
     }
 };
@@ -257,12 +270,12 @@ struct EpiAxbar {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sha_axbar0(T* __restrict__ out, const T* __restrict__ ax, const double* __restrict__ Wbar,
-             const double* __restrict__ adj, int ld, double s) {
+             const double* __restrict__ adj, int ld, int d, double s) {
     const int p = blockIdx.x;
     const double* a = adj + (int64_t)p * A_NS;
     for (int i = threadIdx.x; i < ld; i += blockDim.x)
-        out[(int64_t)p * ld + i] =
-            (T)(s * s * a[A_ZC] * (double)ax[(int64_t)p * ld + i] - a[A_ABAR] * s * Wbar[i]);
+        out[(int64_t)p * ld + i] = (T)(s * s * a[A_ZC] * (double)ax[(int64_t)p * ld + i] +
+                                       ((i < d) ? s * a[A_Z1] : 0.0) - a[A_ABAR] * s * Wbar[i]);
 }
 
 // FP64 [P][M] -> element type.
@@ -318,6 +331,9 @@ k_sha_terminal(const double* __restrict__ G, const double* __restrict__ qt, int 
         double hp = 0.0, d0 = 0.0, d1 = 0.0;
         if (g_kind == G_AFFINE) {
             d0 = 1.0;
+        } else if (g_kind == G_LOGISTIC) {
+            const double gv = 1.0 / (1.0 + exp(-(qt[(int64_t)p * M + j] + ga)));
+            d0 = gv * (1.0 - gv);
         } else {
             const double q = qt[(int64_t)p * M + j];
             if (g_kind == G_QUAD) { hp = ga / (double)d; d0 = q / (double)d; d1 = 1.0; }
@@ -356,12 +372,13 @@ struct EpiX0bar {
     }
 };
 
-// Affine g: x0bar[p] = (sum_j G_j) gvec.
+// g of gvec . X: x0bar[p] = c_p gvec with c_p the adjoint slot `slot` (affine: sum_j G_j; logistic:
+// sum_j G_j g'_j, the gp0 sum).
 __global__ void __launch_bounds__(256)
-k_sha_x0bar_affine(const double* __restrict__ gvec, int d, const double* __restrict__ adj,
+k_sha_x0bar_affine(const double* __restrict__ gvec, int d, const double* __restrict__ adj, int slot,
                    double* __restrict__ x0bar) {
     const int p = blockIdx.x;
-    const double sg = adj[(int64_t)p * A_NS + A_SG];
+    const double sg = adj[(int64_t)p * A_NS + slot];
     for (int i = threadIdx.x; i < d; i += blockDim.x) x0bar[(int64_t)p * d + i] = sg * gvec[i];
 }
 

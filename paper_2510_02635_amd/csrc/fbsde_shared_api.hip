@@ -100,9 +100,9 @@ int solve_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl1, 
     shared_forward<T>(pb, pl1, W, ws.ysc, ws.rn2, status, st);
     double* Ycur = ws.Ya;
     double* Yk = ws.Yb;
-    if (pb->g_kind == FBSDE_G_AFFINE) {
+    if (pb->g_kind == FBSDE_G_AFFINE || pb->g_kind == FBSDE_G_LOGISTIC) {
         hipLaunchKernelGGL((k_sh_affine_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, W, ld, M, d, pb->gvec, x0,
-                           pb->mu, pb->T, s, pb->gp[0], Pi, Ycur);
+                           pb->mu, pb->T, s, pb->gp[0], Pi, pb->g_kind, Ycur, ws.tape ? ws.tq : nullptr, status);
     } else {
         hipLaunchKernelGGL((k_sh_xc<T>), dim3((unsigned)P), dim3(256), 0, st, x0, pb->mu, d, ld, pb->T, xc, ws.xc2);
         gemm<T, true>(Pi, M, ld, xc, ld, W, ld,
@@ -198,12 +198,12 @@ int backward_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl
         // alpha_xbar: the cloud term needs W_k before it is advanced
         if (k == 0) {
             hipLaunchKernelGGL((k_sha_axbar0<T>), dim3((unsigned)P), dim3(256), 0, st, axbar, tax_k, tWbar_k, ws.adj,
-                               ld, s);
+                               ld, d, s);
         } else {
             const int64_t n = P * (int64_t)M;
             hipLaunchKernelGGL((k_sha_to_elem<T>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
                                0, st, ws.cbar, n, V);
-            gemm<T, false>(Pi, ld, M, V, M, W, ld, EpiAxbar<T>{axbar, tax_k, tWbar_k, ws.adj, ld, s}, st);
+            gemm<T, false>(Pi, ld, M, V, M, W, ld, EpiAxbar<T>{axbar, tax_k, tWbar_k, ws.adj, ld, d, s}, st);
         }
         shared_advance<T>(pb, pl1, k, W, st);
         hipLaunchKernelGGL((k_sha_dtilde<T>), dim3(cblocks, 32), dim3(256), 0, st, W, ld, M, tWbar_k,
@@ -223,10 +223,12 @@ int backward_shared_impl(const fbsde_problem* pb, const Plan& pl, const Plan& pl
     // G_N, then the terminal condition on the cloud at t_N (W now holds W_N)
     adj_newton(pb, P, ws.G, ws.tw + (size_t)(pl.N - 1) * M, 0, ws.psc, 1, nullptr, ws.tscal, u_bar, ws.cbar, ws.adj,
                0, 1, status, st);
-    if (pb->g_kind == FBSDE_G_AFFINE) {
-        hipLaunchKernelGGL((k_sha_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, ws.G, nullptr, M, d, pb->g_kind,
-                           pb->gp[0], nullptr, ws.adj);
-        hipLaunchKernelGGL(k_sha_x0bar_affine, dim3((unsigned)P), dim3(256), 0, st, pb->gvec, d, ws.adj, x0_bar);
+    if (pb->g_kind == FBSDE_G_AFFINE || pb->g_kind == FBSDE_G_LOGISTIC) {
+        const bool lg = pb->g_kind == FBSDE_G_LOGISTIC;
+        hipLaunchKernelGGL((k_sha_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, ws.G, lg ? ws.tq : nullptr, M, d,
+                           pb->g_kind, pb->gp[0], nullptr, ws.adj);
+        hipLaunchKernelGGL(k_sha_x0bar_affine, dim3((unsigned)P), dim3(256), 0, st, pb->gvec, d, ws.adj,
+                           lg ? A_GP + 0 : A_SG, x0_bar);
     } else {
         hipLaunchKernelGGL((k_sha_terminal<T>), dim3((unsigned)P), dim3(256), 0, st, ws.G, ws.tq, M, d, pb->g_kind,
                            pb->gp[0], V, ws.adj);

@@ -45,6 +45,12 @@ ADJ_CASES = [
                             g_kind=F.G_HJB_LOG, gp=(0.6, 0, 0, 0)), "normal_over_sqrt_d", 2),
     ("ac_d10000_team16", dict(d=10000, M=40, N=2, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
                               gp=(0.4, 0, 0, 0)), "normal_over_sqrt_d", 1),
+    ("burgers_logistic_d50", dict(d=50, M=300, N=3, T=0.5, f_kind=F.F_BURGERS, fp=(2 ** 0.5 / 50, 25.5, 0, 0),
+                                  g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0), gvec=np.linspace(-1.0, 2.0, 50) / 50),
+     "normal:0.5", 3),
+    ("burgers_logistic_d400_M120", dict(d=400, M=120, N=2, T=0.5, f_kind=F.F_BURGERS,
+                                        fp=(2 ** 0.5 / 400, 200.5, 0, 0), g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0),
+                                        gvec=np.ones(400) / 400), "normal:0.5", 2),
 ]
 
 

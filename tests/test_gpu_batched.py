@@ -48,6 +48,8 @@ INSTANCES = [
           instance=4), "uniform", 1),
     (dict(d=200, M=400, N=4, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0),
           instance=5), "normal_over_sqrt_d", 3),   # M > d + 1: warm-started CG
+    (dict(d=80, M=200, N=3, T=0.5, f_kind=F.F_BURGERS, fp=(2 ** 0.5 / 80, 40.5, 0, 0), g_kind=F.G_LOGISTIC,
+          gp=(0.5, 0, 0, 0), gvec=np.ones(80) / 80, instance=7), "normal:0.5", 2),
 ]
 
 
@@ -109,6 +111,8 @@ ADJ = [
           instance=5), "normal_over_sqrt_d", 3),
     (dict(d=700, M=96, N=2, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0),
           prec=F.F32C, instance=6), "normal:0.2", 2),
+    (dict(d=80, M=200, N=3, T=0.5, f_kind=F.F_BURGERS, fp=(2 ** 0.5 / 80, 40.5, 0, 0), g_kind=F.G_LOGISTIC,
+          gp=(0.5, 0, 0, 0), gvec=np.ones(80) / 80, instance=7), "normal:0.5", 2),
 ]
 
 

@@ -163,6 +163,12 @@ CASES = [
                               gp=(0.4, 0, 0, 0)), "normal_over_sqrt_d", 1),
     ("uniform_weights_d64", dict(d=64, M=200, N=4, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(0.5, 2.0, 0, 0),
                                  g_kind=F.G_HJB_LOG, gp=(0.6, 0, 0, 0), eps_h=0.0, ridge_rel=0.0), "normal:0.3", 2),
+    # Burgers-type family with the logistic terminal (fp0 = s/d, fp1 = d/s^2 + 1/2, gvec = 1/d)
+    ("burgers_logistic_d50", dict(d=50, M=300, N=3, T=0.5, f_kind=F.F_BURGERS, fp=(2 ** 0.5 / 50, 25.5, 0, 0),
+                                  g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0), gvec=np.ones(50) / 50), "normal:0.5", 3),
+    ("burgers_logistic_d400_M120", dict(d=400, M=120, N=2, T=0.5, f_kind=F.F_BURGERS,
+                                        fp=(2 ** 0.5 / 400, 200.5, 0, 0), g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0),
+                                        gvec=np.linspace(-1.0, 2.0, 400) / 400), "normal:0.5", 2),
 ]
 
 
@@ -175,7 +181,10 @@ def test_solve_fp64_matches_oracle(name, kw, xkind, P):
     _run_solve(hp, op, _x0(xkind, P, kw["d"], 5), 1e-10, 1e-10)
 
 
-@pytest.mark.parametrize("name,kw,xkind,P", CASES[:3] + CASES[5:6], ids=[c[0] for c in CASES[:3] + CASES[5:6]])
+FP32C_CASES = CASES[:3] + CASES[5:6] + CASES[9:11]
+
+
+@pytest.mark.parametrize("name,kw,xkind,P", FP32C_CASES, ids=[c[0] for c in FP32C_CASES])
 def test_solve_fp32c_matches_fp64_oracle(name, kw, xkind, P):
     mu = None
     if "mu" in name:

@@ -82,6 +82,12 @@ SHARED_CASES = [
      "normal:0.5", 3),
     ("ac_d2000_M300", dict(d=2000, M=300, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
                            gp=(0.4, 0, 0, 0)), "normal_over_sqrt_d", 4),
+    ("burgers_logistic_d60_primal", dict(d=60, M=150, N=3, T=0.5, f_kind=F.F_BURGERS, fp=(2 ** 0.5 / 60, 30.5, 0, 0),
+                                         g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0),
+                                         gvec=np.linspace(-1.0, 2.0, 60) / 60), "normal:0.5", 6),
+    ("burgers_logistic_d300_dual", dict(d=300, M=120, N=2, T=0.5, f_kind=F.F_BURGERS,
+                                        fp=(2 ** 0.5 / 300, 150.5, 0, 0), g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0),
+                                        gvec=np.ones(300) / 300), "normal:0.5", 4),
 ]
 
 

@@ -62,3 +62,13 @@ def test_affine_closed_form_is_first_order():
     _say(f"[affine order] errors {['%.3e' % e for e in errs]} slope {res['slope']:.4f}")
     assert all(a > b for a, b in zip(errs, errs[1:]))
     assert abs(res["slope"] - 1.0) < 0.05
+
+
+def test_burgers_family_against_its_closed_form():
+    # the Burgers-type family against u(0, x) = logistic(sum x / d) with more particles than dimensions; the
+    # scheme's own bias (cloud-shared Z) is about 5e-3 (same loose gate as the oracle's pin at d = 10)
+    r = study.burgers_closed_form(F, torch, d=1000, M=4096, N=10, points=16)
+    _say(f"[burgers d=1000 M=4096] max {r['max_err']:.3e} mean {r['mean_err']:.3e} grad {r['grad_err']:.3f} "
+         f"cg {r['cg']} {r['sec']:.2f} s")
+    assert r["status"] == 0
+    assert r["max_err"] < 3e-2 and abs(r["mean_err"]) < 1.5e-2 and r["grad_err"] < 0.3

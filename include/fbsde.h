@@ -31,8 +31,9 @@
  * Conventions for every entry point
  *   - Pointers named "device" are device memory of the current HIP device; the caller owns
  *     every buffer, including the workspace; the library allocates no device memory.  Its
- *     only process-wide state is the table of launch shapes chosen by fbsde_autotune; the
- *     tiled batched schedule creates host threads, streams and events for the length of a call.
+ *     only process-wide state is the table of launch shapes chosen by fbsde_autotune and the
+ *     optional launch timer (events kept once created); the tiled batched schedule creates host
+ *     threads, streams and events for the length of a call.
  *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
  *     once it is enqueued, except where stated (CG convergence polling, see fbsde_solve; the
  *     tiled batched schedule and the autotuner return after their work has completed).
@@ -271,8 +272,8 @@ int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t 
  * runs on the forward sweep of the given points x0 (device [P][d]) in ws (fbsde_workspace_size(pb, P,
  * 0) bytes, overwritten).  The fastest shape (a new one must win by 2 %) is recorded in a process-wide
  * table that every later plan with the same (precision, d, M, P) uses -- fbsde_solve, _step, _backward,
- * fbsde_time_kernel and the workspace sizes (never larger than before tuning).  This table is the
- * library's only global state; fbsde_autotune_reset clears it.  Thread-safe; synchronises the stream. */
+ * fbsde_time_kernel and the workspace sizes (never larger than before tuning).  This table and the
+ * launch timer below are the library's only global state; fbsde_autotune_reset clears the table.  Thread-safe; synchronises the stream. */
 typedef struct fbsde_tune_result {
     int32_t team;            /* wavefronts per particle row                        */
     int32_t q;               /* groups of four coordinates per lane                */
@@ -284,6 +285,17 @@ typedef struct fbsde_tune_result {
 int fbsde_autotune(const fbsde_problem* pb, int64_t P, const double* x0, void* ws, size_t ws_bytes,
                    fbsde_tune_result* out, fbsde_stream stream);
 int fbsde_autotune_reset(void);
+
+/* Launch timer of the fused CG product (the dominant kernel), for measuring it inside a caller's own
+ * timed region.  fbsde_launch_timer(1) clears the record and starts it, fbsde_launch_timer(0) stops
+ * it (the record is kept).  While it runs, every CG-product launch of fbsde_solve and
+ * fbsde_solve_backward on a stream that is not being captured is bracketed by two HIP events on that
+ * stream (a few microseconds of host time per launch).  fbsde_launch_timer_read waits for the
+ * recorded launches and writes the duration in milliseconds of the first `cap` of them, in launch
+ * order, to `ms` (host), and their total count to *n.  The events are created on first use and kept
+ * for the life of the process.  Thread-safe; the record is process-wide. */
+int fbsde_launch_timer(int32_t on);
+int fbsde_launch_timer_read(float* ms, int64_t cap, int64_t* n);
 
 /* Captured solve, for callers that repeat one solve with the same problem, sizes and buffers
  * (serving loops, parameter sweeps that rewrite x0 in place): the launch sequence of fbsde_solve

@@ -15,7 +15,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
-            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_strerror")
+            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_strerror")
 
 
 BATCH_TILED, BATCH_PERSISTENT = 0, 1
@@ -81,6 +81,8 @@ def load():
     lib.fbsde_normals.argtypes = [pb, i64, i32, i64, i64, vp, vp, vp]
     lib.fbsde_time_kernel.argtypes = [pb, i64, i32, i32, vp, sz, P(ctypes.c_float), vp]
     lib.fbsde_box_muller.argtypes = [i32, i64, vp, vp, vp]
+    lib.fbsde_launch_timer.argtypes = [i32]
+    lib.fbsde_launch_timer_read.argtypes = [vp, i64, P(i64)]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
                                ctypes.c_double, vp]
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]

@@ -188,6 +188,21 @@ def box_muller(words, prec):
     return out
 
 
+def launch_timer(on):
+    """Start (clearing the record) or stop the library's launch timer of the fused CG product."""
+    N.check(N.load().fbsde_launch_timer(1 if on else 0))
+
+
+def launch_timer_read():
+    """Durations (ms, numpy float32, launch order) of the CG-product launches recorded by the launch timer."""
+    import numpy as np
+    n = ctypes.c_int64(0)
+    N.check(N.load().fbsde_launch_timer_read(None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), dtype=np.float32)
+    N.check(N.load().fbsde_launch_timer_read(out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(n)))
+    return out[:n.value]
+
+
 KERNELS = {"cg_matvec": 0, "reverse_newton": 1, "moments": 2, "forward_terminal": 3, "stream_read": 4}
 
 

@@ -22,6 +22,41 @@ std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
 TuneKey tune_key(const fbsde_problem* pb, int64_t P) { return TuneKey{pb->prec, pb->d, pb->M, P}; }
 
+// ------------------------------------------------------------------ launch timer of the CG product
+// While on, every CG-product launch is bracketed by two events on its own stream (not inside a stream
+// capture).  The events are created on first use and reused after each restart.
+struct TimedLaunch {
+    hipEvent_t a, b;
+    bool ok;
+};
+std::mutex g_lt_mu;
+bool g_lt_on = false;
+std::vector<TimedLaunch> g_lt;
+size_t g_lt_used = 0;
+
+long lt_begin(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_lt_mu);
+    if (!g_lt_on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
+    if (g_lt_used == g_lt.size()) {
+        TimedLaunch t{nullptr, nullptr, false};
+        if (hipEventCreate(&t.a) != hipSuccess) return -1;
+        if (hipEventCreate(&t.b) != hipSuccess) { (void)hipEventDestroy(t.a); return -1; }
+        g_lt.push_back(t);
+    }
+    const size_t i = g_lt_used++;
+    g_lt[i].ok = false;
+    if (hipEventRecord(g_lt[i].a, st) != hipSuccess) return -1;
+    return (long)i;
+}
+
+void lt_end(long i, hipStream_t st) {
+    if (i < 0) return;
+    std::lock_guard<std::mutex> lk(g_lt_mu);
+    g_lt[(size_t)i].ok = hipEventRecord(g_lt[(size_t)i].b, st) == hipSuccess;
+}
+
 }  // namespace
 
 namespace fbsde {
@@ -140,12 +175,14 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
     const int poll = 8;
     int it = 0;
     for (; it < cap; ++it) {
+        const long tl = lt_begin(st);
         dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
             constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
             hipLaunchKernelGGL((k_matvec<S, R, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
                                W, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, ws.pv, ws.scal, NS,
                                ws.iscal, ws.part1, ws.psc);
         });
+        lt_end(tl, st);
         const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
         hipLaunchKernelGGL(k_cg_update, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, pl.ld,
                            pb->s, Wbar, ws.x, ws.r, ws.pv, ws.qv, ws.scal, NS, ws.iscal,
@@ -811,6 +848,30 @@ int fbsde_autotune(const fbsde_problem* pb, int64_t P, const double* x0, void* w
     out->n_candidates = (int32_t)cand.size();
     out->best_ms = best;
     out->default_ms = dflt;
+    return FBSDE_OK;
+}
+
+int fbsde_launch_timer(int32_t on) {
+    if (on != 0 && on != 1) return FBSDE_EINVAL;
+    std::lock_guard<std::mutex> lk(g_lt_mu);
+    if (on) g_lt_used = 0;
+    g_lt_on = on != 0;
+    return FBSDE_OK;
+}
+
+int fbsde_launch_timer_read(float* ms, int64_t cap, int64_t* n) {
+    if (!n || cap < 0 || (cap > 0 && !ms)) return FBSDE_EINVAL;
+    std::lock_guard<std::mutex> lk(g_lt_mu);
+    int64_t k = 0;
+    for (size_t i = 0; i < g_lt_used; ++i) {
+        if (!g_lt[i].ok) continue;
+        float t = 0.0f;
+        if (hipEventSynchronize(g_lt[i].b) != hipSuccess || hipEventElapsedTime(&t, g_lt[i].a, g_lt[i].b) != hipSuccess)
+            return FBSDE_EHIP;
+        if (k < cap) ms[k] = t;
+        ++k;
+    }
+    *n = k;
     return FBSDE_OK;
 }
 

@@ -83,3 +83,26 @@ def test_kernel_timer_and_read_ceiling(prec):
         t = F.time_kernel(hp, P, which, ws, reps=2)
         _say(f"  {which} {t:.4f} ms")
         assert t > 0
+
+
+def test_launch_timer_records_every_cg_product():
+    hp, _ = problems(d=300, M=256, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
+                     gp=(0.4, 0, 0, 0))
+    xt = torch.tensor(workloads.points("normal:0.3", 4, 300, 2), device=DEV)
+    ws = F.workspace(hp, 4)
+    F.solve(hp, xt, ws=ws)
+    torch.cuda.synchronize()
+    F.launch_timer(True)
+    _, _, st, iters = F.solve(hp, xt, ws=ws, return_iters=True)
+    F.launch_timer(False)
+    ms = F.launch_timer_read()
+    _say(f"[launch timer] {ms.size} launches for per-level iterations {iters}, mean {ms.mean():.4f} ms")
+    # the host loop polls every 8 iterations, so each level launches at most 7 more products than it needs
+    assert sum(iters) <= ms.size <= sum(iters) + 7 * len(iters)
+    assert np.all(ms > 0) and int(st.abs().sum().item()) == 0
+    # stopped: a further solve adds nothing; restarting clears the record
+    F.solve(hp, xt, ws=ws)
+    assert F.launch_timer_read().size == ms.size
+    F.launch_timer(True)
+    F.launch_timer(False)
+    assert F.launch_timer_read().size == 0

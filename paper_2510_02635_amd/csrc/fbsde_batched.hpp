@@ -33,10 +33,11 @@ struct SlotLayout {
     size_t off_rn2, off_Y, off_w, off_c2, off_vec;   // byte offsets of the [M] arrays and the [6][ld] vectors
 };
 
-template <typename S, int Q, int TEAM>
+// R: arithmetic type of the row dots and column sums (FP64 on the FP32 state for a rank-deficient FP32C
+// design, as in the single-instance path; otherwise the state's type).
+template <typename S, typename R, int Q, int TEAM>
 struct PointSolver {
     using G = Geo<Q, TEAM>;
-    using R = S;
     static constexpr int SPAN = 4 * Q * G::TL;
 
     const BatchInst& I;
@@ -393,7 +394,7 @@ struct PointSolver {
     }
 };
 
-template <typename S, int Q, int TEAM>
+template <typename S, typename R, int Q, int TEAM>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_batched(const BatchInst* __restrict__ insts, const BatchItem* __restrict__ items, int n_items, int* queue,
           char* __restrict__ slots, SlotLayout lay) {
@@ -411,7 +412,7 @@ k_batched(const BatchInst* __restrict__ insts, const BatchItem* __restrict__ ite
         const BatchItem item = items[it];
         const BatchInst& I = insts[item.inst];
         double* vec = (double*)(slot + lay.off_vec);
-        PointSolver<S, Q, TEAM> ps{I, item.p, (S*)slot, (double*)(slot + lay.off_rn2), (double*)(slot + lay.off_Y),
+        PointSolver<S, R, Q, TEAM> ps{I, item.p, (S*)slot, (double*)(slot + lay.off_rn2), (double*)(slot + lay.off_Y),
                                    (double*)(slot + lay.off_w), (double*)(slot + lay.off_c2), vec,
                                    vec + (size_t)I.ld, vec + 2 * (size_t)I.ld, vec + 3 * (size_t)I.ld,
                                    vec + 4 * (size_t)I.ld, vec + 5 * (size_t)I.ld, lds, red,

@@ -47,6 +47,7 @@ void batch_geometry(Plan& pl) {
 
 struct BatchClass {
     int prec, Q, TEAM;
+    bool r64 = false;         // FP32C with a rank-deficient centred design (M <= d + 1): FP64 arithmetic
     std::vector<int> insts;   // instance indices, by decreasing per-point cost
     int64_t items = 0;
     int64_t maxM = 0;
@@ -54,7 +55,7 @@ struct BatchClass {
 };
 
 int batch_classes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, std::vector<BatchClass>& out) {
-    std::map<std::tuple<int, int, int, int>, BatchClass> cls;
+    std::map<std::tuple<int, int, int, int, int>, BatchClass> cls;
     for (int64_t i = 0; i < n_inst; ++i) {
         int rc = check_problem(&pbs[i], P[i]);
         if (rc) return rc;
@@ -62,9 +63,10 @@ int batch_classes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, st
         Plan pl;
         if ((rc = make_plan(&pbs[i], 1, pl))) return rc;
         batch_geometry(pl);
-        const auto key = std::make_tuple(pbs[i].prec, pl.Q, pl.TEAM, pl.ld);
+        const bool r64 = pbs[i].prec == FBSDE_F32C && pbs[i].M <= pbs[i].d + 1;
+        const auto key = std::make_tuple(pbs[i].prec, (int)r64, pl.Q, pl.TEAM, pl.ld);
         BatchClass& c = cls[key];
-        c.prec = pbs[i].prec; c.Q = pl.Q; c.TEAM = pl.TEAM; c.ld = pl.ld;
+        c.prec = pbs[i].prec; c.Q = pl.Q; c.TEAM = pl.TEAM; c.ld = pl.ld; c.r64 = r64;
         c.insts.push_back((int)i);
         c.items += P[i];
         c.maxM = std::max<int64_t>(c.maxM, pbs[i].M);
@@ -88,8 +90,12 @@ void launch_batched_class(const BatchClass& c, const BatchInst* d_insts, const B
     set_int(queue, 0, st);
     dispatch<S>(c.Q, c.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        hipLaunchKernelGGL((k_batched<S, QQ, TT>), dim3(nslots), dim3(Geo<QQ, TT>::BS), 0, st, d_insts, d_items,
-                           n_items, queue, slots, lay);
+        if (c.r64)
+            hipLaunchKernelGGL((k_batched<S, double, QQ, TT>), dim3(nslots), dim3(Geo<QQ, TT>::BS), 0, st, d_insts,
+                               d_items, n_items, queue, slots, lay);
+        else
+            hipLaunchKernelGGL((k_batched<S, S, QQ, TT>), dim3(nslots), dim3(Geo<QQ, TT>::BS), 0, st, d_insts,
+                               d_items, n_items, queue, slots, lay);
     });
 }
 

@@ -149,3 +149,21 @@ def test_batched_backward_matches_single_and_oracle(tile_small):
         e = rel_err(xbs[i][0].cpu().numpy(), ref["x0bar"])
         _say(f"  inst {i}: oracle rel_err x0bar[0] = {e:.2e}")
         assert e <= tol
+
+
+def test_persistent_rank_deficient_fp32c_matches_oracle():
+    # the uneven-instance set's smallest-M instance of the d = 1000 class (HJB, T = 1, M <= d + 1): the persistent
+    # schedule runs its rows with FP64 arithmetic on the FP32 state, as the single-instance path does
+    it = min((i for i in workloads.batched_instances(64) if i["d"] == 1000), key=lambda i: i["M"])
+    hp, op = problems(d=it["d"], M=it["M"], N=20, T=1.0, f_kind=F.F_HJB, fp=(it["lam"], 0, 0, 0),
+                      g_kind=F.G_HJB_LOG, gp=(1.0, 0, 0, 0), prec=F.F32C, seed=0, instance=it["instance"])
+    x = workloads.points("uniform", 2, it["d"], 100 + it["instance"])
+    _say(f"[batched persistent] rank-deficient FP32C d={it['d']} M={it['M']}")
+    us, gs, sts = F.solve_batched([hp], [torch.tensor(x, device=DEV)], mode="persistent", max_slots=8)
+    torch.cuda.synchronize()
+    for p in range(2):
+        ref = OS.solve_point(op, x[p], p)
+        eu = abs(us[0][p].item() - ref["u"]) / abs(ref["u"])
+        eg = rel_err(gs[0][p].cpu().numpy(), ref["grad"])
+        _say(f"  p={p} rel_u={eu:.2e} rel_grad={eg:.2e}")
+        assert int(sts[0][p].item()) == 0 and eu <= 1e-5 and eg <= 1e-5

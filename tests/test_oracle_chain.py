@@ -9,6 +9,8 @@
 * Allen-Cahn Case 1 (paper Sec. 4.1: d = 100, T = 0.3, x0 = 0, f = u - u^3,
   g = 1/(2 + 0.4|x|^2)): the Richardson-extrapolated value is within 5e-4 of the printed
   reference 0.0528 (three printed digits); uniform weights.
+* Allen-Cahn at d = 1, 2 against a Crank-Nicolson solution of the PDE (radial reduction, independent
+  of the scheme): first-order error in dt, Richardson value within the Monte Carlo error.
 * HJB against the Cole-Hopf quadrature (loose gate: the scheme shares Z over the cloud,
   which biases u upward by the cloud variance of grad u).
 * Level-0 particles coincide, so all Y^m_0 are equal; shared-increment mode equals the
@@ -18,6 +20,7 @@ import numpy as np
 import pytest
 
 from oracle import colehopf as CH
+from oracle import radial_pde as RP
 from oracle import scheme as S
 
 
@@ -153,3 +156,23 @@ def test_burgers_scheme_against_closed_form():
         assert r["status"] == 0
     assert np.max(np.abs(errs)) < 2e-2 and abs(np.mean(errs)) < 1e-2
     assert np.median(gerr) < 0.15
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_allen_cahn_against_finite_differences(d):
+    # the scheme against a Crank-Nicolson solution of the same PDE (radial reduction; not the scheme): the error
+    # is first order in dt and the Richardson value agrees within the Monte Carlo error (about 2e-4 here)
+    s = np.sqrt(2.0)
+    ref = RP.radial_value(d, 0.3, s, lambda v: v - v ** 3, lambda r: 1.0 / (2.0 + 0.4 * r * r), 0.7,
+                          n=1200, steps=3000)
+    x0 = np.zeros(d)
+    x0[0] = 0.7
+    vals = {}
+    for N in (20, 40):
+        us = [S.solve_point(S.Problem(d=d, M=16384, N=N, T=0.3, f_kind=S.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0),
+                                      g_kind=S.G_AC, gp=(0.4, 0, 0, 0), eps_h=0.0, seed=seed), x0, 0)["u"]
+              for seed in range(2)]
+        vals[N] = float(np.mean(us))
+    rich = 2 * vals[40] - vals[20]
+    assert abs(vals[40] - ref) < abs(vals[20] - ref) < 2e-3
+    assert abs(rich - ref) < 1e-3

@@ -74,6 +74,25 @@ def timed_solves(F, torch, pb, x0, ws, warmup, steps, launches=None):
     return dt / steps, u, g, st, iters
 
 
+def batched_cg_traffic(ms, nbytes, wall_s):
+    """Algorithmic bytes the CG products of a batched run read, over its wall time.  Launches are grouped by
+    their size (one per tile shape); within a group, those shorter than half the longest are the launches
+    after every point of the tile converged, which exit at once and read nothing."""
+    import numpy as np
+    ms = np.asarray(ms, dtype=np.float64)
+    nbytes = np.asarray(nbytes, dtype=np.float64)
+    total, full = 0.0, 0
+    for b in np.unique(nbytes):
+        sel = ms[nbytes == b]
+        k = int((sel > 0.5 * sel.max()).sum())
+        total += k * b
+        full += k
+    total = float(total)
+    return {"launches": int(ms.size), "full_pass_launches": full, "bytes": total,
+            "achieved_GBs": round(total / wall_s / 1e9, 1), "frac_of_hbm_peak": round(total / wall_s / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "one read of the state per full-pass product, summed over the 4 streams, over the wall time"}
+
+
 def full_pass_mean(ms):
     """Mean of the launches that did a full pass: the launches after every point converged exit at once
     (the host polls every 8 iterations), and are told apart by a duration below half the largest."""
@@ -322,11 +341,15 @@ def main():
         # one small warm-up batch (thread pool, streams, first launches), then the timed batch
         F.solve_batched(probs[:2], [x[:1] for x in xb[:2]])
         torch.cuda.synchronize()
+        F.launch_timer(True)
         t0 = time.perf_counter()
         ub, gb, stb = F.solve_batched(probs, xb)
         torch.cuda.synchronize()
         sec_b = time.perf_counter() - t0
-        log(f"[bench] batched 64 instances x {Pb} points (tiled): {sec_b * 1e3:.1f} ms")
+        F.launch_timer(False)
+        cg_b = batched_cg_traffic(*F.launch_timer_read(with_bytes=True), sec_b)
+        log(f"[bench] batched 64 instances x {Pb} points (tiled): {sec_b * 1e3:.1f} ms, CG products "
+            f"{cg_b['achieved_GBs']:.0f} GB/s over the wall time")
         ubs = [torch.ones(x.shape[0], dtype=torch.float64, device=dev) for x in xb]
         t0 = time.perf_counter()
         rb = F.solve_batched_backward(probs, xb, ubs)
@@ -344,6 +367,7 @@ def main():
                               "d": "uniform over {100, 500, 1000, 5000, 10000}", "M": "multiples of 64 in [512, 8192]",
                               "T": 1.0, "N": 20, "f": "-lam |z|^2, lam ~ U[0.5, 2]", "g": "ln((1+|x|^2)/2)",
                               "x0": "U[-1,1]^d", "state_elements": elems},
+                   "cg_product_traffic": cg_b,
                    "status_nonzero_points": int(sum(int((s_ != 0).sum().item()) for s_ in stb))}
         del rb, ubs
         del xb, ub, gb, stb

@@ -292,10 +292,12 @@ int fbsde_autotune_reset(void);
  * fbsde_solve_backward on a stream that is not being captured is bracketed by two HIP events on that
  * stream (a few microseconds of host time per launch).  fbsde_launch_timer_read waits for the
  * recorded launches and writes the duration in milliseconds of the first `cap` of them, in launch
- * order, to `ms` (host), and their total count to *n.  The events are created on first use and kept
- * for the life of the process.  Thread-safe; the record is process-wide. */
+ * order, to `ms` (host), their algorithmic bytes (points x particles x d x element bytes: the one read
+ * of the state each product needs) to `bytes` (host, or NULL), and their total count to *n.  The
+ * events are created on first use and kept for the life of the process.  Thread-safe; the record is
+ * process-wide. */
 int fbsde_launch_timer(int32_t on);
-int fbsde_launch_timer_read(float* ms, int64_t cap, int64_t* n);
+int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n);
 
 /* Captured solve, for callers that repeat one solve with the same problem, sizes and buffers
  * (serving loops, parameter sweeps that rewrite x0 in place): the launch sequence of fbsde_solve

@@ -82,7 +82,7 @@ def load():
     lib.fbsde_time_kernel.argtypes = [pb, i64, i32, i32, vp, sz, P(ctypes.c_float), vp]
     lib.fbsde_box_muller.argtypes = [i32, i64, vp, vp, vp]
     lib.fbsde_launch_timer.argtypes = [i32]
-    lib.fbsde_launch_timer_read.argtypes = [vp, i64, P(i64)]
+    lib.fbsde_launch_timer_read.argtypes = [vp, vp, i64, P(i64)]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
                                ctypes.c_double, vp]
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]

@@ -193,13 +193,18 @@ def launch_timer(on):
     N.check(N.load().fbsde_launch_timer(1 if on else 0))
 
 
-def launch_timer_read():
-    """Durations (ms, numpy float32, launch order) of the CG-product launches recorded by the launch timer."""
+def launch_timer_read(with_bytes=False):
+    """Durations (ms, numpy float32, launch order) of the CG-product launches recorded by the launch timer,
+    and with `with_bytes` also their algorithmic bytes (numpy float64)."""
     import numpy as np
     n = ctypes.c_int64(0)
-    N.check(N.load().fbsde_launch_timer_read(None, 0, ctypes.byref(n)))
+    N.check(N.load().fbsde_launch_timer_read(None, None, 0, ctypes.byref(n)))
     out = np.zeros(max(n.value, 1), dtype=np.float32)
-    N.check(N.load().fbsde_launch_timer_read(out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(n)))
+    nb = np.zeros(out.size, dtype=np.float64)
+    N.check(N.load().fbsde_launch_timer_read(out.ctypes.data_as(ctypes.c_void_p), nb.ctypes.data_as(ctypes.c_void_p),
+                                             out.size, ctypes.byref(n)))
+    if with_bytes:
+        return out[:n.value], nb[:n.value]
     return out[:n.value]
 
 

@@ -28,25 +28,27 @@ TuneKey tune_key(const fbsde_problem* pb, int64_t P) { return TuneKey{pb->prec, 
 struct TimedLaunch {
     hipEvent_t a, b;
     bool ok;
+    double bytes;   // algorithmic bytes of the launch: P M d element bytes
 };
 std::mutex g_lt_mu;
 bool g_lt_on = false;
 std::vector<TimedLaunch> g_lt;
 size_t g_lt_used = 0;
 
-long lt_begin(hipStream_t st) {
+long lt_begin(hipStream_t st, double bytes) {
     std::lock_guard<std::mutex> lk(g_lt_mu);
     if (!g_lt_on) return -1;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
     if (g_lt_used == g_lt.size()) {
-        TimedLaunch t{nullptr, nullptr, false};
+        TimedLaunch t{nullptr, nullptr, false, 0.0};
         if (hipEventCreate(&t.a) != hipSuccess) return -1;
         if (hipEventCreate(&t.b) != hipSuccess) { (void)hipEventDestroy(t.a); return -1; }
         g_lt.push_back(t);
     }
     const size_t i = g_lt_used++;
     g_lt[i].ok = false;
+    g_lt[i].bytes = bytes;
     if (hipEventRecord(g_lt[i].a, st) != hipSuccess) return -1;
     return (long)i;
 }
@@ -175,7 +177,7 @@ int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64
     const int poll = 8;
     int it = 0;
     for (; it < cap; ++it) {
-        const long tl = lt_begin(st);
+        const long tl = lt_begin(st, (double)P * (double)pl.M * (double)pl.d * (double)sizeof(S));
         dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
             constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
             hipLaunchKernelGGL((k_matvec<S, R, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
@@ -859,7 +861,7 @@ int fbsde_launch_timer(int32_t on) {
     return FBSDE_OK;
 }
 
-int fbsde_launch_timer_read(float* ms, int64_t cap, int64_t* n) {
+int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n) {
     if (!n || cap < 0 || (cap > 0 && !ms)) return FBSDE_EINVAL;
     std::lock_guard<std::mutex> lk(g_lt_mu);
     int64_t k = 0;
@@ -868,7 +870,10 @@ int fbsde_launch_timer_read(float* ms, int64_t cap, int64_t* n) {
         float t = 0.0f;
         if (hipEventSynchronize(g_lt[i].b) != hipSuccess || hipEventElapsedTime(&t, g_lt[i].a, g_lt[i].b) != hipSuccess)
             return FBSDE_EHIP;
-        if (k < cap) ms[k] = t;
+        if (k < cap) {
+            ms[k] = t;
+            if (bytes) bytes[k] = g_lt[i].bytes;
+        }
         ++k;
     }
     *n = k;

@@ -111,8 +111,8 @@ def test_launch_timer_validation_on_host():
     lib = N.load()
     n = ctypes.c_int64(-1)
     assert lib.fbsde_launch_timer(2) == N.EINVAL
-    assert lib.fbsde_launch_timer_read(None, -1, ctypes.byref(n)) == N.EINVAL
-    assert lib.fbsde_launch_timer_read(None, 4, ctypes.byref(n)) == N.EINVAL
+    assert lib.fbsde_launch_timer_read(None, None, -1, ctypes.byref(n)) == N.EINVAL
+    assert lib.fbsde_launch_timer_read(None, None, 4, ctypes.byref(n)) == N.EINVAL
     # starting and stopping an empty record makes no HIP call
     assert lib.fbsde_launch_timer(1) == 0 and lib.fbsde_launch_timer(0) == 0
-    assert lib.fbsde_launch_timer_read(None, 0, ctypes.byref(n)) == 0 and n.value == 0
+    assert lib.fbsde_launch_timer_read(None, None, 0, ctypes.byref(n)) == 0 and n.value == 0

@@ -95,8 +95,9 @@ def test_launch_timer_records_every_cg_product():
     F.launch_timer(True)
     _, _, st, iters = F.solve(hp, xt, ws=ws, return_iters=True)
     F.launch_timer(False)
-    ms = F.launch_timer_read()
+    ms, nb = F.launch_timer_read(with_bytes=True)
     _say(f"[launch timer] {ms.size} launches for per-level iterations {iters}, mean {ms.mean():.4f} ms")
+    assert np.all(nb == 4 * 256 * 300 * 8)   # points x particles x d x FP64 bytes
     # the host loop polls every 8 iterations, so each level launches at most 7 more products than it needs
     assert sum(iters) <= ms.size <= sum(iters) + 7 * len(iters)
     assert np.all(ms > 0) and int(st.abs().sum().item()) == 0

@@ -90,7 +90,11 @@ def batched_cg_traffic(ms, nbytes, wall_s):
     total = float(total)
     return {"launches": int(ms.size), "full_pass_launches": full, "bytes": total,
             "achieved_GBs": round(total / wall_s / 1e9, 1), "frac_of_hbm_peak": round(total / wall_s / 1e9 / HBM_PEAK_GBS, 4),
-            "note": "one read of the state per full-pass product, summed over the 4 streams, over the wall time"}
+            "launch_time_s": round(float(ms.sum()) / 1e3, 3),
+            "stream_time_share": round(float(ms.sum()) / 1e3 / (4 * wall_s), 3),
+            "note": "bytes: one state read per launch that ran at least half as long as the longest launch of its "
+                    "tile (a lower bound: launches with part of a tile's points converged are left out); over the "
+                    "wall time; stream_time_share: CG-product time over 4 streams x wall time"}
 
 
 def full_pass_mean(ms):

@@ -5,6 +5,7 @@
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <new>
@@ -31,13 +32,14 @@ struct TimedLaunch {
     double bytes;   // algorithmic bytes of the launch: P M d element bytes
 };
 std::mutex g_lt_mu;
-bool g_lt_on = false;
+std::atomic<bool> g_lt_on{false};   // read without the lock on every launch, so a stopped timer costs nothing
 std::vector<TimedLaunch> g_lt;
 size_t g_lt_used = 0;
 
 long lt_begin(hipStream_t st, double bytes) {
+    if (!g_lt_on.load(std::memory_order_relaxed)) return -1;
     std::lock_guard<std::mutex> lk(g_lt_mu);
-    if (!g_lt_on) return -1;
+    if (!g_lt_on.load(std::memory_order_relaxed)) return -1;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
     if (g_lt_used == g_lt.size()) {
@@ -857,7 +859,7 @@ int fbsde_launch_timer(int32_t on) {
     if (on != 0 && on != 1) return FBSDE_EINVAL;
     std::lock_guard<std::mutex> lk(g_lt_mu);
     if (on) g_lt_used = 0;
-    g_lt_on = on != 0;
+    g_lt_on.store(on != 0);
     return FBSDE_OK;
 }
 

@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--no-shared", action="store_true", help="skip the shared-increment (MFMA) leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance leg")
     ap.add_argument("--batched-points", type=int, default=8, help="points per instance in the batched leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the one-point and d = 10^4 adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the points of this workload are independent, so a multi-GPU run "
@@ -258,8 +259,15 @@ def main():
         t0 = time.perf_counter()
         refs = [OS.solve_point(op, x0_np[p], p) for p in range(n)]
         tcpu = time.perf_counter() - t0
+        model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+        except OSError:
+            pass
         cpu = {"value": round(n / tcpu, 5), "unit": "points/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"points 0..{n - 1} of the {P}-point workload, full solve each ({tcpu:.1f} s)"}
+               "sample": f"points 0..{n - 1} of the {P}-point workload, full solve each ({tcpu:.1f} s)",
+               "host": {"cpu_model": model, "logical_cpus": os.cpu_count()}}
         adj_ref = OS.adjoint_point(op, x0_np[0], 0, ubar=1.0)
         errs["fp32c_x0bar_point0"] = float(f"{np.linalg.norm(x0bar[0] - adj_ref['x0bar']) / np.linalg.norm(adj_ref['x0bar']):.3e}")
         for name, uu, gg in (("fp32c", u32, g32), ("fp64", u64, g64)):
@@ -269,6 +277,57 @@ def main():
             eg = max(float(np.linalg.norm(gg[p] - refs[p]["grad"]) / np.linalg.norm(refs[p]["grad"]))
                      for p in range(n))
             errs[name] = {"u": float(f"{eu:.3e}"), "grad": float(f"{eg:.3e}")}
+
+    # ---------------- the other single-GPU configurations: one point at d = 100 (latency-bound, no roofline
+    # claim) and 128 points at d = 10^4 with M = 1024, forward + adjoint
+    small = None
+    if not args.no_small:
+        small = {}
+        pb0 = F.Problem(d=100, M=512, N=5, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,
+                        gp=(0.4, 0, 0, 0))
+        x00 = torch.zeros((1, 100), dtype=torch.float64, device=dev)
+        ws0 = F.workspace(pb0, 1, device=dev)
+        for _ in range(3):
+            F.solve(pb0, x00, ws=ws0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            F.solve(pb0, x00, ws=ws0)
+        torch.cuda.synchronize()
+        sec0 = (time.perf_counter() - t0) / 20
+        small["allen_cahn_d100_P1_M512_N5_fp64"] = {"ms_per_solve": round(sec0 * 1e3, 3),
+                                                    "points_per_s": round(1.0 / sec0, 1),
+                                                    "bound": "launch latency (a 0.4 MB state)"}
+        log(f"[bench] one point, d = 100: {sec0 * 1e3:.2f} ms per solve")
+        del ws0
+        P3, d3, M3 = 128, 10000, 1024
+        pb3 = F.Problem(d=d3, M=M3, N=20, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,
+                        gp=(0.4, 0, 0, 0), prec=F.F32C, instance=3)
+        x3 = torch.tensor(workloads.points("normal_over_sqrt_d", P3, d3, seed=3), dtype=torch.float64, device=dev)
+        ws3 = F.workspace(pb3, P3, tape=True, device=dev)
+        ub3 = torch.ones(P3, dtype=torch.float64, device=dev)
+
+        def fwd_adj3():
+            it_f = F.solve(pb3, x3, tape=True, ws=ws3, return_iters=True)[3]
+            return it_f, F.solve_backward(pb3, x3, ub3, ws3, return_iters=True)[4]
+
+        fwd_adj3()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            it3f, it3a = fwd_adj3()
+        torch.cuda.synchronize()
+        sec3 = (time.perf_counter() - t0) / args.steps
+        state3 = P3 * M3 * F.state_ld(pb3) * 4
+        # M <= d + 1: neither CG is warm-started, so the adjoint has no extra product per level
+        passes3 = fwd_passes(it3f) + sum(3 + k for k in it3a) + 1
+        small["allen_cahn_d10000_P128_M1024_N20_fp32c_fwd_adj"] = {
+            "value": round(P3 / sec3, 2), "unit": "points/s", "ms_per_step": round(sec3 * 1e3, 3),
+            "state_passes": passes3, "achieved_GBs": round(passes3 * state3 / sec3 / 1e9, 1),
+            "frac_of_hbm_peak": round(passes3 * state3 / sec3 / 1e9 / HBM_PEAK_GBS, 4),
+            "cg_iters_per_level": it3f, "adjoint_cg_iters_per_level": it3a}
+        log(f"[bench] d = 10^4, 128 points fwd+adj: {sec3 * 1e3:.1f} ms")
+        del ws3, x3
 
     # ---------------- shared increments: d = 10^4, 4096 points, M = 2048, N = 20 on the matrix cores
     shared = None
@@ -397,6 +456,7 @@ def main():
         "cg_iters_per_level_fp32c": it32,
         "adjoint_cg_iters_per_level_fp32c": it_adj,
         "whole_job_state_traffic": whole_job,
+        "other_configurations": small,
         "shared_increments_mfma": shared,
         "batched": batched,
         "reverse_sweep_avg_ms_fp32c": round(rev32_ms, 4),

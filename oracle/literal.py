@@ -1,0 +1,117 @@
+"""FP64 reference of the paper-literal per-anchor scheme.  Test infrastructure only.
+
+This is Algorithm 1 exactly as printed (Sec. 2.3 to 2.5). It keeps none of the readings that
+scheme.py takes for the local linear regression:
+
+* One regression per particle m and level k (the inner parallel loop of Algorithm 1). It is set in
+  X_k-space about the particle itself (eq. Dj): D^m_j = X^j_k - X^m_k.
+* The weights are the normalised Gaussian kernel of eq. Dj. The bandwidth is
+  eps_k^2 = h^2 E|X^j_k - X^m_k|^2 = h^2 2 s^2 t_k d, the expected squared distance between two
+  independent particles of the cloud. At k = 0 every D^m_j is zero, and the weights are uniform
+  (they are for h = 0 too).
+* The ridge functional J_lambda of the remark after the matrix-free steps penalises the
+  intercept as well, as printed, with lambda_k = ridge_rel s^2 t_{k+1} > 0.
+* The conditional expectation is the plain particle mean of eq. discreteYkm,
+  (1/M) sum_j Y^j_{k+1}. The fitted intercept is discarded.
+* Z^m_k = sigma^T alpha_x = s alpha_x. Y^m_k comes from the fixed-count Newton iteration of eq. NRiter
+  on y - mean - dt f(t_k, X^m_k, y, Z^m_k), started at the mean.
+* u(0, x0) = mean_m Y^m_0 (last step of Algorithm 1). At k = 0 the design is zero, so alpha_x = 0:
+  the scheme gives no gradient.
+
+The particles and increments are those of scheme.py: same counters, so the same paths.
+"""
+import numpy as np
+
+from . import scheme as S
+
+
+def anchor_weights(pb, D, k):
+    """Normalised Gaussian kernel weights of eq. Dj about one anchor (D: [M, d], rows X^j_k - X^m_k).
+
+    eps_k^2 = h^2 2 s^2 t_k d.  The smallest squared distance is subtracted inside the exponential,
+    which leaves the normalised weights unchanged (weight-ratio identity of the kernel remark).
+    """
+    n2 = np.einsum("ij,ij->i", D, D)
+    if pb.eps_h == 0.0 or k == 0:
+        e = np.ones(D.shape[0])
+    else:
+        t_k = k * pb.T / pb.N
+        eps2 = pb.eps_h ** 2 * 2.0 * pb.s ** 2 * t_k * pb.d
+        e = np.exp(-(n2 - n2.min()) / eps2)
+    return e / e.sum()
+
+
+def ridge_lambda(pb, k):
+    return pb.ridge_rel * pb.s ** 2 * (k + 1) * pb.T / pb.N
+
+
+def anchor_fit(pb, Xk, Y_next, m, k, form=None):
+    """alpha = (alpha, alpha_x) [d + 1] minimising J_lambda about anchor m (eq. normal-eq with the ridge).
+
+    Design rows [1, D_j] (eq. AY), weights of eq. Dj.  form "primal": the (d+1) x (d+1) normal
+    equations (D^T W D + lambda I) alpha = D^T W Y; "dual": the same minimiser through the M x M
+    system, alpha = B^T (B B^T + lambda I)^{-1} W^{1/2} Y with B = W^{1/2} D (push-through identity).
+    Default: the smaller of the two.  Returns (alpha, w).
+    """
+    M, d = Xk.shape
+    D = Xk - Xk[m][None, :]
+    w = anchor_weights(pb, D, k)
+    lam = ridge_lambda(pb, k)
+    if not lam > 0.0:
+        raise ValueError("the literal scheme needs a positive ridge")
+    A = np.hstack([np.ones((M, 1)), D])
+    if form is None:
+        form = "primal" if M > d + 1 else "dual"
+    if form == "primal":
+        H = A.T @ (w[:, None] * A) + lam * np.eye(d + 1)
+        alpha = np.linalg.solve(H, A.T @ (w * Y_next))
+    else:
+        sw = np.sqrt(w)
+        B = sw[:, None] * A
+        alpha = B.T @ np.linalg.solve(B @ B.T + lam * np.eye(M), sw * Y_next)
+    return alpha, w
+
+
+def solve_point(pb, x0, p, k_stop=0, form=None, tape=False):
+    """Algorithm 1 as printed for one evaluation point x0 [d] (global point index point_base + p).
+
+    Runs the backward levels N-1 .. k_stop.  Returns dict(u = mean_m Y^m_{k_stop}, Y = Y_{k_stop} [M],
+    status) and, with tape=True, zz[k] = |Z^m_k|^2 [M] and zs[k] = sum_i Z^m_k,i [M] per level.
+    """
+    x0 = np.asarray(x0, dtype=np.float64)
+    W = S.brownian_path(pb, p)
+    Y, _, _ = S.g_eval(pb, S.positions(pb, x0, W[pb.N], pb.N))
+    status = 0
+    zz_t, zs_t = {}, {}
+    for k in range(pb.N - 1, k_stop - 1, -1):
+        Xk = S.positions(pb, x0, W[k], k)
+        Ybar = float(Y.mean())
+        Ynew = np.empty(pb.M)
+        zz = np.empty(pb.M)
+        zs = np.empty(pb.M)
+        for m in range(pb.M):
+            alpha, _ = anchor_fit(pb, Xk, Y, m, k, form)
+            Z = pb.s * alpha[1:]
+            y, _, st = S.newton(pb, k, np.array([Ybar]), Z)
+            Ynew[m] = y[0]
+            zz[m] = Z @ Z
+            zs[m] = Z.sum()
+            status |= st
+        Y = Ynew
+        zz_t[k], zs_t[k] = zz, zs
+    u = float(Y.mean())
+    if not np.all(np.isfinite(Y)):
+        status |= S.ST_NONFINITE
+    out = dict(u=u, Y=Y, status=status)
+    if tape:
+        out.update(zz=zz_t, zs=zs_t)
+    return out
+
+
+def solve(pb, x0s, k_stop=0, points=None, form=None):
+    """u [P], Y_{k_stop} [P, M], status [P] for rows of x0s (optionally a subset of point indices)."""
+    x0s = np.asarray(x0s, dtype=np.float64)
+    idx = range(x0s.shape[0]) if points is None else points
+    res = [solve_point(pb, x0s[p], p, k_stop, form) for p in idx]
+    return (np.array([r["u"] for r in res]), np.stack([r["Y"] for r in res]),
+            np.array([r["status"] for r in res], dtype=np.uint32))

@@ -1,0 +1,121 @@
+"""Pins of the oracle's paper-literal per-anchor scheme (Algorithm 1 as printed, Sec. 2.3 to 2.5).
+
+* Each anchor's fit is checked against scikit-learn's weighted ridge regression on the design [1, D]
+  with no separate intercept. That is the functional J_lambda of the ridge remark, intercept
+  included. Both forms (primal and dual) are checked.
+* The kernel weights are checked against the weight-ratio identity of the kernel remark. They are
+  uniform at level 0 and largest at the anchor itself.
+* For an f that does not depend on z (Allen-Cahn), every particle's Y is the same below the terminal
+  level. u is then N implicit steps of the scalar equation y = c + dt f(y), started from the mean of
+  g over the cloud; each step's root is checked against bisection.
+* HJB (f = -lam |z|^2) and the Burgers-type f = c (y - kappa) sum z are checked at the first backward
+  level. Y^m has closed forms there, in the slope that scikit-learn fits. This pins Z = s alpha_x and
+  the sign of f.
+* At level 0 the design is zero, so the slope is exactly zero.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+from sklearn.linear_model import Ridge
+
+from oracle import literal as L
+from oracle import scheme as S
+
+
+def _sk_fit(pb, Xk, Y, m, k):
+    D = Xk - Xk[m][None, :]
+    w = L.anchor_weights(pb, D, k)
+    A = np.hstack([np.ones((Xk.shape[0], 1)), D])
+    r = Ridge(alpha=L.ridge_lambda(pb, k), fit_intercept=False, solver="cholesky")
+    r.fit(A, Y, sample_weight=w)
+    return r.coef_
+
+
+@pytest.mark.parametrize("M,d,form", [(12, 5, "primal"), (12, 5, "dual"), (6, 10, "dual"), (6, 10, "primal"),
+                                      (30, 3, None)])
+def test_anchor_fit_matches_sklearn_ridge(M, d, form):
+    rng = np.random.default_rng(M * 31 + d)
+    pb = S.Problem(d=d, M=M, N=6, T=0.6, s=1.3, ridge_rel=3e-2, eps_h=0.8)
+    k = 3
+    Xk = rng.normal(size=(M, d)) * np.sqrt(k * pb.T / pb.N) * pb.s + 0.4
+    Y = np.sin(Xk @ rng.normal(size=d)) + 0.1 * rng.normal(size=M)
+    for m in (0, M // 2, M - 1):
+        a, _ = L.anchor_fit(pb, Xk, Y, m, k, form)
+        ref = _sk_fit(pb, Xk, Y, m, k)
+        assert np.max(np.abs(a - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_primal_and_dual_agree():
+    rng = np.random.default_rng(5)
+    for M, d in ((9, 4), (5, 12), (20, 19)):
+        pb = S.Problem(d=d, M=M, N=4, T=1.0, ridge_rel=1e-3)
+        Xk = rng.normal(size=(M, d))
+        Y = rng.normal(size=M)
+        a1, _ = L.anchor_fit(pb, Xk, Y, 1, 2, "primal")
+        a2, _ = L.anchor_fit(pb, Xk, Y, 1, 2, "dual")
+        assert np.max(np.abs(a1 - a2)) <= 1e-9 * np.max(np.abs(a1))
+
+
+def test_weights_ratio_identity_uniform_at_level0():
+    rng = np.random.default_rng(8)
+    pb = S.Problem(d=7, M=15, N=5, T=0.5, s=1.1, eps_h=1.3)
+    k = 2
+    X = rng.normal(size=(15, 7))
+    D = X - X[4][None, :]
+    w = L.anchor_weights(pb, D, k)
+    eps2 = pb.eps_h ** 2 * 2 * pb.s ** 2 * (k * pb.T / pb.N) * pb.d
+    n2 = np.sum(D * D, axis=1)
+    for i, j in ((0, 1), (3, 9), (4, 14)):
+        assert w[j] / w[i] == pytest.approx(np.exp(-(n2[j] - n2[i]) / eps2), rel=1e-12)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.argmax(w) == 4
+    w0 = L.anchor_weights(pb, np.zeros((15, 7)), 0)
+    assert np.all(w0 == 1.0 / 15)
+    assert np.all(L.anchor_weights(pb.copy(eps_h=0.0), D, k) == 1.0 / 15)
+
+
+def test_allen_cahn_regression_drops_out():
+    pb = S.Problem(d=6, M=10, N=4, T=0.3, f_kind=S.F_ALLEN_CAHN, fp=(1.0, 1.0, 0.0, 0.0), g_kind=S.G_AC,
+                   gp=(0.4, 0.0, 0.0, 0.0), ridge_rel=1e-2, seed=3)
+    x0 = np.linspace(-0.5, 0.5, 6)
+    out = L.solve_point(pb, x0, 0)
+    W = S.brownian_path(pb, 0)
+    gN, _, _ = S.g_eval(pb, S.positions(pb, x0, W[pb.N], pb.N))
+    c = gN.mean()
+    dt = pb.T / pb.N
+    for _ in range(pb.N):
+        c = brentq(lambda y: y - c - dt * (y - y ** 3), c - 1.0, c + 1.0, xtol=1e-15)
+    assert out["u"] == pytest.approx(c, abs=1e-14)
+    assert np.ptp(out["Y"]) == 0.0
+
+
+@pytest.mark.parametrize("f_kind", [S.F_HJB, S.F_BURGERS])
+def test_first_level_closed_forms(f_kind):
+    d, M, N = 5, 9, 3
+    fp = (0.7, 0.0, 0.0, 0.0) if f_kind == S.F_HJB else (0.4, 2.0, 0.0, 0.0)
+    pb = S.Problem(d=d, M=M, N=N, T=0.9, s=1.2, f_kind=f_kind, fp=fp, g_kind=S.G_QUAD, gp=(1.0, 0.3, 0.0, 0.0),
+                   ridge_rel=2e-2, eps_h=1.0, seed=11)
+    x0 = np.full(d, 0.2)
+    k = N - 1
+    out = L.solve_point(pb, x0, 0, k_stop=k)
+    W = S.brownian_path(pb, 0)
+    YN, _, _ = S.g_eval(pb, S.positions(pb, x0, W[N], N))
+    Xk = S.positions(pb, x0, W[k], k)
+    Ybar = YN.mean()
+    dt = pb.T / N
+    for m in range(M):
+        ax = _sk_fit(pb, Xk, YN, m, k)[1:]
+        if f_kind == S.F_HJB:
+            ref = Ybar - dt * fp[0] * pb.s ** 2 * (ax @ ax)
+        else:
+            zs = pb.s * ax.sum()
+            ref = (Ybar - dt * fp[0] * fp[1] * zs) / (1.0 - dt * fp[0] * zs)
+        assert out["Y"][m] == pytest.approx(ref, rel=1e-10, abs=1e-13)
+
+
+def test_level0_slope_is_zero():
+    pb = S.Problem(d=4, M=6, N=2, T=0.2, ridge_rel=1e-2)
+    X0 = np.tile(np.array([0.1, -0.2, 0.3, 0.0]), (6, 1))
+    a, w = L.anchor_fit(pb, X0, np.arange(6.0), 2, 0)
+    assert np.all(a[1:] == 0.0)
+    assert np.all(w == 1.0 / 6)

@@ -200,7 +200,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
                       size_t ws_bytes, float* avg_ms, fbsde_stream stream);
 
 /* Many evaluation points of many PDE instances (uneven d, M, f, g, N, precision) in one call
- * (spec extension: batching over points and instances; the per-point chain is Algorithm 1).
+ * (batching over points and instances goes beyond the paper; the per-point chain is Algorithm 1).
  * Two schedules, chosen by opts->mode:
  *  FBSDE_BATCH_TILED (default): the work items are (instance, point-tile) pairs, largest first.  Each
  *    tile runs the whole chain through the multi-block path of fbsde_solve (each point split over
@@ -264,7 +264,7 @@ size_t fbsde_cholesky_workspace(int32_t prec, int64_t n, int64_t P);
 int fbsde_cholesky_solve(int32_t prec, int64_t n, void* K, int64_t ldk, int64_t P, void* R, int64_t ldr,
                          void* ws, size_t ws_bytes, int32_t* info, fbsde_stream stream);
 
-/* Autotuner of the launch shape (spec extension: the tile and split choices are picked by
+/* Autotuner of the launch shape (beyond the paper: the tile and split choices are picked by
  * measurement).  For this problem's precision, d, M and this P it times the fused CG product -- the
  * kernel that dominates a solve -- over the candidate shapes: the split of a particle row over 1, 2
  * or 4 times the default team width of wavefronts (fewer coordinates per lane) and the split of a
@@ -314,6 +314,30 @@ int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, do
                         fbsde_stream stream);
 int fbsde_graph_launch(fbsde_graph graph, fbsde_stream stream);
 int fbsde_graph_destroy(fbsde_graph graph);
+
+/* Paper-literal per-anchor scheme: Algorithm 1 as printed (Sec. 2.3 to 2.5), with none of the
+ * readings that fbsde_solve takes for the regression.  At every level k and for every particle m:
+ * the weighted ridge regression of eq. normal-eq (functional J_lambda of the ridge remark, intercept
+ * penalised as printed) over D^m_j = X^j_k - X^m_k (eq. Dj), Gaussian weights with
+ * eps_k^2 = eps_h^2 2 s^2 t_k d (uniform at k = 0 and for eps_h = 0), lambda_k = ridge_rel s^2 t_{k+1};
+ * Z^m_k = s alpha_x; Y^m_k from pb->newton_iters Newton steps (eq. NRiter) on
+ * y - Ybar - dt f(y, Z^m_k) started at the plain particle mean Ybar = (1/M) sum_j Y^j_{k+1}
+ * (eq. discreteYkm).  The slope is identically zero at k = 0 (every particle starts at x0), so the
+ * scheme gives no gradient.  Same particles (Philox counters) as fbsde_solve.
+ * Each regression is solved through its M x M dual system, built from the Gram matrix of the
+ * particles at level k; O(M^2 d + M^4 / 3) per level and point.
+ *   Requires prec = FBSDE_F64, shared_dw = 0, 2 <= M <= 256, ridge_rel > 0 (FBSDE_EINVAL otherwise).
+ *   k_stop   0 <= k_stop < N: the backward sweep runs levels N-1 .. k_stop
+ *   x0       device [P][d];  u device [P] out: mean_m Y^m_{k_stop} (u(0, x0) for k_stop = 0)
+ *   Y_out    device [P][M] out: Y^m_{k_stop}, or NULL
+ *   z_stats  device [P][M][2] out: |Z^m_{k_stop}|^2 and sum_i Z^m_{k_stop,i}, or NULL
+ *   status   device [P] cleared, then OR-ed with FBSDE_ST_NEWTON_FLAT / FBSDE_ST_NONFINITE
+ *   ws       device workspace of fbsde_literal_workspace_size(pb, P) bytes (FBSDE_ENOSPC if smaller)
+ * P = 0 returns FBSDE_OK without touching the pointers. */
+int fbsde_literal_workspace_size(const fbsde_problem* pb, int64_t P, size_t* bytes);
+int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, const double* x0, double* u,
+                        double* Y_out, double* z_stats, uint32_t* status, void* ws, size_t ws_bytes,
+                        fbsde_stream stream);
 
 /* Human-readable text of a return code. */
 const char* fbsde_strerror(int code);

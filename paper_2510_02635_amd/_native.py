@@ -15,7 +15,8 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
-            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_strerror")
+            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_literal_workspace_size",
+            "fbsde_solve_literal", "fbsde_strerror")
 
 
 BATCH_TILED, BATCH_PERSISTENT = 0, 1
@@ -96,13 +97,16 @@ def load():
     lib.fbsde_graph_destroy.argtypes = [vp]
     lib.fbsde_autotune.argtypes = [pb, i64, vp, vp, sz, P(CTuneResult), vp]
     lib.fbsde_autotune_reset.argtypes = []
+    lib.fbsde_literal_workspace_size.argtypes = [pb, i64, P(sz)]
+    lib.fbsde_solve_literal.argtypes = [pb, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
                  "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm",
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
-                 "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset"):
+                 "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
+                 "fbsde_solve_literal"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -422,3 +422,26 @@ def autotune(pb, x0, ws=None):
 
 def autotune_reset():
     N.check(N.load().fbsde_autotune_reset())
+
+
+def literal_workspace_size(pb, P):
+    out = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_literal_workspace_size(ctypes.byref(pb.c()), P, ctypes.byref(out)))
+    return int(out.value)
+
+
+def solve_literal(pb, x0, k_stop=0, want_Y=False, want_zstats=False, ws=None):
+    """Paper-literal per-anchor scheme (Algorithm 1 as printed): u [P] = mean_m Y^m_{k_stop}, status [P],
+    and optionally Y^m_{k_stop} [P][M] and (|Z^m|^2, sum_i Z^m_i) [P][M][2] at level k_stop."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    dev = x0.device
+    u = torch.empty(P, dtype=torch.float64, device=dev)
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+    Y = torch.empty((P, pb.M), dtype=torch.float64, device=dev) if want_Y else None
+    zs = torch.empty((P, pb.M, 2), dtype=torch.float64, device=dev) if want_zstats else None
+    if ws is None:
+        ws = torch.empty(max(literal_workspace_size(pb, P), 1), dtype=torch.uint8, device=dev)
+    N.check(N.load().fbsde_solve_literal(ctypes.byref(pb.c()), P, int(k_stop), x0.data_ptr(), u.data_ptr(), _ptr(Y),
+                                         _ptr(zs), st.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return u, st, Y, zs

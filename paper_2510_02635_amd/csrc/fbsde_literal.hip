@@ -1,0 +1,412 @@
+// Paper-literal per-anchor scheme on gfx950: Algorithm 1 as printed (Sec. 2.3 to 2.5), with one
+// weighted ridge regression per particle m and level k. Each regression is set in X_k-space about
+// the particle itself (eq. Dj, D^m_j = X^j_k - X^m_k) and penalises the intercept as printed. The
+// conditional expectation is the plain particle mean (eq. discreteYkm).
+//
+// Per level and evaluation point, where W are the Brownian displacements and X = x0 + mu t + s W:
+//   1. reversal    W_k = W_{k+1} - sqrt(dt) xi_k, with the increments regenerated from their counters
+//                  (all particles start at x0, so W_0 = 0 exactly);
+//   2. Gram        G = W_k W_k^T [M][M] and the row sums rho_j = sum_i W^j_k,i. Every anchor's
+//                  design follows from them:
+//                  D^m_i . D^m_j = s^2 (G_ij - G_im - G_jm + G_mm);
+//   3. anchors     one block per (m, p). The ridge minimiser alpha = (alpha, alpha_x) of J_lambda
+//                  comes from the M x M dual system (push-through identity):
+//                    S = Om (1 1^T + K) Om + lambda I,  Om = diag(sqrt(w)),  K_ij = D_i . D_j,
+//                    c = Om S^{-1} Om Y_{k+1},  alpha = sum_j c_j,  alpha_x = sum_j c_j D_j.
+//                  S, bordered by the right-hand side Om Y as an extra row, is factored in
+//                  registers. Each lane holds a block-cyclic set of lower-triangle entries. Each
+//                  pivot column is broadcast through LDS, one barrier per column with two column
+//                  buffers. The bordered row comes out as L^{-1} Om Y, so the forward solve is free,
+//                  and a back substitution gives S^{-1} Om Y. The nonlinearity needs only
+//                  |Z|^2 = s^2 c^T K c and sum_i Z_i = s^2 sum_j c_j (rho_j - rho_m) (Z = s alpha_x).
+//                  Both come from G without forming alpha_x. Newton (eq. NRiter) on
+//                  y - Ybar - dt f(y, Z) then gives Y^m_k.
+// Cost per level and point: O(M^2 d) for the Gram, and O(M^3 / 3) per anchor for the factorisation,
+// so O(M^4 / 3) in all. The anchors are independent blocks; the paper's M <= 200 fits in registers.
+//
+// FP64 throughout.  Limits: M <= 256, lambda > 0 (the dual form), no shared increments.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fbsde_host.hpp"
+
+namespace {
+
+using namespace fbsde;
+
+constexpr int LMAX = 256;   // largest M of the register-resident factorisation
+
+// W_k = W_{k+1} - sqrt(dt) xi_k for every point, particle and 4-coordinate group (zero: W_0 = 0).
+__global__ void __launch_bounds__(256)
+k_lit_reverse(double* __restrict__ W, int64_t ldw, int M, int d, int k, double sqdt, uint32_t point_base,
+              uint32_t k0, uint32_t k1, int64_t P, int zero) {
+    const int ng = (d + 3) / 4;
+    const int64_t n = P * (int64_t)M * ng;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(t % ng);
+        const int64_t pj = t / ng;
+        const int j = (int)(pj % M);
+        const int64_t p = pj / M;
+        double* row = W + pj * ldw + 4 * g;
+        if (zero) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * g + e < d) row[e] = 0.0;
+            continue;
+        }
+        double z[4];
+        increment4<double>((uint32_t)g, (uint32_t)j, (uint32_t)k, point_base + (uint32_t)p, k0, k1, z);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * g + e < d) row[e] -= sqdt * z[e];
+    }
+}
+
+// G = W W^T per point: 64 x 64 tiles of the lower triangle (mirrored on store), 4 x 4 outputs per
+// thread, the coordinate axis staged through LDS 16 at a time.  Grid (tiles, P).
+__global__ void __launch_bounds__(256)
+k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, double* __restrict__ G) {
+    __shared__ double As[64][17], Bs[64][17];
+    int bi = 0, t = blockIdx.x;
+    while (t > bi) { t -= bi + 1; ++bi; }
+    const int bj = t;
+    const int p = blockIdx.y, tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    const double* Wp = W + (int64_t)p * M * ldw;
+    const int r0 = 64 * bi, c0 = 64 * bj;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int k0 = 0; k0 < ld; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            const int row = e / 16, kk = e % 16;
+            As[row][kk] = (r0 + row < M) ? Wp[(int64_t)(r0 + row) * ldw + k0 + kk] : 0.0;
+            Bs[row][kk] = (c0 + row < M) ? Wp[(int64_t)(c0 + row) * ldw + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[4 * ty + r][kk];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[4 * tx + c][kk];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+        }
+        __syncthreads();
+    }
+    double* Gp = G + (int64_t)p * M * M;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = r0 + 4 * ty + r, j = c0 + 4 * tx + c;
+            if (i < M && j < M) {
+                Gp[(int64_t)i * M + j] = acc[r][c];
+                Gp[(int64_t)j * M + i] = acc[r][c];
+            }
+        }
+}
+
+// rho_j = sum_i W^j_i (one wave per particle row; the row pad is zero).  Grid (M, P).
+__global__ void __launch_bounds__(64)
+k_lit_rowsum(const double* __restrict__ W, int64_t ldw, int M, int ld, double* __restrict__ rho) {
+    const int j = blockIdx.x, p = blockIdx.y;
+    const double* row = W + ((int64_t)p * M + j) * ldw;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < ld; i += 64) v += row[i];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) rho[(int64_t)p * M + j] = v;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// One anchor m of point p at level k.  Grid (M, P), R x R threads.  The bordered (M + 1) x (M + 1)
+// system (row M holds the right-hand side) is spread block-cyclically: lane (r, c) = (tid / R, tid % R)
+// owns the lower-triangle entries (r + R a, c + R b), b <= a < A.  So every index is the lane's
+// coordinate plus a compile-time offset, and only the values take registers.
+//   eps2 = h^2 2 s^2 t_k d (0: uniform weights);  lam = ridge_rel s^2 t_{k+1} > 0.
+template <int R, int A>
+__global__ void __launch_bounds__(R * R)
+k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho, const double* __restrict__ Ynext,
+             double* __restrict__ Ynew, double s, double dt, double eps2, double lam, FSpec f, int newton_iters,
+             double* __restrict__ zstats, uint32_t* __restrict__ status) {
+    constexpr int NT = R * R;
+    constexpr int E = A * (A + 1) / 2;   // slot (a, b) is a (a + 1) / 2 + b
+    __shared__ double gm[LMAX], om[LMAX], yv[LMAX], dg[LMAX], rr[LMAX];
+    __shared__ double col[2][LMAX + 1];
+    __shared__ double red[NT / 64];
+    __shared__ double ybar_s;
+    const int m = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+    const int tr = tid / R, tc = tid % R;
+    const double* Gp = G + (int64_t)p * M * M;
+    const double s2 = s * s;
+    for (int j = tid; j < M; j += NT) {
+        gm[j] = Gp[(int64_t)m * M + j];
+        dg[j] = Gp[(int64_t)j * M + j];
+        yv[j] = Ynext[(int64_t)p * M + j];
+    }
+    __syncthreads();
+    const double gmm = gm[m];
+    // kernel weights of eq. Dj about the anchor (smallest squared distance subtracted) and the plain mean
+    if (tid < 64) {
+        double qmin = INFINITY, ys = 0.0;
+        for (int j = tid; j < M; j += 64) {
+            qmin = fmin(qmin, s2 * (dg[j] - 2.0 * gm[j] + gmm));
+            ys += yv[j];
+        }
+        qmin = wave_min(qmin);
+        ys = wave_sum(ys);
+        double es = 0.0;
+        for (int j = tid; j < M; j += 64) {
+            const double e = (eps2 > 0.0) ? exp(-(s2 * (dg[j] - 2.0 * gm[j] + gmm) - qmin) / eps2) : 1.0;
+            om[j] = e;
+            es += e;
+        }
+        es = wave_sum(es);
+        for (int j = tid; j < M; j += 64) om[j] = sqrt(om[j] / es);
+        if (tid == 0) ybar_s = ys / (double)M;
+    }
+    __syncthreads();
+
+    // entries of the bordered system
+    const int n = M + 1;
+    double v[E];
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + R * a, j = tc + R * b;
+            double x = 0.0;
+            if (i < n && j <= i) {
+                if (i < M) {
+                    const double Kij = s2 * (Gp[(int64_t)i * M + j] - gm[i] - gm[j] + gmm);
+                    x = om[i] * om[j] * (1.0 + Kij) + ((i == j) ? lam : 0.0);
+                } else if (j < M) {
+                    x = om[j] * yv[j];   // bordered row: the right-hand side (corner entry unused)
+                }
+            }
+            v[a * (a + 1) / 2 + b] = x;
+        }
+
+    // Cholesky, right-looking; pivot column jp broadcast through col[jp & 1] (two buffers: one barrier
+    // per column suffices, since a buffer is rewritten only after every lane passed the next barrier)
+    uint32_t st = 0;
+    for (int jp = 0; jp < M; ++jp) {
+        double* cb = col[jp & 1];
+        const int jb = jp / R;
+        if (tc == jp % R) {
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b) {
+                    const int i = tr + R * a;
+                    if (b == jb && i < n && i >= jp) cb[i] = v[a * (a + 1) / 2 + b];
+                }
+        }
+        __syncthreads();
+        const double dj = cb[jp];
+        if (!(dj > 0.0)) st |= ST_NONFINITE;
+        const double rs = 1.0 / sqrt(dj), inv = 1.0 / dj;
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                if (b < jb) continue;   // column block already factored (uniform)
+                const int i = tr + R * a, j = tc + R * b;
+                if (i < n && j <= i) {
+                    double& x = v[a * (a + 1) / 2 + b];
+                    if (j == jp) x *= rs;
+                    else if (j > jp) x -= cb[i] * cb[j] * inv;
+                }
+            }
+    }
+    // the bordered row now holds L^{-1} Om Y; back substitution L^T ct = L^{-1} Om Y
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + R * a, j = tc + R * b;
+            if (i == M && j < M) rr[j] = v[a * (a + 1) / 2 + b];
+            if (i == j && i < M) dg[i] = v[a * (a + 1) / 2 + b];
+        }
+    __syncthreads();
+    for (int jp = M - 1; jp >= 0; --jp) {
+        const double cj = rr[jp] / dg[jp];
+        if (tr == jp % R) {
+            const int ib = jp / R;
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b) {
+                    const int j = tc + R * b;
+                    if (a == ib && j < jp) rr[j] -= v[a * (a + 1) / 2 + b] * cj;
+                }
+        }
+        __syncthreads();
+        if (tid == 0) rr[jp] = cj;
+    }
+    __syncthreads();
+    for (int j = tid; j < M; j += NT) rr[j] *= om[j];   // c = Om ct
+    __syncthreads();
+
+    // c^T K c over the lower triangle (K from G) and sum_j c_j (rho_j - rho_m)
+    double q = 0.0;
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + R * a, j = tc + R * b;
+            if (i < M && j <= i) {
+                const double Kij = s2 * (Gp[(int64_t)i * M + j] - gm[i] - gm[j] + gmm);
+                q += ((i == j) ? 1.0 : 2.0) * rr[i] * rr[j] * Kij;
+            }
+        }
+    const double* rp = rho + (int64_t)p * M;
+    const double rm = rp[m];
+    double r = 0.0;
+    for (int j = tid; j < M; j += NT) r += rr[j] * (rp[j] - rm);
+    const double cKc = block_sum<NT>(q, red);
+    const double crho = block_sum<NT>(r, red);
+    if (tid == 0) {
+        const double zz = s2 * cKc;          // |Z|^2, Z = s alpha_x
+        const double zs = s2 * crho;         // sum_i Z_i
+        double Fp;
+        const double y = newton_y(f, ybar_s, zz, zs, dt, newton_iters, Fp, st);
+        Ynew[(int64_t)p * M + m] = y;
+        if (zstats) {
+            zstats[((int64_t)p * M + m) * 2 + 0] = zz;
+            zstats[((int64_t)p * M + m) * 2 + 1] = zs;
+        }
+        if (st) atomicOr(&status[p], st);
+    }
+}
+
+// u_p = mean_m Y^m (one wave per point).
+__global__ void __launch_bounds__(64) k_lit_mean(const double* __restrict__ Y, int M, double* __restrict__ u) {
+    const int p = blockIdx.x;
+    double v = 0.0;
+    for (int j = threadIdx.x; j < M; j += 64) v += Y[(int64_t)p * M + j];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) u[p] = v / (double)M;
+}
+
+struct LitWS {
+    double *W, *Ya, *Yb, *G, *rho;
+};
+
+size_t lit_carve(int64_t P, int64_t M, int64_t ld, char* base, LitWS& w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* ptr = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return (double*)ptr;
+    };
+    w.W = take((size_t)P * M * ld * 8);
+    w.Ya = take((size_t)P * M * 8);
+    w.Yb = take((size_t)P * M * 8);
+    w.G = take((size_t)P * M * M * 8);
+    w.rho = take((size_t)P * M * 8);
+    return off;
+}
+
+int lit_check(const fbsde_problem* pb, int64_t P, host::Plan& pl) {
+    int rc = host::check_problem(pb, P);
+    if (rc) return rc;
+    if (pb->prec != FBSDE_F64 || pb->shared_dw != 0) return FBSDE_EINVAL;
+    if (pb->M > LMAX || !(pb->ridge_rel > 0.0)) return FBSDE_EINVAL;
+    return host::make_plan(pb, P, pl);
+}
+
+template <int R, int A>
+int launch_anchor(int64_t P, int M, const double* G, const double* rho, const double* Yn, double* Y, double s,
+                  double dt, double eps2, double lam, FSpec f, int iters, double* zst, uint32_t* status,
+                  hipStream_t st) {
+    static_assert((R * R) % 64 == 0, "whole wavefronts");
+    if (R * A < M + 1 || M > LMAX) return FBSDE_EINVAL;   // the bordered system must fit the slots
+    hipLaunchKernelGGL((k_lit_anchor<R, A>), dim3(M, (unsigned)P), dim3(R * R), 0, st, G, M, rho, Yn, Y, s, dt, eps2,
+                       lam, f, iters, zst, status);
+    return FBSDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fbsde_literal_workspace_size(const fbsde_problem* pb, int64_t P, size_t* bytes) {
+    if (!bytes) return FBSDE_EINVAL;
+    host::Plan pl;
+    const int rc = lit_check(pb, P, pl);
+    if (rc) return rc;
+    LitWS w;
+    *bytes = lit_carve(P, pb->M, pl.ld, nullptr, w);
+    return FBSDE_OK;
+}
+
+int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, const double* x0, double* u,
+                        double* Y_out, double* z_stats, uint32_t* status, void* wsp, size_t ws_bytes,
+                        fbsde_stream stream) {
+    host::Plan pl;
+    int rc = lit_check(pb, P, pl);
+    if (rc) return rc;
+    if (k_stop < 0 || k_stop >= pb->N) return FBSDE_EINVAL;
+    if (P == 0) return FBSDE_OK;   // nothing is read or written; the pointers may be null
+    if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    LitWS w;
+    if (lit_carve(P, pb->M, pl.ld, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
+    lit_carve(P, pb->M, pl.ld, (char*)wsp, w);
+    hipStream_t st = (hipStream_t)stream;
+    const int M = (int)pb->M, d = (int)pb->d;
+    // forward sweep and terminal condition (clears status)
+    if ((rc = fbsde_terminal(pb, P, x0, w.W, pl.ld, w.Ya, status, stream))) return rc;
+    const host::Keys ky = host::keys_of(pb);
+    const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt), s = pb->s;
+    const int nb = (M + 63) / 64;
+    const int64_t ngroups = P * (int64_t)M * ((d + 3) / 4);
+    const unsigned rblocks = (unsigned)std::min<int64_t>((ngroups + 255) / 256, (int64_t)1 << 20);
+    const FSpec f = host::fspec_of(pb);
+    double* Yn = w.Ya;
+    double* Yk = w.Yb;
+    for (int k = (int)pb->N - 1; k >= k_stop; --k) {
+        hipLaunchKernelGGL(k_lit_reverse, dim3(rblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, k, sqdt,
+                           pb->point_base, ky.k0, ky.k1, P, k == 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_lit_gram, dim3(nb * (nb + 1) / 2, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
+                           M, pl.ld, w.G);
+        hipLaunchKernelGGL(k_lit_rowsum, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, pl.ld,
+                           w.rho);
+        const double eps2 = (pb->eps_h == 0.0 || k == 0) ? 0.0 : pb->eps_h * pb->eps_h * 2.0 * s * s * (k * dt) * d;
+        const double lam = pb->ridge_rel * s * s * ((k + 1) * dt);
+        double* zst = (k == k_stop) ? z_stats : nullptr;
+        const int it = pb->newton_iters;
+        if (M + 1 <= 80) rc = launch_anchor<16, 5>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 112) rc = launch_anchor<16, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 144) rc = launch_anchor<16, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 224) rc = launch_anchor<32, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else rc = launch_anchor<32, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        if (rc) return rc;
+        std::swap(Yn, Yk);
+    }
+    hipLaunchKernelGGL(k_lit_mean, dim3((unsigned)P), dim3(64), 0, st, Yn, M, u);
+    if (Y_out) (void)hipMemcpyAsync(Y_out, Yn, (size_t)P * M * 8, hipMemcpyDeviceToDevice, st);
+    return host::last_error();
+}
+
+}  // extern "C"

@@ -116,3 +116,25 @@ def test_launch_timer_validation_on_host():
     # starting and stopping an empty record makes no HIP call
     assert lib.fbsde_launch_timer(1) == 0 and lib.fbsde_launch_timer(0) == 0
     assert lib.fbsde_launch_timer_read(None, None, 0, ctypes.byref(n)) == 0 and n.value == 0
+
+
+def test_literal_scheme_validation_on_host():
+    lib = N.load()
+    size = ctypes.c_size_t(0)
+    ok = F.Problem(d=100, M=200, N=4, T=0.3)
+    assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 3, ctypes.byref(size)) == N.OK
+    # state W [P][M][ld], two Y buffers, the Gram matrices and row sums
+    assert size.value >= 3 * 200 * (112 + 200 + 3) * 8
+    for bad in (dict(M=257), dict(prec=N.F32C), dict(ridge_rel=0.0, M=300, d=8), dict(ridge_rel=0.0),
+                dict(shared_dw=1)):
+        kw = dict(d=100, M=200, N=4, T=0.3)
+        kw.update(bad)
+        pb = F.Problem(**kw)
+        assert lib.fbsde_literal_workspace_size(ctypes.byref(pb.c()), 3, ctypes.byref(size)) == N.EINVAL, bad
+    assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 3, None) == N.EINVAL
+    # P = 0: nothing to do, null pointers accepted; k_stop outside [0, N) and missing buffers rejected
+    c = ctypes.byref(ok.c())
+    assert lib.fbsde_solve_literal(c, 0, 0, None, None, None, None, None, None, 0, None) == N.OK
+    for k_stop in (-1, 4):
+        assert lib.fbsde_solve_literal(c, 1, k_stop, None, None, None, None, None, None, 0, None) == N.EINVAL
+    assert lib.fbsde_solve_literal(c, 1, 0, None, None, None, None, None, None, 0, None) == N.EINVAL

@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline] [
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 METRIC = "solved points/sec (u,∇u) + fwd+adjoint points/sec at d=1000, rel err vs FP64"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2510_02635_amd", "csrc", f)
                for f in ("fbsde_kernels.hpp", "fbsde_rowteam.hpp", "fbsde_device.hpp")]
@@ -119,6 +121,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance leg")
     ap.add_argument("--batched-points", type=int, default=8, help="points per instance in the batched leg")
     ap.add_argument("--no-small", action="store_true", help="skip the one-point and d = 10^4 adjoint legs")
+    ap.add_argument("--no-literal", action="store_true", help="skip the paper-literal per-anchor leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the points of this workload are independent, so a multi-GPU run "
@@ -329,6 +332,49 @@ def main():
         log(f"[bench] d = 10^4, 128 points fwd+adj: {sec3 * 1e3:.1f} ms")
         del ws3, x3
 
+    # ---------------- paper-literal per-anchor scheme at the paper's Burgers runtime setting:
+    # d = 10^4, M = 100, dt = 0.003 (N = 100), T = 0.3, x0 = 0, as 64 independent replicas of the point
+    literal = None
+    if not args.no_literal:
+        dl, Ml, Nl, Pl, Tl = 10000, 100, 100, 64, 0.3
+        sl = math.sqrt(2.0)
+        gvl = torch.full((dl,), 1.0 / dl, dtype=torch.float64, device=dev)
+        pbl = F.Problem(d=dl, M=Ml, N=Nl, T=Tl, s=sl, f_kind=F.F_BURGERS, fp=(sl / dl, dl / (sl * sl) + 0.5, 0, 0),
+                        g_kind=F.G_LOGISTIC, gp=(Tl, 0, 0, 0), gvec=gvl, eps_h=1.0, ridge_rel=1e-3, instance=6)
+        xl = torch.zeros((Pl, dl), dtype=torch.float64, device=dev)
+        wsl = torch.empty(F.literal_workspace_size(pbl, Pl), dtype=torch.uint8, device=dev)
+        F.solve_literal(pbl, xl, ws=wsl)
+        torch.cuda.synchronize()
+        F.launch_timer(True)
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps)):
+            ul, stl, _, _ = F.solve_literal(pbl, xl, ws=wsl)
+        torch.cuda.synchronize()
+        secl = (time.perf_counter() - t0) / max(1, args.steps)
+        F.launch_timer(False)
+        ms_l, work_l = F.launch_timer_read(with_bytes=True)
+        kinds_l = F.launch_timer_kinds()
+        legs = {}
+        for name, kind in (("gram", F.TIMED_LITERAL_GRAM), ("anchors", F.TIMED_LITERAL_ANCHORS)):
+            sel = kinds_l == kind
+            t_ms = float(ms_l[sel].mean())
+            tf = float(work_l[sel][0]) / (t_ms * 1e-3) / 1e12
+            legs[name] = {"launches": int(sel.sum()), "avg_ms": round(t_ms, 4),
+                          "share_of_solve": round(float(ms_l[sel].sum()) / 1e3 / (secl * max(1, args.steps)), 3),
+                          "flops_per_launch": float(work_l[sel][0]), "achieved_TFLOPs": round(tf, 2),
+                          "frac_of_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4)}
+        ul = ul.cpu().numpy()
+        literal = {"value": round(Pl / secl, 3), "unit": "points/s", "ms_per_step": round(secl * 1e3, 3),
+                   "dtype": "f64", "config": {"workload": "literal_burgers_d10000_M100_N100_T0.3_P64", "d": dl,
+                                              "M": Ml, "N": Nl, "T": Tl, "points": Pl, "x0": "0 (replicas)",
+                                              "ridge_rel": 1e-3, "kernel_h": 1.0},
+                   "u_mean": round(float(ul.mean()), 6), "u_sd": round(float(ul.std()), 6), "u_exact": 0.5,
+                   "status_nonzero_points": int((stl != 0).sum().item()), "kernels": legs,
+                   "paper_cpu_s_per_point_context": 1040.15}
+        log(f"[bench] literal per-anchor d=1e4 M=100 N=100 P=64: {secl * 1e3:.1f} ms "
+            f"(gram {legs['gram']['avg_ms']:.3f} ms/level, anchors {legs['anchors']['avg_ms']:.3f} ms/level)")
+        del wsl, xl
+
     # ---------------- shared increments: d = 10^4, 4096 points, M = 2048, N = 20 on the matrix cores
     shared = None
     if not args.no_shared:
@@ -458,6 +504,7 @@ def main():
         "whole_job_state_traffic": whole_job,
         "other_configurations": small,
         "shared_increments_mfma": shared,
+        "literal_per_anchor": literal,
         "batched": batched,
         "reverse_sweep_avg_ms_fp32c": round(rev32_ms, 4),
         "status_nonzero_points": int(np.count_nonzero(st32)),

@@ -286,18 +286,26 @@ int fbsde_autotune(const fbsde_problem* pb, int64_t P, const double* x0, void* w
                    fbsde_tune_result* out, fbsde_stream stream);
 int fbsde_autotune_reset(void);
 
-/* Launch timer of the fused CG product (the dominant kernel), for measuring it inside a caller's own
- * timed region.  fbsde_launch_timer(1) clears the record and starts it, fbsde_launch_timer(0) stops
- * it (the record is kept).  While it runs, every CG-product launch of fbsde_solve and
- * fbsde_solve_backward on a stream that is not being captured is bracketed by two HIP events on that
- * stream (a few microseconds of host time per launch).  fbsde_launch_timer_read waits for the
- * recorded launches and writes the duration in milliseconds of the first `cap` of them, in launch
- * order, to `ms` (host), their algorithmic bytes (points x particles x d x element bytes: the one read
- * of the state each product needs) to `bytes` (host, or NULL), and their total count to *n.  The
- * events are created on first use and kept for the life of the process.  Thread-safe; the record is
- * process-wide. */
+/* Launch timer of the dominant kernels, for measuring them inside a caller's own timed region.
+ * fbsde_launch_timer(1) clears the record and starts it; fbsde_launch_timer(0) stops it and keeps the
+ * record.  While it runs, each timed launch on a stream that is not being captured is bracketed by two
+ * HIP events on that stream, at a few microseconds of host time per launch. The timed launches are the
+ * CG products of fbsde_solve and fbsde_solve_backward, and the Gram and anchor launches of
+ * fbsde_solve_literal.
+ * fbsde_launch_timer_read waits for the recorded launches. For the first `cap` of them, in launch
+ * order, it writes the duration in milliseconds to `ms` (host) and the algorithmic work to `bytes`
+ * (host, or NULL); it writes their total count to *n. The work unit depends on the kind:
+ *   FBSDE_TIMED_CG_PRODUCT       bytes: points x particles x d x element bytes, the one read of the
+ *                                state that each product needs
+ *   FBSDE_TIMED_LITERAL_GRAM     FP64 flops: points x M (M + 1) x d (lower triangle of W W^T)
+ *   FBSDE_TIMED_LITERAL_ANCHORS  FP64 flops: points x M x (2/3 (M + 1)^3 + 6 M^2) (bordered factorisation,
+ *                                back substitution, system and quadratic-form assembly)
+ * fbsde_launch_timer_kinds writes the kinds of the same records.  The events are created on first use
+ * and kept for the life of the process.  Thread-safe; the record is process-wide. */
+enum { FBSDE_TIMED_CG_PRODUCT = 0, FBSDE_TIMED_LITERAL_GRAM = 1, FBSDE_TIMED_LITERAL_ANCHORS = 2 };
 int fbsde_launch_timer(int32_t on);
 int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n);
+int fbsde_launch_timer_kinds(int32_t* kinds, int64_t cap, int64_t* n);
 
 /* Captured solve, for callers that repeat one solve with the same problem, sizes and buffers
  * (serving loops, parameter sweeps that rewrite x0 in place): the launch sequence of fbsde_solve

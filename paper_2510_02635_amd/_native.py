@@ -15,7 +15,8 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
-            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_literal_workspace_size",
+            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
+            "fbsde_literal_workspace_size",
             "fbsde_solve_literal", "fbsde_strerror")
 
 
@@ -84,6 +85,7 @@ def load():
     lib.fbsde_box_muller.argtypes = [i32, i64, vp, vp, vp]
     lib.fbsde_launch_timer.argtypes = [i32]
     lib.fbsde_launch_timer_read.argtypes = [vp, vp, i64, P(i64)]
+    lib.fbsde_launch_timer_kinds.argtypes = [vp, i64, P(i64)]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
                                ctypes.c_double, vp]
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]
@@ -106,6 +108,7 @@ def load():
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
+                 "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
                  "fbsde_solve_literal"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

@@ -193,9 +193,23 @@ def launch_timer(on):
     N.check(N.load().fbsde_launch_timer(1 if on else 0))
 
 
+TIMED_CG_PRODUCT, TIMED_LITERAL_GRAM, TIMED_LITERAL_ANCHORS = 0, 1, 2
+
+
+def launch_timer_kinds():
+    """Kinds (numpy int32, TIMED_*) of the launches recorded by the launch timer, in launch order."""
+    import numpy as np
+    n = ctypes.c_int64(0)
+    N.check(N.load().fbsde_launch_timer_kinds(None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), dtype=np.int32)
+    N.check(N.load().fbsde_launch_timer_kinds(out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(n)))
+    return out[:n.value]
+
+
 def launch_timer_read(with_bytes=False):
-    """Durations (ms, numpy float32, launch order) of the CG-product launches recorded by the launch timer,
-    and with `with_bytes` also their algorithmic bytes (numpy float64)."""
+    """Durations (ms, numpy float32, launch order) of the launches recorded by the launch timer, and with
+    `with_bytes` also their algorithmic work (numpy float64: bytes for the CG product, FP64 flops for the
+    literal scheme's launches; launch_timer_kinds tells which)."""
     import numpy as np
     n = ctypes.c_int64(0)
     N.check(N.load().fbsde_launch_timer_read(None, None, 0, ctypes.byref(n)))

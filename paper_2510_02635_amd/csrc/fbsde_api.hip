@@ -23,34 +23,37 @@ std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
 TuneKey tune_key(const fbsde_problem* pb, int64_t P) { return TuneKey{pb->prec, pb->d, pb->M, P}; }
 
-// ------------------------------------------------------------------ launch timer of the CG product
-// While on, every CG-product launch is bracketed by two events on its own stream (not inside a stream
-// capture).  The events are created on first use and reused after each restart.
+// ------------------------------------------------------------------ launch timer
+// While on, every timed launch (the CG product; the Gram and anchor launches of the literal scheme) is
+// bracketed by two events on its own stream (not inside a stream capture).  The events are created on
+// first use and reused after each restart.
 struct TimedLaunch {
     hipEvent_t a, b;
     bool ok;
-    double bytes;   // algorithmic bytes of the launch: P M d element bytes
+    double work;    // algorithmic work of the launch: bytes (CG product) or FP64 flops (literal scheme)
+    int kind;       // FBSDE_TIMED_*
 };
 std::mutex g_lt_mu;
 std::atomic<bool> g_lt_on{false};   // read without the lock on every launch, so a stopped timer costs nothing
 std::vector<TimedLaunch> g_lt;
 size_t g_lt_used = 0;
 
-long lt_begin(hipStream_t st, double bytes) {
+long lt_begin(hipStream_t st, double work, int kind = FBSDE_TIMED_CG_PRODUCT) {
     if (!g_lt_on.load(std::memory_order_relaxed)) return -1;
     std::lock_guard<std::mutex> lk(g_lt_mu);
     if (!g_lt_on.load(std::memory_order_relaxed)) return -1;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
     if (g_lt_used == g_lt.size()) {
-        TimedLaunch t{nullptr, nullptr, false, 0.0};
+        TimedLaunch t{nullptr, nullptr, false, 0.0, 0};
         if (hipEventCreate(&t.a) != hipSuccess) return -1;
         if (hipEventCreate(&t.b) != hipSuccess) { (void)hipEventDestroy(t.a); return -1; }
         g_lt.push_back(t);
     }
     const size_t i = g_lt_used++;
     g_lt[i].ok = false;
-    g_lt[i].bytes = bytes;
+    g_lt[i].work = work;
+    g_lt[i].kind = kind;
     if (hipEventRecord(g_lt[i].a, st) != hipSuccess) return -1;
     return (long)i;
 }
@@ -65,6 +68,9 @@ void lt_end(long i, hipStream_t st) {
 
 namespace fbsde {
 namespace host {
+long timer_begin(hipStream_t st, double work, int kind) { return lt_begin(st, work, kind); }
+void timer_end(long i, hipStream_t st) { lt_end(i, st); }
+
 bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const auto it = g_tune.find(tune_key(pb, P));
@@ -874,8 +880,21 @@ int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n) {
             return FBSDE_EHIP;
         if (k < cap) {
             ms[k] = t;
-            if (bytes) bytes[k] = g_lt[i].bytes;
+            if (bytes) bytes[k] = g_lt[i].work;
         }
+        ++k;
+    }
+    *n = k;
+    return FBSDE_OK;
+}
+
+int fbsde_launch_timer_kinds(int32_t* kinds, int64_t cap, int64_t* n) {
+    if (!n || cap < 0 || (cap > 0 && !kinds)) return FBSDE_EINVAL;
+    std::lock_guard<std::mutex> lk(g_lt_mu);
+    int64_t k = 0;
+    for (size_t i = 0; i < g_lt_used; ++i) {
+        if (!g_lt[i].ok) continue;
+        if (k < cap) kinds[k] = g_lt[i].kind;
         ++k;
     }
     *n = k;

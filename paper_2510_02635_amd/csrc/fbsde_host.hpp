@@ -50,6 +50,10 @@ inline double cg_rtol_of(const fbsde_problem* pb) {
     return pb->cg_rtol;
 }
 
+// Launch timer records (fbsde_launch_timer): begin returns a record index or -1 when the timer is off.
+long timer_begin(hipStream_t st, double work, int kind);
+void timer_end(long i, hipStream_t st);
+
 // Launch shapes recorded by fbsde_autotune (process-wide table keyed by precision, d, M and P).
 bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk);
 

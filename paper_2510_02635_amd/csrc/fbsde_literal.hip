@@ -64,11 +64,16 @@ k_lit_reverse(double* __restrict__ W, int64_t ldw, int M, int d, int k, double s
 }
 
 // G = W W^T per point: 64 x 64 tiles of the lower triangle (mirrored on store), 4 x 4 outputs per
-// thread, the coordinate axis staged through LDS 16 at a time.  Grid (tiles, P).
+// thread, the coordinate axis staged through LDS 16 at a time.  The axis is split into `nsplit`
+// chunks of `chunk` coordinates (a multiple of 16), one workgroup each, so that a launch has enough
+// workgroups for the whole chip; chunk ks writes its partial matrix to Gpart[ks][P][M][M].
+// Grid (tiles * nsplit, P).
 __global__ void __launch_bounds__(256)
-k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, double* __restrict__ G) {
+k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, int ntiles, int chunk,
+           double* __restrict__ Gpart) {
     __shared__ double As[64][17], Bs[64][17];
-    int bi = 0, t = blockIdx.x;
+    const int ks = blockIdx.x / ntiles;
+    int bi = 0, t = blockIdx.x % ntiles;
     while (t > bi) { t -= bi + 1; ++bi; }
     const int bj = t;
     const int p = blockIdx.y, tid = threadIdx.x;
@@ -80,7 +85,8 @@ k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, double* __r
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-    for (int k0 = 0; k0 < ld; k0 += 16) {
+    const int kb = ks * chunk, ke = min(ld, kb + chunk);
+    for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + 256 * q;
@@ -103,7 +109,7 @@ k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, double* __r
         }
         __syncthreads();
     }
-    double* Gp = G + (int64_t)p * M * M;
+    double* Gp = Gpart + ((int64_t)ks * gridDim.y + p) * M * M;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -114,6 +120,92 @@ k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, double* __r
                 Gp[(int64_t)j * M + i] = acc[r][c];
             }
         }
+}
+
+// G = W W^T per point for M <= 128: one workgroup per (coordinate chunk, point) holds the chunk of all M
+// rows in LDS, 16 coordinates at a time, so each element of W is read once; thread t owns the 4 x 4
+// output blocks q = t + 256 r (r < NB) of the lower block triangle (q = bi (bi + 1) / 2 + bj, bj <= bi).
+// Grid (nsplit, P); chunk ks writes its partial matrix to Gpart[ks][P][M][M].
+template <int NB>
+__global__ void __launch_bounds__(256)
+k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int chunk, double* __restrict__ Gpart) {
+    __shared__ double Ws[128][17];
+    const int ks = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+    const int nb4 = (M + 3) / 4;
+    const int nblk = nb4 * (nb4 + 1) / 2;
+    int bi[NB], bj[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        const int q = tid + 256 * r;
+        int i = 0;
+        if (q < nblk) {
+            i = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+            while (i * (i + 1) / 2 > q) --i;
+            while ((i + 1) * (i + 2) / 2 <= q) ++i;
+        }
+        bi[r] = (q < nblk) ? i : 0;
+        bj[r] = (q < nblk) ? q - i * (i + 1) / 2 : 0;
+    }
+    double acc[NB][4][4];
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[r][x][y] = 0.0;
+    const double* Wp = W + (int64_t)p * M * ldw;
+    const int kb = ks * chunk, ke = min(ld, kb + chunk);
+    const int rows = 4 * nb4;
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        for (int e = tid; e < rows * 16; e += 256) {
+            const int row = e / 16, kk = e % 16;
+            Ws[row][kk] = (row < M) ? Wp[(int64_t)row * ldw + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            if (tid + 256 * r >= nblk) break;
+#pragma unroll 4
+            for (int kk = 0; kk < 16; ++kk) {
+                double a[4], b[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[x] = Ws[4 * bi[r] + x][kk];
+                    b[x] = Ws[4 * bj[r] + x][kk];
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[r][x][y] += a[x] * b[y];
+            }
+        }
+        __syncthreads();
+    }
+    double* Gp = Gpart + ((int64_t)ks * gridDim.y + p) * M * M;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        if (tid + 256 * r >= nblk) break;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int i = 4 * bi[r] + x, j = 4 * bj[r] + y;
+                if (i < M && j < M) {
+                    Gp[(int64_t)i * M + j] = acc[r][x][y];
+                    Gp[(int64_t)j * M + i] = acc[r][x][y];
+                }
+            }
+    }
+}
+
+// G = sum_ks Gpart[ks] in chunk order (deterministic), over P M M elements.
+__global__ void __launch_bounds__(256)
+k_lit_gram_sum(const double* __restrict__ Gpart, int nsplit, int64_t n, double* __restrict__ G) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int ks = 0; ks < nsplit; ++ks) v += Gpart[(int64_t)ks * n + e];
+        G[e] = v;
+    }
 }
 
 // rho_j = sum_i W^j_i (one wave per particle row; the row pad is zero).  Grid (M, P).
@@ -139,24 +231,37 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return s;
 }
 
-// One anchor m of point p at level k.  Grid (M, P), R x R threads.  The bordered (M + 1) x (M + 1)
-// system (row M holds the right-hand side) is spread block-cyclically: lane (r, c) = (tid / R, tid % R)
-// owns the lower-triangle entries (r + R a, c + R b), b <= a < A.  So every index is the lane's
-// coordinate plus a compile-time offset, and only the values take registers.
+// Slot layout of the anchor system on an RI x RJ lane grid: row block a < A holds rows RI a .. RI a + RI - 1
+// and meets the lower triangle in the column blocks b <= bmax(a).
+template <int RI, int RJ>
+constexpr int bmax(int a) { return (RI * a + RI - 1) / RJ; }
+template <int RI, int RJ>
+constexpr int slot0(int a) {   // first slot of row block a
+    int e = 0;
+    for (int q = 0; q < a; ++q) e += bmax<RI, RJ>(q) + 1;
+    return e;
+}
+
+// One anchor m of point p at level k.  Grid (M, P), RI x RJ threads.  The bordered (M + 1) x (M + 1)
+// system (row M holds the right-hand side) is spread block-cyclically: lane (r, c) = (tid / RJ, tid % RJ)
+// owns the entries (r + RI a, c + RJ b), b <= bmax(a), a < A.  So every index is the lane's coordinate
+// plus a compile-time offset, and only the values take registers.
 //   eps2 = h^2 2 s^2 t_k d (0: uniform weights);  lam = ridge_rel s^2 t_{k+1} > 0.
-template <int R, int A>
-__global__ void __launch_bounds__(R * R)
+template <int RI, int RJ, int A, bool CACHE>
+__global__ void __launch_bounds__(RI * RJ)
 k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho, const double* __restrict__ Ynext,
              double* __restrict__ Ynew, double s, double dt, double eps2, double lam, FSpec f, int newton_iters,
              double* __restrict__ zstats, uint32_t* __restrict__ status) {
-    constexpr int NT = R * R;
-    constexpr int E = A * (A + 1) / 2;   // slot (a, b) is a (a + 1) / 2 + b
+    constexpr int NT = RI * RJ;
+    constexpr int B = bmax<RI, RJ>(A - 1) + 1;                        // column blocks
+    constexpr int E = slot0<RI, RJ>(A);                               // slot (a, b) is slot0(a) + b
+    constexpr int CW = (RI * A > RJ * B) ? RI * A : RJ * B;            // padded column length
     __shared__ double gm[LMAX], om[LMAX], yv[LMAX], dg[LMAX], rr[LMAX];
-    __shared__ double col[2][LMAX + 1];
+    __shared__ double col[2][CW];          // pivot column, padded to every slot's row and column index
     __shared__ double red[NT / 64];
     __shared__ double ybar_s;
     const int m = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-    const int tr = tid / R, tc = tid % R;
+    const int tr = tid / RJ, tc = tid % RJ;
     const double* Gp = G + (int64_t)p * M * M;
     const double s2 = s * s;
     for (int j = tid; j < M; j += NT) {
@@ -193,8 +298,8 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + R * a, j = tc + R * b;
+        for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
+            const int i = tr + RI * a, j = tc + RJ * b;
             double x = 0.0;
             if (i < n && j <= i) {
                 if (i < M) {
@@ -204,61 +309,81 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
                     x = om[j] * yv[j];   // bordered row: the right-hand side (corner entry unused)
                 }
             }
-            v[a * (a + 1) / 2 + b] = x;
+            v[slot0<RI, RJ>(a) + b] = x;
         }
 
-    // Cholesky, right-looking; pivot column jp broadcast through col[jp & 1] (two buffers: one barrier
-    // per column suffices, since a buffer is rewritten only after every lane passed the next barrier)
+    // Symmetric elimination (L D L^T, no square roots), right-looking.  Step jp: the owners of column jp
+    // broadcast it through col[jp & 1] (two buffers: one barrier per column suffices, since a buffer
+    // is rewritten only after every lane has passed the next barrier); every entry (i, j), j > jp,
+    // takes S_ij -= S_i,jp S_j,jp / S_jp,jp.  Column jp keeps its values u_i,jp = L_i,jp d_jp, and the
+    // bordered row ends as z = L^{-1} Om Y with L unit lower triangular.  Slots outside the triangle
+    // (i >= n or j > i) are updated too: their values are never read, and the padded column buffer
+    // keeps every read in bounds.  In the pivot's own column block only lanes right of the pivot
+    // update; blocks left of it are finished (a uniform skip).
     uint32_t st = 0;
     for (int jp = 0; jp < M; ++jp) {
         double* cb = col[jp & 1];
-        const int jb = jp / R;
-        if (tc == jp % R) {
+        const int jb = jp / RJ, jr = jp % RJ;
+        if (tc == jr) {
 #pragma unroll
             for (int a = 0; a < A; ++a)
 #pragma unroll
-                for (int b = 0; b <= a; ++b) {
-                    const int i = tr + R * a;
-                    if (b == jb && i < n && i >= jp) cb[i] = v[a * (a + 1) / 2 + b];
-                }
+                for (int b = 0; b <= bmax<RI, RJ>(a); ++b)
+                    if (b == jb) cb[tr + RI * a] = v[slot0<RI, RJ>(a) + b];
         }
         __syncthreads();
         const double dj = cb[jp];
         if (!(dj > 0.0)) st |= ST_NONFINITE;
-        const double rs = 1.0 / sqrt(dj), inv = 1.0 / dj;
+        const double inv = 1.0 / dj;
+        const bool right = tc > jr;
+        if constexpr (CACHE) {
+            // the lane's A row and A column values of the pivot column, read once per step
+            double ci[A], cj[B];
 #pragma unroll
-        for (int a = 0; a < A; ++a)
+            for (int a = 0; a < A; ++a) ci[a] = cb[tr + RI * a];
 #pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                if (b < jb) continue;   // column block already factored (uniform)
-                const int i = tr + R * a, j = tc + R * b;
-                if (i < n && j <= i) {
-                    double& x = v[a * (a + 1) / 2 + b];
-                    if (j == jp) x *= rs;
-                    else if (j > jp) x -= cb[i] * cb[j] * inv;
+            for (int b = 0; b < B; ++b) cj[b] = (b >= jb) ? cb[tc + RJ * b] * inv : 0.0;
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+#pragma unroll
+                for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
+                    if (b < jb) continue;   // column block already factored (uniform)
+                    double& x = v[slot0<RI, RJ>(a) + b];
+                    const double y = fma(-ci[a], cj[b], x);
+                    x = (b > jb || right) ? y : x;
                 }
-            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+#pragma unroll
+                for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
+                    if (b < jb) continue;
+                    double& x = v[slot0<RI, RJ>(a) + b];
+                    const double y = fma(-cb[tr + RI * a], cb[tc + RJ * b] * inv, x);
+                    x = (b > jb || right) ? y : x;
+                }
+        }
     }
-    // the bordered row now holds L^{-1} Om Y; back substitution L^T ct = L^{-1} Om Y
+    // back substitution D L^T ct = z: ct_j = (z_j - sum_{i > j} u_ij ct_i) / d_j
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + R * a, j = tc + R * b;
-            if (i == M && j < M) rr[j] = v[a * (a + 1) / 2 + b];
-            if (i == j && i < M) dg[i] = v[a * (a + 1) / 2 + b];
+        for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
+            const int i = tr + RI * a, j = tc + RJ * b;
+            if (i == M && j < M) rr[j] = v[slot0<RI, RJ>(a) + b];
+            if (i == j && i < M) dg[i] = v[slot0<RI, RJ>(a) + b];
         }
     __syncthreads();
     for (int jp = M - 1; jp >= 0; --jp) {
         const double cj = rr[jp] / dg[jp];
-        if (tr == jp % R) {
-            const int ib = jp / R;
+        if (tr == jp % RI) {
+            const int ib = jp / RI;
 #pragma unroll
             for (int a = 0; a < A; ++a)
 #pragma unroll
-                for (int b = 0; b <= a; ++b) {
-                    const int j = tc + R * b;
-                    if (a == ib && j < jp) rr[j] -= v[a * (a + 1) / 2 + b] * cj;
+                for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
+                    const int j = tc + RJ * b;
+                    if (a == ib && j < jp) rr[j] -= v[slot0<RI, RJ>(a) + b] * cj;
                 }
         }
         __syncthreads();
@@ -273,8 +398,8 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + R * a, j = tc + R * b;
+        for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
+            const int i = tr + RI * a, j = tc + RJ * b;
             if (i < M && j <= i) {
                 const double Kij = s2 * (Gp[(int64_t)i * M + j] - gm[i] - gm[j] + gmm);
                 q += ((i == j) ? 1.0 : 2.0) * rr[i] * rr[j] * Kij;
@@ -310,8 +435,27 @@ __global__ void __launch_bounds__(64) k_lit_mean(const double* __restrict__ Y, i
 }
 
 struct LitWS {
-    double *W, *Ya, *Yb, *G, *rho;
+    double *W, *Ya, *Yb, *G, *rho, *Gpart;
 };
+
+// Split of the Gram contraction.  M <= 128: the row-resident kernel, one tile per point, about 1024
+// workgroups per launch; otherwise 64 x 64 tiles of the lower triangle, about 2048 workgroups.  At least
+// 256 coordinates per workgroup either way.
+struct GramSplit {
+    bool rows;
+    int ntiles, nsplit, chunk;
+};
+GramSplit gram_split(int64_t P, int64_t M, int64_t ld) {
+    GramSplit g;
+    g.rows = M <= 128;
+    const int nb = (int)((M + 63) / 64);
+    g.ntiles = g.rows ? 1 : nb * (nb + 1) / 2;
+    const int64_t tp = g.ntiles * std::max<int64_t>(P, 1);   // P = 0: a size query with nothing to split
+    const int64_t want = ((g.rows ? 1024 : 2048) + tp - 1) / tp;
+    g.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, ld / 256));
+    g.chunk = (int)host::round_up((ld + g.nsplit - 1) / g.nsplit, 16);
+    return g;
+}
 
 size_t lit_carve(int64_t P, int64_t M, int64_t ld, char* base, LitWS& w) {
     size_t off = 0;
@@ -325,6 +469,8 @@ size_t lit_carve(int64_t P, int64_t M, int64_t ld, char* base, LitWS& w) {
     w.Yb = take((size_t)P * M * 8);
     w.G = take((size_t)P * M * M * 8);
     w.rho = take((size_t)P * M * 8);
+    const GramSplit gs = gram_split(P, M, ld);
+    w.Gpart = (gs.nsplit > 1) ? take((size_t)gs.nsplit * P * M * M * 8) : w.G;
     return off;
 }
 
@@ -336,14 +482,18 @@ int lit_check(const fbsde_problem* pb, int64_t P, host::Plan& pl) {
     return host::make_plan(pb, P, pl);
 }
 
-template <int R, int A>
+template <int RI, int RJ, int A>
 int launch_anchor(int64_t P, int M, const double* G, const double* rho, const double* Yn, double* Y, double s,
                   double dt, double eps2, double lam, FSpec f, int iters, double* zst, uint32_t* status,
                   hipStream_t st) {
-    static_assert((R * R) % 64 == 0, "whole wavefronts");
-    if (R * A < M + 1 || M > LMAX) return FBSDE_EINVAL;   // the bordered system must fit the slots
-    hipLaunchKernelGGL((k_lit_anchor<R, A>), dim3(M, (unsigned)P), dim3(R * R), 0, st, G, M, rho, Yn, Y, s, dt, eps2,
-                       lam, f, iters, zst, status);
+    static_assert((RI * RJ) % 64 == 0, "whole wavefronts");
+    // every row and column of the bordered system must have a slot
+    if (RI * A < M + 1 || RJ * (bmax<RI, RJ>(A - 1) + 1) < M + 1 || M > LMAX) return FBSDE_EINVAL;
+    // the per-step cache of the pivot column costs A + B registers: left out where the slots alone
+    // nearly fill the 128-register budget of 1024-thread blocks
+    constexpr bool CACHE = !(RI * RJ == 1024 && A == 9);
+    hipLaunchKernelGGL((k_lit_anchor<RI, RJ, A, CACHE>), dim3(M, (unsigned)P), dim3(RI * RJ), 0, st, G, M, rho, Yn,
+                       Y, s, dt, eps2, lam, f, iters, zst, status);
     return FBSDE_OK;
 }
 
@@ -379,7 +529,11 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
     if ((rc = fbsde_terminal(pb, P, x0, w.W, pl.ld, w.Ya, status, stream))) return rc;
     const host::Keys ky = host::keys_of(pb);
     const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt), s = pb->s;
-    const int nb = (M + 63) / 64;
+    const GramSplit gs = gram_split(P, M, pl.ld);
+    const int64_t nG = P * (int64_t)M * M;
+    const unsigned sblocks = (unsigned)std::min<int64_t>((nG + 255) / 256, (int64_t)1 << 16);
+    const double gram_flops = (double)P * M * (M + 1.0) * d;
+    const double anchor_flops = (double)P * M * (2.0 / 3.0 * std::pow(M + 1.0, 3) + 6.0 * M * (double)M);
     const int64_t ngroups = P * (int64_t)M * ((d + 3) / 4);
     const unsigned rblocks = (unsigned)std::min<int64_t>((ngroups + 255) / 256, (int64_t)1 << 20);
     const FSpec f = host::fspec_of(pb);
@@ -388,19 +542,36 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
     for (int k = (int)pb->N - 1; k >= k_stop; --k) {
         hipLaunchKernelGGL(k_lit_reverse, dim3(rblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, k, sqdt,
                            pb->point_base, ky.k0, ky.k1, P, k == 0 ? 1 : 0);
-        hipLaunchKernelGGL(k_lit_gram, dim3(nb * (nb + 1) / 2, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
-                           M, pl.ld, w.G);
+        const long tg = host::timer_begin(st, gram_flops, FBSDE_TIMED_LITERAL_GRAM);
+        if (gs.rows && M <= 88)   // at most 256 blocks of 4 x 4: one per thread
+            hipLaunchKernelGGL(k_lit_gram_rows<1>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
+                               M, pl.ld, gs.chunk, w.Gpart);
+        else if (gs.rows)         // M <= 128: at most 528 blocks
+            hipLaunchKernelGGL(k_lit_gram_rows<3>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
+                               M, pl.ld, gs.chunk, w.Gpart);
+        else
+            hipLaunchKernelGGL(k_lit_gram, dim3(gs.ntiles * gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W,
+                               (int64_t)pl.ld, M, pl.ld, gs.ntiles, gs.chunk, w.Gpart);
+        if (gs.nsplit > 1)
+            hipLaunchKernelGGL(k_lit_gram_sum, dim3(sblocks), dim3(256), 0, st, w.Gpart, gs.nsplit, nG, w.G);
+        host::timer_end(tg, st);
         hipLaunchKernelGGL(k_lit_rowsum, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, pl.ld,
                            w.rho);
         const double eps2 = (pb->eps_h == 0.0 || k == 0) ? 0.0 : pb->eps_h * pb->eps_h * 2.0 * s * s * (k * dt) * d;
         const double lam = pb->ridge_rel * s * s * ((k + 1) * dt);
         double* zst = (k == k_stop) ? z_stats : nullptr;
         const int it = pb->newton_iters;
-        if (M + 1 <= 80) rc = launch_anchor<16, 5>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 112) rc = launch_anchor<16, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 144) rc = launch_anchor<16, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 224) rc = launch_anchor<32, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else rc = launch_anchor<32, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        const long ta = host::timer_begin(st, anchor_flops, FBSDE_TIMED_LITERAL_ANCHORS);
+        // lane grids: one wavefront up to M + 1 = 56, four up to 144, sixteen up to 257.  Measured at
+        // M = 100: four wavefronts per anchor beat two (2 x 8 lanes per row) by 1.4x; the kernel is bound
+        // by the issue of the per-step updates, which fewer lanes per anchor serialise.
+        if (M + 1 <= 56) rc = launch_anchor<8, 8, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 80) rc = launch_anchor<16, 16, 5>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 112) rc = launch_anchor<16, 16, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 144) rc = launch_anchor<16, 16, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else if (M + 1 <= 224) rc = launch_anchor<32, 32, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        else rc = launch_anchor<32, 32, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
+        host::timer_end(ta, st);
         if (rc) return rc;
         std::swap(Yn, Yk);
     }

@@ -116,6 +116,9 @@ def test_launch_timer_validation_on_host():
     # starting and stopping an empty record makes no HIP call
     assert lib.fbsde_launch_timer(1) == 0 and lib.fbsde_launch_timer(0) == 0
     assert lib.fbsde_launch_timer_read(None, None, 0, ctypes.byref(n)) == 0 and n.value == 0
+    assert lib.fbsde_launch_timer_kinds(None, 0, ctypes.byref(n)) == 0 and n.value == 0
+    assert lib.fbsde_launch_timer_kinds(None, 2, ctypes.byref(n)) == N.EINVAL
+    assert lib.fbsde_launch_timer_kinds(None, 0, None) == N.EINVAL
 
 
 def test_literal_scheme_validation_on_host():
@@ -132,6 +135,7 @@ def test_literal_scheme_validation_on_host():
         pb = F.Problem(**kw)
         assert lib.fbsde_literal_workspace_size(ctypes.byref(pb.c()), 3, ctypes.byref(size)) == N.EINVAL, bad
     assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 3, None) == N.EINVAL
+    assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 0, ctypes.byref(size)) == N.OK
     # P = 0: nothing to do, null pointers accepted; k_stop outside [0, N) and missing buffers rejected
     c = ctypes.byref(ok.c())
     assert lib.fbsde_solve_literal(c, 0, 0, None, None, None, None, None, None, 0, None) == N.OK

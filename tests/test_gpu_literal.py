@@ -4,8 +4,8 @@ Every case compares u = mean_m Y^m_{k_stop}, Y^m_{k_stop} for every anchor m and
 at level k_stop element by element. The tolerance is FP64's 1e-10 relative; |Z|^2 gets 1e-8 of its
 largest value, since it is a quadratic form of an ill-conditioned ridge solve (condition number up to
 about 2e3 d). The cases cover:
-* each of the four register layouts of the anchor factorisation (M + 1 <= 80, 112, 144, 224, 256)
-  and the boundaries between them;
+* each register layout of the anchor factorisation (one wavefront for M + 1 <= 56; four wavefronts
+  for M + 1 <= 80, 112, 144; sixteen for M + 1 <= 224, 257) and the boundaries between them;
 * every f family, including z-dependent ones (HJB, Burgers-type), and the affine and logistic
   terminal conditions;
 * uniform weights (h = 0) and the first, a middle and the last backward level;
@@ -58,7 +58,7 @@ HJB = dict(f_kind=OS.F_HJB, fp=(1.0, 0.0, 0.0, 0.0), g_kind=OS.G_HJB_LOG, gp=(1.
 AC = dict(f_kind=OS.F_ALLEN_CAHN, fp=(1.0, 1.0, 0.0, 0.0), g_kind=OS.G_AC, gp=(0.4, 0.0, 0.0, 0.0))
 
 
-@pytest.mark.parametrize("M", [2, 16, 79, 80, 111, 112, 143, 144, 200, 223, 224])
+@pytest.mark.parametrize("M", [2, 16, 55, 56, 79, 80, 100, 111, 112, 143, 144, 200, 223, 224])
 def test_literal_hjb_every_layout(M):
     kw = dict(d=24, M=M, N=3, T=0.5, s=np.sqrt(2.0), ridge_rel=1e-2, seed=M, **HJB)
     _run(kw, P=2)               # u(0, x0)

@@ -37,6 +37,55 @@ using namespace fbsde;
 
 constexpr int LMAX = 256;   // largest M of the register-resident factorisation
 
+// Forward sweep (Algorithm 1, eq. Xk): W^j_N = sum_k sqrt(dt) xi^j_k for every point, particle and
+// 4-coordinate group, accumulated in level order; the row pad up to ldw is written as zero.
+__global__ void __launch_bounds__(256)
+k_lit_forward(double* __restrict__ W, int64_t ldw, int M, int d, int N, double sqdt, uint32_t point_base,
+              uint32_t k0, uint32_t k1, int64_t P) {
+    const int ngl = (int)(ldw / 4);
+    const int64_t n = P * (int64_t)M * ngl;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(t % ngl);
+        const int64_t pj = t / ngl;
+        const int j = (int)(pj % M);
+        const int64_t p = pj / M;
+        double w[4] = {0.0, 0.0, 0.0, 0.0};
+        if (4 * g < d) {
+            for (int k = 0; k < N; ++k) {
+                double z[4];
+                increment4<double>((uint32_t)g, (uint32_t)j, (uint32_t)k, point_base + (uint32_t)p, k0, k1, z);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[e] += sqdt * z[e];
+            }
+        }
+        double* row = W + pj * ldw + 4 * g;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) row[e] = (4 * g + e < d) ? w[e] : 0.0;
+    }
+}
+
+// Terminal condition Y^j_N = g(x0 + mu T + s W^j_N) (one wave per particle row).  Grid (M, P).
+__global__ void __launch_bounds__(64)
+k_lit_terminal(const double* __restrict__ W, int64_t ldw, int M, int d, const double* __restrict__ x0,
+               const double* __restrict__ mu, const double* __restrict__ gvec, double s, double T, int g_kind,
+               double ga, double gb, double* __restrict__ Y, uint32_t* __restrict__ status) {
+    const int j = blockIdx.x, p = blockIdx.y;
+    const double* row = W + ((int64_t)p * M + j) * ldw;
+    const double* xp = x0 + (int64_t)p * d;
+    const bool dot = g_dot_arg(g_kind);
+    double q = 0.0;
+    for (int i = threadIdx.x; i < d; i += 64) {
+        const double X = xp[i] + (mu ? mu[i] * T : 0.0) + s * row[i];
+        q += dot ? gvec[i] * X : X * X;
+    }
+    q = wave_sum(q);
+    if (threadIdx.x == 0) {
+        const double y = g_of(g_kind, ga, gb, q, d);
+        Y[(int64_t)p * M + j] = y;
+        if (!isfinite(y)) atomicOr(&status[p], (uint32_t)ST_NONFINITE);
+    }
+}
+
 // W_k = W_{k+1} - sqrt(dt) xi_k for every point, particle and 4-coordinate group (zero: W_0 = 0).
 __global__ void __launch_bounds__(256)
 k_lit_reverse(double* __restrict__ W, int64_t ldw, int M, int d, int k, double sqdt, uint32_t point_base,
@@ -128,7 +177,8 @@ k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, int ntiles,
 // Grid (nsplit, P); chunk ks writes its partial matrix to Gpart[ks][P][M][M].
 template <int NB>
 __global__ void __launch_bounds__(256)
-k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int chunk, double* __restrict__ Gpart) {
+k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int chunk, double* __restrict__ Gpart,
+                double* __restrict__ Rpart) {
     __shared__ double Ws[128][17];
     const int ks = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
     const int nb4 = (M + 3) / 4;
@@ -156,12 +206,17 @@ k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int ch
     const double* Wp = W + (int64_t)p * M * ldw;
     const int kb = ks * chunk, ke = min(ld, kb + chunk);
     const int rows = 4 * nb4;
+    double rsum = 0.0;   // thread tid < M: its row's sum over the chunk (the row sums rho, fused)
     for (int k0 = kb; k0 < ke; k0 += 16) {
         for (int e = tid; e < rows * 16; e += 256) {
             const int row = e / 16, kk = e % 16;
             Ws[row][kk] = (row < M) ? Wp[(int64_t)row * ldw + k0 + kk] : 0.0;
         }
         __syncthreads();
+        if (tid < M) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) rsum += Ws[tid][kk];
+        }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             if (tid + 256 * r >= nblk) break;
@@ -181,6 +236,7 @@ k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int ch
         }
         __syncthreads();
     }
+    if (tid < M) Rpart[((int64_t)ks * gridDim.y + p) * M + tid] = rsum;
     double* Gp = Gpart + ((int64_t)ks * gridDim.y + p) * M * M;
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
@@ -198,13 +254,20 @@ k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int ch
     }
 }
 
-// G = sum_ks Gpart[ks] in chunk order (deterministic), over P M M elements.
+// G = sum_ks Gpart[ks] over P M M elements and, with Rpart, rho = sum_ks Rpart[ks] over nr = P M
+// elements, in chunk order (deterministic).
 __global__ void __launch_bounds__(256)
-k_lit_gram_sum(const double* __restrict__ Gpart, int nsplit, int64_t n, double* __restrict__ G) {
+k_lit_gram_sum(const double* __restrict__ Gpart, const double* __restrict__ Rpart, int nsplit, int64_t n,
+               int64_t nr, double* __restrict__ G, double* __restrict__ rho) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         double v = 0.0;
         for (int ks = 0; ks < nsplit; ++ks) v += Gpart[(int64_t)ks * n + e];
         G[e] = v;
+        if (Rpart && e < nr) {
+            double r = 0.0;
+            for (int ks = 0; ks < nsplit; ++ks) r += Rpart[(int64_t)ks * nr + e];
+            rho[e] = r;
+        }
     }
 }
 
@@ -435,7 +498,7 @@ __global__ void __launch_bounds__(64) k_lit_mean(const double* __restrict__ Y, i
 }
 
 struct LitWS {
-    double *W, *Ya, *Yb, *G, *rho, *Gpart;
+    double *W, *Ya, *Yb, *G, *rho, *Gpart, *Rpart;
 };
 
 // Split of the Gram contraction.  M <= 128: the row-resident kernel, one tile per point, about 1024
@@ -471,6 +534,8 @@ size_t lit_carve(int64_t P, int64_t M, int64_t ld, char* base, LitWS& w) {
     w.rho = take((size_t)P * M * 8);
     const GramSplit gs = gram_split(P, M, ld);
     w.Gpart = (gs.nsplit > 1) ? take((size_t)gs.nsplit * P * M * M * 8) : w.G;
+    // row sums: fused into the row-resident Gram kernel (partials per chunk), else their own kernel
+    w.Rpart = !gs.rows ? nullptr : (gs.nsplit > 1) ? take((size_t)gs.nsplit * P * M * 8) : w.rho;
     return off;
 }
 
@@ -525,10 +590,15 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
     lit_carve(P, pb->M, pl.ld, (char*)wsp, w);
     hipStream_t st = (hipStream_t)stream;
     const int M = (int)pb->M, d = (int)pb->d;
-    // forward sweep and terminal condition (clears status)
-    if ((rc = fbsde_terminal(pb, P, x0, w.W, pl.ld, w.Ya, status, stream))) return rc;
     const host::Keys ky = host::keys_of(pb);
     const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt), s = pb->s;
+    // forward sweep over every (point, particle, 4-coordinate group) and the terminal condition
+    host::clear_status(status, P, st);
+    const int64_t nfwd = P * (int64_t)M * (pl.ld / 4);
+    hipLaunchKernelGGL(k_lit_forward, dim3((unsigned)std::min<int64_t>((nfwd + 255) / 256, (int64_t)1 << 20)),
+                       dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, (int)pb->N, sqdt, pb->point_base, ky.k0, ky.k1, P);
+    hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, d, x0, pb->mu,
+                       pb->gvec, s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], w.Ya, status);
     const GramSplit gs = gram_split(P, M, pl.ld);
     const int64_t nG = P * (int64_t)M * M;
     const unsigned sblocks = (unsigned)std::min<int64_t>((nG + 255) / 256, (int64_t)1 << 16);
@@ -545,18 +615,20 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
         const long tg = host::timer_begin(st, gram_flops, FBSDE_TIMED_LITERAL_GRAM);
         if (gs.rows && M <= 88)   // at most 256 blocks of 4 x 4: one per thread
             hipLaunchKernelGGL(k_lit_gram_rows<1>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
-                               M, pl.ld, gs.chunk, w.Gpart);
+                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
         else if (gs.rows)         // M <= 128: at most 528 blocks
             hipLaunchKernelGGL(k_lit_gram_rows<3>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
-                               M, pl.ld, gs.chunk, w.Gpart);
+                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
         else
             hipLaunchKernelGGL(k_lit_gram, dim3(gs.ntiles * gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W,
                                (int64_t)pl.ld, M, pl.ld, gs.ntiles, gs.chunk, w.Gpart);
         if (gs.nsplit > 1)
-            hipLaunchKernelGGL(k_lit_gram_sum, dim3(sblocks), dim3(256), 0, st, w.Gpart, gs.nsplit, nG, w.G);
+            hipLaunchKernelGGL(k_lit_gram_sum, dim3(sblocks), dim3(256), 0, st, w.Gpart, gs.rows ? w.Rpart : nullptr,
+                               gs.nsplit, nG, P * (int64_t)M, w.G, w.rho);
         host::timer_end(tg, st);
-        hipLaunchKernelGGL(k_lit_rowsum, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, pl.ld,
-                           w.rho);
+        if (!gs.rows)
+            hipLaunchKernelGGL(k_lit_rowsum, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, pl.ld,
+                               w.rho);
         const double eps2 = (pb->eps_h == 0.0 || k == 0) ? 0.0 : pb->eps_h * pb->eps_h * 2.0 * s * s * (k * dt) * d;
         const double lam = pb->ridge_rel * s * s * ((k + 1) * dt);
         double* zst = (k == k_stop) ? z_stats : nullptr;

@@ -22,7 +22,14 @@ WORKLOADS = {
     "shared_allen_cahn_d10000_P4096_M2048_N20": (dict(d=10000, M=2048, N=20, T=0.3, f_kind=1, fp=(1.0, 1.0, 0, 0),
                                                       g_kind=1, gp=(0.4, 0, 0, 0), shared_dw=1, seed=0, instance=4),
                                                  "normal_over_sqrt_d", 4096),
+    # the paper's Burgers runtime setting (d = 10^4, M = 100, dt = 0.003, T = 0.3) under the paper-literal
+    # per-anchor scheme, 64 replicas of the point x0 = 0
+    "literal_burgers_d10000_M100_N100_P64": (dict(d=10000, M=100, N=100, T=0.3, f_kind=3,
+                                                  fp=(2 ** 0.5 / 10000, 10000 / 2 + 0.5, 0, 0), g_kind=4,
+                                                  gp=(0.3, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3, instance=6),
+                                             "zeros", 64),
 }
+LITERAL = ("literal_burgers_d10000_M100_N100_P64",)
 
 
 def main():
@@ -38,6 +45,16 @@ def main():
     from paper_2510_02635_amd import workloads
 
     kw, xkind, P = WORKLOADS[args.workload]
+    if args.workload in LITERAL:
+        gvec = torch.full((kw["d"],), 1.0 / kw["d"], dtype=torch.float64, device="cuda")
+        pb = F.Problem(gvec=gvec, **kw)
+        x0 = torch.zeros((P, kw["d"]), dtype=torch.float64, device="cuda")
+        u, st, _, _ = F.solve_literal(pb, x0)
+        u, st, _, _ = F.solve_literal(pb, x0)
+        torch.cuda.synchronize()
+        print(f"{args.workload} fp64 (literal, 2 solves): u[0]={u[0].item():.12g} "
+              f"nonzero status={int((st != 0).sum())}", flush=True)
+        return
     pb = F.Problem(prec=F.F32C if args.prec == "fp32c" else F.F64, **kw)
     x0 = torch.tensor(workloads.points(xkind, P, kw["d"], 1), dtype=torch.float64, device="cuda")
     if args.copy_mib > 0:

@@ -107,3 +107,20 @@ def test_literal_empty_and_errors():
         F.solve_literal(pb, x, ws=ws)
     with pytest.raises(F.FbsdeError):
         F.solve_literal(F.Problem(d=8, M=300, N=3, T=0.3), x)
+
+
+def test_literal_launch_timer_records_gram_and_anchor_launches():
+    d, M, N, P = 40, 30, 3, 2
+    pb = F.Problem(d=d, M=M, N=N, T=0.3, ridge_rel=1e-2, **HJB)
+    x = torch.zeros((P, d), dtype=torch.float64, device="cuda")
+    F.launch_timer(True)
+    F.solve_literal(pb, x)
+    torch.cuda.synchronize()
+    F.launch_timer(False)
+    ms, work = F.launch_timer_read(with_bytes=True)
+    kinds = F.launch_timer_kinds()
+    assert list(kinds) == [F.TIMED_LITERAL_GRAM, F.TIMED_LITERAL_ANCHORS] * N
+    assert np.all(ms > 0)
+    assert np.all(work[kinds == F.TIMED_LITERAL_GRAM] == P * M * (M + 1.0) * d)
+    ref = P * M * (2.0 / 3.0 * (M + 1.0) ** 3 + 6.0 * M * M)
+    assert np.allclose(work[kinds == F.TIMED_LITERAL_ANCHORS], ref, rtol=1e-12)

@@ -115,3 +115,75 @@ def solve(pb, x0s, k_stop=0, points=None, form=None):
     res = [solve_point(pb, x0s[p], p, k_stop, form) for p in idx]
     return (np.array([r["u"] for r in res]), np.stack([r["Y"] for r in res]),
             np.array([r["status"] for r in res], dtype=np.uint32))
+
+
+# ---------------------------------------------------------------- x-dependent coefficients
+# The same printed scheme with a coefficient family that depends on x (the paper's problem class of Sec.
+# 2.1 allows mu(t, x) and sigma(t, x)): the geometric family mu(x) = mu0 x, sigma(x) = sigma0 diag(x).
+# Readings for this family:
+# * Particles follow the Euler-Maruyama step of eq. Xk with the same normals as above:
+#   X_{k+1} = X_k + mu0 X_k dt + sigma0 X_k * sqrt(dt) xi_k (componentwise), X_0 = x0.
+# * Bandwidth: no closed form of E|X^j_k - X^m_k|^2 is used; eps_k^2 = h^2 2 (1/M) sum_j |X^j_k - Xbar_k|^2,
+#   the cloud's own mean squared pairwise distance (uniform weights at k = 0, where it is zero).
+# * Ridge: lambda_k = ridge_rel sigma0^2 t_{k+1}.
+# * Z^m_k = sigma(X^m_k)^T alpha_x = sigma0 X^m_k * alpha_x (componentwise).
+def geometric_path(pb, x0, p, mu0, sigma0):
+    """X[k, j, :] for k = 0..N under the geometric family (Euler-Maruyama, eq. Xk)."""
+    from . import philox
+    dt = pb.T / pb.N
+    X = np.empty((pb.N + 1, pb.M, pb.d))
+    X[0] = np.asarray(x0, dtype=np.float64)[None, :]
+    q = S.stream_of(pb, p)
+    for k in range(pb.N):
+        xi = philox.normals(pb.seed, pb.instance, q, k, pb.M, pb.d)
+        X[k + 1] = X[k] + mu0 * X[k] * dt + sigma0 * X[k] * (np.sqrt(dt) * xi)
+    return X
+
+
+def cloud_bandwidth(pb, Xk, k):
+    """eps_k^2 = h^2 2 (1/M) sum_j |X^j_k - Xbar|^2; 0 (uniform weights) at k = 0 or h = 0."""
+    if pb.eps_h == 0.0 or k == 0:
+        return 0.0
+    C = Xk - Xk.mean(axis=0)[None, :]
+    return pb.eps_h ** 2 * 2.0 * float(np.einsum("ij,ij->", C, C)) / Xk.shape[0]
+
+
+def anchor_fit_eps(Xk, Y_next, m, eps2, lam):
+    """Minimiser of J_lambda about anchor m (intercept penalised, as in anchor_fit) with bandwidth eps2
+    (0: uniform weights), by the (d+1) normal equations.  Returns (alpha [d+1], w)."""
+    M, d = Xk.shape
+    D = Xk - Xk[m][None, :]
+    n2 = np.einsum("ij,ij->i", D, D)
+    e = np.ones(M) if eps2 == 0.0 else np.exp(-(n2 - n2.min()) / eps2)
+    w = e / e.sum()
+    A = np.hstack([np.ones((M, 1)), D])
+    H = A.T @ (w[:, None] * A) + lam * np.eye(d + 1)
+    return np.linalg.solve(H, A.T @ (w * Y_next)), w
+
+
+def solve_point_geometric(pb, x0, p, mu0, sigma0, k_stop=0, tape=False):
+    """Algorithm 1 as printed under the geometric family, levels N-1 .. k_stop (pb.s and pb.mu unused).
+    Returns dict(u = mean_m Y^m_{k_stop}, Y, status) and, with tape, zz[k], zs[k] per particle."""
+    X = geometric_path(pb, x0, p, mu0, sigma0)
+    Y, _, _ = S.g_eval(pb, X[pb.N])
+    dt = pb.T / pb.N
+    status = 0
+    zz_t, zs_t = {}, {}
+    for k in range(pb.N - 1, k_stop - 1, -1):
+        Xk = X[k]
+        Ybar = float(Y.mean())
+        eps2 = cloud_bandwidth(pb, Xk, k)
+        lam = pb.ridge_rel * sigma0 ** 2 * (k + 1) * dt
+        Ynew, zz, zs = np.empty(pb.M), np.empty(pb.M), np.empty(pb.M)
+        for m in range(pb.M):
+            alpha, _ = anchor_fit_eps(Xk, Y, m, eps2, lam)
+            Z = sigma0 * Xk[m] * alpha[1:]
+            y, _, st = S.newton(pb, k, np.array([Ybar]), Z)
+            Ynew[m], zz[m], zs[m] = y[0], Z @ Z, Z.sum()
+            status |= st
+        Y = Ynew
+        zz_t[k], zs_t[k] = zz, zs
+    out = dict(u=float(Y.mean()), Y=Y, status=status | (0 if np.all(np.isfinite(Y)) else S.ST_NONFINITE))
+    if tape:
+        out.update(zz=zz_t, zs=zs_t)
+    return out

@@ -12,6 +12,10 @@
   level. Y^m has closed forms there, in the slope that scikit-learn fits. This pins Z = s alpha_x and
   the sign of f.
 * At level 0 the design is zero, so the slope is exactly zero.
+* Geometric family (mu = mu0 x, sigma = sigma0 diag(x)), an x-dependent-coefficient case of the paper's
+  problem class:
+  - the Euler-Maruyama cloud against its exact first and second moments, per coordinate, by z-tests;
+  - the first level against scikit-learn's ridge, with Z = sigma(X^m)^T alpha_x and the cloud bandwidth.
 """
 import numpy as np
 import pytest
@@ -119,3 +123,48 @@ def test_level0_slope_is_zero():
     a, w = L.anchor_fit(pb, X0, np.arange(6.0), 2, 0)
     assert np.all(a[1:] == 0.0)
     assert np.all(w == 1.0 / 6)
+
+
+# ---------------------------------------------------------------- geometric (x-dependent) coefficients
+def test_geometric_path_second_moment():
+    # E X_{k+1,i}^2 = X_{k,i}^2 ((1 + mu0 dt)^2 + sigma0^2 dt) for the Euler-Maruyama step with mu = mu0 x,
+    # sigma = sigma0 diag(x): a z-test of the cloud's mean over 4000 particles and 3 coordinates
+    mu0, s0 = 0.3, 0.4
+    pb = S.Problem(d=3, M=4000, N=5, T=1.0, seed=2)
+    x0 = np.array([1.0, -0.5, 2.0])
+    X = L.geometric_path(pb, x0, 0, mu0, s0)
+    dt = pb.T / pb.N
+    fac = ((1 + mu0 * dt) ** 2 + s0 ** 2 * dt) ** pb.N
+    for i in range(3):
+        v = X[pb.N, :, i] ** 2
+        z = (v.mean() - x0[i] ** 2 * fac) / (v.std() / np.sqrt(v.size))
+        assert abs(z) < 4.5, (i, z)
+    # the mean follows (1 + mu0 dt)^N
+    m = X[pb.N].mean(axis=0)
+    se = X[pb.N].std(axis=0) / np.sqrt(pb.M)
+    assert np.all(np.abs(m - x0 * (1 + mu0 * dt) ** pb.N) < 4.5 * se)
+
+
+def test_geometric_first_level_hjb_closed_form():
+    d, M, N, mu0, s0 = 4, 11, 3, 0.2, 0.5
+    pb = S.Problem(d=d, M=M, N=N, T=0.9, f_kind=S.F_HJB, fp=(0.6, 0, 0, 0), g_kind=S.G_QUAD, gp=(1.0, 0.2, 0, 0),
+                   ridge_rel=2e-2, eps_h=1.0, seed=4)
+    x0 = np.array([0.8, 1.2, -0.6, 1.0])
+    k = N - 1
+    out = L.solve_point_geometric(pb, x0, 0, mu0, s0, k_stop=k, tape=True)
+    X = L.geometric_path(pb, x0, 0, mu0, s0)
+    YN, _, _ = S.g_eval(pb, X[N])
+    Xk = X[k]
+    C = Xk - Xk.mean(axis=0)
+    eps2 = 2.0 * np.sum(C * C) / M
+    dt = pb.T / N
+    for m in range(M):
+        D = Xk - Xk[m]
+        n2 = np.sum(D * D, axis=1)
+        w = np.exp(-n2 / eps2)
+        w /= w.sum()
+        r = Ridge(alpha=pb.ridge_rel * s0 ** 2 * (k + 1) * dt, fit_intercept=False, solver="cholesky")
+        r.fit(np.hstack([np.ones((M, 1)), D]), YN, sample_weight=w)
+        Z = s0 * Xk[m] * r.coef_[1:]
+        assert out["zz"][k][m] == pytest.approx(Z @ Z, rel=1e-8)
+        assert out["Y"][m] == pytest.approx(YN.mean() - dt * 0.6 * (Z @ Z), rel=1e-10, abs=1e-13)

@@ -16,7 +16,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
             "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
-            "fbsde_literal_workspace_size",
+            "fbsde_literal_workspace_size", "fbsde_literal_coef_workspace_size", "fbsde_solve_literal_coef",
             "fbsde_solve_literal", "fbsde_strerror")
 
 
@@ -31,6 +31,14 @@ class CBatchOpts(ctypes.Structure):
 class CTuneResult(ctypes.Structure):
     _fields_ = [("team", ctypes.c_int32), ("q", ctypes.c_int32), ("nchunk", ctypes.c_int32),
                 ("n_candidates", ctypes.c_int32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
+
+
+COEF_GEOMETRIC = 1
+
+
+class CCoef(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu0", ctypes.c_double),
+                ("sigma0", ctypes.c_double)]
 
 
 class CProblem(ctypes.Structure):
@@ -101,6 +109,8 @@ def load():
     lib.fbsde_autotune_reset.argtypes = []
     lib.fbsde_literal_workspace_size.argtypes = [pb, i64, P(sz)]
     lib.fbsde_solve_literal.argtypes = [pb, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fbsde_literal_coef_workspace_size.argtypes = [pb, P(CCoef), i64, P(sz)]
+    lib.fbsde_solve_literal_coef.argtypes = [pb, P(CCoef), i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
@@ -108,7 +118,8 @@ def load():
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
-                 "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
+                 "fbsde_launch_timer_read", "fbsde_launch_timer_kinds", "fbsde_literal_coef_workspace_size",
+                 "fbsde_solve_literal_coef",
                  "fbsde_solve_literal"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

@@ -313,8 +313,9 @@ constexpr int slot0(int a) {   // first slot of row block a
 template <int RI, int RJ, int A, bool CACHE>
 __global__ void __launch_bounds__(RI * RJ)
 k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho, const double* __restrict__ Ynext,
-             double* __restrict__ Ynew, double s, double dt, double eps2, double lam, FSpec f, int newton_iters,
-             double* __restrict__ zstats, uint32_t* __restrict__ status) {
+             double* __restrict__ Ynew, double s, double dt, double eps2_all, const double* __restrict__ eps2_pp,
+             double lam, FSpec f, int newton_iters, double* __restrict__ zstats, double* __restrict__ c_out,
+             uint32_t* __restrict__ status) {
     constexpr int NT = RI * RJ;
     constexpr int B = bmax<RI, RJ>(A - 1) + 1;                        // column blocks
     constexpr int E = slot0<RI, RJ>(A);                               // slot (a, b) is slot0(a) + b
@@ -334,6 +335,7 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     }
     __syncthreads();
     const double gmm = gm[m];
+    const double eps2 = eps2_pp ? eps2_pp[p] : eps2_all;
     // kernel weights of eq. Dj about the anchor (smallest squared distance subtracted) and the plain mean
     if (tid < 64) {
         double qmin = INFINITY, ys = 0.0;
@@ -455,6 +457,11 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     __syncthreads();
     for (int j = tid; j < M; j += NT) rr[j] *= om[j];   // c = Om ct
     __syncthreads();
+    if (c_out) {   // x-dependent coefficients: Z needs alpha_x itself, formed by k_geo_zstats
+        for (int j = tid; j < M; j += NT) c_out[((int64_t)p * M + m) * M + j] = rr[j];
+        if (tid == 0 && st) atomicOr(&status[p], st);
+        return;
+    }
 
     // c^T K c over the lower triangle (K from G) and sum_j c_j (rho_j - rho_m)
     double q = 0.0;
@@ -488,6 +495,107 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     }
 }
 
+// ------------------------------------------------------------------ geometric coefficient family
+// mu(x) = mu0 x, sigma(x) = sigma0 diag(x).  The displacement V = X - x0 is stored at every level (the
+// path cannot be reversed from its increments), V_k at Vs + k P M ldw.
+
+// Forward sweep (eq. Xk): V_{k+1} = V_k + (mu0 dt + sigma0 sqrt(dt) xi_k) (x0 + V_k) componentwise,
+// V_0 = 0; one thread per (point, particle, 4-coordinate group), the row pad written as zero.
+__global__ void __launch_bounds__(256)
+k_geo_forward(double* __restrict__ Vs, int64_t ldw, int M, int d, int N, double dt, double sqdt, double mu0,
+              double s0, const double* __restrict__ x0, uint32_t point_base, uint32_t k0, uint32_t k1, int64_t P) {
+    const int ngl = (int)(ldw / 4);
+    const int64_t n = P * (int64_t)M * ngl;
+    const int64_t lstride = P * (int64_t)M * ldw;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(t % ngl);
+        const int64_t pj = t / ngl;
+        const int j = (int)(pj % M);
+        const int64_t p = pj / M;
+        double xg[4], v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xg[e] = (4 * g + e < d) ? x0[p * d + 4 * g + e] : 0.0;
+        double* row = Vs + pj * ldw + 4 * g;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) row[e] = 0.0;
+        for (int k = 0; k < N; ++k) {
+            if (4 * g < d) {
+                double z[4];
+                increment4<double>((uint32_t)g, (uint32_t)j, (uint32_t)k, point_base + (uint32_t)p, k0, k1, z);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] += (mu0 * dt + s0 * (sqdt * z[e])) * (xg[e] + v[e]);
+            }
+            double* rk = row + (int64_t)(k + 1) * lstride;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rk[e] = (4 * g + e < d) ? v[e] : 0.0;
+        }
+    }
+}
+
+// eps_k^2 = h2 2 (1/M) sum_j |V_j - Vbar|^2 = h2 2 (tr G / M - sum G / M^2) per point (one block each).
+__global__ void __launch_bounds__(256)
+k_geo_bandwidth(const double* __restrict__ G, int M, double h2, double* __restrict__ eps2) {
+    __shared__ double red[4];
+    const int p = blockIdx.x;
+    const double* Gp = G + (int64_t)p * M * M;
+    double tr = 0.0, tot = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)M * M; e += 256) {
+        const double g = Gp[e];
+        tot += g;
+        if (e / M == e % M) tr += g;
+    }
+    tr = block_sum<256>(tr, red);
+    tot = block_sum<256>(tot, red);
+    if (threadIdx.x == 0) eps2[p] = fmax(0.0, h2 * 2.0 * (tr / M - tot / ((double)M * M)));
+}
+
+// One anchor m of point p: alpha_x = sum_j c_j (V_j - V_m) from the dual solution c of k_lit_anchor,
+// Z = sigma0 (x0 + V_m) alpha_x componentwise, |Z|^2 and sum_i Z_i, then Newton (eq. NRiter) from the
+// plain mean.  Grid (M, P), 256 threads over the coordinates.
+__global__ void __launch_bounds__(256)
+k_geo_zstats(const double* __restrict__ Vk, int64_t ldw, int M, int d, const double* __restrict__ x0,
+             const double* __restrict__ C, const double* __restrict__ Ynext, double* __restrict__ Ynew, double s0,
+             double dt, FSpec f, int newton_iters, double* __restrict__ zstats, uint32_t* __restrict__ status) {
+    __shared__ double cv[LMAX], red[4], sc[2];
+    const int m = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+    for (int j = tid; j < M; j += 256) cv[j] = C[((int64_t)p * M + m) * M + j];
+    __syncthreads();
+    if (tid < 64) {
+        double cs = 0.0, ys = 0.0;
+        for (int j = tid; j < M; j += 64) {
+            cs += cv[j];
+            ys += Ynext[(int64_t)p * M + j];
+        }
+        cs = wave_sum(cs);
+        ys = wave_sum(ys);
+        if (tid == 0) { sc[0] = cs; sc[1] = ys / (double)M; }
+    }
+    __syncthreads();
+    const double* Vp = Vk + (int64_t)p * M * ldw;
+    const double* vm = Vp + (int64_t)m * ldw;
+    double zz = 0.0, zs = 0.0;
+    for (int i = tid; i < d; i += 256) {
+        double a = -sc[0] * vm[i];
+        for (int j = 0; j < M; ++j) a += cv[j] * Vp[(int64_t)j * ldw + i];
+        const double z = s0 * (x0[(int64_t)p * d + i] + vm[i]) * a;
+        zz += z * z;
+        zs += z;
+    }
+    zz = block_sum<256>(zz, red);
+    zs = block_sum<256>(zs, red);
+    if (tid == 0) {
+        uint32_t st = 0;
+        double Fp;
+        const double y = newton_y(f, sc[1], zz, zs, dt, newton_iters, Fp, st);
+        Ynew[(int64_t)p * M + m] = y;
+        if (zstats) {
+            zstats[((int64_t)p * M + m) * 2 + 0] = zz;
+            zstats[((int64_t)p * M + m) * 2 + 1] = zs;
+        }
+        if (st) atomicOr(&status[p], st);
+    }
+}
+
 // u_p = mean_m Y^m (one wave per point).
 __global__ void __launch_bounds__(64) k_lit_mean(const double* __restrict__ Y, int M, double* __restrict__ u) {
     const int p = blockIdx.x;
@@ -498,7 +606,14 @@ __global__ void __launch_bounds__(64) k_lit_mean(const double* __restrict__ Y, i
 }
 
 struct LitWS {
-    double *W, *Ya, *Yb, *G, *rho, *Gpart, *Rpart;
+    double *W, *Ya, *Yb, *G, *rho, *Gpart, *Rpart, *C, *eps2;
+};
+
+// Coefficient family of a literal solve: sigma = s I with constant drift (geo = false), or the
+// geometric family mu(x) = mu0 x, sigma(x) = sigma0 diag(x).
+struct Coef {
+    bool geo;
+    double mu0, s0;
 };
 
 // Split of the Gram contraction.  M <= 128: the row-resident kernel, one tile per point, about 1024
@@ -520,14 +635,17 @@ GramSplit gram_split(int64_t P, int64_t M, int64_t ld) {
     return g;
 }
 
-size_t lit_carve(int64_t P, int64_t M, int64_t ld, char* base, LitWS& w) {
+// Workspace: the state (scalar family: W_k, one level, reversed in place; geometric family: V_k for
+// k = 0..N), two Y buffers, the Gram matrices and row sums with their per-chunk partials, and for the
+// geometric family the dual solutions C [P][M][M] and the per-point bandwidths.
+size_t lit_carve(int64_t P, int64_t M, int64_t N, int64_t ld, bool geo, char* base, LitWS& w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* ptr = base ? base + off : nullptr;
         off += (bytes + 255) / 256 * 256;
         return (double*)ptr;
     };
-    w.W = take((size_t)P * M * ld * 8);
+    w.W = take((size_t)(geo ? N + 1 : 1) * P * M * ld * 8);
     w.Ya = take((size_t)P * M * 8);
     w.Yb = take((size_t)P * M * 8);
     w.G = take((size_t)P * M * M * 8);
@@ -536,6 +654,8 @@ size_t lit_carve(int64_t P, int64_t M, int64_t ld, char* base, LitWS& w) {
     w.Gpart = (gs.nsplit > 1) ? take((size_t)gs.nsplit * P * M * M * 8) : w.G;
     // row sums: fused into the row-resident Gram kernel (partials per chunk), else their own kernel
     w.Rpart = !gs.rows ? nullptr : (gs.nsplit > 1) ? take((size_t)gs.nsplit * P * M * 8) : w.rho;
+    w.C = geo ? take((size_t)P * M * M * 8) : nullptr;
+    w.eps2 = geo ? take((size_t)P * 8) : nullptr;
     return off;
 }
 
@@ -547,10 +667,18 @@ int lit_check(const fbsde_problem* pb, int64_t P, host::Plan& pl) {
     return host::make_plan(pb, P, pl);
 }
 
+int coef_check(const fbsde_problem* pb, const fbsde_coef* coef, Coef& c) {
+    if (!coef || coef->kind != FBSDE_COEF_GEOMETRIC || coef->reserved != 0) return FBSDE_EINVAL;
+    if (!(coef->sigma0 > 0.0) || !std::isfinite(coef->sigma0) || !std::isfinite(coef->mu0)) return FBSDE_EINVAL;
+    if (pb && pb->mu) return FBSDE_EINVAL;   // the family's drift replaces the constant one
+    c = {true, coef->mu0, coef->sigma0};
+    return FBSDE_OK;
+}
+
 template <int RI, int RJ, int A>
 int launch_anchor(int64_t P, int M, const double* G, const double* rho, const double* Yn, double* Y, double s,
                   double dt, double eps2, double lam, FSpec f, int iters, double* zst, uint32_t* status,
-                  hipStream_t st) {
+                  hipStream_t st, const double* eps2_pp, double* c_out) {
     static_assert((RI * RJ) % 64 == 0, "whole wavefronts");
     // every row and column of the bordered system must have a slot
     if (RI * A < M + 1 || RJ * (bmax<RI, RJ>(A - 1) + 1) < M + 1 || M > LMAX) return FBSDE_EINVAL;
@@ -558,8 +686,110 @@ int launch_anchor(int64_t P, int M, const double* G, const double* rho, const do
     // nearly fill the 128-register budget of 1024-thread blocks
     constexpr bool CACHE = !(RI * RJ == 1024 && A == 9);
     hipLaunchKernelGGL((k_lit_anchor<RI, RJ, A, CACHE>), dim3(M, (unsigned)P), dim3(RI * RJ), 0, st, G, M, rho, Yn,
-                       Y, s, dt, eps2, lam, f, iters, zst, status);
+                       Y, s, dt, eps2, eps2_pp, lam, f, iters, zst, c_out, status);
     return FBSDE_OK;
+}
+
+int anchors(int64_t P, int M, const double* G, const double* rho, const double* Yn, double* Y, double s, double dt,
+            double eps2, double lam, FSpec f, int it, double* zst, uint32_t* status, hipStream_t st,
+            const double* eps2_pp, double* c_out) {
+    // lane grids: one wavefront up to M + 1 = 56, four up to 144, sixteen up to 257.  Measured at
+    // M = 100: four wavefronts per anchor beat two (2 x 8 lanes per row) by 1.4x; the kernel is bound
+    // by the issue of the per-step updates, which fewer lanes per anchor serialise.
+#define LIT_ANCHOR(RI, RJ, A) \
+    launch_anchor<RI, RJ, A>(P, M, G, rho, Yn, Y, s, dt, eps2, lam, f, it, zst, status, st, eps2_pp, c_out)
+    if (M + 1 <= 56) return LIT_ANCHOR(8, 8, 7);
+    if (M + 1 <= 80) return LIT_ANCHOR(16, 16, 5);
+    if (M + 1 <= 112) return LIT_ANCHOR(16, 16, 7);
+    if (M + 1 <= 144) return LIT_ANCHOR(16, 16, 9);
+    if (M + 1 <= 224) return LIT_ANCHOR(32, 32, 7);
+    return LIT_ANCHOR(32, 32, 9);
+#undef LIT_ANCHOR
+}
+
+// The whole literal solve for either coefficient family (arguments validated by the callers).
+int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64_t P, int32_t k_stop,
+            const double* x0, double* u, double* Y_out, double* z_stats, uint32_t* status, const LitWS& w,
+            hipStream_t st) {
+    int rc = FBSDE_OK;
+    const int M = (int)pb->M, d = (int)pb->d;
+    const host::Keys ky = host::keys_of(pb);
+    const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt);
+    // the regression is in X-space: the scalar family's state is W (X = x0 + mu t + s W), the geometric
+    // family's is V = X - x0
+    const double s = cf.geo ? 1.0 : pb->s;
+    const int64_t lstride = P * (int64_t)M * pl.ld;
+    // forward sweep over every (point, particle, 4-coordinate group) and the terminal condition
+    host::clear_status(status, P, st);
+    const int64_t nfwd = P * (int64_t)M * (pl.ld / 4);
+    const unsigned fblocks = (unsigned)std::min<int64_t>((nfwd + 255) / 256, (int64_t)1 << 20);
+    if (cf.geo) {
+        hipLaunchKernelGGL(k_geo_forward, dim3(fblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, (int)pb->N, dt,
+                           sqdt, cf.mu0, cf.s0, x0, pb->point_base, ky.k0, ky.k1, P);
+        hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, w.W + pb->N * lstride,
+                           (int64_t)pl.ld, M, d, x0, nullptr, pb->gvec, 1.0, pb->T, pb->g_kind, pb->gp[0], pb->gp[1],
+                           w.Ya, status);
+    } else {
+        hipLaunchKernelGGL(k_lit_forward, dim3(fblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, (int)pb->N, sqdt,
+                           pb->point_base, ky.k0, ky.k1, P);
+        hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, d, x0,
+                           pb->mu, pb->gvec, s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], w.Ya, status);
+    }
+    const GramSplit gs = gram_split(P, M, pl.ld);
+    const int64_t nG = P * (int64_t)M * M;
+    const unsigned sblocks = (unsigned)std::min<int64_t>((nG + 255) / 256, (int64_t)1 << 16);
+    const double gram_flops = (double)P * M * (M + 1.0) * d;
+    const double anchor_flops = (double)P * M * (2.0 / 3.0 * std::pow(M + 1.0, 3) + 6.0 * M * (double)M);
+    const int64_t ngroups = P * (int64_t)M * ((d + 3) / 4);
+    const unsigned rblocks = (unsigned)std::min<int64_t>((ngroups + 255) / 256, (int64_t)1 << 20);
+    const FSpec f = host::fspec_of(pb);
+    const double s_ridge = cf.geo ? cf.s0 : pb->s;   // lambda_k = ridge_rel sigma^2 t_{k+1}
+    double* Yn = w.Ya;
+    double* Yk = w.Yb;
+    for (int k = (int)pb->N - 1; k >= k_stop; --k) {
+        double* Xk = w.W;
+        if (cf.geo) Xk = w.W + k * lstride;
+        else
+            hipLaunchKernelGGL(k_lit_reverse, dim3(rblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, k, sqdt,
+                               pb->point_base, ky.k0, ky.k1, P, k == 0 ? 1 : 0);
+        const long tg = host::timer_begin(st, gram_flops, FBSDE_TIMED_LITERAL_GRAM);
+        if (gs.rows && M <= 88)   // at most 256 blocks of 4 x 4: one per thread
+            hipLaunchKernelGGL(k_lit_gram_rows<1>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
+                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
+        else if (gs.rows)         // M <= 128: at most 528 blocks
+            hipLaunchKernelGGL(k_lit_gram_rows<3>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
+                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
+        else
+            hipLaunchKernelGGL(k_lit_gram, dim3(gs.ntiles * gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk,
+                               (int64_t)pl.ld, M, pl.ld, gs.ntiles, gs.chunk, w.Gpart);
+        if (gs.nsplit > 1)
+            hipLaunchKernelGGL(k_lit_gram_sum, dim3(sblocks), dim3(256), 0, st, w.Gpart, gs.rows ? w.Rpart : nullptr,
+                               gs.nsplit, nG, P * (int64_t)M, w.G, w.rho);
+        host::timer_end(tg, st);
+        if (!gs.rows && !cf.geo)
+            hipLaunchKernelGGL(k_lit_rowsum, dim3(M, (unsigned)P), dim3(64), 0, st, Xk, (int64_t)pl.ld, M, pl.ld,
+                               w.rho);
+        double eps2 = 0.0;
+        if (cf.geo)
+            hipLaunchKernelGGL(k_geo_bandwidth, dim3((unsigned)P), dim3(256), 0, st, w.G, M,
+                               k == 0 ? 0.0 : pb->eps_h * pb->eps_h, w.eps2);
+        else if (pb->eps_h != 0.0 && k != 0)
+            eps2 = pb->eps_h * pb->eps_h * 2.0 * s * s * (k * dt) * d;
+        const double lam = pb->ridge_rel * s_ridge * s_ridge * ((k + 1) * dt);
+        double* zst = (k == k_stop) ? z_stats : nullptr;
+        const long ta = host::timer_begin(st, anchor_flops, FBSDE_TIMED_LITERAL_ANCHORS);
+        rc = anchors(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, pb->newton_iters, zst, status, st,
+                     cf.geo ? w.eps2 : nullptr, cf.geo ? w.C : nullptr);
+        host::timer_end(ta, st);
+        if (rc) return rc;
+        if (cf.geo)
+            hipLaunchKernelGGL(k_geo_zstats, dim3(M, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld, M, d, x0, w.C,
+                               Yn, Yk, cf.s0, dt, f, pb->newton_iters, zst, status);
+        std::swap(Yn, Yk);
+    }
+    hipLaunchKernelGGL(k_lit_mean, dim3((unsigned)P), dim3(64), 0, st, Yn, M, u);
+    if (Y_out) (void)hipMemcpyAsync(Y_out, Yn, (size_t)P * M * 8, hipMemcpyDeviceToDevice, st);
+    return host::last_error();
 }
 
 }  // namespace
@@ -572,7 +802,7 @@ int fbsde_literal_workspace_size(const fbsde_problem* pb, int64_t P, size_t* byt
     const int rc = lit_check(pb, P, pl);
     if (rc) return rc;
     LitWS w;
-    *bytes = lit_carve(P, pb->M, pl.ld, nullptr, w);
+    *bytes = lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w);
     return FBSDE_OK;
 }
 
@@ -586,70 +816,38 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
     if (P == 0) return FBSDE_OK;   // nothing is read or written; the pointers may be null
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     LitWS w;
-    if (lit_carve(P, pb->M, pl.ld, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
-    lit_carve(P, pb->M, pl.ld, (char*)wsp, w);
-    hipStream_t st = (hipStream_t)stream;
-    const int M = (int)pb->M, d = (int)pb->d;
-    const host::Keys ky = host::keys_of(pb);
-    const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt), s = pb->s;
-    // forward sweep over every (point, particle, 4-coordinate group) and the terminal condition
-    host::clear_status(status, P, st);
-    const int64_t nfwd = P * (int64_t)M * (pl.ld / 4);
-    hipLaunchKernelGGL(k_lit_forward, dim3((unsigned)std::min<int64_t>((nfwd + 255) / 256, (int64_t)1 << 20)),
-                       dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, (int)pb->N, sqdt, pb->point_base, ky.k0, ky.k1, P);
-    hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, d, x0, pb->mu,
-                       pb->gvec, s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], w.Ya, status);
-    const GramSplit gs = gram_split(P, M, pl.ld);
-    const int64_t nG = P * (int64_t)M * M;
-    const unsigned sblocks = (unsigned)std::min<int64_t>((nG + 255) / 256, (int64_t)1 << 16);
-    const double gram_flops = (double)P * M * (M + 1.0) * d;
-    const double anchor_flops = (double)P * M * (2.0 / 3.0 * std::pow(M + 1.0, 3) + 6.0 * M * (double)M);
-    const int64_t ngroups = P * (int64_t)M * ((d + 3) / 4);
-    const unsigned rblocks = (unsigned)std::min<int64_t>((ngroups + 255) / 256, (int64_t)1 << 20);
-    const FSpec f = host::fspec_of(pb);
-    double* Yn = w.Ya;
-    double* Yk = w.Yb;
-    for (int k = (int)pb->N - 1; k >= k_stop; --k) {
-        hipLaunchKernelGGL(k_lit_reverse, dim3(rblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, k, sqdt,
-                           pb->point_base, ky.k0, ky.k1, P, k == 0 ? 1 : 0);
-        const long tg = host::timer_begin(st, gram_flops, FBSDE_TIMED_LITERAL_GRAM);
-        if (gs.rows && M <= 88)   // at most 256 blocks of 4 x 4: one per thread
-            hipLaunchKernelGGL(k_lit_gram_rows<1>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
-                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
-        else if (gs.rows)         // M <= 128: at most 528 blocks
-            hipLaunchKernelGGL(k_lit_gram_rows<3>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W, (int64_t)pl.ld,
-                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
-        else
-            hipLaunchKernelGGL(k_lit_gram, dim3(gs.ntiles * gs.nsplit, (unsigned)P), dim3(256), 0, st, w.W,
-                               (int64_t)pl.ld, M, pl.ld, gs.ntiles, gs.chunk, w.Gpart);
-        if (gs.nsplit > 1)
-            hipLaunchKernelGGL(k_lit_gram_sum, dim3(sblocks), dim3(256), 0, st, w.Gpart, gs.rows ? w.Rpart : nullptr,
-                               gs.nsplit, nG, P * (int64_t)M, w.G, w.rho);
-        host::timer_end(tg, st);
-        if (!gs.rows)
-            hipLaunchKernelGGL(k_lit_rowsum, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, pl.ld,
-                               w.rho);
-        const double eps2 = (pb->eps_h == 0.0 || k == 0) ? 0.0 : pb->eps_h * pb->eps_h * 2.0 * s * s * (k * dt) * d;
-        const double lam = pb->ridge_rel * s * s * ((k + 1) * dt);
-        double* zst = (k == k_stop) ? z_stats : nullptr;
-        const int it = pb->newton_iters;
-        const long ta = host::timer_begin(st, anchor_flops, FBSDE_TIMED_LITERAL_ANCHORS);
-        // lane grids: one wavefront up to M + 1 = 56, four up to 144, sixteen up to 257.  Measured at
-        // M = 100: four wavefronts per anchor beat two (2 x 8 lanes per row) by 1.4x; the kernel is bound
-        // by the issue of the per-step updates, which fewer lanes per anchor serialise.
-        if (M + 1 <= 56) rc = launch_anchor<8, 8, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 80) rc = launch_anchor<16, 16, 5>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 112) rc = launch_anchor<16, 16, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 144) rc = launch_anchor<16, 16, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else if (M + 1 <= 224) rc = launch_anchor<32, 32, 7>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        else rc = launch_anchor<32, 32, 9>(P, M, w.G, w.rho, Yn, Yk, s, dt, eps2, lam, f, it, zst, status, st);
-        host::timer_end(ta, st);
-        if (rc) return rc;
-        std::swap(Yn, Yk);
-    }
-    hipLaunchKernelGGL(k_lit_mean, dim3((unsigned)P), dim3(64), 0, st, Yn, M, u);
-    if (Y_out) (void)hipMemcpyAsync(Y_out, Yn, (size_t)P * M * 8, hipMemcpyDeviceToDevice, st);
-    return host::last_error();
+    if (lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
+    lit_carve(P, pb->M, pb->N, pl.ld, false, (char*)wsp, w);
+    return lit_run(pb, Coef{false, 0.0, 0.0}, pl, P, k_stop, x0, u, Y_out, z_stats, status, w, (hipStream_t)stream);
+}
+
+int fbsde_literal_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes) {
+    if (!bytes) return FBSDE_EINVAL;
+    host::Plan pl;
+    int rc = lit_check(pb, P, pl);
+    if (rc) return rc;
+    Coef cf;
+    if ((rc = coef_check(pb, coef, cf))) return rc;
+    LitWS w;
+    *bytes = lit_carve(P, pb->M, pb->N, pl.ld, true, nullptr, w);
+    return FBSDE_OK;
+}
+
+int fbsde_solve_literal_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, int32_t k_stop,
+                             const double* x0, double* u, double* Y_out, double* z_stats, uint32_t* status, void* wsp,
+                             size_t ws_bytes, fbsde_stream stream) {
+    host::Plan pl;
+    int rc = lit_check(pb, P, pl);
+    if (rc) return rc;
+    Coef cf;
+    if ((rc = coef_check(pb, coef, cf))) return rc;
+    if (k_stop < 0 || k_stop >= pb->N) return FBSDE_EINVAL;
+    if (P == 0) return FBSDE_OK;   // nothing is read or written; the pointers may be null
+    if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    LitWS w;
+    if (lit_carve(P, pb->M, pb->N, pl.ld, true, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
+    lit_carve(P, pb->M, pb->N, pl.ld, true, (char*)wsp, w);
+    return lit_run(pb, cf, pl, P, k_stop, x0, u, Y_out, z_stats, status, w, (hipStream_t)stream);
 }
 
 }  // extern "C"

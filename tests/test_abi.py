@@ -142,3 +142,21 @@ def test_literal_scheme_validation_on_host():
     for k_stop in (-1, 4):
         assert lib.fbsde_solve_literal(c, 1, k_stop, None, None, None, None, None, None, 0, None) == N.EINVAL
     assert lib.fbsde_solve_literal(c, 1, 0, None, None, None, None, None, None, 0, None) == N.EINVAL
+
+
+def test_literal_coef_validation_on_host():
+    lib = N.load()
+    size = ctypes.c_size_t(0)
+    pb = F.Problem(d=20, M=30, N=5, T=0.3)
+    ok = N.CCoef(N.COEF_GEOMETRIC, 0, 0.1, 0.4)
+    assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(ok), 2, ctypes.byref(size)) == N.OK
+    # every level's displacements are kept: (N + 1) P M ld doubles at least
+    assert size.value >= 6 * 2 * 30 * 32 * 8
+    for bad in (N.CCoef(0, 0, 0.1, 0.4), N.CCoef(N.COEF_GEOMETRIC, 1, 0.1, 0.4), N.CCoef(N.COEF_GEOMETRIC, 0, 0.1, 0.0),
+                N.CCoef(N.COEF_GEOMETRIC, 0, float("nan"), 0.4)):
+        assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(bad), 2,
+                                                     ctypes.byref(size)) == N.EINVAL
+    assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), None, 2, ctypes.byref(size)) == N.EINVAL
+    c = ctypes.byref(pb.c())
+    assert lib.fbsde_solve_literal_coef(c, ctypes.byref(ok), 0, 0, None, None, None, None, None, None, 0, None) == N.OK
+    assert lib.fbsde_solve_literal_coef(c, ctypes.byref(ok), 1, 5, None, None, None, None, None, None, 0, None) == N.EINVAL

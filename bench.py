@@ -374,6 +374,26 @@ def main():
         log(f"[bench] literal per-anchor d=1e4 M=100 N=100 P=64: {secl * 1e3:.1f} ms "
             f"(gram {legs['gram']['avg_ms']:.3f} ms/level, anchors {legs['anchors']['avg_ms']:.3f} ms/level)")
         del wsl, xl
+        # x-dependent coefficients: geometric family mu = mu0 x, sigma = sigma0 diag(x), the path stored per level
+        dg_, Mg, Ng, Pg = 1000, 100, 50, 64
+        pbg = F.Problem(d=dg_, M=Mg, N=Ng, T=0.5, f_kind=F.F_HJB, fp=(1.0, 0, 0, 0), g_kind=F.G_HJB_LOG,
+                        gp=(1.0, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3, instance=7)
+        xg = torch.ones((Pg, dg_), dtype=torch.float64, device=dev)
+        wsg = torch.empty(F.literal_coef_workspace_size(pbg, Pg, 0.05, 0.2), dtype=torch.uint8, device=dev)
+        F.solve_literal_geometric(pbg, xg, 0.05, 0.2, ws=wsg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps)):
+            ug, stg, _, _ = F.solve_literal_geometric(pbg, xg, 0.05, 0.2, ws=wsg)
+        torch.cuda.synchronize()
+        secg = (time.perf_counter() - t0) / max(1, args.steps)
+        literal["geometric_coefficients"] = {
+            "value": round(Pg / secg, 3), "unit": "points/s", "ms_per_step": round(secg * 1e3, 3),
+            "config": {"workload": "literal_geometric_hjb_d1000_M100_N50_P64", "mu0": 0.05, "sigma0": 0.2,
+                       "x0": "1 (replicas)", "stored_path_GB": round(wsg.numel() / 1e9, 2)},
+            "u_mean": round(float(ug.mean().item()), 6), "status_nonzero_points": int((stg != 0).sum().item())}
+        log(f"[bench] literal geometric d=1e3 M=100 N=50 P=64: {secg * 1e3:.1f} ms")
+        del wsg, xg
 
     # ---------------- shared increments: d = 10^4, 4096 points, M = 2048, N = 20 on the matrix cores
     shared = None

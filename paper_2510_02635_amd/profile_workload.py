@@ -28,8 +28,12 @@ WORKLOADS = {
                                                   fp=(2 ** 0.5 / 10000, 10000 / 2 + 0.5, 0, 0), g_kind=4,
                                                   gp=(0.3, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3, instance=6),
                                              "zeros", 64),
+    # the same scheme under the geometric coefficient family mu = 0.05 x, sigma = 0.2 diag(x), x0 = 1
+    "literal_geometric_hjb_d1000_M100_N50_P64": (dict(d=1000, M=100, N=50, T=0.5, f_kind=2, fp=(1.0, 0, 0, 0),
+                                                      g_kind=2, gp=(1.0, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3,
+                                                      instance=7), "ones", 64),
 }
-LITERAL = ("literal_burgers_d10000_M100_N100_P64",)
+LITERAL = ("literal_burgers_d10000_M100_N100_P64", "literal_geometric_hjb_d1000_M100_N50_P64")
 
 
 def main():
@@ -46,11 +50,17 @@ def main():
 
     kw, xkind, P = WORKLOADS[args.workload]
     if args.workload in LITERAL:
-        gvec = torch.full((kw["d"],), 1.0 / kw["d"], dtype=torch.float64, device="cuda")
-        pb = F.Problem(gvec=gvec, **kw)
-        x0 = torch.zeros((P, kw["d"]), dtype=torch.float64, device="cuda")
-        u, st, _, _ = F.solve_literal(pb, x0)
-        u, st, _, _ = F.solve_literal(pb, x0)
+        if "geometric" in args.workload:
+            pb = F.Problem(**kw)
+            x0 = torch.ones((P, kw["d"]), dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                u, st, _, _ = F.solve_literal_geometric(pb, x0, 0.05, 0.2)
+        else:
+            gvec = torch.full((kw["d"],), 1.0 / kw["d"], dtype=torch.float64, device="cuda")
+            pb = F.Problem(gvec=gvec, **kw)
+            x0 = torch.zeros((P, kw["d"]), dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                u, st, _, _ = F.solve_literal(pb, x0)
         torch.cuda.synchronize()
         print(f"{args.workload} fp64 (literal, 2 solves): u[0]={u[0].item():.12g} "
               f"nonzero status={int((st != 0).sum())}", flush=True)

@@ -299,10 +299,71 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 template <int RI, int RJ>
 constexpr int bmax(int a) { return (RI * a + RI - 1) / RJ; }
 template <int RI, int RJ>
+constexpr int amin(int b) {    // first row block that meets column block b
+    int a = 0;
+    while (bmax<RI, RJ>(a) < b) ++a;
+    return a;
+}
+template <int RI, int RJ>
 constexpr int slot0(int a) {   // first slot of row block a
     int e = 0;
     for (int q = 0; q < a; ++q) e += bmax<RI, RJ>(q) + 1;
     return e;
+}
+
+// One elimination step with the pivot in column block JB (a compile-time constant, so that only the
+// slots of blocks JB.. are touched: blocks left of the pivot are finished).  Writes the lanes' share of
+// pivot column jp into cb, waits at the barrier, then updates S_ij -= S_i,jp S_j,jp / S_jp,jp for
+// j > jp (in block JB only lanes right of the pivot).  Returns the pivot S_jp,jp.
+template <int RI, int RJ, int A, bool CACHE, int JB, int E>
+__device__ __forceinline__ double elim_step(double (&v)[E], double* cb, int jp, int tr, int tc) {
+    constexpr int B = bmax<RI, RJ>(A - 1) + 1;
+    const int jr = jp - RJ * JB;
+    if (tc == jr) {
+#pragma unroll
+        for (int a = amin<RI, RJ>(JB); a < A; ++a) cb[tr + RI * a] = v[slot0<RI, RJ>(a) + JB];
+    }
+    __syncthreads();
+    const double dj = cb[jp];
+    const double inv = 1.0 / dj;
+    const bool right = tc > jr;
+    if constexpr (CACHE) {
+        double ci[A], cj[B];
+#pragma unroll
+        for (int a = amin<RI, RJ>(JB); a < A; ++a) ci[a] = cb[tr + RI * a];
+#pragma unroll
+        for (int b = JB; b < B; ++b) cj[b] = cb[tc + RJ * b] * inv;
+#pragma unroll
+        for (int a = amin<RI, RJ>(JB); a < A; ++a)
+#pragma unroll
+            for (int b = JB; b <= bmax<RI, RJ>(a); ++b) {
+                double& x = v[slot0<RI, RJ>(a) + b];
+                const double y = fma(-ci[a], cj[b], x);
+                x = (b > JB || right) ? y : x;
+            }
+    } else {
+#pragma unroll
+        for (int a = amin<RI, RJ>(JB); a < A; ++a)
+#pragma unroll
+            for (int b = JB; b <= bmax<RI, RJ>(a); ++b) {
+                double& x = v[slot0<RI, RJ>(a) + b];
+                const double y = fma(-cb[tr + RI * a], cb[tc + RJ * b] * inv, x);
+                x = (b > JB || right) ? y : x;
+            }
+    }
+    return dj;
+}
+
+// Calls elim_step with the runtime column block jb as a compile-time constant (a chain of uniform tests).
+template <int RI, int RJ, int A, bool CACHE, int JB, int E>
+__device__ __forceinline__ double elim_dispatch(int jb, double (&v)[E], double* cb, int jp, int tr, int tc) {
+    constexpr int B = bmax<RI, RJ>(A - 1) + 1;
+    if constexpr (JB + 1 < B) {
+        if (jb == JB) return elim_step<RI, RJ, A, CACHE, JB>(v, cb, jp, tr, tc);
+        return elim_dispatch<RI, RJ, A, CACHE, JB + 1>(jb, v, cb, jp, tr, tc);
+    } else {
+        return elim_step<RI, RJ, A, CACHE, JB>(v, cb, jp, tr, tc);
+    }
 }
 
 // One anchor m of point p at level k.  Grid (M, P), RI x RJ threads.  The bordered (M + 1) x (M + 1)
@@ -384,40 +445,31 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     // bordered row ends as z = L^{-1} Om Y with L unit lower triangular.  Slots outside the triangle
     // (i >= n or j > i) are updated too: their values are never read, and the padded column buffer
     // keeps every read in bounds.  In the pivot's own column block only lanes right of the pivot
-    // update; blocks left of it are finished (a uniform skip).
+    // update; blocks left of it are finished and not touched (elim_step is specialised per block).
     uint32_t st = 0;
-    for (int jp = 0; jp < M; ++jp) {
-        double* cb = col[jp & 1];
-        const int jb = jp / RJ, jr = jp % RJ;
-        if (tc == jr) {
-#pragma unroll
-            for (int a = 0; a < A; ++a)
-#pragma unroll
-                for (int b = 0; b <= bmax<RI, RJ>(a); ++b)
-                    if (b == jb) cb[tr + RI * a] = v[slot0<RI, RJ>(a) + b];
+    if constexpr (RI * RJ <= 256) {
+        for (int jp = 0; jp < M; ++jp) {
+            const double dj = elim_dispatch<RI, RJ, A, CACHE, 0>(jp / RJ, v, col[jp & 1], jp, tr, tc);
+            if (!(dj > 0.0)) st |= ST_NONFINITE;
         }
-        __syncthreads();
-        const double dj = cb[jp];
-        if (!(dj > 0.0)) st |= ST_NONFINITE;
-        const double inv = 1.0 / dj;
-        const bool right = tc > jr;
-        if constexpr (CACHE) {
-            // the lane's A row and A column values of the pivot column, read once per step
-            double ci[A], cj[B];
+    } else {
+        // 1024-thread layouts: their slots nearly fill the 128-register budget, so one loop body with the
+        // pivot's block at run time (the specialised bodies would spill)
+        for (int jp = 0; jp < M; ++jp) {
+            double* cb = col[jp & 1];
+            const int jb = jp / RJ, jr = jp % RJ;
+            if (tc == jr) {
 #pragma unroll
-            for (int a = 0; a < A; ++a) ci[a] = cb[tr + RI * a];
+                for (int a = 0; a < A; ++a)
 #pragma unroll
-            for (int b = 0; b < B; ++b) cj[b] = (b >= jb) ? cb[tc + RJ * b] * inv : 0.0;
-#pragma unroll
-            for (int a = 0; a < A; ++a)
-#pragma unroll
-                for (int b = 0; b <= bmax<RI, RJ>(a); ++b) {
-                    if (b < jb) continue;   // column block already factored (uniform)
-                    double& x = v[slot0<RI, RJ>(a) + b];
-                    const double y = fma(-ci[a], cj[b], x);
-                    x = (b > jb || right) ? y : x;
-                }
-        } else {
+                    for (int b = 0; b <= bmax<RI, RJ>(a); ++b)
+                        if (b == jb) cb[tr + RI * a] = v[slot0<RI, RJ>(a) + b];
+            }
+            __syncthreads();
+            const double dj = cb[jp];
+            if (!(dj > 0.0)) st |= ST_NONFINITE;
+            const double inv = 1.0 / dj;
+            const bool right = tc > jr;
 #pragma unroll
             for (int a = 0; a < A; ++a)
 #pragma unroll

@@ -366,6 +366,29 @@ __device__ __forceinline__ double elim_dispatch(int jb, double (&v)[E], double* 
     }
 }
 
+// One back-substitution step for row jp in row block IB (compile-time, so that only that block's slots
+// are touched): the lanes holding row jp take rr_j -= u_jp,j ct_jp for j < jp.
+template <int RI, int RJ, int IB, int E>
+__device__ __forceinline__ void bsub_step(const double (&v)[E], double* rr, int jp, int tr, int tc, double cj) {
+    if (tr == jp - RI * IB) {
+#pragma unroll
+        for (int b = 0; b <= bmax<RI, RJ>(IB); ++b) {
+            const int j = tc + RJ * b;
+            if (j < jp) rr[j] -= v[slot0<RI, RJ>(IB) + b] * cj;
+        }
+    }
+}
+template <int RI, int RJ, int A, int IB, int E>
+__device__ __forceinline__ void bsub_dispatch(int ib, const double (&v)[E], double* rr, int jp, int tr, int tc,
+                                              double cj) {
+    if constexpr (IB + 1 < A) {
+        if (ib == IB) return bsub_step<RI, RJ, IB>(v, rr, jp, tr, tc, cj);
+        return bsub_dispatch<RI, RJ, A, IB + 1>(ib, v, rr, jp, tr, tc, cj);
+    } else {
+        return bsub_step<RI, RJ, IB>(v, rr, jp, tr, tc, cj);
+    }
+}
+
 // One anchor m of point p at level k.  Grid (M, P), RI x RJ threads.  The bordered (M + 1) x (M + 1)
 // system (row M holds the right-hand side) is spread block-cyclically: lane (r, c) = (tid / RJ, tid % RJ)
 // owns the entries (r + RI a, c + RJ b), b <= bmax(a), a < A.  So every index is the lane's coordinate
@@ -493,7 +516,9 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     __syncthreads();
     for (int jp = M - 1; jp >= 0; --jp) {
         const double cj = rr[jp] / dg[jp];
-        if (tr == jp % RI) {
+        if constexpr (RI * RJ <= 256) {
+            bsub_dispatch<RI, RJ, A, 0>(jp / RI, v, rr, jp, tr, tc, cj);
+        } else if (tr == jp % RI) {
             const int ib = jp / RI;
 #pragma unroll
             for (int a = 0; a < A; ++a)

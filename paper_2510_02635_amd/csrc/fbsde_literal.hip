@@ -172,41 +172,35 @@ k_lit_gram(const double* __restrict__ W, int64_t ldw, int M, int ld, int ntiles,
 }
 
 // G = W W^T per point for M <= 128: one workgroup per (coordinate chunk, point) holds the chunk of all M
-// rows in LDS, 16 coordinates at a time, so each element of W is read once; thread t owns the 4 x 4
-// output blocks q = t + 256 r (r < NB) of the lower block triangle (q = bi (bi + 1) / 2 + bj, bj <= bi).
-// Grid (nsplit, P); chunk ks writes its partial matrix to Gpart[ks][P][M][M].
-template <int NB>
+// rows in LDS, 16 coordinates at a time, so each element of W is read once.  Thread t owns the BSZ x BSZ
+// output block t = bi (bi + 1) / 2 + bj (bj <= bi) of the lower block triangle; BSZ is chosen per M so
+// that there are at most 256 blocks.  The row sums rho are fused in.  Grid (nsplit, P); chunk ks writes
+// its partial matrix to Gpart[ks][P][M][M] and its row sums to Rpart[ks][P][M].
+template <int BSZ>
 __global__ void __launch_bounds__(256)
 k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int chunk, double* __restrict__ Gpart,
                 double* __restrict__ Rpart) {
-    __shared__ double Ws[128][17];
+    __shared__ double Ws[136][17];
     const int ks = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-    const int nb4 = (M + 3) / 4;
-    const int nblk = nb4 * (nb4 + 1) / 2;
-    int bi[NB], bj[NB];
-#pragma unroll
-    for (int r = 0; r < NB; ++r) {
-        const int q = tid + 256 * r;
-        int i = 0;
-        if (q < nblk) {
-            i = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
-            while (i * (i + 1) / 2 > q) --i;
-            while ((i + 1) * (i + 2) / 2 <= q) ++i;
-        }
-        bi[r] = (q < nblk) ? i : 0;
-        bj[r] = (q < nblk) ? q - i * (i + 1) / 2 : 0;
+    const int nbk = (M + BSZ - 1) / BSZ;
+    const int nblk = nbk * (nbk + 1) / 2;
+    const bool mine = tid < nblk;
+    int bi = 0;
+    if (mine) {
+        bi = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+        while (bi * (bi + 1) / 2 > tid) --bi;
+        while ((bi + 1) * (bi + 2) / 2 <= tid) ++bi;
     }
-    double acc[NB][4][4];
+    const int bj = mine ? tid - bi * (bi + 1) / 2 : 0;
+    double acc[BSZ][BSZ];
 #pragma unroll
-    for (int r = 0; r < NB; ++r)
+    for (int x = 0; x < BSZ; ++x)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[r][x][y] = 0.0;
+        for (int y = 0; y < BSZ; ++y) acc[x][y] = 0.0;
     const double* Wp = W + (int64_t)p * M * ldw;
     const int kb = ks * chunk, ke = min(ld, kb + chunk);
-    const int rows = 4 * nb4;
-    double rsum = 0.0;   // thread tid < M: its row's sum over the chunk (the row sums rho, fused)
+    const int rows = BSZ * nbk;
+    double rsum = 0.0;   // thread tid < M: its row's sum over the chunk
     for (int k0 = kb; k0 < ke; k0 += 16) {
         for (int e = tid; e < rows * 16; e += 256) {
             const int row = e / 16, kk = e % 16;
@@ -217,38 +211,34 @@ k_lit_gram_rows(const double* __restrict__ W, int64_t ldw, int M, int ld, int ch
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) rsum += Ws[tid][kk];
         }
-#pragma unroll
-        for (int r = 0; r < NB; ++r) {
-            if (tid + 256 * r >= nblk) break;
+        if (mine) {
 #pragma unroll 4
             for (int kk = 0; kk < 16; ++kk) {
-                double a[4], b[4];
+                double a[BSZ], b[BSZ];
 #pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[x] = Ws[4 * bi[r] + x][kk];
-                    b[x] = Ws[4 * bj[r] + x][kk];
+                for (int x = 0; x < BSZ; ++x) {
+                    a[x] = Ws[BSZ * bi + x][kk];
+                    b[x] = Ws[BSZ * bj + x][kk];
                 }
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+                for (int x = 0; x < BSZ; ++x)
 #pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[r][x][y] += a[x] * b[y];
+                    for (int y = 0; y < BSZ; ++y) acc[x][y] += a[x] * b[y];
             }
         }
         __syncthreads();
     }
     if (tid < M) Rpart[((int64_t)ks * gridDim.y + p) * M + tid] = rsum;
     double* Gp = Gpart + ((int64_t)ks * gridDim.y + p) * M * M;
+    if (mine) {
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-        if (tid + 256 * r >= nblk) break;
+        for (int x = 0; x < BSZ; ++x)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                const int i = 4 * bi[r] + x, j = 4 * bj[r] + y;
+            for (int y = 0; y < BSZ; ++y) {
+                const int i = BSZ * bi + x, j = BSZ * bj + y;
                 if (i < M && j < M) {
-                    Gp[(int64_t)i * M + j] = acc[r][x][y];
-                    Gp[(int64_t)j * M + i] = acc[r][x][y];
+                    Gp[(int64_t)i * M + j] = acc[x][y];
+                    Gp[(int64_t)j * M + i] = acc[x][y];
                 }
             }
     }
@@ -833,11 +823,15 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
             hipLaunchKernelGGL(k_lit_reverse, dim3(rblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, k, sqdt,
                                pb->point_base, ky.k0, ky.k1, P, k == 0 ? 1 : 0);
         const long tg = host::timer_begin(st, gram_flops, FBSDE_TIMED_LITERAL_GRAM);
-        if (gs.rows && M <= 88)   // at most 256 blocks of 4 x 4: one per thread
-            hipLaunchKernelGGL(k_lit_gram_rows<1>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
+        // row-resident Gram: block size per M so that at most 256 blocks cover the lower triangle
+        if (gs.rows && M <= 88)
+            hipLaunchKernelGGL(k_lit_gram_rows<4>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
                                M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
-        else if (gs.rows)         // M <= 128: at most 528 blocks
-            hipLaunchKernelGGL(k_lit_gram_rows<3>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
+        else if (gs.rows && M <= 110)
+            hipLaunchKernelGGL(k_lit_gram_rows<5>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
+                               M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
+        else if (gs.rows)
+            hipLaunchKernelGGL(k_lit_gram_rows<6>, dim3(gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld,
                                M, pl.ld, gs.chunk, w.Gpart, w.Rpart);
         else
             hipLaunchKernelGGL(k_lit_gram, dim3(gs.ntiles * gs.nsplit, (unsigned)P), dim3(256), 0, st, Xk,

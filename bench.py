@@ -373,7 +373,23 @@ def main():
                    "paper_cpu_s_per_point_context": 1040.15}
         log(f"[bench] literal per-anchor d=1e4 M=100 N=100 P=64: {secl * 1e3:.1f} ms "
             f"(gram {legs['gram']['avg_ms']:.3f} ms/level, anchors {legs['anchors']['avg_ms']:.3f} ms/level)")
-        del wsl, xl
+        del wsl
+        # the paper's second particle count at this setting, M = 200 (16-wavefront anchor layout)
+        pb2 = F.Problem(d=dl, M=200, N=Nl, T=Tl, s=sl, f_kind=F.F_BURGERS, fp=(sl / dl, dl / (sl * sl) + 0.5, 0, 0),
+                        g_kind=F.G_LOGISTIC, gp=(Tl, 0, 0, 0), gvec=gvl, eps_h=1.0, ridge_rel=1e-3, instance=6)
+        ws2 = torch.empty(F.literal_workspace_size(pb2, Pl), dtype=torch.uint8, device=dev)
+        F.solve_literal(pb2, xl, ws=ws2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u2, st2, _, _ = F.solve_literal(pb2, xl, ws=ws2)
+        torch.cuda.synchronize()
+        sec2 = time.perf_counter() - t0
+        literal["M200"] = {"value": round(Pl / sec2, 3), "unit": "points/s", "ms_per_step": round(sec2 * 1e3, 3),
+                           "u_mean": round(float(u2.mean().item()), 6),
+                           "status_nonzero_points": int((st2 != 0).sum().item()),
+                           "paper_cpu_s_per_point_context": 2189.28}
+        log(f"[bench] literal per-anchor d=1e4 M=200 N=100 P=64: {sec2 * 1e3:.1f} ms")
+        del ws2, xl
         # x-dependent coefficients: geometric family mu = mu0 x, sigma = sigma0 diag(x), the path stored per level
         dg_, Mg, Ng, Pg = 1000, 100, 50, 64
         pbg = F.Problem(d=dg_, M=Mg, N=Ng, T=0.5, f_kind=F.F_HJB, fp=(1.0, 0, 0, 0), g_kind=F.G_HJB_LOG,

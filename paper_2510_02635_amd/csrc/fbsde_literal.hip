@@ -460,13 +460,13 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     // keeps every read in bounds.  In the pivot's own column block only lanes right of the pivot
     // update; blocks left of it are finished and not touched (elim_step is specialised per block).
     uint32_t st = 0;
-    if constexpr (RI * RJ <= 256) {
+    if constexpr (RI * RJ <= 512) {
         for (int jp = 0; jp < M; ++jp) {
             const double dj = elim_dispatch<RI, RJ, A, CACHE, 0>(jp / RJ, v, col[jp & 1], jp, tr, tc);
             if (!(dj > 0.0)) st |= ST_NONFINITE;
         }
     } else {
-        // 1024-thread layouts: their slots nearly fill the 128-register budget, so one loop body with the
+        // 1024-thread layout: its slots nearly fill the 128-register budget, so one loop body with the
         // pivot's block at run time (the specialised bodies would spill)
         for (int jp = 0; jp < M; ++jp) {
             double* cb = col[jp & 1];
@@ -506,7 +506,7 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     __syncthreads();
     for (int jp = M - 1; jp >= 0; --jp) {
         const double cj = rr[jp] / dg[jp];
-        if constexpr (RI * RJ <= 256) {
+        if constexpr (RI * RJ <= 512) {
             bsub_dispatch<RI, RJ, A, 0>(jp / RI, v, rr, jp, tr, tc, cj);
         } else if (tr == jp % RI) {
             const int ib = jp / RI;
@@ -763,16 +763,16 @@ int launch_anchor(int64_t P, int M, const double* G, const double* rho, const do
 int anchors(int64_t P, int M, const double* G, const double* rho, const double* Yn, double* Y, double s, double dt,
             double eps2, double lam, FSpec f, int it, double* zst, uint32_t* status, hipStream_t st,
             const double* eps2_pp, double* c_out) {
-    // lane grids: one wavefront up to M + 1 = 56, four up to 144, sixteen up to 257.  Measured at
-    // M = 100: four wavefronts per anchor beat two (2 x 8 lanes per row) by 1.4x; the kernel is bound
-    // by the issue of the per-step updates, which fewer lanes per anchor serialise.
+    // lane grids: one wavefront up to M + 1 = 56, four up to 144, eight (32 x 16 lanes) up to 224,
+    // sixteen up to 257.  Measured at M = 100: four wavefronts per anchor beat two (16 x 8 lanes) by 1.4x;
+    // at M = 200 the 32 x 16 grid with specialised steps beat the 32 x 32 one by 1.9x.
 #define LIT_ANCHOR(RI, RJ, A) \
     launch_anchor<RI, RJ, A>(P, M, G, rho, Yn, Y, s, dt, eps2, lam, f, it, zst, status, st, eps2_pp, c_out)
     if (M + 1 <= 56) return LIT_ANCHOR(8, 8, 7);
     if (M + 1 <= 80) return LIT_ANCHOR(16, 16, 5);
     if (M + 1 <= 112) return LIT_ANCHOR(16, 16, 7);
     if (M + 1 <= 144) return LIT_ANCHOR(16, 16, 9);
-    if (M + 1 <= 224) return LIT_ANCHOR(32, 32, 7);
+    if (M + 1 <= 224) return LIT_ANCHOR(32, 16, 7);
     return LIT_ANCHOR(32, 32, 9);
 #undef LIT_ANCHOR
 }

@@ -5,7 +5,8 @@ at level k_stop element by element. The tolerance is FP64's 1e-10 relative; |Z|^
 largest value, since it is a quadratic form of an ill-conditioned ridge solve (condition number up to
 about 2e3 d). The cases cover:
 * each register layout of the anchor factorisation (one wavefront for M + 1 <= 56; four wavefronts
-  for M + 1 <= 80, 112, 144; sixteen for M + 1 <= 224, 257) and the boundaries between them;
+  for M + 1 <= 80, 112, 144; eight for M + 1 <= 224; sixteen for M + 1 <= 257) and the boundaries
+  between them;
 * every f family, including z-dependent ones (HJB, Burgers-type), and the affine and logistic
   terminal conditions;
 * uniform weights (h = 0) and the first, a middle and the last backward level;

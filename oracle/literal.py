@@ -148,17 +148,24 @@ def cloud_bandwidth(pb, Xk, k):
     return pb.eps_h ** 2 * 2.0 * float(np.einsum("ij,ij->", C, C)) / Xk.shape[0]
 
 
-def anchor_fit_eps(Xk, Y_next, m, eps2, lam):
+def anchor_fit_eps(Xk, Y_next, m, eps2, lam, form=None):
     """Minimiser of J_lambda about anchor m (intercept penalised, as in anchor_fit) with bandwidth eps2
-    (0: uniform weights), by the (d+1) normal equations.  Returns (alpha [d+1], w)."""
+    (0: uniform weights): the (d+1) normal equations ("primal") or the same minimiser through the M x M
+    system ("dual", push-through identity, as in anchor_fit).  Default: the smaller.  Returns (alpha, w)."""
     M, d = Xk.shape
     D = Xk - Xk[m][None, :]
     n2 = np.einsum("ij,ij->i", D, D)
     e = np.ones(M) if eps2 == 0.0 else np.exp(-(n2 - n2.min()) / eps2)
     w = e / e.sum()
     A = np.hstack([np.ones((M, 1)), D])
-    H = A.T @ (w[:, None] * A) + lam * np.eye(d + 1)
-    return np.linalg.solve(H, A.T @ (w * Y_next)), w
+    if form is None:
+        form = "primal" if M > d + 1 else "dual"
+    if form == "primal":
+        H = A.T @ (w[:, None] * A) + lam * np.eye(d + 1)
+        return np.linalg.solve(H, A.T @ (w * Y_next)), w
+    sw = np.sqrt(w)
+    B = sw[:, None] * A
+    return B.T @ np.linalg.solve(B @ B.T + lam * np.eye(M), sw * Y_next), w
 
 
 def solve_point_geometric(pb, x0, p, mu0, sigma0, k_stop=0, tape=False):

@@ -125,3 +125,26 @@ def test_literal_launch_timer_records_gram_and_anchor_launches():
     assert np.all(work[kinds == F.TIMED_LITERAL_GRAM] == P * M * (M + 1.0) * d)
     ref = P * M * (2.0 / 3.0 * (M + 1.0) ** 3 + 6.0 * M * M)
     assert np.allclose(work[kinds == F.TIMED_LITERAL_ANCHORS], ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("M,N", [(100, 6), (200, 3)])
+def test_literal_full_size_burgers_d10000(M, N):
+    # the benchmarked shape (d = 10^4, M = 100 or 200, dt = 0.003) in the bench's launch configuration
+    # (64 points), fewer levels; sampled points against the oracle one by one
+    d, P = 10000, 64
+    s = float(np.sqrt(2.0))
+    kw = dict(d=d, M=M, N=N, T=0.003 * N, s=s, f_kind=OS.F_BURGERS, fp=(s / d, d / 2 + 0.5, 0.0, 0.0),
+              g_kind=OS.G_LOGISTIC, gp=(0.3, 0.0, 0.0, 0.0), gvec=np.full(d, 1.0 / d), ridge_rel=1e-3, seed=0,
+              instance=6)
+    gkw = dict(kw, gvec=torch.tensor(kw["gvec"], device="cuda"))
+    print(f"[literal full size] d={d} M={M} N={N} P={P}", flush=True)
+    u, st, Y, zs = F.solve_literal(F.Problem(**gkw), torch.zeros((P, d), dtype=torch.float64, device="cuda"),
+                                   want_Y=True)
+    torch.cuda.synchronize()
+    u, st, Y = u.cpu().numpy(), st.cpu().numpy(), Y.cpu().numpy()
+    assert np.all(st == 0)
+    opb = OS.Problem(**kw)
+    for p in ((0, P - 1) if M == 100 else (P - 1,)):
+        ref = OL.solve_point(opb, np.zeros(d), p)
+        assert abs(u[p] - ref["u"]) <= 1e-10 * abs(ref["u"]), (p, u[p], ref["u"])
+        assert np.max(np.abs(Y[p] - ref["Y"])) <= 1e-10 * np.max(np.abs(ref["Y"]))

@@ -88,3 +88,23 @@ def test_geometric_errors():
     u, st, _, _ = F.solve_literal_geometric(F.Problem(d=8, M=16, N=3, T=0.3),
                                             torch.empty((0, 8), dtype=torch.float64, device="cuda"), 0.1, 0.3)
     assert u.numel() == 0
+
+
+def test_geometric_full_size_d1000_M100():
+    # the benchmarked shape (d = 1000, M = 100, dt = 0.01, mu0 = 0.05, sigma0 = 0.2) in the bench's launch
+    # configuration (64 points), fewer levels; sampled points against the oracle one by one
+    d, M, N, P = 1000, 100, 5, 64
+    kw = dict(d=d, M=M, N=N, T=0.01 * N, f_kind=OS.F_HJB, fp=(1.0, 0, 0, 0), g_kind=OS.G_HJB_LOG, gp=(1.0, 0, 0, 0),
+              ridge_rel=1e-3, seed=0, instance=7)
+    print(f"[literal-geometric full size] d={d} M={M} N={N} P={P}", flush=True)
+    x0 = np.ones((P, d))
+    u, st, Y, zs = F.solve_literal_geometric(F.Problem(**kw), torch.tensor(x0, device="cuda"), 0.05, 0.2,
+                                             want_Y=True, want_zstats=True)
+    torch.cuda.synchronize()
+    u, st, Y = u.cpu().numpy(), st.cpu().numpy(), Y.cpu().numpy()
+    assert np.all(st == 0)
+    opb = OS.Problem(**kw)
+    for p in (0, 31, P - 1):
+        ref = OL.solve_point_geometric(opb, x0[p], p, 0.05, 0.2)
+        assert abs(u[p] - ref["u"]) <= 1e-10 * abs(ref["u"]), (p, u[p], ref["u"])
+        assert np.max(np.abs(Y[p] - ref["Y"])) <= 1e-10 * np.max(np.abs(ref["Y"]))

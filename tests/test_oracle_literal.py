@@ -168,3 +168,13 @@ def test_geometric_first_level_hjb_closed_form():
         Z = s0 * Xk[m] * r.coef_[1:]
         assert out["zz"][k][m] == pytest.approx(Z @ Z, rel=1e-8)
         assert out["Y"][m] == pytest.approx(YN.mean() - dt * 0.6 * (Z @ Z), rel=1e-10, abs=1e-13)
+
+
+def test_geometric_fit_primal_equals_dual():
+    rng = np.random.default_rng(12)
+    for M, d in ((9, 4), (6, 15)):
+        X = 1.0 + 0.2 * rng.normal(size=(M, d))
+        Y = rng.normal(size=M)
+        a1, _ = L.anchor_fit_eps(X, Y, 2, 0.7, 3e-3, "primal")
+        a2, _ = L.anchor_fit_eps(X, Y, 2, 0.7, 3e-3, "dual")
+        assert np.max(np.abs(a1 - a2)) <= 1e-9 * np.max(np.abs(a1))

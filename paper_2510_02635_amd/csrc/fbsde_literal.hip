@@ -754,7 +754,8 @@ int launch_anchor(int64_t P, int M, const double* G, const double* rho, const do
     constexpr bool CACHE = !(RI * RJ == 1024 && A == 9);
     // waves per SIMD asked of the register allocator: four for the 16 x 16 grid with 7 row blocks (the
     // paper's M = 100), which its specialised steps otherwise hold to three
-    constexpr int WPE = (RI == 16 && RJ == 16 && A == 7) ? 4 : 1;
+    constexpr int WPE = (RI == 16 && RJ == 16 && A == 7) ? 4 : (RI == 16 && RJ == 16 && A == 9) ? 3
+                      : (RI == 8 && RJ == 8) ? 4 : 1;
     hipLaunchKernelGGL((k_lit_anchor<RI, RJ, A, CACHE, WPE>), dim3(M, (unsigned)P), dim3(RI * RJ), 0, st, G, M, rho, Yn,
                        Y, s, dt, eps2, eps2_pp, lam, f, iters, zst, c_out, status);
     return FBSDE_OK;

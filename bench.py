@@ -384,6 +384,20 @@ def main():
         u2, st2, _, _ = F.solve_literal(pb2, xl, ws=ws2)
         torch.cuda.synchronize()
         sec2 = time.perf_counter() - t0
+        if not args.no_cpu_baseline:
+            # the oracle on a bounded sample: one point, 6 of the 100 levels (same d, M, dt), scaled by 100 / 6
+            from oracle import literal as OL
+            from oracle import scheme as OS
+            ocw = dict(d=dl, M=Ml, N=6, T=0.003 * 6, s=sl, f_kind=OS.F_BURGERS, fp=(sl / dl, dl / (sl * sl) + 0.5, 0, 0),
+                       g_kind=OS.G_LOGISTIC, gp=(Tl, 0, 0, 0), gvec=np.full(dl, 1.0 / dl), ridge_rel=1e-3, eps_h=1.0,
+                       instance=6)
+            t0 = time.perf_counter()
+            OL.solve_point(OS.Problem(**ocw), np.zeros(dl), 0)
+            sec_o = (time.perf_counter() - t0) * Nl / 6
+            literal["cpu_oracle"] = {"value": round(1.0 / sec_o, 5), "unit": "points/s", "kind": "oracle",
+                                     "cores": int(threads),
+                                     "sample": "1 point, 6 of the 100 levels (same d, M, dt), time scaled by 100/6"}
+            log(f"[bench] literal oracle sample: {sec_o:.1f} s per point (scaled)")
         literal["M200"] = {"value": round(Pl / sec2, 3), "unit": "points/s", "ms_per_step": round(sec2 * 1e3, 3),
                            "u_mean": round(float(u2.mean().item()), 6),
                            "status_nonzero_points": int((st2 != 0).sum().item()),

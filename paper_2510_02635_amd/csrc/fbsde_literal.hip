@@ -524,7 +524,7 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     __syncthreads();
     for (int j = tid; j < M; j += NT) rr[j] *= om[j];   // c = Om ct
     __syncthreads();
-    if (c_out) {   // x-dependent coefficients: Z needs alpha_x itself, formed by k_geo_zstats
+    if (c_out) {   // x-dependent coefficients: Z needs alpha_x itself, formed by k_geo_alpha_z
         for (int j = tid; j < M; j += NT) c_out[((int64_t)p * M + m) * M + j] = rr[j];
         if (tid == 0 && st) atomicOr(&status[p], st);
         return;
@@ -616,44 +616,73 @@ k_geo_bandwidth(const double* __restrict__ G, int M, double h2, double* __restri
     if (threadIdx.x == 0) eps2[p] = fmax(0.0, h2 * 2.0 * (tr / M - tot / ((double)M * M)));
 }
 
-// One anchor m of point p: alpha_x = sum_j c_j (V_j - V_m) from the dual solution c of k_lit_anchor,
-// Z = sigma0 (x0 + V_m) alpha_x componentwise, |Z|^2 and sum_i Z_i, then Newton (eq. NRiter) from the
-// plain mean.  Grid (M, P), 256 threads over the coordinates.
+// One level's slopes and Z of every anchor of the geometric family, from the dual solutions c of
+// k_lit_anchor (c_out mode): alpha_x = sum_j c_j (V_j - V_m), the [M x M] . [M x d] product per point.
+// One workgroup per (32-coordinate slice, point) holds the slice of all M displacements in LDS and serves
+// every anchor from it.  Thread (g, i) = (tid / 32, tid % 32) takes
+// coordinate i of the slice for the anchors m = g, g + 8, ...: alpha_i = sum_j c_mj V_ji - (sum_j c_mj) V_mi,
+// Z_i = sigma0 (x0_i + V_mi) alpha_i.  The slice's sums of Z_i^2 and Z_i per anchor go to
+// part[(p M + m) nsl + slice][2] (reduced over the 32 lanes of a half wave).  Grid (nsl, P).
 __global__ void __launch_bounds__(256)
-k_geo_zstats(const double* __restrict__ Vk, int64_t ldw, int M, int d, const double* __restrict__ x0,
-             const double* __restrict__ C, const double* __restrict__ Ynext, double* __restrict__ Ynew, double s0,
-             double dt, FSpec f, int newton_iters, double* __restrict__ zstats, uint32_t* __restrict__ status) {
-    __shared__ double cv[LMAX], red[4], sc[2];
-    const int m = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-    for (int j = tid; j < M; j += 256) cv[j] = C[((int64_t)p * M + m) * M + j];
-    __syncthreads();
-    if (tid < 64) {
-        double cs = 0.0, ys = 0.0;
-        for (int j = tid; j < M; j += 64) {
-            cs += cv[j];
-            ys += Ynext[(int64_t)p * M + j];
-        }
-        cs = wave_sum(cs);
-        ys = wave_sum(ys);
-        if (tid == 0) { sc[0] = cs; sc[1] = ys / (double)M; }
-    }
-    __syncthreads();
+k_geo_alpha_z(const double* __restrict__ Vk, int64_t ldw, int M, int d, const double* __restrict__ x0,
+              const double* __restrict__ C, double s0, int nsl, double* __restrict__ part) {
+    extern __shared__ double Vsl[];   // [M][33]
+    const int sl = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+    const int i = tid & 31, g = tid >> 5;
+    const int c0 = 32 * sl;
     const double* Vp = Vk + (int64_t)p * M * ldw;
-    const double* vm = Vp + (int64_t)m * ldw;
-    double zz = 0.0, zs = 0.0;
-    for (int i = tid; i < d; i += 256) {
-        double a = -sc[0] * vm[i];
-        for (int j = 0; j < M; ++j) a += cv[j] * Vp[(int64_t)j * ldw + i];
-        const double z = s0 * (x0[(int64_t)p * d + i] + vm[i]) * a;
-        zz += z * z;
-        zs += z;
+    for (int e = tid; e < M * 32; e += 256) {
+        const int j = e / 32, ii = e % 32;
+        Vsl[j * 33 + ii] = (c0 + ii < d) ? Vp[(int64_t)j * ldw + c0 + ii] : 0.0;
     }
-    zz = block_sum<256>(zz, red);
-    zs = block_sum<256>(zs, red);
-    if (tid == 0) {
+    __syncthreads();
+    const bool in = c0 + i < d;
+    const double xi = in ? x0[(int64_t)p * d + c0 + i] : 0.0;
+    for (int m = g; m < M; m += 8) {
+        const double* cm = C + ((int64_t)p * M + m) * M;
+        double a = 0.0, cs = 0.0;
+        for (int j = 0; j < M; ++j) {
+            const double c = cm[j];
+            a += c * Vsl[j * 33 + i];
+            cs += c;
+        }
+        const double vm = Vsl[m * 33 + i];
+        a -= cs * vm;
+        const double z = in ? s0 * (xi + vm) * a : 0.0;
+        double zz = z * z, zs = z;
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {   // within the 32 lanes of this anchor group
+            zz += __shfl_xor(zz, off, 64);
+            zs += __shfl_xor(zs, off, 64);
+        }
+        if (i == 0) {
+            double* q = part + (((int64_t)p * M + m) * nsl + sl) * 2;
+            q[0] = zz;
+            q[1] = zs;
+        }
+    }
+}
+
+// Sums the slices' partials of one anchor in slice order, then Newton (eq. NRiter) from the plain mean.
+// Grid (M, P), one wave.
+__global__ void __launch_bounds__(64)
+k_geo_newton(const double* __restrict__ part, int nsl, int M, const double* __restrict__ Ynext,
+             double* __restrict__ Ynew, double dt, FSpec f, int newton_iters, double* __restrict__ zstats,
+             uint32_t* __restrict__ status) {
+    const int m = blockIdx.x, p = blockIdx.y, lane = threadIdx.x;
+    double ys = 0.0;
+    for (int j = lane; j < M; j += 64) ys += Ynext[(int64_t)p * M + j];
+    ys = wave_sum(ys);
+    if (lane == 0) {
+        const double* q = part + ((int64_t)p * M + m) * nsl * 2;
+        double zz = 0.0, zs = 0.0;
+        for (int sl = 0; sl < nsl; ++sl) {
+            zz += q[2 * sl];
+            zs += q[2 * sl + 1];
+        }
         uint32_t st = 0;
         double Fp;
-        const double y = newton_y(f, sc[1], zz, zs, dt, newton_iters, Fp, st);
+        const double y = newton_y(f, ys / (double)M, zz, zs, dt, newton_iters, Fp, st);
         Ynew[(int64_t)p * M + m] = y;
         if (zstats) {
             zstats[((int64_t)p * M + m) * 2 + 0] = zz;
@@ -673,7 +702,7 @@ __global__ void __launch_bounds__(64) k_lit_mean(const double* __restrict__ Y, i
 }
 
 struct LitWS {
-    double *W, *Ya, *Yb, *G, *rho, *Gpart, *Rpart, *C, *eps2;
+    double *W, *Ya, *Yb, *G, *rho, *Gpart, *Rpart, *C, *eps2, *Zpart;
 };
 
 // Coefficient family of a literal solve: sigma = s I with constant drift (geo = false), or the
@@ -723,6 +752,7 @@ size_t lit_carve(int64_t P, int64_t M, int64_t N, int64_t ld, bool geo, char* ba
     w.Rpart = !gs.rows ? nullptr : (gs.nsplit > 1) ? take((size_t)gs.nsplit * P * M * 8) : w.rho;
     w.C = geo ? take((size_t)P * M * M * 8) : nullptr;
     w.eps2 = geo ? take((size_t)P * 8) : nullptr;
+    w.Zpart = geo ? take((size_t)P * M * ((ld + 31) / 32) * 2 * 8) : nullptr;   // per 32-coordinate slice
     return off;
 }
 
@@ -857,9 +887,18 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
                      cf.geo ? w.eps2 : nullptr, cf.geo ? w.C : nullptr);
         host::timer_end(ta, st);
         if (rc) return rc;
-        if (cf.geo)
-            hipLaunchKernelGGL(k_geo_zstats, dim3(M, (unsigned)P), dim3(256), 0, st, Xk, (int64_t)pl.ld, M, d, x0, w.C,
-                               Yn, Yk, cf.s0, dt, f, pb->newton_iters, zst, status);
+        if (cf.geo) {
+            const int nsl = (d + 31) / 32;
+            const size_t lds = (size_t)M * 33 * 8;
+            if (lds > 65536 &&
+                hipFuncSetAttribute((const void*)k_geo_alpha_z, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+                    hipSuccess)
+                return FBSDE_EHIP;
+            hipLaunchKernelGGL(k_geo_alpha_z, dim3(nsl, (unsigned)P), dim3(256), lds, st, Xk,
+                               (int64_t)pl.ld, M, d, x0, w.C, cf.s0, nsl, w.Zpart);
+            hipLaunchKernelGGL(k_geo_newton, dim3(M, (unsigned)P), dim3(64), 0, st, w.Zpart, nsl, M, Yn, Yk, dt, f,
+                               pb->newton_iters, zst, status);
+        }
         std::swap(Yn, Yk);
     }
     hipLaunchKernelGGL(k_lit_mean, dim3((unsigned)P), dim3(64), 0, st, Yn, M, u);

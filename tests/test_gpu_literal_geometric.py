@@ -6,7 +6,7 @@ Every case compares u, every particle's Y and (|Z|^2, sum Z) at level k_stop ele
 slope is small beside the response, and its error is about eps kappa |Y| with the ridge solve's condition
 number kappa (about 1e6 at d = 600), i.e. 1e-10 |Y|. Z = sigma(X^m)^T alpha_x needs the explicit slope. The
 cases cover: the first, a middle and the last level; HJB, Burgers-type with logistic g, and Allen-Cahn at
-M = 100; uniform weights at d = 1; M = 150 (the tiled Gram path); d = 600 (M << d).
+M = 100; uniform weights at d = 1; M = 150 (the tiled Gram path); M = 256; d = 600 (M << d).
 """
 import numpy as np
 import pytest
@@ -108,3 +108,8 @@ def test_geometric_full_size_d1000_M100():
         ref = OL.solve_point_geometric(opb, x0[p], p, 0.05, 0.2)
         assert abs(u[p] - ref["u"]) <= 1e-10 * abs(ref["u"]), (p, u[p], ref["u"])
         assert np.max(np.abs(Y[p] - ref["Y"])) <= 1e-10 * np.max(np.abs(ref["Y"]))
+
+
+def test_geometric_largest_M():
+    # M = 256: the slice of all displacements needs more than 64 KB of LDS (raised per launch)
+    _run(dict(d=40, M=256, N=2, T=0.4, ridge_rel=1e-2, seed=10, **HJB), P=1, mu0=0.1, s0=0.3, k_stop=1)

@@ -118,17 +118,18 @@ def solve(pb, x0s, k_stop=0, points=None, form=None):
 
 
 # ---------------------------------------------------------------- x-dependent coefficients
-# The same printed scheme with a coefficient family that depends on x (the paper's problem class of Sec.
-# 2.1 allows mu(t, x) and sigma(t, x)): the geometric family mu(x) = mu0 x, sigma(x) = sigma0 diag(x).
-# Readings for this family:
+# The same printed scheme with coefficients that depend on x (the paper's problem class of Sec. 2.1 allows
+# mu(t, x) and sigma(t, x)): the affine diagonal family mu(x) = mu0 x + mu1, sigma(x) = diag(sigma0 x + sigma1),
+# componentwise.  mu1 = sigma1 = 0 is the geometric family (Black-Scholes-type volatility); sigma0 = 0 with
+# mu0 < 0 is an Ornstein-Uhlenbeck drift with additive noise.  Readings for this family:
 # * Particles follow the Euler-Maruyama step of eq. Xk with the same normals as above:
-#   X_{k+1} = X_k + mu0 X_k dt + sigma0 X_k * sqrt(dt) xi_k (componentwise), X_0 = x0.
+#   X_{k+1} = X_k + (mu0 X_k + mu1) dt + (sigma0 X_k + sigma1) * sqrt(dt) xi_k (componentwise), X_0 = x0.
 # * Bandwidth: no closed form of E|X^j_k - X^m_k|^2 is used; eps_k^2 = h^2 2 (1/M) sum_j |X^j_k - Xbar_k|^2,
 #   the cloud's own mean squared pairwise distance (uniform weights at k = 0, where it is zero).
-# * Ridge: lambda_k = ridge_rel sigma0^2 t_{k+1}.
-# * Z^m_k = sigma(X^m_k)^T alpha_x = sigma0 X^m_k * alpha_x (componentwise).
-def geometric_path(pb, x0, p, mu0, sigma0):
-    """X[k, j, :] for k = 0..N under the geometric family (Euler-Maruyama, eq. Xk)."""
+# * Ridge: lambda_k = ridge_rel (sigma0^2 + sigma1^2) t_{k+1}.
+# * Z^m_k = sigma(X^m_k)^T alpha_x = (sigma0 X^m_k + sigma1) * alpha_x (componentwise).
+def geometric_path(pb, x0, p, mu0, sigma0, mu1=0.0, sigma1=0.0):
+    """X[k, j, :] for k = 0..N under the affine diagonal family (Euler-Maruyama, eq. Xk)."""
     from . import philox
     dt = pb.T / pb.N
     X = np.empty((pb.N + 1, pb.M, pb.d))
@@ -136,7 +137,7 @@ def geometric_path(pb, x0, p, mu0, sigma0):
     q = S.stream_of(pb, p)
     for k in range(pb.N):
         xi = philox.normals(pb.seed, pb.instance, q, k, pb.M, pb.d)
-        X[k + 1] = X[k] + mu0 * X[k] * dt + sigma0 * X[k] * (np.sqrt(dt) * xi)
+        X[k + 1] = X[k] + (mu0 * X[k] + mu1) * dt + (sigma0 * X[k] + sigma1) * (np.sqrt(dt) * xi)
     return X
 
 
@@ -168,10 +169,11 @@ def anchor_fit_eps(Xk, Y_next, m, eps2, lam, form=None):
     return B.T @ np.linalg.solve(B @ B.T + lam * np.eye(M), sw * Y_next), w
 
 
-def solve_point_geometric(pb, x0, p, mu0, sigma0, k_stop=0, tape=False):
-    """Algorithm 1 as printed under the geometric family, levels N-1 .. k_stop (pb.s and pb.mu unused).
-    Returns dict(u = mean_m Y^m_{k_stop}, Y, status) and, with tape, zz[k], zs[k] per particle."""
-    X = geometric_path(pb, x0, p, mu0, sigma0)
+def solve_point_geometric(pb, x0, p, mu0, sigma0, k_stop=0, tape=False, mu1=0.0, sigma1=0.0):
+    """Algorithm 1 as printed under the affine diagonal family (geometric for mu1 = sigma1 = 0), levels
+    N-1 .. k_stop (pb.s and pb.mu unused).  Returns dict(u = mean_m Y^m_{k_stop}, Y, status) and, with
+    tape, zz[k], zs[k] per particle."""
+    X = geometric_path(pb, x0, p, mu0, sigma0, mu1, sigma1)
     Y, _, _ = S.g_eval(pb, X[pb.N])
     dt = pb.T / pb.N
     status = 0
@@ -180,11 +182,11 @@ def solve_point_geometric(pb, x0, p, mu0, sigma0, k_stop=0, tape=False):
         Xk = X[k]
         Ybar = float(Y.mean())
         eps2 = cloud_bandwidth(pb, Xk, k)
-        lam = pb.ridge_rel * sigma0 ** 2 * (k + 1) * dt
+        lam = pb.ridge_rel * (sigma0 ** 2 + sigma1 ** 2) * (k + 1) * dt
         Ynew, zz, zs = np.empty(pb.M), np.empty(pb.M), np.empty(pb.M)
         for m in range(pb.M):
             alpha, _ = anchor_fit_eps(Xk, Y, m, eps2, lam)
-            Z = sigma0 * Xk[m] * alpha[1:]
+            Z = (sigma0 * Xk[m] + sigma1) * alpha[1:]
             y, _, st = S.newton(pb, k, np.array([Ybar]), Z)
             Ynew[m], zz[m], zs[m] = y[0], Z @ Z, Z.sum()
             status |= st

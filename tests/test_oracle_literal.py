@@ -12,8 +12,8 @@
   level. Y^m has closed forms there, in the slope that scikit-learn fits. This pins Z = s alpha_x and
   the sign of f.
 * At level 0 the design is zero, so the slope is exactly zero.
-* Geometric family (mu = mu0 x, sigma = sigma0 diag(x)), an x-dependent-coefficient case of the paper's
-  problem class:
+* Affine diagonal family (mu = mu0 x + mu1, sigma = diag(sigma0 x + sigma1); geometric for mu1 = sigma1 = 0),
+  an x-dependent-coefficient case of the paper's problem class:
   - the Euler-Maruyama cloud against its exact first and second moments, per coordinate, by z-tests;
   - the first level against scikit-learn's ridge, with Z = sigma(X^m)^T alpha_x and the cloud bandwidth.
 """
@@ -178,3 +178,46 @@ def test_geometric_fit_primal_equals_dual():
         a1, _ = L.anchor_fit_eps(X, Y, 2, 0.7, 3e-3, "primal")
         a2, _ = L.anchor_fit_eps(X, Y, 2, 0.7, 3e-3, "dual")
         assert np.max(np.abs(a1 - a2)) <= 1e-9 * np.max(np.abs(a1))
+
+
+def test_affine_diag_path_moments():
+    # exact moments of the Euler-Maruyama recursion for mu = mu0 x + mu1, sigma = diag(sigma0 x + sigma1):
+    # E X' = a E X + mu1 dt and E X'^2 = a^2 E X^2 + 2 a mu1 dt E X + mu1^2 dt^2
+    #        + dt (sigma0^2 E X^2 + 2 sigma0 sigma1 E X + sigma1^2), with a = 1 + mu0 dt
+    mu0, mu1, s0, s1 = -0.8, 0.3, 0.2, 0.5
+    pb = S.Problem(d=3, M=4000, N=5, T=1.0, seed=6)
+    x0 = np.array([1.0, -0.5, 2.0])
+    X = L.geometric_path(pb, x0, 0, mu0, s0, mu1, s1)
+    dt = pb.T / pb.N
+    a = 1 + mu0 * dt
+    m1, m2 = x0.copy(), x0 ** 2
+    for _ in range(pb.N):
+        m1, m2 = (a * m1 + mu1 * dt,
+                  a * a * m2 + 2 * a * mu1 * dt * m1 + mu1 ** 2 * dt ** 2 + dt * (s0 ** 2 * m2 + 2 * s0 * s1 * m1 + s1 ** 2))
+    for i in range(3):
+        v1, v2 = X[pb.N, :, i], X[pb.N, :, i] ** 2
+        assert abs(v1.mean() - m1[i]) < 4.5 * v1.std() / np.sqrt(pb.M), i
+        assert abs(v2.mean() - m2[i]) < 4.5 * v2.std() / np.sqrt(pb.M), i
+
+
+def test_affine_diag_first_level_hjb_closed_form():
+    d, M, N, mu0, mu1, s0, s1 = 4, 13, 3, -0.5, 0.2, 0.3, 0.4
+    pb = S.Problem(d=d, M=M, N=N, T=0.9, f_kind=S.F_HJB, fp=(0.6, 0, 0, 0), g_kind=S.G_QUAD, gp=(1.0, 0.2, 0, 0),
+                   ridge_rel=2e-2, eps_h=1.0, seed=9)
+    x0 = np.array([0.8, 1.2, -0.6, 1.0])
+    k = N - 1
+    out = L.solve_point_geometric(pb, x0, 0, mu0, s0, k_stop=k, tape=True, mu1=mu1, sigma1=s1)
+    X = L.geometric_path(pb, x0, 0, mu0, s0, mu1, s1)
+    YN, _, _ = S.g_eval(pb, X[N])
+    Xk = X[k]
+    C = Xk - Xk.mean(axis=0)
+    eps2 = 2.0 * np.sum(C * C) / M
+    dt = pb.T / N
+    for m in range(M):
+        D = Xk - Xk[m]
+        w = np.exp(-np.sum(D * D, axis=1) / eps2)
+        w /= w.sum()
+        r = Ridge(alpha=pb.ridge_rel * (s0 ** 2 + s1 ** 2) * (k + 1) * dt, fit_intercept=False, solver="cholesky")
+        r.fit(np.hstack([np.ones((M, 1)), D]), YN, sample_weight=w)
+        Z = (s0 * Xk[m] + s1) * r.coef_[1:]
+        assert out["Y"][m] == pytest.approx(YN.mean() - dt * 0.6 * (Z @ Z), rel=1e-10, abs=1e-13)

@@ -348,25 +348,29 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
                         fbsde_stream stream);
 
 /* The same printed scheme with x-dependent coefficients (the problem class of Sec. 2.1 allows mu(t, x)
- * and sigma(t, x)).  Family FBSDE_COEF_GEOMETRIC: mu(x) = mu0 x, sigma(x) = sigma0 diag(x), so the
- * particles follow the Euler-Maruyama step of eq. Xk,
- *   X_{k+1} = X_k + mu0 X_k dt + sigma0 X_k * sqrt(dt) xi_k (componentwise), X_0 = x0,
+ * and sigma(t, x)).  Affine diagonal family, componentwise: mu(x) = mu0 x + mu1, sigma(x) =
+ * diag(sigma0 x + sigma1).  FBSDE_COEF_GEOMETRIC is its case mu1 = sigma1 = 0 (both must be 0);
+ * FBSDE_COEF_AFFINE_DIAG takes all four (sigma0 = 0, mu0 < 0: an Ornstein-Uhlenbeck drift with additive
+ * noise).  The particles follow the Euler-Maruyama step of eq. Xk,
+ *   X_{k+1} = X_k + (mu0 X_k + mu1) dt + (sigma0 X_k + sigma1) * sqrt(dt) xi_k, X_0 = x0,
  * with the same increments xi as every other entry point.  Per level and particle m, as in
  * fbsde_solve_literal, except:
- *   Z^m_k = sigma(X^m_k)^T alpha_x = sigma0 X^m_k * alpha_x (componentwise), from the explicit slope;
+ *   Z^m_k = sigma(X^m_k)^T alpha_x = (sigma0 X^m_k + sigma1) * alpha_x (componentwise), from the explicit slope;
  *   eps_k^2 = eps_h^2 2 (1/M) sum_j |X^j_k - Xbar_k|^2, the cloud's own mean squared pairwise distance
  *     (uniform weights at k = 0);
- *   lambda_k = ridge_rel sigma0^2 t_{k+1}.
+ *   lambda_k = ridge_rel (sigma0^2 + sigma1^2) t_{k+1}.
  * The path is not reversible from its increments, so the displacements X_k - x0 of every level are
  * kept: the workspace holds (N + 1) P M d doubles.  pb->s is not used; pb->mu must be NULL.
- * Arguments, outputs, limits and errors as fbsde_solve_literal; coef host, kind FBSDE_COEF_GEOMETRIC,
- * reserved 0, sigma0 > 0 and finite mu0 (FBSDE_EINVAL otherwise). */
-enum { FBSDE_COEF_GEOMETRIC = 1 };
+ * Arguments, outputs, limits and errors as fbsde_solve_literal; coef host, reserved 0, finite
+ * coefficients with sigma0^2 + sigma1^2 > 0 (FBSDE_EINVAL otherwise). */
+enum { FBSDE_COEF_GEOMETRIC = 1, FBSDE_COEF_AFFINE_DIAG = 2 };
 typedef struct fbsde_coef {
-    int32_t kind;            /* FBSDE_COEF_GEOMETRIC                                          */
+    int32_t kind;            /* FBSDE_COEF_GEOMETRIC or FBSDE_COEF_AFFINE_DIAG                */
     int32_t reserved;        /* must be 0                                                     */
-    double mu0;              /* drift factor: mu(x) = mu0 x                                   */
-    double sigma0;           /* volatility factor: sigma(x) = sigma0 diag(x), > 0             */
+    double mu0;              /* drift: mu(x) = mu0 x + mu1                                    */
+    double sigma0;           /* volatility: sigma(x) = diag(sigma0 x + sigma1)                */
+    double mu1;              /* 0 for FBSDE_COEF_GEOMETRIC                                    */
+    double sigma1;           /* 0 for FBSDE_COEF_GEOMETRIC                                    */
 } fbsde_coef;
 int fbsde_literal_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes);
 int fbsde_solve_literal_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, int32_t k_stop,

@@ -33,12 +33,12 @@ class CTuneResult(ctypes.Structure):
                 ("n_candidates", ctypes.c_int32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
 
 
-COEF_GEOMETRIC = 1
+COEF_GEOMETRIC, COEF_AFFINE_DIAG = 1, 2
 
 
 class CCoef(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu0", ctypes.c_double),
-                ("sigma0", ctypes.c_double)]
+                ("sigma0", ctypes.c_double), ("mu1", ctypes.c_double), ("sigma1", ctypes.c_double)]
 
 
 class CProblem(ctypes.Structure):

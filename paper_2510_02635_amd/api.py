@@ -444,20 +444,22 @@ def literal_workspace_size(pb, P):
     return int(out.value)
 
 
-def _coef(mu0, sigma0):
-    return N.CCoef(N.COEF_GEOMETRIC, 0, float(mu0), float(sigma0))
+def _coef(mu0, sigma0, mu1=0.0, sigma1=0.0):
+    kind = N.COEF_GEOMETRIC if (mu1 == 0.0 and sigma1 == 0.0) else N.COEF_AFFINE_DIAG
+    return N.CCoef(kind, 0, float(mu0), float(sigma0), float(mu1), float(sigma1))
 
 
-def literal_coef_workspace_size(pb, P, mu0, sigma0):
+def literal_coef_workspace_size(pb, P, mu0, sigma0, mu1=0.0, sigma1=0.0):
     out = ctypes.c_size_t(0)
-    N.check(N.load().fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0)), P,
-                                                       ctypes.byref(out)))
+    N.check(N.load().fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)),
+                                                       P, ctypes.byref(out)))
     return int(out.value)
 
 
-def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zstats=False, ws=None):
-    """Paper-literal per-anchor scheme under the geometric coefficient family mu(x) = mu0 x,
-    sigma(x) = sigma0 diag(x): outputs as solve_literal."""
+def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zstats=False, ws=None, mu1=0.0,
+                            sigma1=0.0):
+    """Paper-literal per-anchor scheme under the affine diagonal coefficients mu(x) = mu0 x + mu1,
+    sigma(x) = diag(sigma0 x + sigma1) (the geometric family when mu1 = sigma1 = 0): outputs as solve_literal."""
     P = x0.shape[0]
     _dev_f64(x0, (P, pb.d))
     dev = x0.device
@@ -466,8 +468,10 @@ def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zs
     Y = torch.empty((P, pb.M), dtype=torch.float64, device=dev) if want_Y else None
     zs = torch.empty((P, pb.M, 2), dtype=torch.float64, device=dev) if want_zstats else None
     if ws is None:
-        ws = torch.empty(max(literal_coef_workspace_size(pb, P, mu0, sigma0), 1), dtype=torch.uint8, device=dev)
-    N.check(N.load().fbsde_solve_literal_coef(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0)), P, int(k_stop),
+        ws = torch.empty(max(literal_coef_workspace_size(pb, P, mu0, sigma0, mu1, sigma1), 1), dtype=torch.uint8,
+                         device=dev)
+    N.check(N.load().fbsde_solve_literal_coef(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)), P,
+                                              int(k_stop),
                                               x0.data_ptr(), u.data_ptr(), _ptr(Y), _ptr(zs), st.data_ptr(),
                                               ws.data_ptr(), ws.numel(), _stream()))
     return u, st, Y, zs

@@ -562,15 +562,18 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
     }
 }
 
-// ------------------------------------------------------------------ geometric coefficient family
-// mu(x) = mu0 x, sigma(x) = sigma0 diag(x).  The displacement V = X - x0 is stored at every level (the
-// path cannot be reversed from its increments), V_k at Vs + k P M ldw.
+// ------------------------------------------------------------------ affine diagonal coefficient family
+// mu(x) = mu0 x + mu1, sigma(x) = diag(sigma0 x + sigma1) (geometric: mu1 = sigma1 = 0).  The displacement
+// V = X - x0 is stored at every level (the path cannot be reversed from its increments), V_k at
+// Vs + k P M ldw.
 
-// Forward sweep (eq. Xk): V_{k+1} = V_k + (mu0 dt + sigma0 sqrt(dt) xi_k) (x0 + V_k) componentwise,
-// V_0 = 0; one thread per (point, particle, 4-coordinate group), the row pad written as zero.
+// Forward sweep (eq. Xk): V_{k+1} = V_k + (mu0 X + mu1) dt + (sigma0 X + sigma1) sqrt(dt) xi_k with
+// X = x0 + V_k, componentwise, V_0 = 0; one thread per (point, particle, 4-coordinate group), the row
+// pad written as zero.
 __global__ void __launch_bounds__(256)
 k_geo_forward(double* __restrict__ Vs, int64_t ldw, int M, int d, int N, double dt, double sqdt, double mu0,
-              double s0, const double* __restrict__ x0, uint32_t point_base, uint32_t k0, uint32_t k1, int64_t P) {
+              double s0, double mu1, double s1, const double* __restrict__ x0, uint32_t point_base, uint32_t k0,
+              uint32_t k1, int64_t P) {
     const int ngl = (int)(ldw / 4);
     const int64_t n = P * (int64_t)M * ngl;
     const int64_t lstride = P * (int64_t)M * ldw;
@@ -590,7 +593,10 @@ k_geo_forward(double* __restrict__ Vs, int64_t ldw, int M, int d, int N, double 
                 double z[4];
                 increment4<double>((uint32_t)g, (uint32_t)j, (uint32_t)k, point_base + (uint32_t)p, k0, k1, z);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] += (mu0 * dt + s0 * (sqdt * z[e])) * (xg[e] + v[e]);
+                for (int e = 0; e < 4; ++e) {
+                    const double X = xg[e] + v[e];
+                    v[e] += (mu0 * X + mu1) * dt + (s0 * X + s1) * (sqdt * z[e]);
+                }
             }
             double* rk = row + (int64_t)(k + 1) * lstride;
 #pragma unroll
@@ -621,11 +627,11 @@ k_geo_bandwidth(const double* __restrict__ G, int M, double h2, double* __restri
 // One workgroup per (32-coordinate slice, point) holds the slice of all M displacements in LDS and serves
 // every anchor from it.  Thread (g, i) = (tid / 32, tid % 32) takes
 // coordinate i of the slice for the anchors m = g, g + 8, ...: alpha_i = sum_j c_mj V_ji - (sum_j c_mj) V_mi,
-// Z_i = sigma0 (x0_i + V_mi) alpha_i.  The slice's sums of Z_i^2 and Z_i per anchor go to
+// Z_i = (sigma0 (x0_i + V_mi) + sigma1) alpha_i.  The slice's sums of Z_i^2 and Z_i per anchor go to
 // part[(p M + m) nsl + slice][2] (reduced over the 32 lanes of a half wave).  Grid (nsl, P).
 __global__ void __launch_bounds__(256)
 k_geo_alpha_z(const double* __restrict__ Vk, int64_t ldw, int M, int d, const double* __restrict__ x0,
-              const double* __restrict__ C, double s0, int nsl, double* __restrict__ part) {
+              const double* __restrict__ C, double s0, double s1, int nsl, double* __restrict__ part) {
     extern __shared__ double Vsl[];   // [M][33]
     const int sl = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
     const int i = tid & 31, g = tid >> 5;
@@ -648,7 +654,7 @@ k_geo_alpha_z(const double* __restrict__ Vk, int64_t ldw, int M, int d, const do
         }
         const double vm = Vsl[m * 33 + i];
         a -= cs * vm;
-        const double z = in ? s0 * (xi + vm) * a : 0.0;
+        const double z = in ? (s0 * (xi + vm) + s1) * a : 0.0;
         double zz = z * z, zs = z;
 #pragma unroll
         for (int off = 16; off > 0; off >>= 1) {   // within the 32 lanes of this anchor group
@@ -705,11 +711,11 @@ struct LitWS {
     double *W, *Ya, *Yb, *G, *rho, *Gpart, *Rpart, *C, *eps2, *Zpart;
 };
 
-// Coefficient family of a literal solve: sigma = s I with constant drift (geo = false), or the
-// geometric family mu(x) = mu0 x, sigma(x) = sigma0 diag(x).
+// Coefficient family of a literal solve: sigma = s I with constant drift (geo = false), or the affine
+// diagonal family mu(x) = mu0 x + mu1, sigma(x) = diag(sigma0 x + sigma1) (geometric: mu1 = sigma1 = 0).
 struct Coef {
     bool geo;
-    double mu0, s0;
+    double mu0, s0, mu1, s1;
 };
 
 // Split of the Gram contraction.  M <= 128: the row-resident kernel, one tile per point, about 1024
@@ -765,10 +771,15 @@ int lit_check(const fbsde_problem* pb, int64_t P, host::Plan& pl) {
 }
 
 int coef_check(const fbsde_problem* pb, const fbsde_coef* coef, Coef& c) {
-    if (!coef || coef->kind != FBSDE_COEF_GEOMETRIC || coef->reserved != 0) return FBSDE_EINVAL;
-    if (!(coef->sigma0 > 0.0) || !std::isfinite(coef->sigma0) || !std::isfinite(coef->mu0)) return FBSDE_EINVAL;
+    if (!coef || coef->reserved != 0) return FBSDE_EINVAL;
+    if (coef->kind != FBSDE_COEF_GEOMETRIC && coef->kind != FBSDE_COEF_AFFINE_DIAG) return FBSDE_EINVAL;
+    if (coef->kind == FBSDE_COEF_GEOMETRIC && (coef->mu1 != 0.0 || coef->sigma1 != 0.0)) return FBSDE_EINVAL;
+    const double v[4] = {coef->mu0, coef->sigma0, coef->mu1, coef->sigma1};
+    for (double x : v)
+        if (!std::isfinite(x)) return FBSDE_EINVAL;
+    if (!(coef->sigma0 * coef->sigma0 + coef->sigma1 * coef->sigma1 > 0.0)) return FBSDE_EINVAL;
     if (pb && pb->mu) return FBSDE_EINVAL;   // the family's drift replaces the constant one
-    c = {true, coef->mu0, coef->sigma0};
+    c = {true, coef->mu0, coef->sigma0, coef->mu1, coef->sigma1};
     return FBSDE_OK;
 }
 
@@ -826,7 +837,7 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
     const unsigned fblocks = (unsigned)std::min<int64_t>((nfwd + 255) / 256, (int64_t)1 << 20);
     if (cf.geo) {
         hipLaunchKernelGGL(k_geo_forward, dim3(fblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, (int)pb->N, dt,
-                           sqdt, cf.mu0, cf.s0, x0, pb->point_base, ky.k0, ky.k1, P);
+                           sqdt, cf.mu0, cf.s0, cf.mu1, cf.s1, x0, pb->point_base, ky.k0, ky.k1, P);
         hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, w.W + pb->N * lstride,
                            (int64_t)pl.ld, M, d, x0, nullptr, pb->gvec, 1.0, pb->T, pb->g_kind, pb->gp[0], pb->gp[1],
                            w.Ya, status);
@@ -844,7 +855,8 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
     const int64_t ngroups = P * (int64_t)M * ((d + 3) / 4);
     const unsigned rblocks = (unsigned)std::min<int64_t>((ngroups + 255) / 256, (int64_t)1 << 20);
     const FSpec f = host::fspec_of(pb);
-    const double s_ridge = cf.geo ? cf.s0 : pb->s;   // lambda_k = ridge_rel sigma^2 t_{k+1}
+    // lambda_k = ridge_rel sigma^2 t_{k+1}, sigma^2 = sigma0^2 + sigma1^2 for the affine diagonal family
+    const double s_ridge = cf.geo ? std::sqrt(cf.s0 * cf.s0 + cf.s1 * cf.s1) : pb->s;
     double* Yn = w.Ya;
     double* Yk = w.Yb;
     for (int k = (int)pb->N - 1; k >= k_stop; --k) {
@@ -895,7 +907,7 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
                     hipSuccess)
                 return FBSDE_EHIP;
             hipLaunchKernelGGL(k_geo_alpha_z, dim3(nsl, (unsigned)P), dim3(256), lds, st, Xk,
-                               (int64_t)pl.ld, M, d, x0, w.C, cf.s0, nsl, w.Zpart);
+                               (int64_t)pl.ld, M, d, x0, w.C, cf.s0, cf.s1, nsl, w.Zpart);
             hipLaunchKernelGGL(k_geo_newton, dim3(M, (unsigned)P), dim3(64), 0, st, w.Zpart, nsl, M, Yn, Yk, dt, f,
                                pb->newton_iters, zst, status);
         }
@@ -932,7 +944,7 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
     LitWS w;
     if (lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
     lit_carve(P, pb->M, pb->N, pl.ld, false, (char*)wsp, w);
-    return lit_run(pb, Coef{false, 0.0, 0.0}, pl, P, k_stop, x0, u, Y_out, z_stats, status, w, (hipStream_t)stream);
+    return lit_run(pb, Coef{false, 0.0, 0.0, 0.0, 0.0}, pl, P, k_stop, x0, u, Y_out, z_stats, status, w, (hipStream_t)stream);
 }
 
 int fbsde_literal_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes) {

@@ -157,6 +157,15 @@ def test_literal_coef_validation_on_host():
         assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(bad), 2,
                                                      ctypes.byref(size)) == N.EINVAL
     assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), None, 2, ctypes.byref(size)) == N.EINVAL
+    # the geometric kind takes no affine parts; the affine diagonal kind takes additive noise alone
+    geo_aff = N.CCoef(N.COEF_GEOMETRIC, 0, 0.1, 0.4, 0.2, 0.0)
+    assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(geo_aff), 2,
+                                                 ctypes.byref(size)) == N.EINVAL
+    ou = N.CCoef(N.COEF_AFFINE_DIAG, 0, -0.8, 0.0, 0.2, 0.5)
+    assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(ou), 2, ctypes.byref(size)) == N.OK
+    flat = N.CCoef(N.COEF_AFFINE_DIAG, 0, -0.8, 0.0, 0.2, 0.0)
+    assert lib.fbsde_literal_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(flat), 2,
+                                                 ctypes.byref(size)) == N.EINVAL
     c = ctypes.byref(pb.c())
     assert lib.fbsde_solve_literal_coef(c, ctypes.byref(ok), 0, 0, None, None, None, None, None, None, 0, None) == N.OK
     assert lib.fbsde_solve_literal_coef(c, ctypes.byref(ok), 1, 5, None, None, None, None, None, None, 0, None) == N.EINVAL

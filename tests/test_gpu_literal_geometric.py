@@ -1,5 +1,5 @@
-"""GPU parity of the paper-literal scheme under x-dependent coefficients (the geometric family
-mu(x) = mu0 x, sigma(x) = sigma0 diag(x)) against the FP64 oracle.
+"""GPU parity of the paper-literal scheme under x-dependent coefficients (the affine diagonal family
+mu(x) = mu0 x + mu1, sigma(x) = diag(sigma0 x + sigma1); geometric when mu1 = sigma1 = 0) against the FP64 oracle.
 
 Every case compares u, every particle's Y and (|Z|^2, sum Z) at level k_stop element by element, at 1e-10.
 |Z|^2 and sum Z get 1e-8 of their largest values plus a floor of 1e-12 |Y|^2 and 1e-10 |Y|: with M << d the
@@ -19,7 +19,7 @@ from oracle import scheme as OS
 pytestmark = pytest.mark.gpu
 
 
-def _run(kw, P, mu0, s0, k_stop=0, seed=1):
+def _run(kw, P, mu0, s0, k_stop=0, seed=1, mu1=0.0, s1=0.0):
     rng = np.random.default_rng(seed)
     x0 = 1.0 + 0.3 * rng.normal(size=(P, kw["d"]))
     gkw = dict(kw)
@@ -28,12 +28,12 @@ def _run(kw, P, mu0, s0, k_stop=0, seed=1):
     pb = F.Problem(**gkw)
     print(f"[literal-geometric] d={kw['d']} M={kw['M']} N={kw['N']} P={P} k_stop={k_stop}", flush=True)
     u, st, Y, zs = F.solve_literal_geometric(pb, torch.tensor(x0, device="cuda"), mu0, s0, k_stop=k_stop,
-                                             want_Y=True, want_zstats=True)
+                                             want_Y=True, want_zstats=True, mu1=mu1, sigma1=s1)
     torch.cuda.synchronize()
     u, st, Y, zs = u.cpu().numpy(), st.cpu().numpy(), Y.cpu().numpy(), zs.cpu().numpy()
     opb = OS.Problem(**kw)
     for p in range(P):
-        ref = OL.solve_point_geometric(opb, x0[p], p, mu0, s0, k_stop=k_stop, tape=True)
+        ref = OL.solve_point_geometric(opb, x0[p], p, mu0, s0, k_stop=k_stop, tape=True, mu1=mu1, sigma1=s1)
         assert int(st[p]) == ref["status"] == 0
         assert abs(u[p] - ref["u"]) <= 1e-10 * max(1.0, abs(ref["u"])), (p, u[p], ref["u"])
         assert np.max(np.abs(Y[p] - ref["Y"])) <= 1e-10 * max(1.0, np.max(np.abs(ref["Y"])))
@@ -113,3 +113,11 @@ def test_geometric_full_size_d1000_M100():
 def test_geometric_largest_M():
     # M = 256: the slice of all displacements needs more than 64 KB of LDS (raised per launch)
     _run(dict(d=40, M=256, N=2, T=0.4, ridge_rel=1e-2, seed=10, **HJB), P=1, mu0=0.1, s0=0.3, k_stop=1)
+
+
+
+@pytest.mark.parametrize("mu0,mu1,s0,s1", [(-0.8, 0.2, 0.0, 0.5), (-0.3, 0.1, 0.2, 0.3)])
+def test_affine_diag_ou_and_mixed(mu0, mu1, s0, s1):
+    # Ornstein-Uhlenbeck drift with additive noise (sigma0 = 0), and all four coefficients at once
+    _run(dict(d=10, M=30, N=4, T=0.6, ridge_rel=1e-2, seed=11, **HJB), P=2, mu0=mu0, s0=s0, k_stop=1, mu1=mu1, s1=s1)
+    _run(dict(d=10, M=30, N=4, T=0.6, ridge_rel=1e-2, seed=11, **HJB), P=2, mu0=mu0, s0=s0, k_stop=0, mu1=mu1, s1=s1)

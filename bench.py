@@ -342,7 +342,9 @@ def main():
         pbl = F.Problem(d=dl, M=Ml, N=Nl, T=Tl, s=sl, f_kind=F.F_BURGERS, fp=(sl / dl, dl / (sl * sl) + 0.5, 0, 0),
                         g_kind=F.G_LOGISTIC, gp=(Tl, 0, 0, 0), gvec=gvl, eps_h=1.0, ridge_rel=1e-3, instance=6)
         xl = torch.zeros((Pl, dl), dtype=torch.float64, device=dev)
-        wsl = torch.empty(F.literal_workspace_size(pbl, Pl), dtype=torch.uint8, device=dev)
+        torch.cuda.empty_cache()
+        # a workspace that keeps every level's particles (52 GB): no reversal by regenerated increments
+        wsl = torch.empty(F.literal_workspace_size(pbl, Pl, stored=True), dtype=torch.uint8, device=dev)
         F.solve_literal(pbl, xl, ws=wsl)
         torch.cuda.synchronize()
         F.launch_timer(True)
@@ -368,13 +370,15 @@ def main():
                    "dtype": "f64", "config": {"workload": "literal_burgers_d10000_M100_N100_T0.3_P64", "d": dl,
                                               "M": Ml, "N": Nl, "T": Tl, "points": Pl, "x0": "0 (replicas)",
                                               "ridge_rel": 1e-3, "kernel_h": 1.0},
+                   "stored_path_GB": round(wsl.numel() / 1e9, 2),
                    "u_mean": round(float(ul.mean()), 6), "u_sd": round(float(ul.std()), 6), "u_exact": 0.5,
                    "status_nonzero_points": int((stl != 0).sum().item()), "kernels": legs,
                    "paper_cpu_s_per_point_context": 1040.15}
         log(f"[bench] literal per-anchor d=1e4 M=100 N=100 P=64: {secl * 1e3:.1f} ms "
             f"(gram {legs['gram']['avg_ms']:.3f} ms/level, anchors {legs['anchors']['avg_ms']:.3f} ms/level)")
         del wsl
-        # the paper's second particle count at this setting, M = 200 (16-wavefront anchor layout)
+        # the paper's second particle count at this setting, M = 200 (eight-wavefront anchor layout), with the
+        # minimal workspace (the path reversed by regenerated increments)
         pb2 = F.Problem(d=dl, M=200, N=Nl, T=Tl, s=sl, f_kind=F.F_BURGERS, fp=(sl / dl, dl / (sl * sl) + 0.5, 0, 0),
                         g_kind=F.G_LOGISTIC, gp=(Tl, 0, 0, 0), gvec=gvl, eps_h=1.0, ridge_rel=1e-3, instance=6)
         ws2 = torch.empty(F.literal_workspace_size(pb2, Pl), dtype=torch.uint8, device=dev)

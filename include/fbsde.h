@@ -340,9 +340,13 @@ int fbsde_graph_destroy(fbsde_graph graph);
  *   Y_out    device [P][M] out: Y^m_{k_stop}, or NULL
  *   z_stats  device [P][M][2] out: |Z^m_{k_stop}|^2 and sum_i Z^m_{k_stop,i}, or NULL
  *   status   device [P] cleared, then OR-ed with FBSDE_ST_NEWTON_FLAT / FBSDE_ST_NONFINITE
- *   ws       device workspace of fbsde_literal_workspace_size(pb, P) bytes (FBSDE_ENOSPC if smaller)
+ *   ws       device workspace of fbsde_literal_workspace_size(pb, P) bytes (FBSDE_ENOSPC if smaller).  With
+ *            at least fbsde_literal_workspace_size_stored(pb, P) bytes ((N + 1) P M d doubles and more) the
+ *            forward sweep keeps the particles of every level and the backward sweep reads them, instead
+ *            of reversing the path with regenerated increments; the results agree to rounding.
  * P = 0 returns FBSDE_OK without touching the pointers. */
 int fbsde_literal_workspace_size(const fbsde_problem* pb, int64_t P, size_t* bytes);
+int fbsde_literal_workspace_size_stored(const fbsde_problem* pb, int64_t P, size_t* bytes);
 int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, const double* x0, double* u,
                         double* Y_out, double* z_stats, uint32_t* status, void* ws, size_t ws_bytes,
                         fbsde_stream stream);

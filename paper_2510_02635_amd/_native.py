@@ -16,7 +16,8 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
             "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
-            "fbsde_literal_workspace_size", "fbsde_literal_coef_workspace_size", "fbsde_solve_literal_coef",
+            "fbsde_literal_workspace_size", "fbsde_literal_workspace_size_stored", "fbsde_literal_coef_workspace_size",
+            "fbsde_solve_literal_coef",
             "fbsde_solve_literal", "fbsde_strerror")
 
 
@@ -108,6 +109,7 @@ def load():
     lib.fbsde_autotune.argtypes = [pb, i64, vp, vp, sz, P(CTuneResult), vp]
     lib.fbsde_autotune_reset.argtypes = []
     lib.fbsde_literal_workspace_size.argtypes = [pb, i64, P(sz)]
+    lib.fbsde_literal_workspace_size_stored.argtypes = [pb, i64, P(sz)]
     lib.fbsde_solve_literal.argtypes = [pb, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_literal_coef_workspace_size.argtypes = [pb, P(CCoef), i64, P(sz)]
     lib.fbsde_solve_literal_coef.argtypes = [pb, P(CCoef), i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -119,6 +121,7 @@ def load():
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
                  "fbsde_launch_timer_read", "fbsde_launch_timer_kinds", "fbsde_literal_coef_workspace_size",
+                 "fbsde_literal_workspace_size_stored",
                  "fbsde_solve_literal_coef",
                  "fbsde_solve_literal"):
         getattr(lib, name).restype = ctypes.c_int

@@ -438,9 +438,11 @@ def autotune_reset():
     N.check(N.load().fbsde_autotune_reset())
 
 
-def literal_workspace_size(pb, P):
+def literal_workspace_size(pb, P, stored=False):
+    """Bytes of workspace for solve_literal; stored=True: the size that keeps every level's particles."""
     out = ctypes.c_size_t(0)
-    N.check(N.load().fbsde_literal_workspace_size(ctypes.byref(pb.c()), P, ctypes.byref(out)))
+    fn = N.load().fbsde_literal_workspace_size_stored if stored else N.load().fbsde_literal_workspace_size
+    N.check(fn(ctypes.byref(pb.c()), P, ctypes.byref(out)))
     return int(out.value)
 
 
@@ -477,9 +479,10 @@ def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zs
     return u, st, Y, zs
 
 
-def solve_literal(pb, x0, k_stop=0, want_Y=False, want_zstats=False, ws=None):
+def solve_literal(pb, x0, k_stop=0, want_Y=False, want_zstats=False, ws=None, stored=False):
     """Paper-literal per-anchor scheme (Algorithm 1 as printed): u [P] = mean_m Y^m_{k_stop}, status [P],
-    and optionally Y^m_{k_stop} [P][M] and (|Z^m|^2, sum_i Z^m_i) [P][M][2] at level k_stop."""
+    and optionally Y^m_{k_stop} [P][M] and (|Z^m|^2, sum_i Z^m_i) [P][M][2] at level k_stop.  stored=True
+    allocates the workspace that keeps every level's particles (no reversal by regenerated increments)."""
     P = x0.shape[0]
     _dev_f64(x0, (P, pb.d))
     dev = x0.device
@@ -488,7 +491,7 @@ def solve_literal(pb, x0, k_stop=0, want_Y=False, want_zstats=False, ws=None):
     Y = torch.empty((P, pb.M), dtype=torch.float64, device=dev) if want_Y else None
     zs = torch.empty((P, pb.M, 2), dtype=torch.float64, device=dev) if want_zstats else None
     if ws is None:
-        ws = torch.empty(max(literal_workspace_size(pb, P), 1), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(literal_workspace_size(pb, P, stored), 1), dtype=torch.uint8, device=dev)
     N.check(N.load().fbsde_solve_literal(ctypes.byref(pb.c()), P, int(k_stop), x0.data_ptr(), u.data_ptr(), _ptr(Y),
                                          _ptr(zs), st.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
     return u, st, Y, zs

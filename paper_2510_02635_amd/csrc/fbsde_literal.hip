@@ -39,9 +39,10 @@ constexpr int LMAX = 256;   // largest M of the register-resident factorisation
 
 // Forward sweep (Algorithm 1, eq. Xk): W^j_N = sum_k sqrt(dt) xi^j_k for every point, particle and
 // 4-coordinate group, accumulated in level order; the row pad up to ldw is written as zero.
+// With all_levels the row of every level k = 0..N is stored, at W + k P M ldw (level 0 is zero).
 __global__ void __launch_bounds__(256)
 k_lit_forward(double* __restrict__ W, int64_t ldw, int M, int d, int N, double sqdt, uint32_t point_base,
-              uint32_t k0, uint32_t k1, int64_t P) {
+              uint32_t k0, uint32_t k1, int64_t P, int all_levels) {
     const int ngl = (int)(ldw / 4);
     const int64_t n = P * (int64_t)M * ngl;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
@@ -50,17 +51,29 @@ k_lit_forward(double* __restrict__ W, int64_t ldw, int M, int d, int N, double s
         const int j = (int)(pj % M);
         const int64_t p = pj / M;
         double w[4] = {0.0, 0.0, 0.0, 0.0};
-        if (4 * g < d) {
-            for (int k = 0; k < N; ++k) {
+        double* row = W + pj * ldw + 4 * g;
+        const int64_t lstride = P * (int64_t)M * ldw;
+        if (all_levels) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) row[e] = 0.0;
+        }
+        for (int k = 0; k < N; ++k) {
+            if (4 * g < d) {
                 double z[4];
                 increment4<double>((uint32_t)g, (uint32_t)j, (uint32_t)k, point_base + (uint32_t)p, k0, k1, z);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) w[e] += sqdt * z[e];
             }
-        }
-        double* row = W + pj * ldw + 4 * g;
+            if (all_levels) {
+                double* rk = row + (int64_t)(k + 1) * lstride;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) row[e] = (4 * g + e < d) ? w[e] : 0.0;
+                for (int e = 0; e < 4; ++e) rk[e] = (4 * g + e < d) ? w[e] : 0.0;
+            }
+        }
+        if (!all_levels) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) row[e] = (4 * g + e < d) ? w[e] : 0.0;
+        }
     }
 }
 
@@ -740,14 +753,14 @@ GramSplit gram_split(int64_t P, int64_t M, int64_t ld) {
 // Workspace: the state (scalar family: W_k, one level, reversed in place; geometric family: V_k for
 // k = 0..N), two Y buffers, the Gram matrices and row sums with their per-chunk partials, and for the
 // geometric family the dual solutions C [P][M][M] and the per-point bandwidths.
-size_t lit_carve(int64_t P, int64_t M, int64_t N, int64_t ld, bool geo, char* base, LitWS& w) {
+size_t lit_carve(int64_t P, int64_t M, int64_t N, int64_t ld, bool geo, char* base, LitWS& w, bool stored = false) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* ptr = base ? base + off : nullptr;
         off += (bytes + 255) / 256 * 256;
         return (double*)ptr;
     };
-    w.W = take((size_t)(geo ? N + 1 : 1) * P * M * ld * 8);
+    w.W = take((size_t)((geo || stored) ? N + 1 : 1) * P * M * ld * 8);
     w.Ya = take((size_t)P * M * 8);
     w.Yb = take((size_t)P * M * 8);
     w.G = take((size_t)P * M * M * 8);
@@ -822,7 +835,7 @@ int anchors(int64_t P, int M, const double* G, const double* rho, const double* 
 // The whole literal solve for either coefficient family (arguments validated by the callers).
 int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64_t P, int32_t k_stop,
             const double* x0, double* u, double* Y_out, double* z_stats, uint32_t* status, const LitWS& w,
-            hipStream_t st) {
+            hipStream_t st, bool stored = false) {
     int rc = FBSDE_OK;
     const int M = (int)pb->M, d = (int)pb->d;
     const host::Keys ky = host::keys_of(pb);
@@ -843,9 +856,10 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
                            w.Ya, status);
     } else {
         hipLaunchKernelGGL(k_lit_forward, dim3(fblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, (int)pb->N, sqdt,
-                           pb->point_base, ky.k0, ky.k1, P);
-        hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, w.W, (int64_t)pl.ld, M, d, x0,
-                           pb->mu, pb->gvec, s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], w.Ya, status);
+                           pb->point_base, ky.k0, ky.k1, P, stored ? 1 : 0);
+        hipLaunchKernelGGL(k_lit_terminal, dim3(M, (unsigned)P), dim3(64), 0, st, stored ? w.W + pb->N * lstride : w.W,
+                           (int64_t)pl.ld, M, d, x0, pb->mu, pb->gvec, s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], w.Ya,
+                           status);
     }
     const GramSplit gs = gram_split(P, M, pl.ld);
     const int64_t nG = P * (int64_t)M * M;
@@ -861,7 +875,7 @@ int lit_run(const fbsde_problem* pb, const Coef& cf, const host::Plan& pl, int64
     double* Yk = w.Yb;
     for (int k = (int)pb->N - 1; k >= k_stop; --k) {
         double* Xk = w.W;
-        if (cf.geo) Xk = w.W + k * lstride;
+        if (cf.geo || stored) Xk = w.W + k * lstride;
         else
             hipLaunchKernelGGL(k_lit_reverse, dim3(rblocks), dim3(256), 0, st, w.W, (int64_t)pl.ld, M, d, k, sqdt,
                                pb->point_base, ky.k0, ky.k1, P, k == 0 ? 1 : 0);
@@ -932,6 +946,16 @@ int fbsde_literal_workspace_size(const fbsde_problem* pb, int64_t P, size_t* byt
     return FBSDE_OK;
 }
 
+int fbsde_literal_workspace_size_stored(const fbsde_problem* pb, int64_t P, size_t* bytes) {
+    if (!bytes) return FBSDE_EINVAL;
+    host::Plan pl;
+    const int rc = lit_check(pb, P, pl);
+    if (rc) return rc;
+    LitWS w;
+    *bytes = lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w, true);
+    return FBSDE_OK;
+}
+
 int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, const double* x0, double* u,
                         double* Y_out, double* z_stats, uint32_t* status, void* wsp, size_t ws_bytes,
                         fbsde_stream stream) {
@@ -942,9 +966,12 @@ int fbsde_solve_literal(const fbsde_problem* pb, int64_t P, int32_t k_stop, cons
     if (P == 0) return FBSDE_OK;   // nothing is read or written; the pointers may be null
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     LitWS w;
-    if (lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
-    lit_carve(P, pb->M, pb->N, pl.ld, false, (char*)wsp, w);
-    return lit_run(pb, Coef{false, 0.0, 0.0, 0.0, 0.0}, pl, P, k_stop, x0, u, Y_out, z_stats, status, w, (hipStream_t)stream);
+    // a workspace that holds every level selects the stored path (no reversal by regenerated increments)
+    const bool stored = lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w, true) <= ws_bytes;
+    if (!stored && lit_carve(P, pb->M, pb->N, pl.ld, false, nullptr, w) > ws_bytes) return FBSDE_ENOSPC;
+    lit_carve(P, pb->M, pb->N, pl.ld, false, (char*)wsp, w, stored);
+    return lit_run(pb, Coef{false, 0.0, 0.0, 0.0, 0.0}, pl, P, k_stop, x0, u, Y_out, z_stats, status, w,
+                   (hipStream_t)stream, stored);
 }
 
 int fbsde_literal_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes) {

@@ -59,8 +59,9 @@ def main():
             gvec = torch.full((kw["d"],), 1.0 / kw["d"], dtype=torch.float64, device="cuda")
             pb = F.Problem(gvec=gvec, **kw)
             x0 = torch.zeros((P, kw["d"]), dtype=torch.float64, device="cuda")
-            for _ in range(2):
-                u, st, _, _ = F.solve_literal(pb, x0)
+            ws = torch.empty(F.literal_workspace_size(pb, P, stored=True), dtype=torch.uint8, device="cuda")
+            for _ in range(2):   # every level's particles kept, as in the bench
+                u, st, _, _ = F.solve_literal(pb, x0, ws=ws)
         torch.cuda.synchronize()
         print(f"{args.workload} fp64 (literal, 2 solves): u[0]={u[0].item():.12g} "
               f"nonzero status={int((st != 0).sum())}", flush=True)

@@ -136,6 +136,10 @@ def test_literal_scheme_validation_on_host():
         assert lib.fbsde_literal_workspace_size(ctypes.byref(pb.c()), 3, ctypes.byref(size)) == N.EINVAL, bad
     assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 3, None) == N.EINVAL
     assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 0, ctypes.byref(size)) == N.OK
+    small, full = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.fbsde_literal_workspace_size(ctypes.byref(ok.c()), 3, ctypes.byref(small)) == N.OK
+    assert lib.fbsde_literal_workspace_size_stored(ctypes.byref(ok.c()), 3, ctypes.byref(full)) == N.OK
+    assert full.value >= small.value + 4 * 3 * 200 * 112 * 8   # N + 1 = 5 levels instead of one
     # P = 0: nothing to do, null pointers accepted; k_stop outside [0, N) and missing buffers rejected
     c = ctypes.byref(ok.c())
     assert lib.fbsde_solve_literal(c, 0, 0, None, None, None, None, None, None, 0, None) == N.OK

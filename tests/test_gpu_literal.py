@@ -148,3 +148,25 @@ def test_literal_full_size_burgers_d10000(M, N):
         ref = OL.solve_point(opb, np.zeros(d), p)
         assert abs(u[p] - ref["u"]) <= 1e-10 * abs(ref["u"]), (p, u[p], ref["u"])
         assert np.max(np.abs(Y[p] - ref["Y"])) <= 1e-10 * np.max(np.abs(ref["Y"]))
+
+
+
+@pytest.mark.parametrize("M", [40, 100])
+def test_literal_stored_path(M):
+    # a workspace that holds every level: the backward sweep reads the stored particles instead of reversing
+    # the path; against the oracle at 1e-10 and against the reversing form to rounding
+    kw = dict(d=300, M=M, N=5, T=0.5, s=np.sqrt(2.0), ridge_rel=1e-2, seed=2, **HJB)
+    P = 3
+    x0 = _x0(P, kw["d"], 4)
+    pb = F.Problem(**kw)
+    xt = torch.tensor(x0, device="cuda")
+    print(f"[literal stored] M={M}", flush=True)
+    u1, st1, Y1, _ = F.solve_literal(pb, xt, want_Y=True, stored=True)
+    u0, st0, Y0, _ = F.solve_literal(pb, xt, want_Y=True)
+    torch.cuda.synchronize()
+    u1, Y1, u0, Y0 = u1.cpu().numpy(), Y1.cpu().numpy(), u0.cpu().numpy(), Y0.cpu().numpy()
+    assert np.max(np.abs(Y1 - Y0)) <= 1e-12 * np.max(np.abs(Y0))
+    opb = OS.Problem(**kw)
+    for p in range(P):
+        ref = OL.solve_point(opb, x0[p], p)
+        assert abs(u1[p] - ref["u"]) <= 1e-10 * max(1.0, abs(ref["u"]))

@@ -298,10 +298,29 @@ def main():
             F.solve(pb0, x00, ws=ws0)
         torch.cuda.synchronize()
         sec0 = (time.perf_counter() - t0) / 20
+        # the same solve captured once into a HIP graph and replayed with one launch; the graph needs a fixed
+        # number of CG launches per level (a converged point's launches exit at once)
+        it0 = F.solve(pb0, x00, ws=ws0, return_iters=True)[3]
+        pbg0 = F.Problem(d=100, M=512, N=5, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,
+                         gp=(0.4, 0, 0, 0), cg_fixed_iters=max(it0) + 2)
+        cs0 = F.CapturedSolve(pbg0, x00, want_grad=True)
+        for _ in range(3):
+            cs0.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            ug0, _, _ = cs0.launch()
+        torch.cuda.synchronize()
+        secg0 = (time.perf_counter() - t0) / 20
+        ue0 = F.solve(pb0, x00, ws=ws0)[0]
         small["allen_cahn_d100_P1_M512_N5_fp64"] = {"ms_per_solve": round(sec0 * 1e3, 3),
                                                     "points_per_s": round(1.0 / sec0, 1),
+                                                    "graph_replay_ms_per_solve": round(secg0 * 1e3, 3),
+                                                    "graph_cg_launches_per_level": max(it0) + 2,
+                                                    "graph_u_equals_eager": bool((ug0 == ue0).all().item()),
                                                     "bound": "launch latency (a 0.4 MB state)"}
-        log(f"[bench] one point, d = 100: {sec0 * 1e3:.2f} ms per solve")
+        cs0.close()
+        log(f"[bench] one point, d = 100: {sec0 * 1e3:.2f} ms per solve, {secg0 * 1e3:.2f} ms as a HIP graph replay")
         del ws0
         P3, d3, M3 = 128, 10000, 1024
         pb3 = F.Problem(d=d3, M=M3, N=20, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,

@@ -427,6 +427,27 @@ def main():
                            "paper_cpu_s_per_point_context": 2189.28}
         log(f"[bench] literal per-anchor d=1e4 M=200 N=100 P=64: {sec2 * 1e3:.1f} ms")
         del ws2, xl
+        # the shape of the paper's HJ-type runtime table (d = 500, dt = 0.0005, T = 0.5: N = 1000 levels), with
+        # the HJB family f = -|z|^2, g = ln((1 + |x|^2) / 2) standing in for its equation; stored path
+        torch.cuda.empty_cache()
+        hj = {}
+        for Mh in (50, 100):
+            pbh = F.Problem(d=500, M=Mh, N=1000, T=0.5, f_kind=F.F_HJB, fp=(1.0, 0, 0, 0), g_kind=F.G_HJB_LOG,
+                            gp=(1.0, 0, 0, 0), eps_h=1.0, ridge_rel=1e-3, instance=9)
+            xh = torch.zeros((Pl, 500), dtype=torch.float64, device=dev)
+            wsh = torch.empty(F.literal_workspace_size(pbh, Pl, stored=True), dtype=torch.uint8, device=dev)
+            F.solve_literal(pbh, xh, ws=wsh)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uh, sth, _, _ = F.solve_literal(pbh, xh, ws=wsh)
+            torch.cuda.synchronize()
+            sech = time.perf_counter() - t0
+            hj[f"M{Mh}"] = {"value": round(Pl / sech, 3), "unit": "points/s", "ms_per_step": round(sech * 1e3, 3),
+                            "status_nonzero_points": int((sth != 0).sum().item()),
+                            "paper_cpu_s_per_point_context": 89.07 if Mh == 50 else 185.06}
+            log(f"[bench] literal HJB-type d=500 M={Mh} N=1000 P=64: {sech * 1e3:.1f} ms")
+            del wsh, xh
+        literal["hj_shape_d500_N1000"] = hj
         # x-dependent coefficients: geometric family mu = mu0 x, sigma = sigma0 diag(x), the path stored per level
         dg_, Mg, Ng, Pg = 1000, 100, 50, 64
         pbg = F.Problem(d=dg_, M=Mg, N=Ng, T=0.5, f_kind=F.F_HJB, fp=(1.0, 0, 0, 0), g_kind=F.G_HJB_LOG,

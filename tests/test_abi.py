@@ -28,6 +28,9 @@ def test_struct_layout_matches_header():
     # the ctypes mirror of fbsde_problem: 24 + 16 + 8 + 8 + 64 + 8 + 16 + 8 + 8 + 8 + 8 + 8 + 8 = 192 bytes
     assert ctypes.sizeof(N.CProblem) == 192
     assert N.CProblem.seed.offset == 168 and N.CProblem.prec.offset == 184
+    # fbsde_coef: two int32 and four doubles
+    assert ctypes.sizeof(N.CCoef) == 40
+    assert N.CCoef.mu0.offset == 8 and N.CCoef.sigma1.offset == 32
 
 
 @pytest.mark.parametrize("bad", [dict(d=0), dict(M=1), dict(N=0), dict(T=0.0), dict(s=-1.0), dict(f_kind=7),

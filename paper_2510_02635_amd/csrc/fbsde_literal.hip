@@ -314,6 +314,16 @@ constexpr int slot0(int a) {   // first slot of row block a
     return e;
 }
 
+// 1 / x from the hardware reciprocal refined by two Newton steps r <- r + r (1 - x r) (each step squares
+// the relative error), to the last bits of the quotient: shorter than the IEEE division sequence on the
+// per-column critical path.
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 // One elimination step with the pivot in column block JB (a compile-time constant, so that only the
 // slots of blocks JB.. are touched: blocks left of the pivot are finished).  Writes the lanes' share of
 // pivot column jp into cb, waits at the barrier, then updates S_ij -= S_i,jp S_j,jp / S_jp,jp for
@@ -328,7 +338,7 @@ __device__ __forceinline__ double elim_step(double (&v)[E], double* cb, int jp, 
     }
     __syncthreads();
     const double dj = cb[jp];
-    const double inv = 1.0 / dj;
+    const double inv = recip(dj);
     const bool right = tc > jr;
     if constexpr (CACHE) {
         double ci[A], cj[B];
@@ -507,7 +517,7 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
                 }
         }
     }
-    // back substitution D L^T ct = z: ct_j = (z_j - sum_{i > j} u_ij ct_i) / d_j
+    // back substitution D L^T ct = z: ct_j = (z_j - sum_{i > j} u_ij ct_i) / d_j (dg holds 1 / d_j)
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
@@ -517,8 +527,10 @@ k_lit_anchor(const double* __restrict__ G, int M, const double* __restrict__ rho
             if (i == j && i < M) dg[i] = v[slot0<RI, RJ>(a) + b];
         }
     __syncthreads();
+    for (int j = tid; j < M; j += NT) dg[j] = 1.0 / dg[j];   // the pivots' reciprocals, once
+    __syncthreads();
     for (int jp = M - 1; jp >= 0; --jp) {
-        const double cj = rr[jp] / dg[jp];
+        const double cj = rr[jp] * dg[jp];
         if constexpr (RI * RJ <= 512) {
             bsub_dispatch<RI, RJ, A, 0>(jp / RI, v, rr, jp, tr, tc, cj);
         } else if (tr == jp % RI) {

@@ -35,8 +35,10 @@
  *     optional launch timer (events kept once created); the tiled batched schedule creates host
  *     threads, streams and events for the length of a call.
  *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
- *     once it is enqueued, except where stated (CG convergence polling, see fbsde_solve; the
- *     tiled batched schedule and the autotuner return after their work has completed).
+ *     once it is enqueued, except where stated (the optional per-level CG iteration record of
+ *     fbsde_solve, the tape check of fbsde_solve_backward, the tiled batched schedule, the
+ *     autotuner and the diagnostics return after their work has completed).  The CG iterations of
+ *     a level run in one device-side loop, so no call waits for convergence on the host.
  *   - Return value: FBSDE_OK, or a negative code decided on the host before any launch
  *     (FBSDE_EINVAL, FBSDE_ENOSPC) or after a failed launch (FBSDE_EHIP).
  *   - Per-point numerical failures do not stop other points: they are OR-ed into
@@ -75,7 +77,9 @@ enum { FBSDE_G_QUAD = 0,                      /* g = gp0 |x|^2 / d + gp1        
        FBSDE_G_AFFINE = 3,                    /* g = gvec . x + gp0                            */
        FBSDE_G_LOGISTIC = 4 };                /* g = 1 / (1 + exp(-(gvec . x + gp0)))          */
 enum { FBSDE_OK = 0, FBSDE_EINVAL = -1, FBSDE_ENOSPC = -2, FBSDE_EHIP = -3, FBSDE_ESTATE = -4 };
-enum { FBSDE_ST_CG_MAXIT = 1, FBSDE_ST_NEWTON_FLAT = 2, FBSDE_ST_NONFINITE = 4 };
+enum { FBSDE_ST_CG_MAXIT = 1, FBSDE_ST_NEWTON_FLAT = 2, FBSDE_ST_NONFINITE = 4,
+       FBSDE_ST_WAIT_LIMIT = 8 };              /* a bounded device-side wait of the CG loop gave
+                                                 up (internal error: the point's values are void) */
 enum { FBSDE_WS_TAPE = 1 };                   /* workspace flag: keep the tape for the adjoint */
 
 /* Problem descriptor (host memory).  Paper Algorithm 1 takes T, d, M, N, dt = T/N and the
@@ -99,9 +103,9 @@ typedef struct fbsde_problem {
     int32_t cg_maxit;        /* CG iteration cap per level, >= 1                              */
     double cg_rtol;          /* CG stop: |r| <= cg_rtol |b|; FP32C with M <= d + 1 uses at     */
                              /* least 1e-7 (FP32 rounding in the ridge-only null space)        */
-    int32_t cg_fixed_iters;  /* > 0: this many CG launches per level, no host polling (a     */
-                             /* converged point's launches exit at once; a point still not   */
-                             /* converged after them is flagged FBSDE_ST_CG_MAXIT)             */
+    int32_t cg_fixed_iters;  /* > 0: at most this many CG iterations per level (a point not   */
+                             /* converged after them is flagged FBSDE_ST_CG_MAXIT); 0: the cap */
+                             /* is cg_maxit                                                    */
     int32_t shared_dw;       /* 1: the same increments for every evaluation point             */
     uint64_t seed;           /* Philox key                                                     */
     uint32_t instance;       /* PDE instance id, folded into the key                          */
@@ -145,8 +149,10 @@ int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double
  *          keeps the tape that fbsde_solve_backward reads (then do not reuse ws in between)
  *   cg_iters_out  host [N] or NULL: at each level k the largest CG iteration count over the points
  *                 (read back from the device after the level: one extra stream wait per level)
- * Unless cg_fixed_iters > 0, the host waits on the stream every few CG iterations to read the
- * number of points still iterating (so the call returns after the work is done). */
+ * Each level's CG solve is one launch of a device-side loop: work items (iteration, point, chunk of
+ * particle rows) are taken in order from a device counter, a point's next iteration starts when its
+ * chunks' partial sums have been combined, and the point leaves the loop at |r| <= cg_rtol |b| or the
+ * cap.  With cg_iters_out NULL the call returns once the work is enqueued. */
 int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
                 uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, int32_t* cg_iters_out,
                 fbsde_stream stream);
@@ -302,18 +308,28 @@ int fbsde_autotune_reset(void);
  *                                back substitution, system and quadratic-form assembly)
  * fbsde_launch_timer_kinds writes the kinds of the same records.  The events are created on first use
  * and kept for the life of the process.  Thread-safe; the record is process-wide. */
-enum { FBSDE_TIMED_CG_PRODUCT = 0, FBSDE_TIMED_LITERAL_GRAM = 1, FBSDE_TIMED_LITERAL_ANCHORS = 2 };
+enum { FBSDE_TIMED_CG_PRODUCT = 0, FBSDE_TIMED_LITERAL_GRAM = 1, FBSDE_TIMED_LITERAL_ANCHORS = 2,
+       FBSDE_TIMED_CG_LOOP = 3 };   /* the device-side CG loop of one level: its work is not known when
+                                       it is launched (recorded as 0); fbsde_workspace_cg_rows gives the
+                                       rows its products streamed */
 int fbsde_launch_timer(int32_t on);
 int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n);
 int fbsde_launch_timer_kinds(int32_t* kinds, int64_t cap, int64_t* n);
+
+/* Diagnostic: the particle rows that the CG products of the per-point path have streamed since the
+ * start of the last fbsde_solve on this workspace (its backward pass included).  One row of a point is
+ * d elements of the state, so rows x d x element bytes is the algorithmic read traffic of those
+ * products.  ws: the device workspace of that solve; *rows host; synchronises the stream. */
+int fbsde_workspace_cg_rows(const void* ws, int64_t* rows, fbsde_stream stream);
 
 /* Captured solve, for callers that repeat one solve with the same problem, sizes and buffers
  * (serving loops, parameter sweeps that rewrite x0 in place): the launch sequence of fbsde_solve
  * (flags as there) is captured once into a HIP graph on a private stream that waits for `stream`,
  * and fbsde_graph_launch replays it with a single launch.  The graph binds every pointer given here
  * and in pb (mu, gvec): a replay reads x0 and writes u, grad, status and ws at these addresses, so
- * they must stay allocated until fbsde_graph_destroy.  The per-point form needs cg_fixed_iters > 0
- * (FBSDE_EINVAL otherwise: no host polling can run inside a graph); the shared form has no CG.
+ * they must stay allocated until fbsde_graph_destroy.  Every level's CG solve is one device-side
+ * loop, so any descriptor can be captured (with FBSDE_CG_HOST_LOOP=1 in the environment, the host-
+ * polled diagnostic loop, the per-point form needs cg_fixed_iters > 0).
  * Status words and flags are cleared by kernels, so no memset node enters the graph.  Nothing is
  * launched by the capture itself. */
 typedef struct fbsde_graph_s* fbsde_graph;

@@ -8,7 +8,7 @@ F64, F32C = 0, 1
 F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS = 0, 1, 2, 3
 G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC = 0, 1, 2, 3, 4
 OK, EINVAL, ENOSPC, EHIP, ESTATE = 0, -1, -2, -3, -4
-ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
+ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE, ST_WAIT_LIMIT = 1, 2, 4, 8
 WS_TAPE = 1
 
 EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
@@ -16,6 +16,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
             "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
+            "fbsde_workspace_cg_rows",
             "fbsde_literal_workspace_size", "fbsde_literal_workspace_size_stored", "fbsde_literal_coef_workspace_size",
             "fbsde_solve_literal_coef",
             "fbsde_solve_literal", "fbsde_strerror")
@@ -95,6 +96,7 @@ def load():
     lib.fbsde_launch_timer.argtypes = [i32]
     lib.fbsde_launch_timer_read.argtypes = [vp, vp, i64, P(i64)]
     lib.fbsde_launch_timer_kinds.argtypes = [vp, i64, P(i64)]
+    lib.fbsde_workspace_cg_rows.argtypes = [vp, P(i64), vp]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
                                ctypes.c_double, vp]
     lib.fbsde_cholesky_workspace.argtypes = [i32, i64, i64]
@@ -121,6 +123,7 @@ def load():
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
                  "fbsde_launch_timer_read", "fbsde_launch_timer_kinds", "fbsde_literal_coef_workspace_size",
+                 "fbsde_workspace_cg_rows",
                  "fbsde_literal_workspace_size_stored",
                  "fbsde_solve_literal_coef",
                  "fbsde_solve_literal"):

@@ -137,10 +137,11 @@ def solve(pb, x0, want_grad=True, tape=False, ws=None, return_iters=False):
     st = torch.empty(P, dtype=torch.int32, device=dev)
     if ws is None:
         ws = workspace(pb, P, tape=tape, device=dev)
-    iters = (ctypes.c_int32 * pb.N)()
+    # the per-level iteration record makes the library wait for each level: only asked for on request
+    iters = (ctypes.c_int32 * pb.N)() if return_iters else None
     N.check(N.load().fbsde_solve(ctypes.byref(pb.c()), P, x0.data_ptr(), u.data_ptr(), _ptr(grad), st.data_ptr(),
                                  ws.data_ptr(), ws.numel(), N.WS_TAPE if tape else 0,
-                                 ctypes.cast(iters, ctypes.c_void_p), _stream()))
+                                 ctypes.cast(iters, ctypes.c_void_p) if return_iters else None, _stream()))
     if return_iters:
         return u, grad, st, list(iters)
     return u, grad, st
@@ -158,10 +159,11 @@ def solve_backward(pb, x0, u_bar, ws, return_iters=False):
     gp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
     fp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
     st = torch.zeros(P, dtype=torch.int32, device=dev)
-    iters = (ctypes.c_int32 * pb.N)()
+    iters = (ctypes.c_int32 * pb.N)() if return_iters else None
     N.check(N.load().fbsde_solve_backward(ctypes.byref(pb.c()), P, x0.data_ptr(), u_bar.data_ptr(),
                                           x0_bar.data_ptr(), gp_bar.data_ptr(), fp_bar.data_ptr(), st.data_ptr(),
-                                          ws.data_ptr(), ws.numel(), ctypes.cast(iters, ctypes.c_void_p), _stream()))
+                                          ws.data_ptr(), ws.numel(),
+                                          ctypes.cast(iters, ctypes.c_void_p) if return_iters else None, _stream()))
     if return_iters:
         return x0_bar, gp_bar, fp_bar, st, list(iters)
     return x0_bar, gp_bar, fp_bar, st
@@ -193,7 +195,15 @@ def launch_timer(on):
     N.check(N.load().fbsde_launch_timer(1 if on else 0))
 
 
-TIMED_CG_PRODUCT, TIMED_LITERAL_GRAM, TIMED_LITERAL_ANCHORS = 0, 1, 2
+TIMED_CG_PRODUCT, TIMED_LITERAL_GRAM, TIMED_LITERAL_ANCHORS, TIMED_CG_LOOP = 0, 1, 2, 3
+
+
+def workspace_cg_rows(ws):
+    """Particle rows streamed by the CG products since the start of the last solve on this workspace
+    (its backward pass included); rows x d x element bytes is their algorithmic read traffic."""
+    out = ctypes.c_int64(0)
+    N.check(N.load().fbsde_workspace_cg_rows(ws.data_ptr(), ctypes.byref(out), _stream()))
+    return int(out.value)
 
 
 def launch_timer_kinds():
@@ -382,7 +392,8 @@ class CapturedSolve:
     """A solve captured once into a HIP graph (fbsde_graph_capture) and replayed with one launch.
 
     The graph is bound to this object's tensors: write new points into `x0` in place, call `launch()`,
-    read `u`, `grad`, `status`.  The per-point form needs `pb.cg_fixed_iters > 0`.
+    read `u`, `grad`, `status`.  Each level's CG solve is one device-side loop, so any descriptor can be
+    captured.
     """
 
     def __init__(self, pb, x0, want_grad=True, tape=False):

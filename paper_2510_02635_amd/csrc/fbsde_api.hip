@@ -4,8 +4,10 @@
 #include "fbsde_host.hpp"
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
+#include "fbsde_cgloop.hpp"
 
 #include <atomic>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <new>
@@ -85,11 +87,17 @@ bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk) {
 namespace {
 
 struct WS {
+    CgCtl* ctl;     // device-side CG loop control (offset 0 of the workspace)
     void* W;
     double *Ya, *Yb, *rn2, *w, *c2;
     double *x, *r, *pv, *qv, *Wbar;
     double *part1, *part2, *part3, *psc, *scal;
     int *iscal, *active;
+    int* cnt;       // CG arrival counters [P][ncnt]
+    int ncnt;
+    unsigned long long* queue;   // CG work queues [nq][qcap]
+    int nq;
+    int64_t qcap;
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
     int* tag;
@@ -97,7 +105,9 @@ struct WS {
     double *G, *cbar, *adj;
 };
 
-// Carve the workspace (base == nullptr: only count).  Returns bytes.
+// Carve the workspace (base == nullptr: only count).  Returns bytes.  The loop control comes first and
+// the buffers whose size depends on the chunk count (partials, arrival counters) last, so that the tape
+// keeps its place whatever launch shape a later call takes.
 size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
@@ -107,6 +117,7 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     };
     const size_t PM = (size_t)P * pl.M, PL = (size_t)P * pl.ld;
     const size_t parts = (size_t)P * pl.nchunk * pl.ld;
+    ws.ctl = (CgCtl*)take(sizeof(CgCtl));
     ws.W = take(PM * pl.ld * pl.esz);
     ws.Ya = (double*)take(PM * 8);
     ws.Yb = (double*)take(PM * 8);
@@ -118,10 +129,6 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     ws.pv = (double*)take(PL * 8);
     ws.qv = (double*)take(PL * 8);
     ws.Wbar = (double*)take(PL * 8);
-    ws.part1 = (double*)take(parts * 8);
-    ws.part2 = (double*)take(parts * 8);
-    ws.part3 = (double*)take(parts * 8);
-    ws.psc = (double*)take((size_t)P * pl.nchunk * 4 * 8);
     ws.scal = (double*)take((size_t)P * NS * 8);
     ws.iscal = (int*)take((size_t)P * 4 * 4);
     ws.active = (int*)take(64);
@@ -139,6 +146,15 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
         ws.cbar = (double*)take(PM * 8);
         ws.adj = (double*)take((size_t)P * 16 * 8);
     }
+    ws.part1 = (double*)take(parts * 8);
+    ws.part2 = (double*)take(parts * 8);
+    ws.part3 = (double*)take(parts * 8);
+    ws.psc = (double*)take((size_t)P * pl.nchunk * 4 * 8);
+    ws.ncnt = std::max(1, cg_tree_counters(pl.nchunk));
+    ws.cnt = (int*)take((size_t)P * ws.ncnt * 4);
+    ws.nq = (int)std::min<int64_t>(CG_MAXQ, std::max<int64_t>(P, 1));
+    ws.qcap = (P + ws.nq - 1) / ws.nq * (int64_t)pl.nchunk;
+    ws.queue = (unsigned long long*)take((size_t)ws.nq * ws.qcap * 8);
     return off;
 }
 
@@ -177,9 +193,59 @@ int fold_parts(const Plan& pl, int64_t P, double* a, double* b, double* c, hipSt
     return 1;
 }
 
+// The CG solve of a level as one launch of the device-side loop (fbsde_cgloop.hpp): every iteration of
+// every point, no host round trip.  The loop's grid is what the chip holds at once (more blocks would only
+// take tickets later); the wait bound is two seconds of the device's wall clock.
+template <typename S, typename R>
+int run_cg_device(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
+                  const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
+    const int fixed = pb->cg_fixed_iters;
+    const int cap = (fixed > 0) ? fixed : pb->cg_maxit;
+    int dev = 0, ncu = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+        err = FBSDE_EHIP;
+        return 0;
+    }
+    const uint64_t wait_ticks = (uint64_t)std::max(khz, 1000) * 2000ull;
+    const int64_t ncnt_total = P * (int64_t)ws.ncnt, nitems = P * (int64_t)pl.nchunk;
+    const int64_t nslots = ws.nq * ws.qcap;
+    hipLaunchKernelGGL(k_cg_arm,
+                       dim3((unsigned)std::min<int64_t>((std::max({ncnt_total, nslots, P}) + 255) / 256, 1024)),
+                       dim3(256), 0, st, ws.ctl, ws.queue, ws.nq, ws.qcap, pl.nchunk, ws.cnt, ncnt_total, ws.iscal, P,
+                       0);
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_cg_loop<S, R, QQ, TT>),
+                                                         Geo<QQ, TT>::BS, 0) != hipSuccess)
+            per_cu = 1;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)std::max(per_cu, 1) * ncu));
+        const long tl = lt_begin(st, 0.0, FBSDE_TIMED_CG_LOOP);
+        hipLaunchKernelGGL((k_cg_loop<S, R, QQ, TT>), dim3((unsigned)grid), dim3(Geo<QQ, TT>::BS), 0, st, W, ldw,
+                           (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, Wbar, ws.x, ws.r, ws.pv, ws.qv,
+                           ws.scal, NS, ws.iscal, ws.part1, ws.psc, ws.ctl, ws.queue, ws.nq, ws.qcap, ws.active,
+                           ws.cnt, ws.ncnt, cg_rtol_of(pb) * cg_rtol_of(pb), std::min(cap, pb->cg_maxit), status,
+                           wait_ticks);
+        lt_end(tl, st);
+    });
+    hipLaunchKernelGGL(k_cg_check, dim3((unsigned)std::min<int64_t>((P + 255) / 256, 1024)), dim3(256), 0, st,
+                       ws.ctl, ws.iscal, P, (int64_t)pl.M, status);
+    err = last_error();
+    return cap;
+}
+
+// The host-driven loop: three launches per iteration and a poll of the active-point count every eight
+// (kept as a diagnostic alternative, selected by the environment variable FBSDE_CG_HOST_LOOP=1).
+bool host_cg_loop() {
+    const char* e = std::getenv("FBSDE_CG_HOST_LOOP");
+    return e && e[0] == '1';
+}
+
 template <typename S, typename R = S>
 int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
            const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
+    if (!host_cg_loop()) return run_cg_device<S, R>(pb, pl, P, W, ldw, w, Wbar, ws, status, st, err);
     const int fixed = pb->cg_fixed_iters;
     const int cap = (fixed > 0) ? fixed : pb->cg_maxit;
     const int poll = 8;
@@ -301,6 +367,9 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
     const int64_t ldw = pl.ld;
     const int64_t PM = P * pl.M, PL = P * (int64_t)pl.ld;
     clear_status(status, P, st);
+    // the count of particle rows streamed by CG products starts again with every solve
+    hipLaunchKernelGGL(k_cg_arm, dim3(1), dim3(64), 0, st, ws.ctl, nullptr, 0, (int64_t)0, 1, nullptr, (int64_t)0,
+                       nullptr, (int64_t)0, 1);
     double* Ycur = ws.Ya;
     double* Yk = ws.Yb;
     launch_forward<S>(pb, pl, P, x0, W, ldw, Ycur, ws.rn2, status, st);
@@ -888,6 +957,17 @@ int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n) {
     return FBSDE_OK;
 }
 
+int fbsde_workspace_cg_rows(const void* ws, int64_t* rows, fbsde_stream stream) {
+    if (!ws || !rows) return FBSDE_EINVAL;
+    unsigned long long v = 0;
+    const CgCtl* ctl = (const CgCtl*)ws;   // the loop control sits at offset 0 of the per-point workspace
+    if (hipMemcpyAsync(&v, &ctl->rows, sizeof(v), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return FBSDE_EHIP;
+    *rows = (int64_t)v;
+    return FBSDE_OK;
+}
+
 int fbsde_launch_timer_kinds(int32_t* kinds, int64_t cap, int64_t* n) {
     if (!n || cap < 0 || (cap > 0 && !kinds)) return FBSDE_EINVAL;
     std::lock_guard<std::mutex> lk(g_lt_mu);
@@ -919,7 +999,8 @@ int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, do
     *out = nullptr;
     int rc = check_problem(pb, P);
     if (rc) return rc;
-    if (!pb->shared_dw && pb->cg_fixed_iters <= 0) return FBSDE_EINVAL;   // no host polling inside a graph
+    // the host-driven CG loop (a diagnostic alternative) polls the device, which a graph cannot do
+    if (!pb->shared_dw && pb->cg_fixed_iters <= 0 && host_cg_loop()) return FBSDE_EINVAL;
     if (!x0 || !u || !status || !ws || P < 1) return FBSDE_EINVAL;
     size_t need = 0;
     if ((rc = fbsde_workspace_size(pb, P, flags, &need))) return rc;

@@ -21,6 +21,12 @@ def problems(device="cuda", mu=None, gvec=None, **kw):
 
 
 def rel_err(a, b):
+    """The larger of the norm-wise relative error |a - b| / |b| and the element-wise one,
+    max_i |a_i - b_i| / max_i |b_i|: a tolerance on it bounds every element, not only the norm."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    if b.size == 0:
+        return 0.0
+    norm = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    elem = float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+    return max(norm, elem)

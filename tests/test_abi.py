@@ -68,9 +68,11 @@ def test_missing_gvec_and_tiny_workspace():
     assert rc == N.ENOSPC
 
 
-def test_graph_capture_needs_fixed_cg_launches():
-    # the per-point form polls the host between CG launches unless cg_fixed_iters > 0: refused before any
-    # HIP call, so this runs without a GPU
+def test_graph_capture_refuses_the_host_polled_loop(monkeypatch):
+    # with the diagnostic host-polled CG loop selected, the per-point form polls the host between CG launches
+    # unless cg_fixed_iters > 0: refused before any HIP call, so this runs without a GPU (the default
+    # device-side loop captures any descriptor)
+    monkeypatch.setenv("FBSDE_CG_HOST_LOOP", "1")
     pb = F.Problem(d=8, M=64, N=2, T=0.3)
     h = ctypes.c_void_p()
     rc = N.load().fbsde_graph_capture(ctypes.byref(pb.c()), 2, 1, 1, None, 1, 1, 1 << 30, 0, ctypes.byref(h), None)

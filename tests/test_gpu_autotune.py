@@ -85,18 +85,32 @@ def test_kernel_timer_and_read_ceiling(prec):
         assert t > 0
 
 
-def test_launch_timer_records_every_cg_product():
+def test_launch_timer_records_every_cg_product(monkeypatch):
     hp, _ = problems(d=300, M=256, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
                      gp=(0.4, 0, 0, 0))
     xt = torch.tensor(workloads.points("normal:0.3", 4, 300, 2), device=DEV)
     ws = F.workspace(hp, 4)
     F.solve(hp, xt, ws=ws)
     torch.cuda.synchronize()
+    # the device-side loop: one timed launch per level, whose work is the rows its products streamed
     F.launch_timer(True)
     _, _, st, iters = F.solve(hp, xt, ws=ws, return_iters=True)
     F.launch_timer(False)
     ms, nb = F.launch_timer_read(with_bytes=True)
-    _say(f"[launch timer] {ms.size} launches for per-level iterations {iters}, mean {ms.mean():.4f} ms")
+    rows = F.workspace_cg_rows(ws)
+    _say(f"[launch timer] {ms.size} loop launches for per-level iterations {iters}, mean {ms.mean():.4f} ms, "
+         f"{rows} rows streamed")
+    assert ms.size == 3 and np.all(F.launch_timer_kinds() == F.TIMED_CG_LOOP) and np.all(nb == 0)
+    assert 256 * sum(iters) <= rows <= 4 * 256 * sum(iters)
+    assert np.all(ms > 0) and int(st.abs().sum().item()) == 0
+    # the host-polled loop: one record per product
+    monkeypatch.setenv("FBSDE_CG_HOST_LOOP", "1")
+    F.launch_timer(True)
+    _, _, st, iters = F.solve(hp, xt, ws=ws, return_iters=True)
+    F.launch_timer(False)
+    monkeypatch.delenv("FBSDE_CG_HOST_LOOP")
+    ms, nb = F.launch_timer_read(with_bytes=True)
+    _say(f"[launch timer] {ms.size} product launches for per-level iterations {iters}, mean {ms.mean():.4f} ms")
     assert np.all(nb == 4 * 256 * 300 * 8)   # points x particles x d x FP64 bytes
     # the host loop polls every 8 iterations, so each level launches at most 7 more products than it needs
     assert sum(iters) <= ms.size <= sum(iters) + 7 * len(iters)

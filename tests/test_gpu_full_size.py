@@ -7,7 +7,9 @@ properties that hold at any size where the oracle is too slow.
       oracle on points 0 and 1023.
   C2  uneven HJB instances (T=1, N=20, FP32C): the smallest-M instance of the d = 100, 500, 1000 classes
       against the oracle; the largest (d, M) of the d = 5000 and 10^4 classes through the batched call
-      equal, bit for bit, to the single-instance solve of the same points (one tile each).
+      equal, bit for bit, to the single-instance solve of the same points (one tile each); the nearly
+      square designs (d = 5000 with M = 4800 and 5376, d = 10^4 with M = 8192) at two levels, forward and
+      adjoint, against the oracle.
   C3  d=10^4, 128 points x0 ~ N(0, I/d), T=0.3, N=20, M=1024, Allen-Cahn: forward + adjoint in FP32C and
       FP64 against the oracle's reverse mode on point 0.
   C4  shared increments, d=10^4, 4096 points, M=2048, N=20, T=0.3, Allen-Cahn, FP32C: the forward against
@@ -122,6 +124,34 @@ def test_c2_instances_full_size():
         torch.cuda.synchronize()
         assert torch.equal(us[i], u1) and torch.equal(gs[i], g1) and torch.equal(sts[i], st1)
         assert int((st1 != 0).sum().item()) == 0
+
+
+@pytest.mark.parametrize("d,M", [(5000, 4800), (5000, 5376), (10000, 8192)])
+def test_c2_near_square_instances_against_oracle(d, M):
+    # The nearly square designs of the uneven HJB set (FP32C, T = 1), where CG needs the most iterations and
+    # FP32 rounding in CG matters most, at their full d and M through the batched forward and forward +
+    # adjoint calls, on 4 points; the oracle's cost bounds the levels to N = 2 (the per-level shape the batch
+    # runs 20 times).  Point 0 against the oracle's reverse mode, u and grad u and x0_bar at the FP32C bar.
+    it = next(i for i in workloads.batched_instances(64) if i["d"] == d and i["M"] == M)
+    P, N = 4, 2
+    hp, op = problems(d=d, M=M, N=N, T=1.0, f_kind=F.F_HJB, fp=(it["lam"], 0, 0, 0), g_kind=F.G_HJB_LOG,
+                      gp=(1.0, 0, 0, 0), prec=F.F32C, seed=0, instance=it["instance"])
+    x = workloads.points("uniform", P, d, seed=100 + it["instance"])
+    xt = torch.tensor(x, device=DEV)
+    ub = torch.ones(P, dtype=torch.float64, device=DEV)
+    _say(f"[C2 near-square] d={d} M={M} P={P} N={N} fp32c batched forward and forward + adjoint")
+    us, gs, sts = F.solve_batched([hp], [xt])
+    ub_, xbs, gps, fps, sts2 = F.solve_batched_backward([hp], [xt], [ub])
+    torch.cuda.synchronize()
+    u, g, xb = us[0].cpu().numpy(), gs[0].cpu().numpy(), xbs[0].cpu().numpy()
+    assert int((sts[0] != 0).sum().item()) == 0 and int((sts2[0] != 0).sum().item()) == 0
+    assert torch.allclose(ub_[0], us[0], rtol=1e-12, atol=0)
+    ref = OS.adjoint_point(op, x[0], 0, ubar=1.0)
+    eu = abs(u[0] - ref["u"]) / abs(ref["u"])
+    eg = rel_err(g[0], ref["grad"])
+    ex = rel_err(xb[0], ref["x0bar"])
+    _say(f"  p=0 rel_u={eu:.2e} rel_grad={eg:.2e} rel_x0bar={ex:.2e}")
+    assert eu <= 1e-5 and eg <= 1e-5 and ex <= 1e-5
 
 
 def test_c3_forward_adjoint_full_size():

@@ -208,10 +208,13 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
 /* Many evaluation points of many PDE instances (uneven d, M, f, g, N, precision) in one call
  * (batching over points and instances goes beyond the paper; the per-point chain is Algorithm 1).
  * Two schedules, chosen by opts->mode:
- *  FBSDE_BATCH_TILED (default): the work items are (instance, point-tile) pairs, largest first.  Each
- *    tile runs the whole chain through the multi-block path of fbsde_solve (each point split over
- *    many workgroups along its particle rows) on one of `streams` HIP streams, each owned by a host
- *    worker thread with its own workspace arena, so tiles of different instances overlap on the chip.
+ *  FBSDE_BATCH_TILED (default): the work items are (instance, point-tile) pairs.  Each tile runs the
+ *    whole chain through the multi-block path of fbsde_solve (each point split over many workgroups
+ *    along its particle rows, every level's CG on the device) on one of `streams` HIP streams, each fed
+ *    by a host worker thread with its own workspace arena, so tiles of different instances overlap on
+ *    the chip.  The tiles are dealt to the streams before any is enqueued: largest expected time first
+ *    (state bytes x levels x estimated passes, the CG count estimated from the design's condition),
+ *    each to the stream with the least expected time so far.
  *    A tile holds as many points as fit `tile_bytes` of workspace (at least one, at most 65535), so
  *    memory is bounded by the tiles in flight, not by the batch.  Tile i of an instance covers its
  *    points [p0, p0 + np) with point_base + p0: results equal fbsde_solve of the whole instance up to
@@ -225,7 +228,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
  *   P       host [n_inst] point counts (>= 0)
  *   x0, u, grad, status   host arrays of n_inst device pointers ([P_i][d_i], [P_i], [P_i][d_i] or
  *                         NULL, [P_i]); grad itself may be NULL
- *   opts    NULL for the defaults (tiled, 4 streams, 8 GiB tiles, 512 persistent slots)
+ *   opts    NULL for the defaults (tiled, 4 streams, 24 GiB tiles, 512 persistent slots)
  *   ws      device workspace of fbsde_batched_workspace_size(pbs, n_inst, P, opts, adjoint) bytes
  * The tiled schedule waits for the caller's stream, returns after all tiles have completed, and
  * needs the calling thread's current device to be the one holding the buffers; the persistent one
@@ -234,7 +237,7 @@ enum { FBSDE_BATCH_TILED = 0, FBSDE_BATCH_PERSISTENT = 1 };
 typedef struct fbsde_batch_opts {
     int32_t mode;         /* FBSDE_BATCH_TILED or FBSDE_BATCH_PERSISTENT                 */
     int32_t streams;      /* tiled: concurrent streams / worker threads, 1..8 (0: 4)     */
-    int64_t tile_bytes;   /* tiled: workspace cap of one tile in bytes (0: 8 GiB)        */
+    int64_t tile_bytes;   /* tiled: workspace cap of one tile in bytes (0: 24 GiB)       */
     int32_t max_slots;    /* persistent: workgroups (points in flight) per class (0: 512) */
     int32_t reserved;     /* must be 0                                                   */
 } fbsde_batch_opts;
@@ -254,6 +257,14 @@ int fbsde_solve_batched_backward(const fbsde_problem* pbs, int64_t n_inst, const
                                  double* const* x0_bar, double* const* gp_bar, double* const* fp_bar,
                                  uint32_t* const* status, const fbsde_batch_opts* opts, void* ws,
                                  size_t ws_bytes, fbsde_stream stream);
+
+/* Diagnostic: the algorithmic bytes that the CG products of the last tiled batched call (forward, or
+ * forward + reverse with adjoint = 1) on this workspace streamed: for every product, the particle rows of
+ * the points still iterating x d x element bytes (per-point tiles; shared-increment tiles have no CG).
+ * pbs, n_inst, P, opts, adjoint: as in that call;  ws: its workspace;  *bytes host;  synchronises. */
+int fbsde_batched_cg_bytes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                           const fbsde_batch_opts* opts, int32_t adjoint, const void* ws, double* bytes,
+                           fbsde_stream stream);
 
 /* Dense helpers of the shared-increment form, exported for verification and reuse.
  * fbsde_gemm: C = alpha * A op(B) + beta * C on the matrix cores (v_mfma 16x16x4, FP64 or FP32

@@ -364,6 +364,17 @@ def solve_batched(problems, x0s, want_grad=True, mode="tiled", streams=4, tile_b
     return us, grads, sts
 
 
+def batched_cg_bytes(problems, x0s, ws, adjoint=False, streams=4, tile_bytes=0):
+    """Algorithmic bytes the CG products of the last tiled batched call on `ws` streamed (same problems, x0
+    shapes and options as that call)."""
+    n, cps, Ps = _batch_common(problems, x0s)
+    opts = _batch_opts("tiled", streams, tile_bytes, 512)
+    out = ctypes.c_double(0.0)
+    N.check(N.load().fbsde_batched_cg_bytes(cps, n, ctypes.cast(Ps, ctypes.c_void_p), ctypes.byref(opts),
+                                            1 if adjoint else 0, ws.data_ptr(), ctypes.byref(out), _stream()))
+    return float(out.value)
+
+
 def solve_batched_backward(problems, x0s, u_bars, streams=4, tile_bytes=0, ws=None):
     """Batched forward + reverse mode: per instance u [P_i], x0_bar [P_i][d_i], gp_bar [4], fp_bar [4], status."""
     n, cps, Ps = _batch_common(problems, x0s)

@@ -230,7 +230,7 @@ int run_cg_device(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W
         lt_end(tl, st);
     });
     hipLaunchKernelGGL(k_cg_check, dim3((unsigned)std::min<int64_t>((P + 255) / 256, 1024)), dim3(256), 0, st,
-                       ws.ctl, ws.iscal, P, (int64_t)pl.M, status);
+                       ws.ctl, ws.iscal, P, (int64_t)pl.M, (int64_t)pl.d * (int64_t)pl.esz, status);
     err = last_error();
     return cap;
 }
@@ -362,14 +362,15 @@ void clear_status_impl(uint32_t* status, int64_t P, hipStream_t st) {
 
 template <typename S>
 int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, double* u, double* grad,
-               uint32_t* status, WS& ws, bool tape, int32_t* cg_iters_out, hipStream_t st) {
+               uint32_t* status, WS& ws, bool tape, int32_t* cg_iters_out, hipStream_t st, bool reset_counts = true) {
     S* W = (S*)ws.W;
     const int64_t ldw = pl.ld;
     const int64_t PM = P * pl.M, PL = P * (int64_t)pl.ld;
     clear_status(status, P, st);
-    // the count of particle rows streamed by CG products starts again with every solve
+    // the count of particle rows streamed by CG products starts again with every solve (a batched tile
+    // after the first on its arena adds to the count instead)
     hipLaunchKernelGGL(k_cg_arm, dim3(1), dim3(64), 0, st, ws.ctl, nullptr, 0, (int64_t)0, 1, nullptr, (int64_t)0,
-                       nullptr, (int64_t)0, 1);
+                       nullptr, (int64_t)0, reset_counts ? 1 : 0);
     double* Ycur = ws.Ya;
     double* Yk = ws.Yb;
     launch_forward<S>(pb, pl, P, x0, W, ldw, Ycur, ws.rn2, status, st);
@@ -708,9 +709,14 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
 }
 
-int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
-                         double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
-                         int32_t* cg_iters_out, fbsde_stream stream) {
+}  // extern "C"
+
+namespace {
+// The reverse mode; check_tape: read the tape's tag back first (one stream wait) and refuse a workspace
+// whose tape does not belong to this problem.
+int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
+                   double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
+                   int32_t* cg_iters_out, fbsde_stream stream, bool check_tape) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
     Plan pl;
@@ -732,14 +738,55 @@ int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, c
     if (carve(pl, P, FBSDE_WS_TAPE, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, FBSDE_WS_TAPE, (char*)wsp, ws);
     hipStream_t st = (hipStream_t)stream;
-    int tag = 0;
-    if (hipMemcpyAsync(&tag, ws.tag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return FBSDE_EHIP;
-    if (tag != tape_tag(pb, P)) return FBSDE_ESTATE;
+    if (check_tape) {
+        int tag = 0;
+        if (hipMemcpyAsync(&tag, ws.tag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return FBSDE_EHIP;
+        if (tag != tape_tag(pb, P)) return FBSDE_ESTATE;
+    }
     if (pb->prec == FBSDE_F64)
         return backward_impl<double>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, cg_iters_out, st);
     return backward_impl<float>(pb, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, cg_iters_out, st);
+}
+}  // namespace
+
+namespace fbsde {
+namespace host {
+int solve_tile(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
+               void* wsp, size_t ws_bytes, int32_t flags, bool reset_counts, hipStream_t st) {
+    if (pb->shared_dw || P == 0)
+        return fbsde_solve(pb, P, x0, u, grad, status, wsp, ws_bytes, flags, nullptr, (fbsde_stream)st);
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, flags, (char*)wsp, ws);
+    const bool tape = (flags & FBSDE_WS_TAPE) != 0;
+    if (pb->prec == FBSDE_F64)
+        return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, tape, nullptr, st, reset_counts);
+    return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, tape, nullptr, st, reset_counts);
+}
+
+int solve_backward_after_forward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar,
+                                 double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, void* ws,
+                                 size_t ws_bytes, hipStream_t st) {
+    return backward_entry(pb, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, ws_bytes, nullptr,
+                          (fbsde_stream)st, false);
+}
+}  // namespace host
+}  // namespace fbsde
+
+extern "C" {
+
+int fbsde_solve_backward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
+                         double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
+                         int32_t* cg_iters_out, fbsde_stream stream) {
+    return backward_entry(pb, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, wsp, ws_bytes, cg_iters_out, stream,
+                          true);
 }
 
 int fbsde_normals(const fbsde_problem* pb, int64_t p, int32_t k, int64_t j0, int64_t rows, double* out,
@@ -956,6 +1003,16 @@ int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n) {
     *n = k;
     return FBSDE_OK;
 }
+
+}  // extern "C"
+
+namespace fbsde {
+namespace host {
+unsigned long long* cg_bytes_counter(void* ws) { return &((CgCtl*)ws)->bytes; }
+}  // namespace host
+}  // namespace fbsde
+
+extern "C" {
 
 int fbsde_workspace_cg_rows(const void* ws, int64_t* rows, fbsde_stream stream) {
     if (!ws || !rows) return FBSDE_EINVAL;

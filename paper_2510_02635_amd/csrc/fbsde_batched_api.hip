@@ -116,11 +116,25 @@ int read_opts(const fbsde_batch_opts* o, Opts& r) {
     r.mode = o ? o->mode : FBSDE_BATCH_TILED;
     r.streams = (o && o->streams) ? o->streams : 4;
     r.max_slots = (o && o->max_slots) ? o->max_slots : 512;
-    r.tile_bytes = (o && o->tile_bytes) ? (size_t)o->tile_bytes : ((size_t)8 << 30);
+    r.tile_bytes = (o && o->tile_bytes) ? (size_t)o->tile_bytes : ((size_t)24 << 30);
     if (r.mode != FBSDE_BATCH_TILED && r.mode != FBSDE_BATCH_PERSISTENT) return FBSDE_EINVAL;
     if (r.streams < 1 || r.streams > 8 || r.max_slots < 1 || (o && o->tile_bytes < 0)) return FBSDE_EINVAL;
     if (o && o->reserved != 0) return FBSDE_EINVAL;
     return FBSDE_OK;
+}
+
+// Expected time of a tile, in state bytes streamed: per level the moments pass, the reversal (read and
+// write) and the CG products.  The CG iteration count is estimated from the condition number of the
+// centred ridge system of an isotropic cloud: the Marchenko-Pastur edges (1 -+ sqrt(r))^2 with
+// r = min(d, M) / max(d, M), the smallest eigenvalue held above the ridge (relative to the spread s^2 t of
+// the cloud); CG reaches a relative residual rtol in about sqrt(kappa) ln(2 / rtol) / 2 iterations.
+double tile_cost(const fbsde_problem& pb, const Plan& pl, int64_t m) {
+    const double r = (double)std::min(pb.d, pb.M) / (double)std::max(pb.d, pb.M);
+    const double hi = (1.0 + std::sqrt(r)) * (1.0 + std::sqrt(r));
+    const double lo = std::max((1.0 - std::sqrt(r)) * (1.0 - std::sqrt(r)), std::max(pb.ridge_rel, 1e-6));
+    const double rtol = std::max(cg_rtol_of(&pb), 1e-16);
+    const double iters = std::min((double)pb.cg_maxit, 3.0 + 0.5 * std::sqrt(hi / lo) * std::log(2.0 / rtol));
+    return (double)m * (double)pb.M * (double)pl.ld * (double)pl.esz * (double)pb.N * (3.0 + iters);
 }
 
 // Point tiles of every instance: the largest tile whose workspace fits the arena cap (at least one
@@ -154,14 +168,28 @@ int plan_tiles(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const
             const int64_t m = std::min<int64_t>(np, P[i] - p0);
             if ((rc = ws_of(m, b))) return rc;
             arena = std::max(arena, (size_t)round_up((int64_t)b, 256));
-            units.push_back(TileUnit{(int)i, p0, m, (double)m * (double)pbs[i].M * (double)pl.ld * (double)pl.esz});
+            units.push_back(TileUnit{(int)i, p0, m, tile_cost(pbs[i], pl, m)});
         }
     }
     std::stable_sort(units.begin(), units.end(), [](const TileUnit& a, const TileUnit& b) { return a.cost > b.cost; });
     return FBSDE_OK;
 }
 
-size_t tiled_header_bytes(size_t n_units) { return (size_t)round_up((int64_t)(n_units * 8 * sizeof(double)), 256); }
+// Header of the tiled schedule's workspace: per tile its 8 parameter adjoints, then one counter per stream
+// of the algorithmic bytes its tiles' CG products streamed.
+size_t tiled_header_bytes(size_t n_units) {
+    return (size_t)round_up((int64_t)(n_units * 8 * sizeof(double) + 8 * sizeof(unsigned long long)), 256);
+}
+unsigned long long* tiled_cg_counters(char* base, size_t n_units) {
+    return (unsigned long long*)(base + n_units * 8 * sizeof(double));
+}
+
+__global__ void k_zero_u64(unsigned long long* a, int n) {
+    if (threadIdx.x < n) a[threadIdx.x] = 0ull;
+}
+__global__ void k_add_u64(unsigned long long* acc, const unsigned long long* v) {
+    if (threadIdx.x == 0) *acc += *v;
+}
 
 int tiled_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const Opts& o, int32_t flags,
                size_t* bytes, std::vector<TileUnit>* keep = nullptr, size_t* arena_out = nullptr, int* nw_out = nullptr) {
@@ -218,13 +246,26 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
     }
     char* base = (char*)wsp;
     double* tpart = (double*)base;   // [units][8]: gp_bar, fp_bar of each tile
+    unsigned long long* cgc = tiled_cg_counters(base, units.size());
     char* arenas = base + tiled_header_bytes(units.size());
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, caller, cgc, 8);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return FBSDE_EHIP;
     hipEvent_t ev0;
     if (hipEventCreateWithFlags(&ev0, hipEventDisableTiming) != hipSuccess) return FBSDE_EHIP;
     if (hipEventRecord(ev0, caller) != hipSuccess) { (void)hipEventDestroy(ev0); return FBSDE_EHIP; }
-    std::atomic<int> next{0}, first_err{0};
+    // The solves only enqueue their work (no call waits for the device), so the tiles are dealt to the
+    // streams up front: largest expected time first, each to the stream with the least time so far.
+    std::vector<std::vector<int>> deal((size_t)nw);
+    {
+        std::vector<double> load((size_t)nw, 0.0);
+        for (size_t k = 0; k < units.size(); ++k) {
+            const size_t w = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+            deal[w].push_back((int)k);
+            load[w] += units[k].cost;
+        }
+    }
+    std::atomic<int> first_err{0};
     auto fail = [&](int e) { int z = 0; first_err.compare_exchange_strong(z, e); };
     auto worker = [&](int w) {
         if (hipSetDevice(dev) != hipSuccess) { fail(FBSDE_EHIP); return; }
@@ -232,10 +273,8 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { fail(FBSDE_EHIP); return; }
         if (hipStreamWaitEvent(s, ev0, 0) != hipSuccess) fail(FBSDE_EHIP);
         char* ar = arenas + (size_t)w * arena;
-        for (;;) {
+        for (const int k : deal[(size_t)w]) {
             if (first_err.load()) break;
-            const int k = next.fetch_add(1);
-            if (k >= (int)units.size()) break;
             const TileUnit& t = units[(size_t)k];
             const int i = t.inst;
             fbsde_problem pb = a.pbs[i];
@@ -245,11 +284,12 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
             double* u = a.u[i] + t.p0;
             double* g = a.grad && a.grad[i] ? a.grad[i] + t.p0 * d : nullptr;
             uint32_t* st = a.status[i] + t.p0;
-            int e = fbsde_solve(&pb, t.np, x0, u, g, st, ar, arena, flags, nullptr, (fbsde_stream)s);
+            int e = solve_tile(&pb, t.np, x0, u, g, st, ar, arena, flags, true, s);
             if (!e && adjoint)
-                e = fbsde_solve_backward(&pb, t.np, x0, a.u_bar[i] + t.p0, a.x0_bar[i] + t.p0 * d,
-                                         tpart + (size_t)k * 8, tpart + (size_t)k * 8 + 4, st, ar, arena, nullptr,
-                                         (fbsde_stream)s);
+                e = solve_backward_after_forward(&pb, t.np, x0, a.u_bar[i] + t.p0, a.x0_bar[i] + t.p0 * d,
+                                                 tpart + (size_t)k * 8, tpart + (size_t)k * 8 + 4, st, ar, arena, s);
+            // the tile's CG traffic (forward and reverse), counted in the arena's loop control
+            if (!e && !pb.shared_dw) hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, s, cgc + w, cg_bytes_counter(ar));
             if (e) fail(e);
         }
         if (hipStreamSynchronize(s) != hipSuccess) fail(FBSDE_EHIP);
@@ -421,6 +461,30 @@ int fbsde_solve_batched_backward(const fbsde_problem* pbs, int64_t n_inst, const
             return FBSDE_EINVAL;
     TiledArgs a{pbs, x0, u, nullptr, status, u_bar, x0_bar, gp_bar, fp_bar};
     return run_tiled(a, n_inst, P, o, true, wsp, ws_bytes, (hipStream_t)stream);
+}
+
+int fbsde_batched_cg_bytes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const fbsde_batch_opts* opts,
+                           int32_t adjoint, const void* wsp, double* bytes, fbsde_stream stream) {
+    if (!pbs || !P || !wsp || !bytes || n_inst < 1 || (adjoint != 0 && adjoint != 1)) return FBSDE_EINVAL;
+    Opts o;
+    int rc = read_opts(opts, o);
+    if (rc) return rc;
+    if (o.mode != FBSDE_BATCH_TILED) return FBSDE_EINVAL;
+    std::vector<TileUnit> units;
+    size_t need = 0, arena = 0;
+    int nw = 1;
+    if ((rc = tiled_size(pbs, n_inst, P, o, adjoint ? FBSDE_WS_TAPE : 0, &need, &units, &arena, &nw))) return rc;
+    *bytes = 0.0;
+    if (units.empty()) return FBSDE_OK;
+    unsigned long long c[8] = {};
+    const unsigned long long* cgc = tiled_cg_counters((char*)wsp, units.size());
+    if (hipMemcpyAsync(c, cgc, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return FBSDE_EHIP;
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += (double)c[w];
+    *bytes = t;
+    return FBSDE_OK;
 }
 
 }  // extern "C"

@@ -2,26 +2,27 @@
 // level in ONE launch, with no host round trip (the matrix-free product of the ridge normal equations,
 // paper Sec. 2.4, matrix-free steps 1-2 fused into one read of the state, then the CG step).
 //
-// Work items are (point, chunk) pairs of the point's current iteration, kept in NQ <= 8 ring queues (point
-// p in queue p mod NQ; a block serves queue blockIdx mod NQ, so no single counter is shared by every
-// block): the launch starts with every point's chunks of the first iteration in them, and the block that
-// finishes a point's CG step enqueues that point's chunks of the next iteration (none once the point has
-// converged).  A block takes the next index of its queue from that queue's counter, waits until the slot is
-// filled, streams its chunk of the point's particle rows (the same per-row work as k_matvec), and reports
-// the chunk's partial column sums up a per-point arrival tree of fan-in CG_FAN.  The block that completes
-// the root does the CG step of the point (the same arithmetic as k_cg_update, chunk partials summed in a
-// fixed order) and publishes the point's new iteration count.
+// Work items are (point, chunk) pairs of the point's current iteration, kept in NQ <= 32 ring queues (point
+// p in queue p mod NQ; a block takes from queue blockIdx mod NQ first and from the others when that one is
+// empty, so no single counter is hit by every block and no queue depends on particular blocks being
+// resident): the launch starts with every point's chunks of the first iteration in them, and the block
+// that finishes a point's CG step enqueues that point's chunks of the next iteration (none once the point
+// has converged).  A block takes an index below a queue's fill counter, waits until that slot is filled,
+// streams its chunk of the point's particle rows (the same per-row work as k_matvec), and reports the
+// chunk's partial column sums up a per-point arrival tree of fan-in CG_FAN.  The block that completes the
+// root does the CG step of the point (the same arithmetic as k_cg_update, chunk partials summed in a fixed
+// order) and publishes the point's new iteration count.
 //
-// Every item in a queue is ready when it is filled, so a block waits only for a slot that a running block
-// is about to fill, or for the end of the level: once no point is left iterating, a block whose slot is
-// still empty leaves (no item can come any more: a point enqueues only while it iterates, and a point that
-// iterates holds the count of iterating points above zero).  A queue is a bounded ring of (its points) x
-// nchunk slots, each with a sequence number (the classic bounded multi-producer multi-consumer ring):
-// slot j mod cap is free for index j when its number is j, filled when it is j + 1, and the taker frees it
-// for j + cap.  A point has at most nchunk items outstanding, so a producer that finds its slot not yet
-// free waits only for a taker that already holds the earlier index.  Every wait is bounded in wall-clock
-// time all the same: past the bound the loop winds down and the points still iterating are flagged
-// FBSDE_ST_WAIT_LIMIT (an internal error, never expected).
+// A block takes only indices below a fill counter, so it waits only for a slot whose producer (a running
+// block) is about to fill it, or, with every queue empty, until an item appears or no point iterates any
+// more (then no item can come: a point enqueues only while it iterates, and a point that iterates holds
+// the count of iterating points above zero).  A queue is a bounded ring of (its points) x nchunk slots,
+// each with a sequence number (the classic bounded multi-producer multi-consumer ring): slot j mod cap is
+// free for index j when its number is j, filled when it is j + 1, and the taker frees it for j + cap.  A
+// point has at most nchunk items outstanding, so a producer that finds its slot not yet free waits only for
+// a taker that already holds the earlier index.  Every wait is bounded in wall-clock time all the same
+// (the empty-queue wait from the last time any queue moved): past the bound the loop winds down and the
+// points still iterating are flagged FBSDE_ST_WAIT_LIMIT (an internal error, never expected).
 //
 // Coherence: the L2 caches of the XCDs are not coherent with each other within a kernel.  The data that
 // blocks hand to one another inside the loop (chunk partials, the CG vectors and scalars of a point, the
@@ -41,11 +42,12 @@ enum { ST_WAIT_LIMIT = 8 };                // status bit: a bounded device-side 
 // Control words of the device loop, in the workspace: the particle rows streamed by products since the
 // last reset (algorithmic work for measurement), an error flag, and per queue its take and fill counters,
 // each pair on a line of its own.
-constexpr int CG_MAXQ = 8;
+constexpr int CG_MAXQ = 32;
 struct CgCtl {
     unsigned long long rows;
+    unsigned long long bytes;            // the same rows x d x element bytes (algorithmic read traffic)
     int err;
-    int pad[29];
+    int pad[27];
     unsigned long long q[CG_MAXQ][16];   // [0] head (taken), [1] tail (filled)
 };
 
@@ -91,7 +93,10 @@ k_cg_arm(CgCtl* ctl, unsigned long long* __restrict__ queue, int nq, int64_t qca
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, n = (int64_t)gridDim.x * blockDim.x;
     if (t == 0) {
         ctl->err = 0;
-        if (reset_rows) ctl->rows = 0ull;
+        if (reset_rows) {
+            ctl->rows = 0ull;
+            ctl->bytes = 0ull;
+        }
         for (int q = 0; q < nq; ++q) {
             ctl->q[q][0] = 0ull;
             ctl->q[q][1] = (unsigned long long)(((P - q + nq - 1) / nq) * nchunk);
@@ -234,10 +239,11 @@ __device__ __forceinline__ void cg_root_update(int p, int it, const double* __re
 }
 
 // After the loop: the rows its products streamed (each point's iterations x M, summed per block, one atomic
-// per block) and, after a loop that gave up a bounded wait (an internal error), every point still
+// per block) and their bytes (row_bytes = d x element bytes), and, after a loop that gave up a bounded wait (an internal error), every point still
 // iterating flagged.
 __global__ void __launch_bounds__(256)
-k_cg_check(CgCtl* ctl, const int* __restrict__ iscal, int64_t P, int64_t M, uint32_t* __restrict__ status) {
+k_cg_check(CgCtl* ctl, const int* __restrict__ iscal, int64_t P, int64_t M, int64_t row_bytes,
+           uint32_t* __restrict__ status) {
     __shared__ double lds[16];
     const int err = ctl->err;
     double rows = 0.0;
@@ -246,7 +252,10 @@ k_cg_check(CgCtl* ctl, const int* __restrict__ iscal, int64_t P, int64_t M, uint
         if (err && !(iscal[p * 4 + 2] >> 30)) status[p] |= (uint32_t)ST_WAIT_LIMIT;
     }
     rows = block_sum(rows, lds);
-    if (threadIdx.x == 0 && rows > 0.0) atomicAdd(&ctl->rows, (unsigned long long)rows);
+    if (threadIdx.x == 0 && rows > 0.0) {
+        atomicAdd(&ctl->rows, (unsigned long long)rows);
+        atomicAdd(&ctl->bytes, (unsigned long long)rows * (unsigned long long)row_bytes);
+    }
 }
 
 // Waves per SIMD asked of the register allocator: the occupancy of the stand-alone product kernel
@@ -270,19 +279,53 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
     __shared__ double red[2 * G::BS / 64 + 16];
     __shared__ int sh_flag;
     const int team0 = threadIdx.x / G::TL, L0 = threadIdx.x % G::TL;
-    const int qi = blockIdx.x % nq;
-    unsigned long long* const qq = queue + (int64_t)qi * qcap;
+    const int qi = blockIdx.x % nq;   // home queue
     constexpr bool PF = G::BS < 1024 && !(sizeof(R) > sizeof(S) && Q == 8);
     for (;;) {
         // ------------------------------------------------------------ next work item
         if (threadIdx.x == 0) {
             int item = -1;   // -1: leave
-            if (ldc(&ctl->err) == 0) {
-                const unsigned long long n = atomicAdd(&ctl->q[qi][0], 1ull);
-                unsigned long long* slot = qq + (n % (unsigned long long)qcap);
+            // Take an index below the fill counter of the home queue, else of another queue (any running
+            // block serves any queue, so no queue waits for blocks that are not resident).  With every
+            // queue empty, poll until an item appears or no point iterates any more; the wait bound
+            // counts from the last time any queue's take counter moved.
+            unsigned long long n = 0;
+            int qt = -1;
+            uint64_t t0 = wall_clock64();
+            unsigned long long seen = ~0ull;
+            for (int k = 0; qt < 0; ++k) {
+                if (ldc(&ctl->err) != 0) break;
+                unsigned long long moved = 0;
+                for (int j = 0; j < nq && qt < 0; ++j) {
+                    const int q = (qi + j) % nq;
+                    const unsigned long long h = __hip_atomic_load(&ctl->q[q][0], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long tl = __hip_atomic_load(&ctl->q[q][1], __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    moved += h;
+                    if (h < tl && atomicCAS(&ctl->q[q][0], h, h + 1ull) == h) {
+                        n = h;
+                        qt = q;
+                    }
+                }
+                if (qt >= 0) break;
+                if (ldc(active) <= 0) break;   // the level is over
+                if (moved != seen) {
+                    seen = moved;
+                    t0 = wall_clock64();
+                } else if (wall_clock64() - t0 > wait_ticks) {
+                    atomicExch(&ctl->err, 1);
+                    break;
+                }
+                if (k < 16) __builtin_amdgcn_s_sleep(1);
+                else __builtin_amdgcn_s_sleep(8);
+            }
+            if (qt >= 0) {
+                // the index is below the fill counter: its producer has reserved it and fills it shortly
+                unsigned long long* slot = queue + (int64_t)qt * qcap + (int64_t)(n % (unsigned long long)qcap);
                 const uint32_t want = (uint32_t)(n + 1);
-                const uint64_t t0 = wall_clock64();
-                for (int k = 0;; ++k) {
+                const uint64_t t1 = wall_clock64();
+                for (;;) {
                     const unsigned long long v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if ((uint32_t)(v >> 32) == want) {
                         item = (int)(uint32_t)v;
@@ -291,13 +334,11 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
-                    if (ldc(active) <= 0 || ldc(&ctl->err) != 0) break;   // the level is over
-                    if (wall_clock64() - t0 > wait_ticks) {
+                    if (wall_clock64() - t1 > wait_ticks) {
                         atomicExch(&ctl->err, 1);
                         break;
                     }
-                    if (k < 16) __builtin_amdgcn_s_sleep(1);
-                    else __builtin_amdgcn_s_sleep(8);
+                    __builtin_amdgcn_s_sleep(1);
                 }
             }
             sh_flag = item;

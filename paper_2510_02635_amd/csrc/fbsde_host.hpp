@@ -160,6 +160,17 @@ template <typename S>
 void shared_reverse(const fbsde_problem* pb, const Plan& pl1, int k, S* W, const double* ax_dummy, const double* scal,
                     double* Yscratch, double* rn2, uint32_t* status, hipStream_t st);
 void clear_status(uint32_t* status, int64_t P, hipStream_t st);
+// fbsde_solve for one tile of a batched call; reset_counts = false adds its CG traffic to the count the
+// arena already holds (the per-point form keeps it in the loop control at offset 0 of the workspace).
+int solve_tile(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
+               void* ws, size_t ws_bytes, int32_t flags, bool reset_counts, hipStream_t st);
+// Device address of the algorithmic CG-product byte count in a per-point workspace.
+unsigned long long* cg_bytes_counter(void* ws);
+// fbsde_solve_backward without the read-back of the tape's tag, for a caller that has just enqueued the
+// forward solve with the tape on the same stream and workspace (the batched schedule): no stream wait.
+int solve_backward_after_forward(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar,
+                                 double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, void* ws,
+                                 size_t ws_bytes, hipStream_t st);
 void set_int(int* a, int v, hipStream_t st);
 
 }  // namespace host

@@ -1,8 +1,9 @@
 """Host-side checks of the batched scheduler's tile plan (no GPU: fbsde_batched_workspace_size only plans).
 
 Tiled schedule: each instance is cut into equal point tiles, each the largest whose single-instance
-workspace fits the tile cap (at least one point); the workspace is a [tiles][8] FP64 header plus one
-arena (the largest tile workspace) per stream, streams = min(requested, tiles)."""
+workspace fits the tile cap (at least one point); the workspace is a [tiles][8] FP64 header with eight
+64-bit per-stream traffic counters after it, plus one arena (the largest tile workspace) per stream,
+streams = min(requested, tiles)."""
 import ctypes
 
 import pytest
@@ -42,7 +43,7 @@ def _expected(pbs, Ps, tile_bytes, streams, tape=False):
             arena = max(arena, _round(F.workspace_size(pb, min(np_, P - p0), tape)))
             tiles += 1
     nw = min(streams, max(tiles, 1))
-    return _round(tiles * 64) + nw * arena
+    return _round(tiles * 64 + 64) + nw * arena
 
 
 PBS = [F.Problem(d=37, M=100, N=3, T=0.5), F.Problem(d=600, M=130, N=2, T=0.3),

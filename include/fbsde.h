@@ -327,6 +327,20 @@ int fbsde_launch_timer(int32_t on);
 int fbsde_launch_timer_read(float* ms, double* bytes, int64_t cap, int64_t* n);
 int fbsde_launch_timer_kinds(int32_t* kinds, int64_t cap, int64_t* n);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): fbsde_solve of the per-point form (shared_dw = 0, flags = 0, no
+ * iteration record) with the workspace taken from a file-scope device array of
+ * FBSDE_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on (until the process ends).
+ * The caller still passes the inputs and outputs (x0, u, grad or NULL, status: device memory as in
+ * fbsde_solve).  No device or host memory is allocated and no launch timer events are created.
+ * FBSDE_ENOSPC if fbsde_workspace_size(pb, P, 0) exceeds that size, FBSDE_EINVAL for shared_dw = 1.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one GPU (different streams or
+ * host threads without ordering) race and must not be issued; calls on one stream are ordered.  The
+ * array keeps the last call's contents; every value a solve reads is written by that solve first. */
+#define FBSDE_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int fbsde_solve_noalloc(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                        uint32_t* status, fbsde_stream stream);
+
 /* Diagnostic: the particle rows that the CG products of the per-point path have streamed since the
  * start of the last fbsde_solve on this workspace (its backward pass included).  One row of a point is
  * d elements of the state, so rows x d x element bytes is the algorithmic read traffic of those

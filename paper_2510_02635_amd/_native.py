@@ -16,7 +16,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
             "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
-            "fbsde_workspace_cg_rows", "fbsde_batched_cg_bytes",
+            "fbsde_workspace_cg_rows", "fbsde_solve_noalloc", "fbsde_batched_cg_bytes",
             "fbsde_literal_workspace_size", "fbsde_literal_workspace_size_stored", "fbsde_literal_coef_workspace_size",
             "fbsde_solve_literal_coef",
             "fbsde_solve_literal", "fbsde_strerror")
@@ -97,6 +97,7 @@ def load():
     lib.fbsde_launch_timer_read.argtypes = [vp, vp, i64, P(i64)]
     lib.fbsde_launch_timer_kinds.argtypes = [vp, i64, P(i64)]
     lib.fbsde_workspace_cg_rows.argtypes = [vp, P(i64), vp]
+    lib.fbsde_solve_noalloc.argtypes = [pb, i64, vp, vp, vp, vp, vp]
     lib.fbsde_batched_cg_bytes.argtypes = [pb, i64, vp, vp, i32, vp, P(ctypes.c_double), vp]
     lib.fbsde_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.c_double,
                                ctypes.c_double, vp]
@@ -124,7 +125,7 @@ def load():
                  "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
                  "fbsde_launch_timer_read", "fbsde_launch_timer_kinds", "fbsde_literal_coef_workspace_size",
-                 "fbsde_workspace_cg_rows", "fbsde_batched_cg_bytes",
+                 "fbsde_workspace_cg_rows", "fbsde_solve_noalloc", "fbsde_batched_cg_bytes",
                  "fbsde_literal_workspace_size_stored",
                  "fbsde_solve_literal_coef",
                  "fbsde_solve_literal"):

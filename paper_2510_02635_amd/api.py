@@ -147,6 +147,24 @@ def solve(pb, x0, want_grad=True, tape=False, ws=None, return_iters=False):
     return u, grad, st
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def solve_noalloc(pb, x0, u, grad, status):
+    """fbsde_solve_noalloc: the per-point solve with the library's own fixed device scratch array as its
+    workspace (no allocation inside the call); u [P], grad [P][d] or None, status [P] are caller tensors."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    _dev_f64(u, (P,))
+    if grad is not None:
+        _dev_f64(grad, (P, pb.d))
+    if status.dtype != torch.int32 or not status.is_cuda or tuple(status.shape) != (P,):
+        raise ValueError("status must be an int32 device tensor of shape [P]")
+    N.check(N.load().fbsde_solve_noalloc(ctypes.byref(pb.c()), P, x0.data_ptr(), u.data_ptr(), _ptr(grad),
+                                         status.data_ptr(), _stream()))
+    return u, grad, status
+
+
 def solve_backward(pb, x0, u_bar, ws, return_iters=False):
     """Adjoint of solve for L = sum_p u_bar[p] u_p; needs ws from solve(..., tape=True).
 

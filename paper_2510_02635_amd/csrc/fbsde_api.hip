@@ -98,6 +98,7 @@ struct WS {
     unsigned long long* queue;   // CG work queues [nq][qcap]
     int nq;
     int64_t qcap;
+    bool fixed_buffer;           // the allocation-free entry point: no timer events, device CG loop only
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
     int* tag;
@@ -117,6 +118,7 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     };
     const size_t PM = (size_t)P * pl.M, PL = (size_t)P * pl.ld;
     const size_t parts = (size_t)P * pl.nchunk * pl.ld;
+    ws.fixed_buffer = false;
     ws.ctl = (CgCtl*)take(sizeof(CgCtl));
     ws.W = take(PM * pl.ld * pl.esz);
     ws.Ya = (double*)take(PM * 8);
@@ -221,7 +223,7 @@ int run_cg_device(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W
                                                          Geo<QQ, TT>::BS, 0) != hipSuccess)
             per_cu = 1;
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)std::max(per_cu, 1) * ncu));
-        const long tl = lt_begin(st, 0.0, FBSDE_TIMED_CG_LOOP);
+        const long tl = ws.fixed_buffer ? -1 : lt_begin(st, 0.0, FBSDE_TIMED_CG_LOOP);
         hipLaunchKernelGGL((k_cg_loop<S, R, QQ, TT>), dim3((unsigned)grid), dim3(Geo<QQ, TT>::BS), 0, st, W, ldw,
                            (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, Wbar, ws.x, ws.r, ws.pv, ws.qv,
                            ws.scal, NS, ws.iscal, ws.part1, ws.psc, ws.ctl, ws.queue, ws.nq, ws.qcap, ws.active,
@@ -245,7 +247,7 @@ bool host_cg_loop() {
 template <typename S, typename R = S>
 int run_cg(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
            const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
-    if (!host_cg_loop()) return run_cg_device<S, R>(pb, pl, P, W, ldw, w, Wbar, ws, status, st, err);
+    if (ws.fixed_buffer || !host_cg_loop()) return run_cg_device<S, R>(pb, pl, P, W, ldw, w, Wbar, ws, status, st, err);
     const int fixed = pb->cg_fixed_iters;
     const int cap = (fixed > 0) ? fixed : pb->cg_maxit;
     const int poll = 8;
@@ -1105,6 +1107,57 @@ int fbsde_graph_destroy(fbsde_graph g) {
     const bool ok = hipGraphExecDestroy(g->exec) == hipSuccess && hipGraphDestroy(g->graph) == hipSuccess;
     delete g;
     return ok ? FBSDE_OK : FBSDE_EHIP;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free entry point
+// The workspace of fbsde_solve_noalloc: a file-scope device array (each GPU that runs the library holds
+// its own copy until the process ends).  Host code never passes its name to a kernel: the name is a
+// host-side stand-in, so its device address is looked up once per device (hipGetSymbolAddress, with the
+// device current) and that address is used everywhere.
+__device__ __align__(256) unsigned char scratch[FBSDE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (set-up on the first call on each device).
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FBSDE_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FBSDE_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FBSDE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fbsde_solve_noalloc(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                        uint32_t* status, fbsde_stream stream) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    if (pb->shared_dw) return FBSDE_EINVAL;   // the per-point form only
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (P == 0) return FBSDE_OK;
+    if (!x0 || !u || !status) return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, 0, nullptr, ws) > (size_t)FBSDE_NOALLOC_SCRATCH_BYTES) return FBSDE_ENOSPC;
+    void* base = nullptr;
+    if ((rc = scratch_of_current_device(&base))) return rc;
+    carve(pl, P, 0, (char*)base, ws);
+    ws.fixed_buffer = true;
+    hipStream_t st = (hipStream_t)stream;
+    if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, false, nullptr, st);
+    return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, false, nullptr, st);
 }
 
 const char* fbsde_strerror(int code) {

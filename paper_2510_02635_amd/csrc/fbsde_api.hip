@@ -70,6 +70,11 @@ void lt_end(long i, hipStream_t st) {
 
 namespace fbsde {
 namespace host {
+// The share of the chip one CG loop launch asks for: 1 (all of it) unless the calling thread runs one of
+// several streams of a batched call (run_tiled sets it for the duration of its worker), where a loop
+// sized for the whole chip would keep the other streams' loops out until its level ends.
+thread_local int loop_share = 1;
+
 long timer_begin(hipStream_t st, double work, int kind) { return lt_begin(st, work, kind); }
 void timer_end(long i, hipStream_t st) { lt_end(i, st); }
 
@@ -196,8 +201,9 @@ int fold_parts(const Plan& pl, int64_t P, double* a, double* b, double* c, hipSt
 }
 
 // The CG solve of a level as one launch of the device-side loop (fbsde_cgloop.hpp): every iteration of
-// every point, no host round trip.  The loop's grid is what the chip holds at once (more blocks would only
-// take tickets later); the wait bound is two seconds of the device's wall clock.
+// every point, no host round trip.  The loop's grid is what the chip holds at once, or the calling
+// thread's share of it (more blocks would only take tickets later); the wait bound is two seconds of the
+// device's wall clock.
 template <typename S, typename R>
 int run_cg_device(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W, int64_t ldw, const double* w,
                   const double* Wbar, WS& ws, uint32_t* status, hipStream_t st, int& err) {
@@ -222,7 +228,8 @@ int run_cg_device(const fbsde_problem* pb, const Plan& pl, int64_t P, const S* W
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_cg_loop<S, R, QQ, TT>),
                                                          Geo<QQ, TT>::BS, 0) != hipSuccess)
             per_cu = 1;
-        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)std::max(per_cu, 1) * ncu));
+        const int64_t slots = std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * ncu / std::max(loop_share, 1));
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, slots));
         const long tl = ws.fixed_buffer ? -1 : lt_begin(st, 0.0, FBSDE_TIMED_CG_LOOP);
         hipLaunchKernelGGL((k_cg_loop<S, R, QQ, TT>), dim3((unsigned)grid), dim3(Geo<QQ, TT>::BS), 0, st, W, ldw,
                            (int)pl.M, pl.rows_per_chunk, pl.nchunk, pl.ld, pb->s, w, Wbar, ws.x, ws.r, ws.pv, ws.qv,

@@ -2,27 +2,33 @@
 // level in ONE launch, with no host round trip (the matrix-free product of the ridge normal equations,
 // paper Sec. 2.4, matrix-free steps 1-2 fused into one read of the state, then the CG step).
 //
-// Work items are (point, chunk) pairs of the point's current iteration, kept in NQ <= 32 ring queues (point
-// p in queue p mod NQ; a block takes from queue blockIdx mod NQ first and from the others when that one is
-// empty, so no single counter is hit by every block and no queue depends on particular blocks being
-// resident): the launch starts with every point's chunks of the first iteration in them, and the block
-// that finishes a point's CG step enqueues that point's chunks of the next iteration (none once the point
-// has converged).  A block takes an index below a queue's fill counter, waits until that slot is filled,
-// streams its chunk of the point's particle rows (the same per-row work as k_matvec), and reports the
-// chunk's partial column sums up a per-point arrival tree of fan-in CG_FAN.  The block that completes the
-// root does the CG step of the point (the same arithmetic as k_cg_update, chunk partials summed in a fixed
-// order) and publishes the point's new iteration count.
+// Work items are (point, chunk) pairs of the point's current iteration, kept in NQ <= 32 ring queues
+// (point p in queue p mod NQ; block b's home queue is b mod NQ): the launch starts with every point's
+// chunks of the first iteration in them, and the block that finishes a point's CG step enqueues that
+// point's chunks of the next iteration (none once the point has converged).  A block streams its chunk of
+// the point's particle rows (the same per-row work as k_matvec) and reports the chunk's partial column
+// sums up a per-point arrival tree of fan-in CG_FAN.  The block that completes the root does the CG step
+// of the point (the same arithmetic as k_cg_update, chunk partials summed in a fixed order) and publishes
+// the point's new iteration count.
 //
-// A block takes only indices below a fill counter, so it waits only for a slot whose producer (a running
-// block) is about to fill it, or, with every queue empty, until an item appears or no point iterates any
-// more (then no item can come: a point enqueues only while it iterates, and a point that iterates holds
-// the count of iterating points above zero).  A queue is a bounded ring of (its points) x nchunk slots,
-// each with a sequence number (the classic bounded multi-producer multi-consumer ring): slot j mod cap is
-// free for index j when its number is j, filled when it is j + 1, and the taker frees it for j + cap.  A
-// point has at most nchunk items outstanding, so a producer that finds its slot not yet free waits only for
-// a taker that already holds the earlier index.  Every wait is bounded in wall-clock time all the same
-// (the empty-queue wait from the last time any queue moved): past the bound the loop winds down and the
-// points still iterating are flagged FBSDE_ST_WAIT_LIMIT (an internal error, never expected).
+// Taking items: a block holds a ticket, an index of its home queue drawn with one fetch-and-add, and the
+// item filled at that index is its next one.  Tickets may run ahead of the fill counter (the item comes
+// with a later iteration).  A block whose ticket is not filled yet takes, now and then, an item nobody
+// holds a ticket for (an index below a queue's fill counter, claimed with a compare-and-swap of the take
+// counter), so the items of a queue whose home blocks are not resident (other kernels holding their
+// compute units) still get done, and no block ever waits on a block that is not running.  Drawing
+// tickets with fetch-and-add rather than claiming every item with compare-and-swap matters: with hundreds
+// of blocks polling a few queues, the failed swaps of the losers delayed the winners (measured: 8 points
+// at d = 5000, M = 4800 went 721 -> 369 ms per solve).  The loop is over when no point iterates any more:
+// then no item can come (a point enqueues only while it iterates, and a point that iterates holds the
+// count of iterating points above zero).  A queue is a bounded ring of (its points) x nchunk slots, each
+// with a sequence number (the classic bounded multi-producer multi-consumer ring): slot j mod cap is free
+// for index j when its number is j, filled when it is j + 1, and the taker frees it for j + cap.  A point
+// has at most nchunk items outstanding, so a producer that finds its slot not yet free waits only for the
+// holder of the earlier index, a running block.  The waits that could only end by another block's action
+// are bounded in wall-clock time (counted from the last time any queue counter moved): past the bound
+// the loop winds down and the points still iterating are flagged FBSDE_ST_WAIT_LIMIT (an internal error,
+// never expected).
 //
 // Coherence: the L2 caches of the XCDs are not coherent with each other within a kernel.  The data that
 // blocks hand to one another inside the loop (chunk partials, the CG vectors and scalars of a point, the
@@ -146,9 +152,22 @@ __device__ __forceinline__ void block_columns_out_c(CSum<R> (&acc)[Q][4], double
     }
 }
 
+// Coherent loads that one thread issues back to back before it uses any of them: each loop below takes
+// RU of its elements per round (RU2 where every element sums up to CG_FAN children), so a round costs
+// one memory round trip instead of one per element.  Loads past the end of a vector or the last child
+// re-read an element that exists and are not used.
+// Kernels whose row registers already exceed what wider rounds take (eight groups of four per lane) use
+// wider rounds, and 16-wave teams (128 registers at most) narrower ones: the rounds then add nothing to
+// the kernel's register peak.
+template <int Q, int TEAM> struct CgRounds {
+    static constexpr int RU = (TEAM >= 16) ? 2 : (Q >= 8) ? 8 : 4;
+    static constexpr int RU2 = (TEAM >= 16) ? 1 : (Q >= 8) ? 3 : 2;   // the same for sums of CG_FAN children
+};
+
 // The CG step of point p at iteration `it`, by the whole block, from the nchild partial vectors / tau
 // partials at chunk slots k * stride (k < nchild, summed in that order).  Ends with the point's new state
 // published (iterations | done << 30) and, while it iterates, its chunks of the next iteration enqueued.
+template <int CG_RU, int CG_RU2>
 __device__ __forceinline__ void cg_root_update(int p, int it, const double* __restrict__ part,
                                                const double* __restrict__ psc, int nchunk, int nchild, int stride,
                                                int ld, double s, const double* __restrict__ Wbar, double* __restrict__ x,
@@ -160,27 +179,65 @@ __device__ __forceinline__ void cg_root_update(int p, int it, const double* __re
     double* sc = scal + (int64_t)p * ns;
     const double lam = sc[3];
     double tau = 0.0;
-    for (int k = 0; k < nchild; ++k) tau += ldc(psc + (int64_t)p * nchunk + k * stride);
+    {
+        double t[CG_FAN];
+#pragma unroll
+        for (int k = 0; k < CG_FAN; ++k) t[k] = ldc(psc + (int64_t)p * nchunk + min(k, nchild - 1) * stride);
+#pragma unroll
+        for (int k = 0; k < CG_FAN; ++k)
+            if (k < nchild) tau += t[k];
+    }
     const int64_t o = (int64_t)p * ld;
+    const int bs = blockDim.x;
     double pq = 0.0;
-    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-        double a = 0.0;
-        for (int k = 0; k < nchild; ++k) a += ldc(part + ((int64_t)p * nchunk + k * stride) * ld + i);
-        const double pvi = ldc(pv + o + i);
-        const double q = s * (a - tau * Wbar[o + i]) + lam * pvi;
-        stc(qv + o + i, q);
-        pq += pvi * q;
+    for (int i0 = threadIdx.x; i0 < ld; i0 += CG_RU2 * bs) {
+        double a[CG_RU2][CG_FAN], pw[CG_RU2];
+#pragma unroll
+        for (int u = 0; u < CG_RU2; ++u) {
+            const int i = min(i0 + u * bs, ld - 1);
+#pragma unroll
+            for (int k = 0; k < CG_FAN; ++k)
+                a[u][k] = ldc(part + ((int64_t)p * nchunk + min(k, nchild - 1) * stride) * ld + i);
+            pw[u] = ldc(pv + o + i);
+        }
+#pragma unroll
+        for (int u = 0; u < CG_RU2; ++u) {
+            const int i = i0 + u * bs;
+            if (i < ld) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < CG_FAN; ++k)
+                    if (k < nchild) acc += a[u][k];
+                const double q = s * (acc - tau * Wbar[o + i]) + lam * pw[u];
+                stc(qv + o + i, q);
+                pq += pw[u] * q;
+            }
+        }
     }
     pq = block_sum(pq, lds);
     const double rr = ldc(sc + 0);
     const double alpha = (pq > 0.0) ? rr / pq : 0.0;
     double rr2 = 0.0;
-    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-        const double pvi = ldc(pv + o + i);
-        stc(x + o + i, ldc(x + o + i) + alpha * pvi);
-        const double ri = ldc(r + o + i) - alpha * ldc(qv + o + i);
-        stc(r + o + i, ri);
-        rr2 += ri * ri;
+    for (int i0 = threadIdx.x; i0 < ld; i0 += CG_RU * bs) {
+        double pw[CG_RU], xw[CG_RU], rw[CG_RU], qw[CG_RU];
+#pragma unroll
+        for (int u = 0; u < CG_RU; ++u) {
+            const int i = min(i0 + u * bs, ld - 1);
+            pw[u] = ldc(pv + o + i);
+            xw[u] = ldc(x + o + i);
+            rw[u] = ldc(r + o + i);
+            qw[u] = ldc(qv + o + i);
+        }
+#pragma unroll
+        for (int u = 0; u < CG_RU; ++u) {
+            const int i = i0 + u * bs;
+            if (i < ld) {
+                stc(x + o + i, xw[u] + alpha * pw[u]);
+                const double ri = rw[u] - alpha * qw[u];
+                stc(r + o + i, ri);
+                rr2 += ri * ri;
+            }
+        }
     }
     rr2 = block_sum(rr2, lds);
     const int itn = it + 1;
@@ -191,10 +248,23 @@ __device__ __forceinline__ void cg_root_update(int p, int it, const double* __re
     double wv = 0.0;
     if (!done) {
         const double beta = rr2 / rr;
-        for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-            const double pi = ldc(r + o + i) + beta * ldc(pv + o + i);
-            stc(pv + o + i, pi);
-            wv += Wbar[o + i] * pi;
+        for (int i0 = threadIdx.x; i0 < ld; i0 += CG_RU * bs) {
+            double pw[CG_RU], rw[CG_RU];
+#pragma unroll
+            for (int u = 0; u < CG_RU; ++u) {
+                const int i = min(i0 + u * bs, ld - 1);
+                rw[u] = ldc(r + o + i);
+                pw[u] = ldc(pv + o + i);
+            }
+#pragma unroll
+            for (int u = 0; u < CG_RU; ++u) {
+                const int i = i0 + u * bs;
+                if (i < ld) {
+                    const double pi = rw[u] + beta * pw[u];
+                    stc(pv + o + i, pi);
+                    wv += Wbar[o + i] * pi;
+                }
+            }
         }
         wv = block_sum(wv, lds);
     }
@@ -280,68 +350,107 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
     __shared__ int sh_flag;
     const int team0 = threadIdx.x / G::TL, L0 = threadIdx.x % G::TL;
     const int qi = blockIdx.x % nq;   // home queue
+    long long tick = -1;               // the block's ticket on its home queue (wave 0), -1: none
     constexpr bool PF = G::BS < 1024 && !(sizeof(R) > sizeof(S) && Q == 8);
     for (;;) {
         // ------------------------------------------------------------ next work item
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 64) {
+            // Wave 0 finds the block's next item.  The block holds a ticket, an index of its home queue
+            // taken with one fetch-and-add (no retries however many blocks share the queue): the item
+            // filled at that index is the block's.  A ticket may run ahead of the fill counter (the item
+            // comes with a later iteration of a point of that queue); while it waits, the block takes
+            // items nobody holds a ticket for (indices below a queue's fill counter, claimed with a
+            // compare-and-swap of the take counter), so items of a queue whose blocks are not resident
+            // still get done.  The loop is over when no point iterates any more: then no item can come
+            // (a point enqueues only while it iterates, and a point that iterates holds the count above
+            // zero).  The wait bound counts from the last time any queue counter moved.
+            const int lane = threadIdx.x;
             int item = -1;   // -1: leave
-            // Take an index below the fill counter of the home queue, else of another queue (any running
-            // block serves any queue, so no queue waits for blocks that are not resident).  With every
-            // queue empty, poll until an item appears or no point iterates any more; the wait bound
-            // counts from the last time any queue's take counter moved.
-            unsigned long long n = 0;
-            int qt = -1;
             uint64_t t0 = wall_clock64();
             unsigned long long seen = ~0ull;
-            for (int k = 0; qt < 0; ++k) {
-                if (ldc(&ctl->err) != 0) break;
-                unsigned long long moved = 0;
-                for (int j = 0; j < nq && qt < 0; ++j) {
-                    const int q = (qi + j) % nq;
-                    const unsigned long long h = __hip_atomic_load(&ctl->q[q][0], __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_AGENT);
-                    const unsigned long long tl = __hip_atomic_load(&ctl->q[q][1], __ATOMIC_RELAXED,
-                                                                    __HIP_MEMORY_SCOPE_AGENT);
-                    moved += h;
-                    if (h < tl && atomicCAS(&ctl->q[q][0], h, h + 1ull) == h) {
-                        n = h;
-                        qt = q;
-                    }
+            for (int k = 0;; ++k) {
+                if (tick < 0) {
+                    unsigned long long t = 0;
+                    if (lane == 0) t = atomicAdd(&ctl->q[qi][0], 1ull);
+                    tick = (long long)__shfl(t, 0, 64);
                 }
-                if (qt >= 0) break;
-                if (ldc(active) <= 0) break;   // the level is over
-                if (moved != seen) {
-                    seen = moved;
-                    t0 = wall_clock64();
-                } else if (wall_clock64() - t0 > wait_ticks) {
-                    atomicExch(&ctl->err, 1);
+                unsigned long long* myslot = queue + (int64_t)qi * qcap + (int64_t)((unsigned long long)tick % (unsigned long long)qcap);
+                const unsigned long long v = __hip_atomic_load(myslot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int err = ldc(&ctl->err);
+                const int act = ldc(active);
+                if ((uint32_t)(v >> 32) == (uint32_t)(tick + 1)) {
+                    item = (int)(uint32_t)v;
+                    // taken: the slot is free for the index one ring later
+                    if (lane == 0)
+                        __hip_atomic_store(myslot, (unsigned long long)(uint32_t)(tick + qcap) << 32, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    tick = -1;
                     break;
                 }
-                if (k < 16) __builtin_amdgcn_s_sleep(1);
-                else __builtin_amdgcn_s_sleep(8);
-            }
-            if (qt >= 0) {
-                // the index is below the fill counter: its producer has reserved it and fills it shortly
-                unsigned long long* slot = queue + (int64_t)qt * qcap + (int64_t)(n % (unsigned long long)qcap);
-                const uint32_t want = (uint32_t)(n + 1);
-                const uint64_t t1 = wall_clock64();
-                for (;;) {
-                    const unsigned long long v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((uint32_t)(v >> 32) == want) {
-                        item = (int)(uint32_t)v;
-                        // taken: the slot is free for the index one ring later
-                        __hip_atomic_store(slot, (unsigned long long)(uint32_t)(n + (unsigned long long)qcap) << 32,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (err != 0) break;
+                // every fourth round: lane q reads queue q's counters (one round trip for all queues), then
+                // the block claims an unticketed item if there is one, home queue first
+                if ((k & 3) == 3) {
+                    unsigned long long h = 0, tl = 0;
+                    if (lane < nq) {
+                        h = __hip_atomic_load(&ctl->q[lane][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        tl = __hip_atomic_load(&ctl->q[lane][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    unsigned long long moved = 0, n = 0;
+                    int qt = -1;
+                    for (int j = 0; j < nq; ++j) {
+                        const int q = (qi + j) % nq;
+                        const unsigned long long hq = __shfl(h, q, 64);
+                        const unsigned long long tq = __shfl(tl, q, 64);
+                        moved += hq + tq;
+                        if (qt < 0 && hq < tq) {
+                            unsigned long long got = 0;
+                            if (lane == 0) got = (atomicCAS(&ctl->q[q][0], hq, hq + 1ull) == hq) ? 1ull : 0ull;
+                            if (__shfl(got, 0, 64)) {
+                                n = hq;
+                                qt = q;
+                            }
+                        }
+                    }
+                    if (qt >= 0) {
+                        // below the fill counter: the producer has reserved the index and fills it shortly
+                        if (lane == 0) {
+                            unsigned long long* slot = queue + (int64_t)qt * qcap + (int64_t)(n % (unsigned long long)qcap);
+                            const uint32_t want = (uint32_t)(n + 1);
+                            const uint64_t t1 = wall_clock64();
+                            for (;;) {
+                                const unsigned long long w = __hip_atomic_load(slot, __ATOMIC_RELAXED,
+                                                                               __HIP_MEMORY_SCOPE_AGENT);
+                                if ((uint32_t)(w >> 32) == want) {
+                                    item = (int)(uint32_t)w;
+                                    __hip_atomic_store(slot,
+                                                       (unsigned long long)(uint32_t)(n + (unsigned long long)qcap) << 32,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                    break;
+                                }
+                                if (wall_clock64() - t1 > wait_ticks) {
+                                    atomicExch(&ctl->err, 1);
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                        }
+                        item = __shfl(item, 0, 64);
                         break;
                     }
-                    if (wall_clock64() - t1 > wait_ticks) {
-                        atomicExch(&ctl->err, 1);
+                    if (moved != seen) {
+                        seen = moved;
+                        t0 = wall_clock64();
+                    } else if (wall_clock64() - t0 > wait_ticks) {
+                        if (lane == 0) atomicExch(&ctl->err, 1);
                         break;
                     }
-                    __builtin_amdgcn_s_sleep(1);
                 }
+                if (act <= 0) break;   // the level is over
+                if (k < 16) __builtin_amdgcn_s_sleep(1);
+                else __builtin_amdgcn_s_sleep(4);
             }
-            sh_flag = item;
+            if (lane == 0) sh_flag = item;
         }
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(sh_flag);
@@ -418,7 +527,7 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
         for (;;) {
             stores_done_barrier();   // this block's partials are complete before it reports them
             if (n_l == 1) {          // a single chunk: this block holds the whole product
-                cg_root_update(p, it, part, psc, nchunk, 1, stride, ld, s, Wbar, x, r, pv, qv, scal, ns, iscal,
+                cg_root_update<CgRounds<Q, TEAM>::RU, CgRounds<Q, TEAM>::RU2>(p, it, part, psc, nchunk, 1, stride, ld, s, Wbar, x, r, pv, qv, scal, ns, iscal,
                                rtol2, maxit, active, status, red, ctl, queue, nq, qcap, wait_ticks);
                 break;
             }
@@ -437,17 +546,33 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
             const int cstride = stride;                  // children at slots (parent * FAN + k) * cstride
             const int pslot = parent * CG_FAN * cstride;
             if (n_up == 1) {
-                cg_root_update(p, it, part + (int64_t)pslot * ld, psc + pslot, nchunk, nchild, cstride, ld, s,
+                cg_root_update<CgRounds<Q, TEAM>::RU, CgRounds<Q, TEAM>::RU2>(p, it, part + (int64_t)pslot * ld, psc + pslot, nchunk, nchild, cstride, ld, s,
                                Wbar, x, r, pv, qv, scal, ns, iscal, rtol2, maxit, active, status, red, ctl, queue,
                                nq, qcap, wait_ticks);
                 break;
             }
             // sum the children into the first child's slot, which is the parent's slot one level up
             double* dst = part + ((int64_t)p * nchunk + pslot) * ld;
-            for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-                double a = 0.0;
-                for (int k = 0; k < nchild; ++k) a += ldc(dst + (int64_t)k * cstride * ld + i);
-                stc(dst + i, a);
+            constexpr int CG_RU2 = CgRounds<Q, TEAM>::RU2;
+            for (int i0 = threadIdx.x; i0 < ld; i0 += CG_RU2 * (int)blockDim.x) {
+                double a[CG_RU2][CG_FAN];
+#pragma unroll
+                for (int u = 0; u < CG_RU2; ++u) {
+                    const int i = min(i0 + u * (int)blockDim.x, ld - 1);
+#pragma unroll
+                    for (int k = 0; k < CG_FAN; ++k) a[u][k] = ldc(dst + (int64_t)min(k, nchild - 1) * cstride * ld + i);
+                }
+#pragma unroll
+                for (int u = 0; u < CG_RU2; ++u) {
+                    const int i = i0 + u * (int)blockDim.x;
+                    if (i < ld) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int k = 0; k < CG_FAN; ++k)
+                            if (k < nchild) acc += a[u][k];
+                        stc(dst + i, acc);
+                    }
+                }
             }
             if (threadIdx.x == 0) {
                 double a = 0.0;

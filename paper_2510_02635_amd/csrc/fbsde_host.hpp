@@ -95,8 +95,13 @@ inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     const int64_t target_blocks = 4096;
     int64_t nchunk = (target_blocks + std::max<int64_t>(P, 1) - 1) / std::max<int64_t>(P, 1);
     // at least 64 rows per chunk: each chunk writes one [ld] FP64 partial per pass, so the partials stay
-    // within a few per cent of the state bytes the pass reads
-    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, std::min<int64_t>(pb->M / (2 * pl.TPW), pb->M / 64)));
+    // within a few per cent of the state bytes the pass reads.  Short rows (ld <= 1024) take chunks of 16
+    // rows: there a CG iteration of few points is bound by the time one chunk's rows take one after
+    // another, and summing the extra partials costs little (measured: one point at d = 100, M = 512
+    // 4.4 -> 2.7 ms per solve; 8 points at d = 1000, M = 832 20.7 -> 14.2 ms; at d >= 5000 smaller chunks
+    // were slower, the deeper arrival tree adding more than the shorter chunks save).
+    const int64_t min_rows = (pl.ld <= 1024) ? 16 : 64;
+    nchunk = std::max<int64_t>(1, std::min<int64_t>(nchunk, std::min<int64_t>(pb->M / (2 * pl.TPW), pb->M / min_rows)));
     pl.rows_per_chunk = (int)((pb->M + nchunk - 1) / nchunk);
     pl.nchunk = (int)((pb->M + pl.rows_per_chunk - 1) / pl.rows_per_chunk);
     // a shape chosen by the autotuner: never more chunks than the default, so workspaces sized
@@ -160,6 +165,8 @@ template <typename S>
 void shared_reverse(const fbsde_problem* pb, const Plan& pl1, int k, S* W, const double* ax_dummy, const double* scal,
                     double* Yscratch, double* rn2, uint32_t* status, hipStream_t st);
 void clear_status(uint32_t* status, int64_t P, hipStream_t st);
+// Divisor of the chip's block slots that a CG loop launch from this host thread asks for (1 by default).
+extern thread_local int loop_share;
 // fbsde_solve for one tile of a batched call; reset_counts = false adds its CG traffic to the count the
 // arena already holds (the per-point form keeps it in the loop control at offset 0 of the workspace).
 int solve_tile(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,

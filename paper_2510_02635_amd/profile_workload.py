@@ -80,9 +80,14 @@ def main():
         u, g, st = F.solve(pb, x0, tape=True, ws=ws)
         F.solve_backward(pb, x0, torch.ones(P, dtype=torch.float64, device="cuda"), ws)
     else:
-        u, g, st = F.solve(pb, x0)
+        ws = F.workspace(pb, P)
+        u, g, st = F.solve(pb, x0, ws=ws)
     torch.cuda.synchronize()
-    print(f"{args.workload} {args.prec}: u[0]={u[0].item():.12g} nonzero status={int((st != 0).sum())}", flush=True)
+    # the rows the CG products streamed (device count; x d x element bytes = their algorithmic read bytes)
+    rows = F.workspace_cg_rows(ws)
+    esz = 4 if args.prec == "fp32c" else 8
+    print(f"{args.workload} {args.prec}: u[0]={u[0].item():.12g} nonzero status={int((st != 0).sum())} "
+          f"cg rows streamed={rows} algorithmic CG bytes={rows * kw['d'] * esz}", flush=True)
 
 
 if __name__ == "__main__":

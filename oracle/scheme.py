@@ -36,8 +36,10 @@ import scipy.linalg as sla
 
 from . import philox
 
-F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS = 0, 1, 2, 3
-G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC = 0, 1, 2, 3, 4
+F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS, F_HJ_SINK = 0, 1, 2, 3, 4
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC, G_HJ_GAUSS = 0, 1, 2, 3, 4, 5
+# families whose f depends on x (through a source term): Newton needs the particles' positions
+X_DEPENDENT_F = (F_HJ_SINK,)
 
 ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
 
@@ -67,14 +69,47 @@ class Problem:
         return replace(self, **kw)
 
 
+# ---------------------------------------------------------------- the Hamilton-Jacobi-type family
+# Sec. 4's Hamilton-Jacobi-type equation: a gradient-dependent sink R(u, grad u) = kappa u |grad u|^2 and
+# a source term chosen so that v(t, x) = (1 + 4t)^(-d/2) exp(-|x|^2 / (1 + 4t)) is the exact solution.
+# The printed forcing and equation do not reproduce that solution (the generator term is garbled and the
+# forcing's Gaussian factor lacks the 1 + 4t); the source below is re-derived for the problem class of
+# Sec. 2.1 with sigma = s I, so that v is exact (a reading of the paper).
+def hj_exact(d, t, r2):
+    """v(t, x) = (1 + 4t)^(-d/2) exp(-|x|^2 / (1 + 4t)) with r2 = |x|^2 (the printed exact solution).
+    It is the heat kernel started at t = -1/4, so v_t = Lap v."""
+    a = 1.0 + 4.0 * t
+    return np.exp(-0.5 * d * np.log(a) - np.asarray(r2, dtype=np.float64) / a)
+
+
+def hj_source(d, s, kappa, t, r2):
+    """S(t, x) such that v_t + (s^2/2) Lap v + S - kappa v |grad v|^2 = 0, and d S / d(r2).
+
+    With Lap v = v_t (v is a heat kernel), S = -(1 + s^2/2) v_t + kappa v |grad v|^2, where
+    v_t = v (-2d/a + 4 r2/a^2) and |grad v|^2 = 4 r2 v^2 / a^2, a = 1 + 4t.
+    """
+    r2 = np.asarray(r2, dtype=np.float64)
+    a = 1.0 + 4.0 * t
+    c = 1.0 + 0.5 * s * s
+    v = hj_exact(d, t, r2)
+    B = -2.0 * d / a + 4.0 * r2 / a ** 2
+    E = 4.0 * r2 / a ** 2
+    S = -c * v * B + kappa * v ** 3 * E
+    dv = -v / a
+    dS = -c * (dv * B + v * 4.0 / a ** 2) + kappa * (3.0 * v * v * dv * E + v ** 3 * 4.0 / a ** 2)
+    return S, dS
+
+
 # ---------------------------------------------------------------- f and g families
-def f_eval(pb, t, y, z):
+def f_eval(pb, t, y, z, X=None):
     """f(t, x, y, z) of the built-in families with d f/dy, d f/dz and d f/d(fp).
 
-    The families do not depend on t or x.  ALLEN_CAHN: c1 y - c3 y^3 (paper Sec. 4.1
-    Case 1 has c1 = c3 = 1); HJB: -lam |z|^2; BURGERS: c (y - kappa) sum_i z_i, the Burgers-type
-    nonlinearity of the paper's Sec. 4 experiments in a form whose logistic solution is exact (see
-    colehopf.burgers_coefficients).  y: array [M]; z: array [d].
+    ALLEN_CAHN: c1 y - c3 y^3 (paper Sec. 4.1 Case 1 has c1 = c3 = 1); HJB: -lam |z|^2; BURGERS:
+    c (y - kappa) sum_i z_i, the Burgers-type nonlinearity of the paper's Sec. 4 experiments in a form
+    whose logistic solution is exact (see colehopf.burgers_coefficients); HJ_SINK: the Hamilton-Jacobi-type
+    equation of Sec. 4, S(t, x) - kappa y |z|^2 / s^2 with kappa = fp0 (|z|^2 / s^2 = |grad u|^2) and the
+    source S of hj_source, the only family that depends on t and x (X [M, d]: the particles' positions).
+    y: array [M]; z: array [d].
     Returns (f [M], fy [M], fz [d] per unit of the factor fz_scale [M], fth [4, M]).
     """
     y = np.asarray(y, dtype=np.float64)
@@ -105,7 +140,30 @@ def f_eval(pb, t, y, z):
         fth[1] = np.full_like(y, -c * zs)
         # d f / d z_i = c (y - kappa) for every i: the vector c 1 scaled per particle by y - kappa
         return f, fy, np.full_like(z, c), y - kap, fth
+    if pb.f_kind == F_HJ_SINK:
+        if X is None:
+            raise ValueError("the HJ_SINK family depends on x: f_eval needs the particles' positions")
+        kap = pb.fp[0]
+        s2 = pb.s * pb.s
+        zz = float(z @ z)
+        r2 = np.einsum("ij,ij->i", X, X)
+        S, _ = hj_source(pb.d, pb.s, kap, t, r2)
+        f = S - kap * y * zz / s2
+        fy = np.full_like(y, -kap * zz / s2)
+        v = hj_exact(pb.d, t, r2)
+        a = 1.0 + 4.0 * t
+        fth[0] = v ** 3 * 4.0 * r2 / a ** 2 - y * zz / s2
+        # d f / d z = -2 kappa y z / s^2: the vector z scaled per particle by -2 kappa y / s^2
+        return f, fy, z.copy(), -2.0 * kap * y / s2, fth
     raise ValueError("unknown f kind")
+
+
+def f_grad_x(pb, t, y, z, x):
+    """grad_x f(t, x, y, z) at one point x [d] (zero for the families that do not depend on x)."""
+    if pb.f_kind == F_HJ_SINK:
+        _, dS = hj_source(pb.d, pb.s, pb.fp[0], t, float(x @ x))
+        return 2.0 * float(dS) * np.asarray(x, dtype=np.float64)
+    return np.zeros(pb.d)
 
 
 def g_eval(pb, X):
@@ -145,6 +203,13 @@ def g_eval(pb, X):
         g = np.log(den / 2.0)
         gx = (2.0 * a / den)[:, None] * X
         gth[0] = n2 / den
+        return g, gx, gth
+    if pb.g_kind == G_HJ_GAUSS:
+        # the Hamilton-Jacobi-type solution at time gp0 (= T): (1 + 4 gp0)^(-d/2) exp(-|x|^2 / (1 + 4 gp0))
+        a = 1.0 + 4.0 * pb.gp[0]
+        g = hj_exact(pb.d, pb.gp[0], n2)
+        gx = (-2.0 / a) * g[:, None] * X
+        gth[0] = g * (-2.0 * pb.d / a + 4.0 * n2 / a ** 2)
         return g, gx, gth
     raise ValueError("unknown g kind")
 
@@ -241,19 +306,20 @@ def llr(pb, W_next, Y_next, k):
     return dict(w=w, Wbar=Dbar / pb.s, Ybar=Ybar, alpha_x=alpha_x, alpha=alpha, sys=sysm)
 
 
-def newton(pb, k, C, Z):
-    """Fixed-count Newton on F(y) = y - C - dt f(t_k, X, y, Z), from y = C (paper eq. NRiter)."""
+def newton(pb, k, C, Z, X=None):
+    """Fixed-count Newton on F(y) = y - C - dt f(t_k, X, y, Z), from y = C (paper eq. NRiter).
+    X [M, d]: the particles' positions at t_k (used by the families whose f depends on x)."""
     dt = pb.T / pb.N
     y = np.array(C, dtype=np.float64)
     status = 0
     for _ in range(pb.newton_iters):
-        f, fy, _, _, _ = f_eval(pb, k * dt, y, Z)
+        f, fy, _, _, _ = f_eval(pb, k * dt, y, Z, X)
         F = y - C - dt * f
         Fp = 1.0 - dt * fy
         if np.any(np.abs(Fp) < 1e-12):
             status |= ST_NEWTON_FLAT
         y = y - F / Fp
-    _, fy, _, _, _ = f_eval(pb, k * dt, y, Z)
+    _, fy, _, _, _ = f_eval(pb, k * dt, y, Z, X)
     return y, 1.0 - dt * fy, status
 
 
@@ -277,15 +343,16 @@ def solve_point(pb, x0, p, tape=False):
         fit = llr(pb, W[k + 1], Y, k)
         C = fit["alpha"] + pb.s * (W[k] @ fit["alpha_x"])
         Z = pb.s * fit["alpha_x"]
-        Y, Fp, st = newton(pb, k, C, Z)
+        X = positions(pb, x0, W[k], k) if pb.f_kind in X_DEPENDENT_F else None
+        Y, Fp, st = newton(pb, k, C, Z, X)
         status |= st
         fit.update(C=C, Z=Z, Fp=Fp)
         levels[k] = fit
         Ys[k] = Y
     u = float(Y.mean())
-    # grad u(0, x0): x-derivative of y = alpha + alpha_x.(x - x0) + dt f(t_0, x, y, Z_0);
-    # the built-in f families do not depend on x.
-    grad = levels[0]["alpha_x"] / levels[0]["Fp"][0]
+    # grad u(0, x0): x-derivative of y = alpha + alpha_x.(x - x0) + dt f(t_0, x, y, Z_0) at x0, where
+    # every particle of level 0 sits
+    grad = (levels[0]["alpha_x"] + dt * f_grad_x(pb, 0.0, u, levels[0]["Z"], x0)) / levels[0]["Fp"][0]
     if not (np.isfinite(u) and np.all(np.isfinite(grad))):
         status |= ST_NONFINITE
     out = dict(u=u, grad=grad, status=status)
@@ -318,6 +385,8 @@ def adjoint_point(pb, x0, p, ubar=1.0):
       Ybar = sum_j w_j Y_j:           G^j_{k+1} += w_j Ybarbar.
     Terminal: x0bar += sum_j G^j_N grad g(X^j_N), gpbar += sum_j G^j_N dg/dgp.
     """
+    if pb.f_kind in X_DEPENDENT_F:
+        raise NotImplementedError("the reverse mode covers the families whose f does not depend on x")
     x0 = np.asarray(x0, dtype=np.float64)
     dt = pb.T / pb.N
     fw = solve_point(pb, x0, p, tape=True)
@@ -345,10 +414,14 @@ def adjoint_point(pb, x0, p, ubar=1.0):
 
 
 # ---------------------------------------------------------------- one level on given state
-def level_step(pb, k, W_next, W_k, Y_next):
-    """One backward level on a given cloud: returns alpha, alpha_x, Y_k, F'(Y_k)."""
+def level_step(pb, k, W_next, W_k, Y_next, x0=None):
+    """One backward level on a given cloud: returns alpha, alpha_x, Y_k, F'(Y_k).  x0 [d] (default 0) is
+    used only by the families whose f depends on x."""
     fit = llr(pb, W_next, Y_next, k)
     C = fit["alpha"] + pb.s * (W_k @ fit["alpha_x"])
-    Y, Fp, st = newton(pb, k, C, pb.s * fit["alpha_x"])
+    X = None
+    if pb.f_kind in X_DEPENDENT_F:
+        X = positions(pb, np.zeros(pb.d) if x0 is None else np.asarray(x0, dtype=np.float64), W_k, k)
+    Y, Fp, st = newton(pb, k, C, pb.s * fit["alpha_x"], X)
     return dict(alpha=fit["alpha"], alpha_x=fit["alpha_x"], Y=Y, Fp=Fp, status=st, w=fit["w"],
                 Wbar=fit["Wbar"], Ybar=fit["Ybar"])

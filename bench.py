@@ -347,6 +347,31 @@ def main():
             "cg_iters_per_level": it3f, "adjoint_cg_iters_per_level": it3a}
         log(f"[bench] d = 10^4, 128 points fwd+adj: {sec3 * 1e3:.1f} ms")
         del ws3, x3
+        # the Hamilton-Jacobi-type equation at the shape of the paper's runtime table (d = 500, T = 0.5,
+        # M = 100, x = 0, dt = 0.0005 and dt / 2^4), 64 independent replicas of the point, FP64; its exact
+        # solution at (0, 0) is 1
+        hj = {}
+        for Nh in (1000, 16000):
+            pbh = F.Problem(d=500, M=100, N=Nh, T=0.5, f_kind=F.F_HJ_SINK, fp=(0.1, 0, 0, 0), g_kind=F.G_HJ_GAUSS,
+                            gp=(0.5, 0, 0, 0), seed=0, instance=9)
+            xh = torch.zeros((64, 500), dtype=torch.float64, device=dev)
+            wsh = F.workspace(pbh, 64, device=dev)
+            F.solve(pbh, xh, ws=wsh)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uh, _, sth = F.solve(pbh, xh, ws=wsh)
+            torch.cuda.synchronize()
+            sech = time.perf_counter() - t0
+            uh = uh.cpu().numpy()
+            hj[f"N{Nh}"] = {"value": round(64 / sech, 2), "unit": "points/s", "ms_per_step": round(sech * 1e3, 2),
+                            "u_mean": round(float(uh.mean()), 6), "u_sd": round(float(uh.std()), 6),
+                            "u_exact": 1.0, "rel_err_vs_exact": round(abs(float(uh.mean()) - 1.0), 5),
+                            "status_nonzero_points": int((sth != 0).sum().item()),
+                            "paper_cpu_s_per_point_context": 185.06 if Nh == 1000 else 3016.35}
+            log(f"[bench] HJ-type d=500 M=100 N={Nh} P=64 (FP64): {sech * 1e3:.1f} ms, u = {uh.mean():.5f} "
+                f"(exact 1)")
+            del wsh, xh
+        small["hj_type_d500_M100_T0.5_P64_fp64"] = hj
 
     # ---------------- paper-literal per-anchor scheme at the paper's Burgers runtime setting:
     # d = 10^4, M = 100, dt = 0.003 (N = 100), T = 0.3, x0 = 0, as 64 independent replicas of the point

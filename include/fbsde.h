@@ -68,14 +68,25 @@ enum { FBSDE_F64 = 0, FBSDE_F32C = 1 };       /* FP64 everywhere | FP32 state + 
 enum { FBSDE_F_ZERO = 0,                      /* f = 0 (heat)                                  */
        FBSDE_F_ALLEN_CAHN = 1,                /* f = fp0 y - fp1 y^3 (Sec. 4.1 Case 1: 1, 1)  */
        FBSDE_F_HJB = 2,                       /* f = -fp0 |z|^2, z = sigma^T grad u            */
-       FBSDE_F_BURGERS = 3 };                 /* f = fp0 (y - fp1) sum_i z_i (Burgers type, Sec.
+       FBSDE_F_BURGERS = 3,                   /* f = fp0 (y - fp1) sum_i z_i (Burgers type, Sec.
                                                  4; with fp0 = s/d, fp1 = d/s^2 + 1/2 and the
                                                  logistic g below, u = logistic(t + sum x / d)) */
+       FBSDE_F_HJ_SINK = 4 };                 /* f = S(t, x) - fp0 y |z|^2 / s^2: the Hamilton-
+                                                 Jacobi-type equation of Sec. 4, sink kappa u
+                                                 |grad u|^2 (kappa = fp0) and the source S that
+                                                 makes v = (1+4t)^(-d/2) exp(-|x|^2/(1+4t)) exact
+                                                 for v_t + (s^2/2) Lap v + f = 0 (with Lap v = v_t,
+                                                 S = -(1 + s^2/2) v_t + kappa v |grad v|^2).  The
+                                                 only family that depends on x: per-point solves
+                                                 (fbsde_solve, _solve_step, _solve_noalloc, tiled
+                                                 batches) only, forward only                      */
 enum { FBSDE_G_QUAD = 0,                      /* g = gp0 |x|^2 / d + gp1                       */
        FBSDE_G_AC = 1,                        /* g = 1 / (2 + gp0 |x|^2)   (Sec. 4.1 Case 1)   */
        FBSDE_G_HJB_LOG = 2,                   /* g = ln((1 + gp0 |x|^2) / 2)                   */
        FBSDE_G_AFFINE = 3,                    /* g = gvec . x + gp0                            */
-       FBSDE_G_LOGISTIC = 4 };                /* g = 1 / (1 + exp(-(gvec . x + gp0)))          */
+       FBSDE_G_LOGISTIC = 4,                  /* g = 1 / (1 + exp(-(gvec . x + gp0)))          */
+       FBSDE_G_HJ_GAUSS = 5 };                /* g = (1 + 4 gp0)^(-d/2) exp(-|x|^2 / (1 + 4 gp0)):
+                                                 the HJ-type solution at time gp0 (= T)           */
 enum { FBSDE_OK = 0, FBSDE_EINVAL = -1, FBSDE_ENOSPC = -2, FBSDE_EHIP = -3, FBSDE_ESTATE = -4 };
 enum { FBSDE_ST_CG_MAXIT = 1, FBSDE_ST_NEWTON_FLAT = 2, FBSDE_ST_NONFINITE = 4,
        FBSDE_ST_WAIT_LIMIT = 8 };              /* a bounded device-side wait of the CG loop gave

@@ -344,15 +344,21 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
 template <typename S>
 void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S* W, int64_t ldw, const double* ax,
                     WS& ws, double* Y, double* rn2, uint32_t* status, hipStream_t st, double* dydc = nullptr,
-                    const double* scal = nullptr, int shared = 0) {
+                    const double* scal = nullptr, int shared = 0, const double* x0 = nullptr) {
     const Keys ky = keys_of(pb);
     const double dt = pb->T / (double)pb->N;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        hipLaunchKernelGGL((k_reverse<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
-                           ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0, std::sqrt(dt),
-                           pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters, ky.k0, ky.k1,
-                           pb->point_base, Y, rn2, dydc, status, shared);
+        if (f_depends_on_x(pb))   // the particles' positions x0 + t_k mu + s W_k enter f
+            hipLaunchKernelGGL((k_reverse<S, QQ, TT, true>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
+                               std::sqrt(dt), pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters,
+                               ky.k0, ky.k1, pb->point_base, Y, rn2, dydc, status, shared, x0, pb->mu, (double)k * dt);
+        else
+            hipLaunchKernelGGL((k_reverse<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                               ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0, std::sqrt(dt),
+                               pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters, ky.k0, ky.k1,
+                               pb->point_base, Y, rn2, dydc, status, shared, nullptr, nullptr, 0.0);
     });
 }
 
@@ -409,12 +415,12 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
         }
         if (k > 0) {
             double* Yout = tape ? ws.tY + (size_t)k * PM : Yk;
-            launch_reverse<S>(pb, pl, P, k, W, ldw, ws.x, ws, Yout, ws.rn2, status, st, ws.c2);
+            launch_reverse<S>(pb, pl, P, k, W, ldw, ws.x, ws, Yout, ws.rn2, status, st, ws.c2, nullptr, 0, x0);
             if (!tape) std::swap(Ycur, Yk);
             else Ycur = Yout;
         } else {
             hipLaunchKernelGGL(k_outputs, dim3((unsigned)P), dim3(256), 0, st, ws.x, pl.ld, (int)pl.d, ws.scal, NS,
-                               fspec_of(pb), pb->T / (double)pb->N, pb->newton_iters, u, grad, status);
+                               fspec_of(pb), pb->T / (double)pb->N, pb->newton_iters, u, grad, status, x0, pb->s);
         }
         err = last_error();
         if (err) return err;
@@ -662,7 +668,6 @@ int fbsde_terminal(const fbsde_problem* pb, int64_t P, const double* x0, void* W
 int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double* x0, void* W, int64_t ldw,
                      const double* Y_next, double* Y, double* alpha, double* alpha_x, uint32_t* status, void* wsp,
                      size_t ws_bytes, fbsde_stream stream) {
-    (void)x0;
     int rc = check_problem(pb, P);
     if (rc) return rc;
     if (pb->shared_dw) return FBSDE_EINVAL;   // the shared form runs only as a whole solve
@@ -681,13 +686,13 @@ int fbsde_solve_step(const fbsde_problem* pb, int64_t P, int32_t k, const double
         launch_rownorm<double>(pl, P, Ws, ldw, ws.rn2, st);
         run_level<double>(pb, pl, P, k, Ws, ldw, Y_next, ws.rn2, ws.w, ws.Wbar, ws, alpha, alpha_x, status, st, err);
         if (err) return err;
-        launch_reverse<double>(pb, pl, P, k, Ws, ldw, ws.x, ws, Y, ws.rn2, status, st);
+        launch_reverse<double>(pb, pl, P, k, Ws, ldw, ws.x, ws, Y, ws.rn2, status, st, nullptr, nullptr, 0, x0);
     } else {
         float* Ws = (float*)W;
         launch_rownorm<float>(pl, P, Ws, ldw, ws.rn2, st);
         run_level<float>(pb, pl, P, k, Ws, ldw, Y_next, ws.rn2, ws.w, ws.Wbar, ws, alpha, alpha_x, status, st, err);
         if (err) return err;
-        launch_reverse<float>(pb, pl, P, k, Ws, ldw, ws.x, ws, Y, ws.rn2, status, st);
+        launch_reverse<float>(pb, pl, P, k, Ws, ldw, ws.x, ws, Y, ws.rn2, status, st, nullptr, nullptr, 0, x0);
     }
     return last_error();
 }
@@ -705,6 +710,7 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     }
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
+        if (f_depends_on_x(pb)) return FBSDE_EINVAL;   // the per-point form evaluates x-dependent f
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solve
         return solve_shared(pb, P, x0, u, grad, status, wsp, ws_bytes, flags, (hipStream_t)stream);
@@ -728,6 +734,7 @@ int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const d
                    int32_t* cg_iters_out, fbsde_stream stream, bool check_tape) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
+    if (f_depends_on_x(pb)) return FBSDE_EINVAL;   // the reverse mode covers f independent of x
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!gp_bar || !fp_bar) return FBSDE_EINVAL;
@@ -739,6 +746,7 @@ int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const d
     }
     if (!x0 || !u_bar || !x0_bar || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
+        if (f_depends_on_x(pb)) return FBSDE_EINVAL;   // the per-point form evaluates x-dependent f
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solves
         return backward_shared(pb, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, wsp, ws_bytes, (hipStream_t)stream);

@@ -223,8 +223,8 @@ __device__ __forceinline__ double block_min(double v, double* lds) {
 }
 
 // ------------------------------------------------------------------ f, g, Newton
-enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2, F_BURGERS = 3 };
-enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3, G_LOGISTIC = 4 };
+enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2, F_BURGERS = 3, F_HJ_SINK = 4 };
+enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3, G_LOGISTIC = 4, G_HJ_GAUSS = 5 };
 
 // g families whose argument is q = gvec . X (the others take q = |X|^2)
 __device__ __forceinline__ bool g_dot_arg(int kind) { return kind == G_AFFINE || kind == G_LOGISTIC; }
@@ -240,11 +240,31 @@ struct FSpec { int kind; double p0, p1; };
 // f(t, x, y, z) and d f / d y of the built-in families; zz = |z|^2 and zs = sum_i z_i (z shared by the
 // cloud).  BURGERS: fp0 (y - fp1) sum_i z_i, the Burgers-type nonlinearity of the Sec. 4 experiments in
 // a form whose logistic solution is exact (fp0 = s/d, fp1 = d/s^2 + 1/2).
+// HJ_SINK: the sink -fp0 y |z|^2 / s^2 with p1 = 1 / s^2; its x-dependent source S(t, x) does not depend
+// on y and enters Newton through C (hj_source).
 __device__ __forceinline__ void f_and_fy(const FSpec& f, double y, double zz, double zs, double& fv, double& fy) {
     if (f.kind == F_ALLEN_CAHN) { fv = f.p0 * y - f.p1 * y * y * y; fy = f.p0 - 3.0 * f.p1 * y * y; }
     else if (f.kind == F_HJB) { fv = -f.p0 * zz; fy = 0.0; }
     else if (f.kind == F_BURGERS) { fv = f.p0 * (y - f.p1) * zs; fy = f.p0 * zs; }
+    else if (f.kind == F_HJ_SINK) { fv = -f.p0 * f.p1 * y * zz; fy = -f.p0 * f.p1 * zz; }
     else { fv = 0.0; fy = 0.0; }
+}
+
+// Source of the Hamilton-Jacobi-type family at time t and r2 = |x|^2, and its derivative in r2: with
+// v = a^(-d/2) exp(-r2/a), a = 1 + 4t (a heat kernel: Lap v = v_t), the source that makes v exact for
+// v_t + (s^2/2) Lap v + S - kappa v |grad v|^2 = 0 is S = -(1 + s^2/2) v_t + kappa v |grad v|^2, where
+// v_t = v (-2d/a + 4 r2/a^2) and |grad v|^2 = 4 r2 v^2 / a^2.
+__device__ __forceinline__ double hj_source(double t, double r2, double d, double s, double kappa, double* dS) {
+    const double a = 1.0 + 4.0 * t, ia = 1.0 / a;
+    const double c = 1.0 + 0.5 * s * s;
+    const double v = exp(-0.5 * d * log(a) - r2 * ia);
+    const double B = -2.0 * d * ia + 4.0 * r2 * ia * ia;
+    const double E = 4.0 * r2 * ia * ia;
+    if (dS) {
+        const double dv = -v * ia;
+        *dS = -c * (dv * B + v * 4.0 * ia * ia) + kappa * (3.0 * v * v * dv * E + v * v * v * 4.0 * ia * ia);
+    }
+    return -c * v * B + kappa * v * v * v * E;
 }
 
 // Fixed-count Newton for F(y) = y - C - dt f(y) from y = C; returns y and F'(y).
@@ -270,6 +290,7 @@ __device__ __forceinline__ double g_of(int kind, double a, double b, double q, i
     if (kind == G_AC) return 1.0 / (2.0 + a * q);
     if (kind == G_HJB_LOG) return log((1.0 + a * q) * 0.5);
     if (kind == G_LOGISTIC) return 1.0 / (1.0 + exp(-(q + a)));   // a = offset
+    if (kind == G_HJ_GAUSS) return exp(-0.5 * (double)d * log1p(4.0 * a) - q / (1.0 + 4.0 * a));
     return q + a;   // G_AFFINE: q = gvec . X, a = offset
 }
 

@@ -486,13 +486,16 @@ k_level_finish(const double* __restrict__ x, const double* __restrict__ Wbar, in
 // Particle reversal W_k = W_{k+1} - sqrt(dt) xi_k (Philox regenerated, in place) fused with the
 // per-particle dots |W_k|^2 and alpha_x . W_k, the local linear model C = alpha + s alpha_x . W_k
 // and the Newton solve for Y_k (eqs. nonlinearf / NRiter).  zero_state: level 0, W_0 = 0.
-template <typename S, int Q, int TEAM>
+// XR: f has the x-dependent source of the Hamilton-Jacobi-type family, evaluated at the particle's
+// position X = b + s W_k with b = x0 + t_k mu (a third row dot b . W_k gives |X|^2), and added to C.
+template <typename S, int Q, int TEAM, bool XR = false>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int ld, int k, int zero_state,
           double sqdt, double s, double dt, const double* __restrict__ ax, const double* __restrict__ scal,
           int ns, FSpec f, int newton_iters, uint32_t k0, uint32_t k1, uint32_t point_base,
           double* __restrict__ Y, double* __restrict__ rn2, double* __restrict__ dydc, uint32_t* __restrict__ status,
-          int shared) {
+          int shared, const double* __restrict__ x0 = nullptr, const double* __restrict__ mu = nullptr,
+          double tk = 0.0) {
     using G = Geo<Q, TEAM>;
     using R = S;
     __shared__ double red[2 * G::BS / 64];
@@ -511,6 +514,22 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     const double alpha = scal[(int64_t)p * ns + 5];
     const double zz = scal[(int64_t)p * ns + 6], zs = scal[(int64_t)p * ns + 8];
     uint32_t st = 0;
+    R b[Q][4];        // XR: the lane's coordinates of b = x0 + t_k mu
+    double bb = 0.0;  // XR: |b|^2
+    if constexpr (XR) {
+        double lb = 0.0, unused = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 4 * (L + q * G::TL) + e;
+                const double v = (i < d) ? (x0 ? x0[(int64_t)p * d + i] : 0.0) + (mu ? mu[i] * tk : 0.0) : 0.0;
+                b[q][e] = (R)v;
+                lb += v * v;
+            }
+        team_sum2<TEAM>(lb, unused, red, team);
+        bb = lb;
+    }
     // Newton runs 64 rows at a time: lane (row count mod 64) of the team's first wave keeps the row's
     // C and |W|^2, and every 64 rows those lanes solve together instead of one lane per row
     int j_keep = -1;
@@ -529,7 +548,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     for (int jb = r0; jb < r1; jb += G::TPW) {
         const int j = jb + team;
         const bool valid = j < r1;
-        CSum<R> n2s, dots;
+        CSum<R> n2s, dots, xbs;
         if (valid) {
             S* row = W + ((int64_t)p * M + j) * ldw;
 #pragma unroll
@@ -554,14 +573,24 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
                     store4(row + e0, v);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) { n2s.add(v[e] * v[e]); dots.add(a[q][e] * v[e]); }
+                    if constexpr (XR) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) xbs.add(b[q][e] * v[e]);
+                    }
                 }
             }
         }
         double n2 = n2s.get(), dt_ = dots.get();
         team_sum2<TEAM>(n2, dt_, red, team);
+        double src = 0.0;
+        if constexpr (XR) {
+            double xb = xbs.get(), unused = 0.0;
+            team_sum2<TEAM>(xb, unused, red, team);
+            src = dt * hj_source(tk, bb + 2.0 * s * xb + s * s * n2, (double)d, s, f.p0, nullptr);
+        }
         if (valid && L == (cnt & 63)) {
             j_keep = j;
-            c_keep = alpha + s * dt_;
+            c_keep = alpha + s * dt_ + src;
             n2_keep = n2;
         }
         if ((++cnt & 63) == 0) flush();
@@ -571,20 +600,32 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
 }
 
 // Level-0 outputs: u = Y^m_0 (every particle sits at x0, so C = alpha) and
-// grad u = alpha_x / F'(u) (the x-derivative of the level-0 Newton equation).
+// grad u = (alpha_x + dt grad_x f) / F'(u) (the x-derivative of the level-0 Newton equation).  x0: the
+// points [P][d], read only when f depends on x (the HJ-type source at t = 0 and |x0|^2, added to C, and
+// its x-gradient 2 x0 dS/d|x|^2).
 __global__ void __launch_bounds__(256)
 k_outputs(const double* __restrict__ x, int ld, int d, const double* __restrict__ scal, int ns, FSpec f,
           double dt, int newton_iters, double* __restrict__ u, double* __restrict__ grad,
-          uint32_t* __restrict__ status) {
+          uint32_t* __restrict__ status, const double* __restrict__ x0 = nullptr, double s = 0.0) {
+    __shared__ double lds[16];
     const int p = blockIdx.x;
     uint32_t st = 0;
+    double src = 0.0, dsrc = 0.0;
+    if (f.kind == F_HJ_SINK) {
+        double r2 = 0.0;
+        if (x0)
+            for (int i = threadIdx.x; i < d; i += blockDim.x) r2 += x0[(int64_t)p * d + i] * x0[(int64_t)p * d + i];
+        r2 = block_sum(r2, lds);
+        src = hj_source(0.0, r2, (double)d, s, f.p0, &dsrc);
+    }
     double Fp;
-    const double y = newton_y(f, scal[(int64_t)p * ns + 5], scal[(int64_t)p * ns + 6], scal[(int64_t)p * ns + 8], dt,
-                              newton_iters, Fp, st);
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5] + dt * src, scal[(int64_t)p * ns + 6],
+                              scal[(int64_t)p * ns + 8], dt, newton_iters, Fp, st);
     if (threadIdx.x == 0) u[p] = y;
     if (grad)
         for (int i = threadIdx.x; i < d; i += blockDim.x) {
-            const double gi = x[(int64_t)p * ld + i] / Fp;
+            const double gx = (f.kind == F_HJ_SINK && x0) ? 2.0 * dsrc * x0[(int64_t)p * d + i] : 0.0;
+            const double gi = (x[(int64_t)p * ld + i] + dt * gx) / Fp;
             grad[(int64_t)p * d + i] = gi;
             if (!isfinite(gi)) st |= ST_NONFINITE;
         }

@@ -28,6 +28,7 @@ in the design notes of the repository):
 The linear solve is direct (Cholesky): primal d x d when M > d, otherwise the dual
 M x M form (push-through identity), which needs lambda > 0.
 """
+import math
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
@@ -36,10 +37,10 @@ import scipy.linalg as sla
 
 from . import philox
 
-F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS, F_HJ_SINK = 0, 1, 2, 3, 4
-G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC, G_HJ_GAUSS = 0, 1, 2, 3, 4, 5
+F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS, F_HJ_SINK, F_LOG_POT = 0, 1, 2, 3, 4, 5
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC, G_HJ_GAUSS, G_CASE2 = 0, 1, 2, 3, 4, 5, 6
 # families whose f depends on x (through a source term): Newton needs the particles' positions
-X_DEPENDENT_F = (F_HJ_SINK,)
+X_DEPENDENT_F = (F_HJ_SINK, F_LOG_POT)
 
 ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE = 1, 2, 4
 
@@ -100,6 +101,71 @@ def hj_source(d, s, kappa, t, r2):
     return S, dS
 
 
+# ---------------------------------------------------------------- Allen-Cahn Case 2 (log potential)
+# Sec. 4.1 Case 2: f(u) = (theta/2) ln((1 + u)/(1 - u)) - theta_c u with theta < theta_c, and a source that
+# makes the manufactured solution v = cos(prod_j x_j) e^(cos t - |x|^2) exact.  The printed v reaches e > 1
+# at the origin, outside the potential's domain |u| < 1; the solution built here carries an amplitude a
+# (v = a cos(P) e^(cos t - |x|^2), a < 1/e), a reading of the paper.  With P = prod_j x_j and
+# Q2 = sum_i prod_{j != i} x_j^2:
+#   v_t = -sin(t) v,
+#   Lap v = a e^(cos t - |x|^2) (-cos(P) Q2 + 4 d P sin(P) + cos(P) (4 |x|^2 - 2 d)),
+# and the source S2 = v_t + (s^2/2) Lap v + F(v) makes v exact for u_t + (s^2/2) Lap u + F(u) - S2 = 0.
+def leave_one_out_products(X):
+    """prod_{j != i} X[..., j] for every i: the product of the coordinates before i times those after i."""
+    X = np.asarray(X, dtype=np.float64)
+    ones = np.ones(X.shape[:-1] + (1,))
+    before = np.concatenate([ones, np.cumprod(X[..., :-1], axis=-1)], axis=-1)
+    after = np.concatenate([np.cumprod(X[..., :0:-1], axis=-1)[..., ::-1], ones], axis=-1)
+    return before * after
+
+
+def log_potential(theta, theta_c, u):
+    """F(u) = (theta/2) ln((1 + u)/(1 - u)) - theta_c u and F'(u) = theta / (1 - u^2) - theta_c."""
+    u = np.asarray(u, dtype=np.float64)
+    return 0.5 * theta * np.log((1.0 + u) / (1.0 - u)) - theta_c * u, theta / (1.0 - u * u) - theta_c
+
+
+def case2_exact(amp, t, X):
+    """v(t, x) = amp cos(prod_j x_j) e^(cos t - |x|^2) for X [M, d]."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    return amp * np.cos(np.prod(X, axis=1)) * np.exp(np.cos(t) - np.einsum("ij,ij->i", X, X))
+
+
+def case2_source(d, s, theta, theta_c, amp, t, X):
+    """S2(t, x) = v_t + (s^2/2) Lap v + F(v) at the rows of X [M, d]."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    P = np.prod(X, axis=1)
+    Q2 = np.sum(leave_one_out_products(X * X), axis=1)
+    r2 = np.einsum("ij,ij->i", X, X)
+    w = np.exp(np.cos(t) - r2)
+    v = amp * np.cos(P) * w
+    lap = amp * w * (-np.cos(P) * Q2 + 4.0 * d * P * np.sin(P) + np.cos(P) * (4.0 * r2 - 2.0 * d))
+    Fv, _ = log_potential(theta, theta_c, v)
+    return -np.sin(t) * v + 0.5 * s * s * lap + Fv
+
+
+def case2_source_grad(d, s, theta, theta_c, amp, t, x):
+    """grad_x S2(t, x) at one point x [d], from the derivatives of P, Q2, |x|^2 and v written out:
+    d_k P = P_k, d_k Q2 = 2 x_k Q2^(k) (P_k, Q2^(k): P and Q2 of the coordinates other than k)."""
+    x = np.asarray(x, dtype=np.float64)
+    P = float(np.prod(x))
+    Pk = leave_one_out_products(x)
+    Q2 = float(np.sum(leave_one_out_products(x * x)))
+    Q2k = np.array([np.sum(leave_one_out_products(np.delete(x, k) ** 2)) if d > 1 else 0.0 for k in range(d)])
+    r2 = float(x @ x)
+    w = math.exp(math.cos(t) - r2)
+    cP, sP = math.cos(P), math.sin(P)
+    v = amp * cP * w
+    D = -cP * Q2 + 4.0 * d * P * sP + cP * (4.0 * r2 - 2.0 * d)
+    dw = -2.0 * x * w
+    dv = amp * w * (-sP * Pk - 2.0 * x * cP)
+    dD = (sP * Pk * Q2 - cP * 2.0 * x * Q2k + 4.0 * d * (Pk * sP + P * cP * Pk) - sP * Pk * (4.0 * r2 - 2.0 * d)
+          + cP * 8.0 * x)
+    dlap = amp * (dw * D + w * dD)
+    _, dF = log_potential(theta, theta_c, v)
+    return -math.sin(t) * dv + 0.5 * s * s * dlap + dF * dv
+
+
 # ---------------------------------------------------------------- f and g families
 def f_eval(pb, t, y, z, X=None):
     """f(t, x, y, z) of the built-in families with d f/dy, d f/dz and d f/d(fp).
@@ -108,8 +174,9 @@ def f_eval(pb, t, y, z, X=None):
     c (y - kappa) sum_i z_i, the Burgers-type nonlinearity of the paper's Sec. 4 experiments in a form
     whose logistic solution is exact (see colehopf.burgers_coefficients); HJ_SINK: the Hamilton-Jacobi-type
     equation of Sec. 4, S(t, x) - kappa y |z|^2 / s^2 with kappa = fp0 (|z|^2 / s^2 = |grad u|^2) and the
-    source S of hj_source, the only family that depends on t and x (X [M, d]: the particles' positions).
-    y: array [M]; z: array [d].
+    source S of hj_source; LOG_POT: Allen-Cahn Case 2, F(y) - S2(t, x) with theta = fp0, theta_c = fp1 and
+    the amplitude fp2 of the manufactured solution.  HJ_SINK and LOG_POT depend on t and x (X [M, d]: the
+    particles' positions).  y: array [M]; z: array [d].
     Returns (f [M], fy [M], fz [d] per unit of the factor fz_scale [M], fth [4, M]).
     """
     y = np.asarray(y, dtype=np.float64)
@@ -155,6 +222,13 @@ def f_eval(pb, t, y, z, X=None):
         fth[0] = v ** 3 * 4.0 * r2 / a ** 2 - y * zz / s2
         # d f / d z = -2 kappa y z / s^2: the vector z scaled per particle by -2 kappa y / s^2
         return f, fy, z.copy(), -2.0 * kap * y / s2, fth
+    if pb.f_kind == F_LOG_POT:
+        if X is None:
+            raise ValueError("the LOG_POT family depends on x: f_eval needs the particles' positions")
+        th, thc, amp = pb.fp[0], pb.fp[1], pb.fp[2]
+        Fy, dF = log_potential(th, thc, y)
+        f = Fy - case2_source(pb.d, pb.s, th, thc, amp, t, X)
+        return f, dF, np.zeros_like(z), zero, fth
     raise ValueError("unknown f kind")
 
 
@@ -163,6 +237,8 @@ def f_grad_x(pb, t, y, z, x):
     if pb.f_kind == F_HJ_SINK:
         _, dS = hj_source(pb.d, pb.s, pb.fp[0], t, float(x @ x))
         return 2.0 * float(dS) * np.asarray(x, dtype=np.float64)
+    if pb.f_kind == F_LOG_POT:
+        return -case2_source_grad(pb.d, pb.s, pb.fp[0], pb.fp[1], pb.fp[2], t, x)
     return np.zeros(pb.d)
 
 
@@ -210,6 +286,15 @@ def g_eval(pb, X):
         g = hj_exact(pb.d, pb.gp[0], n2)
         gx = (-2.0 / a) * g[:, None] * X
         gth[0] = g * (-2.0 * pb.d / a + 4.0 * n2 / a ** 2)
+        return g, gx, gth
+    if pb.g_kind == G_CASE2:
+        # the Case 2 manufactured solution at time gp0 (= T) with amplitude gp1
+        T_, amp = pb.gp[0], pb.gp[1]
+        P = np.prod(X, axis=1)
+        w = np.exp(np.cos(T_) - n2)
+        g = amp * np.cos(P) * w
+        gx = amp * w[:, None] * (-np.sin(P)[:, None] * leave_one_out_products(X) - 2.0 * np.cos(P)[:, None] * X)
+        gth[1] = np.cos(P) * w
         return g, gx, gth
     raise ValueError("unknown g kind")
 

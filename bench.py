@@ -372,6 +372,32 @@ def main():
                 f"(exact 1)")
             del wsh, xh
         small["hj_type_d500_M100_T0.5_P64_fp64"] = hj
+        # Allen-Cahn Case 2 (log potential, theta = 0.8 < theta_c = 1.6, manufactured solution
+        # 0.25 cos(prod x) e^(cos t - |x|^2)) at the paper's T = 1 and evaluation points x = 0 and (0.1, ..., 0.1):
+        # d = 100 at dt = 0.002 / 2^4 (N = 8000) and d = 1000 at dt = 0.0005 / 2^2 (N = 8000), M = 100, FP64
+        c2 = {}
+        for dc, xv in ((100, 0.0), (100, 0.1), (1000, 0.0)):
+            pbc = F.Problem(d=dc, M=100, N=8000, T=1.0, f_kind=F.F_LOG_POT, fp=(0.8, 1.6, 0.25, 0), g_kind=F.G_CASE2,
+                            gp=(1.0, 0.25, 0, 0), seed=0, instance=8)
+            xc = torch.full((64, dc), xv, dtype=torch.float64, device=dev)
+            wsc = F.workspace(pbc, 64, device=dev)
+            F.solve(pbc, xc, ws=wsc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uc, _, stc = F.solve(pbc, xc, ws=wsc)
+            torch.cuda.synchronize()
+            secc = time.perf_counter() - t0
+            uc = uc.cpu().numpy()
+            exact = 0.25 * math.cos(xv ** dc) * math.exp(1.0 - dc * xv * xv)
+            c2[f"d{dc}_x{xv}"] = {"value": round(64 / secc, 2), "unit": "points/s", "ms_per_step": round(secc * 1e3, 2),
+                                  "u_mean": round(float(uc.mean()), 6), "u_sd": round(float(uc.std()), 6),
+                                  "u_exact": round(exact, 6),
+                                  "rel_err_vs_exact": round(abs(float(uc.mean()) - exact) / exact, 5),
+                                  "status_nonzero_points": int((stc != 0).sum().item())}
+            log(f"[bench] Case 2 d={dc} x={xv} M=100 N=8000 P=64 (FP64): {secc * 1e3:.1f} ms, u = {uc.mean():.5f} "
+                f"(exact {exact:.5f})")
+            del wsc, xc
+        small["allen_cahn_case2_M100_N8000_T1_P64_fp64"] = c2
 
     # ---------------- paper-literal per-anchor scheme at the paper's Burgers runtime setting:
     # d = 10^4, M = 100, dt = 0.003 (N = 100), T = 0.3, x0 = 0, as 64 independent replicas of the point

@@ -71,7 +71,7 @@ enum { FBSDE_F_ZERO = 0,                      /* f = 0 (heat)                   
        FBSDE_F_BURGERS = 3,                   /* f = fp0 (y - fp1) sum_i z_i (Burgers type, Sec.
                                                  4; with fp0 = s/d, fp1 = d/s^2 + 1/2 and the
                                                  logistic g below, u = logistic(t + sum x / d)) */
-       FBSDE_F_HJ_SINK = 4 };                 /* f = S(t, x) - fp0 y |z|^2 / s^2: the Hamilton-
+       FBSDE_F_HJ_SINK = 4,                   /* f = S(t, x) - fp0 y |z|^2 / s^2: the Hamilton-
                                                  Jacobi-type equation of Sec. 4, sink kappa u
                                                  |grad u|^2 (kappa = fp0) and the source S that
                                                  makes v = (1+4t)^(-d/2) exp(-|x|^2/(1+4t)) exact
@@ -80,13 +80,21 @@ enum { FBSDE_F_ZERO = 0,                      /* f = 0 (heat)                   
                                                  only family that depends on x: per-point solves
                                                  (fbsde_solve, _solve_step, _solve_noalloc, tiled
                                                  batches) only, forward only                      */
+       FBSDE_F_LOG_POT = 5 };                 /* f = (fp0/2) ln((1+y)/(1-y)) - fp1 y - S2(t, x):
+                                                 Allen-Cahn Case 2 (Sec. 4.1), log potential with
+                                                 theta = fp0 < theta_c = fp1, and the source S2 that
+                                                 makes v = fp2 cos(prod_j x_j) e^(cos t - |x|^2)
+                                                 exact (amplitude fp2 < 1/e keeps |v| < 1).  Depends
+                                                 on x: the same paths as FBSDE_F_HJ_SINK          */
 enum { FBSDE_G_QUAD = 0,                      /* g = gp0 |x|^2 / d + gp1                       */
        FBSDE_G_AC = 1,                        /* g = 1 / (2 + gp0 |x|^2)   (Sec. 4.1 Case 1)   */
        FBSDE_G_HJB_LOG = 2,                   /* g = ln((1 + gp0 |x|^2) / 2)                   */
        FBSDE_G_AFFINE = 3,                    /* g = gvec . x + gp0                            */
        FBSDE_G_LOGISTIC = 4,                  /* g = 1 / (1 + exp(-(gvec . x + gp0)))          */
-       FBSDE_G_HJ_GAUSS = 5 };                /* g = (1 + 4 gp0)^(-d/2) exp(-|x|^2 / (1 + 4 gp0)):
+       FBSDE_G_HJ_GAUSS = 5,                  /* g = (1 + 4 gp0)^(-d/2) exp(-|x|^2 / (1 + 4 gp0)):
                                                  the HJ-type solution at time gp0 (= T)           */
+       FBSDE_G_CASE2 = 6 };                   /* g = gp1 cos(prod_j x_j) e^(cos gp0 - |x|^2): the
+                                                 Case 2 solution at time gp0 (= T)                */
 enum { FBSDE_OK = 0, FBSDE_EINVAL = -1, FBSDE_ENOSPC = -2, FBSDE_EHIP = -3, FBSDE_ESTATE = -4 };
 enum { FBSDE_ST_CG_MAXIT = 1, FBSDE_ST_NEWTON_FLAT = 2, FBSDE_ST_NONFINITE = 4,
        FBSDE_ST_WAIT_LIMIT = 8 };              /* a bounded device-side wait of the CG loop gave

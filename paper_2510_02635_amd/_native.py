@@ -5,8 +5,8 @@ import os
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfbsde.so")
 
 F64, F32C = 0, 1
-F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS, F_HJ_SINK = 0, 1, 2, 3, 4
-G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC, G_HJ_GAUSS = 0, 1, 2, 3, 4, 5
+F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS, F_HJ_SINK, F_LOG_POT = 0, 1, 2, 3, 4, 5
+G_QUAD, G_AC, G_HJB_LOG, G_AFFINE, G_LOGISTIC, G_HJ_GAUSS, G_CASE2 = 0, 1, 2, 3, 4, 5, 6
 OK, EINVAL, ENOSPC, EHIP, ESTATE = 0, -1, -2, -3, -4
 ST_CG_MAXIT, ST_NEWTON_FLAT, ST_NONFINITE, ST_WAIT_LIMIT = 1, 2, 4, 8
 WS_TAPE = 1

@@ -349,8 +349,14 @@ void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S
     const double dt = pb->T / (double)pb->N;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        if (f_depends_on_x(pb))   // the particles' positions x0 + t_k mu + s W_k enter f
-            hipLaunchKernelGGL((k_reverse<S, QQ, TT, true>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+        // the particles' positions x0 + t_k mu + s W_k enter f
+        if (pb->f_kind == FBSDE_F_HJ_SINK)
+            hipLaunchKernelGGL((k_reverse<S, QQ, TT, 1>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
+                               std::sqrt(dt), pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters,
+                               ky.k0, ky.k1, pb->point_base, Y, rn2, dydc, status, shared, x0, pb->mu, (double)k * dt);
+        else if (pb->f_kind == FBSDE_F_LOG_POT)
+            hipLaunchKernelGGL((k_reverse<S, QQ, TT, 2>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
                                st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
                                std::sqrt(dt), pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters,
                                ky.k0, ky.k1, pb->point_base, Y, rn2, dydc, status, shared, x0, pb->mu, (double)k * dt);
@@ -710,7 +716,7 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     }
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
-        if (f_depends_on_x(pb)) return FBSDE_EINVAL;   // the per-point form evaluates x-dependent f
+        if (per_point_forward_only(pb)) return FBSDE_EINVAL;   // evaluated by the per-point form only
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solve
         return solve_shared(pb, P, x0, u, grad, status, wsp, ws_bytes, flags, (hipStream_t)stream);
@@ -734,7 +740,7 @@ int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const d
                    int32_t* cg_iters_out, fbsde_stream stream, bool check_tape) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
-    if (f_depends_on_x(pb)) return FBSDE_EINVAL;   // the reverse mode covers f independent of x
+    if (per_point_forward_only(pb)) return FBSDE_EINVAL;   // the reverse mode covers neither family
     Plan pl;
     if ((rc = make_plan(pb, P, pl))) return rc;
     if (!gp_bar || !fp_bar) return FBSDE_EINVAL;
@@ -746,7 +752,7 @@ int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const d
     }
     if (!x0 || !u_bar || !x0_bar || !status || !wsp) return FBSDE_EINVAL;
     if (pb->shared_dw) {
-        if (f_depends_on_x(pb)) return FBSDE_EINVAL;   // the per-point form evaluates x-dependent f
+        if (per_point_forward_only(pb)) return FBSDE_EINVAL;   // evaluated by the per-point form only
         if (cg_iters_out)
             for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;   // direct (Cholesky) solves
         return backward_shared(pb, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, wsp, ws_bytes, (hipStream_t)stream);

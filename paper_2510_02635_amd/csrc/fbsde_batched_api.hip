@@ -59,7 +59,7 @@ int batch_classes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, st
     for (int64_t i = 0; i < n_inst; ++i) {
         int rc = check_problem(&pbs[i], P[i]);
         if (rc) return rc;
-        if (pbs[i].shared_dw || f_depends_on_x(&pbs[i])) return FBSDE_EINVAL;
+        if (pbs[i].shared_dw || per_point_forward_only(&pbs[i])) return FBSDE_EINVAL;
         Plan pl;
         if ((rc = make_plan(&pbs[i], 1, pl))) return rc;
         batch_geometry(pl);

@@ -223,8 +223,8 @@ __device__ __forceinline__ double block_min(double v, double* lds) {
 }
 
 // ------------------------------------------------------------------ f, g, Newton
-enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2, F_BURGERS = 3, F_HJ_SINK = 4 };
-enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3, G_LOGISTIC = 4, G_HJ_GAUSS = 5 };
+enum { F_ZERO = 0, F_ALLEN_CAHN = 1, F_HJB = 2, F_BURGERS = 3, F_HJ_SINK = 4, F_LOG_POT = 5 };
+enum { G_QUAD = 0, G_AC = 1, G_HJB_LOG = 2, G_AFFINE = 3, G_LOGISTIC = 4, G_HJ_GAUSS = 5, G_CASE2 = 6 };
 
 // g families whose argument is q = gvec . X (the others take q = |X|^2)
 __device__ __forceinline__ bool g_dot_arg(int kind) { return kind == G_AFFINE || kind == G_LOGISTIC; }
@@ -235,7 +235,7 @@ __device__ __forceinline__ bool g_dot_arg(int kind) { return kind == G_AFFINE ||
 enum { A_ABAR = 0, A_TAU = 1, A_ZC = 2, A_WB = 3, A_FP = 4, A_GP = 8, A_S1 = 12, A_SG = 13, A_Z1 = 14, A_NS = 16 };
 enum { ST_CG_MAXIT = 1, ST_NEWTON_FLAT = 2, ST_NONFINITE = 4 };
 
-struct FSpec { int kind; double p0, p1; };
+struct FSpec { int kind; double p0, p1, p2 = 0.0; };
 
 // f(t, x, y, z) and d f / d y of the built-in families; zz = |z|^2 and zs = sum_i z_i (z shared by the
 // cloud).  BURGERS: fp0 (y - fp1) sum_i z_i, the Burgers-type nonlinearity of the Sec. 4 experiments in
@@ -247,7 +247,49 @@ __device__ __forceinline__ void f_and_fy(const FSpec& f, double y, double zz, do
     else if (f.kind == F_HJB) { fv = -f.p0 * zz; fy = 0.0; }
     else if (f.kind == F_BURGERS) { fv = f.p0 * (y - f.p1) * zs; fy = f.p0 * zs; }
     else if (f.kind == F_HJ_SINK) { fv = -f.p0 * f.p1 * y * zz; fy = -f.p0 * f.p1 * zz; }
+    else if (f.kind == F_LOG_POT) {
+        fv = 0.5 * f.p0 * log((1.0 + y) / (1.0 - y)) - f.p1 * y;
+        fy = f.p0 / (1.0 - y * y) - f.p1;
+    }
     else { fv = 0.0; fy = 0.0; }
+}
+
+// Products over the coordinates of a point, for Allen-Cahn Case 2: the pair (P, Q) = (prod_j x_j,
+// sum_i prod_{j != i} x_j^2) of a set of coordinates; one coordinate is (x, 1), and two disjoint sets
+// combine as (Pa Pb, Qa Pb^2 + Qb Pa^2) (associative and commutative, identity (1, 0)).
+__device__ __forceinline__ void pq_add(double& P, double& Q, double x) {
+    Q = Q * x * x + P * P;
+    P *= x;
+}
+__device__ __forceinline__ void pq_combine(double& P, double& Q, double Pb, double Qb) {
+    Q = Q * Pb * Pb + Qb * P * P;
+    P *= Pb;
+}
+
+// Source of Allen-Cahn Case 2 at time t for r2 = |x|^2 and (P, Q2) of x: with v = amp cos(P) w,
+// w = e^(cos t - r2), S2 = v_t + (s^2/2) Lap v + F(v), v_t = -sin(t) v,
+// Lap v = amp w (-cos(P) Q2 + 4 d P sin(P) + cos(P) (4 r2 - 2 d)), F the log potential (theta, theta_c).
+__device__ __forceinline__ double case2_source(double t, double r2, double P, double Q2, double d, double s,
+                                               double theta, double theta_c, double amp) {
+    const double w = exp(cos(t) - r2), cP = cos(P), sP = sin(P);
+    const double v = amp * cP * w;
+    const double lap = amp * w * (-cP * Q2 + 4.0 * d * P * sP + cP * (4.0 * r2 - 2.0 * d));
+    return -sin(t) * v + 0.5 * s * s * lap + 0.5 * theta * log((1.0 + v) / (1.0 - v)) - theta_c * v;
+}
+
+// d S2 / d x_k for the same point: Pk, Q2k are P and Q2 of the coordinates other than k, so that
+// d_k P = Pk and d_k Q2 = 2 x_k Q2k; the derivatives of w, v, the Laplacian's bracket and F written out.
+__device__ __forceinline__ double case2_source_dk(double t, double r2, double P, double Q2, double xk, double Pk,
+                                                  double Q2k, double d, double s, double theta, double theta_c,
+                                                  double amp) {
+    const double w = exp(cos(t) - r2), cP = cos(P), sP = sin(P);
+    const double v = amp * cP * w;
+    const double D = -cP * Q2 + 4.0 * d * P * sP + cP * (4.0 * r2 - 2.0 * d);
+    const double dv = amp * w * (-sP * Pk - 2.0 * xk * cP);
+    const double dD = sP * Pk * Q2 - cP * 2.0 * xk * Q2k + 4.0 * d * (Pk * sP + P * cP * Pk) -
+                      sP * Pk * (4.0 * r2 - 2.0 * d) + cP * 8.0 * xk;
+    const double dlap = amp * (-2.0 * xk * w * D + w * dD);
+    return -sin(t) * dv + 0.5 * s * s * dlap + (theta / (1.0 - v * v) - theta_c) * dv;
 }
 
 // Source of the Hamilton-Jacobi-type family at time t and r2 = |x|^2, and its derivative in r2: with

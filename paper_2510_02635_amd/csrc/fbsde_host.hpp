@@ -28,8 +28,8 @@ inline int check_problem(const fbsde_problem* pb, int64_t P) {
     if (!pb || P < 0) return FBSDE_EINVAL;
     if (pb->d < 1 || pb->M < 2 || pb->N < 1) return FBSDE_EINVAL;
     if (!(pb->T > 0.0) || !(pb->s > 0.0)) return FBSDE_EINVAL;
-    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_HJ_SINK) return FBSDE_EINVAL;
-    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_HJ_GAUSS) return FBSDE_EINVAL;
+    if (pb->f_kind < FBSDE_F_ZERO || pb->f_kind > FBSDE_F_LOG_POT) return FBSDE_EINVAL;
+    if (pb->g_kind < FBSDE_G_QUAD || pb->g_kind > FBSDE_G_CASE2) return FBSDE_EINVAL;
     if ((pb->g_kind == FBSDE_G_AFFINE || pb->g_kind == FBSDE_G_LOGISTIC) && !pb->gvec) return FBSDE_EINVAL;
     if (!(pb->eps_h >= 0.0) || !(pb->ridge_rel >= 0.0)) return FBSDE_EINVAL;
     if (pb->ridge_rel == 0.0 && pb->M <= pb->d + 1) return FBSDE_EINVAL;
@@ -139,11 +139,18 @@ inline Keys keys_of(const fbsde_problem* pb) {
 }
 inline FSpec fspec_of(const fbsde_problem* pb) {
     if (pb->f_kind == FBSDE_F_HJ_SINK) return {pb->f_kind, pb->fp[0], 1.0 / (pb->s * pb->s)};
-    return {pb->f_kind, pb->fp[0], pb->fp[1]};
+    return {pb->f_kind, pb->fp[0], pb->fp[1], pb->fp[2]};
 }
 // f depends on x (a source term): only the per-point forward paths evaluate it, at the particles'
 // positions.
-inline bool f_depends_on_x(const fbsde_problem* pb) { return pb->f_kind == FBSDE_F_HJ_SINK; }
+inline bool f_depends_on_x(const fbsde_problem* pb) {
+    return pb->f_kind == FBSDE_F_HJ_SINK || pb->f_kind == FBSDE_F_LOG_POT;
+}
+// A family only the per-point forward paths evaluate: f depends on x, or g needs the product of the
+// coordinates (the Case 2 terminal value, formed in the forward sweep of the per-point form).
+inline bool per_point_forward_only(const fbsde_problem* pb) {
+    return f_depends_on_x(pb) || pb->g_kind == FBSDE_G_CASE2;
+}
 
 inline int last_error() { return (hipGetLastError() == hipSuccess) ? FBSDE_OK : FBSDE_EHIP; }
 

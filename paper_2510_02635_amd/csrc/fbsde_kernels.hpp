@@ -72,7 +72,7 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
                 }
             }
         }
-        double n2 = 0.0, gq = 0.0;
+        double n2 = 0.0, gq = 0.0, Pp = 1.0, Pq = 0.0;   // Pp: product of the coordinates (G_CASE2)
         if (valid) {
             S* row = W + ((int64_t)(shared ? 0 : p) * M + j) * ldw;
 #pragma unroll
@@ -90,13 +90,16 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
                         const double X = xc[q][e] + s * ws;
                         if (g_dot_arg(g_kind)) gq += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
                         else gq += X * X;
+                        if (g_kind == G_CASE2 && e0 + e < d) Pp *= X;
                     }
                 }
             }
         }
         team_sum2<TEAM>(n2, gq, red, team);
+        if (g_kind == G_CASE2) team_pq<TEAM>(Pp, Pq, red, team);
         if (valid && (L == 0)) {
-            const double y = g_of(g_kind, ga, gb, gq, d);
+            // G_CASE2: gb cos(prod x) e^(cos ga - |x|^2)
+            const double y = (g_kind == G_CASE2) ? gb * cos(Pp) * exp(cos(ga) - gq) : g_of(g_kind, ga, gb, gq, d);
             Y[(int64_t)p * M + j] = y;
             if (rn2) rn2[(int64_t)p * M + j] = n2;
             if (!isfinite(y)) st |= ST_NONFINITE;
@@ -486,9 +489,12 @@ k_level_finish(const double* __restrict__ x, const double* __restrict__ Wbar, in
 // Particle reversal W_k = W_{k+1} - sqrt(dt) xi_k (Philox regenerated, in place) fused with the
 // per-particle dots |W_k|^2 and alpha_x . W_k, the local linear model C = alpha + s alpha_x . W_k
 // and the Newton solve for Y_k (eqs. nonlinearf / NRiter).  zero_state: level 0, W_0 = 0.
-// XR: f has the x-dependent source of the Hamilton-Jacobi-type family, evaluated at the particle's
-// position X = b + s W_k with b = x0 + t_k mu (a third row dot b . W_k gives |X|^2), and added to C.
-template <typename S, int Q, int TEAM, bool XR = false>
+// XK != 0: f has an x-dependent source, evaluated at the particle's position X = b + s W_k with
+// b = x0 + t_k mu (a third row dot b . W_k gives |X|^2) and moved into C (Newton's F(y) = y - C - dt f
+// with f = f(y) + source): XK = 1 the Hamilton-Jacobi-type source (a function of |X|^2), XK = 2 the
+// Allen-Cahn Case 2 source, which also needs the coordinate products (P, Q2) of X (pq_add per lane,
+// team_pq across the team).
+template <typename S, int Q, int TEAM, int XK = 0>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int ld, int k, int zero_state,
           double sqdt, double s, double dt, const double* __restrict__ ax, const double* __restrict__ scal,
@@ -514,9 +520,9 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     const double alpha = scal[(int64_t)p * ns + 5];
     const double zz = scal[(int64_t)p * ns + 6], zs = scal[(int64_t)p * ns + 8];
     uint32_t st = 0;
-    R b[Q][4];        // XR: the lane's coordinates of b = x0 + t_k mu
-    double bb = 0.0;  // XR: |b|^2
-    if constexpr (XR) {
+    R b[Q][4];        // XK: the lane's coordinates of b = x0 + t_k mu
+    double bb = 0.0;  // XK: |b|^2
+    if constexpr (XK != 0) {
         double lb = 0.0, unused = 0.0;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -549,6 +555,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
         const int j = jb + team;
         const bool valid = j < r1;
         CSum<R> n2s, dots, xbs;
+        double Pp = 1.0, Pq = 0.0;   // XK == 2: (P, Q2) of the lane's coordinates of X
         if (valid) {
             S* row = W + ((int64_t)p * M + j) * ldw;
 #pragma unroll
@@ -573,9 +580,14 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
                     store4(row + e0, v);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) { n2s.add(v[e] * v[e]); dots.add(a[q][e] * v[e]); }
-                    if constexpr (XR) {
+                    if constexpr (XK != 0) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) xbs.add(b[q][e] * v[e]);
+                    }
+                    if constexpr (XK == 2) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (e0 + e < d) pq_add(Pp, Pq, (double)b[q][e] + s * (double)v[e]);
                     }
                 }
             }
@@ -583,10 +595,15 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
         double n2 = n2s.get(), dt_ = dots.get();
         team_sum2<TEAM>(n2, dt_, red, team);
         double src = 0.0;
-        if constexpr (XR) {
+        if constexpr (XK != 0) {
             double xb = xbs.get(), unused = 0.0;
             team_sum2<TEAM>(xb, unused, red, team);
-            src = dt * hj_source(tk, bb + 2.0 * s * xb + s * s * n2, (double)d, s, f.p0, nullptr);
+            const double r2 = bb + 2.0 * s * xb + s * s * n2;
+            if constexpr (XK == 1) src = dt * hj_source(tk, r2, (double)d, s, f.p0, nullptr);
+            if constexpr (XK == 2) {
+                team_pq<TEAM>(Pp, Pq, red, team);
+                src = -dt * case2_source(tk, r2, Pp, Pq, (double)d, s, f.p0, f.p1, f.p2);
+            }
         }
         if (valid && L == (cnt & 63)) {
             j_keep = j;
@@ -601,34 +618,76 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
 
 // Level-0 outputs: u = Y^m_0 (every particle sits at x0, so C = alpha) and
 // grad u = (alpha_x + dt grad_x f) / F'(u) (the x-derivative of the level-0 Newton equation).  x0: the
-// points [P][d], read only when f depends on x (the HJ-type source at t = 0 and |x0|^2, added to C, and
-// its x-gradient 2 x0 dS/d|x|^2).
+// points [P][d], read only when f depends on x: the source at t = 0 and x0 moves into C, and its
+// x-gradient enters grad u.  HJ type: a function of |x0|^2 (gradient 2 x0 dS/d|x|^2).  Allen-Cahn Case 2:
+// also of the coordinate products of x0; d_k of them needs the products of the coordinates other than k,
+// formed per thread over a contiguous segment of coordinates with the other segments' products combined
+// on either side (no division, so zero coordinates are exact).
 __global__ void __launch_bounds__(256)
 k_outputs(const double* __restrict__ x, int ld, int d, const double* __restrict__ scal, int ns, FSpec f,
           double dt, int newton_iters, double* __restrict__ u, double* __restrict__ grad,
           uint32_t* __restrict__ status, const double* __restrict__ x0 = nullptr, double s = 0.0) {
     __shared__ double lds[16];
+    __shared__ double segP[256], segQ[256];
     const int p = blockIdx.x;
+    const double* xp = x0 ? x0 + (int64_t)p * d : nullptr;
     uint32_t st = 0;
-    double src = 0.0, dsrc = 0.0;
+    double csrc = 0.0, dsrc = 0.0, r2 = 0.0, Pall = 1.0, Qall = 0.0;
+    const int nt = blockDim.x, seg = (d + nt - 1) / nt;
+    const int lo = min(d, (int)threadIdx.x * seg), hi = min(d, lo + seg);
     if (f.kind == F_HJ_SINK) {
-        double r2 = 0.0;
-        if (x0)
-            for (int i = threadIdx.x; i < d; i += blockDim.x) r2 += x0[(int64_t)p * d + i] * x0[(int64_t)p * d + i];
+        if (xp)
+            for (int i = threadIdx.x; i < d; i += blockDim.x) r2 += xp[i] * xp[i];
         r2 = block_sum(r2, lds);
-        src = hj_source(0.0, r2, (double)d, s, f.p0, &dsrc);
+        csrc = hj_source(0.0, r2, (double)d, s, f.p0, &dsrc);
+    } else if (f.kind == F_LOG_POT) {
+        double P = 1.0, Q = 0.0;
+        for (int i = lo; i < hi; ++i) {
+            const double xi = xp ? xp[i] : 0.0;
+            r2 += xi * xi;
+            pq_add(P, Q, xi);
+        }
+        segP[threadIdx.x] = P;
+        segQ[threadIdx.x] = Q;
+        r2 = block_sum(r2, lds);   // its barrier also publishes the segments
+        for (int t = 0; t < nt; ++t) pq_combine(Pall, Qall, segP[t], segQ[t]);
+        csrc = -case2_source(0.0, r2, Pall, Qall, (double)d, s, f.p0, f.p1, f.p2);   // f = F(y) - S2
     }
     double Fp;
-    const double y = newton_y(f, scal[(int64_t)p * ns + 5] + dt * src, scal[(int64_t)p * ns + 6],
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5] + dt * csrc, scal[(int64_t)p * ns + 6],
                               scal[(int64_t)p * ns + 8], dt, newton_iters, Fp, st);
     if (threadIdx.x == 0) u[p] = y;
-    if (grad)
-        for (int i = threadIdx.x; i < d; i += blockDim.x) {
-            const double gx = (f.kind == F_HJ_SINK && x0) ? 2.0 * dsrc * x0[(int64_t)p * d + i] : 0.0;
-            const double gi = (x[(int64_t)p * ld + i] + dt * gx) / Fp;
-            grad[(int64_t)p * d + i] = gi;
-            if (!isfinite(gi)) st |= ST_NONFINITE;
+    if (grad) {
+        if (f.kind == F_LOG_POT) {
+            double EP = 1.0, EQ = 0.0, FP = 1.0, FQ = 0.0;   // segments before / after this thread's
+            for (int t = 0; t < nt; ++t) {
+                if (t < (int)threadIdx.x) pq_combine(EP, EQ, segP[t], segQ[t]);
+                else if (t > (int)threadIdx.x) pq_combine(FP, FQ, segP[t], segQ[t]);
+            }
+            double preP = 1.0, preQ = 0.0;
+            for (int k = lo; k < hi; ++k) {
+                double sP = 1.0, sQ = 0.0;
+                for (int j = k + 1; j < hi; ++j) pq_add(sP, sQ, xp ? xp[j] : 0.0);
+                double lP = EP, lQ = EQ;
+                pq_combine(lP, lQ, preP, preQ);
+                pq_combine(lP, lQ, sP, sQ);
+                pq_combine(lP, lQ, FP, FQ);
+                const double xk = xp ? xp[k] : 0.0;
+                const double gx = -case2_source_dk(0.0, r2, Pall, Qall, xk, lP, lQ, (double)d, s, f.p0, f.p1, f.p2);
+                const double gi = (x[(int64_t)p * ld + k] + dt * gx) / Fp;
+                grad[(int64_t)p * d + k] = gi;
+                if (!isfinite(gi)) st |= ST_NONFINITE;
+                pq_add(preP, preQ, xk);
+            }
+        } else {
+            for (int i = threadIdx.x; i < d; i += blockDim.x) {
+                const double gx = (f.kind == F_HJ_SINK && xp) ? 2.0 * dsrc * xp[i] : 0.0;
+                const double gi = (x[(int64_t)p * ld + i] + dt * gx) / Fp;
+                grad[(int64_t)p * d + i] = gi;
+                if (!isfinite(gi)) st |= ST_NONFINITE;
+            }
         }
+    }
     if (st) atomicOr(&status[p], st);
 }
 

@@ -790,7 +790,7 @@ size_t lit_carve(int64_t P, int64_t M, int64_t N, int64_t ld, bool geo, char* ba
 int lit_check(const fbsde_problem* pb, int64_t P, host::Plan& pl) {
     int rc = host::check_problem(pb, P);
     if (rc) return rc;
-    if (pb->prec != FBSDE_F64 || pb->shared_dw != 0 || host::f_depends_on_x(pb)) return FBSDE_EINVAL;
+    if (pb->prec != FBSDE_F64 || pb->shared_dw != 0 || host::per_point_forward_only(pb)) return FBSDE_EINVAL;
     if (pb->M > LMAX || !(pb->ridge_rel > 0.0)) return FBSDE_EINVAL;
     return host::make_plan(pb, P, pl);
 }

@@ -84,6 +84,26 @@ __device__ __forceinline__ void team_sum2(double& a, double& b, double* red, int
     }
 }
 
+// Combine the coordinate-product pairs (P, Q) of pq_add / pq_combine over the team owning a row; every
+// lane of the team gets the totals (a butterfly: both partners combine the same two pairs).  For TEAM > 1
+// all waves of the block must call it the same number of times.
+template <int TEAM>
+__device__ __forceinline__ void team_pq(double& P, double& Q, double* red, int team) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double Pb = __shfl_xor(P, off, 64), Qb = __shfl_xor(Q, off, 64);
+        pq_combine(P, Q, Pb, Qb);
+    }
+    if constexpr (TEAM > 1) {
+        const int wv = (threadIdx.x >> 6) % TEAM, ln = threadIdx.x & 63;
+        if (ln == 0) { red[2 * (team * TEAM + wv)] = P; red[2 * (team * TEAM + wv) + 1] = Q; }
+        __syncthreads();
+        P = 1.0; Q = 0.0;
+#pragma unroll
+        for (int i = 0; i < TEAM; ++i) pq_combine(P, Q, red[2 * (team * TEAM + i)], red[2 * (team * TEAM + i) + 1]);
+        __syncthreads();
+    }
+}
+
 // Per-block combination of per-lane column accumulators into out[0..ld) (double), in team order.
 template <int Q, int TEAM, typename R>
 __device__ __forceinline__ void block_columns_out(CSum<R> (&acc)[Q][4], double* lds, double* __restrict__ out,

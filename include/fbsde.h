@@ -249,9 +249,13 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
  *                         NULL, [P_i]); grad itself may be NULL
  *   opts    NULL for the defaults (tiled, 4 streams, 24 GiB tiles, 512 persistent slots)
  *   ws      device workspace of fbsde_batched_workspace_size(pbs, n_inst, P, opts, adjoint) bytes
- * The tiled schedule waits for the caller's stream, returns after all tiles have completed, and
- * needs the calling thread's current device to be the one holding the buffers; the persistent one
- * synchronises the stream once (after uploading its work tables), then runs asynchronously. */
+ * The tiled schedule forks from the caller's stream onto a pool of streams (created once per device and
+ * kept for the life of the process), and the caller's stream waits for all of them: the call returns
+ * once its work is enqueued (every level's CG is one device-side loop launch; the runtime may hold the
+ * host back while a stream's command queue is full) and needs the calling
+ * thread's current device to be the one holding the buffers.  Calls that overlap on one device from
+ * several host threads queue their tiles on the same streams.  The persistent schedule synchronises
+ * the stream once (after uploading its work tables), then runs asynchronously. */
 enum { FBSDE_BATCH_TILED = 0, FBSDE_BATCH_PERSISTENT = 1 };
 typedef struct fbsde_batch_opts {
     int32_t mode;         /* FBSDE_BATCH_TILED or FBSDE_BATCH_PERSISTENT                 */
@@ -382,6 +386,15 @@ int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, do
                         fbsde_stream stream);
 int fbsde_graph_launch(fbsde_graph graph, fbsde_stream stream);
 int fbsde_graph_destroy(fbsde_graph graph);
+/* fbsde_solve_batched (tiled schedule) captured into a graph the same way: the fork onto the stream pool
+ * and the join back are recorded with the tiles, so one fbsde_graph_launch replays the whole batch.
+ * Arguments as fbsde_solve_batched (opts->mode must be FBSDE_BATCH_TILED); every pointer, the
+ * workspace included, is bound into the graph.  The graph replays on the pool's streams, so two
+ * graphs (or a graph and an eager tiled call) of one device must not run at the same time. */
+int fbsde_graph_capture_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P,
+                                const double* const* x0, double* const* u, double* const* grad,
+                                uint32_t* const* status, const fbsde_batch_opts* opts, void* ws,
+                                size_t ws_bytes, fbsde_graph* out, fbsde_stream stream);
 
 /* Paper-literal per-anchor scheme: Algorithm 1 as printed (Sec. 2.3 to 2.5), with none of the
  * readings that fbsde_solve takes for the regression.  At every level k and for every particle m:

@@ -15,7 +15,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm", "fbsde_cholesky_workspace",
             "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
             "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch", "fbsde_graph_destroy",
-            "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
+            "fbsde_graph_capture_batched", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_launch_timer", "fbsde_launch_timer_read", "fbsde_launch_timer_kinds",
             "fbsde_workspace_cg_rows", "fbsde_solve_noalloc", "fbsde_batched_cg_bytes",
             "fbsde_literal_workspace_size", "fbsde_literal_workspace_size_stored", "fbsde_literal_coef_workspace_size",
             "fbsde_solve_literal_coef",
@@ -108,6 +108,7 @@ def load():
     lib.fbsde_solve_batched.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_solve_batched_backward.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_graph_capture.argtypes = [pb, i64, vp, vp, vp, vp, vp, sz, i32, P(vp), vp]
+    lib.fbsde_graph_capture_batched.argtypes = [pb, i64, vp, vp, vp, vp, vp, vp, vp, sz, P(vp), vp]
     lib.fbsde_graph_launch.argtypes = [vp, vp]
     lib.fbsde_graph_destroy.argtypes = [vp]
     lib.fbsde_autotune.argtypes = [pb, i64, vp, vp, sz, P(CTuneResult), vp]
@@ -122,7 +123,8 @@ def load():
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
                  "fbsde_solve_backward", "fbsde_normals", "fbsde_box_muller", "fbsde_time_kernel", "fbsde_gemm",
                  "fbsde_cholesky_solve", "fbsde_batched_workspace_size", "fbsde_solve_batched",
-                 "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_launch",
+                 "fbsde_solve_batched_backward", "fbsde_graph_capture", "fbsde_graph_capture_batched",
+                 "fbsde_graph_launch",
                  "fbsde_graph_destroy", "fbsde_autotune", "fbsde_autotune_reset", "fbsde_literal_workspace_size",
                  "fbsde_launch_timer_read", "fbsde_launch_timer_kinds", "fbsde_literal_coef_workspace_size",
                  "fbsde_workspace_cg_rows", "fbsde_solve_noalloc", "fbsde_batched_cg_bytes",

@@ -460,6 +460,52 @@ class CapturedSolve:
             pass
 
 
+class CapturedBatch:
+    """A tiled batched solve captured once into a HIP graph (fbsde_graph_capture_batched): the fork onto
+    the library's stream pool, every tile's level chain and the join back replay with one launch.
+
+    Bound to this object's tensors: write new points into the tensors of `x0s` in place, call
+    `launch()`, read `u`, `grad`, `status` (lists per instance)."""
+
+    def __init__(self, problems, x0s, want_grad=True, streams=4, tile_bytes=0):
+        n, cps, Ps = _batch_common(problems, x0s)
+        self._keep = (cps, Ps)
+        opts = _batch_opts("tiled", streams, tile_bytes, 512)
+        self.x0s = x0s
+        self.u, self.grad, self.status = [], [], []
+        for pb, x in zip(problems, x0s):
+            self.u.append(torch.empty(x.shape[0], dtype=torch.float64, device=x.device))
+            self.grad.append(torch.empty((x.shape[0], pb.d), dtype=torch.float64, device=x.device)
+                             if want_grad else None)
+            self.status.append(torch.empty(x.shape[0], dtype=torch.int32, device=x.device))
+        self.ws = batched_workspace(problems, x0s, streams=streams, tile_bytes=tile_bytes)
+        self._ptr_arrays = (_ptrs(x0s), _ptrs(self.u), _ptrs(self.grad) if want_grad else None, _ptrs(self.status))
+        xp, up, gp, sp = self._ptr_arrays
+        h = ctypes.c_void_p()
+        N.check(N.load().fbsde_graph_capture_batched(cps, n, ctypes.cast(Ps, ctypes.c_void_p), xp, up,
+                                                     None if gp is None else ctypes.cast(gp, ctypes.c_void_p), sp,
+                                                     ctypes.byref(opts), self.ws.data_ptr(), self.ws.numel(),
+                                                     ctypes.byref(h), _stream()))
+        self._h = h
+
+    def launch(self):
+        if self._h is None:
+            raise RuntimeError("graph destroyed")
+        N.check(N.load().fbsde_graph_launch(self._h, _stream()))
+        return self.u, self.grad, self.status
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            N.check(N.load().fbsde_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autotune(pb, x0, ws=None):
     """Time the candidate launch shapes of the CG product for (precision, d, M, P = len(x0)) and record
     the fastest for every later call with the same key (fbsde_autotune).  Returns the choice as a dict."""

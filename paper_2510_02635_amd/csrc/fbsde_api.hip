@@ -9,6 +9,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <map>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -1035,6 +1036,49 @@ unsigned long long* cg_bytes_counter(void* ws) { return &((CgCtl*)ws)->bytes; }
 }  // namespace host
 }  // namespace fbsde
 
+struct fbsde_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace fbsde {
+namespace host {
+// Capture what `body` enqueues on a private stream that first waits for the caller's stream, and
+// instantiate it.  Streams that body forks onto (by events) join the capture and must join back.
+int capture_graph(const std::function<int(hipStream_t)>& body, hipStream_t stream, fbsde_graph* out) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return FBSDE_EHIP;
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { (void)hipStreamDestroy(cap); return FBSDE_EHIP; }
+    int err = FBSDE_OK;
+    if (hipEventRecord(ev, stream) != hipSuccess || hipStreamWaitEvent(cap, ev, 0) != hipSuccess) err = FBSDE_EHIP;
+    hipGraph_t g = nullptr;
+    if (!err && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) err = FBSDE_EHIP;
+    if (!err) {
+        const int rs = body(cap);
+        const hipError_t he = hipStreamEndCapture(cap, &g);
+        err = rs ? rs : (he != hipSuccess ? FBSDE_EHIP : FBSDE_OK);
+    }
+    hipGraphExec_t exec = nullptr;
+    if (!err && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) err = FBSDE_EHIP;
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cap);
+    if (err) {
+        if (g) (void)hipGraphDestroy(g);
+        return err;
+    }
+    fbsde_graph h = new (std::nothrow) fbsde_graph_s{g, exec};
+    if (!h) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(g);
+        return FBSDE_EINVAL;
+    }
+    *out = h;
+    return FBSDE_OK;
+}
+}  // namespace host
+}  // namespace fbsde
+
 extern "C" {
 
 int fbsde_workspace_cg_rows(const void* ws, int64_t* rows, fbsde_stream stream) {
@@ -1067,10 +1111,7 @@ int fbsde_autotune_reset(void) {
     return FBSDE_OK;
 }
 
-struct fbsde_graph_s {
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-};
+
 
 int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
                         uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, fbsde_graph* out,
@@ -1085,37 +1126,9 @@ int fbsde_graph_capture(const fbsde_problem* pb, int64_t P, const double* x0, do
     size_t need = 0;
     if ((rc = fbsde_workspace_size(pb, P, flags, &need))) return rc;
     if (need > ws_bytes) return FBSDE_ENOSPC;
-    // capture on a private stream that first waits for the caller's stream
-    hipStream_t cap;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return FBSDE_EHIP;
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { (void)hipStreamDestroy(cap); return FBSDE_EHIP; }
-    int err = FBSDE_OK;
-    if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess || hipStreamWaitEvent(cap, ev, 0) != hipSuccess)
-        err = FBSDE_EHIP;
-    hipGraph_t g = nullptr;
-    if (!err && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) err = FBSDE_EHIP;
-    if (!err) {
-        const int rs = fbsde_solve(pb, P, x0, u, grad, status, ws, ws_bytes, flags, nullptr, (fbsde_stream)cap);
-        const hipError_t he = hipStreamEndCapture(cap, &g);
-        err = rs ? rs : (he != hipSuccess ? FBSDE_EHIP : FBSDE_OK);
-    }
-    hipGraphExec_t exec = nullptr;
-    if (!err && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) err = FBSDE_EHIP;
-    (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(cap);
-    if (err) {
-        if (g) (void)hipGraphDestroy(g);
-        return err;
-    }
-    fbsde_graph h = new (std::nothrow) fbsde_graph_s{g, exec};
-    if (!h) {
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(g);
-        return FBSDE_EINVAL;
-    }
-    *out = h;
-    return FBSDE_OK;
+    return capture_graph([&](hipStream_t cap) {
+        return fbsde_solve(pb, P, x0, u, grad, status, ws, ws_bytes, flags, nullptr, (fbsde_stream)cap);
+    }, (hipStream_t)stream, out);
 }
 
 int fbsde_graph_launch(fbsde_graph g, fbsde_stream stream) {

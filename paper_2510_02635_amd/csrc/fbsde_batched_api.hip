@@ -1,16 +1,17 @@
 // Host side of the batched solve of many instances.
 //  Tiled (default): the work items are (instance, point-tile) pairs, each run through the whole level
 //    chain by the multi-block path of fbsde_solve (every point split over many workgroups along its
-//    particle rows), on a pool of host worker threads that each own a HIP stream and a workspace arena.
-//    Tiles are sized to the arena, taken largest first, and overlap on the chip across the streams.
+//    particle rows), dealt to a pool of HIP streams that each own a workspace arena.  Tiles are sized to
+//    the arena, taken largest first, and overlap on the chip across the streams; the call only enqueues.
 //  Persistent: one launch per geometry class; every workgroup pulls (instance, point) items from an
 //    atomic queue and runs the whole chain of its point alone.
 #include "fbsde_host.hpp"
 #include "fbsde_batched.hpp"
 
-#include <atomic>
+#include <algorithm>
+#include <cstdlib>
 #include <map>
-#include <thread>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -205,15 +206,50 @@ int tiled_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const
     return FBSDE_OK;
 }
 
-// Parameter adjoints of an instance: the sum of its tiles' sums, in tile order.
-__global__ void k_sum_tiles(const double* __restrict__ part, const int* __restrict__ idx, int n, double* gp_bar,
+// Parameter adjoints of an instance: the sum of its tiles' sums, in tile order.  The tile indices come
+// as a kernel argument (so a captured graph holds them): up to TILE_LIST per launch, later launches of
+// the same instance adding to the first.
+constexpr int TILE_LIST = 30;
+struct TileList {
+    int n;
+    int idx[TILE_LIST];
+};
+__global__ void k_sum_tiles(const double* __restrict__ part, TileList tl, int accumulate, double* gp_bar,
                             double* fp_bar) {
     const int t = threadIdx.x;
     if (t >= 8) return;
-    double v = 0.0;
-    for (int k = 0; k < n; ++k) v += part[(int64_t)idx[k] * 8 + t];
-    if (t < 4) gp_bar[t] = v;
-    else fp_bar[t - 4] = v;
+    double* out = (t < 4) ? gp_bar + t : fp_bar + (t - 4);
+    double v = accumulate ? *out : 0.0;
+    for (int k = 0; k < tl.n; ++k) v += part[(int64_t)tl.idx[k] * 8 + t];
+    *out = v;
+}
+
+// The streams and events the tiled schedule forks onto, created once per device and kept for the life of
+// the process (a captured graph can then fork onto them too).  A mutex serialises the enqueueing of
+// concurrent calls on one device; their tiles then queue up on the same streams.
+constexpr int POOL_STREAMS = 8;
+struct TiledPool {
+    hipStream_t s[POOL_STREAMS];
+    hipEvent_t fork;
+    hipEvent_t join[POOL_STREAMS];
+};
+std::mutex g_pool_mu;
+std::map<int, TiledPool> g_pool;
+
+int tiled_pool(int dev, TiledPool*& out) {   // call with g_pool_mu held
+    auto it = g_pool.find(dev);
+    if (it != g_pool.end()) {
+        out = &it->second;
+        return FBSDE_OK;
+    }
+    TiledPool tp;
+    if (hipEventCreateWithFlags(&tp.fork, hipEventDisableTiming) != hipSuccess) return FBSDE_EHIP;
+    for (int w = 0; w < POOL_STREAMS; ++w)
+        if (hipStreamCreateWithFlags(&tp.s[w], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&tp.join[w], hipEventDisableTiming) != hipSuccess)
+            return FBSDE_EHIP;
+    out = &(g_pool[dev] = tp);
+    return FBSDE_OK;
 }
 
 struct TiledArgs {
@@ -228,6 +264,10 @@ struct TiledArgs {
     double* const* fp_bar;
 };
 
+// Enqueue the whole tiled schedule: the pool's streams wait for the caller's stream, each takes its tiles
+// in turn (every level's CG one device-side loop launch, so no call waits for the device), and the
+// caller's stream then waits for every stream.  Nothing synchronises with the host: the call returns once
+// the work is enqueued, and it can be captured into a graph.
 int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& o, bool adjoint, void* wsp,
               size_t ws_bytes, hipStream_t caller) {
     const int32_t flags = adjoint ? FBSDE_WS_TAPE : 0;
@@ -240,22 +280,23 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
     if (units.empty()) {   // every instance is empty: its parameter adjoints are zero sums
         if (adjoint)
             for (int64_t i = 0; i < n_inst; ++i)
-                hipLaunchKernelGGL(k_sum_tiles, dim3(1), dim3(64), 0, caller, nullptr, nullptr, 0, a.gp_bar[i],
-                                   a.fp_bar[i]);
+                hipLaunchKernelGGL(k_sum_tiles, dim3(1), dim3(64), 0, caller, nullptr, TileList{0, {}}, 0,
+                                   a.gp_bar[i], a.fp_bar[i]);
         return last_error();
     }
     char* base = (char*)wsp;
     double* tpart = (double*)base;   // [units][8]: gp_bar, fp_bar of each tile
     unsigned long long* cgc = tiled_cg_counters(base, units.size());
     char* arenas = base + tiled_header_bytes(units.size());
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, caller, cgc, 8);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return FBSDE_EHIP;
-    hipEvent_t ev0;
-    if (hipEventCreateWithFlags(&ev0, hipEventDisableTiming) != hipSuccess) return FBSDE_EHIP;
-    if (hipEventRecord(ev0, caller) != hipSuccess) { (void)hipEventDestroy(ev0); return FBSDE_EHIP; }
-    // The solves only enqueue their work (no call waits for the device), so the tiles are dealt to the
-    // streams up front: largest expected time first, each to the stream with the least time so far.
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    TiledPool* pool = nullptr;
+    if ((rc = tiled_pool(dev, pool))) return rc;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, caller, cgc, 8);
+    if (hipEventRecord(pool->fork, caller) != hipSuccess) return FBSDE_EHIP;
+    // The tiles are dealt to the streams up front: largest expected time first, each to the stream with
+    // the least time so far.
     std::vector<std::vector<int>> deal((size_t)nw);
     {
         std::vector<double> load((size_t)nw, 0.0);
@@ -265,23 +306,27 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
             load[w] += units[k].cost;
         }
     }
-    std::atomic<int> first_err{0};
-    auto fail = [&](int e) { int z = 0; first_err.compare_exchange_strong(z, e); };
-    auto worker = [&](int w) {
-        if (hipSetDevice(dev) != hipSuccess) { fail(FBSDE_EHIP); return; }
-        // the streams' CG loops share the chip instead of each asking for all of it: each asks for half
-        // (measured on 64 uneven instances x 8 points over four streams: a quarter 20.2 s, half 15.2 s,
-        // all 18.0 s; blocks of a loop that cannot start wait until another stream's loop ends)
-        struct ShareScope {
-            explicit ShareScope(int n) { loop_share = n; }
-            ~ShareScope() { loop_share = 1; }
-        } share_scope(std::min(nw, 2));
-        hipStream_t s;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { fail(FBSDE_EHIP); return; }
-        if (hipStreamWaitEvent(s, ev0, 0) != hipSuccess) fail(FBSDE_EHIP);
-        char* ar = arenas + (size_t)w * arena;
-        for (const int k : deal[(size_t)w]) {
-            if (first_err.load()) break;
+    // the streams' CG loops share the chip instead of each asking for all of it: each asks for half
+    // (measured on 64 uneven instances x 8 points over four streams: a quarter 20.2 s, half 15.2 s,
+    // all 18.0 s; blocks of a loop that cannot start wait until another stream's loop ends)
+    struct ShareScope {
+        explicit ShareScope(int n) { loop_share = n; }
+        ~ShareScope() { loop_share = 1; }
+    } share_scope(std::min(nw, 2));
+    for (int w = 0; w < nw; ++w)
+        if (hipStreamWaitEvent(pool->s[w], pool->fork, 0) != hipSuccess) return FBSDE_EHIP;
+    // Tiles are enqueued round-robin over the streams, one tile per stream in turn: a launch blocks the
+    // host once its stream holds as many commands as the runtime queues, and enqueueing one stream's
+    // whole list first kept the other streams empty meanwhile (measured on 64 uneven instances x 8 points
+    // over four streams: 20.1 s stream by stream, 15.4 s round-robin, forward).
+    size_t rounds = 0;
+    for (const auto& l : deal) rounds = std::max(rounds, l.size());
+    for (size_t r = 0; r < rounds; ++r)
+        for (int w = 0; w < nw; ++w) {
+            if (r >= deal[(size_t)w].size()) continue;
+            hipStream_t s = pool->s[w];
+            char* ar = arenas + (size_t)w * arena;
+            const int k = deal[(size_t)w][r];
             const TileUnit& t = units[(size_t)k];
             const int i = t.inst;
             fbsde_problem pb = a.pbs[i];
@@ -297,42 +342,29 @@ int run_tiled(const TiledArgs& a, int64_t n_inst, const int64_t* P, const Opts& 
                                                  tpart + (size_t)k * 8, tpart + (size_t)k * 8 + 4, st, ar, arena, s);
             // the tile's CG traffic (forward and reverse), counted in the arena's loop control
             if (!e && !pb.shared_dw) hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, s, cgc + w, cg_bytes_counter(ar));
-            if (e) fail(e);
+            if (e) return e;
         }
-        if (hipStreamSynchronize(s) != hipSuccess) fail(FBSDE_EHIP);
-        (void)hipStreamDestroy(s);
-    };
-    std::vector<std::thread> pool;
-    for (int w = 0; w < nw; ++w) pool.emplace_back(worker, w);
-    for (auto& th : pool) th.join();
-    (void)hipEventDestroy(ev0);
-    if ((rc = first_err.load())) return rc;
-    if (adjoint) {
-        // per instance, the indices of its tiles in point order, then one summing launch each
-        std::vector<std::vector<int>> by_inst((size_t)n_inst);
-        std::vector<std::pair<int64_t, int>> order;
-        for (size_t k = 0; k < units.size(); ++k) order.emplace_back(units[k].p0, (int)k);
-        std::sort(order.begin(), order.end());
-        for (const auto& pk : order) by_inst[(size_t)units[(size_t)pk.second].inst].push_back(pk.second);
-        std::vector<int> flat;
-        std::vector<std::pair<size_t, int>> span((size_t)n_inst);
-        for (int64_t i = 0; i < n_inst; ++i) {
-            span[(size_t)i] = {flat.size(), (int)by_inst[(size_t)i].size()};
-            flat.insert(flat.end(), by_inst[(size_t)i].begin(), by_inst[(size_t)i].end());
-        }
-        // the index table goes to arena 0, free once every worker has synchronised its stream
-        int* d_idx = (int*)arenas;
-        if (!flat.empty() &&
-            hipMemcpyAsync(d_idx, flat.data(), flat.size() * sizeof(int), hipMemcpyHostToDevice, caller) != hipSuccess)
+    for (int w = 0; w < nw; ++w)
+        if (hipEventRecord(pool->join[w], pool->s[w]) != hipSuccess ||
+            hipStreamWaitEvent(caller, pool->join[w], 0) != hipSuccess)
             return FBSDE_EHIP;
-        for (int64_t i = 0; i < n_inst; ++i)
-            hipLaunchKernelGGL(k_sum_tiles, dim3(1), dim3(64), 0, caller, tpart, d_idx + span[(size_t)i].first,
-                               span[(size_t)i].second, a.gp_bar[i], a.fp_bar[i]);
-        if ((rc = last_error())) return rc;
-        // the host index table must outlive its copy
-        if (hipStreamSynchronize(caller) != hipSuccess) return FBSDE_EHIP;
+    if (adjoint) {
+        // per instance, its tiles in point order, summed by launches that carry the indices
+        std::vector<std::vector<std::pair<int64_t, int>>> by_inst((size_t)n_inst);
+        for (size_t k = 0; k < units.size(); ++k) by_inst[(size_t)units[k].inst].emplace_back(units[k].p0, (int)k);
+        for (int64_t i = 0; i < n_inst; ++i) {
+            auto& v = by_inst[(size_t)i];
+            std::sort(v.begin(), v.end());
+            size_t k0 = 0;
+            do {
+                TileList tl{0, {}};
+                for (; k0 < v.size() && tl.n < TILE_LIST; ++k0) tl.idx[tl.n++] = v[k0].second;
+                hipLaunchKernelGGL(k_sum_tiles, dim3(1), dim3(64), 0, caller, tpart, tl,
+                                   (k0 > (size_t)tl.n) ? 1 : 0, a.gp_bar[i], a.fp_bar[i]);
+            } while (k0 < v.size());
+        }
     }
-    return FBSDE_OK;
+    return last_error();
 }
 
 int persistent_size(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, int32_t max_slots, size_t* bytes) {
@@ -468,6 +500,32 @@ int fbsde_solve_batched_backward(const fbsde_problem* pbs, int64_t n_inst, const
             return FBSDE_EINVAL;
     TiledArgs a{pbs, x0, u, nullptr, status, u_bar, x0_bar, gp_bar, fp_bar};
     return run_tiled(a, n_inst, P, o, true, wsp, ws_bytes, (hipStream_t)stream);
+}
+
+int fbsde_graph_capture_batched(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const double* const* x0,
+                                double* const* u, double* const* grad, uint32_t* const* status,
+                                const fbsde_batch_opts* opts, void* wsp, size_t ws_bytes, fbsde_graph* out,
+                                fbsde_stream stream) {
+    if (!out) return FBSDE_EINVAL;
+    *out = nullptr;
+    if (!pbs || !P || !x0 || !u || !status || !wsp || n_inst < 1) return FBSDE_EINVAL;
+    Opts o;
+    int rc = read_opts(opts, o);
+    if (rc) return rc;
+    if (o.mode != FBSDE_BATCH_TILED) return FBSDE_EINVAL;   // the persistent schedule uploads host tables
+    for (int64_t i = 0; i < n_inst; ++i) {
+        if (P[i] > 0 && (!x0[i] || !u[i] || !status[i])) return FBSDE_EINVAL;
+        // the host-driven CG loop (a diagnostic alternative) polls the device, which a graph cannot do
+        if (!pbs[i].shared_dw && pbs[i].cg_fixed_iters <= 0 && std::getenv("FBSDE_CG_HOST_LOOP") &&
+            std::getenv("FBSDE_CG_HOST_LOOP")[0] == '1')
+            return FBSDE_EINVAL;
+    }
+    size_t need = 0;
+    if ((rc = tiled_size(pbs, n_inst, P, o, 0, &need))) return rc;
+    if (need > ws_bytes) return FBSDE_ENOSPC;
+    TiledArgs a{pbs, x0, u, grad, status, nullptr, nullptr, nullptr, nullptr};
+    return capture_graph([&](hipStream_t cap) { return run_tiled(a, n_inst, P, o, false, wsp, ws_bytes, cap); },
+                         (hipStream_t)stream, out);
 }
 
 int fbsde_batched_cg_bytes(const fbsde_problem* pbs, int64_t n_inst, const int64_t* P, const fbsde_batch_opts* opts,

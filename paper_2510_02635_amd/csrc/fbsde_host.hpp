@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <type_traits>
 
 #include "fbsde.h"
@@ -178,6 +179,8 @@ template <typename S>
 void shared_reverse(const fbsde_problem* pb, const Plan& pl1, int k, S* W, const double* ax_dummy, const double* scal,
                     double* Yscratch, double* rn2, uint32_t* status, hipStream_t st);
 void clear_status(uint32_t* status, int64_t P, hipStream_t st);
+// Capture what body enqueues (on the stream it is given) into a graph, as fbsde_graph_capture does.
+int capture_graph(const std::function<int(hipStream_t)>& body, hipStream_t stream, fbsde_graph* out);
 // Divisor of the chip's block slots that a CG loop launch from this host thread asks for (1 by default).
 extern thread_local int loop_share;
 // fbsde_solve for one tile of a batched call; reset_counts = false adds its CG traffic to the count the

@@ -510,3 +510,93 @@ def level_step(pb, k, W_next, W_k, Y_next, x0=None):
     Y, Fp, st = newton(pb, k, C, pb.s * fit["alpha_x"], X)
     return dict(alpha=fit["alpha"], alpha_x=fit["alpha_x"], Y=Y, Fp=Fp, status=st, w=fit["w"],
                 Wbar=fit["Wbar"], Ybar=fit["Ybar"])
+
+
+# ---------------------------------------------------------------- x-dependent coefficients (scheme R)
+# The problem class of Sec. 2.1 with mu(x) = mu0 x + mu1 and sigma(x) = diag(sigma0 x + sigma1),
+# componentwise (the affine diagonal family).  Readings for scheme R, each reducing to the constant
+# coefficient scheme above when mu0 = sigma0 = 0 (mu = mu1, s = sigma1):
+# * Particles: eq. Xk's Euler-Maruyama step, X_{k+1} = X_k + mu(X_k) dt + sigma(X_k) sqrt(dt) xi_k.
+# * Centre: the Euler-Maruyama mean path m_{k+1} = m_k + (mu0 m_k + mu1) dt, m_0 = x0 (the exact mean of
+#   the particles); the next-point regressor is D_j = X^j_{k+1} - m_{k+1}.
+# * Bandwidth and ridge: eps_k^2 = h^2 V_{k+1} and lambda_k = ridge_rel V_{k+1} / d, with
+#   V_{k+1} = E|X_{k+1} - m_{k+1}|^2 from the moment recursion
+#   v_{k+1} = v_k (1 + mu0 dt)^2 + dt (sigma0^2 (v_k + m_k^2) + 2 sigma0 sigma1 m_k + sigma1^2) per coordinate
+#   (s^2 t_{k+1} d and ridge_rel s^2 t_{k+1} for constant coefficients).
+# * Conditional expectation: the fitted model at the drift-transported particle,
+#   C^m_k = alpha + alpha_x . (X^m_k + mu(X^m_k) dt - m_{k+1}) = alpha + (1 + mu0 dt) alpha_x . (X^m_k - m_k).
+# * Z^m_k = sigma(X^m_k)^T alpha_x = (sigma0 X^m_k + sigma1) * alpha_x, per particle.
+# * grad u(0, x0): the x-derivative of the level-0 Newton equation
+#   y = alpha + (1 + mu0 dt) alpha_x . (x - x0) + dt f(0, x, y, Z(x)), Z(x) = (sigma0 x + sigma1) * alpha_x:
+#   ((1 + mu0 dt) alpha_x + dt sigma0 alpha_x * d f / d z) / F'.
+def coef_path(pb, x0, p, coef):
+    """X[k, j, :] for k = 0..N under mu = mu0 x + mu1, sigma = diag(sigma0 x + sigma1) (eq. Xk)."""
+    mu0, sigma0, mu1, sigma1 = coef
+    dt = pb.T / pb.N
+    X = np.empty((pb.N + 1, pb.M, pb.d))
+    X[0] = np.asarray(x0, dtype=np.float64)[None, :]
+    q = stream_of(pb, p)
+    for k in range(pb.N):
+        xi = philox.normals(pb.seed, pb.instance, q, k, pb.M, pb.d)
+        X[k + 1] = X[k] + (mu0 * X[k] + mu1) * dt + (sigma0 * X[k] + sigma1) * (np.sqrt(dt) * xi)
+    return X
+
+
+def coef_moments(pb, x0, coef):
+    """Mean path m[k] (each [d]) and V[k] = E|X_k - m_k|^2 of the Euler-Maruyama particles, k = 0..N."""
+    mu0, sigma0, mu1, sigma1 = coef
+    dt = pb.T / pb.N
+    m = np.asarray(x0, dtype=np.float64).copy()
+    v = np.zeros(pb.d)
+    ms, Vs = [m.copy()], [0.0]
+    for _ in range(pb.N):
+        v = v * (1.0 + mu0 * dt) ** 2 + dt * (sigma0 ** 2 * (v + m * m) + 2.0 * sigma0 * sigma1 * m + sigma1 ** 2)
+        m = m + (mu0 * m + mu1) * dt
+        ms.append(m.copy())
+        Vs.append(float(v.sum()))
+    return ms, Vs
+
+
+def solve_point_coef(pb, x0, p, coef):
+    """Scheme R (one regression per level, Algorithm 1's driver) under the affine diagonal coefficients.
+    pb.s and pb.mu are unused.  Returns dict(u, grad, status)."""
+    if pb.f_kind in X_DEPENDENT_F:
+        raise ValueError("x-dependent coefficients with an x-dependent source are not covered")
+    mu0, sigma0, mu1, sigma1 = coef
+    x0 = np.asarray(x0, dtype=np.float64)
+    dt = pb.T / pb.N
+    X = coef_path(pb, x0, p, coef)
+    ms, Vs = coef_moments(pb, x0, coef)
+    Y, _, _ = g_eval(pb, X[pb.N])
+    status = 0
+    for k in range(pb.N - 1, -1, -1):
+        D = X[k + 1] - ms[k + 1][None, :]
+        if pb.eps_h == 0.0:
+            e = np.ones(pb.M)
+        else:
+            n2 = np.einsum("ij,ij->i", D, D)
+            e = np.exp(-(n2 - n2.min()) / (pb.eps_h ** 2 * Vs[k + 1]))
+        w = e / e.sum()
+        Dbar = w @ D
+        Dc = D - Dbar[None, :]
+        Ybar = w @ Y
+        sysm = RidgeSystem(Dc, w, pb.ridge_rel * Vs[k + 1] / pb.d)
+        alpha_x = sysm.solve_rhs_weighted(Y - Ybar)
+        alpha = Ybar - alpha_x @ Dbar
+        C = alpha + (1.0 + mu0 * dt) * ((X[k] - ms[k][None, :]) @ alpha_x)
+        Ynew = np.empty(pb.M)
+        for m in range(pb.M):
+            Z = (sigma0 * X[k][m] + sigma1) * alpha_x
+            y, Fp, st = newton(pb, k, C[m:m + 1], Z)
+            Ynew[m] = y[0]
+            status |= st
+        Y = Ynew
+        if k == 0:
+            Z0 = (sigma0 * x0 + sigma1) * alpha_x
+            _, fy, fz, fz_scale, _ = f_eval(pb, 0.0, Y[:1], Z0)
+            Fp0 = 1.0 - dt * fy[0]
+            grad = ((1.0 + mu0 * dt) * alpha_x + dt * sigma0 * alpha_x * fz * fz_scale[0]) / Fp0
+    u = float(Y.mean())
+    if not (np.isfinite(u) and np.all(np.isfinite(grad))):
+        status |= ST_NONFINITE
+    return dict(u=u, grad=grad, status=status)

@@ -454,6 +454,30 @@ int fbsde_solve_literal_coef(const fbsde_problem* pb, const fbsde_coef* coef, in
                              const double* x0, double* u, double* Y_out, double* z_stats, uint32_t* status,
                              void* ws, size_t ws_bytes, fbsde_stream stream);
 
+/* Scheme R (fbsde_solve: one weighted ridge regression per point and level, CG on the normal equations,
+ * Newton for Y) under the same affine diagonal coefficients, mu(x) = mu0 x + mu1 and sigma(x) =
+ * diag(sigma0 x + sigma1) componentwise.  The particles of point p follow the Euler-Maruyama step of
+ * eq. Xk from x0[p] with fbsde_solve's increments; the regressor is the displacement D_k = X_k - m_k
+ * from the mean path m_{k+1} = m_k + (mu0 m_k + mu1) dt (m_0 = x0), which makes every particle's
+ * position a function of its own increments and lets the path run backwards in place (the step is
+ * inverted, X_k = (X_{k+1} - mu1 dt - sigma1 dW_k) / (1 + mu0 dt + sigma0 dW_k)).  Per level k:
+ *   weights exp(-|D_{k+1}|^2 / (eps_h^2 V_{k+1})) (uniform for eps_h = 0), V_k = E|X_k - m_k|^2 from
+ *     the exact moment recursion of the step;
+ *   ridge lambda_k = ridge_rel V_{k+1} / d;
+ *   the fitted model taken at the drift-transported particle, C = alpha + (1 + mu0 dt) alpha_x . D_k;
+ *   Z = (sigma0 X_k + sigma1) * alpha_x per particle (sigma(X)^T times the slope);
+ *   grad u = ((1 + mu0 dt) alpha_x + dt sigma0 alpha_x * df/dz) / F'(u) at level 0.
+ * pb->s is not used and pb->mu must be NULL; shared_dw, f kinds that read x and the Case 2 terminal
+ * value are refused (FBSDE_EINVAL), as are coef kinds and values fbsde_solve_literal_coef refuses.  A
+ * cloud whose spread vanishes (V = 0: sigma1 = 0 with x0 = 0) has no regression and is undefined.
+ * Workspace: fbsde_coef_workspace_size bytes (no tape: the adjoint is not offered under these
+ * coefficients).  u [P], grad [P][d] or NULL, status [P] and cg_iters_out as fbsde_solve, on stream;
+ * cg_iters_out, when given, makes the call wait for the stream once per level. */
+int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes);
+int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0, double* u,
+                     double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
+                     fbsde_stream stream);
+
 /* Human-readable text of a return code. */
 const char* fbsde_strerror(int code);
 

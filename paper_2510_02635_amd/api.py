@@ -544,6 +544,34 @@ def literal_coef_workspace_size(pb, P, mu0, sigma0, mu1=0.0, sigma1=0.0):
     return int(out.value)
 
 
+def coef_workspace_size(pb, P, mu0, sigma0, mu1=0.0, sigma1=0.0):
+    out = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)), P,
+                                               ctypes.byref(out)))
+    return int(out.value)
+
+
+def solve_coef(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, want_grad=True, ws=None, return_iters=False):
+    """Scheme R (as solve) under the affine diagonal coefficients mu(x) = mu0 x + mu1, sigma(x) =
+    diag(sigma0 x + sigma1): u [P], grad [P][d] (or None), status [P] (and CG iterations per level)."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    dev = x0.device
+    u = torch.empty(P, dtype=torch.float64, device=dev)
+    grad = torch.empty((P, pb.d), dtype=torch.float64, device=dev) if want_grad else None
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = torch.empty(max(coef_workspace_size(pb, P, mu0, sigma0, mu1, sigma1), 1), dtype=torch.uint8, device=dev)
+    iters = (ctypes.c_int32 * pb.N)() if return_iters else None
+    N.check(N.load().fbsde_solve_coef(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)), P,
+                                      x0.data_ptr(), u.data_ptr(), _ptr(grad), st.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), ctypes.cast(iters, ctypes.c_void_p) if return_iters else None,
+                                      _stream()))
+    if return_iters:
+        return u, grad, st, list(iters)
+    return u, grad, st
+
+
 def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zstats=False, ws=None, mu1=0.0,
                             sigma1=0.0):
     """Paper-literal per-anchor scheme under the affine diagonal coefficients mu(x) = mu0 x + mu1,

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <map>
 #include <functional>
+#include <vector>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -105,6 +106,12 @@ struct WS {
     int nq;
     int64_t qcap;
     bool fixed_buffer;           // the allocation-free entry point: no timer events, device CG loop only
+    // x-dependent coefficients (fbsde_solve_coef): the family, V[p][k] of the moment recursion and the
+    // mean path's m_k = x0 A[k] + B[k]; null for the constant-coefficient solve
+    const CoefArgs* coef = nullptr;
+    const double* coefV = nullptr;
+    const double* coefA = nullptr;
+    const double* coefB = nullptr;
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
     int* tag;
@@ -169,15 +176,25 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
 // -------------------------------------------------------------------- launch sequences
 template <typename S>
 void launch_forward(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, S* W, int64_t ldw,
-                    double* Y, double* rn2, uint32_t* status, hipStream_t st) {
+                    double* Y, double* rn2, uint32_t* status, hipStream_t st, const WS* ws = nullptr) {
     const Keys ky = keys_of(pb);
     const double dt = pb->T / (double)pb->N;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
-        hipLaunchKernelGGL((k_forward<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
-                           ldw, (int)pl.M, pl.rows_per_chunk, x0, pb->mu, pb->gvec, (int)pl.d, pl.ld, (int)pl.N,
-                           std::sqrt(dt), pb->s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], ky.k0, ky.k1,
-                           pb->point_base, 0, Y, rn2, status);
+        if (ws && ws->coef) {   // x-dependent coefficients: Euler-Maruyama positions, state D_N = X_N - m_N
+            CoefArgs cf = *ws->coef;
+            cf.Aa = ws->coefA[pl.N];
+            cf.Ba = ws->coefB[pl.N];
+            hipLaunchKernelGGL((k_forward<S, QQ, TT, true>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
+                               W, ldw, (int)pl.M, pl.rows_per_chunk, x0, nullptr, pb->gvec, (int)pl.d, pl.ld,
+                               (int)pl.N, std::sqrt(dt), pb->s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], ky.k0, ky.k1,
+                               pb->point_base, 0, Y, rn2, status, cf);
+        } else {
+            hipLaunchKernelGGL((k_forward<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
+                               ldw, (int)pl.M, pl.rows_per_chunk, x0, pb->mu, pb->gvec, (int)pl.d, pl.ld, (int)pl.N,
+                               std::sqrt(dt), pb->s, pb->T, pb->g_kind, pb->gp[0], pb->gp[1], ky.k0, ky.k1,
+                               pb->point_base, 0, Y, rn2, status, CoefArgs{});
+        }
     });
 }
 
@@ -312,8 +329,11 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
     const double s2 = pb->s * pb->s;
     const double eps2 = (pb->eps_h > 0.0) ? pb->eps_h * pb->eps_h * s2 * t_next * (double)pl.d : 0.0;
     const double lam = pb->ridge_rel * s2 * t_next;
+    // x-dependent coefficients: the point's own bandwidth h^2 V_{k+1} and ridge ridge_rel V_{k+1} / d
+    const double* vt = ws.coef ? ws.coefV + (k + 1) : nullptr;
+    const int vstride = (int)pl.N + 1;
     hipLaunchKernelGGL(k_weights, dim3((unsigned)P), dim3(256), 0, st, rn2, Y_next, (int)pl.M, s2, eps2, w_out,
-                       ws.c2, ws.scal, NS, ws.active, (int)P, warm);
+                       ws.c2, ws.scal, NS, ws.active, (int)P, warm, vt, vstride, pb->eps_h * pb->eps_h);
     // a rank-deficient design (M <= d + 1) in FP32C: FP64 arithmetic on the FP32 state in the moments and
     // the CG product, whose FP32 rounding would otherwise reach the ridge-only null space of the design
     // (where the solution carries it with weight 1/lam)
@@ -332,7 +352,7 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
     const int vc = fold_parts(pl, P, ws.part1, ws.part2, warm ? ws.part3 : nullptr, st);
     hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.part3, ws.psc,
                        pl.nchunk, vc, pl.ld, pb->s, lam, warm, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
-                       ws.active);
+                       ws.active, vt, vstride, pb->ridge_rel / (double)pl.d);
     const int iters = r64 ? run_cg<S, double>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err)
                           : run_cg<S, S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
     if (err) return iters;
@@ -351,7 +371,17 @@ void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
         // the particles' positions x0 + t_k mu + s W_k enter f
-        if (pb->f_kind == FBSDE_F_HJ_SINK)
+        if (ws.coef) {   // x-dependent coefficients: the Euler-Maruyama step inverted, per-particle Z
+            CoefArgs cf = *ws.coef;
+            cf.Aa = ws.coefA[k];
+            cf.Ba = ws.coefB[k];
+            cf.Ab = ws.coefA[k + 1];
+            cf.Bb = ws.coefB[k + 1];
+            hipLaunchKernelGGL((k_reverse<S, QQ, TT, 3>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
+                               std::sqrt(dt), pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters,
+                               ky.k0, ky.k1, pb->point_base, Y, rn2, dydc, status, shared, x0, nullptr, 0.0, cf);
+        } else if (pb->f_kind == FBSDE_F_HJ_SINK)
             hipLaunchKernelGGL((k_reverse<S, QQ, TT, 1>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
                                st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
                                std::sqrt(dt), pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters,
@@ -395,7 +425,10 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
                        nullptr, (int64_t)0, reset_counts ? 1 : 0);
     double* Ycur = ws.Ya;
     double* Yk = ws.Yb;
-    launch_forward<S>(pb, pl, P, x0, W, ldw, Ycur, ws.rn2, status, st);
+    if (ws.coef)   // x-dependent coefficients: V[p][k] and the mean path's coordinates (r, pv as scratch)
+        hipLaunchKernelGGL(k_coef_moments, dim3((unsigned)P), dim3(256), 0, st, x0, (int)pl.d, pl.ld, (int)pl.N,
+                           *ws.coef, ws.r, ws.pv, (double*)ws.coefV);
+    launch_forward<S>(pb, pl, P, x0, W, ldw, Ycur, ws.rn2, status, st, &ws);
     int err = last_error();
     if (err) return err;
     for (int k = (int)pl.N - 1; k >= 0; --k) {
@@ -427,7 +460,8 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
             else Ycur = Yout;
         } else {
             hipLaunchKernelGGL(k_outputs, dim3((unsigned)P), dim3(256), 0, st, ws.x, pl.ld, (int)pl.d, ws.scal, NS,
-                               fspec_of(pb), pb->T / (double)pb->N, pb->newton_iters, u, grad, status, x0, pb->s);
+                               fspec_of(pb), pb->T / (double)pb->N, pb->newton_iters, u, grad, status, x0, pb->s,
+                               ws.coef ? 1 : 0, ws.coef ? *ws.coef : CoefArgs{});
         }
         err = last_error();
         if (err) return err;
@@ -729,6 +763,85 @@ int fbsde_solve(const fbsde_problem* pb, int64_t P, const double* x0, double* u,
     hipStream_t st = (hipStream_t)stream;
     if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
     return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
+}
+
+}  // extern "C"
+
+namespace {
+// The per-point scheme under the affine diagonal coefficients: the problem as the kernels see it (s = 1:
+// the state is the displacement from the mean path itself), the plan and the family.
+int coef_r_check(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, fbsde_problem& pbc, Plan& pl,
+                 CoefArgs& cf) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    if (!coef || coef->reserved != 0) return FBSDE_EINVAL;
+    if (coef->kind != FBSDE_COEF_GEOMETRIC && coef->kind != FBSDE_COEF_AFFINE_DIAG) return FBSDE_EINVAL;
+    if (coef->kind == FBSDE_COEF_GEOMETRIC && (coef->mu1 != 0.0 || coef->sigma1 != 0.0)) return FBSDE_EINVAL;
+    const double v[4] = {coef->mu0, coef->sigma0, coef->mu1, coef->sigma1};
+    for (double x : v)
+        if (!std::isfinite(x)) return FBSDE_EINVAL;
+    if (!(coef->sigma0 * coef->sigma0 + coef->sigma1 * coef->sigma1 > 0.0)) return FBSDE_EINVAL;
+    // the family's drift replaces the constant one; one cloud per point; sources that read x are not covered
+    if (pb->mu || pb->shared_dw || per_point_forward_only(pb)) return FBSDE_EINVAL;
+    pbc = *pb;
+    pbc.s = 1.0;
+    if ((rc = make_plan(&pbc, P, pl))) return rc;
+    cf = CoefArgs{coef->mu0, coef->sigma0, coef->mu1, coef->sigma1, pb->T / (double)pb->N, 0.0, 0.0, 0.0, 0.0};
+    return FBSDE_OK;
+}
+
+// the table V[p][k], k = 0..N, after the per-point workspace
+size_t coef_r_table_bytes(const Plan& pl, int64_t P) { return (size_t)round_up(P * (pl.N + 1) * 8, 256); }
+}  // namespace
+
+extern "C" {
+
+int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes) {
+    if (!bytes) return FBSDE_EINVAL;
+    fbsde_problem pbc;
+    Plan pl;
+    CoefArgs cf;
+    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
+    if (rc) return rc;
+    WS ws;
+    *bytes = carve(pl, P, 0, nullptr, ws) + coef_r_table_bytes(pl, P);
+    return FBSDE_OK;
+}
+
+int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0, double* u,
+                     double* grad, uint32_t* status, void* wsp, size_t ws_bytes, int32_t* cg_iters_out,
+                     fbsde_stream stream) {
+    fbsde_problem pbc;
+    Plan pl;
+    CoefArgs cf;
+    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
+    if (rc) return rc;
+    if (P == 0) {
+        if (cg_iters_out)
+            for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;
+        return FBSDE_OK;
+    }
+    if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    WS ws;
+    const size_t base = carve(pl, P, 0, nullptr, ws);
+    if (base + coef_r_table_bytes(pl, P) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, 0, (char*)wsp, ws);
+    // the mean path m_k = x0 A_k + B_k of the Euler-Maruyama step, per coordinate
+    std::vector<double> A((size_t)pl.N + 1), B((size_t)pl.N + 1);
+    A[0] = 1.0;
+    B[0] = 0.0;
+    for (int64_t k = 0; k < pl.N; ++k) {
+        A[k + 1] = A[k] * (1.0 + cf.mu0 * cf.dt);
+        B[k + 1] = B[k] * (1.0 + cf.mu0 * cf.dt) + cf.mu1 * cf.dt;
+    }
+    ws.coef = &cf;
+    ws.coefV = (const double*)((char*)wsp + base);
+    ws.coefA = A.data();
+    ws.coefB = B.data();
+    hipStream_t st = (hipStream_t)stream;
+    if (pbc.prec == FBSDE_F64)
+        return solve_impl<double>(&pbc, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
+    return solve_impl<float>(&pbc, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
 }
 
 }  // extern "C"

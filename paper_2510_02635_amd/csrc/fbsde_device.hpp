@@ -237,6 +237,11 @@ enum { ST_CG_MAXIT = 1, ST_NEWTON_FLAT = 2, ST_NONFINITE = 4 };
 
 struct FSpec { int kind; double p0, p1, p2 = 0.0; };
 
+// x-dependent coefficients mu(x) = mu0 x + mu1, sigma(x) = diag(sigma0 x + sigma1) in the per-point form:
+// the state holds D = X - m, m the Euler-Maruyama mean path, with m_k = x0 A_k + B_k (A_k = (1 + mu0 dt)^k,
+// B_k its drift part); a, b: the levels a kernel touches (the reversal reads k + 1 and writes k).
+struct CoefArgs { double mu0, s0, mu1, s1, dt, Aa, Ba, Ab, Bb; };
+
 // f(t, x, y, z) and d f / d y of the built-in families; zz = |z|^2 and zs = sum_i z_i (z shared by the
 // cloud).  BURGERS: fp0 (y - fp1) sum_i z_i, the Burgers-type nonlinearity of the Sec. 4 experiments in
 // a form whose logistic solution is exact (fp0 = s/d, fp1 = d/s^2 + 1/2).

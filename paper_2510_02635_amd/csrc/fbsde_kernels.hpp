@@ -26,13 +26,16 @@ namespace fbsde {
 // ------------------------------------------------------------------------------------------
 // Forward sweep and terminal condition (Algorithm 1, first two loops; eq. Xk):
 //   W^j_N = sum_k sqrt(dt) xi^j_k in registers, one store; Y^j_N = g(x0 + mu T + s W^j_N).
-template <typename S, int Q, int TEAM>
+// COEF: x-dependent coefficients (CoefArgs): every coordinate follows the Euler-Maruyama step
+// X_{k+1} = X_k + (mu0 X_k + mu1) dt + (sigma0 X_k + sigma1) sqrt(dt) xi_k from x0, and the state holds
+// D_N = X_N - m_N (cf.Aa, cf.Ba: A_N, B_N).
+template <typename S, int Q, int TEAM, bool COEF = false>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const double* __restrict__ x0,
           const double* __restrict__ mu, const double* __restrict__ gvec, int d, int ld, int N,
           double sqdt, double s, double T, int g_kind, double ga, double gb, uint32_t k0, uint32_t k1,
           uint32_t point_base, int shared, double* __restrict__ Y, double* __restrict__ rn2,
-          uint32_t* __restrict__ status) {
+          uint32_t* __restrict__ status, CoefArgs cf = CoefArgs{}) {
     using G = Geo<Q, TEAM>;
     __shared__ double red[2 * G::BS / 64];
     const int p = blockIdx.y;
@@ -46,17 +49,17 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int i = 4 * (L + q * G::TL) + e;
-            xc[q][e] = (i < d) ? (x0 ? x0[(int64_t)p * d + i] : 0.0) + (mu ? mu[i] * T : 0.0) : 0.0;
+            xc[q][e] = (i < d) ? (x0 ? x0[(int64_t)p * d + i] : 0.0) + ((mu && !COEF) ? mu[i] * T : 0.0) : 0.0;
         }
     uint32_t st = 0;
     for (int jb = r0; jb < r1; jb += G::TPW) {
         const int j = jb + team;
         const bool valid = j < r1;
-        double w[Q][4];
+        double w[Q][4];   // COEF: the position X; otherwise the Brownian displacement W
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) w[q][e] = 0.0;
+            for (int e = 0; e < 4; ++e) w[q][e] = COEF ? xc[q][e] : 0.0;
         if (valid) {
             for (int k = 0; k < N; ++k) {
 #pragma unroll
@@ -67,7 +70,14 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
                         increment4<S>((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (4 * g + e < d) w[q][e] += sqdt * (double)z[e];
+                            if (4 * g + e < d) {
+                                if constexpr (COEF) {
+                                    const double xv = w[q][e];
+                                    w[q][e] = xv + (cf.mu0 * xv + cf.mu1) * cf.dt + (cf.s0 * xv + cf.s1) * (sqdt * (double)z[e]);
+                                } else {
+                                    w[q][e] += sqdt * (double)z[e];
+                                }
+                            }
                     }
                 }
             }
@@ -81,13 +91,14 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
                 if (e0 < ld) {
                     S v[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = (S)w[q][e];
+                    for (int e = 0; e < 4; ++e)
+                        v[e] = COEF ? ((e0 + e < d) ? (S)(w[q][e] - (xc[q][e] * cf.Aa + cf.Ba)) : (S)0) : (S)w[q][e];
                     if (!shared || p == 0) store4(row + e0, v);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const double ws = (double)v[e];
                         n2 += ws * ws;
-                        const double X = xc[q][e] + s * ws;
+                        const double X = COEF ? w[q][e] : xc[q][e] + s * ws;
                         if (g_dot_arg(g_kind)) gq += ((e0 + e < d) ? gvec[e0 + e] : 0.0) * X;
                         else gq += X * X;
                         if (g_kind == G_CASE2 && e0 + e < d) Pp *= X;
@@ -113,11 +124,14 @@ k_forward(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, const doubl
 // dY_j/dC_j = 1/F'(Y_j) from the previous level's Newton solve, and rho = sum_j w_j dY_j/dC_j is
 // stored in scal[7] (the scale of the CG warm start).
 __global__ void __launch_bounds__(256)
-k_weights(const double* __restrict__ rn2, const double* __restrict__ Y, int M, double s2, double eps2,
+k_weights(const double* __restrict__ rn2, const double* __restrict__ Y, int M, double s2, double eps2_all,
           double* __restrict__ w, double* __restrict__ c2, double* __restrict__ scal, int ns, int* active, int P,
-          int warm) {
+          int warm, const double* __restrict__ vt = nullptr, int vstride = 0, double vfac = 0.0) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
+    // x-dependent coefficients: the bandwidth of the point's own cloud, vfac V (vt[p vstride] = V of its
+    // Euler-Maruyama particles at this level)
+    const double eps2 = vt ? vfac * vt[(int64_t)p * vstride] : eps2_all;
     const double* n = rn2 + (int64_t)p * M;
     const double* y = Y + (int64_t)p * M;
     double* wp = w + (int64_t)p * M;
@@ -272,10 +286,12 @@ k_fold_chunks(double* __restrict__ a, double* __restrict__ b, double* __restrict
 __global__ void __launch_bounds__(256)
 k_moments_finish(const double* __restrict__ part1, const double* __restrict__ part2,
                  const double* __restrict__ part3, const double* __restrict__ psc, int nchunk, int vchunks, int ld,
-                 double s, double lam, int warm, double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
-                 double* __restrict__ pv, double* __restrict__ scal, int ns, int* __restrict__ iscal, int* active) {
+                 double s, double lam_all, int warm, double* __restrict__ Wbar, double* __restrict__ x, double* __restrict__ r,
+                 double* __restrict__ pv, double* __restrict__ scal, int ns, int* __restrict__ iscal, int* active,
+                 const double* __restrict__ vt = nullptr, int vstride = 0, double vfac = 0.0) {
     __shared__ double lds[16];
     const int p = blockIdx.x;
+    const double lam = vt ? vfac * vt[(int64_t)p * vstride] : lam_all;   // per point (x-dependent coefficients)
     double sig = 0.0, tau = 0.0;
     for (int c = 0; c < nchunk; ++c) {
         sig += psc[((int64_t)p * nchunk + c) * 2];
@@ -493,7 +509,11 @@ k_level_finish(const double* __restrict__ x, const double* __restrict__ Wbar, in
 // b = x0 + t_k mu (a third row dot b . W_k gives |X|^2) and moved into C (Newton's F(y) = y - C - dt f
 // with f = f(y) + source): XK = 1 the Hamilton-Jacobi-type source (a function of |X|^2), XK = 2 the
 // Allen-Cahn Case 2 source, which also needs the coordinate products (P, Q2) of X (pq_add per lane,
-// team_pq across the team).
+// team_pq across the team).  XK = 3: x-dependent coefficients (CoefArgs; b = x0): the state holds
+// D = X - m, the reversal inverts the Euler-Maruyama step, X_k = (X_{k+1} - mu1 dt - sigma1 dW) /
+// (1 + mu0 dt + sigma0 dW), the model is taken at the drift-transported particle, C = alpha +
+// (1 + mu0 dt) alpha_x . D_k, and Z = (sigma0 X_k + sigma1) * alpha_x is the particle's own (|Z|^2 and
+// sum_i Z_i per row).
 template <typename S, int Q, int TEAM, int XK = 0>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int ld, int k, int zero_state,
@@ -501,7 +521,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
           int ns, FSpec f, int newton_iters, uint32_t k0, uint32_t k1, uint32_t point_base,
           double* __restrict__ Y, double* __restrict__ rn2, double* __restrict__ dydc, uint32_t* __restrict__ status,
           int shared, const double* __restrict__ x0 = nullptr, const double* __restrict__ mu = nullptr,
-          double tk = 0.0) {
+          double tk = 0.0, CoefArgs cf = CoefArgs{}) {
     using G = Geo<Q, TEAM>;
     using R = S;
     __shared__ double red[2 * G::BS / 64];
@@ -539,11 +559,11 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     // Newton runs 64 rows at a time: lane (row count mod 64) of the team's first wave keeps the row's
     // C and |W|^2, and every 64 rows those lanes solve together instead of one lane per row
     int j_keep = -1;
-    double c_keep = 0.0, n2_keep = 0.0;
+    double c_keep = 0.0, n2_keep = 0.0, zz_keep = zz, zs_keep = zs;   // XK == 3: the particle's own Z
     auto flush = [&]() {
         if (j_keep >= 0) {
             double Fp;
-            const double y = newton_y(f, c_keep, zz, zs, dt, newton_iters, Fp, st);
+            const double y = newton_y(f, c_keep, zz_keep, zs_keep, dt, newton_iters, Fp, st);
             Y[(int64_t)p * M + j_keep] = y;
             rn2[(int64_t)p * M + j_keep] = n2_keep;
             if (dydc) dydc[(int64_t)p * M + j_keep] = 1.0 / Fp;
@@ -554,7 +574,7 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
     for (int jb = r0; jb < r1; jb += G::TPW) {
         const int j = jb + team;
         const bool valid = j < r1;
-        CSum<R> n2s, dots, xbs;
+        CSum<R> n2s, dots, xbs, zsum;   // XK == 3: xbs sums |Z|^2, zsum sum_i Z_i
         double Pp = 1.0, Pq = 0.0;   // XK == 2: (P, Q2) of the lane's coordinates of X
         if (valid) {
             S* row = W + ((int64_t)p * M + j) * ldw;
@@ -574,13 +594,26 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
                             increment4<S>((uint32_t)g, (uint32_t)j, (uint32_t)k, qs, k0, k1, z);
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
-                                if (e0 + e < d) v[e] = (S)((double)v[e] - sqdt * (double)z[e]);
+                                if (e0 + e < d) {
+                                    if constexpr (XK == 3) {
+                                        const double xb0 = (double)b[q][e];
+                                        const double dW = sqdt * (double)z[e];
+                                        const double X1 = xb0 * cf.Ab + cf.Bb + (double)v[e];
+                                        const double X0 = (X1 - cf.mu1 * cf.dt - cf.s1 * dW) / (1.0 + cf.mu0 * cf.dt + cf.s0 * dW);
+                                        v[e] = (S)(X0 - (xb0 * cf.Aa + cf.Ba));
+                                        const double zi = (cf.s0 * X0 + cf.s1) * (double)a[q][e];
+                                        xbs.add((R)(zi * zi));
+                                        zsum.add((R)zi);
+                                    } else {
+                                        v[e] = (S)((double)v[e] - sqdt * (double)z[e]);
+                                    }
+                                }
                         }
                     }
                     store4(row + e0, v);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) { n2s.add(v[e] * v[e]); dots.add(a[q][e] * v[e]); }
-                    if constexpr (XK != 0) {
+                    if constexpr (XK == 1 || XK == 2) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) xbs.add(b[q][e] * v[e]);
                     }
@@ -594,8 +627,14 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
         }
         double n2 = n2s.get(), dt_ = dots.get();
         team_sum2<TEAM>(n2, dt_, red, team);
-        double src = 0.0;
-        if constexpr (XK != 0) {
+        double src = 0.0, zz_row = zz, zs_row = zs;
+        if constexpr (XK == 3) {
+            zz_row = xbs.get();
+            zs_row = zsum.get();
+            team_sum2<TEAM>(zz_row, zs_row, red, team);
+            dt_ *= 1.0 + cf.mu0 * cf.dt;   // the drift-transported particle
+        }
+        if constexpr (XK == 1 || XK == 2) {
             double xb = xbs.get(), unused = 0.0;
             team_sum2<TEAM>(xb, unused, red, team);
             const double r2 = bb + 2.0 * s * xb + s * s * n2;
@@ -609,11 +648,44 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
             j_keep = j;
             c_keep = alpha + s * dt_ + src;
             n2_keep = n2;
+            zz_keep = zz_row;
+            zs_keep = zs_row;
         }
         if ((++cnt & 63) == 0) flush();
     }
     flush();
     if (st) atomicOr(&status[p], st);
+}
+
+// x-dependent coefficients: V[p][k] = E|X_k - m_k|^2 of point p's Euler-Maruyama particles, k = 0..N, from
+// the moment recursion per coordinate, m_{k+1} = m_k + (mu0 m_k + mu1) dt (m_0 = x0) and
+// v_{k+1} = v_k (1 + mu0 dt)^2 + dt (sigma0^2 (v_k + m_k^2) + 2 sigma0 sigma1 m_k + sigma1^2) (v_0 = 0).
+// One block per point; m and v of the coordinates live in mbuf, vbuf [P][ld] between levels.
+__global__ void __launch_bounds__(256)
+k_coef_moments(const double* __restrict__ x0, int d, int ld, int N, CoefArgs cf, double* __restrict__ mbuf,
+               double* __restrict__ vbuf, double* __restrict__ V) {
+    __shared__ double lds[16];
+    const int p = blockIdx.x;
+    double* m = mbuf + (int64_t)p * ld;
+    double* v = vbuf + (int64_t)p * ld;
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        m[i] = x0[(int64_t)p * d + i];
+        v[i] = 0.0;
+    }
+    if (threadIdx.x == 0) V[(int64_t)p * (N + 1)] = 0.0;
+    const double a = 1.0 + cf.mu0 * cf.dt;
+    for (int k = 0; k < N; ++k) {
+        double sv = 0.0;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            const double mi = m[i], vi = v[i];
+            const double vn = vi * a * a + cf.dt * (cf.s0 * cf.s0 * (vi + mi * mi) + 2.0 * cf.s0 * cf.s1 * mi + cf.s1 * cf.s1);
+            v[i] = vn;
+            m[i] = mi + (cf.mu0 * mi + cf.mu1) * cf.dt;
+            sv += vn;
+        }
+        sv = block_sum(sv, lds);
+        if (threadIdx.x == 0) V[(int64_t)p * (N + 1) + k + 1] = sv;
+    }
 }
 
 // Level-0 outputs: u = Y^m_0 (every particle sits at x0, so C = alpha) and
@@ -626,7 +698,9 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
 __global__ void __launch_bounds__(256)
 k_outputs(const double* __restrict__ x, int ld, int d, const double* __restrict__ scal, int ns, FSpec f,
           double dt, int newton_iters, double* __restrict__ u, double* __restrict__ grad,
-          uint32_t* __restrict__ status, const double* __restrict__ x0 = nullptr, double s = 0.0) {
+          uint32_t* __restrict__ status, const double* __restrict__ x0 = nullptr, double s = 0.0,
+          int coef_on = 0, CoefArgs cfo = CoefArgs{}) {
+    const CoefArgs* coef = coef_on ? &cfo : nullptr;   // x-dependent coefficients
     __shared__ double lds[16];
     __shared__ double segP[256], segQ[256];
     const int p = blockIdx.x;
@@ -653,11 +727,33 @@ k_outputs(const double* __restrict__ x, int ld, int d, const double* __restrict_
         for (int t = 0; t < nt; ++t) pq_combine(Pall, Qall, segP[t], segQ[t]);
         csrc = -case2_source(0.0, r2, Pall, Qall, (double)d, s, f.p0, f.p1, f.p2);   // f = F(y) - S2
     }
+    // x-dependent coefficients: Z_0 = (sigma0 x0 + sigma1) * alpha_x at x0, where every particle sits
+    double zz0 = scal[(int64_t)p * ns + 6], zs0 = scal[(int64_t)p * ns + 8];
+    if (coef) {
+        double a = 0.0, b = 0.0;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            const double zi = (coef->s0 * (xp ? xp[i] : 0.0) + coef->s1) * x[(int64_t)p * ld + i];
+            a += zi * zi;
+            b += zi;
+        }
+        zz0 = block_sum(a, lds);
+        zs0 = block_sum(b, lds);
+    }
     double Fp;
-    const double y = newton_y(f, scal[(int64_t)p * ns + 5] + dt * csrc, scal[(int64_t)p * ns + 6],
-                              scal[(int64_t)p * ns + 8], dt, newton_iters, Fp, st);
+    const double y = newton_y(f, scal[(int64_t)p * ns + 5] + dt * csrc, zz0, zs0, dt, newton_iters, Fp, st);
     if (threadIdx.x == 0) u[p] = y;
-    if (grad) {
+    if (grad && coef) {
+        // the x-derivative of y = alpha + (1 + mu0 dt) alpha_x . (x - x0) + dt f(0, x, y, Z(x)),
+        // Z(x) = (sigma0 x + sigma1) * alpha_x: ((1 + mu0 dt) alpha_x + dt sigma0 alpha_x * d f / d z) / F'
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            const double ai = x[(int64_t)p * ld + i];
+            const double zi = (coef->s0 * (xp ? xp[i] : 0.0) + coef->s1) * ai;
+            const double fz = (f.kind == F_HJB) ? -2.0 * f.p0 * zi : (f.kind == F_BURGERS) ? f.p0 * (y - f.p1) : 0.0;
+            const double gi = ((1.0 + coef->mu0 * coef->dt) * ai + dt * coef->s0 * ai * fz) / Fp;
+            grad[(int64_t)p * d + i] = gi;
+            if (!isfinite(gi)) st |= ST_NONFINITE;
+        }
+    } else if (grad) {
         if (f.kind == F_LOG_POT) {
             double EP = 1.0, EQ = 0.0, FP = 1.0, FQ = 0.0;   // segments before / after this thread's
             for (int t = 0; t < nt; ++t) {

@@ -600,3 +600,73 @@ def solve_point_coef(pb, x0, p, coef):
     if not (np.isfinite(u) and np.all(np.isfinite(grad))):
         status |= ST_NONFINITE
     return dict(u=u, grad=grad, status=status)
+
+
+# ---------------------------------------------------------------- constant matrix sigma (scheme R)
+# The problem class of Sec. 2.1 with a constant d x d diffusion matrix sigma (invertible) and the
+# constant drift mu: X_{k+1} = X_k + mu dt + sigma sqrt(dt) xi_k (eq. Xk, exact in law here), Z = sigma^T grad u.
+# Readings, each reducing to the scalar scheme above when sigma = s I:
+# * The cloud at t_{k+1} has covariance Sigma_{k+1} = t_{k+1} sigma sigma^T about the mean path
+#   m_{k+1} = x0 + mu t_{k+1}; the regressor is D_j = X^j_{k+1} - m_{k+1}.
+# * Kernel weights in the cloud's own metric: exp(-D^T Sigma_{k+1}^{-1} D / (h^2 d)) (the Gaussian kernel
+#   with bandwidth matrix h^2 d Sigma_{k+1}; the scalar form s^2 t d h^2 I is its case sigma = s I).
+# * Ridge on the quantity the scheme uses, Z = sigma^T alpha_x: penalty lambda |sigma^T alpha_x|^2 with
+#   lambda = ridge_rel t_{k+1} (ridge_rel s^2 t_{k+1} |alpha_x|^2 for sigma = s I), so the normal equations
+#   read (D'^T W D' + lambda sigma sigma^T) alpha_x = D'^T W (Y - Ybar).
+# * C^m_k = alpha + alpha_x . (X^m_k - m_k); Z_k = sigma^T alpha_x (shared by the cloud); grad u(0, x0) =
+#   alpha_x / F'(u) at level 0 (f does not depend on x here).
+def matrix_sigma_path(pb, x0, p, sigma):
+    """X[k, j, :] for k = 0..N: Euler-Maruyama with the constant matrix sigma and drift pb.mu."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    dt = pb.T / pb.N
+    mu = np.zeros(pb.d) if pb.mu is None else np.asarray(pb.mu, dtype=np.float64)
+    X = np.empty((pb.N + 1, pb.M, pb.d))
+    X[0] = np.asarray(x0, dtype=np.float64)[None, :]
+    q = stream_of(pb, p)
+    for k in range(pb.N):
+        xi = philox.normals(pb.seed, pb.instance, q, k, pb.M, pb.d)
+        X[k + 1] = X[k] + mu[None, :] * dt + np.sqrt(dt) * (xi @ sigma.T)
+    return X
+
+
+def solve_point_matrix_sigma(pb, x0, p, sigma):
+    """Scheme R under a constant invertible diffusion matrix sigma [d][d] (pb.s unused).
+    Returns dict(u, grad, status)."""
+    if pb.f_kind in X_DEPENDENT_F:
+        raise ValueError("a matrix sigma with an x-dependent source is not covered")
+    sigma = np.asarray(sigma, dtype=np.float64)
+    x0 = np.asarray(x0, dtype=np.float64)
+    dt = pb.T / pb.N
+    mu = np.zeros(pb.d) if pb.mu is None else np.asarray(pb.mu, dtype=np.float64)
+    SS = sigma @ sigma.T
+    SS_fac = sla.cho_factor(SS, lower=True)
+    X = matrix_sigma_path(pb, x0, p, sigma)
+    Y, _, _ = g_eval(pb, X[pb.N])
+    status = 0
+    for k in range(pb.N - 1, -1, -1):
+        t_next = (k + 1) * dt
+        D = X[k + 1] - (x0 + mu * t_next)[None, :]
+        if pb.eps_h == 0.0:
+            e = np.ones(pb.M)
+        else:
+            # D^T Sigma^{-1} D with Sigma = t_next sigma sigma^T
+            q2 = np.einsum("ij,ij->i", D, sla.cho_solve(SS_fac, D.T).T) / t_next
+            e = np.exp(-(q2 - q2.min()) / (pb.eps_h ** 2 * pb.d))
+        w = e / e.sum()
+        Dbar = w @ D
+        Dc = D - Dbar[None, :]
+        Ybar = w @ Y
+        lam = pb.ridge_rel * t_next
+        A = Dc.T @ (w[:, None] * Dc) + lam * SS
+        alpha_x = np.linalg.solve(A, Dc.T @ (w * (Y - Ybar)))
+        alpha = Ybar - alpha_x @ Dbar
+        C = alpha + (X[k] - (x0 + mu * k * dt)[None, :]) @ alpha_x
+        Z = sigma.T @ alpha_x
+        Y, Fp, st = newton(pb, k, C, Z)
+        status |= st
+        if k == 0:
+            grad = alpha_x / Fp[0]
+    u = float(Y.mean())
+    if not (np.isfinite(u) and np.all(np.isfinite(grad))):
+        status |= ST_NONFINITE
+    return dict(u=u, grad=grad, status=status)

@@ -478,6 +478,26 @@ int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P,
                      double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
                      fbsde_stream stream);
 
+/* Scheme R under a constant diffusion matrix (Sec. 2.1's problem class with matrix sigma; Z = sigma^T
+ * grad u in the steps after the matrix-free solve): X_k = x0 + mu t_k + sigma W_k with sigma [d][d]
+ * invertible (device, FP64, row-major) and pb->mu the constant drift (or NULL).  The regression of level k
+ * uses the cloud's own metric: Gaussian weights exp(-D^T Sigma^{-1} D / (eps_h^2 d)) with Sigma =
+ * t_{k+1} sigma sigma^T, the ridge lambda |sigma^T alpha_x|^2 with lambda = ridge_rel t_{k+1} on the
+ * quantity the scheme uses (Z = sigma^T alpha_x), C = alpha + alpha_x . (X_k - x0 - mu t_k); both reduce
+ * to fbsde_solve's at sigma = s I.  grad u(0, x0) = alpha_x / F'(u).  The library runs the per-point path in
+ * the coordinates W = sigma^{-1} (X - x0 - mu t), where the weights and ridge are fbsde_solve's at s = 1
+ * and the slope is Z; sigma enters the terminal values (sigma W_N on the matrix cores, point chunk by
+ * chunk) and grad u = sigma^{-T} Z / F' (solved through sigma sigma^T, blocked Cholesky).
+ * pb->s is not used; shared_dw, f kinds that read x and the Case 2 terminal value are refused
+ * (FBSDE_EINVAL).  A sigma singular to working precision marks every point's status ST_NONFINITE
+ * (grad NULL: not detected).  Workspace fbsde_sigma_workspace_size bytes (the per-point workspace plus
+ * at most 512 MiB of sigma W_N rows and the d x d factor); u [P], grad [P][d] or NULL, status [P],
+ * cg_iters_out as fbsde_solve, on stream. */
+int fbsde_sigma_workspace_size(const fbsde_problem* pb, int64_t P, size_t* bytes);
+int fbsde_solve_sigma(const fbsde_problem* pb, const double* sigma, int64_t P, const double* x0, double* u,
+                      double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
+                      fbsde_stream stream);
+
 /* Human-readable text of a return code. */
 const char* fbsde_strerror(int code);
 

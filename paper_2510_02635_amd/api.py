@@ -572,6 +572,33 @@ def solve_coef(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, want_grad=True, ws=None
     return u, grad, st
 
 
+def sigma_workspace_size(pb, P):
+    out = ctypes.c_size_t(0)
+    N.check(N.load().fbsde_sigma_workspace_size(ctypes.byref(pb.c()), P, ctypes.byref(out)))
+    return int(out.value)
+
+
+def solve_sigma(pb, x0, sigma, want_grad=True, ws=None, return_iters=False):
+    """Scheme R (as solve) under the constant diffusion matrix sigma [d][d] (FP64 device tensor):
+    u [P], grad [P][d] (or None), status [P] (and CG iterations per level)."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    _dev_f64(sigma, (pb.d, pb.d))
+    dev = x0.device
+    u = torch.empty(P, dtype=torch.float64, device=dev)
+    grad = torch.empty((P, pb.d), dtype=torch.float64, device=dev) if want_grad else None
+    st = torch.empty(P, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = torch.empty(max(sigma_workspace_size(pb, P), 1), dtype=torch.uint8, device=dev)
+    iters = (ctypes.c_int32 * pb.N)() if return_iters else None
+    N.check(N.load().fbsde_solve_sigma(ctypes.byref(pb.c()), sigma.data_ptr(), P, x0.data_ptr(), u.data_ptr(),
+                                       _ptr(grad), st.data_ptr(), ws.data_ptr(), ws.numel(),
+                                       ctypes.cast(iters, ctypes.c_void_p) if return_iters else None, _stream()))
+    if return_iters:
+        return u, grad, st, list(iters)
+    return u, grad, st
+
+
 def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zstats=False, ws=None, mu1=0.0,
                             sigma1=0.0):
     """Paper-literal per-anchor scheme under the affine diagonal coefficients mu(x) = mu0 x + mu1,

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libfbsde.so")
-SOURCES = ["fbsde_api.hip", "fbsde_shared_api.hip", "fbsde_batched_api.hip", "fbsde_literal.hip"]
+SOURCES = ["fbsde_api.hip", "fbsde_shared_api.hip", "fbsde_batched_api.hip", "fbsde_literal.hip", "fbsde_sigma.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for every HIP translation unit: the kernels are

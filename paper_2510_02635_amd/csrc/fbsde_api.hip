@@ -112,6 +112,8 @@ struct WS {
     const double* coefV = nullptr;
     const double* coefA = nullptr;
     const double* coefB = nullptr;
+    // a step after the forward sweep that rewrites the terminal values (constant matrix sigma)
+    const host::TerminalStep* terminal = nullptr;
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
     int* tag;
@@ -431,6 +433,7 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
     launch_forward<S>(pb, pl, P, x0, W, ldw, Ycur, ws.rn2, status, st, &ws);
     int err = last_error();
     if (err) return err;
+    if (ws.terminal && (err = (*ws.terminal)(W, ldw, Ycur, st))) return err;
     for (int k = (int)pl.N - 1; k >= 0; --k) {
         double* w_k = tape ? ws.tw + (size_t)k * PM : ws.w;
         double* Wbar_k = tape ? ws.tWbar + (size_t)k * PL : ws.Wbar;
@@ -790,6 +793,38 @@ int coef_r_check(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, fbs
     return FBSDE_OK;
 }
 
+}  // namespace
+
+namespace fbsde {
+namespace host {
+size_t per_point_workspace_bytes(const fbsde_problem* pb, int64_t P) {
+    Plan pl;
+    if (check_problem(pb, P) != FBSDE_OK || make_plan(pb, P, pl) != FBSDE_OK) return 0;
+    WS ws;
+    return carve(pl, P, 0, nullptr, ws);
+}
+
+int solve_per_point_terminal(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                             uint32_t* status, void* wsp, size_t ws_bytes, int32_t* cg_iters_out, hipStream_t st,
+                             const TerminalStep& terminal) {
+    int rc = check_problem(pb, P);
+    if (rc) return rc;
+    if (pb->shared_dw) return FBSDE_EINVAL;
+    Plan pl;
+    if ((rc = make_plan(pb, P, pl))) return rc;
+    if (P == 0) return FBSDE_OK;
+    if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
+    WS ws;
+    if (carve(pl, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, 0, (char*)wsp, ws);
+    ws.terminal = &terminal;
+    if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
+    return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
+}
+}  // namespace host
+}  // namespace fbsde
+
+namespace {
 // the table V[p][k], k = 0..N, after the per-point workspace
 size_t coef_r_table_bytes(const Plan& pl, int64_t P) { return (size_t)round_up(P * (pl.N + 1) * 8, 256); }
 }  // namespace

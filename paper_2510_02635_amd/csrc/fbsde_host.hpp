@@ -195,6 +195,14 @@ int solve_backward_after_forward(const fbsde_problem* pb, int64_t P, const doubl
                                  double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, void* ws,
                                  size_t ws_bytes, hipStream_t st);
 void set_int(int* a, int v, hipStream_t st);
+// The per-point solve (fbsde_solve, no tape) with a step run after the forward sweep that may rewrite the
+// terminal values Y [P][M] from the state W [P][M][ldw] (a constant diffusion matrix enters here);
+// per_point_workspace_bytes is its workspace.
+using TerminalStep = std::function<int(const void* W, int64_t ldw, double* Y, hipStream_t)>;
+size_t per_point_workspace_bytes(const fbsde_problem* pb, int64_t P);
+int solve_per_point_terminal(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
+                             uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out, hipStream_t st,
+                             const TerminalStep& terminal);
 
 }  // namespace host
 }  // namespace fbsde

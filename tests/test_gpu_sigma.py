@@ -1,0 +1,168 @@
+"""GPU parity of scheme R under a constant diffusion matrix sigma (Sec. 2.1's problem class, Z = sigma^T grad u)
+against the FP64 oracle, which regresses in X-space with the covariance-metric kernel and the ridge on
+sigma^T alpha_x, on identical seeded inputs.
+
+The library runs the per-point path in the coordinates W = sigma^{-1} (X - x0 - mu t); sigma enters the terminal
+values (a GEMM per point chunk) and grad u (a solve through sigma sigma^T).  Covered: non-symmetric sigma with
+a drift; Allen-Cahn, HJB (Z in f) and Burgers with a logistic g; FP64 (1e-10) and FP32C (1e-5); full-rank,
+rank-deficient and two-wave designs; d = 1000, M = 4096 on a sampled point; several point chunks; the scalar
+reduction to fbsde_solve; the affine closed form; a singular sigma flagged in status; refusals.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2510_02635_amd as F  # noqa: E402
+from oracle import scheme as OS  # noqa: E402
+
+from _convert import problems, rel_err  # noqa: E402
+
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F._native.load()
+
+
+def _sigma(d, seed, s=1.2):
+    rng = np.random.default_rng(seed)
+    return s * (np.eye(d) + 0.25 * rng.normal(size=(d, d)) / np.sqrt(d))
+
+
+FAM = {"ac": (F.F_ALLEN_CAHN, (1.0, 1.0, 0, 0), F.G_AC), "hjb": (F.F_HJB, (0.7, 0, 0, 0), F.G_HJB_LOG),
+       "burgers": (F.F_BURGERS, (0.2, 1.5, 0, 0), F.G_LOGISTIC)}
+
+CASES = [
+    # (d, M, N, T, P, prec, f, tol)
+    (20, 384, 4, 0.3, 3, F.F64, "ac", 1e-10),        # full rank, warm-started CG
+    (60, 40, 3, 0.3, 2, F.F64, "hjb", 1e-10),        # rank-deficient (dual) design, Z in f
+    (2000, 256, 2, 0.05, 2, F.F64, "burgers", 1e-10),  # a two-wave team per row, logistic g
+    (20, 512, 4, 0.3, 3, F.F32C, "ac", 1e-5),        # FP32 state and GEMM, FP64 Newton
+    (40, 300, 3, 0.3, 2, F.F32C, "hjb", 1e-5),
+]
+
+
+def _setup(d, M, N, T, prec, fam, seed=4, instance=5, **kw):
+    fk, fp, gk = FAM[fam]
+    rng = np.random.default_rng(d + M)
+    gvec = rng.normal(size=d) / np.sqrt(d) if gk == F.G_LOGISTIC else None
+    mu = 0.3 * np.sin(np.arange(d))
+    return problems(d=d, M=M, N=N, T=T, prec=prec, f_kind=fk, fp=fp, g_kind=gk, gp=(0.4, 0, 0, 0), gvec=gvec,
+                    mu=mu, seed=seed, instance=instance, **kw)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"d{c[0]}_M{c[1]}_{c[6]}_{'f64' if c[5] == F.F64 else 'f32c'}"
+                                             for c in CASES])
+def test_sigma_against_oracle(case):
+    d, M, N, T, P, prec, fam, tol = case
+    hp, op = _setup(d, M, N, T, prec, fam)
+    sig = _sigma(d, d)
+    x0 = np.random.default_rng(M).uniform(-0.5, 0.5, size=(P, d)) / np.sqrt(d / 20.0)
+    _say(f"[sigma] d={d} M={M} N={N} T={T} P={P} prec={prec} f={fam}")
+    u, g, st, it = F.solve_sigma(hp, torch.tensor(x0, device=DEV), torch.tensor(sig, device=DEV), return_iters=True)
+    torch.cuda.synchronize()
+    u, g, st = u.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+    _say(f"  cg iterations per level {it}")
+    for p in range(P):
+        ref = OS.solve_point_matrix_sigma(op, x0[p], p, sig)
+        eu = abs(u[p] - ref["u"]) / abs(ref["u"])
+        eg = rel_err(g[p], ref["grad"])
+        _say(f"  p={p} u={u[p]:.12g} ref={ref['u']:.12g} rel_u={eu:.2e} rel_grad={eg:.2e}")
+        assert st[p] == 0 and ref["status"] == 0
+        assert eu <= tol and eg <= tol
+
+
+def test_sigma_d1000_M4096_sampled_points():
+    # the Allen-Cahn shape d = 1000, M = 4096 (FP32C), 40 points: several chunks of sigma W_N rows (32 points
+    # per 512 MiB chunk); the oracle takes the first and the last point
+    d, M, N, T, P = 1000, 4096, 3, 0.3, 40
+    hp, op = _setup(d, M, N, T, F.F32C, "ac", seed=8, instance=1)
+    sig = _sigma(d, 3, s=1.0)
+    x0 = np.random.default_rng(3).uniform(-0.03, 0.03, size=(P, d))
+    _say(f"[sigma full] d={d} M={M} N={N} P={P}")
+    u, g, st = F.solve_sigma(hp, torch.tensor(x0, device=DEV), torch.tensor(sig, device=DEV))
+    torch.cuda.synchronize()
+    for p in (0, P - 1):
+        ref = OS.solve_point_matrix_sigma(op, x0[p], p, sig)
+        eu = abs(u[p].item() - ref["u"]) / abs(ref["u"])
+        eg = rel_err(g[p].cpu().numpy(), ref["grad"])
+        _say(f"  p={p} u={u[p].item():.12g} ref={ref['u']:.12g} rel_u={eu:.2e} rel_grad={eg:.2e}")
+        assert eu <= 1e-5 and eg <= 1e-5
+    assert not st.cpu().numpy().any()
+
+
+@pytest.mark.parametrize("fam", ["ac", "hjb"])
+@pytest.mark.parametrize("prec,tol", [(F.F64, 1e-11), (F.F32C, 1e-5)], ids=["f64", "f32c"])
+def test_scalar_sigma_reduces_to_solve(fam, prec, tol):
+    d, M, N, T, P, s = 24, 256, 3, 0.3, 3, 1.3
+    hp, _ = _setup(d, M, N, T, prec, fam, s=s, seed=3, instance=2)
+    hq, _ = _setup(d, M, N, T, prec, fam, s=7.0, seed=3, instance=2)
+    x0 = torch.tensor(np.random.default_rng(7).uniform(-0.5, 0.5, size=(P, d)), device=DEV)
+    _say(f"[sigma scalar] f={fam} prec={prec}")
+    u0, g0, s0 = F.solve(hp, x0)
+    u1, g1, s1 = F.solve_sigma(hq, x0, torch.eye(d, dtype=torch.float64, device=DEV) * s)
+    torch.cuda.synchronize()
+    assert rel_err(u1.cpu().numpy(), u0.cpu().numpy()) <= tol
+    assert rel_err(g1.cpu().numpy(), g0.cpu().numpy()) <= 10 * tol
+    assert not s0.any() and not s1.any()
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, 1e-11), (F.F32C, 1e-5)], ids=["f64", "f32c"])
+def test_affine_closed_form(prec, tol):
+    # f = 0, g affine and no ridge: u = gvec . (x0 + mu T) + b and grad u = gvec for any invertible sigma
+    d, M, N, T, P = 12, 200, 4, 0.6, 3
+    rng = np.random.default_rng(2)
+    gvec = rng.normal(size=d)
+    mu = rng.normal(size=d) * 0.3
+    hp, _ = problems(d=d, M=M, N=N, T=T, prec=prec, mu=mu, g_kind=F.G_AFFINE, gp=(0.3, 0, 0, 0), gvec=gvec,
+                     ridge_rel=0.0, eps_h=1.0, seed=11, instance=0)
+    sig = _sigma(d, 5)
+    x0 = rng.uniform(-1, 1, size=(P, d))
+    _say(f"[sigma affine] prec={prec}")
+    u, g, st = F.solve_sigma(hp, torch.tensor(x0, device=DEV), torch.tensor(sig, device=DEV))
+    torch.cuda.synchronize()
+    u, g = u.cpu().numpy(), g.cpu().numpy()
+    for p in range(P):
+        exact = float(gvec @ (x0[p] + mu * T)) + 0.3
+        assert abs(u[p] - exact) <= tol * max(abs(exact), 1.0)
+        assert rel_err(g[p], gvec) <= tol
+    assert not st.cpu().numpy().any()
+
+
+def test_singular_sigma_flagged_and_refusals():
+    d, M, N, T = 16, 64, 2, 0.2
+    hp, _ = _setup(d, M, N, T, F.F64, "ac")
+    x0 = torch.zeros((2, d), dtype=torch.float64, device=DEV)
+    sig = torch.eye(d, dtype=torch.float64, device=DEV)
+    sig[3] = 0.0   # sigma sigma^T has a zero pivot
+    _say("[sigma singular]")
+    u, g, st = F.solve_sigma(hp, x0, sig)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() & 4).all()
+    good = torch.eye(d, dtype=torch.float64, device=DEV)
+    hs, _ = _setup(d, M, N, T, F.F64, "ac", shared_dw=1)
+    with pytest.raises(F.FbsdeError):
+        F.solve_sigma(hs, x0, good)
+    hj, _ = problems(d=d, M=M, N=N, T=T, f_kind=F.F_HJ_SINK, fp=(0.1, 0, 0, 0), g_kind=F.G_HJ_GAUSS,
+                     gp=(T, 0, 0, 0))
+    with pytest.raises(F.FbsdeError):
+        F.solve_sigma(hj, x0, good)
+    lib = F._native.load()
+    assert lib.fbsde_solve_sigma(ctypes.byref(hp.c()), None, 2, x0.data_ptr(), x0.data_ptr(), None, x0.data_ptr(),
+                                 x0.data_ptr(), 1 << 20, None, None) != 0
+    u, g, st = F.solve_sigma(hp, torch.empty((0, d), dtype=torch.float64, device=DEV), good)
+    assert u.numel() == 0

@@ -170,7 +170,9 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     ws.ncnt = std::max(1, cg_tree_counters(pl.nchunk));
     ws.cnt = (int*)take((size_t)P * ws.ncnt * 4);
     ws.nq = (int)std::min<int64_t>(CG_MAXQ, std::max<int64_t>(P, 1));
-    ws.qcap = (P + ws.nq - 1) / ws.nq * (int64_t)pl.nchunk;
+    // a slot for every item the level can produce (its points x chunks x iterations): no slot is reused
+    // within a launch, so a producer never waits for a taker
+    ws.qcap = (P + ws.nq - 1) / ws.nq * (int64_t)pl.nchunk * (int64_t)pl.maxit;
     ws.queue = (unsigned long long*)take((size_t)ws.nq * ws.qcap * 8);
     return off;
 }

@@ -21,14 +21,18 @@
 // of blocks polling a few queues, the failed swaps of the losers delayed the winners (measured: 8 points
 // at d = 5000, M = 4800 went 721 -> 369 ms per solve).  The loop is over when no point iterates any more:
 // then no item can come (a point enqueues only while it iterates, and a point that iterates holds the
-// count of iterating points above zero).  A queue is a bounded ring of (its points) x nchunk slots, each
-// with a sequence number (the classic bounded multi-producer multi-consumer ring): slot j mod cap is free
-// for index j when its number is j, filled when it is j + 1, and the taker frees it for j + cap.  A point
-// has at most nchunk items outstanding, so a producer that finds its slot not yet free waits only for the
-// holder of the earlier index, a running block.  The waits that could only end by another block's action
-// are bounded in wall-clock time (counted from the last time any queue counter moved): past the bound
-// the loop winds down and the points still iterating are flagged FBSDE_ST_WAIT_LIMIT (an internal error,
-// never expected).
+// count of iterating points above zero).  A queue holds a slot for every item the level can produce,
+// (its points) x nchunk x (the iteration cap), each with a sequence number: slot j is free for index j when
+// its number is j and filled when it is j + 1.  No slot is reused within a launch, and that is what keeps
+// the loop free of deadlock: with a ring of (its points) x nchunk slots a producer had to wait until the
+// index one lap earlier was taken, and that index could be the ticket of the producer itself (a block
+// that took a stolen item while holding a ticket on the same queue, then completed that item's point) or
+// of a block waiting, in turn, on this producer's own held ticket; both stalled until the wait bound
+// (seen with 64 points of 6 chunks each, two points per queue).  Now a producer writes at once, and a
+// block waits only for an item that a running producer is writing.  The waits are still bounded in
+// wall-clock time (counted from the last time any queue counter moved): past the bound the loop winds
+// down and the points still iterating are flagged FBSDE_ST_WAIT_LIMIT (an internal error, never
+// expected).
 //
 // Coherence: the L2 caches of the XCDs are not coherent with each other within a kernel.  The data that
 // blocks hand to one another inside the loop (chunk partials, the CG vectors and scalars of a point, the
@@ -284,8 +288,8 @@ __device__ __forceinline__ void cg_root_update(int p, int it, const double* __re
         else sh_base = atomicAdd(&ctl->q[qi][1], (unsigned long long)nchunk);
     }
     if (!done) {
-        // the point's chunks of the next iteration, after its new state is published: each slot once the
-        // taker of its previous index has freed it
+        // the point's chunks of the next iteration, after its new state is published (each slot is fresh:
+        // the wait below ends at once unless the queue were too small, which the wait bound reports)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         const unsigned long long b = sh_base;

@@ -21,6 +21,7 @@ struct Plan {
     int64_t d, M, N;
     int ld, Q, TEAM, BS, TPW, nchunk, rows_per_chunk;
     size_t esz;
+    int maxit;   // CG iterations per point and level at most (sizes the device loop's work queues)
 };
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -77,6 +78,7 @@ inline bool shape_plan(Plan& pl, int team, int nchunk) {
 
 inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
+    pl.maxit = std::max(1, (int)pb->cg_maxit);
     pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;
     pl.ld = (int)round_up(pb->d, (pl.esz == 8) ? 16 : 32);
     const int groups = pl.ld / 4;

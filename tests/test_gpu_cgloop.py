@@ -162,3 +162,40 @@ def test_graph_capture_with_default_cg_settings():
         torch.zeros(1024, device=DEV).sum().item()   # eager work between replays
     ref = OS.solve_point(op, x0[0], 0)
     assert abs(u0[0].item() - ref["u"]) <= 1e-10 * abs(ref["u"])
+
+
+@pytest.mark.parametrize("fam", ["ac", "hj"])
+def test_many_points_few_chunks_no_wait_limit(fam):
+    # 64 points of 6 chunks each (d = 500, M = 100, FP64): two points per work queue, twelve items per
+    # queue and as many blocks.  With queues that reused their slots every lap, a block that held a ticket
+    # and completed a stolen item's point could wait for its own ticket's slot until the wait bound (the
+    # level then took 2 s and its points were flagged).  The HJ-type case also has right-hand sides of
+    # 1e-150 to 1e-180 at the late levels (its terminal value is a d = 500 Gaussian), whose squared norms
+    # leave the normal range unless the CG solves for a power-of-two-scaled right-hand side: without the
+    # scaling one level ran to the iteration cap and the points went non-finite.  Every level must end at
+    # once with every point converged and equal to the oracle.
+    d, M, N, T, P = 500, 100, 10, 0.5, 64
+    if fam == "hj":
+        kw = dict(f_kind=F.F_HJ_SINK, fp=(0.1, 0, 0, 0), g_kind=F.G_HJ_GAUSS, gp=(0.5, 0, 0, 0))
+    else:
+        kw = dict(AC)
+    hp, op = problems(d=d, M=M, N=N, T=T, seed=0, instance=9, **kw)
+    x0 = np.zeros((P, d)) if fam == "hj" else workloads.points("normal:0.05", P, d, seed=3)
+    xt = torch.tensor(x0, device=DEV)
+    ws = F.workspace(hp, P)
+    _say(f"[cgloop many points] f={fam} d={d} M={M} N={N} P={P}")
+    F.solve(hp, xt, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, g, st, it = F.solve(hp, xt, ws=ws, return_iters=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    _say(f"  {sec * 1e3:.1f} ms, iterations per level {it}")
+    assert not st.cpu().numpy().any()
+    assert max(it) < hp.cg_maxit
+    assert sec < 1.0
+    u, g = u.cpu().numpy(), g.cpu().numpy()
+    for p in (0, 17, 63):
+        ref = OS.solve_point(op, x0[p], p)
+        assert abs(u[p] - ref["u"]) <= 1e-10 * abs(ref["u"])
+        assert rel_err(g[p], ref["grad"]) <= 1e-10

@@ -247,18 +247,204 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
             }
 }
 
+// FP32 GEMM, pipelined form (the one the launcher picks for FP32): the same block and wave tiles as
+// k_gemm<float>, with
+//   * two LDS buffers: the next K tile goes from registers into the buffer nobody reads while the MFMAs
+//     consume the current one, so a K tile costs one barrier instead of two and no idle store phase;
+//   * operands k-contiguous in LDS (A rows and, for NT, B rows of BK + 4 floats: 16-byte aligned rows
+//     whose 8-lane groups of 128-bit accesses cover all 32 banks once), written with 128-bit stores;
+//   * a permuted contraction order: at step s of the tile the four k of the 4-deep MFMA are 8 g + s
+//     (g = lane / 16, the operand's k slot), the same permutation for both operands, so a lane's A
+//     (and NT B) fragments for the whole tile are 8 consecutive k of one row: two 128-bit LDS reads
+//     per 16-row tile instead of eight 32-bit ones.  NN B stays n-contiguous ([BK][BN + 4]) and is read
+//     32 bits at a time.
+// FOLD as in k_gemm: FP32 partial sums of 256 terms added into FP64 running sums.
+template <bool NT, typename Epi, bool FOLD>
+__global__ void __launch_bounds__(256)
+k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+            int64_t ldb, Epi epi, int lower_only) {
+    constexpr int BM = 128, BN = 128, BK = 32, SA = BK + 4, SBN = BN + 4;
+    constexpr int BSZ = NT ? BN * SA : BK * SBN;
+    using vec4 = GemmCfg<float>::vec4;
+    __shared__ __attribute__((aligned(16))) float As[2][BM * SA];
+    __shared__ __attribute__((aligned(16))) float Bs[2][BSZ];
+    const int bm = blockIdx.y, bn = blockIdx.x;
+    if (lower_only && bn * BN > bm * BM + BM - 1) return;   // tile entirely above the diagonal
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = bm * BM, n0 = bn * BN;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool avec = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    const bool bvec = (ldb % 4 == 0) && (((uintptr_t)B & 15) == 0);
+    float ra[4][4], rb[4][4];
+    // a K tile into registers: A (and NT B) as 32 rows x 8 groups of four k per pass, NN B as 8 k rows x
+    // 32 groups of four n per pass; 128-bit loads where the group is in bounds and aligned
+    auto load_tile = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+            const int gm = m0 + row, gk = k0 + 4 * kq;
+            if (avec && gm < Md && gk + 3 < Kd) {
+                gload4(A + (int64_t)gm * lda + gk, ra[v]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ra[v][e] = (gm < Md && gk + e < Kd) ? A[(int64_t)gm * lda + gk + e] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if constexpr (NT) {
+                const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+                const int gn = n0 + row, gk = k0 + 4 * kq;
+                if (bvec && gn < Nd && gk + 3 < Kd) {
+                    gload4(B + (int64_t)gn * ldb + gk, rb[v]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rb[v][e] = (gn < Nd && gk + e < Kd) ? B[(int64_t)gn * ldb + gk + e] : 0.0f;
+                }
+            } else {
+                const int krow = (tid >> 5) + 8 * v, nq = tid & 31;
+                const int gk = k0 + krow, gn = n0 + 4 * nq;
+                if (bvec && gk < Kd && gn + 3 < Nd) {
+                    gload4(B + (int64_t)gk * ldb + gn, rb[v]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rb[v][e] = (gk < Kd && gn + e < Nd) ? B[(int64_t)gk * ldb + gn + e] : 0.0f;
+                }
+            }
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+            *reinterpret_cast<float4*>(&As[buf][row * SA + 4 * kq]) = make_float4(ra[v][0], ra[v][1], ra[v][2], ra[v][3]);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if constexpr (NT) {
+                const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+                *reinterpret_cast<float4*>(&Bs[buf][row * SA + 4 * kq]) =
+                    make_float4(rb[v][0], rb[v][1], rb[v][2], rb[v][3]);
+            } else {
+                const int krow = (tid >> 5) + 8 * v, nq = tid & 31;
+                *reinterpret_cast<float4*>(&Bs[buf][krow * SBN + 4 * nq]) =
+                    make_float4(rb[v][0], rb[v][1], rb[v][2], rb[v][3]);
+            }
+        }
+    };
+
+    vec4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0f;
+    double fsum[FOLD ? 4 : 1][FOLD ? 4 : 1][4];
+    if constexpr (FOLD) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) fsum[i][j][r] = 0.0;
+    }
+    const int nk = (Kd + BK - 1) / BK;
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_tile((kt + 1) * BK);
+        // the tile's fragments: a[i][s] = A(row of tile i, k = 8 lk + s), b[j][s] likewise
+        // in two halves (s = 0..3, then 4..7): the first half's reads are all issued before the second
+        // half's, so the first MFMAs wait only for them
+        float a[4][8], b[4][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 x = *reinterpret_cast<const float4*>(&As[buf][(wm * 64 + 16 * i + li) * SA + 8 * lk + 4 * h]);
+                a[i][4 * h + 0] = x.x; a[i][4 * h + 1] = x.y; a[i][4 * h + 2] = x.z; a[i][4 * h + 3] = x.w;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (NT) {
+                    const float4 y = *reinterpret_cast<const float4*>(&Bs[buf][(wn * 64 + 16 * j + li) * SA + 8 * lk + 4 * h]);
+                    b[j][4 * h + 0] = y.x; b[j][4 * h + 1] = y.y; b[j][4 * h + 2] = y.z; b[j][4 * h + 3] = y.w;
+                } else {
+#pragma unroll
+                    for (int s = 4 * h; s < 4 * h + 4; ++s) b[j][s] = Bs[buf][(8 * lk + s) * SBN + wn * 64 + 16 * j + li];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        // the next tile into the other buffer (read by nobody since the barrier that ended tile kt - 1),
+        // between the two halves of the MFMAs
+        if (kt + 1 < nk) store_tile(buf ^ 1);
+#pragma unroll
+        for (int s = 4; s < 8; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        if constexpr (FOLD) {
+            if ((kt & 7) == 7 || kt + 1 == nk) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            fsum[i][j][r] += (double)acc[i][j][r];
+                            acc[i][j][r] = 0.0f;
+                        }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * 64 + 16 * i + 4 * lk + r;
+                const int n = n0 + wn * 64 + 16 * j + li;
+                double val;
+                if constexpr (FOLD) val = fsum[i][j][r];
+                else val = (double)acc[i][j][r];
+                if (m < Md && n < Nd) epi(m, n, val);
+            }
+}
+
 template <typename T, bool NT, typename Epi>
 inline void gemm(int Md, int Nd, int Kd, const T* A, int64_t lda, const T* B, int64_t ldb, const Epi& epi,
                  hipStream_t st, int lower_only = 0) {
     using Cfg = GemmCfg<T>;
     if (Md <= 0 || Nd <= 0) return;
     const dim3 grid((Nd + Cfg::BN - 1) / Cfg::BN, (Md + Cfg::BM - 1) / Cfg::BM);
-    if (std::is_same<T, float>::value && Kd > 1024)
-        hipLaunchKernelGGL((k_gemm<T, NT, Epi, true>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
-                           lower_only);
-    else
+    if constexpr (std::is_same<T, float>::value) {
+        if (Kd > 1024)
+            hipLaunchKernelGGL((k_gemm_f32p<NT, Epi, true>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
+                               lower_only);
+        else
+            hipLaunchKernelGGL((k_gemm_f32p<NT, Epi, false>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
+                               lower_only);
+    } else {
         hipLaunchKernelGGL((k_gemm<T, NT, Epi, false>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
                            lower_only);
+    }
 }
 
 // ------------------------------------------------------------------ blocked Cholesky

@@ -249,8 +249,9 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
 
 // FP32 GEMM, pipelined form (the one the launcher picks for FP32): the same block and wave tiles as
 // k_gemm<float>, with
-//   * two LDS buffers: the next K tile goes from registers into the buffer nobody reads while the MFMAs
-//     consume the current one, so a K tile costs one barrier instead of two and no idle store phase;
+//   * two LDS buffers and a prefetch distance of two tiles: tile kt + 2 is loaded into registers while
+//     the MFMAs consume tile kt, and written at the start of tile kt + 1 into the buffer tile kt read, so
+//     a K tile costs one barrier and the loads have a whole tile to arrive;
 //   * operands k-contiguous in LDS (A rows and, for NT, B rows of BK + 4 floats: 16-byte aligned rows
 //     whose 8-lane groups of 128-bit accesses cover all 32 banks once), written with 128-bit stores;
 //   * a permuted contraction order: at step s of the tile the four k of the 4-deep MFMA are 8 g + s
@@ -352,13 +353,18 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
 #pragma unroll
                 for (int r = 0; r < 4; ++r) fsum[i][j][r] = 0.0;
     }
+    // Tile kt + 1 is loaded into registers during tile kt - 1 and written to LDS at the start of tile kt,
+    // into the buffer tile kt - 1 read (free since the barrier that ended it): the loads have a whole
+    // tile's MFMAs to arrive in.
     const int nk = (Kd + BK - 1) / BK;
     load_tile(0);
     store_tile(0);
+    if (nk > 1) load_tile(BK);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) load_tile((kt + 1) * BK);
+        if (kt + 1 < nk) store_tile(buf ^ 1);
+        if (kt + 2 < nk) load_tile((kt + 2) * BK);
         // the tile's fragments: a[i][s] = A(row of tile i, k = 8 lk + s), b[j][s] likewise
         // in two halves (s = 0..3, then 4..7): the first half's reads are all issued before the second
         // half's, so the first MFMAs wait only for them
@@ -388,9 +394,6 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
-        // the next tile into the other buffer (read by nobody since the barrier that ended tile kt - 1),
-        // between the two halves of the MFMAs
-        if (kt + 1 < nk) store_tile(buf ^ 1);
 #pragma unroll
         for (int s = 4; s < 8; ++s)
 #pragma unroll

@@ -588,7 +588,7 @@ def main():
                               "status_nonzero_points": int((st_sa != 0).sum().item())},
                   "dtype": "fp32c (FP32 MFMA, FP64 Newton)",
                   "config": {"workload": "shared_allen_cahn_d10000_P4096_M2048_N20", "shared_increments": True},
-                  "roofline": {"bound": "mfma", "kernel": "k_gemm<float, NT> [P x ld] x [M x ld]^T",
+                  "roofline": {"bound": "mfma", "kernel": "k_gemm_f32p<NT, FP64-folded> [P x ld] x [M x ld]^T",
                                "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
                                "frac": round(tflops / 157.3, 4), "avg_launch_ms": round(gemm_ms, 4),
                                "flops_per_launch": 2 * Ps * Ms * ldp},

@@ -490,13 +490,23 @@ int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P,
  * chunk) and grad u = sigma^{-T} Z / F' (solved through sigma sigma^T, blocked Cholesky).
  * pb->s is not used; shared_dw, f kinds that read x and the Case 2 terminal value are refused
  * (FBSDE_EINVAL).  A sigma singular to working precision marks every point's status ST_NONFINITE
- * (grad NULL: not detected).  Workspace fbsde_sigma_workspace_size bytes (the per-point workspace plus
- * at most 512 MiB of sigma W_N rows and the d x d factor); u [P], grad [P][d] or NULL, status [P],
- * cg_iters_out as fbsde_solve, on stream. */
-int fbsde_sigma_workspace_size(const fbsde_problem* pb, int64_t P, size_t* bytes);
+ * (grad NULL: not detected).  Workspace fbsde_sigma_workspace_size(pb, P, flags) bytes (the per-point
+ * workspace plus at most 512 MiB of sigma W_N rows, the d x d factor and, with FBSDE_WS_TAPE, the
+ * tape and P x M doubles for the reverse mode); flags 0 or FBSDE_WS_TAPE as fbsde_solve; u [P], grad [P][d]
+ * or NULL, status [P], cg_iters_out as fbsde_solve, on stream.
+ * fbsde_solve_sigma_backward: the reverse mode of L = sum_p u_bar[p] u_p (as fbsde_solve_backward, same
+ * outputs and tape contract) after fbsde_solve_sigma with FBSDE_WS_TAPE on the same workspace and sigma.
+ * x0 enters only through the terminal values, so x0_bar = sum_j G_j grad g(X^j_N) with G the adjoint of
+ * the terminal values: the argument of g is formed again from sigma W_N (GEMM), and the W-column sums of
+ * the radial terms are mapped to X by sigma (one more GEMM). */
+int fbsde_sigma_workspace_size(const fbsde_problem* pb, int64_t P, int32_t flags, size_t* bytes);
 int fbsde_solve_sigma(const fbsde_problem* pb, const double* sigma, int64_t P, const double* x0, double* u,
-                      double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
-                      fbsde_stream stream);
+                      double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t flags,
+                      int32_t* cg_iters_out, fbsde_stream stream);
+int fbsde_solve_sigma_backward(const fbsde_problem* pb, const double* sigma, int64_t P, const double* x0,
+                               const double* u_bar, double* x0_bar, double* gp_bar, double* fp_bar,
+                               uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
+                               fbsde_stream stream);
 
 /* Human-readable text of a return code. */
 const char* fbsde_strerror(int code);

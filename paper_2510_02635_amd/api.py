@@ -572,15 +572,16 @@ def solve_coef(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, want_grad=True, ws=None
     return u, grad, st
 
 
-def sigma_workspace_size(pb, P):
+def sigma_workspace_size(pb, P, tape=False):
     out = ctypes.c_size_t(0)
-    N.check(N.load().fbsde_sigma_workspace_size(ctypes.byref(pb.c()), P, ctypes.byref(out)))
+    N.check(N.load().fbsde_sigma_workspace_size(ctypes.byref(pb.c()), P, N.WS_TAPE if tape else 0, ctypes.byref(out)))
     return int(out.value)
 
 
-def solve_sigma(pb, x0, sigma, want_grad=True, ws=None, return_iters=False):
+def solve_sigma(pb, x0, sigma, want_grad=True, ws=None, return_iters=False, tape=False):
     """Scheme R (as solve) under the constant diffusion matrix sigma [d][d] (FP64 device tensor):
-    u [P], grad [P][d] (or None), status [P] (and CG iterations per level)."""
+    u [P], grad [P][d] (or None), status [P] (and CG iterations per level).  tape=True keeps what
+    solve_sigma_backward needs in ws."""
     P = x0.shape[0]
     _dev_f64(x0, (P, pb.d))
     _dev_f64(sigma, (pb.d, pb.d))
@@ -589,14 +590,34 @@ def solve_sigma(pb, x0, sigma, want_grad=True, ws=None, return_iters=False):
     grad = torch.empty((P, pb.d), dtype=torch.float64, device=dev) if want_grad else None
     st = torch.empty(P, dtype=torch.int32, device=dev)
     if ws is None:
-        ws = torch.empty(max(sigma_workspace_size(pb, P), 1), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(sigma_workspace_size(pb, P, tape), 1), dtype=torch.uint8, device=dev)
     iters = (ctypes.c_int32 * pb.N)() if return_iters else None
     N.check(N.load().fbsde_solve_sigma(ctypes.byref(pb.c()), sigma.data_ptr(), P, x0.data_ptr(), u.data_ptr(),
                                        _ptr(grad), st.data_ptr(), ws.data_ptr(), ws.numel(),
+                                       N.WS_TAPE if tape else 0,
                                        ctypes.cast(iters, ctypes.c_void_p) if return_iters else None, _stream()))
     if return_iters:
         return u, grad, st, list(iters)
     return u, grad, st
+
+
+def solve_sigma_backward(pb, x0, sigma, u_bar, ws):
+    """Reverse mode of solve_sigma for L = sum_p u_bar[p] u_p; ws from solve_sigma(..., tape=True).
+    Returns x0_bar [P][d], gp_bar [4], fp_bar [4], status [P]."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    _dev_f64(sigma, (pb.d, pb.d))
+    _dev_f64(u_bar, (P,))
+    dev = x0.device
+    x0_bar = torch.empty((P, pb.d), dtype=torch.float64, device=dev)
+    gp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
+    fp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
+    st = torch.zeros(P, dtype=torch.int32, device=dev)
+    N.check(N.load().fbsde_solve_sigma_backward(ctypes.byref(pb.c()), sigma.data_ptr(), P, x0.data_ptr(),
+                                                u_bar.data_ptr(), x0_bar.data_ptr(), gp_bar.data_ptr(),
+                                                fp_bar.data_ptr(), st.data_ptr(), ws.data_ptr(), ws.numel(), None,
+                                                _stream()))
+    return x0_bar, gp_bar, fp_bar, st
 
 
 def solve_literal_geometric(pb, x0, mu0, sigma0, k_stop=0, want_Y=False, want_zstats=False, ws=None, mu1=0.0,

@@ -291,13 +291,15 @@ k_adj_rowdot(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, in
 
 // Terminal adjoint on W_N: for radial g = h(|X|^2), grad g(X) = 2 h'(|X|^2) X with X = xc + s W
 // (xc = x0 + mu T): accumulate sum_j G_j 2h'_j W_j (columns) and, per block, sum_j G_j 2h'_j,
-// sum_j G_j dg/dgp0, sum_j G_j dg/dgp1, sum_j G_j.
+// sum_j G_j dg/dgp0, sum_j G_j dg/dgp1, sum_j G_j.  qpre: the argument of g per particle ([P][M], |X|^2 or
+// gvec . X) formed by the caller (a constant diffusion matrix, X = xc + sigma W); the columns stay sums
+// over W.
 template <typename S, int Q, int TEAM>
 __global__ void __launch_bounds__((Geo<Q, TEAM>::BS))
 k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int nchunk, int d, int ld,
                const double* __restrict__ x0, const double* __restrict__ mu, const double* __restrict__ gvec,
                double s, double T, int g_kind, double ga, const double* __restrict__ G, double* __restrict__ part,
-               double* __restrict__ psc) {
+               double* __restrict__ psc, const double* __restrict__ qpre = nullptr) {
     using Gm = Geo<Q, TEAM>;
     using R = S;
     __shared__ double lds[(Gm::TPW > 1) ? Gm::TPW * 4 * Q * Gm::TL : 1];
@@ -341,6 +343,7 @@ k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, 
         }
         double unused = 0.0;
         team_sum2<TEAM>(qsum, unused, red, team);
+        if (qpre && valid) qsum = qpre[(int64_t)p * M + j];
         if (valid) {
             const double gj = G[(int64_t)p * M + j];
             double hp = 0.0, d0 = 0.0, d1 = 0.0;
@@ -348,6 +351,11 @@ k_adj_terminal(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, 
             else if (g_kind == G_AC) { const double den = 2.0 + ga * qsum; hp = -ga / (den * den); d0 = -qsum / (den * den); }
             else if (g_kind == G_HJB_LOG) { const double den = 1.0 + ga * qsum; hp = ga / den; d0 = qsum / den; }
             else if (g_kind == G_LOGISTIC) { const double gv = 1.0 / (1.0 + exp(-(qsum + ga))); d0 = gv * (1.0 - gv); }
+            else if (g_kind == G_HJ_GAUSS) {   // g = (1 + 4a)^(-d/2) e^(-q / (1 + 4a))
+                const double a4 = 1.0 + 4.0 * ga, gv = g_of(G_HJ_GAUSS, ga, 0.0, qsum, d);
+                hp = -gv / a4;
+                d0 = gv * (-2.0 * (double)d / a4 + 4.0 * qsum / (a4 * a4));
+            }
             else { d0 = 1.0; }
             const double phi = 2.0 * hp * gj;
             s1 += phi; g0 += gj * d0; g1 += gj * d1; sg += gj;

@@ -114,6 +114,7 @@ struct WS {
     const double* coefB = nullptr;
     // a step after the forward sweep that rewrites the terminal values (constant matrix sigma)
     const host::TerminalStep* terminal = nullptr;
+    const host::AdjTerminalHooks* adjh = nullptr;   // the same for the reverse mode
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
     int* tag;
@@ -540,15 +541,18 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     hipLaunchKernelGGL(k_adj_newton, dim3((unsigned)P), dim3(256), 0, st, ws.G, ws.tw + (size_t)(pl.N - 1) * PM,
                        (int64_t)pl.M, ws.psc, pl.nchunk, nullptr, ws.tscal, NS, fs, dt, pb->newton_iters, (int)pl.M, u_bar, ws.cbar,
                        ws.adj, 0, 1, status);
+    if (ws.adjh && (err = ws.adjh->before(W, ldw, st))) return err;
     dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
         constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
         hipLaunchKernelGGL((k_adj_terminal<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st, W,
                            ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, (int)pl.d, pl.ld, x0, pb->mu, pb->gvec, pb->s,
-                           pb->T, pb->g_kind, pb->gp[0], ws.G, ws.part1, ws.psc);
+                           pb->T, pb->g_kind, pb->gp[0], ws.G, ws.part1, ws.psc, ws.adjh ? ws.adjh->qpre : nullptr);
     });
     const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+    // with the caller's terminal stage the W-column term is added by its `after` step (s = 0 leaves it out)
     hipLaunchKernelGGL(k_adj_x0bar, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, (int)pl.d,
-                       pl.ld, x0, pb->mu, pb->gvec, pb->s, pb->T, pb->g_kind, ws.adj, x0_bar);
+                       pl.ld, x0, pb->mu, pb->gvec, ws.adjh ? 0.0 : pb->s, pb->T, pb->g_kind, ws.adj, x0_bar);
+    if (ws.adjh && (err = ws.adjh->after(ws.part1, pl.nchunk, vc, pl.ld, x0_bar, st))) return err;
     hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(64), 0, st, ws.adj, P, gp_bar, fp_bar);
     // the tape is consumed: the state no longer holds W_1 of the primal pass
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, 0);
@@ -799,16 +803,16 @@ int coef_r_check(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, fbs
 
 namespace fbsde {
 namespace host {
-size_t per_point_workspace_bytes(const fbsde_problem* pb, int64_t P) {
+size_t per_point_workspace_bytes(const fbsde_problem* pb, int64_t P, int32_t flags) {
     Plan pl;
     if (check_problem(pb, P) != FBSDE_OK || make_plan(pb, P, pl) != FBSDE_OK) return 0;
     WS ws;
-    return carve(pl, P, 0, nullptr, ws);
+    return carve(pl, P, flags, nullptr, ws);
 }
 
 int solve_per_point_terminal(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
-                             uint32_t* status, void* wsp, size_t ws_bytes, int32_t* cg_iters_out, hipStream_t st,
-                             const TerminalStep& terminal) {
+                             uint32_t* status, void* wsp, size_t ws_bytes, int32_t flags, int32_t* cg_iters_out,
+                             hipStream_t st, const TerminalStep& terminal) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
     if (pb->shared_dw) return FBSDE_EINVAL;
@@ -817,12 +821,14 @@ int solve_per_point_terminal(const fbsde_problem* pb, int64_t P, const double* x
     if (P == 0) return FBSDE_OK;
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     WS ws;
-    if (carve(pl, P, 0, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
-    carve(pl, P, 0, (char*)wsp, ws);
+    if (carve(pl, P, flags, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, flags, (char*)wsp, ws);
     ws.terminal = &terminal;
-    if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
-    return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
+    const bool tape = (flags & FBSDE_WS_TAPE) != 0;
+    if (pb->prec == FBSDE_F64) return solve_impl<double>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
+    return solve_impl<float>(pb, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
 }
+
 }  // namespace host
 }  // namespace fbsde
 
@@ -888,7 +894,8 @@ namespace {
 // whose tape does not belong to this problem.
 int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar, double* x0_bar,
                    double* gp_bar, double* fp_bar, uint32_t* status, void* wsp, size_t ws_bytes,
-                   int32_t* cg_iters_out, fbsde_stream stream, bool check_tape) {
+                   int32_t* cg_iters_out, fbsde_stream stream, bool check_tape,
+                   const host::AdjTerminalHooks* hooks = nullptr) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
     if (per_point_forward_only(pb)) return FBSDE_EINVAL;   // the reverse mode covers neither family
@@ -911,6 +918,7 @@ int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const d
     WS ws;
     if (carve(pl, P, FBSDE_WS_TAPE, nullptr, ws) > ws_bytes) return FBSDE_ENOSPC;
     carve(pl, P, FBSDE_WS_TAPE, (char*)wsp, ws);
+    ws.adjh = hooks;
     hipStream_t st = (hipStream_t)stream;
     if (check_tape) {
         int tag = 0;
@@ -927,6 +935,15 @@ int backward_entry(const fbsde_problem* pb, int64_t P, const double* x0, const d
 
 namespace fbsde {
 namespace host {
+int solve_per_point_backward_terminal(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar,
+                                      double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, void* ws,
+                                      size_t ws_bytes, int32_t* cg_iters_out, hipStream_t st,
+                                      const AdjTerminalHooks& hooks) {
+    if (pb->shared_dw) return FBSDE_EINVAL;
+    return backward_entry(pb, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, ws_bytes, cg_iters_out,
+                          (fbsde_stream)st, true, &hooks);
+}
+
 int solve_tile(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad, uint32_t* status,
                void* wsp, size_t ws_bytes, int32_t flags, bool reset_counts, hipStream_t st) {
     if (pb->shared_dw || P == 0)

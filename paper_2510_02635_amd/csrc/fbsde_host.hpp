@@ -201,10 +201,23 @@ void set_int(int* a, int v, hipStream_t st);
 // terminal values Y [P][M] from the state W [P][M][ldw] (a constant diffusion matrix enters here);
 // per_point_workspace_bytes is its workspace.
 using TerminalStep = std::function<int(const void* W, int64_t ldw, double* Y, hipStream_t)>;
-size_t per_point_workspace_bytes(const fbsde_problem* pb, int64_t P);
+size_t per_point_workspace_bytes(const fbsde_problem* pb, int64_t P, int32_t flags);
 int solve_per_point_terminal(const fbsde_problem* pb, int64_t P, const double* x0, double* u, double* grad,
-                             uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out, hipStream_t st,
-                             const TerminalStep& terminal);
+                             uint32_t* status, void* ws, size_t ws_bytes, int32_t flags, int32_t* cg_iters_out,
+                             hipStream_t st, const TerminalStep& terminal);
+// The reverse mode of that solve with the terminal stage changed the same way: `before` fills qpre [P][M]
+// (the argument of g per particle) from the state W_N, the terminal adjoint then reads it, its x0 adjoint is
+// formed without the W-column term, and `after` adds that term from the W-column sums (part, summed over
+// its first vchunks chunk slots of ld) to x0_bar.
+struct AdjTerminalHooks {
+    std::function<int(const void* W, int64_t ldw, hipStream_t)> before;
+    double* qpre;
+    std::function<int(const double* part, int nchunk, int vchunks, int ld, double* x0_bar, hipStream_t)> after;
+};
+int solve_per_point_backward_terminal(const fbsde_problem* pb, int64_t P, const double* x0, const double* u_bar,
+                                      double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, void* ws,
+                                      size_t ws_bytes, int32_t* cg_iters_out, hipStream_t st,
+                                      const AdjTerminalHooks& hooks);
 
 }  // namespace host
 }  // namespace fbsde

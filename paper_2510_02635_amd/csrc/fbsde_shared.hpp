@@ -338,6 +338,11 @@ k_sha_terminal(const double* __restrict__ G, const double* __restrict__ qt, int 
             const double q = qt[(int64_t)p * M + j];
             if (g_kind == G_QUAD) { hp = ga / (double)d; d0 = q / (double)d; d1 = 1.0; }
             else if (g_kind == G_AC) { const double den = 2.0 + ga * q; hp = -ga / (den * den); d0 = -q / (den * den); }
+            else if (g_kind == G_HJ_GAUSS) {   // g = (1 + 4a)^(-d/2) e^(-q / (1 + 4a))
+                const double a4 = 1.0 + 4.0 * ga, gv = g_of(G_HJ_GAUSS, ga, 0.0, q, d);
+                hp = -gv / a4;
+                d0 = gv * (-2.0 * (double)d / a4 + 4.0 * q / (a4 * a4));
+            }
             else { const double den = 1.0 + ga * q; hp = ga / den; d0 = q / den; }
         }
         const double ph = 2.0 * hp * gj;

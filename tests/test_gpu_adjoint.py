@@ -48,6 +48,8 @@ ADJ_CASES = [
     ("burgers_logistic_d50", dict(d=50, M=300, N=3, T=0.5, f_kind=F.F_BURGERS, fp=(2 ** 0.5 / 50, 25.5, 0, 0),
                                   g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0), gvec=np.linspace(-1.0, 2.0, 50) / 50),
      "normal:0.5", 3),
+    ("ac_hjgauss_d40", dict(d=40, M=200, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0),
+                            g_kind=F.G_HJ_GAUSS, gp=(0.3, 0, 0, 0)), "normal:0.3", 2),
     ("burgers_logistic_d400_M120", dict(d=400, M=120, N=2, T=0.5, f_kind=F.F_BURGERS,
                                         fp=(2 ** 0.5 / 400, 200.5, 0, 0), g_kind=F.G_LOGISTIC, gp=(0.5, 0, 0, 0),
                                         gvec=np.ones(400) / 400), "normal:0.5", 2),

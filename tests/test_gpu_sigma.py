@@ -6,7 +6,9 @@ The library runs the per-point path in the coordinates W = sigma^{-1} (X - x0 - 
 values (a GEMM per point chunk) and grad u (a solve through sigma sigma^T).  Covered: non-symmetric sigma with
 a drift; Allen-Cahn, HJB (Z in f) and Burgers with a logistic g; FP64 (1e-10) and FP32C (1e-5); full-rank,
 rank-deficient and two-wave designs; d = 1000, M = 4096 on a sampled point; several point chunks; the scalar
-reduction to fbsde_solve; the affine closed form; a singular sigma flagged in status; refusals.
+reduction to fbsde_solve; the affine closed form; a singular sigma flagged in status; refusals.  The reverse mode
+(fbsde_solve_sigma_backward): the scalar reduction to fbsde_solve_backward, central differences of the GPU forward
+in x0 and in the terminal parameter, FP32C against FP64, and a workspace without the tape refused.
 """
 import ctypes
 import sys
@@ -163,6 +165,93 @@ def test_singular_sigma_flagged_and_refusals():
         F.solve_sigma(hj, x0, good)
     lib = F._native.load()
     assert lib.fbsde_solve_sigma(ctypes.byref(hp.c()), None, 2, x0.data_ptr(), x0.data_ptr(), None, x0.data_ptr(),
-                                 x0.data_ptr(), 1 << 20, None, None) != 0
+                                 x0.data_ptr(), 1 << 20, 0, None, None) != 0
     u, g, st = F.solve_sigma(hp, torch.empty((0, d), dtype=torch.float64, device=DEV), good)
     assert u.numel() == 0
+
+
+# ---------------------------------------------------------------- reverse mode
+def _sigma_adjoint(hp, x0, sig, ubar):
+    P = x0.shape[0]
+    ws = torch.empty(F.sigma_workspace_size(hp, P, tape=True), dtype=torch.uint8, device=DEV)
+    F.solve_sigma(hp, x0, sig, tape=True, ws=ws)
+    return F.solve_sigma_backward(hp, x0, sig, ubar, ws)
+
+
+@pytest.mark.parametrize("fam", ["ac", "hjb", "burgers"])
+def test_sigma_adjoint_scalar_reduces_to_solve_backward(fam):
+    d, M, N, T, P, s = 24, 256, 3, 0.3, 3, 1.3
+    hp, _ = _setup(d, M, N, T, F.F64, fam, s=s, seed=3, instance=2)
+    hq, _ = _setup(d, M, N, T, F.F64, fam, s=7.0, seed=3, instance=2)
+    x0 = torch.tensor(np.random.default_rng(7).uniform(-0.5, 0.5, size=(P, d)), device=DEV)
+    ubar = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device=DEV)
+    _say(f"[sigma adjoint scalar] f={fam}")
+    ws = F.workspace(hp, P, tape=True)
+    F.solve(hp, x0, tape=True, ws=ws)
+    xb0, gb0, fb0, s0 = F.solve_backward(hp, x0, ubar, ws)
+    xb1, gb1, fb1, s1 = _sigma_adjoint(hq, x0, torch.eye(d, dtype=torch.float64, device=DEV) * s, ubar)
+    torch.cuda.synchronize()
+    assert rel_err(xb1.cpu().numpy(), xb0.cpu().numpy()) <= 1e-10
+    assert rel_err(gb1.cpu().numpy(), gb0.cpu().numpy()) <= 1e-10
+    assert rel_err(fb1.cpu().numpy(), fb0.cpu().numpy()) <= 1e-10
+    assert not s0.any() and not s1.any()
+
+
+@pytest.mark.parametrize("fam", ["ac", "hjb", "burgers"])
+def test_sigma_adjoint_against_central_differences(fam):
+    # L(x0, gp) = sum_p ubar_p u_p: the adjoint's x0_bar . e and gp_bar[0] against central differences of
+    # the GPU forward (FP64, common random numbers), at a non-symmetric sigma with a drift
+    d, M, N, T, P = 16, 200, 3, 0.3, 2
+    hp, _ = _setup(d, M, N, T, F.F64, fam, seed=5, instance=1)
+    sig = torch.tensor(_sigma(d, 11), device=DEV)
+    rng = np.random.default_rng(13)
+    x0n = rng.uniform(-0.4, 0.4, size=(P, d))
+    e = rng.normal(size=(P, d))
+    ubar_n = np.array([1.0, 0.7])
+    x0 = torch.tensor(x0n, device=DEV)
+    ubar = torch.tensor(ubar_n, device=DEV)
+    _say(f"[sigma adjoint fd] f={fam}")
+    xb, gb, fb, st = _sigma_adjoint(hp, x0, sig, ubar)
+    torch.cuda.synchronize()
+    assert not st.any()
+
+    def L(xn, hpp):
+        u, _, s_ = F.solve_sigma(hpp, torch.tensor(xn, device=DEV), sig, want_grad=False)
+        torch.cuda.synchronize()
+        assert not s_.any()
+        return float(ubar_n @ u.cpu().numpy())
+
+    h = 1e-4
+    fd = (L(x0n + h * e, hp) - L(x0n - h * e, hp)) / (2 * h)
+    ad = float(np.sum(xb.cpu().numpy() * e))
+    _say(f"  x0: adjoint {ad:.10g} fd {fd:.10g}")
+    assert abs(ad - fd) <= 1e-6 * max(abs(fd), 1e-3)
+    gp = list(hp.gp)
+    hg = 1e-5
+    hpp, _ = _setup(d, M, N, T, F.F64, fam, seed=5, instance=1)
+    hpm, _ = _setup(d, M, N, T, F.F64, fam, seed=5, instance=1)
+    hpp.gp = (gp[0] + hg,) + tuple(gp[1:])
+    hpm.gp = (gp[0] - hg,) + tuple(gp[1:])
+    fdg = (L(x0n, hpp) - L(x0n, hpm)) / (2 * hg)
+    _say(f"  gp0: adjoint {gb[0].item():.10g} fd {fdg:.10g}")
+    assert abs(gb[0].item() - fdg) <= 1e-6 * max(abs(fdg), 1e-3)
+
+
+def test_sigma_adjoint_fp32c_and_refusal():
+    d, M, N, T, P = 40, 300, 3, 0.3, 2
+    h64, _ = _setup(d, M, N, T, F.F64, "hjb")
+    h32, _ = _setup(d, M, N, T, F.F32C, "hjb")
+    sig = torch.tensor(_sigma(d, 2), device=DEV)
+    x0 = torch.tensor(np.random.default_rng(1).uniform(-0.5, 0.5, size=(P, d)), device=DEV)
+    ubar = torch.ones(P, dtype=torch.float64, device=DEV)
+    _say("[sigma adjoint fp32c]")
+    xb64, gb64, _, _ = _sigma_adjoint(h64, x0, sig, ubar)
+    xb32, gb32, _, st = _sigma_adjoint(h32, x0, sig, ubar)
+    torch.cuda.synchronize()
+    assert not st.any()
+    assert rel_err(xb32.cpu().numpy(), xb64.cpu().numpy()) <= 1e-5
+    assert rel_err(gb32.cpu().numpy(), gb64.cpu().numpy()) <= 1e-5
+    # a workspace without the tape of a preceding solve is refused
+    ws = torch.zeros(F.sigma_workspace_size(h64, P, tape=True), dtype=torch.uint8, device=DEV)
+    with pytest.raises(F.FbsdeError):
+        F.solve_sigma_backward(h64, x0, sig, ubar, ws)

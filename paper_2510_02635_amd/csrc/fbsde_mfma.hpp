@@ -260,30 +260,33 @@ k_gemm(int Md, int Nd, int Kd, const T* __restrict__ A, int64_t lda, const T* __
 //     per 16-row tile instead of eight 32-bit ones.  NN B stays n-contiguous ([BK][BN + 4]) and is read
 //     32 bits at a time.
 // FOLD as in k_gemm: FP32 partial sums of 256 terms added into FP64 running sums.
-template <bool NT, typename Epi, bool FOLD>
-__global__ void __launch_bounds__(256)
+template <bool NT, typename Epi, bool FOLD, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
             int64_t ldb, Epi epi, int lower_only) {
     constexpr int BM = 128, BN = 128, BK = 32, SA = BK + 4, SBN = BN + 4;
     constexpr int BSZ = NT ? BN * SA : BK * SBN;
+    // NW waves: 2 along m (64 rows each) x NW / 2 along n (WNT columns each, TN 16-column MFMA tiles)
+    constexpr int WGN = NW / 2, WNT = BN / WGN, TN = WNT / 16;
+    constexpr int LV = 16 / NW;   // 128-bit loads per thread and operand per K tile
     using vec4 = GemmCfg<float>::vec4;
     __shared__ __attribute__((aligned(16))) float As[2][BM * SA];
     __shared__ __attribute__((aligned(16))) float Bs[2][BSZ];
     const int bm = blockIdx.y, bn = blockIdx.x;
     if (lower_only && bn * BN > bm * BM + BM - 1) return;   // tile entirely above the diagonal
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     const int m0 = bm * BM, n0 = bn * BN;
     const int li = lane & 15, lk = lane >> 4;
     const bool avec = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0);
     const bool bvec = (ldb % 4 == 0) && (((uintptr_t)B & 15) == 0);
-    float ra[4][4], rb[4][4];
+    float ra[LV][4], rb[LV][4];
     // a K tile into registers: A (and NT B) as 32 rows x 8 groups of four k per pass, NN B as 8 k rows x
     // 32 groups of four n per pass; 128-bit loads where the group is in bounds and aligned
     auto load_tile = [&](int k0) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+        for (int v = 0; v < LV; ++v) {
+            const int row = (tid >> 3) + 8 * NW * v, kq = tid & 7;
             const int gm = m0 + row, gk = k0 + 4 * kq;
             if (avec && gm < Md && gk + 3 < Kd) {
                 gload4(A + (int64_t)gm * lda + gk, ra[v]);
@@ -293,9 +296,9 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
             }
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < LV; ++v) {
             if constexpr (NT) {
-                const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+                const int row = (tid >> 3) + 8 * NW * v, kq = tid & 7;
                 const int gn = n0 + row, gk = k0 + 4 * kq;
                 if (bvec && gn < Nd && gk + 3 < Kd) {
                     gload4(B + (int64_t)gn * ldb + gk, rb[v]);
@@ -305,7 +308,7 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
                         rb[v][e] = (gn < Nd && gk + e < Kd) ? B[(int64_t)gn * ldb + gk + e] : 0.0f;
                 }
             } else {
-                const int krow = (tid >> 5) + 8 * v, nq = tid & 31;
+                const int krow = (tid >> 5) + 2 * NW * v, nq = tid & 31;
                 const int gk = k0 + krow, gn = n0 + 4 * nq;
                 if (bvec && gk < Kd && gn + 3 < Nd) {
                     gload4(B + (int64_t)gk * ldb + gn, rb[v]);
@@ -319,37 +322,37 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
     };
     auto store_tile = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+        for (int v = 0; v < LV; ++v) {
+            const int row = (tid >> 3) + 8 * NW * v, kq = tid & 7;
             *reinterpret_cast<float4*>(&As[buf][row * SA + 4 * kq]) = make_float4(ra[v][0], ra[v][1], ra[v][2], ra[v][3]);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < LV; ++v) {
             if constexpr (NT) {
-                const int row = (tid >> 3) + 32 * v, kq = tid & 7;
+                const int row = (tid >> 3) + 8 * NW * v, kq = tid & 7;
                 *reinterpret_cast<float4*>(&Bs[buf][row * SA + 4 * kq]) =
                     make_float4(rb[v][0], rb[v][1], rb[v][2], rb[v][3]);
             } else {
-                const int krow = (tid >> 5) + 8 * v, nq = tid & 31;
+                const int krow = (tid >> 5) + 2 * NW * v, nq = tid & 31;
                 *reinterpret_cast<float4*>(&Bs[buf][krow * SBN + 4 * nq]) =
                     make_float4(rb[v][0], rb[v][1], rb[v][2], rb[v][3]);
             }
         }
     };
 
-    vec4 acc[4][4];
+    vec4 acc[4][TN];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0f;
-    double fsum[FOLD ? 4 : 1][FOLD ? 4 : 1][4];
+    double fsum[FOLD ? 4 : 1][FOLD ? TN : 1][4];
     if constexpr (FOLD) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) fsum[i][j][r] = 0.0;
     }
@@ -368,7 +371,7 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
         // the tile's fragments: a[i][s] = A(row of tile i, k = 8 lk + s), b[j][s] likewise
         // in two halves (s = 0..3, then 4..7): the first half's reads are all issued before the second
         // half's, so the first MFMAs wait only for them
-        float a[4][8], b[4][8];
+        float a[4][8], b[TN][8];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -377,13 +380,13 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
                 a[i][4 * h + 0] = x.x; a[i][4 * h + 1] = x.y; a[i][4 * h + 2] = x.z; a[i][4 * h + 3] = x.w;
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < TN; ++j) {
                 if constexpr (NT) {
-                    const float4 y = *reinterpret_cast<const float4*>(&Bs[buf][(wn * 64 + 16 * j + li) * SA + 8 * lk + 4 * h]);
+                    const float4 y = *reinterpret_cast<const float4*>(&Bs[buf][(wn * WNT + 16 * j + li) * SA + 8 * lk + 4 * h]);
                     b[j][4 * h + 0] = y.x; b[j][4 * h + 1] = y.y; b[j][4 * h + 2] = y.z; b[j][4 * h + 3] = y.w;
                 } else {
 #pragma unroll
-                    for (int s = 4 * h; s < 4 * h + 4; ++s) b[j][s] = Bs[buf][(8 * lk + s) * SBN + wn * 64 + 16 * j + li];
+                    for (int s = 4 * h; s < 4 * h + 4; ++s) b[j][s] = Bs[buf][(8 * lk + s) * SBN + wn * WNT + 16 * j + li];
                 }
             }
         }
@@ -392,21 +395,21 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
 #pragma unroll
         for (int s = 4; s < 8; ++s)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
         if constexpr (FOLD) {
             if ((kt & 7) == 7 || kt + 1 == nk) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < TN; ++j)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             fsum[i][j][r] += (double)acc[i][j][r];
@@ -419,11 +422,11 @@ k_gemm_f32p(int Md, int Nd, int Kd, const float* __restrict__ A, int64_t lda, co
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm * 64 + 16 * i + 4 * lk + r;
-                const int n = n0 + wn * 64 + 16 * j + li;
+                const int n = n0 + wn * WNT + 16 * j + li;
                 double val;
                 if constexpr (FOLD) val = fsum[i][j][r];
                 else val = (double)acc[i][j][r];
@@ -438,12 +441,14 @@ inline void gemm(int Md, int Nd, int Kd, const T* A, int64_t lda, const T* B, in
     if (Md <= 0 || Nd <= 0) return;
     const dim3 grid((Nd + Cfg::BN - 1) / Cfg::BN, (Md + Cfg::BM - 1) / Cfg::BM);
     if constexpr (std::is_same<T, float>::value) {
+        // the FP64-folded form keeps 64 x 32 wave tiles (8 waves): half the FP64 running sums per lane, so
+        // two waves share each SIMD
         if (Kd > 1024)
-            hipLaunchKernelGGL((k_gemm_f32p<NT, Epi, true>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
+            hipLaunchKernelGGL((k_gemm_f32p<NT, Epi, true, 8>), grid, dim3(512), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
                                lower_only);
         else
-            hipLaunchKernelGGL((k_gemm_f32p<NT, Epi, false>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
-                               lower_only);
+            hipLaunchKernelGGL((k_gemm_f32p<NT, Epi, false, 4>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb,
+                               epi, lower_only);
     } else {
         hipLaunchKernelGGL((k_gemm<T, NT, Epi, false>), grid, dim3(256), 0, st, Md, Nd, Kd, A, lda, B, ldb, epi,
                            lower_only);

@@ -470,37 +470,66 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 }
 
 // Factor the CB x CB diagonal block at (kb, kb) in place (lower; upper part of the block zeroed).
-// One wavefront: lane i owns row i in registers; the column being eliminated is read from its owner
-// lanes with readlane (no LDS, no barriers).
+// 256 threads: thread t holds 16 entries of row t / 4 (columns 16 (t % 4) ..) in registers.  Per column j
+// the owners of column j publish it unscaled, A[.][j], in LDS (two buffers, alternating), one barrier,
+// and then every thread updates its entries right of the column with x -= A[r][j] A[c][j] / A[j][j]
+// (= L[r][j] L[c][j]) from same-address (broadcast) reads, while the owners scale their entry of the
+// column to L[r][j].  One barrier per column; the update is branch-free so that its reads are issued
+// together.  (One wavefront holding a whole row per lane and broadcasting the column with readlane
+// needed a scalar register per broadcast value; the compiler spilled about 3100 of them and a block
+// took 67 us.  With the pivot and the scaled column each behind a barrier and a branch per entry, 70 us;
+// this form, 40 us at n = 2048.)
 template <typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_potrf_diag(T* __restrict__ K, int64_t ldk, int n, int kb, int* __restrict__ info) {
+    static_assert(CB == 64, "four 16-column groups per row");
+    __shared__ double col[2][CB];
     const int o = kb * CB;
     const int nb = min(CB, n - o);
-    const int i = threadIdx.x;
-    double a[CB];
+    const int t = threadIdx.x, r = t >> 2, g = t & 3;
+    double x[16];
 #pragma unroll
-    for (int j = 0; j < CB; ++j)
-        a[j] = (i < nb && j < nb && j <= i) ? (double)K[(int64_t)(o + i) * ldk + o + j] : ((i == j) ? 1.0 : 0.0);
+    for (int e = 0; e < 16; ++e) {
+        const int c = 16 * g + e;
+        x[e] = (r < nb && c < nb && c <= r) ? (double)K[(int64_t)(o + r) * ldk + o + c] : ((r == c) ? 1.0 : 0.0);
+    }
     int bad = 0;
+    // the group loop is not unrolled (straight-line code for all 64 columns runs once and is fetched
+    // once); the 16 columns of a group are, so that x[ej] is a register
+#pragma unroll 1
+    for (int gj = 0; gj < 4; ++gj)
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-        double d = lane_bcast(a[j], j);
+    for (int ej = 0; ej < 16; ++ej) {
+        const int j = 16 * gj + ej;
+        double* cj = col[ej & 1];
+        if (g == gj) cj[r] = x[ej];   // A[r][j] (updated by the columns before j)
+        __syncthreads();
+        double d = cj[j];
         if (!(d > 0.0)) { bad |= (j < nb); d = 1.0; }
-        const double piv = sqrt(d);
-        if (i == j) a[j] = piv;
-        else if (i > j) a[j] /= piv;
+        const double inv = 1.0 / d;
+        const double arj = cj[r];
+        double cv[16];
 #pragma unroll
-        for (int c = j + 1; c < CB; ++c) {
-            const double lcj = lane_bcast(a[j], c);   // L[c][j]
-            if (i >= c) a[c] -= a[j] * lcj;
+        for (int e = 0; e < 16; ++e) cv[e] = cj[16 * g + e];
+        const double s = arj * inv;   // L[r][j] / L[j][j]
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int c = 16 * g + e;
+            const double upd = x[e] - s * cv[e];
+            x[e] = (c > j && c <= r) ? upd : x[e];
+        }
+        if (g == gj) {
+            const double piv = sqrt(d);
+            x[ej] = (r == j) ? piv : ((r > j) ? arj / piv : x[ej]);
         }
     }
-    if (bad && i == 0) atomicOr(info, 1);
-    if (i < nb)
+    if (bad && t == 0) atomicOr(info, 1);
+    if (r < nb)
 #pragma unroll
-        for (int j = 0; j < CB; ++j)
-            if (j < nb) K[(int64_t)(o + i) * ldk + o + j] = (T)((j <= i) ? a[j] : 0.0);
+        for (int e = 0; e < 16; ++e) {
+            const int c = 16 * g + e;
+            if (c < nb) K[(int64_t)(o + r) * ldk + o + c] = (T)((c <= r) ? x[e] : 0.0);
+        }
 }
 
 // Row-wise triangular solves with the CB x CB lower factor Lkk (row-major, ldl) for rows r of X
@@ -544,7 +573,7 @@ inline void cholesky(T* K, int64_t ldk, int n, int* info, hipStream_t st) {
     const int nb = (n + CB - 1) / CB;
     for (int kb = 0; kb < nb; ++kb) {
         const int o = kb * CB;
-        hipLaunchKernelGGL((k_potrf_diag<T>), dim3(1), dim3(64), 0, st, K, ldk, n, kb, info);
+        hipLaunchKernelGGL((k_potrf_diag<T>), dim3(1), dim3(256), 0, st, K, ldk, n, kb, info);
         const int rows = n - o - CB;
         if (rows <= 0) break;
         // panel: L[i][kb] solves L[i][kb] L_kk^T = A[i][kb]

@@ -541,10 +541,13 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_trsm_rows(const T* __restrict__ Lkk, int64_t ldl, int w, T* __restrict__ X, int64_t ldx, int rows, int c0, int upper) {
     __shared__ double L[CB][CB + 1];
+    __shared__ double inv[CB];   // 1 / L[c][c], so that the substitution chain multiplies
     for (int t = threadIdx.x; t < CB * CB; t += 256) {
         const int i = t / CB, j = t % CB;
         L[i][j] = (i < w && j < w) ? (double)Lkk[(int64_t)i * ldl + j] : ((i == j) ? 1.0 : 0.0);
     }
+    __syncthreads();
+    if (threadIdx.x < CB) inv[threadIdx.x] = 1.0 / L[threadIdx.x][threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int r = blockIdx.x * 4 + wave; r < rows; r += gridDim.x * 4) {
@@ -552,13 +555,13 @@ k_trsm_rows(const T* __restrict__ Lkk, int64_t ldl, int w, T* __restrict__ X, in
         double a = (lane < w) ? (double)row[lane] : 0.0;
         if (!upper) {
             for (int c = 0; c < CB; ++c) {
-                const double xc = lane_bcast(a, c) / L[c][c];
+                const double xc = lane_bcast(a, c) * inv[c];
                 if (lane == c) a = xc;
                 else if (lane > c) a -= xc * L[lane][c];
             }
         } else {
             for (int c = CB - 1; c >= 0; --c) {
-                const double xc = lane_bcast(a, c) / L[c][c];
+                const double xc = lane_bcast(a, c) * inv[c];
                 if (lane == c) a = xc;
                 else if (lane < c) a -= xc * L[c][lane];
             }
@@ -577,7 +580,7 @@ inline void cholesky(T* K, int64_t ldk, int n, int* info, hipStream_t st) {
         const int rows = n - o - CB;
         if (rows <= 0) break;
         // panel: L[i][kb] solves L[i][kb] L_kk^T = A[i][kb]
-        hipLaunchKernelGGL((k_trsm_rows<T>), dim3((unsigned)std::min((rows + 3) / 4, 4096)), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_trsm_rows<T>), dim3((unsigned)std::min((rows + 15) / 16, 1024)), dim3(256), 0, st,
                            K + (int64_t)o * ldk + o, ldk, CB, K + (int64_t)(o + CB) * ldk, ldk, rows, o, 0);
         // trailing update of the lower triangle: K[i][j] -= sum_c L[i][c] L[j][c]
         gemm<T, true>(rows, rows, CB, K + (int64_t)(o + CB) * ldk + o, ldk, K + (int64_t)(o + CB) * ldk + o, ldk,
@@ -591,7 +594,7 @@ inline void cholesky(T* K, int64_t ldk, int n, int* info, hipStream_t st) {
 template <typename T>
 inline void cholesky_solve_rows(const T* L, int64_t ldl, int n, T* R, int64_t ldr, int P, hipStream_t st) {
     const int nb = (n + CB - 1) / CB;
-    const unsigned rblocks = (unsigned)std::min((P + 3) / 4, 4096);
+    const unsigned rblocks = (unsigned)std::min((P + 15) / 16, 1024);   // four rows per wave
     // forward: Y L^T = R
     for (int kb = 0; kb < nb; ++kb) {
         const int o = kb * CB, w = std::min(CB, n - o);

@@ -83,11 +83,15 @@ def main():
         ws = F.workspace(pb, P)
         u, g, st = F.solve(pb, x0, ws=ws)
     torch.cuda.synchronize()
-    # the rows the CG products streamed (device count; x d x element bytes = their algorithmic read bytes)
-    rows = F.workspace_cg_rows(ws)
-    esz = 4 if args.prec == "fp32c" else 8
-    print(f"{args.workload} {args.prec}: u[0]={u[0].item():.12g} nonzero status={int((st != 0).sum())} "
-          f"cg rows streamed={rows} algorithmic CG bytes={rows * kw['d'] * esz}", flush=True)
+    head = f"{args.workload} {args.prec}: u[0]={u[0].item():.12g} nonzero status={int((st != 0).sum())}"
+    if kw.get("shared_dw"):
+        # the shared form solves its regressions directly (Cholesky): no CG products to count
+        print(head, flush=True)
+    else:
+        # the rows the CG products streamed (device count; x d x element bytes = their algorithmic read bytes)
+        rows = F.workspace_cg_rows(ws)
+        esz = 4 if args.prec == "fp32c" else 8
+        print(f"{head} cg rows streamed={rows} algorithmic CG bytes={rows * kw['d'] * esz}", flush=True)
 
 
 if __name__ == "__main__":

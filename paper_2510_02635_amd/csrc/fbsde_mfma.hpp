@@ -580,7 +580,7 @@ inline void cholesky(T* K, int64_t ldk, int n, int* info, hipStream_t st) {
         const int rows = n - o - CB;
         if (rows <= 0) break;
         // panel: L[i][kb] solves L[i][kb] L_kk^T = A[i][kb]
-        hipLaunchKernelGGL((k_trsm_rows<T>), dim3((unsigned)std::min((rows + 15) / 16, 1024)), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_trsm_rows<T>), dim3((unsigned)std::min((rows + 3) / 4, 4096)), dim3(256), 0, st,
                            K + (int64_t)o * ldk + o, ldk, CB, K + (int64_t)(o + CB) * ldk, ldk, rows, o, 0);
         // trailing update of the lower triangle: K[i][j] -= sum_c L[i][c] L[j][c]
         gemm<T, true>(rows, rows, CB, K + (int64_t)(o + CB) * ldk + o, ldk, K + (int64_t)(o + CB) * ldk + o, ldk,
@@ -594,7 +594,7 @@ inline void cholesky(T* K, int64_t ldk, int n, int* info, hipStream_t st) {
 template <typename T>
 inline void cholesky_solve_rows(const T* L, int64_t ldl, int n, T* R, int64_t ldr, int P, hipStream_t st) {
     const int nb = (n + CB - 1) / CB;
-    const unsigned rblocks = (unsigned)std::min((P + 15) / 16, 1024);   // four rows per wave
+    const unsigned rblocks = (unsigned)std::min((P + 3) / 4, 4096);
     // forward: Y L^T = R
     for (int kb = 0; kb < nb; ++kb) {
         const int o = kb * CB, w = std::min(CB, n - o);

@@ -130,8 +130,18 @@ typedef struct fbsde_problem {
     uint32_t instance;       /* PDE instance id, folded into the key                          */
     uint32_t point_base;     /* global index of this call's point 0 (Philox counter word 3)   */
     int32_t prec;            /* FBSDE_F64 or FBSDE_F32C                                       */
-    int32_t reserved;        /* must be 0                                                     */
+    int32_t solver;          /* FBSDE_SOLVER_AUTO or FBSDE_SOLVER_CG (below)                  */
 } fbsde_problem;
+
+/* The level's ridge solve in the per-point form (fbsde_solve and the entry points built on it):
+ * FBSDE_SOLVER_AUTO takes the direct dual solve where the design is rank-deficient and small
+ * (M <= d + 1, M <= FBSDE_DUAL_MAXM, ridge_rel > 0, cg_fixed_iters = 0): the M x M system
+ * (W^1/2 D' D'^T W^1/2 + lambda I) c = W^1/2 (Y - Ybar), alpha_x = D'^T W^1/2 c (the push-through
+ * identity of the normal equations, Sec. 2.4's system in its dual form), factored by Cholesky, with
+ * cg_iters_out 0 for those levels; every other level, and every level with FBSDE_SOLVER_CG, runs the
+ * matrix-free CG.  The reverse mode always runs CG. */
+enum { FBSDE_SOLVER_AUTO = 0, FBSDE_SOLVER_CG = 1 };
+#define FBSDE_DUAL_MAXM 128
 
 /* Row pitch (elements) of the particle state for this problem (d rounded up so that rows
  * start on 128-byte boundaries).  Returns 0 for an invalid descriptor. */

@@ -24,6 +24,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
 
 
 BATCH_TILED, BATCH_PERSISTENT = 0, 1
+SOLVER_AUTO, SOLVER_CG = 0, 1
 
 
 class CBatchOpts(ctypes.Structure):
@@ -58,7 +59,7 @@ class CProblem(ctypes.Structure):
         ("cg_fixed_iters", ctypes.c_int32), ("shared_dw", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("instance", ctypes.c_uint32), ("point_base", ctypes.c_uint32),
-        ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("prec", ctypes.c_int32), ("solver", ctypes.c_int32),
     ]
 
 

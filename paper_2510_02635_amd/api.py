@@ -38,6 +38,7 @@ class Problem:
     instance: int = 0
     point_base: int = 0
     prec: int = N.F64
+    solver: int = N.SOLVER_AUTO             # SOLVER_CG: the matrix-free CG on every level
 
     def c(self):
         cp = N.CProblem()
@@ -52,7 +53,7 @@ class Problem:
         cp.cg_rtol = self.cg_rtol if self.cg_rtol is not None else (1e-13 if self.prec == N.F64 else 1e-7)
         cp.cg_fixed_iters, cp.shared_dw = self.cg_fixed_iters, self.shared_dw
         cp.seed, cp.instance, cp.point_base = self.seed, self.instance, self.point_base
-        cp.prec, cp.reserved = self.prec, 0
+        cp.prec, cp.solver = self.prec, self.solver
         return cp
 
     @property

@@ -5,6 +5,7 @@
 #include "fbsde_kernels.hpp"
 #include "fbsde_adjoint.hpp"
 #include "fbsde_cgloop.hpp"
+#include "fbsde_dual.hpp"
 
 #include <atomic>
 #include <cstdlib>
@@ -100,6 +101,7 @@ struct WS {
     double *x, *r, *pv, *qv, *Wbar;
     double *part1, *part2, *part3, *psc, *scal;
     int *iscal, *active;
+    double *dK, *drhs;   // the direct dual solve's M x M systems and right-hand sides (plan.dual)
     int* cnt;       // CG arrival counters [P][ncnt]
     int ncnt;
     unsigned long long* queue;   // CG work queues [nq][qcap]
@@ -150,6 +152,11 @@ size_t carve(const Plan& pl, int64_t P, int flags, char* base, WS& ws) {
     ws.scal = (double*)take((size_t)P * NS * 8);
     ws.iscal = (int*)take((size_t)P * 4 * 4);
     ws.active = (int*)take(64);
+    ws.dK = ws.drhs = nullptr;
+    if (pl.dual) {
+        ws.dK = (double*)take((size_t)P * pl.M * pl.M * 8);
+        ws.drhs = (double*)take((size_t)P * pl.M * 8);
+    }
     ws.tY = ws.tw = ws.tax = ws.tWbar = ws.tscal = nullptr;
     ws.tag = nullptr;
     ws.G = ws.cbar = ws.adj = nullptr;
@@ -358,8 +365,17 @@ int run_level(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, const S
     hipLaunchKernelGGL(k_moments_finish, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, ws.part3, ws.psc,
                        pl.nchunk, vc, pl.ld, pb->s, lam, warm, Wbar_out, ws.x, ws.r, ws.pv, ws.scal, NS, ws.iscal,
                        ws.active, vt, vstride, pb->ridge_rel / (double)pl.d);
-    const int iters = r64 ? run_cg<S, double>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err)
-                          : run_cg<S, S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
+    int iters = 0;
+    if (pl.dual) {   // small rank-deficient cloud: the M x M dual system, factored
+        hipLaunchKernelGGL((k_dual_gram<S>), dim3((unsigned)P), dim3(256), 0, st, W, ldw, (int)pl.M, (int)pl.d, pl.ld,
+                           pb->s, Wbar_out, w_out, Y_next, ws.scal, NS, ws.dK, ws.drhs);
+        hipLaunchKernelGGL((k_dual_solve<S>), dim3((unsigned)P), dim3(256), 0, st, ws.dK, ws.drhs, (int)pl.M, W, ldw,
+                           (int)pl.d, pl.ld, pb->s, Wbar_out, w_out, ws.x, ws.iscal, status);
+        err = last_error();
+    } else {
+        iters = r64 ? run_cg<S, double>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err)
+                    : run_cg<S, S>(pb, pl, P, W, ldw, w_out, Wbar_out, ws, status, st, err);
+    }
     if (err) return iters;
     hipLaunchKernelGGL(k_level_finish, dim3((unsigned)P), dim3(256), 0, st, ws.x, Wbar_out, pl.ld, (int)pl.d, pb->s,
                        ws.scal, NS, alpha_out, alpha_x_out);

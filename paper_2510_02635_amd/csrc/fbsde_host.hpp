@@ -22,6 +22,7 @@ struct Plan {
     int ld, Q, TEAM, BS, TPW, nchunk, rows_per_chunk;
     size_t esz;
     int maxit;   // CG iterations per point and level at most (sizes the device loop's work queues)
+    bool dual;   // the forward levels use the direct dual solve (M x M Cholesky) instead of CG
 };
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -38,7 +39,7 @@ inline int check_problem(const fbsde_problem* pb, int64_t P) {
     if (pb->newton_iters < 1 || pb->cg_maxit < 1 || !(pb->cg_rtol >= 0.0)) return FBSDE_EINVAL;
     if (pb->prec != FBSDE_F64 && pb->prec != FBSDE_F32C) return FBSDE_EINVAL;
     if (pb->shared_dw != 0 && pb->shared_dw != 1) return FBSDE_EINVAL;
-    if (pb->reserved != 0) return FBSDE_EINVAL;
+    if (pb->solver != FBSDE_SOLVER_AUTO && pb->solver != FBSDE_SOLVER_CG) return FBSDE_EINVAL;
     // grid.y carries the point index
     if (pb->M > (int64_t)1 << 30 || pb->N > (int64_t)1 << 30 || P > 65535) return FBSDE_EINVAL;
     return FBSDE_OK;
@@ -79,6 +80,8 @@ inline bool shape_plan(Plan& pl, int team, int nchunk) {
 inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
     pl.d = pb->d; pl.M = pb->M; pl.N = pb->N;
     pl.maxit = std::max(1, (int)pb->cg_maxit);
+    pl.dual = pb->solver == FBSDE_SOLVER_AUTO && !pb->shared_dw && pb->M <= FBSDE_DUAL_MAXM &&
+              pb->M <= pb->d + 1 && pb->ridge_rel > 0.0 && pb->cg_fixed_iters == 0;
     pl.esz = (pb->prec == FBSDE_F64) ? 8 : 4;
     pl.ld = (int)round_up(pb->d, (pl.esz == 8) ? 16 : 32);
     const int groups = pl.ld / 4;

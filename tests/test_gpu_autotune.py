@@ -87,7 +87,7 @@ def test_kernel_timer_and_read_ceiling(prec):
 
 def test_launch_timer_records_every_cg_product(monkeypatch):
     hp, _ = problems(d=300, M=256, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
-                     gp=(0.4, 0, 0, 0))
+                     gp=(0.4, 0, 0, 0), solver=F.SOLVER_CG)
     xt = torch.tensor(workloads.points("normal:0.3", 4, 300, 2), device=DEV)
     ws = F.workspace(hp, 4)
     F.solve(hp, xt, ws=ws)

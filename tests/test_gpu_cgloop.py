@@ -179,7 +179,8 @@ def test_many_points_few_chunks_no_wait_limit(fam):
         kw = dict(f_kind=F.F_HJ_SINK, fp=(0.1, 0, 0, 0), g_kind=F.G_HJ_GAUSS, gp=(0.5, 0, 0, 0))
     else:
         kw = dict(AC)
-    hp, op = problems(d=d, M=M, N=N, T=T, seed=0, instance=9, **kw)
+    # the CG on every level (this cloud would otherwise take the direct dual solve)
+    hp, op = problems(d=d, M=M, N=N, T=T, seed=0, instance=9, solver=F.SOLVER_CG, **kw)
     x0 = np.zeros((P, d)) if fam == "hj" else workloads.points("normal:0.05", P, d, seed=3)
     xt = torch.tensor(x0, device=DEV)
     ws = F.workspace(hp, P)

@@ -38,6 +38,9 @@ CASES = [
                                   gp=(1.0, 0, 0, 0), prec=F.F32C, cg_fixed_iters=96), 4),
     ("shared_fp32c", dict(d=300, M=200, N=3, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1, 1, 0, 0), g_kind=F.G_AC,
                           gp=(0.4, 0, 0, 0), prec=F.F32C, shared_dw=1), 33),
+    # a small rank-deficient cloud: the direct dual solve on every level, captured
+    ("fp64_dual", dict(d=200, M=64, N=3, T=0.3, f_kind=F.F_HJB, fp=(0.8, 0, 0, 0), g_kind=F.G_HJB_LOG,
+                       gp=(1.0, 0, 0, 0)), 3),
 ]
 
 
@@ -58,8 +61,9 @@ def test_graph_replays_equal_eager(name, kw, P):
         _say(f"  replay {rep}: |du|={float((u - ue).abs().max()):.2e} |dgrad|={float((gr - ge).abs().max()):.2e}")
         assert torch.equal(u, ue) and torch.equal(gr, ge) and torch.equal(st, ste)
         assert int(st.abs().sum().item()) == 0
-        if not kw.get("shared_dw"):
-            kw_poll = dict(kw, cg_fixed_iters=0)
+        if kw.get("cg_fixed_iters"):
+            # the converging CG (stopping per point) gives the bits of the fixed launch count
+            kw_poll = dict(kw, cg_fixed_iters=0, solver=F.SOLVER_CG)
             up, gp_, _ = F.solve(F.Problem(**kw_poll), new.clone())
             torch.cuda.synchronize()
             assert torch.equal(u, up) and torch.equal(gr, gp_)

@@ -135,7 +135,7 @@ typedef struct fbsde_problem {
 
 /* The level's ridge solve in the per-point form (fbsde_solve and the entry points built on it):
  * FBSDE_SOLVER_AUTO takes the direct dual solve where the design is rank-deficient and small
- * (M <= d + 1, M <= FBSDE_DUAL_MAXM, ridge_rel > 0, cg_fixed_iters = 0): the M x M system
+ * (d / 8 <= M <= d + 1, M <= FBSDE_DUAL_MAXM, ridge_rel > 0, cg_fixed_iters = 0): the M x M system
  * (W^1/2 D' D'^T W^1/2 + lambda I) c = W^1/2 (Y - Ybar), alpha_x = D'^T W^1/2 c (the push-through
  * identity of the normal equations, Sec. 2.4's system in its dual form), factored by Cholesky, with
  * cg_iters_out 0 for those levels; every other level, and every level with FBSDE_SOLVER_CG, runs the

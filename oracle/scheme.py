@@ -557,9 +557,10 @@ def coef_moments(pb, x0, coef):
     return ms, Vs
 
 
-def solve_point_coef(pb, x0, p, coef):
+def solve_point_coef(pb, x0, p, coef, tape=False):
     """Scheme R (one regression per level, Algorithm 1's driver) under the affine diagonal coefficients.
-    pb.s and pb.mu are unused.  Returns dict(u, grad, status)."""
+    pb.s and pb.mu are unused.  Returns dict(u, grad, status) and, with tape=True, the path, the moments
+    and the per-level records used by the reverse mode."""
     if pb.f_kind in X_DEPENDENT_F:
         raise ValueError("x-dependent coefficients with an x-dependent source are not covered")
     mu0, sigma0, mu1, sigma1 = coef
@@ -569,6 +570,9 @@ def solve_point_coef(pb, x0, p, coef):
     ms, Vs = coef_moments(pb, x0, coef)
     Y, _, _ = g_eval(pb, X[pb.N])
     status = 0
+    levels = [None] * pb.N
+    Ys = [None] * (pb.N + 1)
+    Ys[pb.N] = Y
     for k in range(pb.N - 1, -1, -1):
         D = X[k + 1] - ms[k + 1][None, :]
         if pb.eps_h == 0.0:
@@ -585,12 +589,17 @@ def solve_point_coef(pb, x0, p, coef):
         alpha = Ybar - alpha_x @ Dbar
         C = alpha + (1.0 + mu0 * dt) * ((X[k] - ms[k][None, :]) @ alpha_x)
         Ynew = np.empty(pb.M)
+        Fps = np.empty(pb.M)
         for m in range(pb.M):
             Z = (sigma0 * X[k][m] + sigma1) * alpha_x
             y, Fp, st = newton(pb, k, C[m:m + 1], Z)
             Ynew[m] = y[0]
+            Fps[m] = Fp[0]
             status |= st
+        levels[k] = dict(D=D, w=w, Dbar=Dbar, Dc=Dc, Ybar=Ybar, Y_next=Y, alpha_x=alpha_x, alpha=alpha, sys=sysm,
+                         Fp=Fps)
         Y = Ynew
+        Ys[k] = Y
         if k == 0:
             Z0 = (sigma0 * x0 + sigma1) * alpha_x
             _, fy, fz, fz_scale, _ = f_eval(pb, 0.0, Y[:1], Z0)
@@ -599,7 +608,115 @@ def solve_point_coef(pb, x0, p, coef):
     u = float(Y.mean())
     if not (np.isfinite(u) and np.all(np.isfinite(grad))):
         status |= ST_NONFINITE
-    return dict(u=u, grad=grad, status=status)
+    out = dict(u=u, grad=grad, status=status)
+    if tape:
+        out.update(X=X, ms=ms, Vs=Vs, Y=Ys, levels=levels)
+    return out
+
+
+def coef_moment_tangents(pb, x0, coef):
+    """d m_k / d x0 (a scalar per level: the mean path is coordinate-wise affine in x0) and the vectors
+    d V_k / d x0 [d] of the moment recursion (coef_moments), k = 0..N."""
+    mu0, sigma0, mu1, sigma1 = coef
+    dt = pb.T / pb.N
+    a = 1.0 + mu0 * dt
+    ms, _ = coef_moments(pb, x0, coef)
+    dm = [a ** k for k in range(pb.N + 1)]
+    dv = np.zeros(pb.d)
+    dVs = [dv.copy()]
+    for k in range(pb.N):
+        # v_{k+1} = v_k a^2 + dt (sigma0^2 (v_k + m_k^2) + 2 sigma0 sigma1 m_k + sigma1^2), differentiated
+        dv = dv * (a * a + dt * sigma0 ** 2) + dt * (2.0 * sigma0 ** 2 * ms[k] + 2.0 * sigma0 * sigma1) * dm[k]
+        dVs.append(dv.copy())
+    return dm, dVs
+
+
+def adjoint_point_coef(pb, x0, p, coef, ubar=1.0):
+    """Reverse mode of solve_point_coef: d(ubar u)/d x0, d/d gp, d/d fp, under the affine diagonal coefficients.
+
+    Unlike the constant-coefficient scheme, the regression design D_j = X^j_{k+1} - m_{k+1}, the kernel weights
+    and the ridge (through V_{k+1}) all depend on x0.  x0 reaches them through three routes, each summed:
+    the particles (X^j_k is coordinate-wise affine in x0 with slope J^j_k = prod_i (1 + mu0 dt + sigma0
+    sqrt(dt) xi_i), the product over the steps so far), the mean path (slope (1 + mu0 dt)^k) and the
+    variance V_k (coef_moment_tangents).  Per level k, walked from k = 0 upwards, given G = Ybar_k:
+      Newton, per particle:   cbar_m = G_m / F'_m;  Zbar_m = dt cbar_m df/dz(Y_m, Z_m);  fpbar += dt cbar df/dfp.
+      C_m = alpha + a alpha_x . E_m, E_m = X_m - m_k (a = 1 + mu0 dt):
+                              alphabar = sum cbar;  alpha_xbar = a sum cbar_m E_m;  Ebar_m = a cbar_m alpha_x.
+      Z_m = (sigma0 X_m + sigma1) alpha_x:  alpha_xbar += sum Zbar_m (sigma0 X_m + sigma1);
+                              Xbar_m += sigma0 Zbar_m alpha_x.
+      alpha = Ybar - alpha_x . Dbar:  alpha_xbar -= alphabar Dbar.
+      alpha_x = A^{-1} b with A = sum_j w_j D'_j D'_j^T + lam I, b = sum_j w_j r_j D'_j (r_j = Y_j - Ybar):
+                              mu = A^{-1} alpha_xbar;  lambar = -mu . alpha_x;
+                              G_{k+1, j} = w_j (mu . D'_j + alphabar);
+                              Dbar_j (the design's adjoint) = w_j ((r_j - alpha_x . D'_j) mu - (mu . D'_j) alpha_x
+                                  - alphabar alpha_x) + (weights' term below);
+                              wbar_j = (mu . D'_j)(r_j - alpha_x . D'_j) + alphabar (Y_j - alpha_x . D_j).
+      w = softmax(-|D_j|^2 / (h^2 V)):  lbar_j = w_j (wbar_j - sum_i w_i wbar_i);
+                              Dbar_j -= 2 lbar_j D_j / (h^2 V);  Vbar += sum_j lbar_j |D_j|^2 / (h^2 V^2).
+      lam = ridge_rel V / d:  Vbar += lambar ridge_rel / d.
+    Each D-adjoint reaches x0 as (J_j - (1 + mu0 dt)^k) Dbar_j (the particle minus the mean path), each direct
+    X-adjoint (Z, the terminal g) as J_j Xbar_j, and each Vbar_k as Vbar_k dV_k/dx0.
+    """
+    if pb.f_kind in X_DEPENDENT_F:
+        raise NotImplementedError("the reverse mode covers the families whose f does not depend on x")
+    mu0, sigma0, mu1, sigma1 = coef
+    x0 = np.asarray(x0, dtype=np.float64)
+    dt = pb.T / pb.N
+    a = 1.0 + mu0 * dt
+    fw = solve_point_coef(pb, x0, p, coef, tape=True)
+    X, ms, Vs, Ys, levels = fw["X"], fw["ms"], fw["Vs"], fw["Y"], fw["levels"]
+    dm, dVs = coef_moment_tangents(pb, x0, coef)
+    # the particles' tangents J_k = d X_k / d x0 (coordinate-wise), from the same increments
+    J = np.ones((pb.N + 1, pb.M, pb.d))
+    q = stream_of(pb, p)
+    for k in range(pb.N):
+        xi = philox.normals(pb.seed, pb.instance, q, k, pb.M, pb.d)
+        J[k + 1] = J[k] * (a + sigma0 * np.sqrt(dt) * xi)
+    x0bar = np.zeros(pb.d)
+    fpbar = np.zeros(4)
+    G = np.full(pb.M, ubar / pb.M)          # u = mean_m Y^m_0
+    h2 = pb.eps_h ** 2
+    for k in range(pb.N):
+        lv = levels[k]
+        ax = lv["alpha_x"]
+        cbar = G / lv["Fp"]
+        E = X[k] - ms[k][None, :]
+        Xdir = np.zeros((pb.M, pb.d))
+        zsum = np.zeros(pb.d)
+        for m in range(pb.M):
+            sx = sigma0 * X[k][m] + sigma1
+            _, _, fz, fz_scale, fth = f_eval(pb, k * dt, Ys[k][m:m + 1], sx * ax)
+            Zbar = dt * cbar[m] * fz_scale[0] * fz
+            fpbar += dt * cbar[m] * fth[:, 0]
+            zsum += Zbar * sx
+            Xdir[m] = sigma0 * Zbar * ax
+        abar = cbar.sum()
+        axbar = a * (E.T @ cbar) + zsum - abar * lv["Dbar"]
+        Ebar = a * cbar[:, None] * ax[None, :]
+        # level k's positions: E is a D-type quantity, Z a direct one
+        x0bar += ((J[k] - dm[k]) * Ebar).sum(axis=0) + (J[k] * Xdir).sum(axis=0)
+        # the regression of level k (design at t_{k+1})
+        D, w, Dc = lv["D"], lv["w"], lv["Dc"]
+        r = lv["Y_next"] - lv["Ybar"]
+        mu = lv["sys"].solve(axbar)
+        lam_bar = -float(mu @ ax)
+        pj = Dc @ mu
+        qj = Dc @ ax
+        G = w * (pj + abar)
+        wbar = pj * (r - qj) + abar * (lv["Y_next"] - D @ ax)
+        Dbar = w[:, None] * ((r - qj)[:, None] * mu[None, :] - pj[:, None] * ax[None, :] - abar * ax[None, :])
+        V = Vs[k + 1]
+        Vbar = lam_bar * pb.ridge_rel / pb.d
+        if pb.eps_h != 0.0:
+            lbar = w * (wbar - float(w @ wbar))
+            n2 = np.einsum("ij,ij->i", D, D)
+            Dbar -= (2.0 * lbar / (h2 * V))[:, None] * D
+            Vbar += float(lbar @ n2) / (h2 * V * V)
+        x0bar += ((J[k + 1] - dm[k + 1]) * Dbar).sum(axis=0) + Vbar * dVs[k + 1]
+    _, gx, gth = g_eval(pb, X[pb.N])
+    x0bar += (J[pb.N] * (G[:, None] * gx)).sum(axis=0)
+    gpbar = gth @ G
+    return dict(x0bar=x0bar, gpbar=gpbar, fpbar=fpbar, u=fw["u"], grad=fw["grad"])
 
 
 # ---------------------------------------------------------------- constant matrix sigma (scheme R)

@@ -403,7 +403,8 @@ def main():
         pbk = F.Problem(d=1000, M=4096, N=20, T=0.3, f_kind=F.F_ALLEN_CAHN, fp=(1.0, 1.0, 0, 0), g_kind=F.G_AC,
                         gp=(0.4, 0, 0, 0), prec=F.F32C, seed=0, instance=0)
         xk = torch.full((1024, 1000), 0.03, dtype=torch.float64, device=dev)
-        wsk = torch.empty(F.coef_workspace_size(pbk, 1024, 0.05, 0.2, -0.1, 0.4), dtype=torch.uint8, device=dev)
+        wsk = torch.empty(F.coef_workspace_size(pbk, 1024, 0.05, 0.2, -0.1, 0.4, tape=True), dtype=torch.uint8,
+                          device=dev)
         F.solve_coef(pbk, xk, 0.05, 0.2, -0.1, 0.4, ws=wsk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -411,11 +412,24 @@ def main():
         torch.cuda.synchronize()
         seck = time.perf_counter() - t0
         itk = F.solve_coef(pbk, xk, 0.05, 0.2, -0.1, 0.4, ws=wsk, return_iters=True)[3]
+        # forward with the tape + reverse mode (the design, weights and ridge depend on x0 here)
+        ubk = torch.ones(1024, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.solve_coef(pbk, xk, 0.05, 0.2, -0.1, 0.4, ws=wsk, tape=True)
+        xbk, _, _, stbk = F.solve_coef_backward(pbk, xk, ubk, wsk, 0.05, 0.2, -0.1, 0.4)
+        torch.cuda.synchronize()
+        secka = time.perf_counter() - t0
         small["allen_cahn_coef_affine_diag_d1000_P1024_M4096_N20_fp32c"] = {
             "value": round(1024 / seck, 2), "unit": "points/s", "ms_per_step": round(seck * 1e3, 2),
             "coef": {"mu0": 0.05, "sigma0": 0.2, "mu1": -0.1, "sigma1": 0.4}, "cg_iters_per_level": itk,
-            "u_mean": round(float(uk.mean().item()), 6), "status_nonzero_points": int((stk != 0).sum().item())}
-        log(f"[bench] x-dependent coefficients d=1000 M=4096 P=1024 N=20 (FP32C): {seck * 1e3:.1f} ms")
+            "u_mean": round(float(uk.mean().item()), 6), "status_nonzero_points": int((stk != 0).sum().item()),
+            "fwd_adj": {"value": round(1024 / secka, 2), "unit": "points/s", "ms_per_step": round(secka * 1e3, 2),
+                        "workspace_with_tape_GiB": round(wsk.numel() / 2 ** 30, 2),
+                        "status_nonzero_points": int((stbk != 0).sum().item())}}
+        log(f"[bench] x-dependent coefficients d=1000 M=4096 P=1024 N=20 (FP32C): {seck * 1e3:.1f} ms, "
+            f"forward + adjoint {secka * 1e3:.1f} ms")
+        del xbk
         del wsk, xk
 
     # ---------------- paper-literal per-anchor scheme at the paper's Burgers runtime setting:

@@ -480,13 +480,30 @@ int fbsde_solve_literal_coef(const fbsde_problem* pb, const fbsde_coef* coef, in
  * pb->s is not used and pb->mu must be NULL; shared_dw, f kinds that read x and the Case 2 terminal
  * value are refused (FBSDE_EINVAL), as are coef kinds and values fbsde_solve_literal_coef refuses.  A
  * cloud whose spread vanishes (V = 0: sigma1 = 0 with x0 = 0) has no regression and is undefined.
- * Workspace: fbsde_coef_workspace_size bytes (no tape: the adjoint is not offered under these
- * coefficients).  u [P], grad [P][d] or NULL, status [P] and cg_iters_out as fbsde_solve, on stream;
- * cg_iters_out, when given, makes the call wait for the stream once per level. */
-int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes);
+ * Workspace: fbsde_coef_workspace_size bytes for the same flags (FBSDE_WS_TAPE: also the tape that
+ * fbsde_solve_coef_backward reads, and the tangent state it regenerates).  u [P], grad [P][d] or NULL,
+ * status [P] and cg_iters_out as fbsde_solve, on stream; cg_iters_out, when given, makes the call wait for
+ * the stream once per level. */
+int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, int32_t flags,
+                              size_t* bytes);
 int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0, double* u,
-                     double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
-                     fbsde_stream stream);
+                     double* grad, uint32_t* status, void* ws, size_t ws_bytes, int32_t flags,
+                     int32_t* cg_iters_out, fbsde_stream stream);
+
+/* Reverse mode of fbsde_solve_coef for L = sum_p u_bar[p] u(0, x0_p), after fbsde_solve_coef with
+ * FBSDE_WS_TAPE on the same workspace, problem, coefficients and points (else FBSDE_ESTATE).  Under these
+ * coefficients x0 reaches u through every level's regression: the particles (X_k is coordinate-wise
+ * affine in x0, with slope J_k = prod_i (1 + mu0 dt + sigma0 dW_i), regenerated beside the state), the mean
+ * path (slope (1 + mu0 dt)^k) and the cloud variance V_k (bandwidth and ridge; its x0-derivative from
+ * the moment recursion).  Per level the adjoint solves one more ridge system (CG) and differentiates the
+ * design, the kernel weights (softmax) and the ridge; Z = sigma(X)^T alpha_x contributes per particle.
+ * Outputs as fbsde_solve_backward: x0_bar [P][d], gp_bar [4], fp_bar [4] (summed over points), status
+ * [P] (flags added).  The tape is consumed (a second call needs a new forward solve).  f kinds and terminal
+ * values as fbsde_solve_coef. */
+int fbsde_solve_coef_backward(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0,
+                              const double* u_bar, double* x0_bar, double* gp_bar, double* fp_bar,
+                              uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,
+                              fbsde_stream stream);
 
 /* Scheme R under a constant diffusion matrix (Sec. 2.1's problem class with matrix sigma; Z = sigma^T
  * grad u in the steps after the matrix-free solve): X_k = x0 + mu t_k + sigma W_k with sigma [d][d]

@@ -20,7 +20,7 @@ EXPORTED = ("fbsde_state_ld", "fbsde_workspace_size", "fbsde_terminal", "fbsde_s
             "fbsde_literal_workspace_size", "fbsde_literal_workspace_size_stored", "fbsde_literal_coef_workspace_size",
             "fbsde_solve_literal_coef", "fbsde_coef_workspace_size", "fbsde_solve_coef",
             "fbsde_sigma_workspace_size", "fbsde_solve_sigma", "fbsde_solve_sigma_backward",
-            "fbsde_solve_literal", "fbsde_strerror")
+            "fbsde_solve_coef_backward", "fbsde_solve_literal", "fbsde_strerror")
 
 
 BATCH_TILED, BATCH_PERSISTENT = 0, 1
@@ -120,11 +120,12 @@ def load():
     lib.fbsde_solve_literal.argtypes = [pb, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fbsde_literal_coef_workspace_size.argtypes = [pb, P(CCoef), i64, P(sz)]
     lib.fbsde_solve_literal_coef.argtypes = [pb, P(CCoef), i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]
-    lib.fbsde_coef_workspace_size.argtypes = [pb, P(CCoef), i64, P(sz)]
+    lib.fbsde_coef_workspace_size.argtypes = [pb, P(CCoef), i64, i32, P(sz)]
     lib.fbsde_sigma_workspace_size.argtypes = [pb, i64, i32, P(sz)]
     lib.fbsde_solve_sigma.argtypes = [pb, vp, i64, vp, vp, vp, vp, vp, sz, i32, vp, vp]
     lib.fbsde_solve_sigma_backward.argtypes = [pb, vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
-    lib.fbsde_solve_coef.argtypes = [pb, P(CCoef), i64, vp, vp, vp, vp, vp, sz, vp, vp]
+    lib.fbsde_solve_coef.argtypes = [pb, P(CCoef), i64, vp, vp, vp, vp, vp, sz, i32, vp, vp]
+    lib.fbsde_solve_coef_backward.argtypes = [pb, P(CCoef), i64, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp]
     lib.fbsde_strerror.argtypes = [ctypes.c_int]
     lib.fbsde_strerror.restype = ctypes.c_char_p
     for name in ("fbsde_workspace_size", "fbsde_terminal", "fbsde_solve_step", "fbsde_solve",
@@ -137,7 +138,8 @@ def load():
                  "fbsde_workspace_cg_rows", "fbsde_solve_noalloc", "fbsde_batched_cg_bytes",
                  "fbsde_literal_workspace_size_stored",
                  "fbsde_solve_literal_coef", "fbsde_coef_workspace_size", "fbsde_solve_coef",
-                 "fbsde_sigma_workspace_size", "fbsde_solve_sigma", "fbsde_solve_sigma_backward", "fbsde_solve_sigma_backward",
+                 "fbsde_sigma_workspace_size", "fbsde_solve_sigma", "fbsde_solve_sigma_backward",
+                 "fbsde_solve_coef_backward",
                  "fbsde_solve_literal"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

@@ -545,16 +545,17 @@ def literal_coef_workspace_size(pb, P, mu0, sigma0, mu1=0.0, sigma1=0.0):
     return int(out.value)
 
 
-def coef_workspace_size(pb, P, mu0, sigma0, mu1=0.0, sigma1=0.0):
+def coef_workspace_size(pb, P, mu0, sigma0, mu1=0.0, sigma1=0.0, tape=False):
     out = ctypes.c_size_t(0)
     N.check(N.load().fbsde_coef_workspace_size(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)), P,
-                                               ctypes.byref(out)))
+                                               N.WS_TAPE if tape else 0, ctypes.byref(out)))
     return int(out.value)
 
 
-def solve_coef(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, want_grad=True, ws=None, return_iters=False):
+def solve_coef(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, want_grad=True, ws=None, return_iters=False, tape=False):
     """Scheme R (as solve) under the affine diagonal coefficients mu(x) = mu0 x + mu1, sigma(x) =
-    diag(sigma0 x + sigma1): u [P], grad [P][d] (or None), status [P] (and CG iterations per level)."""
+    diag(sigma0 x + sigma1): u [P], grad [P][d] (or None), status [P] (and CG iterations per level).
+    tape=True keeps what solve_coef_backward needs in ws."""
     P = x0.shape[0]
     _dev_f64(x0, (P, pb.d))
     dev = x0.device
@@ -562,15 +563,39 @@ def solve_coef(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, want_grad=True, ws=None
     grad = torch.empty((P, pb.d), dtype=torch.float64, device=dev) if want_grad else None
     st = torch.empty(P, dtype=torch.int32, device=dev)
     if ws is None:
-        ws = torch.empty(max(coef_workspace_size(pb, P, mu0, sigma0, mu1, sigma1), 1), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(coef_workspace_size(pb, P, mu0, sigma0, mu1, sigma1, tape), 1), dtype=torch.uint8,
+                         device=dev)
     iters = (ctypes.c_int32 * pb.N)() if return_iters else None
     N.check(N.load().fbsde_solve_coef(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)), P,
                                       x0.data_ptr(), u.data_ptr(), _ptr(grad), st.data_ptr(), ws.data_ptr(),
-                                      ws.numel(), ctypes.cast(iters, ctypes.c_void_p) if return_iters else None,
-                                      _stream()))
+                                      ws.numel(), N.WS_TAPE if tape else 0,
+                                      ctypes.cast(iters, ctypes.c_void_p) if return_iters else None, _stream()))
     if return_iters:
         return u, grad, st, list(iters)
     return u, grad, st
+
+
+def solve_coef_backward(pb, x0, u_bar, ws, mu0, sigma0, mu1=0.0, sigma1=0.0, return_iters=False):
+    """Reverse mode of solve_coef for L = sum_p u_bar[p] u_p; ws from solve_coef(..., tape=True) with the
+    same coefficients.  Returns x0_bar [P][d], gp_bar [4], fp_bar [4], status [P] (and the adjoint's CG
+    iterations per level)."""
+    P = x0.shape[0]
+    _dev_f64(x0, (P, pb.d))
+    _dev_f64(u_bar, (P,))
+    dev = x0.device
+    x0_bar = torch.empty((P, pb.d), dtype=torch.float64, device=dev)
+    gp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
+    fp_bar = torch.zeros(4, dtype=torch.float64, device=dev)
+    st = torch.zeros(P, dtype=torch.int32, device=dev)
+    iters = (ctypes.c_int32 * pb.N)() if return_iters else None
+    N.check(N.load().fbsde_solve_coef_backward(ctypes.byref(pb.c()), ctypes.byref(_coef(mu0, sigma0, mu1, sigma1)), P,
+                                               x0.data_ptr(), u_bar.data_ptr(), x0_bar.data_ptr(), gp_bar.data_ptr(),
+                                               fp_bar.data_ptr(), st.data_ptr(), ws.data_ptr(), ws.numel(),
+                                               ctypes.cast(iters, ctypes.c_void_p) if return_iters else None,
+                                               _stream()))
+    if return_iters:
+        return x0_bar, gp_bar, fp_bar, st, list(iters)
+    return x0_bar, gp_bar, fp_bar, st
 
 
 def sigma_workspace_size(pb, P, tape=False):

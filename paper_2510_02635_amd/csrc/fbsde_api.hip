@@ -6,9 +6,11 @@
 #include "fbsde_adjoint.hpp"
 #include "fbsde_cgloop.hpp"
 #include "fbsde_dual.hpp"
+#include "fbsde_coef_adjoint.hpp"
 
 #include <atomic>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <functional>
 #include <vector>
@@ -94,6 +96,17 @@ bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk) {
 
 namespace {
 
+// Buffers of the reverse mode under x-dependent coefficients (after the per-point workspace): the tape
+// of the reversal per level (1 / F', |Z|^2, sum Z per particle), the tangent state J (as the state), and
+// per particle the Newton adjoint's Z weight, the design adjoint's coefficients and row dots; the x0
+// accumulator [P][ld]; Vbar [P][N + 1].
+struct CoefAdj {
+    void* J;
+    double *dydc, *zz, *zs;
+    double *zw, *c1, *c2, *c3, *pd, *qd, *n2;
+    double *x0acc, *Vbar;
+};
+
 struct WS {
     CgCtl* ctl;     // device-side CG loop control (offset 0 of the workspace)
     void* W;
@@ -117,6 +130,10 @@ struct WS {
     // a step after the forward sweep that rewrites the terminal values (constant matrix sigma)
     const host::TerminalStep* terminal = nullptr;
     const host::AdjTerminalHooks* adjh = nullptr;   // the same for the reverse mode
+    // x-dependent coefficients with a tape: the per-particle tape of the reversal and the reverse mode's
+    // buffers (tangent state, design adjoint, variance adjoint); tag_salt tells such a tape apart
+    const CoefAdj* cadj = nullptr;
+    int tag_salt = 0;
     // tape for the adjoint: per level k (cloud t_{k+1})
     double *tY, *tw, *tax, *tWbar, *tscal;
     int* tag;
@@ -398,10 +415,14 @@ void launch_reverse(const fbsde_problem* pb, const Plan& pl, int64_t P, int k, S
             cf.Ba = ws.coefB[k];
             cf.Ab = ws.coefA[k + 1];
             cf.Bb = ws.coefB[k + 1];
+            const int64_t PM = P * pl.M;
+            double* zz_t = ws.cadj ? ws.cadj->zz + (size_t)k * PM : nullptr;
+            double* zs_t = ws.cadj ? ws.cadj->zs + (size_t)k * PM : nullptr;
             hipLaunchKernelGGL((k_reverse<S, QQ, TT, 3>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
                                st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
                                std::sqrt(dt), pb->s, dt, ax, scal ? scal : ws.scal, NS, fspec_of(pb), pb->newton_iters,
-                               ky.k0, ky.k1, pb->point_base, Y, rn2, dydc, status, shared, x0, nullptr, 0.0, cf);
+                               ky.k0, ky.k1, pb->point_base, Y, rn2, dydc, status, shared, x0, nullptr, 0.0, cf,
+                               zz_t, zs_t);
         } else if (pb->f_kind == FBSDE_F_HJ_SINK)
             hipLaunchKernelGGL((k_reverse<S, QQ, TT, 1>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
                                st, W, ldw, (int)pl.M, pl.rows_per_chunk, (int)pl.d, pl.ld, k, (k == 0) ? 1 : 0,
@@ -478,6 +499,10 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
         if (k > 0) {
             double* Yout = tape ? ws.tY + (size_t)k * PM : Yk;
             launch_reverse<S>(pb, pl, P, k, W, ldw, ws.x, ws, Yout, ws.rn2, status, st, ws.c2, nullptr, 0, x0);
+            // the coefficient family's tape keeps 1 / F' per particle (c2 itself feeds the next warm start)
+            if (tape && ws.cadj &&
+                hipMemcpyAsync(ws.cadj->dydc + (size_t)k * PM, ws.c2, PM * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return FBSDE_EHIP;
             if (!tape) std::swap(Ycur, Yk);
             else Ycur = Yout;
         } else {
@@ -488,7 +513,7 @@ int solve_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double*
         err = last_error();
         if (err) return err;
     }
-    if (tape) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, tape_tag(pb, P));
+    if (tape) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, tape_tag(pb, P) ^ ws.tag_salt);
     return last_error();
 }
 
@@ -571,6 +596,87 @@ int backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const doub
     if (ws.adjh && (err = ws.adjh->after(ws.part1, pl.nchunk, vc, pl.ld, x0_bar, st))) return err;
     hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(64), 0, st, ws.adj, P, gp_bar, fp_bar);
     // the tape is consumed: the state no longer holds W_1 of the primal pass
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, 0);
+    return last_error();
+}
+
+// The reverse mode under the affine diagonal coefficients (fbsde_coef_adjoint.hpp), after a taped
+// fbsde_solve_coef on the same workspace: the state holds D_0 = 0 again.  cf: the family with dt; A, B: the
+// mean path's m_k = x0 A_k + B_k.
+template <typename S>
+int coef_backward_impl(const fbsde_problem* pb, const Plan& pl, int64_t P, const double* x0, const double* u_bar,
+                       double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status, WS& ws, const CoefArgs& cf,
+                       const double* A, const double* B, int32_t* cg_iters_out, hipStream_t st) {
+    S* W = (S*)ws.W;
+    S* J = (S*)ws.cadj->J;
+    const CoefAdj& ca = *ws.cadj;
+    const int64_t ldw = pl.ld;
+    const int64_t PM = P * pl.M, PL = P * (int64_t)pl.ld;
+    const double dt = pb->T / (double)pb->N, sqdt = std::sqrt(dt);
+    const Keys ky = keys_of(pb);
+    const FSpec fs = fspec_of(pb);
+    const int vstride = (int)pl.N + 1;
+    const double rho_d = pb->ridge_rel / (double)pl.d, h2 = pb->eps_h * pb->eps_h;
+    int err = FBSDE_OK;
+    for (int k = 0; k < (int)pl.N; ++k) {
+        const double* ax_k = ws.tax + (size_t)k * PL;
+        const double* w_k = ws.tw + (size_t)k * PM;
+        const double* Dbar_k = ws.tWbar + (size_t)k * PL;
+        const double* ts_k = ws.tscal + (size_t)k * P * NS;
+        CoefArgs ck = cf;
+        ck.Aa = A[k];
+        ck.Ba = B[k];
+        hipLaunchKernelGGL(k_cadj_newton, dim3((unsigned)P), dim3(256), 0, st, ws.G,
+                           k > 0 ? ws.tY + (size_t)k * PM : nullptr, ca.dydc + (size_t)k * PM, ca.zz + (size_t)k * PM,
+                           ca.zs + (size_t)k * PM, ts_k, NS, x0, ax_k, (int)pl.d, pl.ld, ck, fs, dt,
+                           pb->newton_iters, (int)pl.M, u_bar, ws.cbar, ca.zw, ws.adj, k == 0 ? 1 : 0, status);
+        // the previous level's design adjoint (mu = its CG solution, still in x) acts on this state
+        dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+            constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+            hipLaunchKernelGGL((k_cadj_advance<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, J, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, (int)pl.d, pl.ld, k,
+                               k == 0 ? 1 : 0, sqdt, ck, fs.kind, x0, ax_k,
+                               k > 0 ? ws.tax + (size_t)(k - 1) * PL : nullptr, ws.x, ws.cbar, ca.zw, ca.c1, ca.c2,
+                               ca.c3, ky.k0, ky.k1, pb->point_base, ws.part1, ws.part2);
+        });
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.active, (int)P);
+        const int vc = fold_parts(pl, P, ws.part1, ws.part2, nullptr, st);
+        hipLaunchKernelGGL(k_cadj_rhs, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.part2, pl.nchunk, vc, pl.ld,
+                           Dbar_k, ws.adj, ws.coefV + (k + 1), vstride, rho_d, ws.x, ws.r, ws.pv, ws.scal, NS,
+                           ws.iscal, ws.active, ca.x0acc, k == 0 ? 1 : 0);
+        // a rank-deficient design keeps FP64 arithmetic in the CG product, as the constant-coefficient adjoint
+        if (pl.M > pl.d + 1) run_cg<S, S>(pb, pl, P, W, ldw, w_k, Dbar_k, ws, status, st, err);
+        else run_cg<S, double>(pb, pl, P, W, ldw, w_k, Dbar_k, ws, status, st, err);
+        if (err) return err;
+        if (cg_iters_out) {
+            cg_iters_out[k] = point_iters_max(ws, P, st, err);
+            if (err) return err;
+        }
+        dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+            constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+            hipLaunchKernelGGL((k_cadj_rowdot<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0,
+                               st, W, ldw, (int)pl.M, pl.rows_per_chunk, pl.ld, ws.x, ax_k, ca.pd, ca.qd, ca.n2);
+        });
+        const double* Ynext = (k + 1 < (int)pl.N) ? ws.tY + (size_t)(k + 1) * PM : ws.Ya;
+        hipLaunchKernelGGL(k_cadj_design, dim3((unsigned)P), dim3(256), 0, st, ca.pd, ca.qd, ca.n2, w_k, Ynext, ts_k,
+                           NS, ws.x, ax_k, Dbar_k, pl.ld, ws.adj, ws.coefV + (k + 1), ca.Vbar + (k + 1), vstride, h2,
+                           rho_d, (int)pl.M, ws.G, ca.c1, ca.c2, ca.c3);
+        if ((err = last_error())) return err;
+    }
+    CoefArgs cN = cf;
+    cN.Aa = A[pl.N];
+    cN.Ba = B[pl.N];
+    dispatch<S>(pl.Q, pl.TEAM, [&](auto qc, auto tc) {
+        constexpr int QQ = decltype(qc)::value, TT = decltype(tc)::value;
+        hipLaunchKernelGGL((k_cadj_terminal<S, QQ, TT>), dim3(pl.nchunk, (unsigned)P), dim3(Geo<QQ, TT>::BS), 0, st,
+                           W, J, ldw, (int)pl.M, pl.rows_per_chunk, pl.nchunk, (int)pl.d, pl.ld, x0, pb->gvec, cN,
+                           pb->g_kind, pb->gp[0], ws.G, ws.x, ws.tax + (size_t)(pl.N - 1) * PL, ca.c1, ca.c2, ca.c3,
+                           ws.part1, ws.psc);
+    });
+    const int vc = fold_parts(pl, P, ws.part1, nullptr, nullptr, st);
+    hipLaunchKernelGGL(k_cadj_x0bar, dim3((unsigned)P), dim3(256), 0, st, ws.part1, ws.psc, pl.nchunk, vc, (int)pl.d,
+                       pl.ld, ca.x0acc, x0, cf, (int)pl.N, ca.Vbar, vstride, ws.adj, x0_bar);
+    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(64), 0, st, ws.adj, P, gp_bar, fp_bar);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ws.tag, 0);
     return last_error();
 }
@@ -849,27 +955,81 @@ int solve_per_point_terminal(const fbsde_problem* pb, int64_t P, const double* x
 }  // namespace fbsde
 
 namespace {
-// the table V[p][k], k = 0..N, after the per-point workspace
-size_t coef_r_table_bytes(const Plan& pl, int64_t P) { return (size_t)round_up(P * (pl.N + 1) * 8, 256); }
+// After the per-point workspace: the table V[p][k], k = 0..N, and with the tape the reverse mode's buffers
+// (CoefAdj).  base == nullptr: only count.  Returns bytes.
+size_t coef_r_extra(const Plan& pl, int64_t P, int32_t flags, char* base, double** V, CoefAdj* ca) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* q = base ? base + off : nullptr;
+        off += round_up((int64_t)bytes, 256);
+        return q;
+    };
+    const size_t PM = (size_t)P * pl.M, PL = (size_t)P * pl.ld;
+    *V = (double*)take((size_t)P * (pl.N + 1) * 8);
+    if (flags & FBSDE_WS_TAPE) {
+        ca->Vbar = (double*)take((size_t)P * (pl.N + 1) * 8);
+        ca->dydc = (double*)take((size_t)pl.N * PM * 8);
+        ca->zz = (double*)take((size_t)pl.N * PM * 8);
+        ca->zs = (double*)take((size_t)pl.N * PM * 8);
+        ca->J = take(PM * pl.ld * pl.esz);
+        ca->zw = (double*)take(PM * 8);
+        ca->c1 = (double*)take(PM * 8);
+        ca->c2 = (double*)take(PM * 8);
+        ca->c3 = (double*)take(PM * 8);
+        ca->pd = (double*)take(PM * 8);
+        ca->qd = (double*)take(PM * 8);
+        ca->n2 = (double*)take(PM * 8);
+        ca->x0acc = (double*)take(PL * 8);
+    }
+    return off;
+}
+
+// The mean path m_k = x0 A[k] + B[k] of the Euler-Maruyama step, per coordinate.
+void coef_mean_path(const Plan& pl, const CoefArgs& cf, std::vector<double>& A, std::vector<double>& B) {
+    A.assign((size_t)pl.N + 1, 0.0);
+    B.assign((size_t)pl.N + 1, 0.0);
+    A[0] = 1.0;
+    for (int64_t k = 0; k < pl.N; ++k) {
+        A[k + 1] = A[k] * (1.0 + cf.mu0 * cf.dt);
+        B[k + 1] = B[k] * (1.0 + cf.mu0 * cf.dt) + cf.mu1 * cf.dt;
+    }
+}
+
+// Sets a coefficient family's tape apart from the constant-coefficient one (even: tape tags are odd).
+int coef_salt(const CoefArgs& cf) {
+    uint64_t h = 1469598103934665603ull;
+    const double v[4] = {cf.mu0, cf.s0, cf.mu1, cf.s1};
+    for (double x : v) {
+        uint64_t b;
+        std::memcpy(&b, &x, 8);
+        h ^= b;
+        h *= 1099511628211ull;
+    }
+    return (int)((h >> 17) & 0x7FFFFFFE) | 2;
+}
 }  // namespace
 
 extern "C" {
 
-int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, size_t* bytes) {
-    if (!bytes) return FBSDE_EINVAL;
+int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, int32_t flags,
+                              size_t* bytes) {
+    if (!bytes || (flags & ~FBSDE_WS_TAPE)) return FBSDE_EINVAL;
     fbsde_problem pbc;
     Plan pl;
     CoefArgs cf;
     const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
     if (rc) return rc;
     WS ws;
-    *bytes = carve(pl, P, 0, nullptr, ws) + coef_r_table_bytes(pl, P);
+    double* V = nullptr;
+    CoefAdj ca{};
+    *bytes = carve(pl, P, flags, nullptr, ws) + coef_r_extra(pl, P, flags, nullptr, &V, &ca);
     return FBSDE_OK;
 }
 
 int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0, double* u,
-                     double* grad, uint32_t* status, void* wsp, size_t ws_bytes, int32_t* cg_iters_out,
-                     fbsde_stream stream) {
+                     double* grad, uint32_t* status, void* wsp, size_t ws_bytes, int32_t flags,
+                     int32_t* cg_iters_out, fbsde_stream stream) {
+    if (flags & ~FBSDE_WS_TAPE) return FBSDE_EINVAL;
     fbsde_problem pbc;
     Plan pl;
     CoefArgs cf;
@@ -882,25 +1042,70 @@ int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P,
     }
     if (!x0 || !u || !status || !wsp) return FBSDE_EINVAL;
     WS ws;
-    const size_t base = carve(pl, P, 0, nullptr, ws);
-    if (base + coef_r_table_bytes(pl, P) > ws_bytes) return FBSDE_ENOSPC;
-    carve(pl, P, 0, (char*)wsp, ws);
-    // the mean path m_k = x0 A_k + B_k of the Euler-Maruyama step, per coordinate
-    std::vector<double> A((size_t)pl.N + 1), B((size_t)pl.N + 1);
-    A[0] = 1.0;
-    B[0] = 0.0;
-    for (int64_t k = 0; k < pl.N; ++k) {
-        A[k + 1] = A[k] * (1.0 + cf.mu0 * cf.dt);
-        B[k + 1] = B[k] * (1.0 + cf.mu0 * cf.dt) + cf.mu1 * cf.dt;
-    }
+    double* V = nullptr;
+    CoefAdj ca{};
+    const size_t base = carve(pl, P, flags, nullptr, ws);
+    if (base + coef_r_extra(pl, P, flags, nullptr, &V, &ca) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, flags, (char*)wsp, ws);
+    coef_r_extra(pl, P, flags, (char*)wsp + base, &V, &ca);
+    std::vector<double> A, B;
+    coef_mean_path(pl, cf, A, B);
+    const bool tape = (flags & FBSDE_WS_TAPE) != 0;
     ws.coef = &cf;
-    ws.coefV = (const double*)((char*)wsp + base);
+    ws.coefV = V;
     ws.coefA = A.data();
     ws.coefB = B.data();
+    if (tape) {
+        ws.cadj = &ca;
+        ws.tag_salt = coef_salt(cf);
+    }
     hipStream_t st = (hipStream_t)stream;
     if (pbc.prec == FBSDE_F64)
-        return solve_impl<double>(&pbc, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
-    return solve_impl<float>(&pbc, pl, P, x0, u, grad, status, ws, false, cg_iters_out, st);
+        return solve_impl<double>(&pbc, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
+    return solve_impl<float>(&pbc, pl, P, x0, u, grad, status, ws, tape, cg_iters_out, st);
+}
+
+int fbsde_solve_coef_backward(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0,
+                              const double* u_bar, double* x0_bar, double* gp_bar, double* fp_bar, uint32_t* status,
+                              void* wsp, size_t ws_bytes, int32_t* cg_iters_out, fbsde_stream stream) {
+    fbsde_problem pbc;
+    Plan pl;
+    CoefArgs cf;
+    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
+    if (rc) return rc;
+    if (!gp_bar || !fp_bar) return FBSDE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (P == 0) {   // an empty sum: zero parameter adjoints
+        if (cg_iters_out)
+            for (int64_t k = 0; k < pb->N; ++k) cg_iters_out[k] = 0;
+        adj_params(nullptr, 0, gp_bar, fp_bar, st);
+        return last_error();
+    }
+    if (!x0 || !u_bar || !x0_bar || !status || !wsp) return FBSDE_EINVAL;
+    WS ws;
+    double* V = nullptr;
+    CoefAdj ca{};
+    const size_t base = carve(pl, P, FBSDE_WS_TAPE, nullptr, ws);
+    if (base + coef_r_extra(pl, P, FBSDE_WS_TAPE, nullptr, &V, &ca) > ws_bytes) return FBSDE_ENOSPC;
+    carve(pl, P, FBSDE_WS_TAPE, (char*)wsp, ws);
+    coef_r_extra(pl, P, FBSDE_WS_TAPE, (char*)wsp + base, &V, &ca);
+    int tag = 0;
+    if (hipMemcpyAsync(&tag, ws.tag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return FBSDE_EHIP;
+    if (tag != (tape_tag(&pbc, P) ^ coef_salt(cf))) return FBSDE_ESTATE;
+    std::vector<double> A, B;
+    coef_mean_path(pl, cf, A, B);
+    ws.coef = &cf;
+    ws.coefV = V;
+    ws.coefA = A.data();
+    ws.coefB = B.data();
+    ws.cadj = &ca;
+    if (pbc.prec == FBSDE_F64)
+        return coef_backward_impl<double>(&pbc, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, cf, A.data(),
+                                          B.data(), cg_iters_out, st);
+    return coef_backward_impl<float>(&pbc, pl, P, x0, u_bar, x0_bar, gp_bar, fp_bar, status, ws, cf, A.data(),
+                                     B.data(), cg_iters_out, st);
 }
 
 }  // extern "C"

@@ -541,7 +541,8 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
           int ns, FSpec f, int newton_iters, uint32_t k0, uint32_t k1, uint32_t point_base,
           double* __restrict__ Y, double* __restrict__ rn2, double* __restrict__ dydc, uint32_t* __restrict__ status,
           int shared, const double* __restrict__ x0 = nullptr, const double* __restrict__ mu = nullptr,
-          double tk = 0.0, CoefArgs cf = CoefArgs{}) {
+          double tk = 0.0, CoefArgs cf = CoefArgs{}, double* __restrict__ zz_out = nullptr,
+          double* __restrict__ zs_out = nullptr) {
     using G = Geo<Q, TEAM>;
     using R = S;
     __shared__ double red[2 * G::BS / 64];
@@ -587,6 +588,10 @@ k_reverse(S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int d, int 
             Y[(int64_t)p * M + j_keep] = y;
             rn2[(int64_t)p * M + j_keep] = n2_keep;
             if (dydc) dydc[(int64_t)p * M + j_keep] = 1.0 / Fp;
+            if (zz_out) {   // XK == 3 with a tape: the particle's |Z|^2 and sum_i Z_i for the reverse mode
+                zz_out[(int64_t)p * M + j_keep] = zz_keep;
+                zs_out[(int64_t)p * M + j_keep] = zs_keep;
+            }
         }
         j_keep = -1;
     };

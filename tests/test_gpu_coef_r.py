@@ -160,7 +160,7 @@ def test_coef_refusals_and_empty():
     import ctypes
     bad = F._native.CCoef(F._native.COEF_GEOMETRIC, 0, 0.1, 0.3, 0.2, 0.0)
     out = ctypes.c_size_t(0)
-    assert lib.fbsde_coef_workspace_size(ctypes.byref(hp.c()), ctypes.byref(bad), 2, ctypes.byref(out)) != 0
+    assert lib.fbsde_coef_workspace_size(ctypes.byref(hp.c()), ctypes.byref(bad), 2, 0, ctypes.byref(out)) != 0
     # P = 0 touches nothing
     u, g, st = F.solve_coef(hp, torch.empty((0, d), dtype=torch.float64, device=DEV), *GEO)
     assert u.numel() == 0

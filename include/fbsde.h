@@ -499,7 +499,10 @@ int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P,
  * design, the kernel weights (softmax) and the ridge; Z = sigma(X)^T alpha_x contributes per particle.
  * Outputs as fbsde_solve_backward: x0_bar [P][d], gp_bar [4], fp_bar [4] (summed over points), status
  * [P] (flags added).  The tape is consumed (a second call needs a new forward solve).  f kinds and terminal
- * values as fbsde_solve_coef. */
+ * values as fbsde_solve_coef.  With FBSDE_WS_TAPE, FBSDE_F32C and a rank-deficient design (M <= d + 1) the
+ * taped forward and this call keep the state in FP64 (the adjoint's right-hand side reaches the design's
+ * ridge-only null space, where FP32 rounding of the state comes back scaled by 1 / lambda); the workspace
+ * size accounts for it. */
 int fbsde_solve_coef_backward(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, const double* x0,
                               const double* u_bar, double* x0_bar, double* gp_bar, double* fp_bar,
                               uint32_t* status, void* ws, size_t ws_bytes, int32_t* cg_iters_out,

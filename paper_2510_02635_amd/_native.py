@@ -2,7 +2,9 @@
 import ctypes
 import os
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfbsde.so")
+# FBSDE_LIB_PATH selects another build of the same library (the host-sanitized one, for instance)
+_LIB_PATH = os.environ.get("FBSDE_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib",
+                                                             "libfbsde.so")
 
 F64, F32C = 0, 1
 F_ZERO, F_ALLEN_CAHN, F_HJB, F_BURGERS, F_HJ_SINK, F_LOG_POT = 0, 1, 2, 3, 4, 5

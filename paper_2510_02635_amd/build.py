@@ -1,6 +1,10 @@
 """Build the gfx950 HIP library libfbsde.so in-tree (hipcc, no torch extension machinery).
 
-Usage: python -m paper_2510_02635_amd.build  [--jobs N]
+Usage: python -m paper_2510_02635_amd.build  [-q] [--host-sanitize]
+
+--host-sanitize builds a second copy, _lib/hostsan/libfbsde.so, whose host code (argument checks,
+workspace carving, tile plans, schedules, caches) carries AddressSanitizer and UndefinedBehaviorSanitizer
+instrumentation; the device code is the same.  `python -m paper_2510_02635_amd.hostsan` runs tests against it.
 """
 import os
 import shutil
@@ -29,13 +33,22 @@ def hipcc():
     return exe
 
 
-def build(verbose=True):
+# Host-only sanitizers: each -fsanitize applies to the host pass alone (the device code is not instrumented).
+HOSTSAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+HOSTSAN_LIB = os.path.join(LIBDIR, "hostsan", "libfbsde.so")
+
+
+def build(verbose=True, host_sanitize=False):
     from concurrent.futures import ThreadPoolExecutor
-    os.makedirs(LIBDIR, exist_ok=True)
+    libdir = os.path.dirname(HOSTSAN_LIB) if host_sanitize else LIBDIR
+    lib = HOSTSAN_LIB if host_sanitize else LIB
+    extra = HOSTSAN_FLAGS if host_sanitize else []
+    os.makedirs(libdir, exist_ok=True)
     jobs = []
     for src in SOURCES:
-        obj = os.path.join(LIBDIR, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(libdir, src.replace(".hip", ".o"))
+        cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         jobs.append((cmd, obj))
@@ -51,16 +64,16 @@ def build(verbose=True):
             if lines:
                 sys.stderr.write("\n".join(lines) + "\n")
     objs = [obj for _, obj in jobs]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *[f for f in extra if f != "-g"], *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose="-q" not in sys.argv)
+    build(verbose="-q" not in sys.argv, host_sanitize="--host-sanitize" in sys.argv)

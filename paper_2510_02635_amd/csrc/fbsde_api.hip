@@ -902,7 +902,7 @@ namespace {
 // The per-point scheme under the affine diagonal coefficients: the problem as the kernels see it (s = 1:
 // the state is the displacement from the mean path itself), the plan and the family.
 int coef_r_check(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, fbsde_problem& pbc, Plan& pl,
-                 CoefArgs& cf) {
+                 CoefArgs& cf, int32_t flags = 0) {
     int rc = check_problem(pb, P);
     if (rc) return rc;
     if (!coef || coef->reserved != 0) return FBSDE_EINVAL;
@@ -916,6 +916,11 @@ int coef_r_check(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P, fbs
     if (pb->mu || pb->shared_dw || per_point_forward_only(pb)) return FBSDE_EINVAL;
     pbc = *pb;
     pbc.s = 1.0;
+    // The reverse mode on a rank-deficient design (M <= d + 1) keeps the state in FP64: its adjoint
+    // right-hand side reaches the ridge-only null space, whose component the solve scales by 1 / lam and
+    // the sums over the cloud then cancel, so FP32 rounding of the state would come back amplified by the
+    // ridge's inverse (measured 1.6e-5 against the FP64 oracle at ridge_rel = 1e-3, d = 80, M = 64)
+    if ((flags & FBSDE_WS_TAPE) && pbc.prec == FBSDE_F32C && pb->M <= pb->d + 1) pbc.prec = FBSDE_F64;
     if ((rc = make_plan(&pbc, P, pl))) return rc;
     cf = CoefArgs{coef->mu0, coef->sigma0, coef->mu1, coef->sigma1, pb->T / (double)pb->N, 0.0, 0.0, 0.0, 0.0};
     return FBSDE_OK;
@@ -1017,7 +1022,7 @@ int fbsde_coef_workspace_size(const fbsde_problem* pb, const fbsde_coef* coef, i
     fbsde_problem pbc;
     Plan pl;
     CoefArgs cf;
-    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
+    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf, flags);
     if (rc) return rc;
     WS ws;
     double* V = nullptr;
@@ -1033,7 +1038,7 @@ int fbsde_solve_coef(const fbsde_problem* pb, const fbsde_coef* coef, int64_t P,
     fbsde_problem pbc;
     Plan pl;
     CoefArgs cf;
-    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
+    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf, flags);
     if (rc) return rc;
     if (P == 0) {
         if (cg_iters_out)
@@ -1071,7 +1076,7 @@ int fbsde_solve_coef_backward(const fbsde_problem* pb, const fbsde_coef* coef, i
     fbsde_problem pbc;
     Plan pl;
     CoefArgs cf;
-    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf);
+    const int rc = coef_r_check(pb, coef, P, pbc, pl, cf, FBSDE_WS_TAPE);
     if (rc) return rc;
     if (!gp_bar || !fp_bar) return FBSDE_EINVAL;
     hipStream_t st = (hipStream_t)stream;

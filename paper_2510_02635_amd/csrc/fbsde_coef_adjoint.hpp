@@ -104,7 +104,9 @@ k_cadj_advance(S* __restrict__ W, S* __restrict__ J, int64_t ldw, int M, int row
                const double* __restrict__ c2, const double* __restrict__ c3, uint32_t k0, uint32_t k1,
                uint32_t point_base, double* __restrict__ part_ax, double* __restrict__ part_x0) {
     using Gm = Geo<Q, TEAM>;
-    using R = S;
+    // FP64 vectors and sums on either state: mu carries the ridge-only null-space component of its
+    // right-hand side scaled by 1 / lam, which the sums over the cloud largely cancel
+    using R = double;
     __shared__ double lds[(Gm::TPW > 1) ? Gm::TPW * 4 * Q * Gm::TL : 1];
     const int p = blockIdx.y, c = blockIdx.x;
     const int team = threadIdx.x / Gm::TL, L = threadIdx.x % Gm::TL;
@@ -340,7 +342,7 @@ k_cadj_terminal(const S* __restrict__ W, const S* __restrict__ J, int64_t ldw, i
                 const double* __restrict__ axp, const double* __restrict__ c1, const double* __restrict__ c2,
                 const double* __restrict__ c3, double* __restrict__ part, double* __restrict__ psc) {
     using Gm = Geo<Q, TEAM>;
-    using R = S;
+    using R = double;   // as k_cadj_advance
     __shared__ double lds[(Gm::TPW > 1) ? Gm::TPW * 4 * Q * Gm::TL : 1];
     __shared__ double red[2 * Gm::BS / 64];
     const int p = blockIdx.y, c = blockIdx.x;

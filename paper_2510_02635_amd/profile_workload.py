@@ -42,6 +42,8 @@ def main():
     ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a device copy of this many MiB")
     ap.add_argument("--adjoint", action="store_true", help="solve with the tape, then the reverse mode of sum_p u_p")
+    ap.add_argument("--coef", default="", help="mu0,sigma0,mu1,sigma1: the affine diagonal coefficient family "
+                                                "(scheme R per point) instead of constant coefficients")
     args = ap.parse_args()
     import torch
 
@@ -75,7 +77,13 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.adjoint:
+    if args.coef:
+        cf = [float(v) for v in args.coef.split(",")]
+        ws = torch.empty(F.coef_workspace_size(pb, P, *cf, tape=args.adjoint), dtype=torch.uint8, device="cuda")
+        u, g, st = F.solve_coef(pb, x0, *cf, ws=ws, tape=args.adjoint)
+        if args.adjoint:
+            F.solve_coef_backward(pb, x0, torch.ones(P, dtype=torch.float64, device="cuda"), ws, *cf)
+    elif args.adjoint:
         ws = F.workspace(pb, P, tape=True)
         u, g, st = F.solve(pb, x0, tape=True, ws=ws)
         F.solve_backward(pb, x0, torch.ones(P, dtype=torch.float64, device="cuda"), ws)

@@ -4,7 +4,8 @@ after a taped fbsde_solve_coef, against the oracle's reverse mode on identical s
 
 Here x0 moves the regression design, the kernel weights and the ridge of every level.  Covered: the
 geometric, Ornstein-Uhlenbeck and mixed families; Allen-Cahn, HJB (Z per particle in f) and Burgers; FP64
-(1e-9) and FP32C (1e-5); full-rank and rank-deficient designs; uniform weights; a two-wave team (d = 2000);
+(1e-9) and FP32C (1e-5); full-rank and rank-deficient designs (FP32C ones taped with the FP64 state); uniform
+weights; a two-wave team (d = 2000);
 central differences of the GPU forward; the constant-coefficient reduction to fbsde_solve_backward; the
 affine closed form; the tape's checks and the empty call.
 """
@@ -50,7 +51,22 @@ CASES = [
     ("burgers_two_wave_f64", 2000, 256, 2, 0.05, 2, F.F64, "burgers", MIX, 1.0, 1e-9),
     ("ac_mixed_f32c", 20, 512, 4, 0.3, 3, F.F32C, "ac", MIX, 1.0, 1e-5),
     ("hjb_geometric_f32c", 40, 300, 3, 0.3, 2, F.F32C, "hjb", GEO, 1.0, 1e-5),
+    # rank-deficient in FP32C: the taped solve and the reverse mode keep the state in FP64 (below)
+    ("burgers_rank_deficient_f32c", 80, 64, 3, 0.3, 2, F.F32C, "burgers", OU, 1.0, 1e-5),
 ]
+
+
+def test_rank_deficient_fp32c_tape_keeps_fp64_state():
+    # the adjoint's right-hand side reaches the ridge-only null space of a rank-deficient design, where FP32
+    # rounding of the state would come back scaled by 1 / lambda (1.6e-5 measured on the case above): the
+    # taped solve sizes and runs the FP64 state there, and only there
+    kw = dict(N=3, T=0.3, f_kind=F.F_BURGERS, fp=(0.2, 1.5, 0, 0), g_kind=F.G_AC, gp=(0.4, 0, 0, 0))
+    for d, M, fp64_state in ((80, 64, True), (80, 81, True), (80, 82, False)):
+        h32, _ = problems(d=d, M=M, prec=F.F32C, **kw)
+        h64, _ = problems(d=d, M=M, prec=F.F64, **kw)
+        taped32 = F.coef_workspace_size(h32, 4, *OU, tape=True)
+        assert (taped32 == F.coef_workspace_size(h64, 4, *OU, tape=True)) == fp64_state
+        assert F.coef_workspace_size(h32, 4, *OU) < F.coef_workspace_size(h64, 4, *OU)
 
 
 def _x0(P, d, seed):

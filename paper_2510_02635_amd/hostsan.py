@@ -2,7 +2,10 @@
 code; build it with `python -m paper_2510_02635_amd.build --host-sanitize`).
 
 Usage: python -m paper_2510_02635_amd.hostsan [pytest arguments]   (default: the CPU tests that call the
-library, tests/test_abi.py and tests/test_batched_plan.py)
+library: tests/test_abi.py, tests/test_batched_plan.py, tests/test_host_sizes.py)
+
+Host code only: the ROCm AddressSanitizer runtime also intercepts the HSA device-memory calls for device-side
+checking, which needs XNACK, so a process that allocates device memory under it fails at its first allocation.
 
 The interpreter is not instrumented, so the sanitizer runtime is preloaded into a child pytest process;
 leak checking is off (the interpreter and the HIP runtime keep allocations until exit) and the first
@@ -36,7 +39,7 @@ def main(argv):
     env["LD_PRELOAD"] = ":".join([asan_runtime()] + ([env["LD_PRELOAD"]] if env.get("LD_PRELOAD") else []))
     env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1:abort_on_error=0"
     env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
-    args = argv or [os.path.join(B.ROOT, "tests", "test_abi.py"), os.path.join(B.ROOT, "tests", "test_batched_plan.py")]
+    args = argv or [os.path.join(B.ROOT, "tests", t) for t in ("test_abi.py", "test_batched_plan.py", "test_host_sizes.py")]
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *args]
     print("hostsan:", " ".join(cmd), flush=True)
     return subprocess.run(cmd, env=env, cwd=B.ROOT).returncode

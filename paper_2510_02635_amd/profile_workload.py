@@ -44,6 +44,7 @@ def main():
     ap.add_argument("--adjoint", action="store_true", help="solve with the tape, then the reverse mode of sum_p u_p")
     ap.add_argument("--coef", default="", help="mu0,sigma0,mu1,sigma1: the affine diagonal coefficient family "
                                                 "(scheme R per point) instead of constant coefficients")
+    ap.add_argument("--coef-x0", type=float, default=0.03, help="with --coef: every point at this constant")
     args = ap.parse_args()
     import torch
 
@@ -79,6 +80,7 @@ def main():
         del a, b
     if args.coef:
         cf = [float(v) for v in args.coef.split(",")]
+        x0 = torch.full((P, kw["d"]), args.coef_x0, dtype=torch.float64, device="cuda")
         ws = torch.empty(F.coef_workspace_size(pb, P, *cf, tape=args.adjoint), dtype=torch.uint8, device="cuda")
         u, g, st = F.solve_coef(pb, x0, *cf, ws=ws, tape=args.adjoint)
         if args.adjoint:

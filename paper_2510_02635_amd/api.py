@@ -303,6 +303,46 @@ def solve_autograd(pb, x0, gp=None, fp=None):
     return FBSDEFunction.apply(x0, gp, fp, pb)
 
 
+class CoefFBSDEFunction(torch.autograd.Function):
+    """u(0, x0) under the affine diagonal coefficients (solve_coef) as a differentiable function of x0, gp
+    and fp (the coefficients themselves are constants): forward with the tape, backward through
+    fbsde_solve_coef_backward.  grad u and status are non-differentiable outputs."""
+
+    @staticmethod
+    def forward(ctx, x0, gp, fp, pb, coef):
+        from dataclasses import replace
+        pbv = replace(pb, gp=tuple(float(v) for v in gp.detach().cpu().tolist()),
+                      fp=tuple(float(v) for v in fp.detach().cpu().tolist()))
+        P = x0.shape[0]
+        ws = torch.empty(max(coef_workspace_size(pbv, P, *coef, tape=True), 1), dtype=torch.uint8,
+                         device=x0.device)
+        u, grad, st = solve_coef(pbv, x0.detach().contiguous(), *coef, ws=ws, tape=True)
+        ctx.pb, ctx.ws, ctx.coef = pbv, ws, coef
+        ctx.save_for_backward(x0.detach())
+        ctx.gp_meta = (gp.dtype, gp.device)
+        ctx.fp_meta = (fp.dtype, fp.device)
+        ctx.mark_non_differentiable(grad, st)
+        return u, grad, st
+
+    @staticmethod
+    def backward(ctx, u_bar, grad_bar, st_bar):
+        (x0,) = ctx.saved_tensors
+        if u_bar is None:
+            u_bar = torch.zeros(x0.shape[0], dtype=torch.float64, device=x0.device)
+        x0_bar, gp_bar, fp_bar, _ = solve_coef_backward(ctx.pb, x0, u_bar.to(torch.float64).contiguous(), ctx.ws,
+                                                        *ctx.coef)
+        ctx.ws = None
+        return (x0_bar, gp_bar.to(dtype=ctx.gp_meta[0], device=ctx.gp_meta[1]),
+                fp_bar.to(dtype=ctx.fp_meta[0], device=ctx.fp_meta[1]), None, None)
+
+
+def solve_coef_autograd(pb, x0, mu0, sigma0, mu1=0.0, sigma1=0.0, gp=None, fp=None):
+    """Differentiable solve_coef: returns (u, grad, status); u carries gradients to x0, gp and fp."""
+    gp = torch.tensor(pb.gp, dtype=torch.float64) if gp is None else gp
+    fp = torch.tensor(pb.fp, dtype=torch.float64) if fp is None else fp
+    return CoefFBSDEFunction.apply(x0, gp, fp, pb, (float(mu0), float(sigma0), float(mu1), float(sigma1)))
+
+
 def gemm(A, B, nt=True, C=None, alpha=1.0, beta=0.0):
     """C = alpha * A op(B) + beta * C on the matrix cores; op(B) = B^T (nt) or B.  float32 / float64."""
     prec = N.F64 if A.dtype == torch.float64 else N.F32C

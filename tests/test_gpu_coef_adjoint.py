@@ -208,3 +208,21 @@ def test_coef_adjoint_d1000_M4096_sampled_point():
     _say(f"  adjoint cg iterations {it}; rel_x0bar={e:.2e}")
     assert e <= 1e-5
     assert not st.cpu().numpy().any() and not stb.cpu().numpy().any()
+
+
+def test_autograd_matches_the_entry_points():
+    # solve_coef_autograd: torch.autograd through the hand-written reverse mode, equal to the direct calls
+    d, M, N, T, P = 10, 200, 3, 0.3, 3
+    fk, fp = FAM["burgers"]
+    hp, _ = problems(d=d, M=M, N=N, T=T, f_kind=fk, fp=fp, g_kind=F.G_AC, gp=(0.4, 0, 0, 0), seed=6, instance=2)
+    x0 = torch.tensor(_x0(P, d, 4), device=DEV, requires_grad=True)
+    gp = torch.tensor(hp.gp, dtype=torch.float64, requires_grad=True)
+    fpt = torch.tensor(hp.fp, dtype=torch.float64, requires_grad=True)
+    w = torch.tensor([0.5, -1.0, 2.0], dtype=torch.float64, device=DEV)
+    _say("[coef autograd]")
+    u, _, st = F.solve_coef_autograd(hp, x0, *MIX, gp=gp, fp=fpt)
+    (u * w).sum().backward()
+    _, xb, gpb, fpb, *_ = _forward_backward(hp, x0.detach(), MIX, w)
+    assert torch.equal(x0.grad, xb)
+    assert torch.equal(gp.grad, gpb.cpu()) and torch.equal(fpt.grad, fpb.cpu())
+    assert not st.any()

@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--batched-points", type=int, default=8, help="points per instance in the batched leg")
     ap.add_argument("--no-small", action="store_true", help="skip the one-point and d = 10^4 adjoint legs")
     ap.add_argument("--no-literal", action="store_true", help="skip the paper-literal per-anchor leg")
+    ap.add_argument("--batched-full-forward", action="store_true",
+                    help="also run the batched workload at its configured 256 points per instance, forward, in "
+                         "slices of 8 instances (several minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the points of this workload are independent, so a multi-GPU run "
@@ -673,6 +676,43 @@ def main():
         del xb, ub, gb, stb
         torch.cuda.empty_cache()
 
+    # ---------------- the batched workload at its configured size: 64 instances x 256 points, forward, run
+    # as eight calls of eight instances each (each call prints when it ends)
+    batched_full = None
+    if args.batched_full_forward:
+        insts = workloads.batched_instances(64)
+        Pf = 256
+        tot_s, tot_b, nz = 0.0, 0.0, 0
+        for s0 in range(0, len(insts), 8):
+            sl = insts[s0:s0 + 8]
+            probs = [F.Problem(d=it["d"], M=it["M"], N=20, T=1.0, f_kind=F.F_HJB, fp=(it["lam"], 0, 0, 0),
+                               g_kind=F.G_HJB_LOG, gp=(1.0, 0, 0, 0), prec=F.F32C, seed=0, instance=it["instance"])
+                     for it in sl]
+            xs = [torch.tensor(workloads.points("uniform", Pf, it["d"], seed=100 + it["instance"]),
+                               dtype=torch.float64, device=dev) for it in sl]
+            wsf = F.batched_workspace(probs, xs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uf, _, stf = F.solve_batched(probs, xs, want_grad=False, ws=wsf)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            nb = F.batched_cg_bytes(probs, xs, wsf)
+            tot_s += sec
+            tot_b += nb
+            nz += int(sum(int((q != 0).sum().item()) for q in stf))
+            log(f"[bench] full batched slice {s0 // 8 + 1}/8 (instances {s0}..{s0 + len(sl) - 1}, d "
+                f"{sorted(set(it['d'] for it in sl))}): {sec:.1f} s, CG products {nb / sec / 1e12:.2f} TB/s")
+            del wsf, xs, uf, stf
+            torch.cuda.empty_cache()
+        batched_full = {"value": round(Pf * len(insts) / tot_s, 2), "unit": "points/s", "seconds": round(tot_s, 2),
+                        "config": {"workload": "batched_hjb_64_instances", "points_per_instance": Pf,
+                                   "calls": "8 calls of 8 instances"},
+                        "cg_product_traffic": {"bytes": tot_b, "achieved_GBs": round(tot_b / tot_s / 1e9, 1),
+                                               "frac_of_hbm_peak": round(tot_b / tot_s / 1e9 / HBM_PEAK_GBS, 4)},
+                        "status_nonzero_points": nz}
+        log(f"[bench] full batched 64 x 256 forward: {tot_s:.1f} s, {Pf * len(insts) / tot_s:.1f} points/s, CG "
+            f"products {tot_b / tot_s / 1e12:.2f} TB/s")
+
     value = P / sec32
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
@@ -703,6 +743,7 @@ def main():
         "shared_increments_mfma": shared,
         "literal_per_anchor": literal,
         "batched": batched,
+        "batched_full_forward": batched_full,
         "reverse_sweep_avg_ms_fp32c": round(rev32_ms, 4),
         "status_nonzero_points": int(np.count_nonzero(st32)),
     }

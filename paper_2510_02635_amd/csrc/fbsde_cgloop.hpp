@@ -487,6 +487,54 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
         CSum<R> acc[Q][4];
         double tau = 0.0;
         const S* base = W + (int64_t)p * M * ldw;
+        if constexpr (TEAM > 1 && G::BS <= 256) {
+            // A team of two or four waves per row: every row's dot needs a team reduction (two barriers).
+            // Two rows per step share one reduction, and both rows' loads are in flight together; the
+            // rows and the sums keep the one-row order, so the result is the same.  Measured at 64
+            // points: d = 5000 (four-wave teams) 3.9-4.25 -> 4.3-4.5 TB/s in the loop; with eight-wave
+            // teams (d = 10^4, 512-thread blocks) the second row's registers cost more than the barrier
+            // saves (4.2 -> 3.0 TB/s), so those keep one row per step.
+            for (int jb = r0; jb < r1; jb += 2 * G::TPW) {
+                const int j0 = jb + team, j1 = jb + G::TPW + team;
+                const bool v0 = j0 < r1, v1 = j1 < r1;
+                S xa[Q][4], xb[Q][4];
+                if (v0) load_row<S, Q, G::TL>(base + (int64_t)j0 * ldw, ld, L, xa);
+                if (v1) load_row<S, Q, G::TL>(base + (int64_t)j1 * ldw, ld, L, xb);
+                CSum<R> d0, d1;
+                if (v0) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) d0.add((R)xa[q][e] * v[q][e]);
+                }
+                if (v1) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) d1.add((R)xb[q][e] * v[q][e]);
+                }
+                double t0 = d0.get(), t1 = d1.get();
+                team_sum2<TEAM>(t0, t1, red, team);
+                if (v0) {
+                    const double cj = w[(int64_t)p * M + j0] * s * (t0 - wvp);
+                    tau += cj;
+                    const R cr = (R)cj;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[q][e].add(cr * (R)xa[q][e]);
+                }
+                if (v1) {
+                    const double cj = w[(int64_t)p * M + j1] * s * (t1 - wvp);
+                    tau += cj;
+                    const R cr = (R)cj;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[q][e].add(cr * (R)xb[q][e]);
+                }
+            }
+        } else {
         S xr[Q][4];
         if (PF && r0 + team < r1) load_row<S, Q, G::TL>(base + (int64_t)(r0 + team) * ldw, ld, L, xr);
         for (int jb = r0; jb < r1; jb += G::TPW) {
@@ -522,6 +570,7 @@ k_cg_loop(const S* __restrict__ W, int64_t ldw, int M, int rows_per_chunk, int n
 #pragma unroll
                     for (int e = 0; e < 4; ++e) xr[q][e] = xn[q][e];
             }
+        }
         }
         block_columns_out_c<Q, TEAM, R>(acc, lds, part + ((int64_t)p * nchunk + c) * ld, ld, team, L);
         const double tot = block_sum((L == 0) ? tau : 0.0, red);

@@ -53,6 +53,9 @@ CASES = [
     ("hjb_geometric_f32c", 40, 300, 3, 0.3, 2, F.F32C, "hjb", GEO, 1.0, 1e-5),
     # rank-deficient in FP32C: the taped solve and the reverse mode keep the state in FP64 (below)
     ("burgers_rank_deficient_f32c", 80, 64, 3, 0.3, 2, F.F32C, "burgers", OU, 1.0, 1e-5),
+    # the smallest problem (d = 1, M = 2, one level) and the widest team (d = 10^4: 16-wave rows)
+    ("ac_smallest_f64", 1, 2, 1, 0.3, 2, F.F64, "ac", MIX, 1.0, 1e-9),
+    ("hjb_d10000_team16_f32c", 10000, 64, 2, 0.05, 1, F.F32C, "hjb", MIX, 1.0, 1e-5),
 ]
 
 

@@ -4,7 +4,7 @@
 The state is the displacement from the Euler-Maruyama mean path; the reversal inverts the step from the
 regenerated increments; bandwidth and ridge follow the exact moment recursion per point; Z = sigma(X)^T alpha_x
 per particle.  Covered: the geometric, Ornstein-Uhlenbeck and mixed families; Allen-Cahn, HJB (Z in f) and
-Burgers; FP64 (1e-10) and FP32C (1e-5); full-rank and rank-deficient designs; a two-wave team (d = 2000); the
+Burgers; FP64 (1e-10) and FP32C (1e-5); full-rank and rank-deficient designs (both precisions); a two-wave team (d = 2000); the
 d = 1000, M = 4096 shape on one sampled point; the constant-coefficient reduction to fbsde_solve; the affine
 closed form (f = 0, affine g, no ridge: u = gvec . m_N + b exactly); refusals.
 """
@@ -48,6 +48,10 @@ CASES = [
     (2000, 256, 2, 0.05, 2, F.F64, "burgers", MIX, 1e-10),  # a two-wave team per row
     (20, 512, 4, 0.3, 3, F.F32C, "ac", MIX, 1e-5),       # FP32 state, FP64 Newton
     (40, 300, 3, 0.3, 2, F.F32C, "hjb", GEO, 1e-5),
+    # rank-deficient designs on the FP32 state (untaped): the direct dual solve (M >= d / 8) and the CG with
+    # FP64 arithmetic (M < d / 8)
+    (80, 64, 3, 0.3, 2, F.F32C, "burgers", OU, 1e-5),
+    (600, 64, 3, 0.3, 2, F.F32C, "hjb", MIX, 1e-5),
 ]
 
 

@@ -657,7 +657,7 @@ def main():
                     "frac_of_hbm_peak": round(nbytes / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
         batched = {"value": round(n_pts / sec_b, 2), "unit": "points/s", "ms_per_step": round(sec_b * 1e3, 3),
-                   "dtype": "fp32c", "schedule": "tiled: (instance, point-tile) items over 4 streams, each level's "
+                   "dtype": "fp32c", "schedule": "tiled: (instance, point-tile) items over 3 streams, each level's "
                                                  "CG one device-side loop launch",
                    "fwd_adj": {"value": round(n_pts / sec_ba, 2), "unit": "points/s",
                                "ms_per_step": round(sec_ba * 1e3, 3),
@@ -668,7 +668,7 @@ def main():
                               "T": 1.0, "N": 20, "f": "-lam |z|^2, lam ~ U[0.5, 2]", "g": "ln((1+|x|^2)/2)",
                               "x0": "U[-1,1]^d", "state_elements": elems},
                    "cg_product_traffic": dict(traffic(bytes_b, sec_b),
-                                              loop_stream_time_share=round(loop_ms_b / 1e3 / (4 * sec_b), 3),
+                                              loop_stream_time_share=round(loop_ms_b / 1e3 / (3 * sec_b), 3),
                                               note="bytes: rows streamed by every CG product (device count) x d x 4 "
                                                    "B, over the wall time of the whole batched call"),
                    "status_nonzero_points": int(sum(int((s_ != 0).sum().item()) for s_ in stb))}

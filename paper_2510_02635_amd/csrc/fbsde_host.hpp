@@ -60,6 +60,13 @@ void timer_end(long i, hipStream_t st);
 // Launch shapes recorded by fbsde_autotune (process-wide table keyed by precision, d, M and P).
 bool tuned_shape(const fbsde_problem* pb, int64_t P, int& team, int& nchunk);
 
+// Groups of four coordinates per lane for q needed: 1, 2, 4, 8, and 5 on the FP32 state (rows of
+// 4097-5120 coordinates on four-wave teams, 8193-10240 on eight: no idle lane groups, and fewer registers
+// than 8 groups).
+inline int groups_per_lane(int q, int esz) {
+    return (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : (q <= 5 && esz == 4) ? 5 : 8;
+}
+
 // Re-shape a plan: team width `team` (groups per lane recomputed) and `nchunk` chunks per point.
 // Returns false if the team cannot hold the row within the per-lane register budget.
 inline bool shape_plan(Plan& pl, int team, int nchunk) {
@@ -69,7 +76,7 @@ inline bool shape_plan(Plan& pl, int team, int nchunk) {
     const int q = (groups + 64 * team - 1) / (64 * team);
     if (q > qmax) return false;
     pl.TEAM = team;
-    pl.Q = (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : 8;
+    pl.Q = groups_per_lane(q, pl.esz);
     pl.BS = 64 * std::max(pl.TEAM, 4);
     pl.TPW = pl.BS / (64 * pl.TEAM);
     pl.rows_per_chunk = (int)((pl.M + nchunk - 1) / nchunk);
@@ -94,7 +101,7 @@ inline int make_plan(const fbsde_problem* pb, int64_t P, Plan& pl) {
         const int q = (groups + 64 * team - 1) / (64 * team);
         if (q <= qmax) {
             pl.TEAM = team;
-            pl.Q = (q <= 1) ? 1 : (q <= 2) ? 2 : (q <= 4) ? 4 : 8;
+            pl.Q = groups_per_lane(q, pl.esz);
             break;
         }
     }
@@ -135,6 +142,7 @@ void dispatch(int Q, int TEAM, Fn&& fn) {
     }
     if constexpr (std::is_same<S, float>::value) {
         switch (Q * 100 + TEAM) {
+            FB_CASE(5, 1) FB_CASE(5, 2) FB_CASE(5, 4) FB_CASE(5, 8) FB_CASE(5, 16)
             FB_CASE(8, 1) FB_CASE(8, 2) FB_CASE(8, 4) FB_CASE(8, 8) FB_CASE(8, 16)
             default: break;
         }
